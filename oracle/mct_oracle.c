@@ -1,0 +1,964 @@
+/*
+ * Plain FP64 CPU oracle of the MCT-2D-CEM explicit dynamic step
+ * (two-dimensional Crack Element Model with Multiple Crack-tips Tracking,
+ * arXiv 2509.01827).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is compiled into liboracle.so, which
+ * is loaded by tests/, by the smoke check and by the CPU-baseline leg of the
+ * benchmark.  The product library (include/mct2d.h) neither links nor calls
+ * it, and the two share no source, header, table or helper.
+ *
+ * It is deliberately slow and literal: generic mesh tables (element
+ * connectivity, an edge list sorted by node pair, edge->element adjacency),
+ * one loop per formula, one candidate at a time.
+ *
+ * Where each part comes from:
+ *   - ES-FEM edge displacement / smoothed strain: Sec. 2.1, Eq. (disp_ES_FEM)
+ *     and Eq. (strain_discretization); Q4 strain matrix: Eq.
+ *     (QUAD_strain_discretization).
+ *   - Q4 internal force: Eq. (QUAD_fint_discretization), f = B~^T sigma *
+ *     sum_j A_j/4; plane Cauchy stress (Sec. 2.1, text after that equation).
+ *   - Energy release rate of a split elementary topology: Sec. 2.2, the
+ *     unnumbered equation for G_{Gk-G0} = delta_d . sigma_perp / 2 with the
+ *     Heaviside edge-stretch gate, and its Q4 form with three candidate paths.
+ *   - Q4 per-element decision (none / one / two / three candidates over Gc,
+ *     split ratio gamma): Sec. 2.2, itemised rules after Fig. 2-3.
+ *   - Crack patterns I (adjacent edge) and II (opposite edge): Fig. 2-3.
+ *   - Multiple Crack-tips Tracking: Sec. 3 and its pick criterion (the
+ *     unnumbered inequalities G2 > gamma (G2 - Gi)), Fig. 3-1(b).
+ *   - Explicit formulation: Sec. 2 opening sentence.
+ *
+ * Readings where the paper is silent (each is listed in the design doc):
+ *   - B of element j at edge g_s is the isoparametric Q4 gradient evaluated
+ *     at the midpoint of that edge in j's natural coordinates (reference
+ *     configuration, small strain).
+ *   - Linear elastic plane stress, engineering shear strain.
+ *   - Central differences with lumped mass m_i = sum rho A_e / 4, first step
+ *     half a time step, prescribed velocities override v.
+ *   - A split element takes no part in edge smoothing; its pieces carry
+ *     reduced elements (3 nodes: CST, 2 nodes: bar, 1 node: nothing).
+ *   - Candidates are edges with exactly one intact neighbour; the crack-path
+ *     normal orients toward node N2; one split per step; gamma test exactly
+ *     as printed.
+ *
+ * FP contract (binds the HIP library as well): IEEE binary64, round to
+ * nearest, compiled with -ffp-contract=off; fma() only where written.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_EINVAL (-1)
+#define ORC_ESTATE (-2)
+#define ORC_ECAPACITY (-3)
+
+#define SPLIT_FLAG 0x80u
+
+typedef struct {
+    int step, elem, entry, exit;
+    double G;
+} orc_split_t;
+
+typedef struct {
+    /* mesh */
+    int nx, ny, nn, ne, ns;
+    double *X, *Y;
+    int *conn;       /* 4 per element, counter-clockwise */
+    int *edge_node;  /* 2 per edge: (smaller node id, larger node id) */
+    int *edge_elem;  /* 2 per edge: smaller element id first, -1 = none */
+    int *edge_loc;   /* 2 per edge: local edge index inside that element */
+    int *elem_edge;  /* 4 per element: global edge id of local edge k */
+    int *color;
+    int ncolor;
+    double *area;
+    /* material */
+    double E, nu, rho, D11, D12, D33;
+    double *Gc;
+    double gamma;
+    /* loads */
+    double *edge_trac; /* 2 per edge */
+    unsigned char *edge_loaded;
+    unsigned char *vmask; /* per node: bit0 = x prescribed, bit1 = y */
+    double *v0;           /* 2 per node */
+    double t_ramp;
+    double dt_in, cfl;
+    /* derived */
+    double *mass, *minv, *fext;
+    double dt;
+    int finalized;
+    /* state */
+    unsigned char *split;
+    double *ux, *uy, *vx, *vy;
+    long step;
+    orc_split_t *log;
+    int nlog, caplog;
+    double Ud;
+    /* scratch */
+    double *sig;            /* 3 per edge */
+    double *eps;            /* 3 per edge: smoothed strain */
+    unsigned char *sig_ok;  /* edge has >= 1 intact neighbour */
+    double *fe;             /* 8 per element */
+    double *fx, *fy, *ax, *ay;
+} orc_model_t;
+
+/* natural coordinates of the Q4 nodes and of the four edge midpoints */
+static const double XI_N[4] = {-1.0, 1.0, 1.0, -1.0};
+static const double ETA_N[4] = {-1.0, -1.0, 1.0, 1.0};
+static const double XI_M[4] = {0.0, 1.0, 0.0, -1.0};
+static const double ETA_M[4] = {-1.0, 0.0, 1.0, 0.0};
+
+/* ------------------------------------------------------------------ */
+/* element kinematics                                                   */
+/* ------------------------------------------------------------------ */
+
+/* Gradients dN_n/dx, dN_n/dy of the bilinear Q4 shape functions of an
+ * element with node coordinates (x[4], y[4]) at the midpoint of its local
+ * edge k (Eq. QUAD_strain_discretization evaluated at the edge quadrature
+ * point). */
+static void q4_grad_at_edge(const double x[4], const double y[4], int k,
+                            double dndx[4], double dndy[4]) {
+    double dxi[4], deta[4];
+    for (int n = 0; n < 4; ++n) {
+        dxi[n] = 0.25 * XI_N[n] * (1.0 + ETA_M[k] * ETA_N[n]);
+        deta[n] = 0.25 * ETA_N[n] * (1.0 + XI_M[k] * XI_N[n]);
+    }
+    double j11 = 0.0, j12 = 0.0, j21 = 0.0, j22 = 0.0;
+    for (int n = 0; n < 4; ++n) {
+        j11 = fma(dxi[n], x[n], j11);
+        j12 = fma(dxi[n], y[n], j12);
+        j21 = fma(deta[n], x[n], j21);
+        j22 = fma(deta[n], y[n], j22);
+    }
+    double det = j11 * j22 - j12 * j21;
+    double inv = 1.0 / det;
+    for (int n = 0; n < 4; ++n) {
+        dndx[n] = (j22 * dxi[n] - j12 * deta[n]) * inv;
+        dndy[n] = (j11 * deta[n] - j21 * dxi[n]) * inv;
+    }
+}
+
+/* strain (exx, eyy, gxy) = B u for an element with nn nodes */
+static void strain_from_grad(int nn, const double *dndx, const double *dndy,
+                             const double *ux, const double *uy, double eps[3]) {
+    double exx = 0.0, eyy = 0.0, gxy = 0.0;
+    for (int n = 0; n < nn; ++n) {
+        exx = fma(dndx[n], ux[n], exx);
+        eyy = fma(dndy[n], uy[n], eyy);
+        gxy = fma(dndy[n], ux[n], gxy);
+        gxy = fma(dndx[n], uy[n], gxy);
+    }
+    eps[0] = exx;
+    eps[1] = eyy;
+    eps[2] = gxy;
+}
+
+/* plane-stress Hooke law, engineering shear strain */
+static void stress_from_strain(const orc_model_t *m, const double eps[3], double sig[3]) {
+    sig[0] = fma(m->D12, eps[1], m->D11 * eps[0]);
+    sig[1] = fma(m->D12, eps[0], m->D11 * eps[1]);
+    sig[2] = m->D33 * eps[2];
+}
+
+static void elem_coords(const orc_model_t *m, int e, double x[4], double y[4]) {
+    for (int n = 0; n < 4; ++n) {
+        x[n] = m->X[m->conn[4 * e + n]];
+        y[n] = m->Y[m->conn[4 * e + n]];
+    }
+}
+
+static void elem_disp(const orc_model_t *m, int e, double ux[4], double uy[4]) {
+    for (int n = 0; n < 4; ++n) {
+        ux[n] = m->ux[m->conn[4 * e + n]];
+        uy[n] = m->uy[m->conn[4 * e + n]];
+    }
+}
+
+/* quadrilateral area: half the cross product of the diagonals */
+static double quad_area(const double x[4], const double y[4]) {
+    return 0.5 * ((x[2] - x[0]) * (y[3] - y[1]) - (x[3] - x[1]) * (y[2] - y[0]));
+}
+
+/* polygon area by a fan from the first vertex */
+static double polygon_area(int nv, const double *px, const double *py) {
+    double s = 0.0;
+    for (int i = 1; i + 1 < nv; ++i)
+        s += (px[i] - px[0]) * (py[i + 1] - py[0]) - (px[i + 1] - px[0]) * (py[i] - py[0]);
+    return 0.5 * s;
+}
+
+static int is_intact(const orc_model_t *m, int e) { return e >= 0 && m->split[e] == 0; }
+
+/* ------------------------------------------------------------------ */
+/* a1: ES-FEM smoothed strain and stress at every edge                  */
+/* ------------------------------------------------------------------ */
+
+static void edge_stresses(orc_model_t *m) {
+    for (int s = 0; s < m->ns; ++s) {
+        double q[2][3], A[2];
+        int cnt = 0;
+        for (int side = 0; side < 2; ++side) {
+            int e = m->edge_elem[2 * s + side];
+            if (!is_intact(m, e)) continue;
+            double x[4], y[4], ux[4], uy[4], dndx[4], dndy[4];
+            elem_coords(m, e, x, y);
+            elem_disp(m, e, ux, uy);
+            q4_grad_at_edge(x, y, m->edge_loc[2 * s + side], dndx, dndy);
+            strain_from_grad(4, dndx, dndy, ux, uy, q[cnt]);
+            A[cnt] = m->area[e];
+            cnt++;
+        }
+        double eps[3];
+        if (cnt == 0) {
+            m->sig_ok[s] = 0;
+            m->sig[3 * s] = m->sig[3 * s + 1] = m->sig[3 * s + 2] = 0.0;
+            m->eps[3 * s] = m->eps[3 * s + 1] = m->eps[3 * s + 2] = 0.0;
+            continue;
+        }
+        if (cnt == 1) {
+            /* one intact neighbour: w = A/A = 1 */
+            eps[0] = q[0][0];
+            eps[1] = q[0][1];
+            eps[2] = q[0][2];
+        } else {
+            /* w_j = A_j / sum A, lower element id first */
+            double sum = A[0] + A[1];
+            double w0 = A[0] / sum, w1 = A[1] / sum;
+            for (int c = 0; c < 3; ++c) eps[c] = fma(w1, q[1][c], w0 * q[0][c]);
+        }
+        stress_from_strain(m, eps, &m->sig[3 * s]);
+        for (int c = 0; c < 3; ++c) m->eps[3 * s + c] = eps[c];
+        m->sig_ok[s] = 1;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* a2: element internal forces (intact Q4 and split pieces)             */
+/* ------------------------------------------------------------------ */
+
+static void intact_force(const orc_model_t *m, int e, double f[8]) {
+    double x[4], y[4];
+    elem_coords(m, e, x, y);
+    double sx[4] = {0, 0, 0, 0}, sy[4] = {0, 0, 0, 0};
+    for (int k = 0; k < 4; ++k) {
+        double dndx[4], dndy[4];
+        q4_grad_at_edge(x, y, k, dndx, dndy);
+        const double *sg = &m->sig[3 * m->elem_edge[4 * e + k]];
+        for (int n = 0; n < 4; ++n) {
+            double tx = fma(dndy[n], sg[2], dndx[n] * sg[0]);
+            double ty = fma(dndx[n], sg[2], dndy[n] * sg[1]);
+            if (k == 0) {
+                sx[n] = tx;
+                sy[n] = ty;
+            } else {
+                sx[n] = sx[n] + tx;
+                sy[n] = sy[n] + ty;
+            }
+        }
+    }
+    double c = 0.25 * m->area[e];
+    for (int n = 0; n < 4; ++n) {
+        f[2 * n] = c * sx[n];
+        f[2 * n + 1] = c * sy[n];
+    }
+}
+
+/* Piece of a split element: local nodes first..last going CCW, closed by
+ * the crack midpoints of edges `exit_edge` (after last) and `entry_edge`
+ * (before first).  Adds its nodal forces into f[8] (each node belongs to one
+ * piece only).  Returns the piece strain energy. */
+static double piece_force(const orc_model_t *m, int e, int entry_edge, int exit_edge,
+                          double f[8]) {
+    const int *cn = &m->conn[4 * e];
+    int loc[3];
+    int np = 0;
+    for (int k = (entry_edge + 1) & 3;; k = (k + 1) & 3) {
+        loc[np++] = k;
+        if (k == exit_edge) break;
+    }
+    /* polygon: M_entry, nodes..., M_exit */
+    double px[5], py[5];
+    int nv = 0;
+    int a0 = cn[entry_edge], a1 = cn[(entry_edge + 1) & 3];
+    int b0 = cn[exit_edge], b1 = cn[(exit_edge + 1) & 3];
+    px[nv] = 0.5 * (m->X[a0] + m->X[a1]);
+    py[nv++] = 0.5 * (m->Y[a0] + m->Y[a1]);
+    for (int i = 0; i < np; ++i) {
+        px[nv] = m->X[cn[loc[i]]];
+        py[nv++] = m->Y[cn[loc[i]]];
+    }
+    px[nv] = 0.5 * (m->X[b0] + m->X[b1]);
+    py[nv++] = 0.5 * (m->Y[b0] + m->Y[b1]);
+    double Ap = polygon_area(nv, px, py);
+
+    if (np == 3) {
+        /* constant-strain triangle over the three nodes */
+        double x1 = px[1], y1 = py[1], x2 = px[2], y2 = py[2], x3 = px[3], y3 = py[3];
+        double twoA = (x2 - x1) * (y3 - y1) - (x3 - x1) * (y2 - y1);
+        double inv = 1.0 / twoA;
+        double b[3] = {(y2 - y3) * inv, (y3 - y1) * inv, (y1 - y2) * inv};
+        double c[3] = {(x3 - x2) * inv, (x1 - x3) * inv, (x2 - x1) * inv};
+        double ux[3], uy[3];
+        for (int i = 0; i < 3; ++i) {
+            ux[i] = m->ux[cn[loc[i]]];
+            uy[i] = m->uy[cn[loc[i]]];
+        }
+        double eps[3], sg[3];
+        strain_from_grad(3, b, c, ux, uy, eps);
+        stress_from_strain(m, eps, sg);
+        for (int i = 0; i < 3; ++i) {
+            double tx = fma(c[i], sg[2], b[i] * sg[0]);
+            double ty = fma(b[i], sg[2], c[i] * sg[1]);
+            f[2 * loc[i]] = Ap * tx;
+            f[2 * loc[i] + 1] = Ap * ty;
+        }
+        return 0.5 * Ap * (sg[0] * eps[0] + sg[1] * eps[1] + sg[2] * eps[2]);
+    }
+    if (np == 2) {
+        /* bar along the two nodes, cross-section Ap / L */
+        int p = cn[loc[0]], q = cn[loc[1]];
+        double dx = m->X[q] - m->X[p], dy = m->Y[q] - m->Y[p];
+        double L2 = dx * dx + dy * dy;
+        double dux = m->ux[q] - m->ux[p], duy = m->uy[q] - m->uy[p];
+        double strain = (dx * dux + dy * duy) / L2;
+        double stress = m->E * strain;
+        double coef = Ap * stress / L2;
+        f[2 * loc[1]] = coef * dx;
+        f[2 * loc[1] + 1] = coef * dy;
+        f[2 * loc[0]] = -(coef * dx);
+        f[2 * loc[0] + 1] = -(coef * dy);
+        return 0.5 * Ap * stress * strain;
+    }
+    /* one node: a free corner carries no stiffness */
+    f[2 * loc[0]] = 0.0;
+    f[2 * loc[0] + 1] = 0.0;
+    return 0.0;
+}
+
+static double split_force(const orc_model_t *m, int e, double f[8]) {
+    int a = (m->split[e] >> 2) & 3, b = m->split[e] & 3;
+    double w = piece_force(m, e, a, b, f);
+    w += piece_force(m, e, b, a, f);
+    return w;
+}
+
+/* a1 + a2 + a3: internal nodal forces of the current displacement */
+static void internal_forces(orc_model_t *m) {
+    edge_stresses(m);
+    for (int e = 0; e < m->ne; ++e) {
+        if (m->split[e] == 0)
+            intact_force(m, e, &m->fe[8 * e]);
+        else
+            split_force(m, e, &m->fe[8 * e]);
+    }
+    /* graph-coloured scatter: colour 0, 1, ... ; inside a colour no two
+     * elements share a node, so the per-node summation order is the colour
+     * order */
+    for (int i = 0; i < m->nn; ++i) m->fx[i] = m->fy[i] = 0.0;
+    for (int c = 0; c < m->ncolor; ++c)
+        for (int e = 0; e < m->ne; ++e) {
+            if (m->color[e] != c) continue;
+            for (int n = 0; n < 4; ++n) {
+                int g = m->conn[4 * e + n];
+                m->fx[g] = m->fx[g] + m->fe[8 * e + 2 * n];
+                m->fy[g] = m->fy[g] + m->fe[8 * e + 2 * n + 1];
+            }
+        }
+}
+
+/* ------------------------------------------------------------------ */
+/* a5: energy release rate of the split elementary topologies           */
+/* ------------------------------------------------------------------ */
+
+/* Unit normal and length of the crack path from the midpoint G0 of local
+ * edge a to the midpoint Gk of local edge k, oriented toward node N2 = n_{a+1}
+ * (reference configuration). */
+static void path_normal(const orc_model_t *m, int e, int a, int k, double *nx,
+                        double *ny, double *len) {
+    const int *cn = &m->conn[4 * e];
+    int p0 = cn[a], p1 = cn[(a + 1) & 3], q0 = cn[k], q1 = cn[(k + 1) & 3];
+    double g0x = 0.5 * (m->X[p0] + m->X[p1]), g0y = 0.5 * (m->Y[p0] + m->Y[p1]);
+    double gkx = 0.5 * (m->X[q0] + m->X[q1]), gky = 0.5 * (m->Y[q0] + m->Y[q1]);
+    double dx = gkx - g0x, dy = gky - g0y;
+    double L = sqrt(dx * dx + dy * dy);
+    double cx = dy / L, cy = -dx / L;
+    if (cx * (m->X[p1] - g0x) + cy * (m->Y[p1] - g0y) < 0.0) {
+        cx = -cx;
+        cy = -cy;
+    }
+    *nx = cx;
+    *ny = cy;
+    *len = L;
+}
+
+/* G of the three paths of candidate (element e, crack-tip edge a), for
+ * k = a+1, a+2, a+3 (CCW).  Returns the Heaviside gate H. */
+static int candidate_G(const orc_model_t *m, int e, int a, double G[3]) {
+    const int *cn = &m->conn[4 * e];
+    int n1 = cn[a], n2 = cn[(a + 1) & 3];
+    double dux = m->ux[n2] - m->ux[n1], duy = m->uy[n2] - m->uy[n1];
+    /* H(|x2-x1|/|X2-X1| - 1) as a comparison of squared lengths */
+    double x1 = m->X[n1] + m->ux[n1], y1 = m->Y[n1] + m->uy[n1];
+    double x2 = m->X[n2] + m->ux[n2], y2 = m->Y[n2] + m->uy[n2];
+    double lx = x2 - x1, ly = y2 - y1;
+    double Lx = m->X[n2] - m->X[n1], Ly = m->Y[n2] - m->Y[n1];
+    int H = (lx * lx + ly * ly) > (Lx * Lx + Ly * Ly);
+    for (int j = 0; j < 3; ++j) {
+        if (!H) {
+            G[j] = 0.0;
+            continue;
+        }
+        int k = (a + 1 + j) & 3;
+        const double *sg = &m->sig[3 * m->elem_edge[4 * e + k]];
+        double nx, ny, len;
+        path_normal(m, e, a, k, &nx, &ny, &len);
+        double spx = fma(sg[2], ny, sg[0] * nx);
+        double spy = fma(sg[1], ny, sg[2] * nx);
+        G[j] = 0.5 * fma(duy, spy, dux * spx);
+    }
+    return H;
+}
+
+/* Q4 element decision over the three candidate paths (Sec. 2.2).  Returns
+ * the chosen path index j (k = a+1+j) or -1. */
+int orc_element_rule(const double G[3], double Gc, double gamma) {
+    int best = -1;
+    for (int j = 0; j < 3; ++j)
+        if (G[j] > Gc && (best < 0 || G[j] > G[best])) best = j;
+    if (best < 0) return -1;
+    for (int j = 0; j < 3; ++j) {
+        if (j == best || !(G[j] > Gc)) continue;
+        if (!(G[best] > gamma * (G[best] - G[j]))) return -1;
+    }
+    return best;
+}
+
+/* MCT pick (Sec. 3): the candidate with the largest G (ties: lower element
+ * id, then lower tip edge) provided it passes the split-ratio test against
+ * every other candidate.  Returns its index or -1. */
+int orc_mct_pick(int n, const double *G, const int *elem, const int *a, double gamma) {
+    int best = -1;
+    for (int c = 0; c < n; ++c) {
+        if (best < 0 || G[c] > G[best] ||
+            (G[c] == G[best] && (elem[c] < elem[best] || (elem[c] == elem[best] && a[c] < a[best]))))
+            best = c;
+    }
+    if (best < 0) return -1;
+    for (int c = 0; c < n; ++c) {
+        if (c == best) continue;
+        if (!(G[best] > gamma * (G[best] - G[c]))) return -1;
+    }
+    return best;
+}
+
+/* Free-surface candidate (R: edge with exactly one intact neighbour, i.e. a
+ * domain-boundary edge of an intact element or an edge shared with a split
+ * element).  Sets the intact element f and the local index a of the edge in
+ * it. */
+static int edge_candidate(const orc_model_t *m, int s, int *f, int *a) {
+    int e0 = m->edge_elem[2 * s], e1 = m->edge_elem[2 * s + 1];
+    int i0 = is_intact(m, e0), i1 = is_intact(m, e1);
+    if (i0 + i1 != 1) return 0;
+    *f = i0 ? e0 : e1;
+    *a = i0 ? m->edge_loc[2 * s] : m->edge_loc[2 * s + 1];
+    return 1;
+}
+
+/* a5 + a6: evaluate every free-surface quadrature point, pick, split. */
+static void fracture_phase(orc_model_t *m) {
+    int cap = m->ns;
+    double *cG = malloc(sizeof(double) * (size_t)cap);
+    int *cE = malloc(sizeof(int) * (size_t)cap), *cA = malloc(sizeof(int) * (size_t)cap);
+    int *cK = malloc(sizeof(int) * (size_t)cap);
+    int nc = 0;
+    for (int s = 0; s < m->ns; ++s) {
+        int f, a;
+        if (!edge_candidate(m, s, &f, &a)) continue;
+        double G[3];
+        candidate_G(m, f, a, G);
+        int j = orc_element_rule(G, m->Gc[f], m->gamma);
+        if (j < 0) continue;
+        cG[nc] = G[j];
+        cE[nc] = f;
+        cA[nc] = a;
+        cK[nc] = (a + 1 + j) & 3;
+        nc++;
+    }
+    int c = orc_mct_pick(nc, cG, cE, cA, m->gamma);
+    if (c >= 0) {
+        int f = cE[c], a = cA[c], k = cK[c];
+        m->split[f] = (unsigned char)(SPLIT_FLAG | (unsigned)(a << 2) | (unsigned)k);
+        if (m->nlog == m->caplog) {
+            m->caplog = m->caplog ? 2 * m->caplog : 1024;
+            m->log = realloc(m->log, sizeof(orc_split_t) * (size_t)m->caplog);
+        }
+        orc_split_t rec = {(int)m->step, f, a, k, cG[c]};
+        m->log[m->nlog++] = rec;
+        double nx, ny, len;
+        path_normal(m, f, a, k, &nx, &ny, &len);
+        m->Ud += m->Gc[f] * len;
+    }
+    free(cG);
+    free(cE);
+    free(cA);
+    free(cK);
+}
+
+/* ------------------------------------------------------------------ */
+/* a4: central-difference step                                          */
+/* ------------------------------------------------------------------ */
+
+static double prescribed(const orc_model_t *m, double v0, double t) {
+    if (m->t_ramp > 0.0 && t < m->t_ramp) return v0 * (t / m->t_ramp);
+    return v0;
+}
+
+static void one_step(orc_model_t *m) {
+    internal_forces(m);
+    for (int i = 0; i < m->nn; ++i) {
+        m->ax[i] = (m->fext[2 * i] - m->fx[i]) * m->minv[i];
+        m->ay[i] = (m->fext[2 * i + 1] - m->fy[i]) * m->minv[i];
+        if (m->vmask[i] & 1) m->ax[i] = 0.0;
+        if (m->vmask[i] & 2) m->ay[i] = 0.0;
+    }
+    /* fracture on (u^k, sigma^k); the split acts from step k+1 */
+    fracture_phase(m);
+    double dtv = (m->step == 0) ? 0.5 * m->dt : m->dt;
+    double th = ((double)m->step + 0.5) * m->dt;
+    for (int i = 0; i < m->nn; ++i) {
+        double vx = m->vx[i] + dtv * m->ax[i];
+        double vy = m->vy[i] + dtv * m->ay[i];
+        if (m->vmask[i] & 1) vx = prescribed(m, m->v0[2 * i], th);
+        if (m->vmask[i] & 2) vy = prescribed(m, m->v0[2 * i + 1], th);
+        m->vx[i] = vx;
+        m->vy[i] = vy;
+        m->ux[i] = m->ux[i] + m->dt * vx;
+        m->uy[i] = m->uy[i] + m->dt * vy;
+    }
+    m->step++;
+}
+
+/* ------------------------------------------------------------------ */
+/* set-up                                                               */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int lo, hi, e, k;
+} edge_rec_t;
+
+static int cmp_edge_rec(const void *pa, const void *pb) {
+    const edge_rec_t *a = pa, *b = pb;
+    if (a->lo != b->lo) return a->lo < b->lo ? -1 : 1;
+    if (a->hi != b->hi) return a->hi < b->hi ? -1 : 1;
+    if (a->e != b->e) return a->e < b->e ? -1 : 1;
+    return 0;
+}
+
+static void *zalloc(size_t n) { return calloc(n ? n : 1, 1); }
+
+void orc_destroy(orc_model_t *m) {
+    if (!m) return;
+    void *ptrs[] = {m->X, m->Y, m->conn, m->edge_node, m->edge_elem, m->edge_loc, m->elem_edge,
+                    m->color, m->area, m->Gc, m->edge_trac, m->edge_loaded, m->vmask, m->v0,
+                    m->mass, m->minv, m->fext, m->split, m->ux, m->uy, m->vx, m->vy, m->log,
+                    m->sig, m->eps, m->sig_ok, m->fe, m->fx, m->fy, m->ax, m->ay};
+    for (size_t i = 0; i < sizeof(ptrs) / sizeof(ptrs[0]); ++i) free(ptrs[i]);
+    free(m);
+}
+
+/* Structured nx x ny Q4 grid with the given node coordinates (node (i,j) has
+ * id j*(nx+1)+i; element (i,j) id j*nx+i with CCW nodes (i,j),(i+1,j),
+ * (i+1,j+1),(i,j+1)).  Tables are then built generically from conn. */
+orc_model_t *orc_create(int nx, int ny, const double *X, const double *Y) {
+    if (nx < 2 || ny < 2) return NULL;
+    orc_model_t *m = zalloc(sizeof(orc_model_t));
+    m->nx = nx;
+    m->ny = ny;
+    m->nn = (nx + 1) * (ny + 1);
+    m->ne = nx * ny;
+    m->X = zalloc(sizeof(double) * m->nn);
+    m->Y = zalloc(sizeof(double) * m->nn);
+    memcpy(m->X, X, sizeof(double) * m->nn);
+    memcpy(m->Y, Y, sizeof(double) * m->nn);
+    m->conn = zalloc(sizeof(int) * 4 * m->ne);
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            int e = j * nx + i;
+            m->conn[4 * e + 0] = j * (nx + 1) + i;
+            m->conn[4 * e + 1] = j * (nx + 1) + i + 1;
+            m->conn[4 * e + 2] = (j + 1) * (nx + 1) + i + 1;
+            m->conn[4 * e + 3] = (j + 1) * (nx + 1) + i;
+        }
+    /* edge table: every (element, local edge) keyed by its sorted node pair */
+    edge_rec_t *r = zalloc(sizeof(edge_rec_t) * 4 * m->ne);
+    for (int e = 0; e < m->ne; ++e)
+        for (int k = 0; k < 4; ++k) {
+            int a = m->conn[4 * e + k], b = m->conn[4 * e + ((k + 1) & 3)];
+            edge_rec_t t = {a < b ? a : b, a < b ? b : a, e, k};
+            r[4 * e + k] = t;
+        }
+    qsort(r, 4 * (size_t)m->ne, sizeof(edge_rec_t), cmp_edge_rec);
+    m->edge_node = zalloc(sizeof(int) * 8 * m->ne);
+    m->edge_elem = zalloc(sizeof(int) * 8 * m->ne);
+    m->edge_loc = zalloc(sizeof(int) * 8 * m->ne);
+    m->elem_edge = zalloc(sizeof(int) * 4 * m->ne);
+    int ns = 0;
+    for (int i = 0; i < 4 * m->ne; ++i) {
+        if (i > 0 && r[i].lo == r[i - 1].lo && r[i].hi == r[i - 1].hi) {
+            m->edge_elem[2 * (ns - 1) + 1] = r[i].e;
+            m->edge_loc[2 * (ns - 1) + 1] = r[i].k;
+        } else {
+            m->edge_node[2 * ns] = r[i].lo;
+            m->edge_node[2 * ns + 1] = r[i].hi;
+            m->edge_elem[2 * ns] = r[i].e;
+            m->edge_loc[2 * ns] = r[i].k;
+            m->edge_elem[2 * ns + 1] = -1;
+            m->edge_loc[2 * ns + 1] = -1;
+            ns++;
+        }
+        m->elem_edge[4 * r[i].e + r[i].k] = ns - 1;
+    }
+    free(r);
+    m->ns = ns;
+    /* greedy colouring in element-id order: smallest colour not used by an
+     * already coloured element that shares a node */
+    m->color = zalloc(sizeof(int) * m->ne);
+    int *node_cnt = zalloc(sizeof(int) * (m->nn + 1));
+    for (int e = 0; e < m->ne; ++e)
+        for (int n = 0; n < 4; ++n) node_cnt[m->conn[4 * e + n] + 1]++;
+    for (int i = 0; i < m->nn; ++i) node_cnt[i + 1] += node_cnt[i];
+    int *node_el = zalloc(sizeof(int) * 4 * m->ne);
+    int *fill = zalloc(sizeof(int) * m->nn);
+    for (int e = 0; e < m->ne; ++e)
+        for (int n = 0; n < 4; ++n) {
+            int g = m->conn[4 * e + n];
+            node_el[node_cnt[g] + fill[g]++] = e;
+        }
+    m->ncolor = 0;
+    for (int e = 0; e < m->ne; ++e) {
+        unsigned used = 0;
+        for (int n = 0; n < 4; ++n) {
+            int g = m->conn[4 * e + n];
+            for (int t = node_cnt[g]; t < node_cnt[g + 1]; ++t)
+                if (node_el[t] < e) used |= 1u << m->color[node_el[t]];
+        }
+        int c = 0;
+        while (used & (1u << c)) c++;
+        m->color[e] = c;
+        if (c + 1 > m->ncolor) m->ncolor = c + 1;
+    }
+    free(node_cnt);
+    free(node_el);
+    free(fill);
+    m->area = zalloc(sizeof(double) * m->ne);
+    for (int e = 0; e < m->ne; ++e) {
+        double x[4], y[4];
+        elem_coords(m, e, x, y);
+        m->area[e] = quad_area(x, y);
+    }
+    m->Gc = zalloc(sizeof(double) * m->ne);
+    m->edge_trac = zalloc(sizeof(double) * 2 * ns);
+    m->edge_loaded = zalloc(ns);
+    m->vmask = zalloc(m->nn);
+    m->v0 = zalloc(sizeof(double) * 2 * m->nn);
+    m->mass = zalloc(sizeof(double) * m->nn);
+    m->minv = zalloc(sizeof(double) * m->nn);
+    m->fext = zalloc(sizeof(double) * 2 * m->nn);
+    m->split = zalloc(m->ne);
+    m->ux = zalloc(sizeof(double) * m->nn);
+    m->uy = zalloc(sizeof(double) * m->nn);
+    m->vx = zalloc(sizeof(double) * m->nn);
+    m->vy = zalloc(sizeof(double) * m->nn);
+    m->sig = zalloc(sizeof(double) * 3 * ns);
+    m->eps = zalloc(sizeof(double) * 3 * ns);
+    m->sig_ok = zalloc(ns);
+    m->fe = zalloc(sizeof(double) * 8 * m->ne);
+    m->fx = zalloc(sizeof(double) * m->nn);
+    m->fy = zalloc(sizeof(double) * m->nn);
+    m->ax = zalloc(sizeof(double) * m->nn);
+    m->ay = zalloc(sizeof(double) * m->nn);
+    m->gamma = 1.0;
+    m->cfl = 0.5;
+    return m;
+}
+
+int orc_set_material(orc_model_t *m, double E, double nu, double rho, const double *Gc,
+                     double Gc_uniform, double gamma) {
+    if (!(E > 0.0) || !(nu > -1.0 && nu < 0.5) || !(rho > 0.0) || !(gamma > 0.0)) return ORC_EINVAL;
+    m->E = E;
+    m->nu = nu;
+    m->rho = rho;
+    m->gamma = gamma;
+    m->D11 = E / (1.0 - nu * nu);
+    m->D12 = nu * m->D11;
+    m->D33 = E / (2.0 * (1.0 + nu));
+    for (int e = 0; e < m->ne; ++e) m->Gc[e] = Gc ? Gc[e] : Gc_uniform;
+    return ORC_OK;
+}
+
+static int find_edge(const orc_model_t *m, int a, int b) {
+    int lo = a < b ? a : b, hi = a < b ? b : a;
+    int l = 0, h = m->ns - 1;
+    while (l <= h) {
+        int mid = (l + h) / 2;
+        int ml = m->edge_node[2 * mid], mh = m->edge_node[2 * mid + 1];
+        if (ml == lo && mh == hi) return mid;
+        if (ml < lo || (ml == lo && mh < hi))
+            l = mid + 1;
+        else
+            h = mid - 1;
+    }
+    return -1;
+}
+
+/* Constant traction t (Pa, 2 per edge) on boundary edges given by node pairs. */
+int orc_set_traction(orc_model_t *m, int n, const int *edge_nodes, const double *t) {
+    for (int i = 0; i < n; ++i) {
+        int s = find_edge(m, edge_nodes[2 * i], edge_nodes[2 * i + 1]);
+        if (s < 0 || m->edge_elem[2 * s + 1] >= 0 || m->edge_loaded[s]) return ORC_EINVAL;
+        m->edge_loaded[s] = 1;
+        m->edge_trac[2 * s] = t[2 * i];
+        m->edge_trac[2 * s + 1] = t[2 * i + 1];
+    }
+    return ORC_OK;
+}
+
+int orc_set_velocity_bc(orc_model_t *m, int n, const int *node, const unsigned char *mask,
+                        const double *v0, double t_ramp) {
+    for (int i = 0; i < n; ++i) {
+        if (node[i] < 0 || node[i] >= m->nn || (mask[i] & ~3u)) return ORC_EINVAL;
+        m->vmask[node[i]] = mask[i];
+        m->v0[2 * node[i]] = v0[2 * i];
+        m->v0[2 * node[i] + 1] = v0[2 * i + 1];
+    }
+    m->t_ramp = t_ramp;
+    return ORC_OK;
+}
+
+int orc_set_notch(orc_model_t *m, int n, const int *elem, const unsigned char *entry,
+                  const unsigned char *exitp) {
+    for (int i = 0; i < n; ++i) {
+        if (elem[i] < 0 || elem[i] >= m->ne || entry[i] > 3 || exitp[i] > 3 || entry[i] == exitp[i])
+            return ORC_EINVAL;
+        m->split[elem[i]] = (unsigned char)(SPLIT_FLAG | (unsigned)(entry[i] << 2) | exitp[i]);
+    }
+    return ORC_OK;
+}
+
+int orc_set_time(orc_model_t *m, double dt, double cfl) {
+    m->dt_in = dt;
+    m->cfl = cfl;
+    return ORC_OK;
+}
+
+int orc_finalize(orc_model_t *m) {
+    if (!(m->E > 0.0)) return ORC_ESTATE;
+    /* lumped mass, element-id order */
+    for (int i = 0; i < m->nn; ++i) m->mass[i] = 0.0;
+    for (int e = 0; e < m->ne; ++e) {
+        if (!(m->area[e] > 0.0)) return ORC_EINVAL;
+        double me = m->rho * m->area[e] / 4.0;
+        for (int n = 0; n < 4; ++n) m->mass[m->conn[4 * e + n]] += me;
+    }
+    for (int i = 0; i < m->nn; ++i) m->minv[i] = 1.0 / m->mass[i];
+    /* consistent nodal forces of the edge tractions, edge-id order */
+    for (int i = 0; i < 2 * m->nn; ++i) m->fext[i] = 0.0;
+    for (int s = 0; s < m->ns; ++s) {
+        if (!m->edge_loaded[s]) continue;
+        int a = m->edge_node[2 * s], b = m->edge_node[2 * s + 1];
+        double dx = m->X[b] - m->X[a], dy = m->Y[b] - m->Y[a];
+        double L = sqrt(dx * dx + dy * dy);
+        double fx = m->edge_trac[2 * s] * L * 0.5, fy = m->edge_trac[2 * s + 1] * L * 0.5;
+        m->fext[2 * a] += fx;
+        m->fext[2 * a + 1] += fy;
+        m->fext[2 * b] += fx;
+        m->fext[2 * b + 1] += fy;
+    }
+    /* time step: fraction of (shortest edge) / dilatational wave speed */
+    if (m->dt_in > 0.0) {
+        m->dt = m->dt_in;
+    } else {
+        double hmin = INFINITY;
+        for (int s = 0; s < m->ns; ++s) {
+            int a = m->edge_node[2 * s], b = m->edge_node[2 * s + 1];
+            double dx = m->X[b] - m->X[a], dy = m->Y[b] - m->Y[a];
+            double L = sqrt(dx * dx + dy * dy);
+            if (L < hmin) hmin = L;
+        }
+        double cd = sqrt(m->E / (m->rho * (1.0 - m->nu * m->nu)));
+        m->dt = m->cfl * hmin / cd;
+    }
+    m->finalized = 1;
+    return ORC_OK;
+}
+
+int orc_step(orc_model_t *m, long n) {
+    if (!m->finalized) return ORC_ESTATE;
+    for (long i = 0; i < n; ++i) one_step(m);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* queries and test hooks                                               */
+/* ------------------------------------------------------------------ */
+
+void orc_info(const orc_model_t *m, int *ints /*nn,ne,ns,ncolor,nlog*/, double *dbls /*dt,Ud*/,
+              long *step) {
+    ints[0] = m->nn;
+    ints[1] = m->ne;
+    ints[2] = m->ns;
+    ints[3] = m->ncolor;
+    ints[4] = m->nlog;
+    dbls[0] = m->dt;
+    dbls[1] = m->Ud;
+    *step = m->step;
+}
+
+void orc_get_state(const orc_model_t *m, double *ux, double *uy, double *vx, double *vy,
+                   unsigned char *split) {
+    memcpy(ux, m->ux, sizeof(double) * m->nn);
+    memcpy(uy, m->uy, sizeof(double) * m->nn);
+    memcpy(vx, m->vx, sizeof(double) * m->nn);
+    memcpy(vy, m->vy, sizeof(double) * m->nn);
+    memcpy(split, m->split, m->ne);
+}
+
+void orc_set_state(orc_model_t *m, const double *ux, const double *uy, const double *vx,
+                   const double *vy) {
+    memcpy(m->ux, ux, sizeof(double) * m->nn);
+    memcpy(m->uy, uy, sizeof(double) * m->nn);
+    memcpy(m->vx, vx, sizeof(double) * m->nn);
+    memcpy(m->vy, vy, sizeof(double) * m->nn);
+}
+
+void orc_get_log(const orc_model_t *m, int *step, int *elem, int *entry, int *exitp, double *G) {
+    for (int i = 0; i < m->nlog; ++i) {
+        step[i] = m->log[i].step;
+        elem[i] = m->log[i].elem;
+        entry[i] = m->log[i].entry;
+        exitp[i] = m->log[i].exit;
+        G[i] = m->log[i].G;
+    }
+}
+
+void orc_get_tables(const orc_model_t *m, int *edge_node, int *edge_elem, int *edge_loc,
+                    int *color, double *area, double *mass, double *fext) {
+    memcpy(edge_node, m->edge_node, sizeof(int) * 2 * m->ns);
+    memcpy(edge_elem, m->edge_elem, sizeof(int) * 2 * m->ns);
+    memcpy(edge_loc, m->edge_loc, sizeof(int) * 2 * m->ns);
+    memcpy(color, m->color, sizeof(int) * m->ne);
+    memcpy(area, m->area, sizeof(double) * m->ne);
+    memcpy(mass, m->mass, sizeof(double) * m->nn);
+    memcpy(fext, m->fext, sizeof(double) * 2 * m->nn);
+}
+
+/* internal force and edge stresses of an arbitrary displacement field
+ * (the stored state is restored afterwards) */
+void orc_internal_force(orc_model_t *m, const double *ux, const double *uy, double *fx,
+                        double *fy, double *sig, unsigned char *sig_ok) {
+    double *sx = m->ux, *sy = m->uy;
+    m->ux = (double *)ux;
+    m->uy = (double *)uy;
+    internal_forces(m);
+    m->ux = sx;
+    m->uy = sy;
+    memcpy(fx, m->fx, sizeof(double) * m->nn);
+    memcpy(fy, m->fy, sizeof(double) * m->nn);
+    if (sig) memcpy(sig, m->sig, sizeof(double) * 3 * m->ns);
+    if (sig_ok) memcpy(sig_ok, m->sig_ok, m->ns);
+}
+
+/* Every free-surface candidate of the current state: tip edge, element,
+ * local edge a, the three G values, the element decision j (-1 = none).
+ * Returns the count (or ORC_ECAPACITY with *count set). */
+int orc_candidates(orc_model_t *m, int cap, int *edge, int *elem, int *a, double *G3, int *dec,
+                   int *count) {
+    edge_stresses(m);
+    int nc = 0;
+    for (int s = 0; s < m->ns; ++s) {
+        int f, la;
+        if (!edge_candidate(m, s, &f, &la)) continue;
+        if (nc < cap) {
+            edge[nc] = s;
+            elem[nc] = f;
+            a[nc] = la;
+            candidate_G(m, f, la, &G3[3 * nc]);
+            dec[nc] = orc_element_rule(&G3[3 * nc], m->Gc[f], m->gamma);
+        }
+        nc++;
+    }
+    *count = nc;
+    return nc <= cap ? ORC_OK : ORC_ECAPACITY;
+}
+
+/* Crack-surface tips: edges with exactly one intact neighbour whose other
+ * neighbour is a split element (the uncracked domain boundary excluded),
+ * ascending edge id; xy = reference midpoint. */
+int orc_tips(const orc_model_t *m, int cap, int *edge, double *xy, int *count) {
+    int nt = 0;
+    for (int s = 0; s < m->ns; ++s) {
+        int e0 = m->edge_elem[2 * s], e1 = m->edge_elem[2 * s + 1];
+        if (e0 < 0 || e1 < 0) continue;
+        if (is_intact(m, e0) + is_intact(m, e1) != 1) continue;
+        if (nt < cap) {
+            int a = m->edge_node[2 * s], b = m->edge_node[2 * s + 1];
+            edge[nt] = s;
+            xy[2 * nt] = 0.5 * (m->X[a] + m->X[b]);
+            xy[2 * nt + 1] = 0.5 * (m->Y[a] + m->Y[b]);
+        }
+        nt++;
+    }
+    *count = nt;
+    return nt <= cap ? ORC_OK : ORC_ECAPACITY;
+}
+
+/* Energies at t_k: kinetic (v^k = v^{k-1/2} + dt/2 a^k; v^0 at k = 0),
+ * strain (edge smoothing domains A_s = sum of intact A_j/4, plus split
+ * pieces), external work f_ext . u (constant tractions), dissipated Ud. */
+void orc_energies(orc_model_t *m, double out[4]) {
+    internal_forces(m);
+    double ekin = 0.0, estr = 0.0, wext = 0.0;
+    for (int i = 0; i < m->nn; ++i) {
+        double ax = (m->fext[2 * i] - m->fx[i]) * m->minv[i];
+        double ay = (m->fext[2 * i + 1] - m->fy[i]) * m->minv[i];
+        double vx = m->vx[i], vy = m->vy[i];
+        if (m->step > 0) {
+            if (!(m->vmask[i] & 1)) vx = vx + 0.5 * m->dt * ax;
+            if (!(m->vmask[i] & 2)) vy = vy + 0.5 * m->dt * ay;
+        }
+        ekin += 0.5 * m->mass[i] * (vx * vx + vy * vy);
+        wext += m->fext[2 * i] * m->ux[i] + m->fext[2 * i + 1] * m->uy[i];
+    }
+    for (int s = 0; s < m->ns; ++s) {
+        if (!m->sig_ok[s]) continue;
+        double As = 0.0;
+        for (int side = 0; side < 2; ++side) {
+            int e = m->edge_elem[2 * s + side];
+            if (is_intact(m, e)) As += m->area[e] / 4.0;
+        }
+        const double *sg = &m->sig[3 * s], *ep = &m->eps[3 * s];
+        estr += 0.5 * As * (sg[0] * ep[0] + sg[1] * ep[1] + sg[2] * ep[2]);
+    }
+    double tmp[8];
+    for (int e = 0; e < m->ne; ++e)
+        if (m->split[e]) estr += split_force(m, e, tmp);
+    out[0] = ekin;
+    out[1] = estr;
+    out[2] = wext;
+    out[3] = m->Ud;
+}
+
+/* G of one candidate of the current state (fresh edge stresses). */
+int orc_candidate_G(orc_model_t *m, int e, int a, double G[3]) {
+    edge_stresses(m);
+    return candidate_G(m, e, a, G);
+}
+
+int orc_path_normal(const orc_model_t *m, int e, int a, int k, double out[3]) {
+    path_normal(m, e, a, k, &out[0], &out[1], &out[2]);
+    return ORC_OK;
+}
+
+void orc_split_codes(orc_model_t *m, const unsigned char *codes) { memcpy(m->split, codes, m->ne); }

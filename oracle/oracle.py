@@ -1,0 +1,222 @@
+"""ctypes wrapper of the plain FP64 CPU oracle (mct_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+CPU-baseline leg of the benchmark.  The product package never imports it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mct_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math"]
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so with gcc (plain C, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        P = C.c_void_p
+        dp = np.ctypeslib.ndpointer(np.float64, flags="C")
+        ip = np.ctypeslib.ndpointer(np.int32, flags="C")
+        bp = np.ctypeslib.ndpointer(np.uint8, flags="C")
+        _lib.orc_create.restype = P
+        _lib.orc_create.argtypes = [C.c_int, C.c_int, dp, dp]
+        _lib.orc_destroy.argtypes = [P]
+        _lib.orc_set_material.argtypes = [P, C.c_double, C.c_double, C.c_double, C.c_void_p,
+                                          C.c_double, C.c_double]
+        _lib.orc_set_traction.argtypes = [P, C.c_int, ip, dp]
+        _lib.orc_set_velocity_bc.argtypes = [P, C.c_int, ip, bp, dp, C.c_double]
+        _lib.orc_set_notch.argtypes = [P, C.c_int, ip, bp, bp]
+        _lib.orc_set_time.argtypes = [P, C.c_double, C.c_double]
+        _lib.orc_finalize.argtypes = [P]
+        _lib.orc_step.argtypes = [P, C.c_long]
+        _lib.orc_info.argtypes = [P, ip, dp, C.POINTER(C.c_long)]
+        _lib.orc_get_state.argtypes = [P, dp, dp, dp, dp, bp]
+        _lib.orc_set_state.argtypes = [P, dp, dp, dp, dp]
+        _lib.orc_get_log.argtypes = [P, ip, ip, ip, ip, dp]
+        _lib.orc_get_tables.argtypes = [P, ip, ip, ip, ip, dp, dp, dp]
+        _lib.orc_internal_force.argtypes = [P, dp, dp, dp, dp, C.c_void_p, C.c_void_p]
+        _lib.orc_candidates.argtypes = [P, C.c_int, ip, ip, ip, dp, ip, ip]
+        _lib.orc_tips.argtypes = [P, C.c_int, ip, dp, ip]
+        _lib.orc_energies.argtypes = [P, dp]
+        _lib.orc_candidate_G.argtypes = [P, C.c_int, C.c_int, dp]
+        _lib.orc_path_normal.argtypes = [P, C.c_int, C.c_int, C.c_int, dp]
+        _lib.orc_split_codes.argtypes = [P, bp]
+        _lib.orc_element_rule.argtypes = [dp, C.c_double, C.c_double]
+        _lib.orc_mct_pick.argtypes = [C.c_int, dp, ip, ip, C.c_double]
+    return _lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _u8(a):
+    return np.ascontiguousarray(a, dtype=np.uint8)
+
+
+def element_rule(G3, Gc, gamma):
+    return lib().orc_element_rule(_f64(G3), float(Gc), float(gamma))
+
+
+def mct_pick(G, elem, a, gamma):
+    G = _f64(G)
+    return lib().orc_mct_pick(len(G), G, _i32(elem), _i32(a), float(gamma))
+
+
+class Oracle:
+    """One structured-grid model run by the plain CPU oracle."""
+
+    def __init__(self, cfg: dict, *, finalize: bool = True):
+        L = lib()
+        self.cfg = cfg
+        self.nx, self.ny = int(cfg["nx"]), int(cfg["ny"])
+        self.h = L.orc_create(self.nx, self.ny, _f64(cfg["X"]), _f64(cfg["Y"]))
+        if not self.h:
+            raise ValueError("oracle: bad grid")
+        gcf = cfg.get("gc_field")
+        self._gc = None if gcf is None else _f64(gcf)
+        rc = L.orc_set_material(self.h, cfg["E"], cfg["nu"], cfg["rho"],
+                                None if self._gc is None else self._gc.ctypes.data,
+                                float(cfg.get("gc_uniform", 0.0)), float(cfg.get("gamma", 1.0)))
+        self._check(rc)
+        tn = _i32(np.asarray(cfg["traction_nodes"]).reshape(-1))
+        self._check(L.orc_set_traction(self.h, len(tn) // 2, tn, _f64(np.asarray(cfg["traction"]).reshape(-1))))
+        vn, vm, vv = cfg["vbc"]
+        self._check(L.orc_set_velocity_bc(self.h, len(vn), _i32(vn), _u8(vm),
+                                          _f64(np.asarray(vv).reshape(-1)), float(cfg.get("t_ramp", 0.0))))
+        ne_, en_, ex_ = cfg["notch"]
+        self._check(L.orc_set_notch(self.h, len(ne_), _i32(ne_), _u8(en_), _u8(ex_)))
+        self._check(L.orc_set_time(self.h, float(cfg.get("dt", 0.0)), float(cfg.get("cfl", 0.5))))
+        if finalize:
+            self._check(L.orc_finalize(self.h))
+
+    @staticmethod
+    def _check(rc):
+        if rc != 0:
+            raise ValueError("oracle call failed: %d" % rc)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_destroy(self.h)
+            self.h = None
+
+    def info(self):
+        ints = np.zeros(5, np.int32)
+        dbls = np.zeros(2)
+        st = C.c_long(0)
+        lib().orc_info(self.h, ints, dbls, C.byref(st))
+        return dict(nn=int(ints[0]), ne=int(ints[1]), ns=int(ints[2]), ncolor=int(ints[3]),
+                    nlog=int(ints[4]), dt=float(dbls[0]), Ud=float(dbls[1]), step=int(st.value))
+
+    def step(self, n):
+        self._check(lib().orc_step(self.h, int(n)))
+
+    def state(self):
+        inf = self.info()
+        nn, ne = inf["nn"], inf["ne"]
+        ux, uy, vx, vy = (np.zeros(nn) for _ in range(4))
+        sp = np.zeros(ne, np.uint8)
+        lib().orc_get_state(self.h, ux, uy, vx, vy, sp)
+        return dict(ux=ux, uy=uy, vx=vx, vy=vy, split=sp)
+
+    def set_state(self, ux, uy, vx, vy):
+        lib().orc_set_state(self.h, _f64(ux), _f64(uy), _f64(vx), _f64(vy))
+
+    def set_split_codes(self, codes):
+        lib().orc_split_codes(self.h, _u8(codes))
+
+    def log(self):
+        n = self.info()["nlog"]
+        st, el, en, ex = (np.zeros(n, np.int32) for _ in range(4))
+        G = np.zeros(n)
+        lib().orc_get_log(self.h, st, el, en, ex, G)
+        return dict(step=st, elem=el, entry=en, exit=ex, G=G)
+
+    def tables(self):
+        inf = self.info()
+        nn, ne, ns = inf["nn"], inf["ne"], inf["ns"]
+        en = np.zeros(2 * ns, np.int32)
+        ee = np.zeros(2 * ns, np.int32)
+        el = np.zeros(2 * ns, np.int32)
+        col = np.zeros(ne, np.int32)
+        area = np.zeros(ne)
+        mass = np.zeros(nn)
+        fext = np.zeros(2 * nn)
+        lib().orc_get_tables(self.h, en, ee, el, col, area, mass, fext)
+        return dict(edge_node=en.reshape(-1, 2), edge_elem=ee.reshape(-1, 2),
+                    edge_loc=el.reshape(-1, 2), color=col, area=area, mass=mass,
+                    fext=fext.reshape(-1, 2))
+
+    def internal_force(self, ux, uy, with_stress=False):
+        inf = self.info()
+        nn, ns = inf["nn"], inf["ns"]
+        fx, fy = np.zeros(nn), np.zeros(nn)
+        sig = np.zeros(3 * ns)
+        ok = np.zeros(ns, np.uint8)
+        lib().orc_internal_force(self.h, _f64(ux), _f64(uy), fx, fy, sig.ctypes.data, ok.ctypes.data)
+        if with_stress:
+            return fx, fy, sig.reshape(-1, 3), ok
+        return fx, fy
+
+    def candidates(self):
+        ns = self.info()["ns"]
+        edge, elem, a, dec = (np.zeros(ns, np.int32) for _ in range(4))
+        G3 = np.zeros(3 * ns)
+        cnt = np.zeros(1, np.int32)
+        self._check(lib().orc_candidates(self.h, ns, edge, elem, a, G3, dec, cnt))
+        n = int(cnt[0])
+        return dict(edge=edge[:n], elem=elem[:n], a=a[:n], G=G3.reshape(-1, 3)[:n], dec=dec[:n])
+
+    def tips(self):
+        ns = self.info()["ns"]
+        edge = np.zeros(ns, np.int32)
+        xy = np.zeros(2 * ns)
+        cnt = np.zeros(1, np.int32)
+        self._check(lib().orc_tips(self.h, ns, edge, xy, cnt))
+        n = int(cnt[0])
+        return edge[:n], xy.reshape(-1, 2)[:n]
+
+    def energies(self):
+        out = np.zeros(4)
+        lib().orc_energies(self.h, out)
+        return dict(kin=out[0], strain=out[1], wext=out[2], Ud=out[3])
+
+    def candidate_G(self, e, a):
+        G = np.zeros(3)
+        H = lib().orc_candidate_G(self.h, int(e), int(a), G)
+        return G, H
+
+    def path_normal(self, e, a, k):
+        out = np.zeros(3)
+        lib().orc_path_normal(self.h, int(e), int(a), int(k), out)
+        return out
+
+
+def run(cfg: dict, steps: int | None = None) -> Oracle:
+    o = Oracle(cfg)
+    o.step(cfg["steps"] if steps is None else steps)
+    return o
