@@ -1,0 +1,177 @@
+/*
+ * mct2d.h - C ABI of the MI355X (gfx950) library for the explicit dynamic
+ * step of the two-dimensional Crack Element Model with Multiple Crack-tips
+ * Tracking (MCT-2D-CEM, arXiv 2509.01827).
+ *
+ * One time step (mct_step) runs, entirely on the GPU:
+ *   1. ES-FEM smoothed strain and plane stress at every edge quadrature point
+ *      (Sec. 2.1, Eqs. disp_ES_FEM, strain_discretization,
+ *      QUAD_strain_discretization);
+ *   2. Q4 internal force per element, intact (Eq. QUAD_fint_discretization)
+ *      or split into pieces, and a deterministic graph-coloured scatter to the
+ *      nodes (colour of element (i,j) = (i mod 2) + 2 (j mod 2), summed in
+ *      colour order);
+ *   3. the central-difference nodal update (the paper's explicit
+ *      formulation, Sec. 2) with lumped mass;
+ *   4. the energy release rate G of the three split topologies of every
+ *      free-surface quadrature point and the Q4 element rule (Sec. 2.2,
+ *      Fig. 2-3 and the itemised cases after it);
+ *   5. the Multiple Crack-tips Tracking pick over all free-surface
+ *      candidates and the split of the chosen element (Sec. 3, Fig. 3-1(b)).
+ *
+ * Conventions
+ *   - Structured Q4 grid of nx x ny elements (nx, ny >= 2).  Node (i,j),
+ *     0<=i<=nx, 0<=j<=ny, has id j*(nx+1)+i; element (i,j) has id j*nx+i and
+ *     the counter-clockwise nodes (i,j),(i+1,j),(i+1,j+1),(i,j+1).  Local
+ *     edge k joins local nodes k and k+1 (0 bottom, 1 right, 2 top, 3 left).
+ *     Node coordinates are free (any positive-area, counter-clockwise
+ *     elements), so jittered and sheared grids are allowed.
+ *   - Edge ids follow the sorted (smaller node, larger node) order.
+ *   - Split code of an element: 0 = intact, else 0x80 | (entry << 2) | exit,
+ *     entry/exit = local edges whose midpoints the crack joins (pattern I:
+ *     adjacent edges, pattern II: opposite edges, Fig. 2-3).
+ *   - SI units, unit thickness; energies per unit thickness (J/m).
+ *   - All arrays passed in are host pointers; the library copies them during
+ *     the call and the caller keeps ownership.  Query outputs are host
+ *     pointers with a capacity `cap` (elements of the array); `*count` is
+ *     always set and MCT_ECAPACITY is returned when cap < count.
+ *   - Every function returns an int status (MCT_OK = 0, negative on error)
+ *     and never throws; mct_last_error() gives a message owned by the
+ *     context (valid until the next call on it).
+ *   - Device work is enqueued on the HIP stream given to mct_create (or on a
+ *     stream the library creates when it is NULL).  mct_step returns without
+ *     waiting; every query synchronises that stream first.
+ *   - FP64: results are bit-reproducible run to run (fixed summation
+ *     orders, no floating-point atomics).
+ */
+#ifndef MCT2D_H
+#define MCT2D_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MCT_OK = 0,
+    MCT_EINVAL = -1,     /* bad argument (null pointer, size, value, mesh) */
+    MCT_ESTATE = -2,     /* call out of order (e.g. step before finalize) */
+    MCT_ECAPACITY = -3,  /* output capacity too small, *count holds the need */
+    MCT_EDEVICE = -4,    /* HIP runtime or kernel launch failure */
+    MCT_ENOMEM = -5,     /* device or host allocation failed */
+    MCT_EUNSUPPORTED = -6
+};
+
+enum { MCT_FIELD_U = 0, MCT_FIELD_V = 1 };
+
+typedef struct mct_ctx mct_ctx;
+
+typedef struct {
+    int64_t n_nodes, n_elems, n_edges;
+    int64_t step;        /* number of completed time steps */
+    int64_t n_splits;    /* splits made by the tracking (pre-notch excluded) */
+    double dt;           /* time step in use */
+    double dissipated;   /* U_d = sum over splits of Gc * crack-path length */
+    int32_t log_overflow;/* 1 if more splits happened than the log can hold */
+    int32_t precision;
+} mct_info;
+
+/* Create an empty context.  precision: 64 (binary64 state and arithmetic).
+ * hip_stream: a hipStream_t to enqueue on, or NULL for a library stream.
+ * Errors: MCT_EINVAL (out NULL), MCT_EUNSUPPORTED (precision), MCT_EDEVICE. */
+int mct_create(mct_ctx **out, int precision, void *hip_stream);
+
+/* Release every device and host resource of ctx (NULL is a no-op). */
+int mct_destroy(mct_ctx *ctx);
+
+/* Message of the last failing call on ctx. */
+const char *mct_last_error(const mct_ctx *ctx);
+
+/* Mesh (Sec. 2.1: nodes and element connectivity M^{A_j}): structured grid
+ * of nx x ny Q4 elements with reference coordinates X[n], Y[n] of the
+ * (nx+1)(ny+1) nodes.  Rejects nx < 2, ny < 2, and non-positive areas.
+ * Resets material, loads, notch and time settings. */
+int mct_set_mesh_grid(mct_ctx *ctx, int32_t nx, int32_t ny, const double *X, const double *Y);
+
+/* Linear elastic plane-stress material (Young's modulus E, Poisson ratio
+ * nu, density rho) and critical energy release rate: Gc[e] per element
+ * (n_elems values) or, if Gc is NULL, Gc_uniform everywhere.  gamma is the
+ * split ratio of the element rule and of the MCT pick (Sec. 2.2 and 3; > 0).
+ * Errors: MCT_EINVAL for E <= 0, nu outside (-1, 0.5), rho <= 0, gamma <= 0,
+ * Gc <= 0; MCT_ESTATE before mct_set_mesh_grid. */
+int mct_set_material(mct_ctx *ctx, double E, double nu, double rho, const double *Gc,
+                     double Gc_uniform, double gamma);
+
+/* Constant Neumann traction (Pa) on n boundary edges, each given by its two
+ * node ids edge_nodes[2i], edge_nodes[2i+1] and the traction vector
+ * t[2i], t[2i+1]; each end node receives t * L / 2 (equivalent nodal force),
+ * summed in edge-id order.  Rejects interior or repeated edges. */
+int mct_set_traction(mct_ctx *ctx, int64_t n, const int32_t *edge_nodes, const double *t);
+
+/* Prescribed velocity on n boundary nodes: dof_mask bit 0 = x, bit 1 = y;
+ * v0[2i], v0[2i+1] the target velocity, reached linearly over t_ramp
+ * seconds (0 = applied from the first step).  Interior nodes are rejected. */
+int mct_set_velocity_bc(mct_ctx *ctx, int64_t n, const int32_t *node, const uint8_t *dof_mask,
+                        const double *v0, double t_ramp);
+
+/* Pre-notch: n elements split from the start with the given entry/exit
+ * local edges (entry != exit, both 0..3).  Not counted in U_d or the log. */
+int mct_set_notch(mct_ctx *ctx, int64_t n, const int32_t *elem, const uint8_t *entry,
+                  const uint8_t *exit);
+
+/* Time step: dt > 0 is used as given; otherwise dt = cfl_fraction *
+ * (shortest edge) / c_d with c_d = sqrt(E / (rho (1 - nu^2))). */
+int mct_set_time(mct_ctx *ctx, double dt, double cfl_fraction);
+
+/* Build the derived arrays (areas, lumped mass, equivalent nodal forces,
+ * time step, crack-path geometry), upload everything and zero the state
+ * (u = v = 0, step 0).  Errors: MCT_ESTATE if mesh or material is missing,
+ * MCT_ENOMEM / MCT_EDEVICE on device failures. */
+int mct_finalize(mct_ctx *ctx);
+
+/* Enqueue n_steps time steps; asynchronous.  Each step splits at most one
+ * element (the MCT pick) and the split acts from the next step on. */
+int mct_step(mct_ctx *ctx, int64_t n_steps);
+
+/* Wait for the enqueued work; reports asynchronous device errors. */
+int mct_sync(mct_ctx *ctx);
+
+int mct_get_info(mct_ctx *ctx, mct_info *out);
+
+/* Split log in the order the splits were made: step index k (the split was
+ * decided on the state at t_k and acts from step k+1), element id, entry
+ * and exit local edges, G of the chosen path.  Any output may be NULL. */
+int mct_get_crack_set(mct_ctx *ctx, int64_t cap, int32_t *step, int32_t *elem, uint8_t *entry,
+                      uint8_t *exit, double *G, int64_t *count);
+
+/* Crack-surface tips (Fig. 3-1(b), free-surface quadrature points on crack
+ * faces): interior edges with exactly one intact neighbour, ascending edge
+ * id; xy = reference midpoint (2 per tip).  Computed on the GPU. */
+int mct_get_tips(mct_ctx *ctx, int64_t cap, int32_t *edge, double *xy, int64_t *count);
+
+/* Nodal field at the current step: MCT_FIELD_U (u^k) or MCT_FIELD_V
+ * (v^{k-1/2}, v^0 at k = 0), written as [x of all nodes, y of all nodes]
+ * (2 n_nodes values). */
+int mct_get_field(mct_ctx *ctx, int which, int64_t cap, double *out);
+
+/* Split code of every element (n_elems bytes). */
+int mct_get_split_codes(mct_ctx *ctx, int64_t cap, uint8_t *out);
+
+/* Copy the full dynamic state (u, v, split codes, step, U_d, log) into a
+ * caller buffer; *bytes receives the size (call with host_buf NULL to query).
+ * mct_restore loads a buffer produced by mct_checkpoint of a context with
+ * the same mesh. */
+int mct_checkpoint(mct_ctx *ctx, void *host_buf, int64_t cap, int64_t *bytes);
+int mct_restore(mct_ctx *ctx, const void *host_buf, int64_t bytes);
+
+/* Launch tuning: tile shape index (0 = automatic) and whether mct_step
+ * replays captured HIP graphs (1, default) or launches kernel by kernel (0).
+ * Neither changes any result. */
+int mct_set_launch(mct_ctx *ctx, int tile, int use_graph);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCT2D_H */

@@ -1,0 +1,81 @@
+// Internal declarations shared by the host side (mct2d_api.cpp) and the
+// kernels (mct2d_step.hip) of the MCT-2D-CEM library.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mct {
+
+constexpr uint8_t kSplitFlag = 0x80;  // element split code: 0x80 | entry<<2 | exit
+constexpr uint8_t kAbsent = 0x40;     // LDS marker for an element outside the grid
+
+// One accepted split made by the tracking.
+struct LogRec {
+    int32_t step;
+    int32_t elem;
+    uint8_t entry, exit, pad0, pad1;
+    int32_t pad2;
+    double G;
+};
+static_assert(sizeof(LogRec) == 24, "LogRec layout");
+
+// Per-workgroup best candidate of one step (only workgroups with an
+// accepted candidate write one).
+struct Slot {
+    double G;     // largest accepted G of the workgroup
+    double Gmin;  // smallest accepted G of the workgroup
+    int32_t elem, a, k, pad;
+};
+
+// Device-resident control block of one model.
+struct Control {
+    int64_t step;      // index k of the next step to run
+    uint32_t arrive;   // workgroups finished in the running step
+    uint32_t nslots;   // slots written in the running step
+    int64_t nsplit;    // splits made so far (log length if no overflow)
+    double Ud;         // dissipated energy, sum of Gc * path length
+    int32_t overflow;  // 1 when a split could not be logged
+    int32_t pad;
+};
+
+struct StepParams {
+    int32_t nx, ny;     // elements per direction
+    int32_t ntx, nty;   // tiles per direction
+    int32_t nwg;        // ntx * nty
+    int32_t log_cap;
+    const double *X, *Y;
+    double *ux0, *uy0, *ux1, *uy1;  // displacement ping-pong, u^k in (k & 1)
+    double *vx, *vy;
+    const double *minv;
+    uint8_t *split;
+    const double *gc;   // per element, or nullptr for gc_uniform
+    double gc_uniform;
+    const double *geom; // 36 per element: for a in 0..3, j in 0..2: nx, ny, L
+    const double *fext_p;     // 2 per perimeter node
+    const uint8_t *vmask_p;   // 1 per perimeter node
+    const double *v0_p;       // 2 per perimeter node
+    double D11, D12, D33, E;
+    double dt, t_ramp, gamma;
+    Control *ctl;
+    Slot *slots;
+    LogRec *log;
+};
+
+// Tile shapes (elements per workgroup in x and y; nodes owned = one less).
+struct TileShape {
+    int txe, tye;
+};
+constexpr int kNumTiles = 3;
+TileShape tile_shape(int tile);  // tile in 1..kNumTiles
+
+hipError_t launch_step(int tile, const StepParams &p, hipStream_t s);
+
+// Crack-surface tips: compacted edge ids and reference midpoints.
+hipError_t launch_tips(int32_t nx, int32_t ny, const double *X, const double *Y,
+                       const uint8_t *split, int32_t *block_counts, int32_t *nblocks_out,
+                       int32_t *edge_out, double *xy_out, int32_t *count_out, hipStream_t s);
+int tips_nblocks(int64_t n_edges);
+
+}  // namespace mct

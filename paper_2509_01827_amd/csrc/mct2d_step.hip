@@ -1,0 +1,774 @@
+// HIP kernels (gfx950) of the MCT-2D-CEM explicit step.
+//
+// k_step: one launch = one time step.  A workgroup owns a tile of
+// (TXE-1) x (TYE-1) nodes and
+//   1. stages u^k and X of the tile plus a 2-node halo, and the split codes
+//      of every element touching that halo, in LDS;
+//   2. forms the ES-FEM smoothed strain and plane stress at every edge of
+//      the (TXE x TYE) elements around its nodes (Sec. 2.1, Eqs.
+//      disp_ES_FEM / strain_discretization / QUAD_strain_discretization),
+//      one thread per edge, in LDS;
+//   3. computes the internal force of each of those elements (Eq.
+//      QUAD_fint_discretization for intact ones, reduced pieces for split
+//      ones), one thread per element, and scatters it to the owned nodes in
+//      colour order 0..3 (four LDS passes, no two elements of one colour
+//      share a node, so the per-node sum order is fixed);
+//   4. advances its nodes by central differences and writes u^{k+1}, v;
+//   5. compacts the free-surface candidates of the elements it owns with
+//      wavefront ballots, evaluates G of the three split topologies and the
+//      Q4 element rule (Sec. 2.2), reduces the best candidate of the
+//      workgroup and publishes it;
+//   6. the last workgroup to finish reduces the published candidates, applies
+//      the MCT pick with the split-ratio test (Sec. 3) and splits the chosen
+//      element, which the next launch sees.
+//
+// Arithmetic follows one fixed expression order (binary64, compiled with
+// -ffp-contract=off; fma only where written), so the result does not depend
+// on the tile shape or on the schedule.
+#include "mct2d_impl.h"
+
+#include <climits>
+
+namespace mct {
+
+namespace {
+
+// natural coordinates of Q4 nodes and of the edge midpoints
+__device__ __forceinline__ double xi_n(int n) { return (n == 1 || n == 2) ? 1.0 : -1.0; }
+__device__ __forceinline__ double eta_n(int n) { return (n >= 2) ? 1.0 : -1.0; }
+__device__ __forceinline__ double xi_m(int k) { return k == 1 ? 1.0 : (k == 3 ? -1.0 : 0.0); }
+__device__ __forceinline__ double eta_m(int k) { return k == 0 ? -1.0 : (k == 2 ? 1.0 : 0.0); }
+
+// dN/dx, dN/dy of the bilinear element at the midpoint of its local edge k
+__device__ __forceinline__ void q4_grad(const double x[4], const double y[4], int k, double dndx[4],
+                                        double dndy[4]) {
+    double dxi[4], deta[4];
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        dxi[n] = 0.25 * xi_n(n) * (1.0 + eta_m(k) * eta_n(n));
+        deta[n] = 0.25 * eta_n(n) * (1.0 + xi_m(k) * xi_n(n));
+    }
+    double j11 = 0.0, j12 = 0.0, j21 = 0.0, j22 = 0.0;
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        j11 = fma(dxi[n], x[n], j11);
+        j12 = fma(dxi[n], y[n], j12);
+        j21 = fma(deta[n], x[n], j21);
+        j22 = fma(deta[n], y[n], j22);
+    }
+    const double det = j11 * j22 - j12 * j21;
+    const double inv = 1.0 / det;
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        dndx[n] = (j22 * dxi[n] - j12 * deta[n]) * inv;
+        dndy[n] = (j11 * deta[n] - j21 * dxi[n]) * inv;
+    }
+}
+
+template <int NN>
+__device__ __forceinline__ void strain(const double *dndx, const double *dndy, const double *ux,
+                                       const double *uy, double eps[3]) {
+    double exx = 0.0, eyy = 0.0, gxy = 0.0;
+#pragma unroll
+    for (int n = 0; n < NN; ++n) {
+        exx = fma(dndx[n], ux[n], exx);
+        eyy = fma(dndy[n], uy[n], eyy);
+        gxy = fma(dndy[n], ux[n], gxy);
+        gxy = fma(dndx[n], uy[n], gxy);
+    }
+    eps[0] = exx;
+    eps[1] = eyy;
+    eps[2] = gxy;
+}
+
+__device__ __forceinline__ void hooke(const StepParams &p, const double eps[3], double sig[3]) {
+    sig[0] = fma(p.D12, eps[1], p.D11 * eps[0]);
+    sig[1] = fma(p.D12, eps[0], p.D11 * eps[1]);
+    sig[2] = p.D33 * eps[2];
+}
+
+__device__ __forceinline__ double quad_area(const double x[4], const double y[4]) {
+    return 0.5 * ((x[2] - x[0]) * (y[3] - y[1]) - (x[3] - x[1]) * (y[2] - y[0]));
+}
+
+// Best-candidate order: larger G, then smaller element id, then smaller a.
+__device__ __forceinline__ bool better(double g1, int e1, int a1, double g2, int e2, int a2) {
+    return g1 > g2 || (g1 == g2 && (e1 < e2 || (e1 == e2 && a1 < a2)));
+}
+
+struct Cand {
+    double G, Gmin;
+    int e, a, k;
+};
+
+__device__ __forceinline__ void cand_none(Cand &c) {
+    c.G = -1.0;
+    c.Gmin = __builtin_inf();
+    c.e = INT_MAX;
+    c.a = 4;
+    c.k = 0;
+}
+
+__device__ __forceinline__ void cand_merge(Cand &c, double G, double Gmin, int e, int a, int k) {
+    if (better(G, e, a, c.G, c.e, c.a)) {
+        c.G = G;
+        c.e = e;
+        c.a = a;
+        c.k = k;
+    }
+    if (Gmin < c.Gmin) c.Gmin = Gmin;
+}
+
+__device__ __forceinline__ void cand_wave_reduce(Cand &c) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        double G = __shfl_xor(c.G, off, 64);
+        double Gm = __shfl_xor(c.Gmin, off, 64);
+        int e = __shfl_xor(c.e, off, 64);
+        int a = __shfl_xor(c.a, off, 64);
+        int k = __shfl_xor(c.k, off, 64);
+        cand_merge(c, G, Gm, e, a, k);
+    }
+}
+
+// Workgroup-wide reduction; the result is valid in thread 0.
+template <int NT>
+__device__ __forceinline__ void cand_block_reduce(Cand &c, Cand *red) {
+    cand_wave_reduce(c);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < NT / 64; ++w) cand_merge(c, red[w].G, red[w].Gmin, red[w].e, red[w].a, red[w].k);
+    }
+}
+
+__device__ __forceinline__ double prescribed(double v0, double t, double t_ramp) {
+    if (t_ramp > 0.0 && t < t_ramp) return v0 * (t / t_ramp);
+    return v0;
+}
+
+__device__ __forceinline__ int perimeter_index(int i, int j, int nx, int ny) {
+    if (j == 0) return i;
+    if (j == ny) return (nx + 1) + i;
+    if (i == 0) return 2 * (nx + 1) + (j - 1);
+    if (i == nx) return 2 * (nx + 1) + (ny - 1) + (j - 1);
+    return -1;
+}
+
+// Map workgroups onto tiles so that consecutive workgroups of one XCD (the
+// hardware deals workgroup ids round-robin over the 8 XCDs) own a
+// contiguous band of tiles and share halo lines in their L2.
+__device__ __forceinline__ int xcd_tile(int b, int nwg) {
+    const int q = nwg / 8, r = nwg % 8;
+    const int x = b % 8, l = b / 8;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + l;
+}
+
+}  // namespace
+
+template <int TXE, int TYE>
+__global__ __launch_bounds__(TXE *TYE) void k_step(StepParams p) {
+    constexpr int NT = TXE * TYE;
+    constexpr int TX = TXE - 1, TY = TYE - 1;  // owned nodes
+    constexpr int HX = TXE + 3, HY = TYE + 3;  // staged nodes
+    constexpr int EX = TXE + 2, EY = TYE + 2;  // staged elements
+    constexpr int NH = TXE * (TYE + 1);        // horizontal edges
+    constexpr int NV = (TXE + 1) * TYE;        // vertical edges
+    static_assert(NT % 64 == 0, "whole wavefronts");
+
+    __shared__ double s_ux[HX * HY], s_uy[HX * HY], s_X[HX * HY], s_Y[HX * HY];
+    __shared__ double s_area[EX * EY];
+    __shared__ double s_sig[(NH + NV) * 3];
+    __shared__ double s_acc[TX * TY * 2];
+    __shared__ uint8_t s_split[EX * EY];
+    __shared__ uint16_t s_cand[4 * TX * TY];
+    __shared__ int s_ncand;
+    __shared__ int s_wbase[NT / 64];
+    __shared__ Cand s_red[NT / 64];
+    __shared__ int s_last;
+
+    const int tid = threadIdx.x;
+    const int nx = p.nx, ny = p.ny;
+    const int tile = xcd_tile(blockIdx.x, p.nwg);
+    const int i0 = (tile % p.ntx) * TX, j0 = (tile / p.ntx) * TY;
+    const int64_t kstep = p.ctl->step;
+    const double *ux_c = (kstep & 1) ? p.ux1 : p.ux0;
+    const double *uy_c = (kstep & 1) ? p.uy1 : p.uy0;
+    double *ux_n = (kstep & 1) ? p.ux0 : p.ux1;
+    double *uy_n = (kstep & 1) ? p.uy0 : p.uy1;
+
+    // ---- 1. stage nodes and split codes --------------------------------
+    for (int idx = tid; idx < HX * HY; idx += NT) {
+        const int gi = i0 - 2 + idx % HX, gj = j0 - 2 + idx / HX;
+        double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
+        if (gi >= 0 && gi <= nx && gj >= 0 && gj <= ny) {
+            const int64_t n = (int64_t)gj * (nx + 1) + gi;
+            a = ux_c[n];
+            b = uy_c[n];
+            c = p.X[n];
+            d = p.Y[n];
+        }
+        s_ux[idx] = a;
+        s_uy[idx] = b;
+        s_X[idx] = c;
+        s_Y[idx] = d;
+    }
+    for (int idx = tid; idx < EX * EY; idx += NT) {
+        const int gi = i0 - 2 + idx % EX, gj = j0 - 2 + idx / EX;
+        uint8_t code = kAbsent;
+        if (gi >= 0 && gi < nx && gj >= 0 && gj < ny) code = p.split[(int64_t)gj * nx + gi];
+        s_split[idx] = code;
+    }
+    for (int idx = tid; idx < TX * TY * 2; idx += NT) s_acc[idx] = 0.0;
+    if (tid == 0) s_ncand = 0;
+    __syncthreads();
+
+    auto elem_xy = [&](int ex, int ey, double x[4], double y[4]) {
+        const int b = ey * HX + ex;
+        x[0] = s_X[b];
+        x[1] = s_X[b + 1];
+        x[2] = s_X[b + HX + 1];
+        x[3] = s_X[b + HX];
+        y[0] = s_Y[b];
+        y[1] = s_Y[b + 1];
+        y[2] = s_Y[b + HX + 1];
+        y[3] = s_Y[b + HX];
+    };
+    auto elem_u = [&](int ex, int ey, double ux[4], double uy[4]) {
+        const int b = ey * HX + ex;
+        ux[0] = s_ux[b];
+        ux[1] = s_ux[b + 1];
+        ux[2] = s_ux[b + HX + 1];
+        ux[3] = s_ux[b + HX];
+        uy[0] = s_uy[b];
+        uy[1] = s_uy[b + 1];
+        uy[2] = s_uy[b + HX + 1];
+        uy[3] = s_uy[b + HX];
+    };
+
+    for (int idx = tid; idx < EX * EY; idx += NT) {
+        double x[4], y[4];
+        elem_xy(idx % EX, idx / EX, x, y);
+        s_area[idx] = (s_split[idx] == kAbsent) ? 0.0 : quad_area(x, y);
+    }
+    __syncthreads();
+
+    // ---- 2. smoothed strain and stress at the edges --------------------
+    // horizontal edge (h, v): below element E2(h+1, v) edge 2 (lower id),
+    // above element E2(h+1, v+1) edge 0.  Vertical edge (h, v): left element
+    // E2(h, v+1) edge 1 (lower id), right element E2(h+1, v+1) edge 3.
+    for (int idx = tid; idx < NH + NV; idx += NT) {
+        int elo, klo, ehi, khi;
+        if (idx < NH) {
+            const int h = idx % TXE, v = idx / TXE;
+            elo = v * EX + h + 1;
+            klo = 2;
+            ehi = (v + 1) * EX + h + 1;
+            khi = 0;
+        } else {
+            const int r = idx - NH;
+            const int h = r % (TXE + 1), v = r / (TXE + 1);
+            elo = (v + 1) * EX + h;
+            klo = 1;
+            ehi = (v + 1) * EX + h + 1;
+            khi = 3;
+        }
+        const bool ilo = s_split[elo] == 0, ihi = s_split[ehi] == 0;
+        double eps[3] = {0.0, 0.0, 0.0};
+        double q[2][3];
+        int cnt = 0;
+        for (int side = 0; side < 2; ++side) {
+            const bool in = side ? ihi : ilo;
+            if (!in) continue;
+            const int e = side ? ehi : elo;
+            const int kk = side ? khi : klo;
+            double x[4], y[4], ux[4], uy[4], dndx[4], dndy[4];
+            elem_xy(e % EX, e / EX, x, y);
+            elem_u(e % EX, e / EX, ux, uy);
+            q4_grad(x, y, kk, dndx, dndy);
+            strain<4>(dndx, dndy, ux, uy, q[cnt]);
+            ++cnt;
+        }
+        if (cnt == 1) {
+            eps[0] = q[0][0];
+            eps[1] = q[0][1];
+            eps[2] = q[0][2];
+        } else if (cnt == 2) {
+            const double alo = s_area[elo], ahi = s_area[ehi];
+            const double sum = alo + ahi;
+            const double w0 = alo / sum, w1 = ahi / sum;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) eps[c] = fma(w1, q[1][c], w0 * q[0][c]);
+        }
+        double sg[3] = {0.0, 0.0, 0.0};
+        if (cnt > 0) hooke(p, eps, sg);
+        s_sig[3 * idx + 0] = sg[0];
+        s_sig[3 * idx + 1] = sg[1];
+        s_sig[3 * idx + 2] = sg[2];
+    }
+    __syncthreads();
+
+    // ---- 3. element forces, one thread per element of the tile ring ----
+    const int ie = tid % TXE, je = tid / TXE;
+    const int ex = ie + 1, ey = je + 1;
+    const int e2 = ey * EX + ex;
+    const int gi = i0 - 1 + ie, gj = j0 - 1 + je;
+    const uint8_t code = s_split[e2];
+    // edges of this element in local order 0..3 (bottom, right, top, left)
+    int sidx[4];
+    sidx[0] = je * TXE + ie;
+    sidx[1] = NH + je * (TXE + 1) + ie + 1;
+    sidx[2] = (je + 1) * TXE + ie;
+    sidx[3] = NH + je * (TXE + 1) + ie;
+
+    double fe[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) fe[c] = 0.0;
+    if (code == 0) {
+        double x[4], y[4];
+        elem_xy(ex, ey, x, y);
+        double sx[4], sy[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            double dndx[4], dndy[4];
+            q4_grad(x, y, k, dndx, dndy);
+            const double *sg = &s_sig[3 * sidx[k]];
+            const double s0 = sg[0], s1 = sg[1], s2 = sg[2];
+#pragma unroll
+            for (int n = 0; n < 4; ++n) {
+                const double tx = fma(dndy[n], s2, dndx[n] * s0);
+                const double ty = fma(dndx[n], s2, dndy[n] * s1);
+                if (k == 0) {
+                    sx[n] = tx;
+                    sy[n] = ty;
+                } else {
+                    sx[n] = sx[n] + tx;
+                    sy[n] = sy[n] + ty;
+                }
+            }
+        }
+        const double c = 0.25 * s_area[e2];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            fe[2 * n] = c * sx[n];
+            fe[2 * n + 1] = c * sy[n];
+        }
+    } else if (code & kSplitFlag) {
+        // Split element: two pieces bounded by the crack segment between the
+        // midpoints of the entry and exit edges.  3-node piece -> constant-
+        // strain triangle, 2-node piece -> bar along the uncut edge, 1-node
+        // piece -> no stiffness; each carries its polygon area.
+        double x[4], y[4], ux[4], uy[4];
+        elem_xy(ex, ey, x, y);
+        elem_u(ex, ey, ux, uy);
+        const int ea = (code >> 2) & 3, eb = code & 3;
+        for (int piece = 0; piece < 2; ++piece) {
+            const int from = piece ? eb : ea, to = piece ? ea : eb;
+            int loc[3];
+            int np = 0;
+            for (int k = (from + 1) & 3;; k = (k + 1) & 3) {
+                loc[np++] = k;
+                if (k == to) break;
+            }
+            double px[5], py[5];
+            int nv = 0;
+            px[nv] = 0.5 * (x[from] + x[(from + 1) & 3]);
+            py[nv++] = 0.5 * (y[from] + y[(from + 1) & 3]);
+            for (int i = 0; i < np; ++i) {
+                px[nv] = x[loc[i]];
+                py[nv++] = y[loc[i]];
+            }
+            px[nv] = 0.5 * (x[to] + x[(to + 1) & 3]);
+            py[nv++] = 0.5 * (y[to] + y[(to + 1) & 3]);
+            double s = 0.0;
+            for (int i = 1; i + 1 < nv; ++i)
+                s += (px[i] - px[0]) * (py[i + 1] - py[0]) - (px[i + 1] - px[0]) * (py[i] - py[0]);
+            const double Ap = 0.5 * s;
+            if (np == 3) {
+                const double x1 = px[1], y1 = py[1], x2 = px[2], y2 = py[2], x3 = px[3], y3 = py[3];
+                const double twoA = (x2 - x1) * (y3 - y1) - (x3 - x1) * (y2 - y1);
+                const double inv = 1.0 / twoA;
+                const double b[3] = {(y2 - y3) * inv, (y3 - y1) * inv, (y1 - y2) * inv};
+                const double cc[3] = {(x3 - x2) * inv, (x1 - x3) * inv, (x2 - x1) * inv};
+                double pu[3], pv[3];
+                for (int i = 0; i < 3; ++i) {
+                    pu[i] = ux[loc[i]];
+                    pv[i] = uy[loc[i]];
+                }
+                double eps[3], sg[3];
+                strain<3>(b, cc, pu, pv, eps);
+                hooke(p, eps, sg);
+                for (int i = 0; i < 3; ++i) {
+                    const double tx = fma(cc[i], sg[2], b[i] * sg[0]);
+                    const double ty = fma(b[i], sg[2], cc[i] * sg[1]);
+                    fe[2 * loc[i]] = Ap * tx;
+                    fe[2 * loc[i] + 1] = Ap * ty;
+                }
+            } else if (np == 2) {
+                const int a0 = loc[0], a1 = loc[1];
+                const double dx = x[a1] - x[a0], dy = y[a1] - y[a0];
+                const double L2 = dx * dx + dy * dy;
+                const double dux = ux[a1] - ux[a0], duy = uy[a1] - uy[a0];
+                const double st = (dx * dux + dy * duy) / L2;
+                const double stress = p.E * st;
+                const double coef = Ap * stress / L2;
+                fe[2 * a1] = coef * dx;
+                fe[2 * a1 + 1] = coef * dy;
+                fe[2 * a0] = -(coef * dx);
+                fe[2 * a0 + 1] = -(coef * dy);
+            } else {
+                fe[2 * loc[0]] = 0.0;
+                fe[2 * loc[0] + 1] = 0.0;
+            }
+        }
+    }
+
+    // free-surface candidates of the elements this tile owns (node n0 owned)
+    const bool owned = ie >= 1 && je >= 1 && code == 0;
+    unsigned fmask = 0;
+    if (owned) {
+        const uint8_t nb[4] = {s_split[e2 - EX], s_split[e2 + 1], s_split[e2 + EX], s_split[e2 - 1]};
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (nb[k] != 0) fmask |= 1u << k;
+    }
+    {
+        const int lane = tid & 63, wave = tid >> 6;
+        const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        uint64_t bal[4];
+        int wtotal = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            bal[k] = __ballot((fmask >> k) & 1u);
+            wtotal += __popcll(bal[k]);
+        }
+        if (lane == 0 && wtotal) s_wbase[wave] = atomicAdd(&s_ncand, wtotal);
+        __syncthreads();
+        if (fmask) {
+            int off = s_wbase[wave];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if ((fmask >> k) & 1u) s_cand[off + __popcll(bal[k] & lt)] = (uint16_t)((tid << 2) | k);
+                off += __popcll(bal[k]);
+            }
+        }
+    }
+
+    // ---- colour-ordered scatter to the owned nodes ----------------------
+    const bool valid_e = code != kAbsent;
+    const int color = (gi & 1) + 2 * (gj & 1);
+    for (int c = 0; c < 4; ++c) {
+        if (valid_e && color == c) {
+#pragma unroll
+            for (int n = 0; n < 4; ++n) {
+                const int ln = ie - 1 + ((n == 1 || n == 2) ? 1 : 0);
+                const int mn = je - 1 + ((n >= 2) ? 1 : 0);
+                if (ln >= 0 && ln < TX && mn >= 0 && mn < TY) {
+                    const int t = mn * TX + ln;
+                    s_acc[2 * t] = s_acc[2 * t] + fe[2 * n];
+                    s_acc[2 * t + 1] = s_acc[2 * t + 1] + fe[2 * n + 1];
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- 4. central-difference update of the owned nodes ---------------
+    if (tid < TX * TY) {
+        const int ln = tid % TX, mn = tid / TX;
+        const int ni = i0 + ln, nj = j0 + mn;
+        if (ni <= nx && nj <= ny) {
+            const int64_t n = (int64_t)nj * (nx + 1) + ni;
+            const int hidx = (mn + 2) * HX + (ln + 2);
+            double fex = 0.0, fey = 0.0, v0x = 0.0, v0y = 0.0;
+            unsigned m = 0;
+            const int pidx = perimeter_index(ni, nj, nx, ny);
+            if (pidx >= 0) {
+                fex = p.fext_p[2 * pidx];
+                fey = p.fext_p[2 * pidx + 1];
+                m = p.vmask_p[pidx];
+                v0x = p.v0_p[2 * pidx];
+                v0y = p.v0_p[2 * pidx + 1];
+            }
+            const double mi = p.minv[n];
+            double ax = (fex - s_acc[2 * tid]) * mi;
+            double ay = (fey - s_acc[2 * tid + 1]) * mi;
+            if (m & 1u) ax = 0.0;
+            if (m & 2u) ay = 0.0;
+            const double dtv = (kstep == 0) ? 0.5 * p.dt : p.dt;
+            const double th = ((double)kstep + 0.5) * p.dt;
+            double vx = p.vx[n] + dtv * ax;
+            double vy = p.vy[n] + dtv * ay;
+            if (m & 1u) vx = prescribed(v0x, th, p.t_ramp);
+            if (m & 2u) vy = prescribed(v0y, th, p.t_ramp);
+            p.vx[n] = vx;
+            p.vy[n] = vy;
+            ux_n[n] = s_ux[hidx] + p.dt * vx;
+            uy_n[n] = s_uy[hidx] + p.dt * vy;
+        }
+    }
+
+    // ---- 5. energy release rate and element rule of the candidates ------
+    Cand best;
+    cand_none(best);
+    const int ncand = s_ncand;
+    for (int c = tid; c < ncand; c += NT) {
+        const int t = s_cand[c] >> 2, a = s_cand[c] & 3;
+        const int cie = t % TXE, cje = t / TXE;
+        const int cex = cie + 1, cey = cje + 1;
+        const int64_t ge = (int64_t)(j0 - 1 + cje) * nx + (i0 - 1 + cie);
+        double x[4], y[4], ux[4], uy[4];
+        elem_xy(cex, cey, x, y);
+        elem_u(cex, cey, ux, uy);
+        const int n1 = a, n2 = (a + 1) & 3;
+        const double dux = ux[n2] - ux[n1], duy = uy[n2] - uy[n1];
+        const double x1 = x[n1] + ux[n1], y1 = y[n1] + uy[n1];
+        const double x2 = x[n2] + ux[n2], y2 = y[n2] + uy[n2];
+        const double lx = x2 - x1, ly = y2 - y1;
+        const double Lx = x[n2] - x[n1], Ly = y[n2] - y[n1];
+        const bool H = (lx * lx + ly * ly) > (Lx * Lx + Ly * Ly);
+        if (!H) continue;  // G = 0 on all three paths
+        int cs[4];
+        cs[0] = cje * TXE + cie;
+        cs[1] = NH + cje * (TXE + 1) + cie + 1;
+        cs[2] = (cje + 1) * TXE + cie;
+        cs[3] = NH + cje * (TXE + 1) + cie;
+        const double *gm = p.geom + ge * 36 + a * 9;
+        double G[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int k = (a + 1 + j) & 3;
+            const double *sg = &s_sig[3 * cs[k]];
+            const double nxv = gm[3 * j], nyv = gm[3 * j + 1];
+            const double spx = fma(sg[2], nyv, sg[0] * nxv);
+            const double spy = fma(sg[1], nyv, sg[2] * nxv);
+            G[j] = 0.5 * fma(duy, spy, dux * spx);
+        }
+        const double gc = p.gc ? p.gc[ge] : p.gc_uniform;
+        int jb = -1;
+        for (int j = 0; j < 3; ++j)
+            if (G[j] > gc && (jb < 0 || G[j] > G[jb])) jb = j;
+        if (jb < 0) continue;
+        bool ok = true;
+        for (int j = 0; j < 3; ++j) {
+            if (j == jb || !(G[j] > gc)) continue;
+            if (!(G[jb] > p.gamma * (G[jb] - G[j]))) ok = false;
+        }
+        if (!ok) continue;
+        cand_merge(best, G[jb], G[jb], (int)ge, a, (a + 1 + jb) & 3);
+    }
+    cand_block_reduce<NT>(best, s_red);
+
+    // ---- 6. publish, and let the last workgroup decide ------------------
+    if (tid == 0) {
+        if (best.G >= 0.0) {
+            const uint32_t slot = atomicAdd(&p.ctl->nslots, 1u);
+            Slot sl;
+            sl.G = best.G;
+            sl.Gmin = best.Gmin;
+            sl.elem = best.e;
+            sl.a = best.a;
+            sl.k = best.k;
+            sl.pad = 0;
+            p.slots[slot] = sl;
+        }
+        __threadfence();
+        const uint32_t prev = atomicAdd(&p.ctl->arrive, 1u);
+        s_last = (prev == (uint32_t)(p.nwg - 1));
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    const uint32_t nslots = __hip_atomic_load(&p.ctl->nslots, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    Cand g;
+    cand_none(g);
+    for (uint32_t s = tid; s < nslots; s += NT) {
+        const Slot sl = p.slots[s];
+        cand_merge(g, sl.G, sl.Gmin, sl.elem, sl.a, sl.k);
+    }
+    cand_block_reduce<NT>(g, s_red);
+    if (tid == 0) {
+        Control *ctl = p.ctl;
+        // MCT pick: the largest G must pass G* > gamma (G* - G_c) against
+        // every other accepted candidate; (G* - G_c) grows as G_c shrinks
+        // and rounding is monotone, so the smallest accepted G decides.
+        if (g.G >= 0.0 && g.G > p.gamma * (g.G - g.Gmin)) {
+            p.split[g.e] = (uint8_t)(kSplitFlag | (g.a << 2) | g.k);
+            const int64_t n = ctl->nsplit;
+            if (n < p.log_cap) {
+                LogRec r;
+                r.step = (int32_t)kstep;
+                r.elem = g.e;
+                r.entry = (uint8_t)g.a;
+                r.exit = (uint8_t)g.k;
+                r.pad0 = r.pad1 = 0;
+                r.pad2 = 0;
+                r.G = g.G;
+                p.log[n] = r;
+            } else {
+                ctl->overflow = 1;
+            }
+            ctl->nsplit = n + 1;
+            const int jk = (g.k - g.a - 1) & 3;
+            const double gc = p.gc ? p.gc[g.e] : p.gc_uniform;
+            ctl->Ud = ctl->Ud + gc * p.geom[(int64_t)g.e * 36 + g.a * 9 + 3 * jk + 2];
+        }
+        ctl->nslots = 0;
+        ctl->arrive = 0;
+        ctl->step = kstep + 1;
+    }
+}
+
+TileShape tile_shape(int tile) {
+    switch (tile) {
+        case 1: return {16, 16};
+        case 2: return {32, 8};
+        default: return {32, 16};
+    }
+}
+
+hipError_t launch_step(int tile, const StepParams &p, hipStream_t s) {
+    switch (tile) {
+        case 1: k_step<16, 16><<<p.nwg, 256, 0, s>>>(p); break;
+        case 2: k_step<32, 8><<<p.nwg, 256, 0, s>>>(p); break;
+        default: k_step<32, 16><<<p.nwg, 512, 0, s>>>(p); break;
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------
+// Crack-surface tips: interior edges with exactly one intact neighbour.
+// Three passes give an order-preserving compaction (per-block counts with
+// ballots, a scan of the block counts, an in-order write).
+// ------------------------------------------------------------------------
+namespace {
+constexpr int kTipBlock = 256;
+
+struct EdgeInfo {
+    int lo, hi;    // node ids
+    int e0, e1;    // neighbour elements (-1 if none)
+};
+
+__device__ __forceinline__ EdgeInfo edge_info(int64_t s, int nx, int ny) {
+    EdgeInfo r;
+    const int64_t row = 2 * (int64_t)nx + 1;
+    int i, j;
+    bool horiz;
+    if (s < (int64_t)ny * row) {
+        j = (int)(s / row);
+        const int q = (int)(s % row);
+        if (q < 2 * nx) {
+            i = q >> 1;
+            horiz = (q & 1) == 0;
+        } else {
+            i = nx;
+            horiz = false;
+        }
+    } else {
+        j = ny;
+        i = (int)(s - (int64_t)ny * row);
+        horiz = true;
+    }
+    r.lo = j * (nx + 1) + i;
+    if (horiz) {
+        r.hi = r.lo + 1;
+        r.e0 = (j > 0) ? (j - 1) * nx + i : -1;
+        r.e1 = (j < ny) ? j * nx + i : -1;
+    } else {
+        r.hi = r.lo + nx + 1;
+        r.e0 = (i > 0) ? j * nx + i - 1 : -1;
+        r.e1 = (i < nx) ? j * nx + i : -1;
+    }
+    return r;
+}
+
+__device__ __forceinline__ bool is_tip(const EdgeInfo &ei, const uint8_t *split) {
+    if (ei.e0 < 0 || ei.e1 < 0) return false;
+    return ((split[ei.e0] == 0) + (split[ei.e1] == 0)) == 1;
+}
+
+__global__ __launch_bounds__(kTipBlock) void k_tips_count(int nx, int ny, int64_t ns, const uint8_t *split,
+                                                          int32_t *counts) {
+    __shared__ int s_w[kTipBlock / 64];
+    const int64_t s = (int64_t)blockIdx.x * kTipBlock + threadIdx.x;
+    bool t = false;
+    if (s < ns) t = is_tip(edge_info(s, nx, ny), split);
+    const uint64_t b = __ballot(t);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = __popcll(b);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int c = 0;
+        for (int w = 0; w < kTipBlock / 64; ++w) c += s_w[w];
+        counts[blockIdx.x] = c;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_tips_scan(int32_t *counts, int nblocks, int32_t *total) {
+    // exclusive scan in place, one workgroup, sequential chunks
+    __shared__ int s_v[1024];
+    __shared__ int s_carry;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nblocks; base += 1024) {
+        const int i = base + threadIdx.x;
+        const int v = (i < nblocks) ? counts[i] : 0;
+        s_v[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const int t = (threadIdx.x >= off) ? s_v[threadIdx.x - off] : 0;
+            __syncthreads();
+            s_v[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < nblocks) counts[i] = s_carry + s_v[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == 0) s_carry += s_v[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = s_carry;
+}
+
+__global__ __launch_bounds__(kTipBlock) void k_tips_write(int nx, int ny, int64_t ns, const double *X,
+                                                          const double *Y, const uint8_t *split,
+                                                          const int32_t *offsets, int32_t *edge_out,
+                                                          double *xy_out) {
+    __shared__ int s_w[kTipBlock / 64];
+    const int64_t s = (int64_t)blockIdx.x * kTipBlock + threadIdx.x;
+    EdgeInfo ei{0, 0, -1, -1};
+    bool t = false;
+    if (s < ns) {
+        ei = edge_info(s, nx, ny);
+        t = is_tip(ei, split);
+    }
+    const uint64_t b = __ballot(t);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) s_w[wave] = __popcll(b);
+    __syncthreads();
+    if (t) {
+        int off = offsets[blockIdx.x];
+        for (int w = 0; w < wave; ++w) off += s_w[w];
+        const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        off += __popcll(b & lt);
+        edge_out[off] = (int32_t)s;
+        xy_out[2 * off] = 0.5 * (X[ei.lo] + X[ei.hi]);
+        xy_out[2 * off + 1] = 0.5 * (Y[ei.lo] + Y[ei.hi]);
+    }
+}
+}  // namespace
+
+int tips_nblocks(int64_t n_edges) { return (int)((n_edges + kTipBlock - 1) / kTipBlock); }
+
+hipError_t launch_tips(int32_t nx, int32_t ny, const double *X, const double *Y, const uint8_t *split,
+                       int32_t *block_counts, int32_t *nblocks_out, int32_t *edge_out, double *xy_out,
+                       int32_t *count_out, hipStream_t s) {
+    const int64_t ns = 2 * (int64_t)nx * ny + nx + ny;
+    const int nb = tips_nblocks(ns);
+    *nblocks_out = nb;
+    k_tips_count<<<nb, kTipBlock, 0, s>>>(nx, ny, ns, split, block_counts);
+    k_tips_scan<<<1, 1024, 0, s>>>(block_counts, nb, count_out);
+    if (edge_out) k_tips_write<<<nb, kTipBlock, 0, s>>>(nx, ny, ns, X, Y, split, block_counts, edge_out, xy_out);
+    return hipGetLastError();
+}
+
+}  // namespace mct

@@ -1,0 +1,237 @@
+"""Thin ctypes binding of libmct2d.so (include/mct2d.h).
+
+Argument marshalling only: every computation of the step runs in the HIP
+kernels behind the C ABI.  There is no fallback: if the shared library has
+not been built, importing the binding raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "_lib", "libmct2d.so")
+
+MCT_OK = 0
+MCT_ECAPACITY = -3
+FIELD_U = 0
+FIELD_V = 1
+
+
+class MctError(RuntimeError):
+    pass
+
+
+class Info(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("n_elems", C.c_int64), ("n_edges", C.c_int64),
+                ("step", C.c_int64), ("n_splits", C.c_int64), ("dt", C.c_double),
+                ("dissipated", C.c_double), ("log_overflow", C.c_int32), ("precision", C.c_int32)]
+
+
+EXPORTS = [
+    "mct_create", "mct_destroy", "mct_last_error", "mct_set_mesh_grid", "mct_set_material",
+    "mct_set_traction", "mct_set_velocity_bc", "mct_set_notch", "mct_set_time", "mct_finalize",
+    "mct_step", "mct_sync", "mct_get_info", "mct_get_crack_set", "mct_get_tips", "mct_get_field",
+    "mct_get_split_codes", "mct_checkpoint", "mct_restore", "mct_set_launch",
+]
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load the HIP library; raises if it was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise MctError("libmct2d.so is not built (run python -m paper_2509_01827_amd.build)")
+    L = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    dp = np.ctypeslib.ndpointer(np.float64, flags="C")
+    ip = np.ctypeslib.ndpointer(np.int32, flags="C")
+    bp = np.ctypeslib.ndpointer(np.uint8, flags="C")
+    L.mct_create.argtypes = [C.POINTER(P), C.c_int, P]
+    L.mct_destroy.argtypes = [P]
+    L.mct_last_error.argtypes = [P]
+    L.mct_last_error.restype = C.c_char_p
+    L.mct_set_mesh_grid.argtypes = [P, C.c_int32, C.c_int32, dp, dp]
+    L.mct_set_material.argtypes = [P, C.c_double, C.c_double, C.c_double, P, C.c_double, C.c_double]
+    L.mct_set_traction.argtypes = [P, C.c_int64, ip, dp]
+    L.mct_set_velocity_bc.argtypes = [P, C.c_int64, ip, bp, dp, C.c_double]
+    L.mct_set_notch.argtypes = [P, C.c_int64, ip, bp, bp]
+    L.mct_set_time.argtypes = [P, C.c_double, C.c_double]
+    L.mct_finalize.argtypes = [P]
+    L.mct_step.argtypes = [P, C.c_int64]
+    L.mct_sync.argtypes = [P]
+    L.mct_get_info.argtypes = [P, C.POINTER(Info)]
+    L.mct_get_crack_set.argtypes = [P, C.c_int64, P, P, P, P, P, C.POINTER(C.c_int64)]
+    L.mct_get_tips.argtypes = [P, C.c_int64, P, P, C.POINTER(C.c_int64)]
+    L.mct_get_field.argtypes = [P, C.c_int, C.c_int64, dp]
+    L.mct_get_split_codes.argtypes = [P, C.c_int64, bp]
+    L.mct_checkpoint.argtypes = [P, P, C.c_int64, C.POINTER(C.c_int64)]
+    L.mct_restore.argtypes = [P, P, C.c_int64]
+    L.mct_set_launch.argtypes = [P, C.c_int, C.c_int]
+    _lib = L
+    return L
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _u8(a):
+    return np.ascontiguousarray(a, dtype=np.uint8)
+
+
+class Model:
+    """One MCT-2D-CEM model on the current HIP device.
+
+    ``stream`` is a raw hipStream_t handle (an int, e.g.
+    ``torch.cuda.current_stream().cuda_stream``) or None for a library
+    stream."""
+
+    def __init__(self, precision: int = 64, stream: int | None = None):
+        L = load()
+        h = C.c_void_p()
+        rc = L.mct_create(C.byref(h), int(precision), C.c_void_p(stream) if stream else None)
+        if rc != MCT_OK:
+            raise MctError("mct_create failed: %d" % rc)
+        self._h = h
+        self._L = L
+
+    def _check(self, rc, what=""):
+        if rc != MCT_OK:
+            msg = self._L.mct_last_error(self._h).decode(errors="replace")
+            raise MctError("%s failed (%d): %s" % (what, rc, msg))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.mct_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- set-up ---------------------------------------------------------
+    def set_mesh_grid(self, nx, ny, X, Y):
+        self._check(self._L.mct_set_mesh_grid(self._h, int(nx), int(ny), _f64(X), _f64(Y)), "set_mesh_grid")
+
+    def set_material(self, E, nu, rho, gc=None, gc_uniform=0.0, gamma=1.0):
+        self._gc = None if gc is None else _f64(gc)
+        ptr = None if self._gc is None else self._gc.ctypes.data
+        self._check(self._L.mct_set_material(self._h, float(E), float(nu), float(rho), ptr,
+                                             float(gc_uniform), float(gamma)), "set_material")
+
+    def set_traction(self, edge_nodes, t):
+        en = _i32(np.asarray(edge_nodes).reshape(-1))
+        self._check(self._L.mct_set_traction(self._h, len(en) // 2, en, _f64(np.asarray(t).reshape(-1))),
+                    "set_traction")
+
+    def set_velocity_bc(self, nodes, mask, v0, t_ramp=0.0):
+        nodes = _i32(nodes)
+        self._check(self._L.mct_set_velocity_bc(self._h, len(nodes), nodes, _u8(mask),
+                                                _f64(np.asarray(v0).reshape(-1)), float(t_ramp)),
+                    "set_velocity_bc")
+
+    def set_notch(self, elem, entry, exit_):
+        elem = _i32(elem)
+        self._check(self._L.mct_set_notch(self._h, len(elem), elem, _u8(entry), _u8(exit_)), "set_notch")
+
+    def set_time(self, dt=0.0, cfl=0.5):
+        self._check(self._L.mct_set_time(self._h, float(dt), float(cfl)), "set_time")
+
+    def set_launch(self, tile=0, use_graph=True):
+        self._check(self._L.mct_set_launch(self._h, int(tile), int(bool(use_graph))), "set_launch")
+
+    def finalize(self):
+        self._check(self._L.mct_finalize(self._h), "finalize")
+
+    # -- run ------------------------------------------------------------
+    def step(self, n):
+        self._check(self._L.mct_step(self._h, int(n)), "step")
+
+    def sync(self):
+        self._check(self._L.mct_sync(self._h), "sync")
+
+    # -- queries --------------------------------------------------------
+    def info(self) -> dict:
+        inf = Info()
+        self._check(self._L.mct_get_info(self._h, C.byref(inf)), "get_info")
+        return {k: getattr(inf, k) for k, _ in Info._fields_}
+
+    def crack_set(self) -> dict:
+        cnt = C.c_int64(0)
+        rc = self._L.mct_get_crack_set(self._h, 0, None, None, None, None, None, C.byref(cnt))
+        if rc not in (MCT_OK, MCT_ECAPACITY):
+            self._check(rc, "get_crack_set")
+        n = cnt.value
+        st, el = np.zeros(n, np.int32), np.zeros(n, np.int32)
+        en, ex = np.zeros(n, np.uint8), np.zeros(n, np.uint8)
+        G = np.zeros(n)
+        self._check(self._L.mct_get_crack_set(self._h, n, st.ctypes.data, el.ctypes.data, en.ctypes.data,
+                                              ex.ctypes.data, G.ctypes.data, C.byref(cnt)), "get_crack_set")
+        return dict(step=st, elem=el, entry=en, exit=ex, G=G)
+
+    def tips(self):
+        cnt = C.c_int64(0)
+        rc = self._L.mct_get_tips(self._h, 0, None, None, C.byref(cnt))
+        if rc not in (MCT_OK, MCT_ECAPACITY):
+            self._check(rc, "get_tips")
+        n = cnt.value
+        edge = np.zeros(n, np.int32)
+        xy = np.zeros(2 * n)
+        self._check(self._L.mct_get_tips(self._h, n, edge.ctypes.data, xy.ctypes.data, C.byref(cnt)), "get_tips")
+        return edge, xy.reshape(-1, 2)
+
+    def field(self, which=FIELD_U):
+        nn = self.info()["n_nodes"]
+        out = np.zeros(2 * nn)
+        self._check(self._L.mct_get_field(self._h, int(which), 2 * nn, out), "get_field")
+        return out[:nn], out[nn:]
+
+    def split_codes(self):
+        ne = self.info()["n_elems"]
+        out = np.zeros(ne, np.uint8)
+        self._check(self._L.mct_get_split_codes(self._h, ne, out), "get_split_codes")
+        return out
+
+    def checkpoint(self) -> bytes:
+        nb = C.c_int64(0)
+        self._check(self._L.mct_checkpoint(self._h, None, 0, C.byref(nb)), "checkpoint")
+        buf = C.create_string_buffer(nb.value)
+        self._check(self._L.mct_checkpoint(self._h, C.cast(buf, C.c_void_p), nb.value, C.byref(nb)), "checkpoint")
+        return buf.raw[: nb.value]
+
+    def restore(self, data: bytes):
+        buf = C.create_string_buffer(data, len(data))
+        self._check(self._L.mct_restore(self._h, C.cast(buf, C.c_void_p), len(data)), "restore")
+
+
+def from_config(cfg: dict, stream: int | None = None, tile: int = 0, use_graph: bool = True) -> Model:
+    """Build and finalize a model from a workload dictionary
+    (paper_2509_01827_amd.workloads)."""
+    m = Model(64, stream)
+    m.set_mesh_grid(cfg["nx"], cfg["ny"], cfg["X"], cfg["Y"])
+    m.set_material(cfg["E"], cfg["nu"], cfg["rho"], cfg.get("gc_field"), cfg.get("gc_uniform", 0.0),
+                   cfg.get("gamma", 1.0))
+    m.set_traction(cfg["traction_nodes"], cfg["traction"])
+    vn, vm, vv = cfg["vbc"]
+    m.set_velocity_bc(vn, vm, vv, cfg.get("t_ramp", 0.0))
+    ne_, en_, ex_ = cfg["notch"]
+    m.set_notch(ne_, en_, ex_)
+    m.set_time(cfg.get("dt", 0.0), cfg.get("cfl", 0.5))
+    m.set_launch(tile, use_graph)
+    m.finalize()
+    return m
