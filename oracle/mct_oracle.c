@@ -43,8 +43,14 @@
  *
  * FP contract (binds the HIP library as well): IEEE binary64, round to
  * nearest, compiled with -ffp-contract=off; fma() only where written.
+ *
+ * Loops whose iterations write disjoint outputs (edges, elements, elements
+ * of one colour, nodes, candidate evaluation) may run on several OpenMP
+ * threads; every value is still computed by one thread in the order written
+ * here, so results do not depend on the thread count.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -196,6 +202,7 @@ static int is_intact(const orc_model_t *m, int e) { return e >= 0 && m->split[e]
 /* ------------------------------------------------------------------ */
 
 static void edge_stresses(orc_model_t *m) {
+#pragma omp parallel for schedule(static)
     for (int s = 0; s < m->ns; ++s) {
         double q[2][3], A[2];
         int cnt = 0;
@@ -347,6 +354,7 @@ static double split_force(const orc_model_t *m, int e, double f[8]) {
 /* a1 + a2 + a3: internal nodal forces of the current displacement */
 static void internal_forces(orc_model_t *m) {
     edge_stresses(m);
+#pragma omp parallel for schedule(static)
     for (int e = 0; e < m->ne; ++e) {
         if (m->split[e] == 0)
             intact_force(m, e, &m->fe[8 * e]);
@@ -358,6 +366,7 @@ static void internal_forces(orc_model_t *m) {
      * order */
     for (int i = 0; i < m->nn; ++i) m->fx[i] = m->fy[i] = 0.0;
     for (int c = 0; c < m->ncolor; ++c)
+#pragma omp parallel for schedule(static)
         for (int e = 0; e < m->ne; ++e) {
             if (m->color[e] != c) continue;
             for (int n = 0; n < 4; ++n) {
@@ -472,20 +481,35 @@ static void fracture_phase(orc_model_t *m) {
     double *cG = malloc(sizeof(double) * (size_t)cap);
     int *cE = malloc(sizeof(int) * (size_t)cap), *cA = malloc(sizeof(int) * (size_t)cap);
     int *cK = malloc(sizeof(int) * (size_t)cap);
-    int nc = 0;
+    /* per edge: accepted path index or -1 (evaluated independently) */
+    int *acc = malloc(sizeof(int) * (size_t)cap);
+    double *accG = malloc(sizeof(double) * (size_t)cap);
+#pragma omp parallel for schedule(dynamic, 4096)
     for (int s = 0; s < m->ns; ++s) {
         int f, a;
+        acc[s] = -1;
         if (!edge_candidate(m, s, &f, &a)) continue;
         double G[3];
         candidate_G(m, f, a, G);
         int j = orc_element_rule(G, m->Gc[f], m->gamma);
         if (j < 0) continue;
-        cG[nc] = G[j];
+        acc[s] = j;
+        accG[s] = G[j];
+    }
+    /* accepted candidates in edge-id order */
+    int nc = 0;
+    for (int s = 0; s < m->ns; ++s) {
+        if (acc[s] < 0) continue;
+        int f, a;
+        edge_candidate(m, s, &f, &a);
+        cG[nc] = accG[s];
         cE[nc] = f;
         cA[nc] = a;
-        cK[nc] = (a + 1 + j) & 3;
+        cK[nc] = (a + 1 + acc[s]) & 3;
         nc++;
     }
+    free(acc);
+    free(accG);
     int c = orc_mct_pick(nc, cG, cE, cA, m->gamma);
     if (c >= 0) {
         int f = cE[c], a = cA[c], k = cK[c];
@@ -517,6 +541,7 @@ static double prescribed(const orc_model_t *m, double v0, double t) {
 
 static void one_step(orc_model_t *m) {
     internal_forces(m);
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < m->nn; ++i) {
         m->ax[i] = (m->fext[2 * i] - m->fx[i]) * m->minv[i];
         m->ay[i] = (m->fext[2 * i + 1] - m->fy[i]) * m->minv[i];
@@ -527,6 +552,7 @@ static void one_step(orc_model_t *m) {
     fracture_phase(m);
     double dtv = (m->step == 0) ? 0.5 * m->dt : m->dt;
     double th = ((double)m->step + 0.5) * m->dt;
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < m->nn; ++i) {
         double vx = m->vx[i] + dtv * m->ax[i];
         double vy = m->vy[i] + dtv * m->ay[i];
@@ -962,3 +988,7 @@ int orc_path_normal(const orc_model_t *m, int e, int a, int k, double out[3]) {
 }
 
 void orc_split_codes(orc_model_t *m, const unsigned char *codes) { memcpy(m->split, codes, m->ne); }
+
+/* number of OpenMP threads the oracle uses (results do not depend on it) */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_get_threads(void) { return omp_get_max_threads(); }

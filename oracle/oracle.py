@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mct_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math"]
+CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math", "-fopenmp"]
 
 
 def build(force: bool = False) -> str:
@@ -63,6 +63,8 @@ def lib():
         _lib.orc_split_codes.argtypes = [P, bp]
         _lib.orc_element_rule.argtypes = [dp, C.c_double, C.c_double]
         _lib.orc_mct_pick.argtypes = [C.c_int, dp, ip, ip, C.c_double]
+        _lib.orc_set_threads.argtypes = [C.c_int]
+        _lib.orc_get_threads.restype = C.c_int
     return _lib
 
 
@@ -76,6 +78,15 @@ def _i32(a):
 
 def _u8(a):
     return np.ascontiguousarray(a, dtype=np.uint8)
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads used by the oracle (results are thread-count independent)."""
+    lib().orc_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().orc_get_threads())
 
 
 def element_rule(G3, Gc, gamma):

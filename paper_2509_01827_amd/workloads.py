@@ -212,3 +212,34 @@ def small_cases():
         "fragment97x45": fragmentation(97, 45, 1.0e-3, seed=BASE_SEED + 13,
                                        steps=400, name="fragment97x45"),
     }
+
+
+def batch_specimens(n=256, *, seed=BASE_SEED + 4, steps=5000, nx_range=(64, 512),
+                    ny_range=(64, 256), h=1.0e-3):
+    """Independent notched specimens of uneven size (the batched workload).
+
+    Specimen s takes five uniforms u0..u4 from one SplitMix64 stream (seed,
+    specimen order): nx = U{nx_range}, ny = U{ny_range}, notch length
+    round(U(0.2, 0.6) nx) in row ny // 2, Weibull scale lambda = U(2, 4) N/m,
+    traction U(0.5, 1.5) MPa; its Gc field uses the stream seed + 1000 (s+1)
+    (Weibull shape 6).  Square elements of side h, so all share one time
+    step."""
+    u = uniform01(seed, 5 * n).reshape(n, 5)
+    out = []
+    for s in range(n):
+        nx = nx_range[0] + int(u[s, 0] * (nx_range[1] - nx_range[0] + 1))
+        ny = ny_range[0] + int(u[s, 1] * (ny_range[1] - ny_range[0] + 1))
+        notch = int(round((0.2 + 0.4 * u[s, 2]) * nx))
+        lam = 2.0 + 2.0 * u[s, 3]
+        trac = (0.5 + u[s, 4]) * 1.0e6
+        gcf = weibull_gc(seed + 1000 * (s + 1), nx * ny, 6.0, lam)
+        c = plate(nx, ny, nx * h, ny * h, traction=trac, notch_len=notch, gc=0.0,
+                  gc_field=gcf, steps=steps, name="specimen%d" % s)
+        out.append(c)
+    return out
+
+
+def small_batch(n=12, steps=600):
+    """A batch the oracle finishes in seconds (parity tests)."""
+    return batch_specimens(n, seed=BASE_SEED + 40, steps=steps, nx_range=(8, 48),
+                           ny_range=(6, 40))

@@ -15,6 +15,8 @@ a wrong sign or index, a transposed operand, a wrong weight) fails it:
   * rule tables for the element decision and the MCT pick (Sec. 2.2 and
     Sec. 3 inequalities, gamma in {1, 2}, ties, strict '>' at Gc).
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -569,3 +571,17 @@ def test_candidate_and_tip_sets_of_notched_plate(oracle_mod):
     assert len(tips) == 2 * L + 1
     ahead = [s for s in tips if np.isclose(xy[list(tips).index(s), 0], L * 1e-3)]
     assert len(ahead) == 1
+
+
+def test_oracle_thread_count_independent(oracle_mod):
+    c = W.small_cases()["plate70x37_jitter"]
+    outs = []
+    for th in (1, 5):
+        oracle_mod.set_threads(th)
+        o = oracle_mod.run(c, 400)
+        outs.append((o.state(), o.log()))
+    oracle_mod.set_threads(os.cpu_count() or 1)
+    (s1, l1), (s2, l2) = outs
+    for k in ("ux", "uy", "vx", "vy", "split"):
+        assert np.array_equal(s1[k], s2[k])
+    assert np.array_equal(l1["elem"], l2["elem"]) and np.array_equal(l1["G"], l2["G"])
