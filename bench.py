@@ -23,6 +23,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+WORKLOADS = {
+    "plate400": "branching plate 400x400 Q4, 100x40 mm, jitter 1%, notch 50 mm, 1 MPa",
+    "fragment2000": "fragmentation plate 2000x1000 Q4, h 0.1 mm, 5 m/s outward, Weibull(6,3) Gc",
+}
 
 
 def bytes_per_step(nx: int, ny: int) -> int:
@@ -54,7 +58,23 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", default="plate400", choices=["plate400", "fragment2000"],
+                    help="plate400: the 400x400 branching plate (default); fragment2000: the "
+                         "2000x1000 Dirichlet fragmentation plate")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (three times), "
+                         "to calibrate the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        n = args.copy_probe * (1 << 20) // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": 8 * n, "repeats": 3}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d refused)" % args.gpus,
               file=sys.stderr)
@@ -64,7 +84,7 @@ def main():
     from paper_2509_01827_amd import mct2d, workloads as W
 
     torch.cuda.set_device(0)
-    cfg = W.config2()
+    cfg = W.config2() if args.workload == "plate400" else W.config3()
     nx, ny = cfg["nx"], cfg["ny"]
     ne = nx * ny
     stream = torch.cuda.Stream()
@@ -106,7 +126,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "branching plate 400x400 Q4, 100x40 mm, jitter 1%, notch 50 mm, 1 MPa",
+        "config": {"workload": WORKLOADS[args.workload],
                    "elements": ne, "nodes": (nx + 1) * (ny + 1), "time_steps": args.steps,
                    "tile": args.tile, "graph": not args.no_graph},
         "wall_s": wall,

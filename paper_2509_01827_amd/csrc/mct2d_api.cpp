@@ -29,12 +29,6 @@ struct TractionEdge {
     double tx, ty;
 };
 
-template <typename T>
-struct DevBuf {
-    T *p = nullptr;
-    size_t n = 0;
-};
-
 }  // namespace
 
 struct mct_ctx {
@@ -79,8 +73,9 @@ struct mct_ctx {
     double *dtip_xy = nullptr;
     StepParams prm{};
 
-    hipGraphExec_t graph = nullptr;
-    int graph_tile = 0;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};  // by parity of the first step
+    int graph_tile[2] = {0, 0};
+    int64_t steps_enqueued = 0;  // host view of the step counter
 };
 
 namespace {
@@ -108,9 +103,15 @@ void dfree(T *&p) {
     p = nullptr;
 }
 
+void drop_graphs(mct_ctx *c) {
+    for (int i = 0; i < 2; ++i) {
+        if (c->graph[i]) (void)hipGraphExecDestroy(c->graph[i]);
+        c->graph[i] = nullptr;
+    }
+}
+
 void release_device(mct_ctx *c) {
-    if (c->graph) (void)hipGraphExecDestroy(c->graph);
-    c->graph = nullptr;
+    drop_graphs(c);
     dfree(c->dX);
     dfree(c->dY);
     for (int i = 0; i < 2; ++i) {
@@ -207,21 +208,24 @@ void set_launch_geometry(mct_ctx *c) {
     c->prm.nwg = c->prm.ntx * c->prm.nty;
 }
 
-int build_graph(mct_ctx *c) {
-    if (c->graph) (void)hipGraphExecDestroy(c->graph);
-    c->graph = nullptr;
+// A segment of kGraphSteps steps followed by its commit, captured once per
+// parity of the segment's first step.
+int build_graph(mct_ctx *c, int par0) {
+    if (c->graph[par0]) (void)hipGraphExecDestroy(c->graph[par0]);
+    c->graph[par0] = nullptr;
     hipStream_t cap;
     HIP_TRY(c, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
-    for (int i = 0; e == hipSuccess && i < kGraphSteps; ++i) e = mct::launch_step(c->tile, c->prm, cap);
+    for (int i = 0; e == hipSuccess && i < kGraphSteps; ++i) e = mct::launch_step(c->tile, c->prm, i, par0, cap);
+    if (e == hipSuccess) e = mct::launch_commit(c->prm, kGraphSteps, cap);
     hipError_t e2 = hipStreamEndCapture(cap, &g);
     if (e == hipSuccess) e = e2;
-    if (e == hipSuccess) e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphInstantiate(&c->graph[par0], g, nullptr, nullptr, 0);
     if (g) (void)hipGraphDestroy(g);
     (void)hipStreamDestroy(cap);
     if (e != hipSuccess) return fail(c, MCT_EDEVICE, "graph capture: %s", hipGetErrorString(e));
-    c->graph_tile = c->tile;
+    c->graph_tile[par0] = c->tile;
     return MCT_OK;
 }
 
@@ -390,14 +394,12 @@ int mct_set_launch(mct_ctx *c, int tile, int use_graph) {
     c->tile_req = tile;
     c->use_graph = use_graph != 0;
     if (c->finalized) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
         set_launch_geometry(c);
-        if (c->graph && c->graph_tile != c->tile) {
-            (void)hipGraphExecDestroy(c->graph);
-            c->graph = nullptr;
-        }
-        // slots must hold one entry per workgroup of the chosen shape
+        drop_graphs(c);
+        // three slot sets of one entry per workgroup of the chosen shape
         dfree(c->dslots);
-        HIP_TRY(c, hipMalloc((void **)&c->dslots, sizeof(Slot) * (size_t)c->prm.nwg));
+        HIP_TRY(c, hipMalloc((void **)&c->dslots, 3 * sizeof(Slot) * (size_t)c->prm.nwg));
         c->prm.slots = c->dslots;
     }
     return MCT_OK;
@@ -525,7 +527,7 @@ int mct_finalize(mct_ctx *c) {
     HIP_TRY(c, hipMemsetAsync(c->dvy, 0, sizeof(double) * c->nn, c->stream));
     HIP_TRY(c, hipMalloc((void **)&c->dctl, sizeof(Control)));
     HIP_TRY(c, hipMemsetAsync(c->dctl, 0, sizeof(Control), c->stream));
-    HIP_TRY(c, hipMalloc((void **)&c->dslots, sizeof(Slot) * (size_t)c->prm.nwg));
+    HIP_TRY(c, hipMalloc((void **)&c->dslots, 3 * sizeof(Slot) * (size_t)c->prm.nwg));
     HIP_TRY(c, hipMalloc((void **)&c->dlog, sizeof(LogRec) * (size_t)std::max(c->log_cap, 1)));
     const int nb = mct::tips_nblocks(c->ns);
     HIP_TRY(c, hipMalloc((void **)&c->dtip_counts, sizeof(int32_t) * (size_t)nb));
@@ -562,6 +564,7 @@ int mct_finalize(mct_ctx *c) {
     p.slots = c->dslots;
     p.log = c->dlog;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->steps_enqueued = 0;
     c->finalized = true;
     return MCT_OK;
 }
@@ -571,17 +574,27 @@ int mct_step(mct_ctx *c, int64_t n) {
     if (!c->finalized) return fail(c, MCT_ESTATE, "finalize first");
     if (n < 0) return fail(c, MCT_EINVAL, "negative step count");
     int64_t left = n;
-    if (c->use_graph && n >= kGraphSteps) {
-        if (!c->graph || c->graph_tile != c->tile) {
-            int rc = build_graph(c);
-            if (rc) return rc;
-        }
+    if (c->use_graph) {
         while (left >= kGraphSteps) {
-            HIP_TRY(c, hipGraphLaunch(c->graph, c->stream));
+            const int par0 = (int)(c->steps_enqueued & 1);
+            if (!c->graph[par0] || c->graph_tile[par0] != c->tile) {
+                int rc = build_graph(c, par0);
+                if (rc) return rc;
+            }
+            HIP_TRY(c, hipGraphLaunch(c->graph[par0], c->stream));
             left -= kGraphSteps;
+            c->steps_enqueued += kGraphSteps;
         }
     }
-    for (; left > 0; --left) HIP_TRY(c, mct::launch_step(c->tile, c->prm, c->stream));
+    while (left > 0) {
+        // direct segment, closed by its commit
+        const int seg = (int)std::min<int64_t>(left, 1 << 20);
+        const int par0 = (int)(c->steps_enqueued & 1);
+        for (int i = 0; i < seg; ++i) HIP_TRY(c, mct::launch_step(c->tile, c->prm, i, par0, c->stream));
+        HIP_TRY(c, mct::launch_commit(c->prm, seg, c->stream));
+        left -= seg;
+        c->steps_enqueued += seg;
+    }
     return MCT_OK;
 }
 
@@ -609,7 +622,7 @@ int mct_get_info(mct_ctx *c, mct_info *out) {
     Control h;
     int rc = read_control(c, &h);
     if (rc) return rc;
-    out->step = h.step;
+    out->step = h.base;
     out->n_splits = h.nsplit;
     out->dissipated = h.Ud;
     out->log_overflow = h.overflow;
@@ -681,8 +694,8 @@ int mct_get_field(mct_ctx *c, int which, int64_t cap, double *out) {
     if (rc) return rc;
     const double *sx, *sy;
     if (which == MCT_FIELD_U) {
-        sx = c->dux[h.step & 1];
-        sy = c->duy[h.step & 1];
+        sx = c->dux[h.base & 1];
+        sy = c->duy[h.base & 1];
     } else if (which == MCT_FIELD_V) {
         sx = c->dvx;
         sy = c->dvy;
@@ -724,7 +737,7 @@ int mct_checkpoint(mct_ctx *c, void *buf, int64_t cap, int64_t *bytes) {
     p += sizeof hdr;
     std::memcpy(p, &h, sizeof h);
     p += sizeof h;
-    const double *src[4] = {c->dux[h.step & 1], c->duy[h.step & 1], c->dvx, c->dvy};
+    const double *src[4] = {c->dux[h.base & 1], c->duy[h.base & 1], c->dvx, c->dvy};
     for (int i = 0; i < 4; ++i) {
         HIP_TRY(c, hipMemcpyAsync(p, src[i], 8 * c->nn, hipMemcpyDeviceToHost, c->stream));
         p += 8 * c->nn;
@@ -751,11 +764,10 @@ int mct_restore(mct_ctx *c, const void *buf, int64_t bytes) {
     p += sizeof h;
     const int64_t nlog = std::min<int64_t>(h.nsplit, c->log_cap);
     const int64_t need = 24 + (int64_t)sizeof(Control) + 4 * 8 * c->nn + c->ne + nlog * (int64_t)sizeof(LogRec);
-    if (bytes < need || h.step < 0) return fail(c, MCT_EINVAL, "checkpoint truncated");
-    h.arrive = 0;
-    h.nslots = 0;
+    if (bytes < need || h.base < 0) return fail(c, MCT_EINVAL, "checkpoint truncated");
+    h.nslots[0] = h.nslots[1] = h.nslots[2] = 0;
     HIP_TRY(c, hipMemcpyAsync(c->dctl, &h, sizeof h, hipMemcpyHostToDevice, c->stream));
-    double *dst[4] = {c->dux[h.step & 1], c->duy[h.step & 1], c->dvx, c->dvy};
+    double *dst[4] = {c->dux[h.base & 1], c->duy[h.base & 1], c->dvx, c->dvy};
     for (int i = 0; i < 4; ++i) {
         HIP_TRY(c, hipMemcpyAsync(dst[i], p, 8 * c->nn, hipMemcpyHostToDevice, c->stream));
         p += 8 * c->nn;
@@ -764,6 +776,7 @@ int mct_restore(mct_ctx *c, const void *buf, int64_t bytes) {
     p += c->ne;
     if (nlog) HIP_TRY(c, hipMemcpyAsync(c->dlog, p, sizeof(LogRec) * nlog, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->steps_enqueued = h.base;
     return MCT_OK;
 }
 

@@ -31,9 +31,9 @@ struct Slot {
 
 // Device-resident control block of one model.
 struct Control {
-    int64_t step;      // index k of the next step to run
-    uint32_t arrive;   // workgroups finished in the running step
-    uint32_t nslots;   // slots written in the running step
+    int64_t base;         // steps completed before the running segment
+    uint32_t nslots[3];   // slots written by steps k_rel = 0, 1, 2 (mod 3)
+    uint32_t pad0;
     int64_t nsplit;    // splits made so far (log length if no overflow)
     double Ud;         // dissipated energy, sum of Gc * path length
     int32_t overflow;  // 1 when a split could not be logged
@@ -59,7 +59,7 @@ struct StepParams {
     double D11, D12, D33, E;
     double dt, t_ramp, gamma;
     Control *ctl;
-    Slot *slots;
+    Slot *slots;        // 3 sets of nwg slots
     LogRec *log;
 };
 
@@ -70,7 +70,10 @@ struct TileShape {
 constexpr int kNumTiles = 3;
 TileShape tile_shape(int tile);  // tile in 1..kNumTiles
 
-hipError_t launch_step(int tile, const StepParams &p, hipStream_t s);
+// One step of a segment (k_rel = index in the segment, par0 = parity of the
+// segment's first step), and the segment close after n steps.
+hipError_t launch_step(int tile, const StepParams &p, int k_rel, int par0, hipStream_t s);
+hipError_t launch_commit(const StepParams &p, int n, hipStream_t s);
 
 // Crack-surface tips: compacted edge ids and reference midpoints.
 hipError_t launch_tips(int32_t nx, int32_t ny, const double *X, const double *Y,

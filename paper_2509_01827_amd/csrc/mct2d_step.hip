@@ -18,9 +18,10 @@
 //      wavefront ballots, evaluates G of the three split topologies and the
 //      Q4 element rule (Sec. 2.2), reduces the best candidate of the
 //      workgroup and publishes it;
-//   6. the last workgroup to finish reduces the published candidates, applies
-//      the MCT pick with the split-ratio test (Sec. 3) and splits the chosen
-//      element, which the next launch sees.
+//   6. at the start of the next step every workgroup reduces the published
+//      candidates and applies the MCT pick with the split-ratio test
+//      (Sec. 3) to its staged split codes; workgroup 0 records the split.
+//      k_commit does the same for the last step of a launch segment.
 //
 // Arithmetic follows one fixed expression order (binary64, compiled with
 // -ffp-contract=off; fma only where written), so the result does not depend
@@ -39,7 +40,31 @@ __device__ __forceinline__ double eta_n(int n) { return (n >= 2) ? 1.0 : -1.0; }
 __device__ __forceinline__ double xi_m(int k) { return k == 1 ? 1.0 : (k == 3 ? -1.0 : 0.0); }
 __device__ __forceinline__ double eta_m(int k) { return k == 0 ? -1.0 : (k == 2 ? 1.0 : 0.0); }
 
-// dN/dx, dN/dy of the bilinear element at the midpoint of its local edge k
+// dN/dx, dN/dy of the bilinear element at the midpoint of its local edge k.
+//
+// The shape-function derivatives in natural coordinates at an edge midpoint
+// are 0, +-1/4 or +-1/2, so every product with them is exact.  The sums are
+// written over the non-zero terms only: adding a zero product to a running
+// sum, or subtracting one, leaves every non-zero value unchanged (at most
+// the sign of a zero differs), so the result equals the plain evaluation
+//   J = sum_n dN_n/d(xi,eta) * (x_n, y_n)    (fma chain from 0, n = 0..3)
+//   dN_n/dx = (J22 dN_n/dxi - J12 dN_n/deta) / det J  (as * (1/det))
+//   dN_n/dy = (J11 dN_n/deta - J21 dN_n/dxi) / det J
+// bit for bit.  With k a compile-time constant after unrolling, the zero
+// tests fold away.
+__device__ __forceinline__ double exact_dot4(const double c[4], const double v[4]) {
+    double s = 0.0;
+    bool first = true;
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        if (c[n] != 0.0) {
+            s = first ? c[n] * v[n] : fma(c[n], v[n], s);
+            first = false;
+        }
+    }
+    return s;
+}
+
 __device__ __forceinline__ void q4_grad(const double x[4], const double y[4], int k, double dndx[4],
                                         double dndy[4]) {
     double dxi[4], deta[4];
@@ -48,20 +73,38 @@ __device__ __forceinline__ void q4_grad(const double x[4], const double y[4], in
         dxi[n] = 0.25 * xi_n(n) * (1.0 + eta_m(k) * eta_n(n));
         deta[n] = 0.25 * eta_n(n) * (1.0 + xi_m(k) * xi_n(n));
     }
-    double j11 = 0.0, j12 = 0.0, j21 = 0.0, j22 = 0.0;
-#pragma unroll
-    for (int n = 0; n < 4; ++n) {
-        j11 = fma(dxi[n], x[n], j11);
-        j12 = fma(dxi[n], y[n], j12);
-        j21 = fma(deta[n], x[n], j21);
-        j22 = fma(deta[n], y[n], j22);
-    }
+    const double j11 = exact_dot4(dxi, x);
+    const double j12 = exact_dot4(dxi, y);
+    const double j21 = exact_dot4(deta, x);
+    const double j22 = exact_dot4(deta, y);
     const double det = j11 * j22 - j12 * j21;
     const double inv = 1.0 / det;
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
-        dndx[n] = (j22 * dxi[n] - j12 * deta[n]) * inv;
-        dndy[n] = (j11 * deta[n] - j21 * dxi[n]) * inv;
+        double a, b;
+        if (dxi[n] != 0.0 && deta[n] != 0.0) {
+            a = fma(j22, dxi[n], -(j12 * deta[n]));
+            b = fma(j11, deta[n], -(j21 * dxi[n]));
+        } else if (dxi[n] != 0.0) {
+            a = j22 * dxi[n];
+            b = -(j21 * dxi[n]);
+        } else {
+            a = -(j12 * deta[n]);
+            b = j11 * deta[n];
+        }
+        dndx[n] = a * inv;
+        dndy[n] = b * inv;
+    }
+}
+
+// q4_grad with the edge index as a template argument (for runtime k).
+__device__ __forceinline__ void q4_grad_rt(const double x[4], const double y[4], int k, double dndx[4],
+                                           double dndy[4]) {
+    switch (k) {
+        case 0: q4_grad(x, y, 0, dndx, dndy); break;
+        case 1: q4_grad(x, y, 1, dndx, dndy); break;
+        case 2: q4_grad(x, y, 2, dndx, dndy); break;
+        default: q4_grad(x, y, 3, dndx, dndy); break;
     }
 }
 
@@ -167,8 +210,62 @@ __device__ __forceinline__ int xcd_tile(int b, int nwg) {
 
 }  // namespace
 
+// Reduce the candidates published in slot set `set` with the whole
+// workgroup; thread 0 receives the result.  Every thread must call it.
+template <int NT>
+__device__ __forceinline__ Cand reduce_slots(const StepParams &p, int set, Cand *red) {
+    const uint32_t n = p.ctl->nslots[set];
+    const Slot *sl = p.slots + (size_t)set * p.nwg;
+    Cand g;
+    cand_none(g);
+    for (uint32_t s = threadIdx.x; s < n; s += NT) {
+        const Slot x = sl[s];
+        cand_merge(g, x.G, x.Gmin, x.elem, x.a, x.k);
+    }
+    cand_block_reduce<NT>(g, red);
+    return g;
+}
+
+// MCT pick: the largest G must pass G* > gamma (G* - G_c) against every other
+// accepted candidate; (G* - G_c) grows as G_c shrinks and rounding is
+// monotone, so the smallest accepted G decides.
+__device__ __forceinline__ bool pick_accepted(const StepParams &p, const Cand &g) {
+    return g.G >= 0.0 && g.G > p.gamma * (g.G - g.Gmin);
+}
+
+// Split the picked element (acts from the next step), log it and add
+// Gc * crack-path length to U_d.  One thread of one workgroup.
+__device__ __forceinline__ void apply_split(const StepParams &p, const Cand &g, int64_t kdecided) {
+    Control *ctl = p.ctl;
+    p.split[g.e] = (uint8_t)(kSplitFlag | (g.a << 2) | g.k);
+    const int64_t n = ctl->nsplit;
+    if (n < p.log_cap) {
+        LogRec r;
+        r.step = (int32_t)kdecided;
+        r.elem = g.e;
+        r.entry = (uint8_t)g.a;
+        r.exit = (uint8_t)g.k;
+        r.pad0 = r.pad1 = 0;
+        r.pad2 = 0;
+        r.G = g.G;
+        p.log[n] = r;
+    } else {
+        ctl->overflow = 1;
+    }
+    ctl->nsplit = n + 1;
+    const int jk = (g.k - g.a - 1) & 3;
+    const double gc = p.gc ? p.gc[g.e] : p.gc_uniform;
+    ctl->Ud = ctl->Ud + gc * p.geom[(int64_t)g.e * 36 + g.a * 9 + 3 * jk + 2];
+}
+
+// One time step.  Steps run in segments (a captured graph or a run of direct
+// launches) closed by k_commit; k_rel is the index inside the segment and
+// par0 the parity of the segment's first step (u^k lives in buffer k & 1).
+// The pick of step k-1 is taken at the start of step k from the candidates
+// step k-1 published (slot set (k_rel-1) mod 3): every workgroup reduces
+// them, applies the split to its staged codes, and workgroup 0 records it.
 template <int TXE, int TYE>
-__global__ __launch_bounds__(TXE *TYE) void k_step(StepParams p) {
+__global__ __launch_bounds__(TXE *TYE) void k_step(StepParams p, int k_rel, int par0) {
     constexpr int NT = TXE * TYE;
     constexpr int TX = TXE - 1, TY = TYE - 1;  // owned nodes
     constexpr int HX = TXE + 3, HY = TYE + 3;  // staged nodes
@@ -176,29 +273,33 @@ __global__ __launch_bounds__(TXE *TYE) void k_step(StepParams p) {
     constexpr int NH = TXE * (TYE + 1);        // horizontal edges
     constexpr int NV = (TXE + 1) * TYE;        // vertical edges
     static_assert(NT % 64 == 0, "whole wavefronts");
+    static_assert(TX * TY <= NT, "one thread per owned node");
 
+    constexpr int NR = 2 * TXE + 2 * TYE;      // elements just outside the ring
     __shared__ double s_ux[HX * HY], s_uy[HX * HY], s_X[HX * HY], s_Y[HX * HY];
     __shared__ double s_area[EX * EY];
-    __shared__ double s_sig[(NH + NV) * 3];
+    __shared__ double s_qlo[(NH + NV) * 3];  // B u of the lower-id element, then the edge stress
+    __shared__ double s_qhi[(NH + NV) * 3];  // B u of the higher-id element
     __shared__ double s_acc[TX * TY * 2];
     __shared__ uint8_t s_split[EX * EY];
     __shared__ uint16_t s_cand[4 * TX * TY];
     __shared__ int s_ncand;
     __shared__ int s_wbase[NT / 64];
     __shared__ Cand s_red[NT / 64];
-    __shared__ int s_last;
 
     const int tid = threadIdx.x;
     const int nx = p.nx, ny = p.ny;
     const int tile = xcd_tile(blockIdx.x, p.nwg);
     const int i0 = (tile % p.ntx) * TX, j0 = (tile / p.ntx) * TY;
-    const int64_t kstep = p.ctl->step;
-    const double *ux_c = (kstep & 1) ? p.ux1 : p.ux0;
-    const double *uy_c = (kstep & 1) ? p.uy1 : p.uy0;
-    double *ux_n = (kstep & 1) ? p.ux0 : p.ux1;
-    double *uy_n = (kstep & 1) ? p.uy0 : p.uy1;
+    const int par = (par0 + k_rel) & 1;
+    const double *ux_c = par ? p.ux1 : p.ux0;
+    const double *uy_c = par ? p.uy1 : p.uy0;
+    double *ux_n = par ? p.ux0 : p.ux1;
+    double *uy_n = par ? p.uy0 : p.uy1;
+    const int set_w = k_rel % 3, set_r = (k_rel + 2) % 3, set_c = (k_rel + 1) % 3;
+    const int64_t base = p.ctl->base;  // needed late (time, first step, log)
 
-    // ---- 1. stage nodes and split codes --------------------------------
+    // ---- 1. stage nodes and split codes; prefetch owned-node data ------
     for (int idx = tid; idx < HX * HY; idx += NT) {
         const int gi = i0 - 2 + idx % HX, gj = j0 - 2 + idx / HX;
         double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
@@ -222,6 +323,40 @@ __global__ __launch_bounds__(TXE *TYE) void k_step(StepParams p) {
     }
     for (int idx = tid; idx < TX * TY * 2; idx += NT) s_acc[idx] = 0.0;
     if (tid == 0) s_ncand = 0;
+    // owned node of this thread
+    const int on_l = tid % TX, on_m = tid / TX;
+    const int on_i = i0 + on_l, on_j = j0 + on_m;
+    const bool on_valid = tid < TX * TY && on_i <= nx && on_j <= ny;
+    const int64_t on_n = (int64_t)on_j * (nx + 1) + on_i;
+    double n_minv = 0.0, n_vx = 0.0, n_vy = 0.0, n_fex = 0.0, n_fey = 0.0, n_v0x = 0.0, n_v0y = 0.0;
+    unsigned n_mask = 0;
+    if (on_valid) {
+        n_minv = p.minv[on_n];
+        n_vx = p.vx[on_n];
+        n_vy = p.vy[on_n];
+        const int pidx = perimeter_index(on_i, on_j, nx, ny);
+        if (pidx >= 0) {
+            n_fex = p.fext_p[2 * pidx];
+            n_fey = p.fext_p[2 * pidx + 1];
+            n_mask = p.vmask_p[pidx];
+            n_v0x = p.v0_p[2 * pidx];
+            n_v0y = p.v0_p[2 * pidx + 1];
+        }
+    }
+
+    // ---- 2. the pick of the previous step -------------------------------
+    {
+        const Cand g = reduce_slots<NT>(p, set_r, s_red);  // contains a barrier
+        if (tid == 0) {
+            if (pick_accepted(p, g)) {
+                const int fx = g.e % nx - (i0 - 2), fy = g.e / nx - (j0 - 2);
+                if (fx >= 0 && fx < EX && fy >= 0 && fy < EY)
+                    s_split[fy * EX + fx] = (uint8_t)(kSplitFlag | (g.a << 2) | g.k);
+                if (blockIdx.x == 0) apply_split(p, g, base + k_rel - 1);
+            }
+            if (blockIdx.x == 0) p.ctl->nslots[set_c] = 0;
+        }
+    }
     __syncthreads();
 
     auto elem_xy = [&](int ex, int ey, double x[4], double y[4]) {
@@ -247,98 +382,130 @@ __global__ __launch_bounds__(TXE *TYE) void k_step(StepParams p) {
         uy[3] = s_uy[b + HX];
     };
 
-    for (int idx = tid; idx < EX * EY; idx += NT) {
-        double x[4], y[4];
-        elem_xy(idx % EX, idx / EX, x, y);
-        s_area[idx] = (s_split[idx] == kAbsent) ? 0.0 : quad_area(x, y);
-    }
-    __syncthreads();
-
-    // ---- 2. smoothed strain and stress at the edges --------------------
-    // horizontal edge (h, v): below element E2(h+1, v) edge 2 (lower id),
-    // above element E2(h+1, v+1) edge 0.  Vertical edge (h, v): left element
-    // E2(h, v+1) edge 1 (lower id), right element E2(h+1, v+1) edge 3.
-    for (int idx = tid; idx < NH + NV; idx += NT) {
-        int elo, klo, ehi, khi;
-        if (idx < NH) {
-            const int h = idx % TXE, v = idx / TXE;
-            elo = v * EX + h + 1;
-            klo = 2;
-            ehi = (v + 1) * EX + h + 1;
-            khi = 0;
-        } else {
-            const int r = idx - NH;
-            const int h = r % (TXE + 1), v = r / (TXE + 1);
-            elo = (v + 1) * EX + h;
-            klo = 1;
-            ehi = (v + 1) * EX + h + 1;
-            khi = 3;
-        }
-        const bool ilo = s_split[elo] == 0, ihi = s_split[ehi] == 0;
-        double eps[3] = {0.0, 0.0, 0.0};
-        double q[2][3];
-        int cnt = 0;
-        for (int side = 0; side < 2; ++side) {
-            const bool in = side ? ihi : ilo;
-            if (!in) continue;
-            const int e = side ? ehi : elo;
-            const int kk = side ? khi : klo;
-            double x[4], y[4], ux[4], uy[4], dndx[4], dndy[4];
-            elem_xy(e % EX, e / EX, x, y);
-            elem_u(e % EX, e / EX, ux, uy);
-            q4_grad(x, y, kk, dndx, dndy);
-            strain<4>(dndx, dndy, ux, uy, q[cnt]);
-            ++cnt;
-        }
-        if (cnt == 1) {
-            eps[0] = q[0][0];
-            eps[1] = q[0][1];
-            eps[2] = q[0][2];
-        } else if (cnt == 2) {
-            const double alo = s_area[elo], ahi = s_area[ehi];
-            const double sum = alo + ahi;
-            const double w0 = alo / sum, w1 = ahi / sum;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) eps[c] = fma(w1, q[1][c], w0 * q[0][c]);
-        }
-        double sg[3] = {0.0, 0.0, 0.0};
-        if (cnt > 0) hooke(p, eps, sg);
-        s_sig[3 * idx + 0] = sg[0];
-        s_sig[3 * idx + 1] = sg[1];
-        s_sig[3 * idx + 2] = sg[2];
-    }
-    __syncthreads();
-
-    // ---- 3. element forces, one thread per element of the tile ring ----
+    // ---- 3. element gradients and strain contributions B u ---------------
+    // Element (ie, je) of the TXE x TYE ring around the owned nodes: its
+    // gradients at the four edge midpoints stay in registers for the force
+    // phase; B_k u_e goes to the edge's lower-id slot (s_qlo, for local edges
+    // 1 and 2) or higher-id slot (s_qhi, for edges 0 and 3).  Elements one
+    // further out contribute only to the edge they share with the ring.
     const int ie = tid % TXE, je = tid / TXE;
     const int ex = ie + 1, ey = je + 1;
     const int e2 = ey * EX + ex;
     const int gi = i0 - 1 + ie, gj = j0 - 1 + je;
-    const uint8_t code = s_split[e2];
-    // edges of this element in local order 0..3 (bottom, right, top, left)
-    int sidx[4];
+    int sidx[4];  // edges of this element in local order (bottom, right, top, left)
     sidx[0] = je * TXE + ie;
     sidx[1] = NH + je * (TXE + 1) + ie + 1;
     sidx[2] = (je + 1) * TXE + ie;
     sidx[3] = NH + je * (TXE + 1) + ie;
+    double gx[4][4], gy[4][4];
+    double my_area = 0.0;
+    {
+        const uint8_t c0 = s_split[e2];
+        if (c0 != kAbsent) {
+            double x[4], y[4];
+            elem_xy(ex, ey, x, y);
+            my_area = quad_area(x, y);
+            s_area[e2] = my_area;
+            if (c0 == 0) {
+                double ux[4], uy[4];
+                elem_u(ex, ey, ux, uy);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    q4_grad(x, y, k, gx[k], gy[k]);
+                    double q[3];
+                    strain<4>(gx[k], gy[k], ux, uy, q);
+                    double *dst = (k == 1 || k == 2) ? s_qlo : s_qhi;
+                    dst[3 * sidx[k] + 0] = q[0];
+                    dst[3 * sidx[k] + 1] = q[1];
+                    dst[3 * sidx[k] + 2] = q[2];
+                }
+            }
+        }
+    }
+    for (int r = tid; r < NR; r += NT) {
+        int rex, rey, rk, sid;
+        if (r < TXE) {  // below the ring: top edge
+            rex = r + 1; rey = 0; rk = 2; sid = r;
+        } else if (r < 2 * TXE) {  // above: bottom edge
+            rex = r - TXE + 1; rey = TYE + 1; rk = 0; sid = TYE * TXE + (r - TXE);
+        } else if (r < 2 * TXE + TYE) {  // left: right edge
+            rex = 0; rey = r - 2 * TXE + 1; rk = 1; sid = NH + (r - 2 * TXE) * (TXE + 1);
+        } else {  // right: left edge
+            rex = TXE + 1; rey = r - 2 * TXE - TYE + 1; rk = 3; sid = NH + (r - 2 * TXE - TYE) * (TXE + 1) + TXE;
+        }
+        const int re = rey * EX + rex;
+        const uint8_t rc = s_split[re];
+        if (rc == kAbsent) continue;
+        double x[4], y[4];
+        elem_xy(rex, rey, x, y);
+        s_area[re] = quad_area(x, y);
+        if (rc != 0) continue;
+        double ux[4], uy[4], dx[4], dy[4], q[3];
+        elem_u(rex, rey, ux, uy);
+        q4_grad_rt(x, y, rk, dx, dy);
+        strain<4>(dx, dy, ux, uy, q);
+        double *dst = (rk == 1 || rk == 2) ? s_qlo : s_qhi;
+        dst[3 * sid + 0] = q[0];
+        dst[3 * sid + 1] = q[1];
+        dst[3 * sid + 2] = q[2];
+    }
+    __syncthreads();
 
+    // ---- 3E. smoothed strain and stress at the edges -------------------
+    // horizontal edge (h, v): below element E2(h+1, v) (lower id), above
+    // E2(h+1, v+1).  Vertical edge (h, v): left E2(h, v+1) (lower id), right
+    // E2(h+1, v+1).  The stress overwrites the edge's s_qlo slot.
+    for (int idx = tid; idx < NH + NV; idx += NT) {
+        int elo, ehi;
+        if (idx < NH) {
+            const int h = idx % TXE, v = idx / TXE;
+            elo = v * EX + h + 1;
+            ehi = (v + 1) * EX + h + 1;
+        } else {
+            const int r = idx - NH;
+            const int h = r % (TXE + 1), v = r / (TXE + 1);
+            elo = (v + 1) * EX + h;
+            ehi = (v + 1) * EX + h + 1;
+        }
+        const bool ilo = s_split[elo] == 0, ihi = s_split[ehi] == 0;
+        double eps[3];
+        if (ilo && ihi) {
+            const double alo = s_area[elo], ahi = s_area[ehi];
+            const double sum = alo + ahi;
+            const double w0 = alo / sum, w1 = ahi / sum;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) eps[c] = fma(w1, s_qhi[3 * idx + c], w0 * s_qlo[3 * idx + c]);
+        } else if (ilo) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) eps[c] = s_qlo[3 * idx + c];
+        } else if (ihi) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) eps[c] = s_qhi[3 * idx + c];
+        }
+        double sg[3] = {0.0, 0.0, 0.0};
+        if (ilo || ihi) hooke(p, eps, sg);
+        s_qlo[3 * idx + 0] = sg[0];
+        s_qlo[3 * idx + 1] = sg[1];
+        s_qlo[3 * idx + 2] = sg[2];
+    }
+    __syncthreads();
+    const double *s_sig = s_qlo;
+
+    // ---- 4. element forces, one thread per element of the tile ring ----
+    const uint8_t code = s_split[e2];
     double fe[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) fe[c] = 0.0;
     if (code == 0) {
-        double x[4], y[4];
-        elem_xy(ex, ey, x, y);
         double sx[4], sy[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            double dndx[4], dndy[4];
-            q4_grad(x, y, k, dndx, dndy);
             const double *sg = &s_sig[3 * sidx[k]];
             const double s0 = sg[0], s1 = sg[1], s2 = sg[2];
 #pragma unroll
             for (int n = 0; n < 4; ++n) {
-                const double tx = fma(dndy[n], s2, dndx[n] * s0);
-                const double ty = fma(dndx[n], s2, dndy[n] * s1);
+                const double tx = fma(gy[k][n], s2, gx[k][n] * s0);
+                const double ty = fma(gx[k][n], s2, gy[k][n] * s1);
                 if (k == 0) {
                     sx[n] = tx;
                     sy[n] = ty;
@@ -348,7 +515,7 @@ __global__ __launch_bounds__(TXE *TYE) void k_step(StepParams p) {
                 }
             }
         }
-        const double c = 0.25 * s_area[e2];
+        const double c = 0.25 * my_area;
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
             fe[2 * n] = c * sx[n];
@@ -474,42 +641,27 @@ __global__ __launch_bounds__(TXE *TYE) void k_step(StepParams p) {
         __syncthreads();
     }
 
-    // ---- 4. central-difference update of the owned nodes ---------------
-    if (tid < TX * TY) {
-        const int ln = tid % TX, mn = tid / TX;
-        const int ni = i0 + ln, nj = j0 + mn;
-        if (ni <= nx && nj <= ny) {
-            const int64_t n = (int64_t)nj * (nx + 1) + ni;
-            const int hidx = (mn + 2) * HX + (ln + 2);
-            double fex = 0.0, fey = 0.0, v0x = 0.0, v0y = 0.0;
-            unsigned m = 0;
-            const int pidx = perimeter_index(ni, nj, nx, ny);
-            if (pidx >= 0) {
-                fex = p.fext_p[2 * pidx];
-                fey = p.fext_p[2 * pidx + 1];
-                m = p.vmask_p[pidx];
-                v0x = p.v0_p[2 * pidx];
-                v0y = p.v0_p[2 * pidx + 1];
-            }
-            const double mi = p.minv[n];
-            double ax = (fex - s_acc[2 * tid]) * mi;
-            double ay = (fey - s_acc[2 * tid + 1]) * mi;
-            if (m & 1u) ax = 0.0;
-            if (m & 2u) ay = 0.0;
-            const double dtv = (kstep == 0) ? 0.5 * p.dt : p.dt;
-            const double th = ((double)kstep + 0.5) * p.dt;
-            double vx = p.vx[n] + dtv * ax;
-            double vy = p.vy[n] + dtv * ay;
-            if (m & 1u) vx = prescribed(v0x, th, p.t_ramp);
-            if (m & 2u) vy = prescribed(v0y, th, p.t_ramp);
-            p.vx[n] = vx;
-            p.vy[n] = vy;
-            ux_n[n] = s_ux[hidx] + p.dt * vx;
-            uy_n[n] = s_uy[hidx] + p.dt * vy;
-        }
+    // ---- 5. central-difference update of the owned nodes ---------------
+    if (on_valid) {
+        const int64_t kabs = base + k_rel;
+        const int hidx = (on_m + 2) * HX + (on_l + 2);
+        double ax = (n_fex - s_acc[2 * tid]) * n_minv;
+        double ay = (n_fey - s_acc[2 * tid + 1]) * n_minv;
+        if (n_mask & 1u) ax = 0.0;
+        if (n_mask & 2u) ay = 0.0;
+        const double dtv = (kabs == 0) ? 0.5 * p.dt : p.dt;
+        const double th = ((double)kabs + 0.5) * p.dt;
+        double vx = n_vx + dtv * ax;
+        double vy = n_vy + dtv * ay;
+        if (n_mask & 1u) vx = prescribed(n_v0x, th, p.t_ramp);
+        if (n_mask & 2u) vy = prescribed(n_v0y, th, p.t_ramp);
+        p.vx[on_n] = vx;
+        p.vy[on_n] = vy;
+        ux_n[on_n] = s_ux[hidx] + p.dt * vx;
+        uy_n[on_n] = s_uy[hidx] + p.dt * vy;
     }
 
-    // ---- 5. energy release rate and element rule of the candidates ------
+    // ---- 6. energy release rate and element rule of the candidates ------
     Cand best;
     cand_none(best);
     const int ncand = s_ncand;
@@ -560,64 +712,37 @@ __global__ __launch_bounds__(TXE *TYE) void k_step(StepParams p) {
     }
     cand_block_reduce<NT>(best, s_red);
 
-    // ---- 6. publish, and let the last workgroup decide ------------------
-    if (tid == 0) {
-        if (best.G >= 0.0) {
-            const uint32_t slot = atomicAdd(&p.ctl->nslots, 1u);
-            Slot sl;
-            sl.G = best.G;
-            sl.Gmin = best.Gmin;
-            sl.elem = best.e;
-            sl.a = best.a;
-            sl.k = best.k;
-            sl.pad = 0;
-            p.slots[slot] = sl;
-        }
-        __threadfence();
-        const uint32_t prev = atomicAdd(&p.ctl->arrive, 1u);
-        s_last = (prev == (uint32_t)(p.nwg - 1));
+    // ---- 7. publish the workgroup's best candidate -----------------------
+    // Read by the next step after the kernel boundary; no fence here (a
+    // device-scope release would write back the whole L2 of the XCD).
+    if (tid == 0 && best.G >= 0.0) {
+        const uint32_t slot = atomicAdd(&p.ctl->nslots[set_w], 1u);
+        Slot sl;
+        sl.G = best.G;
+        sl.Gmin = best.Gmin;
+        sl.elem = best.e;
+        sl.a = best.a;
+        sl.k = best.k;
+        sl.pad = 0;
+        p.slots[(size_t)set_w * p.nwg + slot] = sl;
     }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    const uint32_t nslots = __hip_atomic_load(&p.ctl->nslots, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    Cand g;
-    cand_none(g);
-    for (uint32_t s = tid; s < nslots; s += NT) {
-        const Slot sl = p.slots[s];
-        cand_merge(g, sl.G, sl.Gmin, sl.elem, sl.a, sl.k);
-    }
-    cand_block_reduce<NT>(g, s_red);
-    if (tid == 0) {
-        Control *ctl = p.ctl;
-        // MCT pick: the largest G must pass G* > gamma (G* - G_c) against
-        // every other accepted candidate; (G* - G_c) grows as G_c shrinks
-        // and rounding is monotone, so the smallest accepted G decides.
-        if (g.G >= 0.0 && g.G > p.gamma * (g.G - g.Gmin)) {
-            p.split[g.e] = (uint8_t)(kSplitFlag | (g.a << 2) | g.k);
-            const int64_t n = ctl->nsplit;
-            if (n < p.log_cap) {
-                LogRec r;
-                r.step = (int32_t)kstep;
-                r.elem = g.e;
-                r.entry = (uint8_t)g.a;
-                r.exit = (uint8_t)g.k;
-                r.pad0 = r.pad1 = 0;
-                r.pad2 = 0;
-                r.G = g.G;
-                p.log[n] = r;
-            } else {
-                ctl->overflow = 1;
-            }
-            ctl->nsplit = n + 1;
-            const int jk = (g.k - g.a - 1) & 3;
-            const double gc = p.gc ? p.gc[g.e] : p.gc_uniform;
-            ctl->Ud = ctl->Ud + gc * p.geom[(int64_t)g.e * 36 + g.a * 9 + 3 * jk + 2];
-        }
-        ctl->nslots = 0;
-        ctl->arrive = 0;
-        ctl->step = kstep + 1;
-    }
+}
+
+// Close a segment of n steps: take the pick of its last step, clear every
+// slot set and advance the step counter.
+constexpr int kCommitThreads = 256;
+
+__global__ __launch_bounds__(kCommitThreads) void k_commit(StepParams p, int n) {
+    __shared__ Cand s_red[kCommitThreads / 64];
+    const int set = (n + 2) % 3;
+    const Cand g = reduce_slots<kCommitThreads>(p, set, s_red);
+    if (threadIdx.x != 0) return;
+    const int64_t base = p.ctl->base;
+    if (n > 0 && pick_accepted(p, g)) apply_split(p, g, base + n - 1);
+    p.ctl->nslots[0] = 0;
+    p.ctl->nslots[1] = 0;
+    p.ctl->nslots[2] = 0;
+    p.ctl->base = base + n;
 }
 
 TileShape tile_shape(int tile) {
@@ -628,12 +753,17 @@ TileShape tile_shape(int tile) {
     }
 }
 
-hipError_t launch_step(int tile, const StepParams &p, hipStream_t s) {
+hipError_t launch_step(int tile, const StepParams &p, int k_rel, int par0, hipStream_t s) {
     switch (tile) {
-        case 1: k_step<16, 16><<<p.nwg, 256, 0, s>>>(p); break;
-        case 2: k_step<32, 8><<<p.nwg, 256, 0, s>>>(p); break;
-        default: k_step<32, 16><<<p.nwg, 512, 0, s>>>(p); break;
+        case 1: k_step<16, 16><<<p.nwg, 256, 0, s>>>(p, k_rel, par0); break;
+        case 2: k_step<32, 8><<<p.nwg, 256, 0, s>>>(p, k_rel, par0); break;
+        default: k_step<32, 16><<<p.nwg, 512, 0, s>>>(p, k_rel, par0); break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_commit(const StepParams &p, int n, hipStream_t s) {
+    k_commit<<<1, kCommitThreads, 0, s>>>(p, n);
     return hipGetLastError();
 }
 
