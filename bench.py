@@ -1,6 +1,6 @@
 """Benchmark of the MCT-2D-CEM explicit fracture step on one MI355X.
 
-Workload: the 400x400 Q4 mesh of the 100 x 40 mm branching plate
+Default workload: the 400x400 Q4 mesh of the 100 x 40 mm branching plate
 (0.25 x 0.1 mm elements, +/-1% seeded nodal jitter, half-length edge notch,
 1 MPa traction on the upper and lower edges), binary64, synthetic inputs.
 A bench "step" is one explicit time step: edge stresses, element forces,
@@ -10,6 +10,11 @@ candidate, and the multi-tip pick and split.
 Timed region: --steps time steps from t = 0 (the state is restored after the
 warm-up), inputs resident in HBM, bracketed by device synchronisation.
 Prints one JSON line.
+
+Other workloads (--workload): fragment2000 (2000 x 1000 fragmentation plate)
+and batch256 (256 uneven notched specimens in one launch per step; with
+--compare-plain every specimen is also run alone with the plain step and the
+crack sets are compared).
 """
 from __future__ import annotations
 
@@ -26,41 +31,69 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 WORKLOADS = {
     "plate400": "branching plate 400x400 Q4, 100x40 mm, jitter 1%, notch 50 mm, 1 MPa",
     "fragment2000": "fragmentation plate 2000x1000 Q4, h 0.1 mm, 5 m/s outward, Weibull(6,3) Gc",
+    "batch256": "256 notched specimens 64..512 x 64..256 Q4, h 1 mm, notch U(0.2,0.6) width, "
+                "Weibull(6, U(2,4)) Gc, traction U(0.5,1.5) MPa",
 }
 
 
-def bytes_per_step(nx: int, ny: int) -> int:
+def bytes_per_step(cfgs) -> int:
     """Algorithmic HBM bytes of one fused step (binary64): per node read u,
     v, X, Y, 1/m and write u, v (11 doubles); per element its split code."""
-    nn = (nx + 1) * (ny + 1)
-    ne = nx * ny
-    return 88 * nn + ne
+    total = 0
+    for c in cfgs:
+        nn = (c["nx"] + 1) * (c["ny"] + 1)
+        total += 88 * nn + c["nx"] * c["ny"]
+    return total
 
 
 def cpu_baseline(cfg, steps: int):
     from oracle import oracle
+    oracle.set_threads(1)
     o = oracle.Oracle(cfg)
     t0 = time.perf_counter()
     o.step(steps)
     dt = time.perf_counter() - t0
     ne = cfg["nx"] * cfg["ny"]
     return {"value": ne * steps / dt, "unit": "element-updates/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d time steps of the same 400x400 plate (single-threaded C oracle, %.1f s)"
-                      % (steps, dt)}
+            "sample": "first %d time steps of the same %dx%d plate (single-threaded C oracle, %.1f s)"
+                      % (steps, cfg["nx"], cfg["ny"], dt)}
+
+
+def timed_run(m, stream, steps, warmup):
+    """Warm up, restore the initial state, time `steps` steps with HIP events
+    on the model's stream.  Returns (gpu_ms, wall_s)."""
+    import torch
+    init = m.checkpoint()
+    if warmup:
+        m.step(warmup)
+        m.sync()
+    m.restore(init)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    m.step(steps)
+    ev1.record(stream)
+    m.sync()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1), time.perf_counter() - t0
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="time steps timed (default: the workload's full run)")
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--autotune", action="store_true", help="pick tile/order by measurement first")
     ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="plate400", choices=["plate400", "fragment2000"],
-                    help="plate400: the 400x400 branching plate (default); fragment2000: the "
-                         "2000x1000 Dirichlet fragmentation plate")
+    ap.add_argument("--workload", default="plate400", choices=sorted(WORKLOADS))
+    ap.add_argument("--compare-plain", action="store_true",
+                    help="batch256: also run each specimen alone and compare")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (three times), "
                          "to calibrate the FETCH_SIZE / WRITE_SIZE counters")
@@ -80,45 +113,46 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
     from paper_2509_01827_amd import mct2d, workloads as W
 
     torch.cuda.set_device(0)
-    cfg = W.config2() if args.workload == "plate400" else W.config3()
-    nx, ny = cfg["nx"], cfg["ny"]
-    ne = nx * ny
     stream = torch.cuda.Stream()
-    m = mct2d.from_config(cfg, stream=stream.cuda_stream, tile=args.tile, use_graph=not args.no_graph)
-    init = m.checkpoint()
-    m.step(args.warmup)
-    m.sync()
-    m.restore(init)
-    torch.cuda.synchronize()
-
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    m.step(args.steps)
-    ev1.record(stream)
-    m.sync()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
-    info = m.info()
-    assert info["step"] == args.steps
-
-    ms_per_step = gpu_ms / args.steps
-    value = ne * args.steps / (gpu_ms * 1e-3)
-    bps = bytes_per_step(nx, ny)
+    if args.workload == "batch256":
+        cfgs = W.batch_specimens()
+        m = mct2d.batch_from_configs(cfgs, stream=stream.cuda_stream, tile=args.tile,
+                                     use_graph=not args.no_graph)
+    else:
+        cfgs = [W.config2() if args.workload == "plate400" else W.config3()]
+        m = mct2d.from_config(cfgs[0], stream=stream.cuda_stream, tile=args.tile,
+                              use_graph=not args.no_graph)
+    steps = args.steps if args.steps is not None else cfgs[0]["steps"]
+    tune = m.autotune(trial_steps=20) if args.autotune else None
+    gpu_ms, wall = timed_run(m, stream, steps, args.warmup)
+    launch = m.launch()
+    ne = sum(c["nx"] * c["ny"] for c in cfgs)
+    splits, ud = 0, 0.0
+    logs = []
+    for s in range(len(cfgs)):
+        if len(cfgs) > 1:
+            m.select(s)
+        inf = m.info()
+        assert inf["step"] == steps
+        splits += inf["n_splits"]
+        ud += inf["dissipated"]
+        if args.compare_plain:
+            logs.append(m.crack_set())
+    ms_per_step = gpu_ms / steps
+    value = ne * steps / (gpu_ms * 1e-3)
+    bps = bytes_per_step(cfgs)
     achieved = bps / (ms_per_step * 1e-3) / 1e9
     out = {
         "metric": "element-updates/s",
         "value": value,
         "unit": "element-updates/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
         "higher_is_better": True,
@@ -126,19 +160,31 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.workload],
-                   "elements": ne, "nodes": (nx + 1) * (ny + 1), "time_steps": args.steps,
-                   "tile": args.tile, "graph": not args.no_graph},
+        "config": {"workload": WORKLOADS[args.workload], "specimens": len(cfgs), "elements": ne,
+                   "time_steps": steps, "tile": launch["tile"], "order": launch["order"],
+                   "workgroups": launch["workgroups"], "graph": not args.no_graph,
+                   "autotuned": tune is not None},
         "wall_s": wall,
-        "splits": info["n_splits"],
-        "dissipated_J_per_m": info["dissipated"],
+        "splits": splits,
+        "dissipated_J_per_m": ud,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_launch": bps},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": bps},
     }
     m.close()
+    if args.compare_plain and len(cfgs) > 1:
+        plain_ms = 0.0
+        same = True
+        for s, cfg in enumerate(cfgs):
+            p = mct2d.from_config(cfg, stream=stream.cuda_stream)
+            ms, _ = timed_run(p, stream, steps, 0)
+            plain_ms += ms
+            lg = p.crack_set()
+            same = same and all(np.array_equal(lg[k], logs[s][k]) for k in ("step", "elem", "entry", "exit", "G"))
+            p.close()
+        out["batched_vs_plain"] = {"speedup": plain_ms / gpu_ms, "plain_ms_total": plain_ms,
+                                   "batched_ms": gpu_ms, "identical_crack_sets": bool(same)}
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(cfgs[0], args.cpu_steps)
     print(json.dumps(out), flush=True)
 
 

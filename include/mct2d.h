@@ -124,9 +124,8 @@ int mct_set_notch(mct_ctx *ctx, int64_t n, const int32_t *elem, const uint8_t *e
  * (shortest edge) / c_d with c_d = sqrt(E / (rho (1 - nu^2))). */
 int mct_set_time(mct_ctx *ctx, double dt, double cfl_fraction);
 
-/* Build the derived arrays (areas, lumped mass, equivalent nodal forces,
- * time step, crack-path geometry), upload everything and zero the state
- * (u = v = 0, step 0).  Errors: MCT_ESTATE if mesh or material is missing,
+/* Build the derived arrays (lumped mass, equivalent nodal forces, time
+ * step), upload everything and zero the state (u = v = 0, step 0).  Errors: MCT_ESTATE if mesh or material is missing,
  * MCT_ENOMEM / MCT_EDEVICE on device failures. */
 int mct_finalize(mct_ctx *ctx);
 
@@ -155,6 +154,14 @@ int mct_get_tips(mct_ctx *ctx, int64_t cap, int32_t *edge, double *xy, int64_t *
  * (2 n_nodes values). */
 int mct_get_field(mct_ctx *ctx, int which, int64_t cap, double *out);
 
+/* Crack-path geometry of n elements (Sec. 2.2, Fig. 2-3: the three paths
+ * from the midpoint G0 of tip edge a to the midpoints Gk of the other edges)
+ * as the step evaluates it on the GPU: 36 doubles per element, for a = 0..3
+ * and j = 0..2 (exit edge k = a+1+j mod 4) the unit normal (x, y) of the
+ * segment G0-Gk oriented toward node n_{a+1}, and its length (reference
+ * coordinates).  Elements out of range give MCT_EINVAL. */
+int mct_get_path_geometry(mct_ctx *ctx, int64_t n, const int32_t *elem, double *out);
+
 /* Split code of every element (n_elems bytes). */
 int mct_get_split_codes(mct_ctx *ctx, int64_t cap, uint8_t *out);
 
@@ -165,10 +172,36 @@ int mct_get_split_codes(mct_ctx *ctx, int64_t cap, uint8_t *out);
 int mct_checkpoint(mct_ctx *ctx, void *host_buf, int64_t cap, int64_t *bytes);
 int mct_restore(mct_ctx *ctx, const void *host_buf, int64_t bytes);
 
-/* Launch tuning: tile shape index (0 = automatic) and whether mct_step
- * replays captured HIP graphs (1, default) or launches kernel by kernel (0).
- * Neither changes any result. */
+/* Launch tuning: tile shape index (0 = automatic, 1 = 16x16, 2 = 32x8,
+ * 3 = 32x16 elements per workgroup) and whether mct_step replays captured
+ * HIP graphs (1, default) or launches kernel by kernel (0).  Results do not
+ * depend on either (fixed summation orders). */
 int mct_set_launch(mct_ctx *ctx, int tile, int use_graph);
+
+/* Batch of independent specimens (same step, one launch per time step over
+ * all their tiles).  Each specimen is set up like a plain model after
+ * mct_batch_select(ctx, s); mct_finalize / mct_step act on the whole batch;
+ * every query and set-up call acts on the selected specimen.  Specimens may
+ * differ in mesh, material, Gc field, loads, notch and time step.  A plain
+ * context (mct_create) is a batch of one.  Errors: MCT_EINVAL for
+ * n_specimens < 1 or s out of range. */
+int mct_batch_create(mct_ctx **out, int64_t n_specimens, int precision, void *hip_stream);
+int mct_batch_select(mct_ctx *ctx, int64_t s);
+
+/* Order in which the workgroups of a batch take (specimen, tile) units:
+ * -1 automatic, 0 specimen order banded per XCD, 1 specimen order
+ * interleaved over XCDs, 2 largest specimens first, banded.  Results do not
+ * depend on it. */
+int mct_set_order(mct_ctx *ctx, int order);
+
+/* Launch autotuner: times trial_steps steps for every tile shape (and, for
+ * a batch, every unit order) from the current state, restores that state
+ * and keeps the fastest choice.  Outputs (any may be NULL): the chosen tile,
+ * order and its time per step in microseconds. */
+int mct_autotune(mct_ctx *ctx, int trial_steps, int *tile, int *order, double *us_per_step);
+
+/* Launch shape in use: tile index, unit order, workgroups per step. */
+int mct_get_launch(mct_ctx *ctx, int *tile, int *order, int64_t *workgroups);
 
 #ifdef __cplusplus
 }

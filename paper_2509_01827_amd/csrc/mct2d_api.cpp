@@ -1,6 +1,11 @@
 // Host side of the MCT-2D-CEM library: the C ABI declared in mct2d.h,
 // mesh/material/load set-up, device memory, step launching (HIP graphs of
-// step kernels) and queries.
+// step kernels), queries, batching of independent specimens and the launch
+// autotuner.
+//
+// A context holds one or more specimens.  A plain context (mct_create) has
+// one; a batch (mct_batch_create) has many, which share one launch per time
+// step.  Set-up calls and queries act on the selected specimen.
 #include "../../include/mct2d.h"
 
 #include <algorithm>
@@ -9,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -21,7 +27,8 @@ using mct::StepParams;
 
 namespace {
 
-constexpr int kGraphSteps = 64;  // kernels per captured graph
+constexpr int kGraphSteps = 64;  // steps per captured graph segment
+constexpr int kNumOrders = 3;    // work-unit orders of a batch (see build_units)
 
 struct TractionEdge {
     int64_t id;
@@ -29,16 +36,9 @@ struct TractionEdge {
     double tx, ty;
 };
 
-}  // namespace
-
-struct mct_ctx {
-    std::string err;
-    int precision = 64;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    int device = 0;
-
-    // mesh and settings (host copies)
+// One specimen: set-up inputs as given, derived sizes and offsets into the
+// batch arrays, and the device view the kernels use.
+struct Spec {
     int32_t nx = 0, ny = 0;
     std::vector<double> X, Y;
     bool have_material = false;
@@ -52,26 +52,43 @@ struct mct_ctx {
     std::vector<int32_t> notch_elem;
     std::vector<uint8_t> notch_code;
     double dt_in = 0, cfl = 0.5;
-
     // derived
-    bool finalized = false;
     double dt = 0;
     int64_t nn = 0, ne = 0, ns = 0, np = 0;
+    int64_t node_off = 0, elem_off = 0, perim_off = 0, tile_base = 0;
+    StepParams prm{};
+};
+
+}  // namespace
+
+struct mct_ctx {
+    std::string err;
+    int precision = 64;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int device = 0;
+
+    std::vector<Spec> specs;
+    int sel = 0;
+    bool batch = false;
+
+    bool finalized = false;
     int tile_req = 0, tile = 3;
+    int order_req = -1, order = 0;
     bool use_graph = true;
 
-    // device
+    // device arrays, specimens concatenated
     double *dX = nullptr, *dY = nullptr, *dux[2] = {nullptr, nullptr}, *duy[2] = {nullptr, nullptr};
-    double *dvx = nullptr, *dvy = nullptr, *dminv = nullptr, *dgc = nullptr, *dgeom = nullptr;
+    double *dvx = nullptr, *dvy = nullptr, *dminv = nullptr, *dgc = nullptr;
     double *dfext = nullptr, *dv0 = nullptr;
     uint8_t *dvmask = nullptr, *dsplit = nullptr;
     Control *dctl = nullptr;
     Slot *dslots = nullptr;
     LogRec *dlog = nullptr;
-    int32_t log_cap = 0;
-    int32_t *dtip_counts = nullptr, *dtip_edge = nullptr, *dtip_total = nullptr;
-    double *dtip_xy = nullptr;
-    StepParams prm{};
+    StepParams *dviews = nullptr;
+    int2 *dunits = nullptr;
+    int nunits = 0;
+    int32_t *dtip_counts = nullptr, *dtip_total = nullptr;
 
     hipGraphExec_t graph[2] = {nullptr, nullptr};  // by parity of the first step
     int graph_tile[2] = {0, 0};
@@ -111,6 +128,7 @@ void drop_graphs(mct_ctx *c) {
 }
 
 void release_device(mct_ctx *c) {
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
     drop_graphs(c);
     dfree(c->dX);
     dfree(c->dY);
@@ -122,7 +140,6 @@ void release_device(mct_ctx *c) {
     dfree(c->dvy);
     dfree(c->dminv);
     dfree(c->dgc);
-    dfree(c->dgeom);
     dfree(c->dfext);
     dfree(c->dv0);
     dfree(c->dvmask);
@@ -130,14 +147,16 @@ void release_device(mct_ctx *c) {
     dfree(c->dctl);
     dfree(c->dslots);
     dfree(c->dlog);
+    dfree(c->dviews);
+    dfree(c->dunits);
     dfree(c->dtip_counts);
-    dfree(c->dtip_edge);
     dfree(c->dtip_total);
-    dfree(c->dtip_xy);
     c->finalized = false;
 }
 
-int64_t node_of(const mct_ctx *c, int i, int j) { return (int64_t)j * (c->nx + 1) + i; }
+Spec &cur(mct_ctx *c) { return c->specs[c->sel]; }
+
+int64_t node_of(const Spec &s, int i, int j) { return (int64_t)j * (s.nx + 1) + i; }
 
 int perimeter_index(int i, int j, int nx, int ny) {
     if (j == 0) return i;
@@ -149,9 +168,9 @@ int perimeter_index(int i, int j, int nx, int ny) {
 
 // Id of the edge joining nodes a and b of the grid, or -1.  Edges are
 // numbered in ascending (smaller node, larger node) order.
-int64_t edge_id(const mct_ctx *c, int64_t a, int64_t b) {
+int64_t edge_id(const Spec &s, int64_t a, int64_t b) {
     const int64_t lo = std::min(a, b), hi = std::max(a, b);
-    const int nx = c->nx, ny = c->ny;
+    const int nx = s.nx, ny = s.ny;
     const int i = (int)(lo % (nx + 1)), j = (int)(lo / (nx + 1));
     const int64_t row = 2 * (int64_t)nx + 1;
     if (hi == lo + 1 && i < nx) return (j < ny) ? j * row + 2 * i : (int64_t)ny * row + i;
@@ -159,53 +178,111 @@ int64_t edge_id(const mct_ctx *c, int64_t a, int64_t b) {
     return -1;
 }
 
-bool boundary_edge(const mct_ctx *c, int64_t a, int64_t b) {
+bool boundary_edge(const Spec &s, int64_t a, int64_t b) {
     const int64_t lo = std::min(a, b), hi = std::max(a, b);
-    const int nx = c->nx, ny = c->ny;
-    const int i = (int)(lo % (nx + 1)), j = (int)(lo / (nx + 1));
-    if (hi == lo + 1) return j == 0 || j == ny;
-    return i == 0 || i == nx;
+    const int i = (int)(lo % (s.nx + 1)), j = (int)(lo / (s.nx + 1));
+    if (hi == lo + 1) return j == 0 || j == s.ny;
+    return i == 0 || i == s.nx;
 }
 
-void elem_nodes(const mct_ctx *c, int64_t e, int64_t n[4]) {
-    const int i = (int)(e % c->nx), j = (int)(e / c->nx);
-    n[0] = node_of(c, i, j);
-    n[1] = node_of(c, i + 1, j);
-    n[2] = node_of(c, i + 1, j + 1);
-    n[3] = node_of(c, i, j + 1);
-}
-
-double elem_area(const mct_ctx *c, int64_t e) {
-    int64_t n[4];
-    elem_nodes(c, e, n);
-    const double *X = c->X.data(), *Y = c->Y.data();
+double elem_area(const Spec &s, int64_t e) {
+    const int i = (int)(e % s.nx), j = (int)(e / s.nx);
+    const int64_t n[4] = {node_of(s, i, j), node_of(s, i + 1, j), node_of(s, i + 1, j + 1), node_of(s, i, j + 1)};
+    const double *X = s.X.data(), *Y = s.Y.data();
     return 0.5 * ((X[n[2]] - X[n[0]]) * (Y[n[3]] - Y[n[1]]) - (X[n[3]] - X[n[1]]) * (Y[n[2]] - Y[n[0]]));
 }
 
-template <typename T>
-int upload(mct_ctx *c, T *&dst, const T *src, size_t n) {
-    HIP_TRY(c, hipMalloc((void **)&dst, std::max<size_t>(n, 1) * sizeof(T)));
-    if (n) HIP_TRY(c, hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyHostToDevice, c->stream));
-    return MCT_OK;
+void tiles_of(const Spec &s, int tile, int &ntx, int &nty) {
+    const mct::TileShape t = mct::tile_shape(tile);
+    ntx = (s.nx + 1 + t.txe - 2) / (t.txe - 1);
+    nty = (s.ny + 1 + t.tye - 2) / (t.tye - 1);
+}
+
+int64_t total_tiles(const mct_ctx *c, int tile) {
+    int64_t n = 0;
+    for (const Spec &s : c->specs) {
+        int a, b;
+        tiles_of(s, tile, a, b);
+        n += (int64_t)a * b;
+    }
+    return n;
 }
 
 int pick_tile(const mct_ctx *c) {
     if (c->tile_req >= 1 && c->tile_req <= mct::kNumTiles) return c->tile_req;
     // largest tile that still gives every CU several workgroups
-    for (int t : {3, 2, 1}) {
-        const mct::TileShape s = mct::tile_shape(t);
-        const int64_t nwg = ((c->nx + 1 + s.txe - 2) / (s.txe - 1)) * (int64_t)((c->ny + 1 + s.tye - 2) / (s.tye - 1));
-        if (nwg >= 4 * 256) return t;
-    }
-    return 1;
+    for (int t : {3, 2})
+        if (total_tiles(c, t) >= 4 * 256) return t;
+    return 2;
 }
 
-void set_launch_geometry(mct_ctx *c) {
+// Work-unit order of a batch: which (specimen, tile) each workgroup takes.
+// Workgroup ids are dealt round-robin over the 8 XCDs, so "banded" orders
+// give each XCD a contiguous run of the list (neighbouring tiles share an L2).
+//   0: specimens in id order, banded;
+//   1: specimens in id order, consecutive workgroups on different XCDs;
+//   2: largest specimens first, banded.
+std::vector<int2> build_units(const mct_ctx *c, int order) {
+    std::vector<int> ord(c->specs.size());
+    std::iota(ord.begin(), ord.end(), 0);
+    if (order == 2)
+        std::stable_sort(ord.begin(), ord.end(),
+                         [&](int a, int b) { return c->specs[a].prm.nwg > c->specs[b].prm.nwg; });
+    std::vector<int2> list;
+    for (int s : ord)
+        for (int t = 0; t < c->specs[s].prm.nwg; ++t) list.push_back(make_int2(s, t));
+    if (order == 1) return list;
+    const int n = (int)list.size(), q = n / 8, r = n % 8;
+    std::vector<int2> out(n);
+    for (int b = 0; b < n; ++b) {
+        const int x = b % 8, l = b / 8;
+        out[b] = list[(x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + l];
+    }
+    return out;
+}
+
+// (Re)build tile geometry, slot sets, views and work units for the chosen
+// tile shape and order.  Device state is untouched.
+int set_launch_geometry(mct_ctx *c) {
     c->tile = pick_tile(c);
-    const mct::TileShape s = mct::tile_shape(c->tile);
-    c->prm.ntx = (c->nx + 1 + s.txe - 2) / (s.txe - 1);
-    c->prm.nty = (c->ny + 1 + s.tye - 2) / (s.tye - 1);
-    c->prm.nwg = c->prm.ntx * c->prm.nty;
+    c->order = (c->order_req >= 0 && c->order_req < kNumOrders) ? c->order_req : 0;
+    int64_t base = 0;
+    for (Spec &s : c->specs) {
+        tiles_of(s, c->tile, s.prm.ntx, s.prm.nty);
+        s.prm.nwg = s.prm.ntx * s.prm.nty;
+        s.tile_base = base;
+        base += s.prm.nwg;
+    }
+    drop_graphs(c);
+    if (!c->finalized) return MCT_OK;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    dfree(c->dslots);
+    HIP_TRY(c, hipMalloc((void **)&c->dslots, 3 * sizeof(Slot) * (size_t)std::max<int64_t>(base, 1)));
+    for (Spec &s : c->specs) s.prm.slots = c->dslots + 3 * s.tile_base;
+    if (c->batch) {
+        std::vector<StepParams> views;
+        for (const Spec &s : c->specs) views.push_back(s.prm);
+        dfree(c->dviews);
+        dfree(c->dunits);
+        HIP_TRY(c, hipMalloc((void **)&c->dviews, sizeof(StepParams) * views.size()));
+        HIP_TRY(c, hipMemcpy(c->dviews, views.data(), sizeof(StepParams) * views.size(), hipMemcpyHostToDevice));
+        const std::vector<int2> units = build_units(c, c->order);
+        c->nunits = (int)units.size();
+        HIP_TRY(c, hipMalloc((void **)&c->dunits, sizeof(int2) * units.size()));
+        HIP_TRY(c, hipMemcpy(c->dunits, units.data(), sizeof(int2) * units.size(), hipMemcpyHostToDevice));
+    }
+    return MCT_OK;
+}
+
+mct::Launch launch_of(const mct_ctx *c) {
+    mct::Launch L;
+    L.batched = c->batch;
+    L.p0 = c->specs[0].prm;
+    L.views = c->dviews;
+    L.units = c->dunits;
+    L.nunits = c->nunits;
+    L.nspec = (int)c->specs.size();
+    return L;
 }
 
 // A segment of kGraphSteps steps followed by its commit, captured once per
@@ -216,9 +293,10 @@ int build_graph(mct_ctx *c, int par0) {
     hipStream_t cap;
     HIP_TRY(c, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     hipGraph_t g = nullptr;
+    const mct::Launch L = launch_of(c);
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
-    for (int i = 0; e == hipSuccess && i < kGraphSteps; ++i) e = mct::launch_step(c->tile, c->prm, i, par0, cap);
-    if (e == hipSuccess) e = mct::launch_commit(c->prm, kGraphSteps, cap);
+    for (int i = 0; e == hipSuccess && i < kGraphSteps; ++i) e = mct::launch_step(c->tile, L, i, par0, cap);
+    if (e == hipSuccess) e = mct::launch_commit(L, kGraphSteps, cap);
     hipError_t e2 = hipStreamEndCapture(cap, &g);
     if (e == hipSuccess) e = e2;
     if (e == hipSuccess) e = hipGraphInstantiate(&c->graph[par0], g, nullptr, nullptr, 0);
@@ -229,17 +307,16 @@ int build_graph(mct_ctx *c, int par0) {
     return MCT_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-int mct_create(mct_ctx **out, int precision, void *hip_stream) {
+int create_ctx(mct_ctx **out, int nspec, bool batch, int precision, void *hip_stream) {
     if (!out) return MCT_EINVAL;
     *out = nullptr;
     if (precision != 64) return MCT_EUNSUPPORTED;
+    if (nspec < 1 || nspec > (1 << 20)) return MCT_EINVAL;
     mct_ctx *c = new (std::nothrow) mct_ctx;
     if (!c) return MCT_ENOMEM;
     c->precision = precision;
+    c->batch = batch;
+    c->specs.resize(nspec);
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         return MCT_EDEVICE;
@@ -257,9 +334,42 @@ int mct_create(mct_ctx **out, int precision, void *hip_stream) {
     return MCT_OK;
 }
 
+template <typename T>
+int upload(mct_ctx *c, T *&dst, const std::vector<T> &src) {
+    HIP_TRY(c, hipMalloc((void **)&dst, std::max<size_t>(src.size(), 1) * sizeof(T)));
+    if (!src.empty())
+        HIP_TRY(c, hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    return MCT_OK;
+}
+
+int read_control(mct_ctx *c, int s, Control *h) {
+    HIP_TRY(c, hipMemcpyAsync(h, c->dctl + s, sizeof(Control), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return MCT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mct_create(mct_ctx **out, int precision, void *hip_stream) {
+    return create_ctx(out, 1, false, precision, hip_stream);
+}
+
+int mct_batch_create(mct_ctx **out, int64_t n_specimens, int precision, void *hip_stream) {
+    if (n_specimens < 1 || n_specimens > (1 << 20)) return MCT_EINVAL;
+    return create_ctx(out, (int)n_specimens, true, precision, hip_stream);
+}
+
+int mct_batch_select(mct_ctx *c, int64_t s) {
+    if (!c) return MCT_EINVAL;
+    if (s < 0 || s >= (int64_t)c->specs.size()) return fail(c, MCT_EINVAL, "specimen %lld out of range", (long long)s);
+    c->sel = (int)s;
+    return MCT_OK;
+}
+
 int mct_destroy(mct_ctx *c) {
     if (!c) return MCT_OK;
-    if (c->stream) (void)hipStreamSynchronize(c->stream);
     release_device(c);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
@@ -273,71 +383,66 @@ int mct_set_mesh_grid(mct_ctx *c, int32_t nx, int32_t ny, const double *X, const
     if (nx < 2 || ny < 2 || !X || !Y) return fail(c, MCT_EINVAL, "grid needs nx, ny >= 2 and coordinates");
     if ((int64_t)nx * ny > (int64_t)1 << 30) return fail(c, MCT_EINVAL, "grid too large");
     release_device(c);
-    c->nx = nx;
-    c->ny = ny;
-    c->nn = (int64_t)(nx + 1) * (ny + 1);
-    c->ne = (int64_t)nx * ny;
-    c->ns = 2 * (int64_t)nx * ny + nx + ny;
-    c->np = 2 * (int64_t)(nx + 1) + 2 * (int64_t)(ny - 1);
-    c->X.assign(X, X + c->nn);
-    c->Y.assign(Y, Y + c->nn);
-    for (int64_t e = 0; e < c->ne; ++e)
-        if (!(elem_area(c, e) > 0.0))
+    Spec s;
+    s.nx = nx;
+    s.ny = ny;
+    s.nn = (int64_t)(nx + 1) * (ny + 1);
+    s.ne = (int64_t)nx * ny;
+    s.ns = 2 * (int64_t)nx * ny + nx + ny;
+    s.np = 2 * (int64_t)(nx + 1) + 2 * (int64_t)(ny - 1);
+    s.X.assign(X, X + s.nn);
+    s.Y.assign(Y, Y + s.nn);
+    for (int64_t e = 0; e < s.ne; ++e)
+        if (!(elem_area(s, e) > 0.0))
             return fail(c, MCT_EINVAL, "element %lld has non-positive area (clockwise or degenerate)", (long long)e);
-    c->have_material = false;
-    c->gc.clear();
-    c->traction.clear();
-    c->vbc_node.clear();
-    c->vbc_mask.clear();
-    c->vbc_v0.clear();
-    c->notch_elem.clear();
-    c->notch_code.clear();
-    c->dt_in = 0;
-    c->cfl = 0.5;
+    cur(c) = std::move(s);
     return MCT_OK;
 }
 
 int mct_set_material(mct_ctx *c, double E, double nu, double rho, const double *Gc, double Gc_uniform,
                      double gamma) {
     if (!c) return MCT_EINVAL;
-    if (!c->nx) return fail(c, MCT_ESTATE, "set the mesh first");
+    Spec &s = cur(c);
+    if (!s.nx) return fail(c, MCT_ESTATE, "set the mesh first");
     if (!(E > 0) || !(nu > -1.0 && nu < 0.5) || !(rho > 0) || !(gamma > 0))
         return fail(c, MCT_EINVAL, "material out of range");
     if (Gc) {
-        for (int64_t e = 0; e < c->ne; ++e)
+        for (int64_t e = 0; e < s.ne; ++e)
             if (!(Gc[e] > 0)) return fail(c, MCT_EINVAL, "Gc[%lld] <= 0", (long long)e);
-        c->gc.assign(Gc, Gc + c->ne);
+        s.gc.assign(Gc, Gc + s.ne);
     } else {
         if (!(Gc_uniform > 0)) return fail(c, MCT_EINVAL, "Gc_uniform <= 0");
-        c->gc.clear();
+        s.gc.clear();
     }
-    c->E = E;
-    c->nu = nu;
-    c->rho = rho;
-    c->gamma = gamma;
-    c->gc_uniform = Gc_uniform;
-    c->have_material = true;
+    s.E = E;
+    s.nu = nu;
+    s.rho = rho;
+    s.gamma = gamma;
+    s.gc_uniform = Gc_uniform;
+    s.have_material = true;
     c->finalized = false;
     return MCT_OK;
 }
 
 int mct_set_traction(mct_ctx *c, int64_t n, const int32_t *edge_nodes, const double *t) {
     if (!c) return MCT_EINVAL;
-    if (!c->nx) return fail(c, MCT_ESTATE, "set the mesh first");
+    Spec &s = cur(c);
+    if (!s.nx) return fail(c, MCT_ESTATE, "set the mesh first");
     if (n < 0 || (n && (!edge_nodes || !t))) return fail(c, MCT_EINVAL, "bad traction arrays");
     std::vector<TractionEdge> v;
     for (int64_t i = 0; i < n; ++i) {
         const int64_t a = edge_nodes[2 * i], b = edge_nodes[2 * i + 1];
-        if (a < 0 || b < 0 || a >= c->nn || b >= c->nn) return fail(c, MCT_EINVAL, "traction edge %lld: node out of range", (long long)i);
-        const int64_t id = edge_id(c, a, b);
-        if (id < 0 || !boundary_edge(c, a, b))
+        if (a < 0 || b < 0 || a >= s.nn || b >= s.nn)
+            return fail(c, MCT_EINVAL, "traction edge %lld: node out of range", (long long)i);
+        const int64_t id = edge_id(s, a, b);
+        if (id < 0 || !boundary_edge(s, a, b))
             return fail(c, MCT_EINVAL, "traction edge %lld is not a boundary edge", (long long)i);
         v.push_back({id, (int32_t)std::min(a, b), (int32_t)std::max(a, b), t[2 * i], t[2 * i + 1]});
     }
     std::sort(v.begin(), v.end(), [](const TractionEdge &x, const TractionEdge &y) { return x.id < y.id; });
     for (size_t i = 1; i < v.size(); ++i)
         if (v[i].id == v[i - 1].id) return fail(c, MCT_EINVAL, "repeated traction edge");
-    c->traction.swap(v);
+    s.traction.swap(v);
     c->finalized = false;
     return MCT_OK;
 }
@@ -345,36 +450,40 @@ int mct_set_traction(mct_ctx *c, int64_t n, const int32_t *edge_nodes, const dou
 int mct_set_velocity_bc(mct_ctx *c, int64_t n, const int32_t *node, const uint8_t *dof_mask, const double *v0,
                         double t_ramp) {
     if (!c) return MCT_EINVAL;
-    if (!c->nx) return fail(c, MCT_ESTATE, "set the mesh first");
+    Spec &s = cur(c);
+    if (!s.nx) return fail(c, MCT_ESTATE, "set the mesh first");
     if (n < 0 || (n && (!node || !dof_mask || !v0)) || !(t_ramp >= 0))
         return fail(c, MCT_EINVAL, "bad velocity arrays");
     for (int64_t i = 0; i < n; ++i) {
-        if (node[i] < 0 || node[i] >= c->nn || (dof_mask[i] & ~3u))
+        if (node[i] < 0 || node[i] >= s.nn || (dof_mask[i] & ~3u))
             return fail(c, MCT_EINVAL, "velocity bc %lld out of range", (long long)i);
-        const int ii = (int)(node[i] % (c->nx + 1)), jj = (int)(node[i] / (c->nx + 1));
-        if (perimeter_index(ii, jj, c->nx, c->ny) < 0)
+        const int ii = (int)(node[i] % (s.nx + 1)), jj = (int)(node[i] / (s.nx + 1));
+        if (perimeter_index(ii, jj, s.nx, s.ny) < 0)
             return fail(c, MCT_EINVAL, "velocity bc on interior node %d is not supported", node[i]);
     }
-    c->vbc_node.assign(node, node + n);
-    c->vbc_mask.assign(dof_mask, dof_mask + n);
-    c->vbc_v0.assign(v0, v0 + 2 * n);
-    c->t_ramp = t_ramp;
+    s.vbc_node.assign(node, node + n);
+    s.vbc_mask.assign(dof_mask, dof_mask + n);
+    s.vbc_v0.assign(v0, v0 + 2 * n);
+    s.t_ramp = t_ramp;
     c->finalized = false;
     return MCT_OK;
 }
 
 int mct_set_notch(mct_ctx *c, int64_t n, const int32_t *elem, const uint8_t *entry, const uint8_t *exit) {
     if (!c) return MCT_EINVAL;
-    if (!c->nx) return fail(c, MCT_ESTATE, "set the mesh first");
+    Spec &s = cur(c);
+    if (!s.nx) return fail(c, MCT_ESTATE, "set the mesh first");
     if (n < 0 || (n && (!elem || !entry || !exit))) return fail(c, MCT_EINVAL, "bad notch arrays");
-    c->notch_elem.clear();
-    c->notch_code.clear();
+    std::vector<int32_t> el;
+    std::vector<uint8_t> code;
     for (int64_t i = 0; i < n; ++i) {
-        if (elem[i] < 0 || elem[i] >= c->ne || entry[i] > 3 || exit[i] > 3 || entry[i] == exit[i])
+        if (elem[i] < 0 || elem[i] >= s.ne || entry[i] > 3 || exit[i] > 3 || entry[i] == exit[i])
             return fail(c, MCT_EINVAL, "notch element %lld invalid", (long long)i);
-        c->notch_elem.push_back(elem[i]);
-        c->notch_code.push_back((uint8_t)(mct::kSplitFlag | (entry[i] << 2) | exit[i]));
+        el.push_back(elem[i]);
+        code.push_back((uint8_t)(mct::kSplitFlag | (entry[i] << 2) | exit[i]));
     }
+    s.notch_elem.swap(el);
+    s.notch_code.swap(code);
     c->finalized = false;
     return MCT_OK;
 }
@@ -382,8 +491,9 @@ int mct_set_notch(mct_ctx *c, int64_t n, const int32_t *elem, const uint8_t *ent
 int mct_set_time(mct_ctx *c, double dt, double cfl_fraction) {
     if (!c) return MCT_EINVAL;
     if (!(dt > 0) && !(cfl_fraction > 0)) return fail(c, MCT_EINVAL, "need dt > 0 or cfl_fraction > 0");
-    c->dt_in = dt;
-    c->cfl = cfl_fraction;
+    Spec &s = cur(c);
+    s.dt_in = dt;
+    s.cfl = cfl_fraction;
     c->finalized = false;
     return MCT_OK;
 }
@@ -393,179 +503,168 @@ int mct_set_launch(mct_ctx *c, int tile, int use_graph) {
     if (tile < 0 || tile > mct::kNumTiles) return fail(c, MCT_EINVAL, "tile index out of range");
     c->tile_req = tile;
     c->use_graph = use_graph != 0;
-    if (c->finalized) {
-        HIP_TRY(c, hipStreamSynchronize(c->stream));
-        set_launch_geometry(c);
-        drop_graphs(c);
-        // three slot sets of one entry per workgroup of the chosen shape
-        dfree(c->dslots);
-        HIP_TRY(c, hipMalloc((void **)&c->dslots, 3 * sizeof(Slot) * (size_t)c->prm.nwg));
-        c->prm.slots = c->dslots;
-    }
-    return MCT_OK;
+    return set_launch_geometry(c);
+}
+
+int mct_set_order(mct_ctx *c, int order) {
+    if (!c) return MCT_EINVAL;
+    if (order < -1 || order >= kNumOrders) return fail(c, MCT_EINVAL, "order out of range");
+    c->order_req = order;
+    return set_launch_geometry(c);
 }
 
 int mct_finalize(mct_ctx *c) {
     if (!c) return MCT_EINVAL;
-    if (!c->nx || !c->have_material) return fail(c, MCT_ESTATE, "mesh and material are required");
+    for (size_t q = 0; q < c->specs.size(); ++q)
+        if (!c->specs[q].nx || !c->specs[q].have_material)
+            return fail(c, MCT_ESTATE, "specimen %zu: mesh and material are required", q);
     release_device(c);
-    const int nx = c->nx, ny = c->ny;
-    const double *X = c->X.data(), *Y = c->Y.data();
 
-    // lumped mass: rho A_e / 4 from each element, element-id order per node
-    std::vector<double> area(c->ne), minv(c->nn);
-    for (int64_t e = 0; e < c->ne; ++e) area[e] = elem_area(c, e);
-    for (int j = 0; j <= ny; ++j)
-        for (int i = 0; i <= nx; ++i) {
-            double m = 0.0;
-            const int ei[4] = {i - 1, i, i - 1, i}, ej[4] = {j - 1, j - 1, j, j};
-            for (int q = 0; q < 4; ++q) {
-                if (ei[q] < 0 || ei[q] >= nx || ej[q] < 0 || ej[q] >= ny) continue;
-                m += c->rho * area[(int64_t)ej[q] * nx + ei[q]] / 4.0;
-            }
-            minv[node_of(c, i, j)] = 1.0 / m;
-        }
-
-    // equivalent nodal forces of the tractions (edge-id order), prescribed
-    // velocities, on perimeter-indexed arrays
-    std::vector<double> fext(2 * c->np, 0.0), v0(2 * c->np, 0.0);
-    std::vector<uint8_t> vmask(c->np, 0);
-    for (const TractionEdge &t : c->traction) {
-        const double dx = X[t.hi] - X[t.lo], dy = Y[t.hi] - Y[t.lo];
-        const double L = std::sqrt(dx * dx + dy * dy);
-        const double fx = t.tx * L * 0.5, fy = t.ty * L * 0.5;
-        for (int32_t nd : {t.lo, t.hi}) {
-            const int pi = perimeter_index(nd % (nx + 1), nd / (nx + 1), nx, ny);
-            fext[2 * pi] += fx;
-            fext[2 * pi + 1] += fy;
-        }
+    int64_t nn = 0, ne = 0, np = 0;
+    bool any_gc = false;
+    for (Spec &s : c->specs) {
+        s.node_off = nn;
+        s.elem_off = ne;
+        s.perim_off = np;
+        nn += s.nn;
+        ne += s.ne;
+        np += s.np;
+        any_gc = any_gc || !s.gc.empty();
     }
-    for (size_t q = 0; q < c->vbc_node.size(); ++q) {
-        const int nd = c->vbc_node[q];
-        const int pi = perimeter_index(nd % (nx + 1), nd / (nx + 1), nx, ny);
-        vmask[pi] = c->vbc_mask[q];
-        v0[2 * pi] = c->vbc_v0[2 * q];
-        v0[2 * pi + 1] = c->vbc_v0[2 * q + 1];
-    }
+    std::vector<double> X(nn), Y(nn), minv(nn), fext(2 * np, 0.0), v0(2 * np, 0.0), gc;
+    std::vector<uint8_t> vmask(np, 0), split(ne, 0);
+    if (any_gc) gc.resize(ne);
 
-    // time step
-    if (c->dt_in > 0) {
-        c->dt = c->dt_in;
-    } else {
-        double hmin = INFINITY;
+    for (Spec &s : c->specs) {
+        const int nx = s.nx, ny = s.ny;
+        const double *sX = s.X.data(), *sY = s.Y.data();
+        std::copy(s.X.begin(), s.X.end(), X.begin() + s.node_off);
+        std::copy(s.Y.begin(), s.Y.end(), Y.begin() + s.node_off);
+        // lumped mass: rho A_e / 4 from each element, element-id order per node
+        std::vector<double> area(s.ne);
+        for (int64_t e = 0; e < s.ne; ++e) area[e] = elem_area(s, e);
         for (int j = 0; j <= ny; ++j)
             for (int i = 0; i <= nx; ++i) {
-                const int64_t a = node_of(c, i, j);
-                if (i < nx) {
-                    const double dx = X[a + 1] - X[a], dy = Y[a + 1] - Y[a];
-                    hmin = std::min(hmin, std::sqrt(dx * dx + dy * dy));
+                double m = 0.0;
+                const int ei[4] = {i - 1, i, i - 1, i}, ej[4] = {j - 1, j - 1, j, j};
+                for (int q = 0; q < 4; ++q) {
+                    if (ei[q] < 0 || ei[q] >= nx || ej[q] < 0 || ej[q] >= ny) continue;
+                    m += s.rho * area[(int64_t)ej[q] * nx + ei[q]] / 4.0;
                 }
-                if (j < ny) {
-                    const int64_t b = a + nx + 1;
-                    const double dx = X[b] - X[a], dy = Y[b] - Y[a];
-                    hmin = std::min(hmin, std::sqrt(dx * dx + dy * dy));
-                }
+                minv[s.node_off + node_of(s, i, j)] = 1.0 / m;
             }
-        const double cd = std::sqrt(c->E / (c->rho * (1.0 - c->nu * c->nu)));
-        c->dt = c->cfl * hmin / cd;
-    }
-
-    // crack-path geometry per element: for tip edge a and exit edge
-    // k = a+1+j, the unit normal of the segment between the two edge
-    // midpoints, oriented toward node n_{a+1}, and its length
-    std::vector<double> geom((size_t)c->ne * 36);
-    for (int64_t e = 0; e < c->ne; ++e) {
-        int64_t n[4];
-        elem_nodes(c, e, n);
-        for (int a = 0; a < 4; ++a) {
-            const int64_t p0 = n[a], p1 = n[(a + 1) & 3];
-            const double g0x = 0.5 * (X[p0] + X[p1]), g0y = 0.5 * (Y[p0] + Y[p1]);
-            for (int j = 0; j < 3; ++j) {
-                const int k = (a + 1 + j) & 3;
-                const int64_t q0 = n[k], q1 = n[(k + 1) & 3];
-                const double gkx = 0.5 * (X[q0] + X[q1]), gky = 0.5 * (Y[q0] + Y[q1]);
-                const double dx = gkx - g0x, dy = gky - g0y;
-                const double L = std::sqrt(dx * dx + dy * dy);
-                double cx = dy / L, cy = -dx / L;
-                if (cx * (X[p1] - g0x) + cy * (Y[p1] - g0y) < 0.0) {
-                    cx = -cx;
-                    cy = -cy;
-                }
-                double *g = &geom[(size_t)e * 36 + a * 9 + 3 * j];
-                g[0] = cx;
-                g[1] = cy;
-                g[2] = L;
+        // equivalent nodal forces of the tractions (edge-id order) and
+        // prescribed velocities, on perimeter-indexed arrays
+        double *fe = fext.data() + 2 * s.perim_off;
+        for (const TractionEdge &t : s.traction) {
+            const double dx = sX[t.hi] - sX[t.lo], dy = sY[t.hi] - sY[t.lo];
+            const double L = std::sqrt(dx * dx + dy * dy);
+            const double fx = t.tx * L * 0.5, fy = t.ty * L * 0.5;
+            for (int32_t nd : {t.lo, t.hi}) {
+                const int pi = perimeter_index(nd % (nx + 1), nd / (nx + 1), nx, ny);
+                fe[2 * pi] += fx;
+                fe[2 * pi + 1] += fy;
             }
         }
+        for (size_t q = 0; q < s.vbc_node.size(); ++q) {
+            const int nd = s.vbc_node[q];
+            const int pi = perimeter_index(nd % (nx + 1), nd / (nx + 1), nx, ny);
+            vmask[s.perim_off + pi] = s.vbc_mask[q];
+            v0[2 * (s.perim_off + pi)] = s.vbc_v0[2 * q];
+            v0[2 * (s.perim_off + pi) + 1] = s.vbc_v0[2 * q + 1];
+        }
+        // time step
+        if (s.dt_in > 0) {
+            s.dt = s.dt_in;
+        } else {
+            double hmin = INFINITY;
+            for (int j = 0; j <= ny; ++j)
+                for (int i = 0; i <= nx; ++i) {
+                    const int64_t a = node_of(s, i, j);
+                    if (i < nx) {
+                        const double dx = sX[a + 1] - sX[a], dy = sY[a + 1] - sY[a];
+                        hmin = std::min(hmin, std::sqrt(dx * dx + dy * dy));
+                    }
+                    if (j < ny) {
+                        const int64_t b = a + nx + 1;
+                        const double dx = sX[b] - sX[a], dy = sY[b] - sY[a];
+                        hmin = std::min(hmin, std::sqrt(dx * dx + dy * dy));
+                    }
+                }
+            const double cd = std::sqrt(s.E / (s.rho * (1.0 - s.nu * s.nu)));
+            s.dt = s.cfl * hmin / cd;
+        }
+        for (size_t q = 0; q < s.notch_elem.size(); ++q) split[s.elem_off + s.notch_elem[q]] = s.notch_code[q];
+        if (any_gc && !s.gc.empty()) std::copy(s.gc.begin(), s.gc.end(), gc.begin() + s.elem_off);
     }
-
-    std::vector<uint8_t> split(c->ne, 0);
-    for (size_t q = 0; q < c->notch_elem.size(); ++q) split[c->notch_elem[q]] = c->notch_code[q];
-
-    set_launch_geometry(c);
-    c->log_cap = (int32_t)std::min<int64_t>(c->ne, INT32_MAX);
 
     int rc;
-    if ((rc = upload(c, c->dX, X, c->nn))) return rc;
-    if ((rc = upload(c, c->dY, Y, c->nn))) return rc;
-    if ((rc = upload(c, c->dminv, minv.data(), c->nn))) return rc;
-    if ((rc = upload(c, c->dgeom, geom.data(), geom.size()))) return rc;
-    if ((rc = upload(c, c->dfext, fext.data(), fext.size()))) return rc;
-    if ((rc = upload(c, c->dv0, v0.data(), v0.size()))) return rc;
-    if ((rc = upload(c, c->dvmask, vmask.data(), vmask.size()))) return rc;
-    if ((rc = upload(c, c->dsplit, split.data(), split.size()))) return rc;
-    if (!c->gc.empty() && (rc = upload(c, c->dgc, c->gc.data(), c->gc.size()))) return rc;
+    if ((rc = upload(c, c->dX, X))) return rc;
+    if ((rc = upload(c, c->dY, Y))) return rc;
+    if ((rc = upload(c, c->dminv, minv))) return rc;
+    if ((rc = upload(c, c->dfext, fext))) return rc;
+    if ((rc = upload(c, c->dv0, v0))) return rc;
+    if ((rc = upload(c, c->dvmask, vmask))) return rc;
+    if ((rc = upload(c, c->dsplit, split))) return rc;
+    if (any_gc && (rc = upload(c, c->dgc, gc))) return rc;
     for (int i = 0; i < 2; ++i) {
-        HIP_TRY(c, hipMalloc((void **)&c->dux[i], sizeof(double) * c->nn));
-        HIP_TRY(c, hipMalloc((void **)&c->duy[i], sizeof(double) * c->nn));
-        HIP_TRY(c, hipMemsetAsync(c->dux[i], 0, sizeof(double) * c->nn, c->stream));
-        HIP_TRY(c, hipMemsetAsync(c->duy[i], 0, sizeof(double) * c->nn, c->stream));
+        HIP_TRY(c, hipMalloc((void **)&c->dux[i], sizeof(double) * nn));
+        HIP_TRY(c, hipMalloc((void **)&c->duy[i], sizeof(double) * nn));
+        HIP_TRY(c, hipMemsetAsync(c->dux[i], 0, sizeof(double) * nn, c->stream));
+        HIP_TRY(c, hipMemsetAsync(c->duy[i], 0, sizeof(double) * nn, c->stream));
     }
-    HIP_TRY(c, hipMalloc((void **)&c->dvx, sizeof(double) * c->nn));
-    HIP_TRY(c, hipMalloc((void **)&c->dvy, sizeof(double) * c->nn));
-    HIP_TRY(c, hipMemsetAsync(c->dvx, 0, sizeof(double) * c->nn, c->stream));
-    HIP_TRY(c, hipMemsetAsync(c->dvy, 0, sizeof(double) * c->nn, c->stream));
-    HIP_TRY(c, hipMalloc((void **)&c->dctl, sizeof(Control)));
-    HIP_TRY(c, hipMemsetAsync(c->dctl, 0, sizeof(Control), c->stream));
-    HIP_TRY(c, hipMalloc((void **)&c->dslots, 3 * sizeof(Slot) * (size_t)c->prm.nwg));
-    HIP_TRY(c, hipMalloc((void **)&c->dlog, sizeof(LogRec) * (size_t)std::max(c->log_cap, 1)));
-    const int nb = mct::tips_nblocks(c->ns);
-    HIP_TRY(c, hipMalloc((void **)&c->dtip_counts, sizeof(int32_t) * (size_t)nb));
+    HIP_TRY(c, hipMalloc((void **)&c->dvx, sizeof(double) * nn));
+    HIP_TRY(c, hipMalloc((void **)&c->dvy, sizeof(double) * nn));
+    HIP_TRY(c, hipMemsetAsync(c->dvx, 0, sizeof(double) * nn, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->dvy, 0, sizeof(double) * nn, c->stream));
+    HIP_TRY(c, hipMalloc((void **)&c->dctl, sizeof(Control) * c->specs.size()));
+    HIP_TRY(c, hipMemsetAsync(c->dctl, 0, sizeof(Control) * c->specs.size(), c->stream));
+    // the log of a specimen holds up to one split per element
+    HIP_TRY(c, hipMalloc((void **)&c->dlog, sizeof(LogRec) * (size_t)std::max<int64_t>(ne, 1)));
+    int64_t max_ns = 0;
+    for (const Spec &s : c->specs) max_ns = std::max(max_ns, s.ns);
+    HIP_TRY(c, hipMalloc((void **)&c->dtip_counts, sizeof(int32_t) * (size_t)mct::tips_nblocks(max_ns)));
     HIP_TRY(c, hipMalloc((void **)&c->dtip_total, sizeof(int32_t)));
 
-    StepParams &p = c->prm;
-    p.nx = nx;
-    p.ny = ny;
-    p.log_cap = c->log_cap;
-    p.X = c->dX;
-    p.Y = c->dY;
-    p.ux0 = c->dux[0];
-    p.uy0 = c->duy[0];
-    p.ux1 = c->dux[1];
-    p.uy1 = c->duy[1];
-    p.vx = c->dvx;
-    p.vy = c->dvy;
-    p.minv = c->dminv;
-    p.split = c->dsplit;
-    p.gc = c->dgc;
-    p.gc_uniform = c->gc_uniform;
-    p.geom = c->dgeom;
-    p.fext_p = c->dfext;
-    p.vmask_p = c->dvmask;
-    p.v0_p = c->dv0;
-    p.D11 = c->E / (1.0 - c->nu * c->nu);
-    p.D12 = c->nu * p.D11;
-    p.D33 = c->E / (2.0 * (1.0 + c->nu));
-    p.E = c->E;
-    p.dt = c->dt;
-    p.t_ramp = c->t_ramp;
-    p.gamma = c->gamma;
-    p.ctl = c->dctl;
-    p.slots = c->dslots;
-    p.log = c->dlog;
+    for (size_t q = 0; q < c->specs.size(); ++q) {
+        Spec &s = c->specs[q];
+        StepParams &p = s.prm;
+        p.nx = s.nx;
+        p.ny = s.ny;
+        p.log_cap = (int32_t)std::min<int64_t>(s.ne, INT32_MAX);
+        p.X = c->dX + s.node_off;
+        p.Y = c->dY + s.node_off;
+        p.ux0 = c->dux[0] + s.node_off;
+        p.uy0 = c->duy[0] + s.node_off;
+        p.ux1 = c->dux[1] + s.node_off;
+        p.uy1 = c->duy[1] + s.node_off;
+        p.vx = c->dvx + s.node_off;
+        p.vy = c->dvy + s.node_off;
+        p.minv = c->dminv + s.node_off;
+        p.split = c->dsplit + s.elem_off;
+        p.gc = s.gc.empty() ? nullptr : c->dgc + s.elem_off;
+        p.gc_uniform = s.gc_uniform;
+        p.fext_p = c->dfext + 2 * s.perim_off;
+        p.vmask_p = c->dvmask + s.perim_off;
+        p.v0_p = c->dv0 + 2 * s.perim_off;
+        p.D11 = s.E / (1.0 - s.nu * s.nu);
+        p.D12 = s.nu * p.D11;
+        p.D33 = s.E / (2.0 * (1.0 + s.nu));
+        p.E = s.E;
+        p.dt = s.dt;
+        p.t_ramp = s.t_ramp;
+        p.gamma = s.gamma;
+        p.ctl = c->dctl + q;
+        p.log = c->dlog + s.elem_off;
+    }
+    c->finalized = true;  // the launch geometry below needs the device arrays
+    rc = set_launch_geometry(c);
+    if (rc) {
+        c->finalized = false;
+        return rc;
+    }
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->steps_enqueued = 0;
-    c->finalized = true;
     return MCT_OK;
 }
 
@@ -586,12 +685,13 @@ int mct_step(mct_ctx *c, int64_t n) {
             c->steps_enqueued += kGraphSteps;
         }
     }
+    const mct::Launch L = launch_of(c);
     while (left > 0) {
         // direct segment, closed by its commit
         const int seg = (int)std::min<int64_t>(left, 1 << 20);
         const int par0 = (int)(c->steps_enqueued & 1);
-        for (int i = 0; i < seg; ++i) HIP_TRY(c, mct::launch_step(c->tile, c->prm, i, par0, c->stream));
-        HIP_TRY(c, mct::launch_commit(c->prm, seg, c->stream));
+        for (int i = 0; i < seg; ++i) HIP_TRY(c, mct::launch_step(c->tile, L, i, par0, c->stream));
+        HIP_TRY(c, mct::launch_commit(L, seg, c->stream));
         left -= seg;
         c->steps_enqueued += seg;
     }
@@ -604,23 +704,18 @@ int mct_sync(mct_ctx *c) {
     return MCT_OK;
 }
 
-static int read_control(mct_ctx *c, Control *h) {
-    HIP_TRY(c, hipMemcpyAsync(h, c->dctl, sizeof(Control), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    return MCT_OK;
-}
-
 int mct_get_info(mct_ctx *c, mct_info *out) {
     if (!c || !out) return MCT_EINVAL;
     std::memset(out, 0, sizeof *out);
-    out->n_nodes = c->nn;
-    out->n_elems = c->ne;
-    out->n_edges = c->ns;
-    out->dt = c->dt;
+    const Spec &s = cur(c);
+    out->n_nodes = s.nn;
+    out->n_elems = s.ne;
+    out->n_edges = s.ns;
+    out->dt = s.dt;
     out->precision = c->precision;
     if (!c->finalized) return MCT_OK;
     Control h;
-    int rc = read_control(c, &h);
+    int rc = read_control(c, c->sel, &h);
     if (rc) return rc;
     out->step = h.base;
     out->n_splits = h.nsplit;
@@ -633,15 +728,16 @@ int mct_get_crack_set(mct_ctx *c, int64_t cap, int32_t *step, int32_t *elem, uin
                       double *G, int64_t *count) {
     if (!c || !count) return MCT_EINVAL;
     if (!c->finalized) return fail(c, MCT_ESTATE, "finalize first");
+    const Spec &s = cur(c);
     Control h;
-    int rc = read_control(c, &h);
+    int rc = read_control(c, c->sel, &h);
     if (rc) return rc;
-    const int64_t n = std::min<int64_t>(h.nsplit, c->log_cap);
+    const int64_t n = std::min<int64_t>(h.nsplit, s.prm.log_cap);
     *count = n;
     if (cap < n) return fail(c, MCT_ECAPACITY, "crack set holds %lld splits", (long long)n);
     std::vector<LogRec> v((size_t)n);
     if (n) {
-        HIP_TRY(c, hipMemcpyAsync(v.data(), c->dlog, sizeof(LogRec) * (size_t)n, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(v.data(), s.prm.log, sizeof(LogRec) * (size_t)n, hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
     }
     for (int64_t i = 0; i < n; ++i) {
@@ -657,8 +753,9 @@ int mct_get_crack_set(mct_ctx *c, int64_t cap, int32_t *step, int32_t *elem, uin
 int mct_get_tips(mct_ctx *c, int64_t cap, int32_t *edge, double *xy, int64_t *count) {
     if (!c || !count) return MCT_EINVAL;
     if (!c->finalized) return fail(c, MCT_ESTATE, "finalize first");
+    const Spec &s = cur(c);
     int32_t nb = 0, total = 0;
-    HIP_TRY(c, mct::launch_tips(c->nx, c->ny, c->dX, c->dY, c->dsplit, c->dtip_counts, &nb, nullptr, nullptr,
+    HIP_TRY(c, mct::launch_tips(s.nx, s.ny, s.prm.X, s.prm.Y, s.prm.split, c->dtip_counts, &nb, nullptr, nullptr,
                                 c->dtip_total, c->stream));
     HIP_TRY(c, hipMemcpyAsync(&total, c->dtip_total, sizeof total, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -672,7 +769,7 @@ int mct_get_tips(mct_ctx *c, int64_t cap, int32_t *edge, double *xy, int64_t *co
         (void)hipFree(de);
         return fail(c, MCT_ENOMEM, "tip buffers");
     }
-    hipError_t e = mct::launch_tips(c->nx, c->ny, c->dX, c->dY, c->dsplit, c->dtip_counts, &nb, de, dxy,
+    hipError_t e = mct::launch_tips(s.nx, s.ny, s.prm.X, s.prm.Y, s.prm.split, c->dtip_counts, &nb, de, dxy,
                                     c->dtip_total, c->stream);
     if (e == hipSuccess && edge)
         e = hipMemcpyAsync(edge, de, sizeof(int32_t) * (size_t)total, hipMemcpyDeviceToHost, c->stream);
@@ -688,63 +785,106 @@ int mct_get_tips(mct_ctx *c, int64_t cap, int32_t *edge, double *xy, int64_t *co
 int mct_get_field(mct_ctx *c, int which, int64_t cap, double *out) {
     if (!c || !out) return MCT_EINVAL;
     if (!c->finalized) return fail(c, MCT_ESTATE, "finalize first");
-    if (cap < 2 * c->nn) return fail(c, MCT_ECAPACITY, "field needs %lld values", (long long)(2 * c->nn));
+    const Spec &s = cur(c);
+    if (cap < 2 * s.nn) return fail(c, MCT_ECAPACITY, "field needs %lld values", (long long)(2 * s.nn));
     Control h;
-    int rc = read_control(c, &h);
+    int rc = read_control(c, c->sel, &h);
     if (rc) return rc;
     const double *sx, *sy;
     if (which == MCT_FIELD_U) {
-        sx = c->dux[h.base & 1];
-        sy = c->duy[h.base & 1];
+        sx = (h.base & 1) ? s.prm.ux1 : s.prm.ux0;
+        sy = (h.base & 1) ? s.prm.uy1 : s.prm.uy0;
     } else if (which == MCT_FIELD_V) {
-        sx = c->dvx;
-        sy = c->dvy;
+        sx = s.prm.vx;
+        sy = s.prm.vy;
     } else {
         return fail(c, MCT_EINVAL, "unknown field %d", which);
     }
-    HIP_TRY(c, hipMemcpyAsync(out, sx, sizeof(double) * c->nn, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(out + c->nn, sy, sizeof(double) * c->nn, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(out, sx, sizeof(double) * s.nn, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(out + s.nn, sy, sizeof(double) * s.nn, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return MCT_OK;
+}
+
+int mct_get_path_geometry(mct_ctx *c, int64_t n, const int32_t *elem, double *out) {
+    if (!c || n < 0 || (n && (!elem || !out))) return MCT_EINVAL;
+    if (!c->finalized) return fail(c, MCT_ESTATE, "finalize first");
+    const Spec &s = cur(c);
+    if (n > INT32_MAX / 36) return fail(c, MCT_EINVAL, "too many elements");
+    for (int64_t i = 0; i < n; ++i)
+        if (elem[i] < 0 || elem[i] >= s.ne) return fail(c, MCT_EINVAL, "element %d out of range", elem[i]);
+    if (!n) return MCT_OK;
+    int32_t *de = nullptr;
+    double *dout = nullptr;
+    HIP_TRY(c, hipMalloc((void **)&de, sizeof(int32_t) * (size_t)n));
+    if (hipMalloc((void **)&dout, sizeof(double) * 36 * (size_t)n) != hipSuccess) {
+        (void)hipFree(de);
+        return fail(c, MCT_ENOMEM, "geometry buffer");
+    }
+    hipError_t e = hipMemcpyAsync(de, elem, sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = mct::launch_path_geometry(s.prm, (int)n, de, dout, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out, dout, sizeof(double) * 36 * (size_t)n, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(de);
+    (void)hipFree(dout);
+    if (e != hipSuccess) return fail(c, MCT_EDEVICE, "path geometry: %s", hipGetErrorString(e));
     return MCT_OK;
 }
 
 int mct_get_split_codes(mct_ctx *c, int64_t cap, uint8_t *out) {
     if (!c || !out) return MCT_EINVAL;
     if (!c->finalized) return fail(c, MCT_ESTATE, "finalize first");
-    if (cap < c->ne) return fail(c, MCT_ECAPACITY, "need %lld bytes", (long long)c->ne);
-    HIP_TRY(c, hipMemcpyAsync(out, c->dsplit, (size_t)c->ne, hipMemcpyDeviceToHost, c->stream));
+    const Spec &s = cur(c);
+    if (cap < s.ne) return fail(c, MCT_ECAPACITY, "need %lld bytes", (long long)s.ne);
+    HIP_TRY(c, hipMemcpyAsync(out, s.prm.split, (size_t)s.ne, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return MCT_OK;
 }
 
-// checkpoint layout: magic, nn, ne, Control, ux, uy, vx, vy, split, log
-static const uint64_t kMagic = 0x4d43543244434b31ull;  // "MCT2DCK1"
+// checkpoint layout: magic, number of specimens, then per specimen: nodes,
+// elements, Control, u, v (x then y), split codes, log records
+static const uint64_t kMagic = 0x4d43543244434b32ull;  // "MCT2DCK2"
 
 int mct_checkpoint(mct_ctx *c, void *buf, int64_t cap, int64_t *bytes) {
     if (!c || !bytes) return MCT_EINVAL;
     if (!c->finalized) return fail(c, MCT_ESTATE, "finalize first");
-    Control h;
-    int rc = read_control(c, &h);
-    if (rc) return rc;
-    const int64_t nlog = std::min<int64_t>(h.nsplit, c->log_cap);
-    const int64_t need = 3 * 8 + (int64_t)sizeof(Control) + 4 * 8 * c->nn + c->ne + nlog * (int64_t)sizeof(LogRec);
+    const int S = (int)c->specs.size();
+    std::vector<Control> h(S);
+    HIP_TRY(c, hipMemcpyAsync(h.data(), c->dctl, sizeof(Control) * S, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    int64_t need = 16;
+    for (int q = 0; q < S; ++q) {
+        const Spec &s = c->specs[q];
+        const int64_t nlog = std::min<int64_t>(h[q].nsplit, s.prm.log_cap);
+        need += 16 + (int64_t)sizeof(Control) + 32 * s.nn + s.ne + nlog * (int64_t)sizeof(LogRec);
+    }
     *bytes = need;
     if (!buf) return MCT_OK;
     if (cap < need) return fail(c, MCT_ECAPACITY, "checkpoint needs %lld bytes", (long long)need);
     char *p = (char *)buf;
-    const uint64_t hdr[3] = {kMagic, (uint64_t)c->nn, (uint64_t)c->ne};
+    const uint64_t hdr[2] = {kMagic, (uint64_t)S};
     std::memcpy(p, hdr, sizeof hdr);
     p += sizeof hdr;
-    std::memcpy(p, &h, sizeof h);
-    p += sizeof h;
-    const double *src[4] = {c->dux[h.base & 1], c->duy[h.base & 1], c->dvx, c->dvy};
-    for (int i = 0; i < 4; ++i) {
-        HIP_TRY(c, hipMemcpyAsync(p, src[i], 8 * c->nn, hipMemcpyDeviceToHost, c->stream));
-        p += 8 * c->nn;
+    for (int q = 0; q < S; ++q) {
+        const Spec &s = c->specs[q];
+        const uint64_t sh[2] = {(uint64_t)s.nn, (uint64_t)s.ne};
+        std::memcpy(p, sh, sizeof sh);
+        p += sizeof sh;
+        std::memcpy(p, &h[q], sizeof(Control));
+        p += sizeof(Control);
+        const int par = (int)(h[q].base & 1);
+        const double *src[4] = {par ? s.prm.ux1 : s.prm.ux0, par ? s.prm.uy1 : s.prm.uy0, s.prm.vx, s.prm.vy};
+        for (int i = 0; i < 4; ++i) {
+            HIP_TRY(c, hipMemcpyAsync(p, src[i], 8 * s.nn, hipMemcpyDeviceToHost, c->stream));
+            p += 8 * s.nn;
+        }
+        HIP_TRY(c, hipMemcpyAsync(p, s.prm.split, s.ne, hipMemcpyDeviceToHost, c->stream));
+        p += s.ne;
+        const int64_t nlog = std::min<int64_t>(h[q].nsplit, s.prm.log_cap);
+        if (nlog) HIP_TRY(c, hipMemcpyAsync(p, s.prm.log, sizeof(LogRec) * nlog, hipMemcpyDeviceToHost, c->stream));
+        p += sizeof(LogRec) * nlog;
     }
-    HIP_TRY(c, hipMemcpyAsync(p, c->dsplit, c->ne, hipMemcpyDeviceToHost, c->stream));
-    p += c->ne;
-    if (nlog) HIP_TRY(c, hipMemcpyAsync(p, c->dlog, sizeof(LogRec) * nlog, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return MCT_OK;
 }
@@ -752,31 +892,115 @@ int mct_checkpoint(mct_ctx *c, void *buf, int64_t cap, int64_t *bytes) {
 int mct_restore(mct_ctx *c, const void *buf, int64_t bytes) {
     if (!c || !buf) return MCT_EINVAL;
     if (!c->finalized) return fail(c, MCT_ESTATE, "finalize first");
-    const char *p = (const char *)buf;
-    if (bytes < 24 + (int64_t)sizeof(Control)) return fail(c, MCT_EINVAL, "checkpoint too short");
-    uint64_t hdr[3];
+    const char *p = (const char *)buf, *end = p + bytes;
+    const int S = (int)c->specs.size();
+    if (bytes < 16) return fail(c, MCT_EINVAL, "checkpoint too short");
+    uint64_t hdr[2];
     std::memcpy(hdr, p, sizeof hdr);
     p += sizeof hdr;
-    if (hdr[0] != kMagic || (int64_t)hdr[1] != c->nn || (int64_t)hdr[2] != c->ne)
-        return fail(c, MCT_EINVAL, "checkpoint does not match this mesh");
-    Control h;
-    std::memcpy(&h, p, sizeof h);
-    p += sizeof h;
-    const int64_t nlog = std::min<int64_t>(h.nsplit, c->log_cap);
-    const int64_t need = 24 + (int64_t)sizeof(Control) + 4 * 8 * c->nn + c->ne + nlog * (int64_t)sizeof(LogRec);
-    if (bytes < need || h.base < 0) return fail(c, MCT_EINVAL, "checkpoint truncated");
-    h.nslots[0] = h.nslots[1] = h.nslots[2] = 0;
-    HIP_TRY(c, hipMemcpyAsync(c->dctl, &h, sizeof h, hipMemcpyHostToDevice, c->stream));
-    double *dst[4] = {c->dux[h.base & 1], c->duy[h.base & 1], c->dvx, c->dvy};
-    for (int i = 0; i < 4; ++i) {
-        HIP_TRY(c, hipMemcpyAsync(dst[i], p, 8 * c->nn, hipMemcpyHostToDevice, c->stream));
-        p += 8 * c->nn;
+    if (hdr[0] != kMagic || (int64_t)hdr[1] != S) return fail(c, MCT_EINVAL, "checkpoint does not match this context");
+    // validate the whole buffer before touching the device
+    const char *q = p;
+    std::vector<Control> hs(S);
+    for (int s = 0; s < S; ++s) {
+        const Spec &sp = c->specs[s];
+        if (end - q < 16 + (int64_t)sizeof(Control)) return fail(c, MCT_EINVAL, "checkpoint truncated");
+        uint64_t sh[2];
+        std::memcpy(sh, q, sizeof sh);
+        if ((int64_t)sh[0] != sp.nn || (int64_t)sh[1] != sp.ne) return fail(c, MCT_EINVAL, "checkpoint mesh mismatch");
+        std::memcpy(&hs[s], q + 16, sizeof(Control));
+        if (hs[s].base < 0 || hs[s].base != hs[0].base || hs[s].nsplit < 0)
+            return fail(c, MCT_EINVAL, "checkpoint step mismatch");
+        const int64_t nlog = std::min<int64_t>(hs[s].nsplit, sp.prm.log_cap);
+        const int64_t len = 16 + (int64_t)sizeof(Control) + 32 * sp.nn + sp.ne + nlog * (int64_t)sizeof(LogRec);
+        if (end - q < len) return fail(c, MCT_EINVAL, "checkpoint truncated");
+        q += len;
     }
-    HIP_TRY(c, hipMemcpyAsync(c->dsplit, p, c->ne, hipMemcpyHostToDevice, c->stream));
-    p += c->ne;
-    if (nlog) HIP_TRY(c, hipMemcpyAsync(c->dlog, p, sizeof(LogRec) * nlog, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    c->steps_enqueued = h.base;
+    for (int s = 0; s < S; ++s) {
+        const Spec &sp = c->specs[s];
+        p += 16 + sizeof(Control);
+        Control h = hs[s];
+        h.nslots[0] = h.nslots[1] = h.nslots[2] = 0;
+        HIP_TRY(c, hipMemcpyAsync(c->dctl + s, &h, sizeof h, hipMemcpyHostToDevice, c->stream));
+        const int par = (int)(h.base & 1);
+        double *dst[4] = {par ? sp.prm.ux1 : sp.prm.ux0, par ? sp.prm.uy1 : sp.prm.uy0, sp.prm.vx, sp.prm.vy};
+        for (int i = 0; i < 4; ++i) {
+            HIP_TRY(c, hipMemcpyAsync(dst[i], p, 8 * sp.nn, hipMemcpyHostToDevice, c->stream));
+            p += 8 * sp.nn;
+        }
+        HIP_TRY(c, hipMemcpyAsync(sp.prm.split, p, sp.ne, hipMemcpyHostToDevice, c->stream));
+        p += sp.ne;
+        const int64_t nlog = std::min<int64_t>(h.nsplit, sp.prm.log_cap);
+        if (nlog) HIP_TRY(c, hipMemcpyAsync(sp.prm.log, p, sizeof(LogRec) * nlog, hipMemcpyHostToDevice, c->stream));
+        p += sizeof(LogRec) * nlog;
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->steps_enqueued = hs[0].base;
+    return MCT_OK;
+}
+
+int mct_autotune(mct_ctx *c, int trial_steps, int *tile_out, int *order_out, double *us_per_step_out) {
+    if (!c) return MCT_EINVAL;
+    if (!c->finalized) return fail(c, MCT_ESTATE, "finalize first");
+    if (trial_steps < 1) return fail(c, MCT_EINVAL, "trial_steps must be positive");
+    int64_t bytes = 0;
+    int rc = mct_checkpoint(c, nullptr, 0, &bytes);
+    if (rc) return rc;
+    std::vector<char> ck((size_t)bytes);
+    if ((rc = mct_checkpoint(c, ck.data(), bytes, &bytes))) return rc;
+    const int saved_tile = c->tile_req, saved_order = c->order_req;
+    const bool saved_graph = c->use_graph;
+    c->use_graph = false;  // candidates are timed with direct launches
+    float best = INFINITY;
+    int best_tile = 0, best_order = 0;
+    const int norders = c->batch ? kNumOrders : 1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = MCT_EDEVICE;
+    for (int t = 1; t <= mct::kNumTiles && rc == MCT_OK; ++t)
+        for (int o = 0; o < norders && rc == MCT_OK; ++o) {
+            c->tile_req = t;
+            c->order_req = o;
+            if ((rc = set_launch_geometry(c))) break;
+            if ((rc = mct_restore(c, ck.data(), bytes))) break;
+            if ((rc = mct_step(c, 2))) break;  // warm
+            if (hipEventRecord(e0, c->stream) != hipSuccess) rc = MCT_EDEVICE;
+            if (!rc) rc = mct_step(c, trial_steps);
+            if (!rc && hipEventRecord(e1, c->stream) != hipSuccess) rc = MCT_EDEVICE;
+            if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = MCT_EDEVICE;
+            float ms = 0.f;
+            if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = MCT_EDEVICE;
+            if (!rc && ms < best) {
+                best = ms;
+                best_tile = t;
+                best_order = o;
+            }
+        }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    c->use_graph = saved_graph;
+    if (rc) {
+        c->tile_req = saved_tile;
+        c->order_req = saved_order;
+        (void)set_launch_geometry(c);
+        (void)mct_restore(c, ck.data(), bytes);
+        return rc == MCT_EDEVICE ? fail(c, rc, "autotune timing failed") : rc;
+    }
+    c->tile_req = best_tile;
+    c->order_req = best_order;
+    if ((rc = set_launch_geometry(c))) return rc;
+    if ((rc = mct_restore(c, ck.data(), bytes))) return rc;
+    if (tile_out) *tile_out = best_tile;
+    if (order_out) *order_out = best_order;
+    if (us_per_step_out) *us_per_step_out = 1e3 * (double)best / trial_steps;
+    return MCT_OK;
+}
+
+int mct_get_launch(mct_ctx *c, int *tile, int *order, int64_t *workgroups) {
+    if (!c) return MCT_EINVAL;
+    if (tile) *tile = c->tile;
+    if (order) *order = c->order;
+    if (workgroups) *workgroups = c->batch ? c->nunits : c->specs[0].prm.nwg;
     return MCT_OK;
 }
 

@@ -40,10 +40,12 @@ struct Control {
     int32_t pad;
 };
 
+// One specimen as the kernels see it: sizes, constants and pointers already
+// offset to the specimen's part of the batch arrays.
 struct StepParams {
     int32_t nx, ny;     // elements per direction
     int32_t ntx, nty;   // tiles per direction
-    int32_t nwg;        // ntx * nty
+    int32_t nwg;        // ntx * nty (also the stride of the three slot sets)
     int32_t log_cap;
     const double *X, *Y;
     double *ux0, *uy0, *ux1, *uy1;  // displacement ping-pong, u^k in (k & 1)
@@ -52,7 +54,6 @@ struct StepParams {
     uint8_t *split;
     const double *gc;   // per element, or nullptr for gc_uniform
     double gc_uniform;
-    const double *geom; // 36 per element: for a in 0..3, j in 0..2: nx, ny, L
     const double *fext_p;     // 2 per perimeter node
     const uint8_t *vmask_p;   // 1 per perimeter node
     const double *v0_p;       // 2 per perimeter node
@@ -70,15 +71,28 @@ struct TileShape {
 constexpr int kNumTiles = 3;
 TileShape tile_shape(int tile);  // tile in 1..kNumTiles
 
+// What one step launch covers: a single specimen (p0, nwg tiles) or a batch
+// (nunits work units (specimen, tile) over nspec device-resident views).
+struct Launch {
+    bool batched;
+    StepParams p0;
+    const StepParams *views;
+    const int2 *units;
+    int nunits, nspec;
+};
+
 // One step of a segment (k_rel = index in the segment, par0 = parity of the
 // segment's first step), and the segment close after n steps.
-hipError_t launch_step(int tile, const StepParams &p, int k_rel, int par0, hipStream_t s);
-hipError_t launch_commit(const StepParams &p, int n, hipStream_t s);
+hipError_t launch_step(int tile, const Launch &L, int k_rel, int par0, hipStream_t s);
+hipError_t launch_commit(const Launch &L, int n, hipStream_t s);
 
 // Crack-surface tips: compacted edge ids and reference midpoints.
 hipError_t launch_tips(int32_t nx, int32_t ny, const double *X, const double *Y,
                        const uint8_t *split, int32_t *block_counts, int32_t *nblocks_out,
                        int32_t *edge_out, double *xy_out, int32_t *count_out, hipStream_t s);
 int tips_nblocks(int64_t n_edges);
+
+// Crack-path normals and lengths of n elements (36 doubles each).
+hipError_t launch_path_geometry(const StepParams &p, int n, const int32_t *elem, double *out, hipStream_t s);
 
 }  // namespace mct

@@ -134,6 +134,26 @@ __device__ __forceinline__ double quad_area(const double x[4], const double y[4]
     return 0.5 * ((x[2] - x[0]) * (y[3] - y[1]) - (x[3] - x[1]) * (y[2] - y[0]));
 }
 
+// Unit normal and length of the crack path from the midpoint of local edge
+// a to the midpoint of local edge k, oriented toward node n_{a+1}
+// (reference coordinates).  Uses correctly rounded sqrt and division only.
+__device__ __forceinline__ void path_geom(const double x[4], const double y[4], int a, int k, double &nxo,
+                                          double &nyo, double &len) {
+    const int a1 = (a + 1) & 3, k1 = (k + 1) & 3;
+    const double g0x = 0.5 * (x[a] + x[a1]), g0y = 0.5 * (y[a] + y[a1]);
+    const double gkx = 0.5 * (x[k] + x[k1]), gky = 0.5 * (y[k] + y[k1]);
+    const double dx = gkx - g0x, dy = gky - g0y;
+    const double L = sqrt(dx * dx + dy * dy);
+    double cx = dy / L, cy = -dx / L;
+    if (cx * (x[a1] - g0x) + cy * (y[a1] - g0y) < 0.0) {
+        cx = -cx;
+        cy = -cy;
+    }
+    nxo = cx;
+    nyo = cy;
+    len = L;
+}
+
 // Best-candidate order: larger G, then smaller element id, then smaller a.
 __device__ __forceinline__ bool better(double g1, int e1, int a1, double g2, int e2, int a2) {
     return g1 > g2 || (g1 == g2 && (e1 < e2 || (e1 == e2 && a1 < a2)));
@@ -213,8 +233,7 @@ __device__ __forceinline__ int xcd_tile(int b, int nwg) {
 // Reduce the candidates published in slot set `set` with the whole
 // workgroup; thread 0 receives the result.  Every thread must call it.
 template <int NT>
-__device__ __forceinline__ Cand reduce_slots(const StepParams &p, int set, Cand *red) {
-    const uint32_t n = p.ctl->nslots[set];
+__device__ __forceinline__ Cand reduce_slots(const StepParams &p, int set, uint32_t n, Cand *red) {
     const Slot *sl = p.slots + (size_t)set * p.nwg;
     Cand g;
     cand_none(g);
@@ -253,9 +272,18 @@ __device__ __forceinline__ void apply_split(const StepParams &p, const Cand &g, 
         ctl->overflow = 1;
     }
     ctl->nsplit = n + 1;
-    const int jk = (g.k - g.a - 1) & 3;
+    const int64_t i = g.e % p.nx, j = g.e / p.nx;
+    const int64_t n0 = j * (p.nx + 1) + i;
+    const int64_t nd[4] = {n0, n0 + 1, n0 + p.nx + 2, n0 + p.nx + 1};
+    double x[4], y[4];
+    for (int q = 0; q < 4; ++q) {
+        x[q] = p.X[nd[q]];
+        y[q] = p.Y[nd[q]];
+    }
+    double cx, cy, L;
+    path_geom(x, y, g.a, g.k, cx, cy, L);
     const double gc = p.gc ? p.gc[g.e] : p.gc_uniform;
-    ctl->Ud = ctl->Ud + gc * p.geom[(int64_t)g.e * 36 + g.a * 9 + 3 * jk + 2];
+    ctl->Ud = ctl->Ud + gc * L;
 }
 
 // One time step.  Steps run in segments (a captured graph or a run of direct
@@ -264,8 +292,14 @@ __device__ __forceinline__ void apply_split(const StepParams &p, const Cand &g, 
 // The pick of step k-1 is taken at the start of step k from the candidates
 // step k-1 published (slot set (k_rel-1) mod 3): every workgroup reduces
 // them, applies the split to its staged codes, and workgroup 0 records it.
-template <int TXE, int TYE>
-__global__ __launch_bounds__(TXE *TYE) void k_step(StepParams p, int k_rel, int par0) {
+//
+// BATCHED: the launch covers the tiles of many independent specimens; work
+// unit b = (specimen, tile) comes from `units` and the specimen's view (its
+// sizes, constants and pre-offset pointers) from `views`.  Otherwise the one
+// view `p0` is passed by value and workgroups map to tiles XCD-banded.
+template <int TXE, int TYE, bool BATCHED>
+__global__ __launch_bounds__(TXE *TYE) void k_step(StepParams p0, const StepParams *views, const int2 *units,
+                                                   int k_rel, int par0) {
     constexpr int NT = TXE * TYE;
     constexpr int TX = TXE - 1, TY = TYE - 1;  // owned nodes
     constexpr int HX = TXE + 3, HY = TYE + 3;  // staged nodes
@@ -275,21 +309,38 @@ __global__ __launch_bounds__(TXE *TYE) void k_step(StepParams p, int k_rel, int 
     static_assert(NT % 64 == 0, "whole wavefronts");
     static_assert(TX * TY <= NT, "one thread per owned node");
 
-    constexpr int NR = 2 * TXE + 2 * TYE;      // elements just outside the ring
+    static_assert(2 * (NH + NV) * 3 >= 8 * NT, "element forces fit over the strain slots");
     __shared__ double s_ux[HX * HY], s_uy[HX * HY], s_X[HX * HY], s_Y[HX * HY];
+    // per edge: w_lo (B u)_lo of the lower-id element (or (B u)_lo alone when
+    // the other side is not intact), (B u)_hi and w_hi of the higher-id one;
+    // after the force phase the same memory holds the element forces
+    __shared__ double s_q[2 * (NH + NV) * 3];
+    __shared__ double s_w1[NH + NV];
     __shared__ double s_area[EX * EY];
-    __shared__ double s_qlo[(NH + NV) * 3];  // B u of the lower-id element, then the edge stress
-    __shared__ double s_qhi[(NH + NV) * 3];  // B u of the higher-id element
-    __shared__ double s_acc[TX * TY * 2];
+    constexpr int NS = NH + NV;  // component stride of the per-edge arrays
+    double *const s_qlo = s_q;             // [3][NS]
+    double *const s_qhi = s_q + NS * 3;    // [3][NS]
+    double *const s_fe = s_q;              // [8][NT] after the force phase
     __shared__ uint8_t s_split[EX * EY];
     __shared__ uint16_t s_cand[4 * TX * TY];
-    __shared__ int s_ncand;
-    __shared__ int s_wbase[NT / 64];
+    __shared__ uint16_t s_splitl[NT];
+    __shared__ int s_ncand, s_nsplit;
+    __shared__ int s_wbase[NT / 64], s_wbase2[NT / 64];
     __shared__ Cand s_red[NT / 64];
 
     const int tid = threadIdx.x;
+    int tile;
+    StepParams p;
+    if constexpr (BATCHED) {
+        const int2 u = units[blockIdx.x];
+        p = views[u.x];
+        tile = u.y;
+    } else {
+        p = p0;
+        tile = xcd_tile(blockIdx.x, p.nwg);
+    }
+    const bool leader = tile == 0;  // records the specimen's previous pick
     const int nx = p.nx, ny = p.ny;
-    const int tile = xcd_tile(blockIdx.x, p.nwg);
     const int i0 = (tile % p.ntx) * TX, j0 = (tile / p.ntx) * TY;
     const int par = (par0 + k_rel) & 1;
     const double *ux_c = par ? p.ux1 : p.ux0;
@@ -300,29 +351,48 @@ __global__ __launch_bounds__(TXE *TYE) void k_step(StepParams p, int k_rel, int 
     const int64_t base = p.ctl->base;  // needed late (time, first step, log)
 
     // ---- 1. stage nodes and split codes; prefetch owned-node data ------
-    for (int idx = tid; idx < HX * HY; idx += NT) {
+    // Every global load of the phase is issued before the first LDS write,
+    // so the workgroup waits for one memory latency instead of several.
+    constexpr int NHALO = HX * HY, RH = (NHALO + NT - 1) / NT;
+    constexpr int NE2 = EX * EY, RE = (NE2 + NT - 1) / NT;
+    const uint32_t nprev = p.ctl->nslots[set_r];
+    double ra[RH], rb[RH], rc[RH], rd[RH];
+#pragma unroll
+    for (int r = 0; r < RH; ++r) {
+        const int idx = tid + r * NT;
         const int gi = i0 - 2 + idx % HX, gj = j0 - 2 + idx / HX;
-        double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
-        if (gi >= 0 && gi <= nx && gj >= 0 && gj <= ny) {
+        ra[r] = rb[r] = rc[r] = rd[r] = 0.0;
+        if (idx < NHALO && gi >= 0 && gi <= nx && gj >= 0 && gj <= ny) {
             const int64_t n = (int64_t)gj * (nx + 1) + gi;
-            a = ux_c[n];
-            b = uy_c[n];
-            c = p.X[n];
-            d = p.Y[n];
+            ra[r] = ux_c[n];
+            rb[r] = uy_c[n];
+            rc[r] = p.X[n];
+            rd[r] = p.Y[n];
         }
-        s_ux[idx] = a;
-        s_uy[idx] = b;
-        s_X[idx] = c;
-        s_Y[idx] = d;
     }
-    for (int idx = tid; idx < EX * EY; idx += NT) {
+    uint8_t rs[RE];
+    double rarea[RE];
+#pragma unroll
+    for (int r = 0; r < RE; ++r) {
+        const int idx = tid + r * NT;
         const int gi = i0 - 2 + idx % EX, gj = j0 - 2 + idx / EX;
-        uint8_t code = kAbsent;
-        if (gi >= 0 && gi < nx && gj >= 0 && gj < ny) code = p.split[(int64_t)gj * nx + gi];
-        s_split[idx] = code;
+        rs[r] = kAbsent;
+        rarea[r] = 0.0;
+        if (idx < NE2 && gi >= 0 && gi < nx && gj >= 0 && gj < ny) {
+            rs[r] = p.split[(int64_t)gj * nx + gi];
+            const int64_t n0 = (int64_t)gj * (nx + 1) + gi;
+            double x[4], y[4];
+            x[0] = p.X[n0];
+            x[1] = p.X[n0 + 1];
+            x[2] = p.X[n0 + nx + 2];
+            x[3] = p.X[n0 + nx + 1];
+            y[0] = p.Y[n0];
+            y[1] = p.Y[n0 + 1];
+            y[2] = p.Y[n0 + nx + 2];
+            y[3] = p.Y[n0 + nx + 1];
+            rarea[r] = quad_area(x, y);
+        }
     }
-    for (int idx = tid; idx < TX * TY * 2; idx += NT) s_acc[idx] = 0.0;
-    if (tid == 0) s_ncand = 0;
     // owned node of this thread
     const int on_l = tid % TX, on_m = tid / TX;
     const int on_i = i0 + on_l, on_j = j0 + on_m;
@@ -343,20 +413,40 @@ __global__ __launch_bounds__(TXE *TYE) void k_step(StepParams p, int k_rel, int 
             n_v0y = p.v0_p[2 * pidx + 1];
         }
     }
-
-    // ---- 2. the pick of the previous step -------------------------------
-    {
-        const Cand g = reduce_slots<NT>(p, set_r, s_red);  // contains a barrier
-        if (tid == 0) {
-            if (pick_accepted(p, g)) {
-                const int fx = g.e % nx - (i0 - 2), fy = g.e / nx - (j0 - 2);
-                if (fx >= 0 && fx < EX && fy >= 0 && fy < EY)
-                    s_split[fy * EX + fx] = (uint8_t)(kSplitFlag | (g.a << 2) | g.k);
-                if (blockIdx.x == 0) apply_split(p, g, base + k_rel - 1);
-            }
-            if (blockIdx.x == 0) p.ctl->nslots[set_c] = 0;
+#pragma unroll
+    for (int r = 0; r < RH; ++r) {
+        const int idx = tid + r * NT;
+        if (idx < NHALO) {
+            s_ux[idx] = ra[r];
+            s_uy[idx] = rb[r];
+            s_X[idx] = rc[r];
+            s_Y[idx] = rd[r];
         }
     }
+#pragma unroll
+    for (int r = 0; r < RE; ++r) {
+        const int idx = tid + r * NT;
+        if (idx < NE2) {
+            s_split[idx] = rs[r];
+            s_area[idx] = rarea[r];
+        }
+    }
+    if (tid == 0) {
+        s_ncand = 0;
+        s_nsplit = 0;
+    }
+
+    // ---- 2. the pick of the previous step -------------------------------
+    if (nprev > 0) {  // uniform over the workgroup
+        const Cand g = reduce_slots<NT>(p, set_r, nprev, s_red);  // contains a barrier
+        if (tid == 0 && pick_accepted(p, g)) {
+            const int fx = g.e % nx - (i0 - 2), fy = g.e / nx - (j0 - 2);
+            if (fx >= 0 && fx < EX && fy >= 0 && fy < EY)
+                s_split[fy * EX + fx] = (uint8_t)(kSplitFlag | (g.a << 2) | g.k);
+            if (leader) apply_split(p, g, base + k_rel - 1);
+        }
+    }
+    if (tid == 0 && leader) p.ctl->nslots[set_c] = 0;
     __syncthreads();
 
     auto elem_xy = [&](int ex, int ey, double x[4], double y[4]) {
@@ -382,117 +472,112 @@ __global__ __launch_bounds__(TXE *TYE) void k_step(StepParams p, int k_rel, int 
         uy[3] = s_uy[b + HX];
     };
 
-    // ---- 3. element gradients and strain contributions B u ---------------
-    // Element (ie, je) of the TXE x TYE ring around the owned nodes: its
-    // gradients at the four edge midpoints stay in registers for the force
-    // phase; B_k u_e goes to the edge's lower-id slot (s_qlo, for local edges
-    // 1 and 2) or higher-id slot (s_qhi, for edges 0 and 3).  Elements one
-    // further out contribute only to the edge they share with the ring.
+    // ---- 3. element gradients and weighted strain contributions ----------
+    // Element (ie, je) of the TXE x TYE ring around the owned nodes keeps its
+    // gradients at the four edge midpoints in registers for the force phase.
+    // For each of its edges it publishes its part of the smoothed strain
+    // eps_s = w_hi (B u)_hi + w_lo (B u)_lo (lower element id first,
+    // w_j = A_j / (A_lo + A_hi) over intact neighbours, w = 1 with one):
+    // as the lower-id element (local edges 1, 2) w_lo (B u)_lo, or (B u)_lo
+    // alone when the neighbour is not intact; as the higher-id element
+    // (local edges 0, 3) (B u)_hi and w_hi.  Elements one further out publish
+    // only the edge they share with the ring.
     const int ie = tid % TXE, je = tid / TXE;
     const int ex = ie + 1, ey = je + 1;
     const int e2 = ey * EX + ex;
-    const int gi = i0 - 1 + ie, gj = j0 - 1 + je;
     int sidx[4];  // edges of this element in local order (bottom, right, top, left)
     sidx[0] = je * TXE + ie;
     sidx[1] = NH + je * (TXE + 1) + ie + 1;
     sidx[2] = (je + 1) * TXE + ie;
     sidx[3] = NH + je * (TXE + 1) + ie;
+    const uint8_t code = s_split[e2];
+    auto nbr = [&](int e, int k) { return (k == 0) ? e - EX : (k == 1) ? e + 1 : (k == 2) ? e + EX : e - 1; };
+    // publish the strain part of element e (area A, strain q) at its edge k
+    auto publish = [&](int e, double A, int k, int sid, const double q[3]) {
+        const int nb = nbr(e, k);
+        const bool other = s_split[nb] == 0;
+        if (k == 1 || k == 2) {  // e is the lower-id element of the edge
+            if (other) {
+                const double w0 = A / (A + s_area[nb]);
+                s_qlo[0 * NS + sid] = w0 * q[0];
+                s_qlo[1 * NS + sid] = w0 * q[1];
+                s_qlo[2 * NS + sid] = w0 * q[2];
+            } else {
+                s_qlo[0 * NS + sid] = q[0];
+                s_qlo[1 * NS + sid] = q[1];
+                s_qlo[2 * NS + sid] = q[2];
+            }
+        } else {
+            s_qhi[0 * NS + sid] = q[0];
+            s_qhi[1 * NS + sid] = q[1];
+            s_qhi[2 * NS + sid] = q[2];
+            if (other) s_w1[sid] = A / (s_area[nb] + A);
+        }
+    };
     double gx[4][4], gy[4][4];
-    double my_area = 0.0;
-    {
-        const uint8_t c0 = s_split[e2];
-        if (c0 != kAbsent) {
-            double x[4], y[4];
-            elem_xy(ex, ey, x, y);
-            my_area = quad_area(x, y);
-            s_area[e2] = my_area;
-            if (c0 == 0) {
-                double ux[4], uy[4];
-                elem_u(ex, ey, ux, uy);
+    const double my_area = s_area[e2];
+    if (code == 0) {
+        double x[4], y[4];
+        elem_xy(ex, ey, x, y);
+        {
+            double ux[4], uy[4];
+            elem_u(ex, ey, ux, uy);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    q4_grad(x, y, k, gx[k], gy[k]);
-                    double q[3];
-                    strain<4>(gx[k], gy[k], ux, uy, q);
-                    double *dst = (k == 1 || k == 2) ? s_qlo : s_qhi;
-                    dst[3 * sidx[k] + 0] = q[0];
-                    dst[3 * sidx[k] + 1] = q[1];
-                    dst[3 * sidx[k] + 2] = q[2];
-                }
+            for (int k = 0; k < 4; ++k) {
+                q4_grad(x, y, k, gx[k], gy[k]);
+                double q[3];
+                strain<4>(gx[k], gy[k], ux, uy, q);
+                publish(e2, my_area, k, sidx[k], q);
             }
         }
     }
-    for (int r = tid; r < NR; r += NT) {
-        int rex, rey, rk, sid;
-        if (r < TXE) {  // below the ring: top edge
-            rex = r + 1; rey = 0; rk = 2; sid = r;
-        } else if (r < 2 * TXE) {  // above: bottom edge
-            rex = r - TXE + 1; rey = TYE + 1; rk = 0; sid = TYE * TXE + (r - TXE);
-        } else if (r < 2 * TXE + TYE) {  // left: right edge
-            rex = 0; rey = r - 2 * TXE + 1; rk = 1; sid = NH + (r - 2 * TXE) * (TXE + 1);
-        } else {  // right: left edge
-            rex = TXE + 1; rey = r - 2 * TXE - TYE + 1; rk = 3; sid = NH + (r - 2 * TXE - TYE) * (TXE + 1) + TXE;
+    // Elements just outside the ring: wavefront g (g = 0..3) takes the row
+    // below, the row above, the column left, the column right, so every
+    // wavefront evaluates one edge type.
+    {
+        static_assert(NT >= 256 && TXE <= 64 && TYE <= 64, "four wavefronts for the outer ring");
+        const int g = tid >> 6, r = tid & 63;
+        const int cnt = (g < 2) ? TXE : TYE;
+        if (g < 4 && r < cnt) {
+            int rex, rey, rk, sid;
+            if (g == 0) {  // below the ring: its top edge
+                rex = r + 1; rey = 0; rk = 2; sid = r;
+            } else if (g == 1) {  // above: bottom edge
+                rex = r + 1; rey = TYE + 1; rk = 0; sid = TYE * TXE + r;
+            } else if (g == 2) {  // left: right edge
+                rex = 0; rey = r + 1; rk = 1; sid = NH + r * (TXE + 1);
+            } else {  // right: left edge
+                rex = TXE + 1; rey = r + 1; rk = 3; sid = NH + r * (TXE + 1) + TXE;
+            }
+            const int re = rey * EX + rex;
+            if (s_split[re] == 0) {
+                double x[4], y[4], ux[4], uy[4], dx[4], dy[4], q[3];
+                elem_xy(rex, rey, x, y);
+                elem_u(rex, rey, ux, uy);
+                q4_grad_rt(x, y, rk, dx, dy);
+                strain<4>(dx, dy, ux, uy, q);
+                publish(re, s_area[re], rk, sid, q);
+            }
         }
-        const int re = rey * EX + rex;
-        const uint8_t rc = s_split[re];
-        if (rc == kAbsent) continue;
-        double x[4], y[4];
-        elem_xy(rex, rey, x, y);
-        s_area[re] = quad_area(x, y);
-        if (rc != 0) continue;
-        double ux[4], uy[4], dx[4], dy[4], q[3];
-        elem_u(rex, rey, ux, uy);
-        q4_grad_rt(x, y, rk, dx, dy);
-        strain<4>(dx, dy, ux, uy, q);
-        double *dst = (rk == 1 || rk == 2) ? s_qlo : s_qhi;
-        dst[3 * sid + 0] = q[0];
-        dst[3 * sid + 1] = q[1];
-        dst[3 * sid + 2] = q[2];
     }
     __syncthreads();
 
-    // ---- 3E. smoothed strain and stress at the edges -------------------
-    // horizontal edge (h, v): below element E2(h+1, v) (lower id), above
-    // E2(h+1, v+1).  Vertical edge (h, v): left E2(h, v+1) (lower id), right
-    // E2(h+1, v+1).  The stress overwrites the edge's s_qlo slot.
-    for (int idx = tid; idx < NH + NV; idx += NT) {
-        int elo, ehi;
-        if (idx < NH) {
-            const int h = idx % TXE, v = idx / TXE;
-            elo = v * EX + h + 1;
-            ehi = (v + 1) * EX + h + 1;
-        } else {
-            const int r = idx - NH;
-            const int h = r % (TXE + 1), v = r / (TXE + 1);
-            elo = (v + 1) * EX + h;
-            ehi = (v + 1) * EX + h + 1;
-        }
-        const bool ilo = s_split[elo] == 0, ihi = s_split[ehi] == 0;
+    // Smoothed stress at local edge k (edge slot sid) of the intact element e.
+    auto edge_sigma = [&](int e, int sid, int k, double sg[3]) {
         double eps[3];
-        if (ilo && ihi) {
-            const double alo = s_area[elo], ahi = s_area[ehi];
-            const double sum = alo + ahi;
-            const double w0 = alo / sum, w1 = ahi / sum;
+        if (s_split[nbr(e, k)] == 0) {
+            const double w1 = s_w1[sid];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) eps[c] = fma(w1, s_qhi[3 * idx + c], w0 * s_qlo[3 * idx + c]);
-        } else if (ilo) {
+            for (int c = 0; c < 3; ++c) eps[c] = fma(w1, s_qhi[c * NS + sid], s_qlo[c * NS + sid]);
+        } else {
+            const double *q = (k == 1 || k == 2) ? s_qlo : s_qhi;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) eps[c] = s_qlo[3 * idx + c];
-        } else if (ihi) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) eps[c] = s_qhi[3 * idx + c];
+            for (int c = 0; c < 3; ++c) eps[c] = q[c * NS + sid];
         }
-        double sg[3] = {0.0, 0.0, 0.0};
-        if (ilo || ihi) hooke(p, eps, sg);
-        s_qlo[3 * idx + 0] = sg[0];
-        s_qlo[3 * idx + 1] = sg[1];
-        s_qlo[3 * idx + 2] = sg[2];
-    }
-    __syncthreads();
-    const double *s_sig = s_qlo;
+        hooke(p, eps, sg);
+    };
 
     // ---- 4. element forces, one thread per element of the tile ring ----
-    const uint8_t code = s_split[e2];
     double fe[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) fe[c] = 0.0;
@@ -500,7 +585,8 @@ __global__ __launch_bounds__(TXE *TYE) void k_step(StepParams p, int k_rel, int 
         double sx[4], sy[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const double *sg = &s_sig[3 * sidx[k]];
+            double sg[3];
+            edge_sigma(e2, sidx[k], k, sg);
             const double s0 = sg[0], s1 = sg[1], s2 = sg[2];
 #pragma unroll
             for (int n = 0; n < 4; ++n) {
@@ -521,15 +607,122 @@ __global__ __launch_bounds__(TXE *TYE) void k_step(StepParams p, int k_rel, int 
             fe[2 * n] = c * sx[n];
             fe[2 * n + 1] = c * sy[n];
         }
-    } else if (code & kSplitFlag) {
+    }
+
+    // free-surface candidates of the elements this tile owns (node n0 owned),
+    // compacted with wavefront ballots into s_cand
+    const bool owned = ie >= 1 && je >= 1 && code == 0;
+    unsigned fmask = 0;
+    if (owned) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (s_split[nbr(e2, k)] != 0) fmask |= 1u << k;
+    }
+    const bool is_split = (code & kSplitFlag) != 0;
+    {
+        const int lane = tid & 63, wave = tid >> 6;
+        const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        uint64_t bal[4];
+        int wtotal = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            bal[k] = __ballot((fmask >> k) & 1u);
+            wtotal += __popcll(bal[k]);
+        }
+        const uint64_t bsp = __ballot(is_split);
+        if (lane == 0 && wtotal) s_wbase[wave] = atomicAdd(&s_ncand, wtotal);
+        if (lane == 0 && bsp) s_wbase2[wave] = atomicAdd(&s_nsplit, __popcll(bsp));
+        __syncthreads();
+        if (is_split) s_splitl[s_wbase2[wave] + __popcll(bsp & lt)] = (uint16_t)tid;
+        if (fmask) {
+            int off = s_wbase[wave];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if ((fmask >> k) & 1u) s_cand[off + __popcll(bal[k] & lt)] = (uint16_t)((tid << 2) | k);
+                off += __popcll(bal[k]);
+            }
+        }
+    }
+    const int ncand = s_ncand;
+    if (ncand > 0) __syncthreads();  // uniform: the list is complete
+
+    // ---- 5. energy release rate and element rule of the candidates ------
+    Cand best;
+    cand_none(best);
+    for (int c = tid; c < ncand; c += NT) {
+        const int t = s_cand[c] >> 2, a = s_cand[c] & 3;
+        const int cie = t % TXE, cje = t / TXE;
+        const int cex = cie + 1, cey = cje + 1;
+        const int ce2 = cey * EX + cex;
+        const int64_t ge = (int64_t)(j0 - 1 + cje) * nx + (i0 - 1 + cie);
+        double x[4], y[4], ux[4], uy[4];
+        elem_xy(cex, cey, x, y);
+        elem_u(cex, cey, ux, uy);
+        const int n1 = a, n2 = (a + 1) & 3;
+        const double dux = ux[n2] - ux[n1], duy = uy[n2] - uy[n1];
+        const double x1 = x[n1] + ux[n1], y1 = y[n1] + uy[n1];
+        const double x2 = x[n2] + ux[n2], y2 = y[n2] + uy[n2];
+        const double lx = x2 - x1, ly = y2 - y1;
+        const double Lx = x[n2] - x[n1], Ly = y[n2] - y[n1];
+        const bool H = (lx * lx + ly * ly) > (Lx * Lx + Ly * Ly);
+        if (!H) continue;  // G = 0 on all three paths
+        int cs[4];
+        cs[0] = cje * TXE + cie;
+        cs[1] = NH + cje * (TXE + 1) + cie + 1;
+        cs[2] = (cje + 1) * TXE + cie;
+        cs[3] = NH + cje * (TXE + 1) + cie;
+        double G[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int k = (a + 1 + j) & 3;
+            double sg[3], nxv, nyv, len;
+            edge_sigma(ce2, cs[k], k, sg);
+            path_geom(x, y, a, k, nxv, nyv, len);
+            const double spx = fma(sg[2], nyv, sg[0] * nxv);
+            const double spy = fma(sg[1], nyv, sg[2] * nxv);
+            G[j] = 0.5 * fma(duy, spy, dux * spx);
+        }
+        const double gc = p.gc ? p.gc[ge] : p.gc_uniform;
+        int jb = -1;
+        for (int j = 0; j < 3; ++j)
+            if (G[j] > gc && (jb < 0 || G[j] > G[jb])) jb = j;
+        if (jb < 0) continue;
+        bool ok = true;
+        for (int j = 0; j < 3; ++j) {
+            if (j == jb || !(G[j] > gc)) continue;
+            if (!(G[jb] > p.gamma * (G[jb] - G[j]))) ok = false;
+        }
+        if (!ok) continue;
+        cand_merge(best, G[jb], G[jb], (int)ge, a, (a + 1 + jb) & 3);
+    }
+    if (ncand > 0) cand_block_reduce<NT>(best, s_red);  // uniform branch
+    __syncthreads();  // strain slots are no longer read: reuse them for forces
+
+    // ---- 6. colour-ordered gather to the owned nodes --------------------
+    // f_int at a node = sum over its elements in colour order 0..3 (colour of
+    // element (i, j) = (i mod 2) + 2 (j mod 2)), as a coloured scatter
+    // would add them.
+    if (!is_split) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) s_fe[c * NT + tid] = fe[c];
+    }
+    // split elements of the tile ring, one per lane (compacted above)
+    const int nsplit_l = s_nsplit;
+    for (int si = tid; si < nsplit_l; si += NT) {
+        const int t = s_splitl[si];
+        const int sx_ = t % TXE + 1, sy_ = t / TXE + 1;
+        const uint8_t scode = s_split[sy_ * EX + sx_];
+        double sfe[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) sfe[c] = 0.0;
         // Split element: two pieces bounded by the crack segment between the
         // midpoints of the entry and exit edges.  3-node piece -> constant-
         // strain triangle, 2-node piece -> bar along the uncut edge, 1-node
         // piece -> no stiffness; each carries its polygon area.
         double x[4], y[4], ux[4], uy[4];
-        elem_xy(ex, ey, x, y);
-        elem_u(ex, ey, ux, uy);
-        const int ea = (code >> 2) & 3, eb = code & 3;
+        elem_xy(sx_, sy_, x, y);
+        elem_u(sx_, sy_, ux, uy);
+        const int ea = (scode >> 2) & 3, eb = scode & 3;
         for (int piece = 0; piece < 2; ++piece) {
             const int from = piece ? eb : ea, to = piece ? ea : eb;
             int loc[3];
@@ -569,8 +762,8 @@ __global__ __launch_bounds__(TXE *TYE) void k_step(StepParams p, int k_rel, int 
                 for (int i = 0; i < 3; ++i) {
                     const double tx = fma(cc[i], sg[2], b[i] * sg[0]);
                     const double ty = fma(b[i], sg[2], cc[i] * sg[1]);
-                    fe[2 * loc[i]] = Ap * tx;
-                    fe[2 * loc[i] + 1] = Ap * ty;
+                    sfe[2 * loc[i]] = Ap * tx;
+                    sfe[2 * loc[i] + 1] = Ap * ty;
                 }
             } else if (np == 2) {
                 const int a0 = loc[0], a1 = loc[1];
@@ -580,73 +773,39 @@ __global__ __launch_bounds__(TXE *TYE) void k_step(StepParams p, int k_rel, int 
                 const double st = (dx * dux + dy * duy) / L2;
                 const double stress = p.E * st;
                 const double coef = Ap * stress / L2;
-                fe[2 * a1] = coef * dx;
-                fe[2 * a1 + 1] = coef * dy;
-                fe[2 * a0] = -(coef * dx);
-                fe[2 * a0 + 1] = -(coef * dy);
+                sfe[2 * a1] = coef * dx;
+                sfe[2 * a1 + 1] = coef * dy;
+                sfe[2 * a0] = -(coef * dx);
+                sfe[2 * a0 + 1] = -(coef * dy);
             } else {
-                fe[2 * loc[0]] = 0.0;
-                fe[2 * loc[0] + 1] = 0.0;
+                sfe[2 * loc[0]] = 0.0;
+                sfe[2 * loc[0] + 1] = 0.0;
             }
         }
-    }
-
-    // free-surface candidates of the elements this tile owns (node n0 owned)
-    const bool owned = ie >= 1 && je >= 1 && code == 0;
-    unsigned fmask = 0;
-    if (owned) {
-        const uint8_t nb[4] = {s_split[e2 - EX], s_split[e2 + 1], s_split[e2 + EX], s_split[e2 - 1]};
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-            if (nb[k] != 0) fmask |= 1u << k;
+        for (int c = 0; c < 8; ++c) s_fe[c * NT + t] = sfe[c];
     }
-    {
-        const int lane = tid & 63, wave = tid >> 6;
-        const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-        uint64_t bal[4];
-        int wtotal = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            bal[k] = __ballot((fmask >> k) & 1u);
-            wtotal += __popcll(bal[k]);
-        }
-        if (lane == 0 && wtotal) s_wbase[wave] = atomicAdd(&s_ncand, wtotal);
-        __syncthreads();
-        if (fmask) {
-            int off = s_wbase[wave];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if ((fmask >> k) & 1u) s_cand[off + __popcll(bal[k] & lt)] = (uint16_t)((tid << 2) | k);
-                off += __popcll(bal[k]);
-            }
-        }
-    }
-
-    // ---- colour-ordered scatter to the owned nodes ----------------------
-    const bool valid_e = code != kAbsent;
-    const int color = (gi & 1) + 2 * (gj & 1);
-    for (int c = 0; c < 4; ++c) {
-        if (valid_e && color == c) {
-#pragma unroll
-            for (int n = 0; n < 4; ++n) {
-                const int ln = ie - 1 + ((n == 1 || n == 2) ? 1 : 0);
-                const int mn = je - 1 + ((n >= 2) ? 1 : 0);
-                if (ln >= 0 && ln < TX && mn >= 0 && mn < TY) {
-                    const int t = mn * TX + ln;
-                    s_acc[2 * t] = s_acc[2 * t] + fe[2 * n];
-                    s_acc[2 * t + 1] = s_acc[2 * t + 1] + fe[2 * n + 1];
-                }
-            }
-        }
-        __syncthreads();
-    }
-
-    // ---- 5. central-difference update of the owned nodes ---------------
+    __syncthreads();
     if (on_valid) {
+        double fx = 0.0, fy = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int dx = ((c & 1) - (i0 - 1 + on_l)) & 1;
+            const int dy = ((c >> 1) - (j0 - 1 + on_m)) & 1;
+            const int eie = on_l + dx, eje = on_m + dy;  // ring element holding colour c
+            if (s_split[(eje + 1) * EX + eie + 1] == kAbsent) continue;
+            const int ln = (1 - dx) + 2 * (1 - dy);   // (1,0)->1, (0,0)->0, (1,1)->3, (0,1)->2
+            const int n = (ln == 0) ? 0 : (ln == 1) ? 1 : (ln == 3) ? 2 : 3;
+            const int t = eje * TXE + eie;
+            fx = fx + s_fe[(2 * n) * NT + t];
+            fy = fy + s_fe[(2 * n + 1) * NT + t];
+        }
+
+        // ---- 7. central-difference update of the owned node --------------
         const int64_t kabs = base + k_rel;
         const int hidx = (on_m + 2) * HX + (on_l + 2);
-        double ax = (n_fex - s_acc[2 * tid]) * n_minv;
-        double ay = (n_fey - s_acc[2 * tid + 1]) * n_minv;
+        double ax = (n_fex - fx) * n_minv;
+        double ay = (n_fey - fy) * n_minv;
         if (n_mask & 1u) ax = 0.0;
         if (n_mask & 2u) ay = 0.0;
         const double dtv = (kabs == 0) ? 0.5 * p.dt : p.dt;
@@ -661,58 +820,7 @@ __global__ __launch_bounds__(TXE *TYE) void k_step(StepParams p, int k_rel, int 
         uy_n[on_n] = s_uy[hidx] + p.dt * vy;
     }
 
-    // ---- 6. energy release rate and element rule of the candidates ------
-    Cand best;
-    cand_none(best);
-    const int ncand = s_ncand;
-    for (int c = tid; c < ncand; c += NT) {
-        const int t = s_cand[c] >> 2, a = s_cand[c] & 3;
-        const int cie = t % TXE, cje = t / TXE;
-        const int cex = cie + 1, cey = cje + 1;
-        const int64_t ge = (int64_t)(j0 - 1 + cje) * nx + (i0 - 1 + cie);
-        double x[4], y[4], ux[4], uy[4];
-        elem_xy(cex, cey, x, y);
-        elem_u(cex, cey, ux, uy);
-        const int n1 = a, n2 = (a + 1) & 3;
-        const double dux = ux[n2] - ux[n1], duy = uy[n2] - uy[n1];
-        const double x1 = x[n1] + ux[n1], y1 = y[n1] + uy[n1];
-        const double x2 = x[n2] + ux[n2], y2 = y[n2] + uy[n2];
-        const double lx = x2 - x1, ly = y2 - y1;
-        const double Lx = x[n2] - x[n1], Ly = y[n2] - y[n1];
-        const bool H = (lx * lx + ly * ly) > (Lx * Lx + Ly * Ly);
-        if (!H) continue;  // G = 0 on all three paths
-        int cs[4];
-        cs[0] = cje * TXE + cie;
-        cs[1] = NH + cje * (TXE + 1) + cie + 1;
-        cs[2] = (cje + 1) * TXE + cie;
-        cs[3] = NH + cje * (TXE + 1) + cie;
-        const double *gm = p.geom + ge * 36 + a * 9;
-        double G[3];
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const int k = (a + 1 + j) & 3;
-            const double *sg = &s_sig[3 * cs[k]];
-            const double nxv = gm[3 * j], nyv = gm[3 * j + 1];
-            const double spx = fma(sg[2], nyv, sg[0] * nxv);
-            const double spy = fma(sg[1], nyv, sg[2] * nxv);
-            G[j] = 0.5 * fma(duy, spy, dux * spx);
-        }
-        const double gc = p.gc ? p.gc[ge] : p.gc_uniform;
-        int jb = -1;
-        for (int j = 0; j < 3; ++j)
-            if (G[j] > gc && (jb < 0 || G[j] > G[jb])) jb = j;
-        if (jb < 0) continue;
-        bool ok = true;
-        for (int j = 0; j < 3; ++j) {
-            if (j == jb || !(G[j] > gc)) continue;
-            if (!(G[jb] > p.gamma * (G[jb] - G[j]))) ok = false;
-        }
-        if (!ok) continue;
-        cand_merge(best, G[jb], G[jb], (int)ge, a, (a + 1 + jb) & 3);
-    }
-    cand_block_reduce<NT>(best, s_red);
-
-    // ---- 7. publish the workgroup's best candidate -----------------------
+    // ---- 8. publish the workgroup's best candidate -----------------------
     // Read by the next step after the kernel boundary; no fence here (a
     // device-scope release would write back the whole L2 of the XCD).
     if (tid == 0 && best.G >= 0.0) {
@@ -732,10 +840,17 @@ __global__ __launch_bounds__(TXE *TYE) void k_step(StepParams p, int k_rel, int 
 // slot set and advance the step counter.
 constexpr int kCommitThreads = 256;
 
-__global__ __launch_bounds__(kCommitThreads) void k_commit(StepParams p, int n) {
+// One workgroup per specimen.
+template <bool BATCHED>
+__global__ __launch_bounds__(kCommitThreads) void k_commit(StepParams p0, const StepParams *views, int n) {
     __shared__ Cand s_red[kCommitThreads / 64];
+    StepParams p;
+    if constexpr (BATCHED)
+        p = views[blockIdx.x];
+    else
+        p = p0;
     const int set = (n + 2) % 3;
-    const Cand g = reduce_slots<kCommitThreads>(p, set, s_red);
+    const Cand g = reduce_slots<kCommitThreads>(p, set, p.ctl->nslots[set], s_red);
     if (threadIdx.x != 0) return;
     const int64_t base = p.ctl->base;
     if (n > 0 && pick_accepted(p, g)) apply_split(p, g, base + n - 1);
@@ -753,17 +868,31 @@ TileShape tile_shape(int tile) {
     }
 }
 
-hipError_t launch_step(int tile, const StepParams &p, int k_rel, int par0, hipStream_t s) {
-    switch (tile) {
-        case 1: k_step<16, 16><<<p.nwg, 256, 0, s>>>(p, k_rel, par0); break;
-        case 2: k_step<32, 8><<<p.nwg, 256, 0, s>>>(p, k_rel, par0); break;
-        default: k_step<32, 16><<<p.nwg, 512, 0, s>>>(p, k_rel, par0); break;
+hipError_t launch_step(int tile, const Launch &L, int k_rel, int par0, hipStream_t s) {
+    (void)hipGetLastError();  // report only this launch's error below
+    const StepParams &p = L.p0;
+    if (L.batched) {
+        switch (tile) {
+            case 1: k_step<16, 16, true><<<L.nunits, 256, 0, s>>>(p, L.views, L.units, k_rel, par0); break;
+            case 2: k_step<32, 8, true><<<L.nunits, 256, 0, s>>>(p, L.views, L.units, k_rel, par0); break;
+            default: k_step<32, 16, true><<<L.nunits, 512, 0, s>>>(p, L.views, L.units, k_rel, par0); break;
+        }
+    } else {
+        switch (tile) {
+            case 1: k_step<16, 16, false><<<p.nwg, 256, 0, s>>>(p, nullptr, nullptr, k_rel, par0); break;
+            case 2: k_step<32, 8, false><<<p.nwg, 256, 0, s>>>(p, nullptr, nullptr, k_rel, par0); break;
+            default: k_step<32, 16, false><<<p.nwg, 512, 0, s>>>(p, nullptr, nullptr, k_rel, par0); break;
+        }
     }
     return hipGetLastError();
 }
 
-hipError_t launch_commit(const StepParams &p, int n, hipStream_t s) {
-    k_commit<<<1, kCommitThreads, 0, s>>>(p, n);
+hipError_t launch_commit(const Launch &L, int n, hipStream_t s) {
+    (void)hipGetLastError();
+    if (L.batched)
+        k_commit<true><<<L.nspec, kCommitThreads, 0, s>>>(L.p0, L.views, n);
+    else
+        k_commit<false><<<1, kCommitThreads, 0, s>>>(L.p0, nullptr, n);
     return hipGetLastError();
 }
 
@@ -887,6 +1016,38 @@ __global__ __launch_bounds__(kTipBlock) void k_tips_write(int nx, int ny, int64_
 }
 }  // namespace
 
+// Crack-path geometry of a list of elements (36 values each: for tip edge a
+// and path j (exit edge a+1+j): normal x, normal y, length), evaluated with
+// the device function the step uses.
+__global__ void k_path_geometry(StepParams p, int n, const int32_t *elem, double *out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int64_t e = elem[t];
+    const int64_t i = e % p.nx, j = e / p.nx;
+    const int64_t n0 = j * (p.nx + 1) + i;
+    const int64_t nd[4] = {n0, n0 + 1, n0 + p.nx + 2, n0 + p.nx + 1};
+    double x[4], y[4];
+    for (int q = 0; q < 4; ++q) {
+        x[q] = p.X[nd[q]];
+        y[q] = p.Y[nd[q]];
+    }
+    for (int a = 0; a < 4; ++a)
+        for (int jj = 0; jj < 3; ++jj) {
+            double cx, cy, L;
+            path_geom(x, y, a, (a + 1 + jj) & 3, cx, cy, L);
+            double *o = out + (int64_t)t * 36 + a * 9 + 3 * jj;
+            o[0] = cx;
+            o[1] = cy;
+            o[2] = L;
+        }
+}
+
+hipError_t launch_path_geometry(const StepParams &p, int n, const int32_t *elem, double *out, hipStream_t s) {
+    (void)hipGetLastError();
+    if (n > 0) k_path_geometry<<<(n + 255) / 256, 256, 0, s>>>(p, n, elem, out);
+    return hipGetLastError();
+}
+
 int tips_nblocks(int64_t n_edges) { return (int)((n_edges + kTipBlock - 1) / kTipBlock); }
 
 hipError_t launch_tips(int32_t nx, int32_t ny, const double *X, const double *Y, const uint8_t *split,
@@ -895,6 +1056,7 @@ hipError_t launch_tips(int32_t nx, int32_t ny, const double *X, const double *Y,
     const int64_t ns = 2 * (int64_t)nx * ny + nx + ny;
     const int nb = tips_nblocks(ns);
     *nblocks_out = nb;
+    (void)hipGetLastError();
     k_tips_count<<<nb, kTipBlock, 0, s>>>(nx, ny, ns, split, block_counts);
     k_tips_scan<<<1, 1024, 0, s>>>(block_counts, nb, count_out);
     if (edge_out) k_tips_write<<<nb, kTipBlock, 0, s>>>(nx, ny, ns, X, Y, split, block_counts, edge_out, xy_out);

@@ -34,7 +34,8 @@ EXPORTS = [
     "mct_create", "mct_destroy", "mct_last_error", "mct_set_mesh_grid", "mct_set_material",
     "mct_set_traction", "mct_set_velocity_bc", "mct_set_notch", "mct_set_time", "mct_finalize",
     "mct_step", "mct_sync", "mct_get_info", "mct_get_crack_set", "mct_get_tips", "mct_get_field",
-    "mct_get_split_codes", "mct_checkpoint", "mct_restore", "mct_set_launch",
+    "mct_get_split_codes", "mct_checkpoint", "mct_restore", "mct_set_launch", "mct_get_path_geometry",
+    "mct_batch_create", "mct_batch_select", "mct_set_order", "mct_autotune", "mct_get_launch",
 ]
 
 _lib = None
@@ -73,6 +74,12 @@ def load() -> C.CDLL:
     L.mct_checkpoint.argtypes = [P, P, C.c_int64, C.POINTER(C.c_int64)]
     L.mct_restore.argtypes = [P, P, C.c_int64]
     L.mct_set_launch.argtypes = [P, C.c_int, C.c_int]
+    L.mct_get_path_geometry.argtypes = [P, C.c_int64, ip, dp]
+    L.mct_batch_create.argtypes = [C.POINTER(P), C.c_int64, C.c_int, P]
+    L.mct_batch_select.argtypes = [P, C.c_int64]
+    L.mct_set_order.argtypes = [P, C.c_int]
+    L.mct_autotune.argtypes = [P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double)]
+    L.mct_get_launch.argtypes = [P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int64)]
     _lib = L
     return L
 
@@ -96,14 +103,19 @@ class Model:
     ``torch.cuda.current_stream().cuda_stream``) or None for a library
     stream."""
 
-    def __init__(self, precision: int = 64, stream: int | None = None):
+    def __init__(self, precision: int = 64, stream: int | None = None, n_specimens: int | None = None):
         L = load()
         h = C.c_void_p()
-        rc = L.mct_create(C.byref(h), int(precision), C.c_void_p(stream) if stream else None)
+        st = C.c_void_p(stream) if stream else None
+        if n_specimens is None:
+            rc = L.mct_create(C.byref(h), int(precision), st)
+        else:
+            rc = L.mct_batch_create(C.byref(h), int(n_specimens), int(precision), st)
         if rc != MCT_OK:
-            raise MctError("mct_create failed: %d" % rc)
+            raise MctError("create failed: %d" % rc)
         self._h = h
         self._L = L
+        self._keep = []
 
     def _check(self, rc, what=""):
         if rc != MCT_OK:
@@ -155,6 +167,23 @@ class Model:
     def set_launch(self, tile=0, use_graph=True):
         self._check(self._L.mct_set_launch(self._h, int(tile), int(bool(use_graph))), "set_launch")
 
+    def select(self, s):
+        """Select the specimen of a batch that set-up calls and queries act on."""
+        self._check(self._L.mct_batch_select(self._h, int(s)), "batch_select")
+
+    def set_order(self, order=-1):
+        self._check(self._L.mct_set_order(self._h, int(order)), "set_order")
+
+    def autotune(self, trial_steps=20):
+        t, o, us = C.c_int(0), C.c_int(0), C.c_double(0.0)
+        self._check(self._L.mct_autotune(self._h, int(trial_steps), C.byref(t), C.byref(o), C.byref(us)), "autotune")
+        return dict(tile=t.value, order=o.value, us_per_step=us.value)
+
+    def launch(self):
+        t, o, w = C.c_int(0), C.c_int(0), C.c_int64(0)
+        self._check(self._L.mct_get_launch(self._h, C.byref(t), C.byref(o), C.byref(w)), "get_launch")
+        return dict(tile=t.value, order=o.value, workgroups=w.value)
+
     def finalize(self):
         self._check(self._L.mct_finalize(self._h), "finalize")
 
@@ -201,6 +230,14 @@ class Model:
         self._check(self._L.mct_get_field(self._h, int(which), 2 * nn, out), "get_field")
         return out[:nn], out[nn:]
 
+    def path_geometry(self, elems):
+        """Crack-path normals and lengths as the GPU step computes them:
+        array [n, 4 (tip edge a), 3 (path j), 3 (nx, ny, length)]."""
+        elems = _i32(elems)
+        out = np.zeros(36 * len(elems))
+        self._check(self._L.mct_get_path_geometry(self._h, len(elems), elems, out), "get_path_geometry")
+        return out.reshape(len(elems), 4, 3, 3)
+
     def split_codes(self):
         ne = self.info()["n_elems"]
         out = np.zeros(ne, np.uint8)
@@ -219,10 +256,7 @@ class Model:
         self._check(self._L.mct_restore(self._h, C.cast(buf, C.c_void_p), len(data)), "restore")
 
 
-def from_config(cfg: dict, stream: int | None = None, tile: int = 0, use_graph: bool = True) -> Model:
-    """Build and finalize a model from a workload dictionary
-    (paper_2509_01827_amd.workloads)."""
-    m = Model(64, stream)
+def _setup(m: Model, cfg: dict):
     m.set_mesh_grid(cfg["nx"], cfg["ny"], cfg["X"], cfg["Y"])
     m.set_material(cfg["E"], cfg["nu"], cfg["rho"], cfg.get("gc_field"), cfg.get("gc_uniform", 0.0),
                    cfg.get("gamma", 1.0))
@@ -232,6 +266,28 @@ def from_config(cfg: dict, stream: int | None = None, tile: int = 0, use_graph: 
     ne_, en_, ex_ = cfg["notch"]
     m.set_notch(ne_, en_, ex_)
     m.set_time(cfg.get("dt", 0.0), cfg.get("cfl", 0.5))
+
+
+def from_config(cfg: dict, stream: int | None = None, tile: int = 0, use_graph: bool = True) -> Model:
+    """Build and finalize a model from a workload dictionary
+    (paper_2509_01827_amd.workloads)."""
+    m = Model(64, stream)
+    _setup(m, cfg)
     m.set_launch(tile, use_graph)
+    m.finalize()
+    return m
+
+
+def batch_from_configs(cfgs, stream: int | None = None, tile: int = 0, order: int = -1,
+                       use_graph: bool = True) -> Model:
+    """Build and finalize a batch of independent specimens, one per workload
+    dictionary."""
+    m = Model(64, stream, n_specimens=len(cfgs))
+    for s, cfg in enumerate(cfgs):
+        m.select(s)
+        _setup(m, cfg)
+    m.select(0)
+    m.set_launch(tile, use_graph)
+    m.set_order(order)
     m.finalize()
     return m

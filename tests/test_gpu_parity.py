@@ -125,6 +125,22 @@ def test_velocity_ramp_and_weibull(gpu, oracle_mod):
     _compare(m, o, label="ramp")
 
 
+def test_device_path_geometry_bitwise(gpu, oracle_mod):
+    """Crack-path normals and lengths evaluated on the GPU (correctly rounded
+    sqrt and division) equal the oracle's host evaluation bit for bit, on a
+    strongly jittered mesh."""
+    c = W.plate(23, 17, 0.023, 0.017, jitter=0.2, seed=W.BASE_SEED + 21)
+    m = gpu.from_config(c)
+    o = oracle_mod.Oracle(c)
+    elems = np.arange(23 * 17, dtype=np.int32)
+    g = m.path_geometry(elems)
+    for e in elems:
+        for a in range(4):
+            for j in range(3):
+                k = (a + 1 + j) % 4
+                assert np.array_equal(g[e, a, j], o.path_normal(e, a, k)), (e, a, k)
+
+
 def test_run_to_run_deterministic(gpu):
     cfg = W.small_cases()["fragment97x45"]
     outs = []
