@@ -89,7 +89,7 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="pick tile/order by measurement first")
-    ap.add_argument("--cpu-steps", type=int, default=100)
+    ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="plate400", choices=sorted(WORKLOADS))
     ap.add_argument("--compare-plain", action="store_true",

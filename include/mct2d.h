@@ -172,7 +172,7 @@ int mct_get_split_codes(mct_ctx *ctx, int64_t cap, uint8_t *out);
 int mct_checkpoint(mct_ctx *ctx, void *host_buf, int64_t cap, int64_t *bytes);
 int mct_restore(mct_ctx *ctx, const void *host_buf, int64_t bytes);
 
-/* Launch tuning: tile shape index (0 = automatic, 1 = 16x16, 2 = 32x8,
+/* Launch tuning: tile shape index (0 = automatic, which is 16x16; 1 = 16x16, 2 = 32x8,
  * 3 = 32x16 elements per workgroup) and whether mct_step replays captured
  * HIP graphs (1, default) or launches kernel by kernel (0).  Results do not
  * depend on either (fixed summation orders). */

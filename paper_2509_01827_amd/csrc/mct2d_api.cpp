@@ -79,7 +79,7 @@ struct mct_ctx {
 
     // device arrays, specimens concatenated
     double *dX = nullptr, *dY = nullptr, *dux[2] = {nullptr, nullptr}, *duy[2] = {nullptr, nullptr};
-    double *dvx = nullptr, *dvy = nullptr, *dminv = nullptr, *dgc = nullptr;
+    double *dvx = nullptr, *dvy = nullptr, *dminv = nullptr, *dgc = nullptr, *darea = nullptr;
     double *dfext = nullptr, *dv0 = nullptr;
     uint8_t *dvmask = nullptr, *dsplit = nullptr;
     Control *dctl = nullptr;
@@ -140,6 +140,7 @@ void release_device(mct_ctx *c) {
     dfree(c->dvy);
     dfree(c->dminv);
     dfree(c->dgc);
+    dfree(c->darea);
     dfree(c->dfext);
     dfree(c->dv0);
     dfree(c->dvmask);
@@ -198,22 +199,11 @@ void tiles_of(const Spec &s, int tile, int &ntx, int &nty) {
     nty = (s.ny + 1 + t.tye - 2) / (t.tye - 1);
 }
 
-int64_t total_tiles(const mct_ctx *c, int tile) {
-    int64_t n = 0;
-    for (const Spec &s : c->specs) {
-        int a, b;
-        tiles_of(s, tile, a, b);
-        n += (int64_t)a * b;
-    }
-    return n;
-}
-
 int pick_tile(const mct_ctx *c) {
     if (c->tile_req >= 1 && c->tile_req <= mct::kNumTiles) return c->tile_req;
-    // largest tile that still gives every CU several workgroups
-    for (int t : {3, 2})
-        if (total_tiles(c, t) >= 4 * 256) return t;
-    return 2;
+    // 16 x 16: four workgroups fit on a CU (LDS and registers), and its
+    // halo overhead is the smallest of the 256-thread shapes
+    return 1;
 }
 
 // Work-unit order of a batch: which (specimen, tile) each workgroup takes.
@@ -531,7 +521,7 @@ int mct_finalize(mct_ctx *c) {
         np += s.np;
         any_gc = any_gc || !s.gc.empty();
     }
-    std::vector<double> X(nn), Y(nn), minv(nn), fext(2 * np, 0.0), v0(2 * np, 0.0), gc;
+    std::vector<double> X(nn), Y(nn), minv(nn), fext(2 * np, 0.0), v0(2 * np, 0.0), gc, area_all(ne);
     std::vector<uint8_t> vmask(np, 0), split(ne, 0);
     if (any_gc) gc.resize(ne);
 
@@ -541,7 +531,7 @@ int mct_finalize(mct_ctx *c) {
         std::copy(s.X.begin(), s.X.end(), X.begin() + s.node_off);
         std::copy(s.Y.begin(), s.Y.end(), Y.begin() + s.node_off);
         // lumped mass: rho A_e / 4 from each element, element-id order per node
-        std::vector<double> area(s.ne);
+        double *area = area_all.data() + s.elem_off;
         for (int64_t e = 0; e < s.ne; ++e) area[e] = elem_area(s, e);
         for (int j = 0; j <= ny; ++j)
             for (int i = 0; i <= nx; ++i) {
@@ -606,6 +596,7 @@ int mct_finalize(mct_ctx *c) {
     if ((rc = upload(c, c->dv0, v0))) return rc;
     if ((rc = upload(c, c->dvmask, vmask))) return rc;
     if ((rc = upload(c, c->dsplit, split))) return rc;
+    if ((rc = upload(c, c->darea, area_all))) return rc;
     if (any_gc && (rc = upload(c, c->dgc, gc))) return rc;
     for (int i = 0; i < 2; ++i) {
         HIP_TRY(c, hipMalloc((void **)&c->dux[i], sizeof(double) * nn));
@@ -642,6 +633,7 @@ int mct_finalize(mct_ctx *c) {
         p.vy = c->dvy + s.node_off;
         p.minv = c->dminv + s.node_off;
         p.split = c->dsplit + s.elem_off;
+        p.area = c->darea + s.elem_off;
         p.gc = s.gc.empty() ? nullptr : c->dgc + s.elem_off;
         p.gc_uniform = s.gc_uniform;
         p.fext_p = c->dfext + 2 * s.perim_off;

@@ -52,6 +52,7 @@ struct StepParams {
     double *vx, *vy;
     const double *minv;
     uint8_t *split;
+    const double *area;  // per element (reference configuration)
     const double *gc;   // per element, or nullptr for gc_uniform
     double gc_uniform;
     const double *fext_p;     // 2 per perimeter node

@@ -130,28 +130,31 @@ __device__ __forceinline__ void hooke(const StepParams &p, const double eps[3], 
     sig[2] = p.D33 * eps[2];
 }
 
-__device__ __forceinline__ double quad_area(const double x[4], const double y[4]) {
-    return 0.5 * ((x[2] - x[0]) * (y[3] - y[1]) - (x[3] - x[1]) * (y[2] - y[0]));
-}
-
 // Unit normal and length of the crack path from the midpoint of local edge
-// a to the midpoint of local edge k, oriented toward node n_{a+1}
+// a (end nodes (xa0, ya0), (xa1, ya1) = n_a, n_{a+1}) to the midpoint of
+// local edge k (end nodes n_k, n_{k+1}), oriented toward node n_{a+1}
 // (reference coordinates).  Uses correctly rounded sqrt and division only.
-__device__ __forceinline__ void path_geom(const double x[4], const double y[4], int a, int k, double &nxo,
-                                          double &nyo, double &len) {
-    const int a1 = (a + 1) & 3, k1 = (k + 1) & 3;
-    const double g0x = 0.5 * (x[a] + x[a1]), g0y = 0.5 * (y[a] + y[a1]);
-    const double gkx = 0.5 * (x[k] + x[k1]), gky = 0.5 * (y[k] + y[k1]);
+__device__ __forceinline__ void path_geom_pts(double xa0, double ya0, double xa1, double ya1, double xk0,
+                                              double yk0, double xk1, double yk1, double &nxo, double &nyo,
+                                              double &len) {
+    const double g0x = 0.5 * (xa0 + xa1), g0y = 0.5 * (ya0 + ya1);
+    const double gkx = 0.5 * (xk0 + xk1), gky = 0.5 * (yk0 + yk1);
     const double dx = gkx - g0x, dy = gky - g0y;
     const double L = sqrt(dx * dx + dy * dy);
     double cx = dy / L, cy = -dx / L;
-    if (cx * (x[a1] - g0x) + cy * (y[a1] - g0y) < 0.0) {
+    if (cx * (xa1 - g0x) + cy * (ya1 - g0y) < 0.0) {
         cx = -cx;
         cy = -cy;
     }
     nxo = cx;
     nyo = cy;
     len = L;
+}
+
+__device__ __forceinline__ void path_geom(const double x[4], const double y[4], int a, int k, double &nxo,
+                                          double &nyo, double &len) {
+    const int a1 = (a + 1) & 3, k1 = (k + 1) & 3;
+    path_geom_pts(x[a], y[a], x[a1], y[a1], x[k], y[k], x[k1], y[k1], nxo, nyo, len);
 }
 
 // Best-candidate order: larger G, then smaller element id, then smaller a.
@@ -298,7 +301,7 @@ __device__ __forceinline__ void apply_split(const StepParams &p, const Cand &g, 
 // sizes, constants and pre-offset pointers) from `views`.  Otherwise the one
 // view `p0` is passed by value and workgroups map to tiles XCD-banded.
 template <int TXE, int TYE, bool BATCHED>
-__global__ __launch_bounds__(TXE *TYE) void k_step(StepParams p0, const StepParams *views, const int2 *units,
+__global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepParams *views, const int2 *units,
                                                    int k_rel, int par0) {
     constexpr int NT = TXE * TYE;
     constexpr int TX = TXE - 1, TY = TYE - 1;  // owned nodes
@@ -309,23 +312,20 @@ __global__ __launch_bounds__(TXE *TYE) void k_step(StepParams p0, const StepPara
     static_assert(NT % 64 == 0, "whole wavefronts");
     static_assert(TX * TY <= NT, "one thread per owned node");
 
-    static_assert(2 * (NH + NV) * 3 >= 8 * NT, "element forces fit over the strain slots");
+    constexpr int NS = NH + NV;  // component stride of the per-edge array
+    constexpr int NQ = (3 * NS > 8 * NT) ? 3 * NS : 8 * NT;
     __shared__ double s_ux[HX * HY], s_uy[HX * HY], s_X[HX * HY], s_Y[HX * HY];
-    // per edge: w_lo (B u)_lo of the lower-id element (or (B u)_lo alone when
-    // the other side is not intact), (B u)_hi and w_hi of the higher-id one;
-    // after the force phase the same memory holds the element forces
-    __shared__ double s_q[2 * (NH + NV) * 3];
-    __shared__ double s_w1[NH + NV];
+    // per edge and component (stride NS): first the strain part of the
+    // lower-id element, then the smoothed stress; after the force phase the
+    // same memory holds the element forces [8][NT]
+    __shared__ double s_e[NQ];
     __shared__ double s_area[EX * EY];
-    constexpr int NS = NH + NV;  // component stride of the per-edge arrays
-    double *const s_qlo = s_q;             // [3][NS]
-    double *const s_qhi = s_q + NS * 3;    // [3][NS]
-    double *const s_fe = s_q;              // [8][NT] after the force phase
+    double *const s_fe = s_e;
     __shared__ uint8_t s_split[EX * EY];
     __shared__ uint16_t s_cand[4 * TX * TY];
     __shared__ uint16_t s_splitl[NT];
-    __shared__ int s_ncand, s_nsplit;
-    __shared__ int s_wbase[NT / 64], s_wbase2[NT / 64];
+    __shared__ int s_ncand, s_ncorner, s_nthru;
+    __shared__ int s_wbase[NT / 64], s_wbase2[NT / 64], s_wbase3[NT / 64];
     __shared__ Cand s_red[NT / 64];
 
     const int tid = threadIdx.x;
@@ -379,18 +379,9 @@ __global__ __launch_bounds__(TXE *TYE) void k_step(StepParams p0, const StepPara
         rs[r] = kAbsent;
         rarea[r] = 0.0;
         if (idx < NE2 && gi >= 0 && gi < nx && gj >= 0 && gj < ny) {
-            rs[r] = p.split[(int64_t)gj * nx + gi];
-            const int64_t n0 = (int64_t)gj * (nx + 1) + gi;
-            double x[4], y[4];
-            x[0] = p.X[n0];
-            x[1] = p.X[n0 + 1];
-            x[2] = p.X[n0 + nx + 2];
-            x[3] = p.X[n0 + nx + 1];
-            y[0] = p.Y[n0];
-            y[1] = p.Y[n0 + 1];
-            y[2] = p.Y[n0 + nx + 2];
-            y[3] = p.Y[n0 + nx + 1];
-            rarea[r] = quad_area(x, y);
+            const int64_t e = (int64_t)gj * nx + gi;
+            rs[r] = p.split[e];
+            rarea[r] = p.area[e];
         }
     }
     // owned node of this thread
@@ -398,21 +389,6 @@ __global__ __launch_bounds__(TXE *TYE) void k_step(StepParams p0, const StepPara
     const int on_i = i0 + on_l, on_j = j0 + on_m;
     const bool on_valid = tid < TX * TY && on_i <= nx && on_j <= ny;
     const int64_t on_n = (int64_t)on_j * (nx + 1) + on_i;
-    double n_minv = 0.0, n_vx = 0.0, n_vy = 0.0, n_fex = 0.0, n_fey = 0.0, n_v0x = 0.0, n_v0y = 0.0;
-    unsigned n_mask = 0;
-    if (on_valid) {
-        n_minv = p.minv[on_n];
-        n_vx = p.vx[on_n];
-        n_vy = p.vy[on_n];
-        const int pidx = perimeter_index(on_i, on_j, nx, ny);
-        if (pidx >= 0) {
-            n_fex = p.fext_p[2 * pidx];
-            n_fey = p.fext_p[2 * pidx + 1];
-            n_mask = p.vmask_p[pidx];
-            n_v0x = p.v0_p[2 * pidx];
-            n_v0y = p.v0_p[2 * pidx + 1];
-        }
-    }
 #pragma unroll
     for (int r = 0; r < RH; ++r) {
         const int idx = tid + r * NT;
@@ -433,7 +409,8 @@ __global__ __launch_bounds__(TXE *TYE) void k_step(StepParams p0, const StepPara
     }
     if (tid == 0) {
         s_ncand = 0;
-        s_nsplit = 0;
+        s_ncorner = 0;
+        s_nthru = 0;
     }
 
     // ---- 2. the pick of the previous step -------------------------------
@@ -472,16 +449,28 @@ __global__ __launch_bounds__(TXE *TYE) void k_step(StepParams p0, const StepPara
         uy[3] = s_uy[b + HX];
     };
 
-    // ---- 3. element gradients and weighted strain contributions ----------
+    // staged-node offset of local node n of an element, relative to its node 0
+    auto corner = [](int n) { return n == 0 ? 0 : n == 1 ? 1 : n == 2 ? HX + 1 : HX; };
+    // edge slot of local edge k of ring element (ie, je)
+    auto edge_slot = [](int ie, int je, int k) {
+        return k == 0 ? je * TXE + ie
+             : k == 1 ? NH + je * (TXE + 1) + ie + 1
+             : k == 2 ? (je + 1) * TXE + ie
+                      : NH + je * (TXE + 1) + ie;
+    };
+
+    // ---- 3. element gradients and smoothed edge stresses -------------------
     // Element (ie, je) of the TXE x TYE ring around the owned nodes keeps its
     // gradients at the four edge midpoints in registers for the force phase.
-    // For each of its edges it publishes its part of the smoothed strain
-    // eps_s = w_hi (B u)_hi + w_lo (B u)_lo (lower element id first,
-    // w_j = A_j / (A_lo + A_hi) over intact neighbours, w = 1 with one):
-    // as the lower-id element (local edges 1, 2) w_lo (B u)_lo, or (B u)_lo
-    // alone when the neighbour is not intact; as the higher-id element
-    // (local edges 0, 3) (B u)_hi and w_hi.  Elements one further out publish
-    // only the edge they share with the ring.
+    // Smoothed strain of an edge: eps_s = w_hi (B u)_hi + w_lo (B u)_lo over
+    // its intact neighbours (lower element id first, w_j = A_j / (A_lo +
+    // A_hi); w = 1 with one intact neighbour).  Stage A: the lower-id element
+    // (local edges 1, 2) stores w_lo (B u)_lo, or (B u)_lo alone when the
+    // other side is not intact; the higher-id element (edges 0, 3) keeps
+    // (B u)_hi in registers.  Stage B: the higher-id element, when intact,
+    // combines the two and stores the plane-stress sigma over the part;
+    // otherwise the lower-id element turns its part into sigma.  Elements
+    // one further out take part through the edge they share with the ring.
     const int ie = tid % TXE, je = tid / TXE;
     const int ex = ie + 1, ey = je + 1;
     const int e2 = ey * EX + ex;
@@ -492,89 +481,130 @@ __global__ __launch_bounds__(TXE *TYE) void k_step(StepParams p0, const StepPara
     sidx[3] = NH + je * (TXE + 1) + ie;
     const uint8_t code = s_split[e2];
     auto nbr = [&](int e, int k) { return (k == 0) ? e - EX : (k == 1) ? e + 1 : (k == 2) ? e + EX : e - 1; };
-    // publish the strain part of element e (area A, strain q) at its edge k
-    auto publish = [&](int e, double A, int k, int sid, const double q[3]) {
+    // stage A, lower-id element e (area A) at its edge k = 1 or 2
+    auto lo_part = [&](int e, double A, int k, int sid, const double q[3]) {
         const int nb = nbr(e, k);
-        const bool other = s_split[nb] == 0;
-        if (k == 1 || k == 2) {  // e is the lower-id element of the edge
-            if (other) {
-                const double w0 = A / (A + s_area[nb]);
-                s_qlo[0 * NS + sid] = w0 * q[0];
-                s_qlo[1 * NS + sid] = w0 * q[1];
-                s_qlo[2 * NS + sid] = w0 * q[2];
-            } else {
-                s_qlo[0 * NS + sid] = q[0];
-                s_qlo[1 * NS + sid] = q[1];
-                s_qlo[2 * NS + sid] = q[2];
-            }
+        if (s_split[nb] == 0) {
+            const double w0 = A / (A + s_area[nb]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) s_e[c * NS + sid] = w0 * q[c];
         } else {
-            s_qhi[0 * NS + sid] = q[0];
-            s_qhi[1 * NS + sid] = q[1];
-            s_qhi[2 * NS + sid] = q[2];
-            if (other) s_w1[sid] = A / (s_area[nb] + A);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) s_e[c * NS + sid] = q[c];
+        }
+    };
+    // stage B, intact higher-id element e (area A) at its edge k = 0 or 3
+    auto hi_sigma = [&](int e, double A, int k, int sid, const double q[3]) {
+        const int nb = nbr(e, k);
+        double eps[3], sg[3];
+        if (s_split[nb] == 0) {
+            const double w1 = A / (s_area[nb] + A);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) eps[c] = fma(w1, q[c], s_e[c * NS + sid]);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) eps[c] = q[c];
+        }
+        hooke(p, eps, sg);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) s_e[c * NS + sid] = sg[c];
+    };
+    // stage B, lower-id element e at its edge k = 1 or 2 when the other side is not intact
+    auto lo_sigma = [&](int e, int k, int sid) {
+        if (s_split[nbr(e, k)] != 0) {
+            double eps[3], sg[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) eps[c] = s_e[c * NS + sid];
+            hooke(p, eps, sg);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) s_e[c * NS + sid] = sg[c];
         }
     };
     double gx[4][4], gy[4][4];
+    double qh0[3], qh3[3];
     const double my_area = s_area[e2];
     if (code == 0) {
         double x[4], y[4];
         elem_xy(ex, ey, x, y);
-        {
-            double ux[4], uy[4];
-            elem_u(ex, ey, ux, uy);
+        double ux[4], uy[4];
+        elem_u(ex, ey, ux, uy);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                q4_grad(x, y, k, gx[k], gy[k]);
-                double q[3];
-                strain<4>(gx[k], gy[k], ux, uy, q);
-                publish(e2, my_area, k, sidx[k], q);
+        for (int k = 0; k < 4; ++k) {
+            q4_grad(x, y, k, gx[k], gy[k]);
+            double q[3];
+            strain<4>(gx[k], gy[k], ux, uy, q);
+            if (k == 0) {
+                qh0[0] = q[0]; qh0[1] = q[1]; qh0[2] = q[2];
+            } else if (k == 3) {
+                qh3[0] = q[0]; qh3[1] = q[1]; qh3[2] = q[2];
+            } else {
+                lo_part(e2, my_area, k, sidx[k], q);
             }
         }
     }
     // Elements just outside the ring: wavefront g (g = 0..3) takes the row
     // below, the row above, the column left, the column right, so every
-    // wavefront evaluates one edge type.
-    {
-        static_assert(NT >= 256 && TXE <= 64 && TYE <= 64, "four wavefronts for the outer ring");
-        const int g = tid >> 6, r = tid & 63;
-        const int cnt = (g < 2) ? TXE : TYE;
-        if (g < 4 && r < cnt) {
-            int rex, rey, rk, sid;
-            if (g == 0) {  // below the ring: its top edge
-                rex = r + 1; rey = 0; rk = 2; sid = r;
-            } else if (g == 1) {  // above: bottom edge
-                rex = r + 1; rey = TYE + 1; rk = 0; sid = TYE * TXE + r;
-            } else if (g == 2) {  // left: right edge
-                rex = 0; rey = r + 1; rk = 1; sid = NH + r * (TXE + 1);
-            } else {  // right: left edge
-                rex = TXE + 1; rey = r + 1; rk = 3; sid = NH + r * (TXE + 1) + TXE;
-            }
-            const int re = rey * EX + rex;
-            if (s_split[re] == 0) {
-                double x[4], y[4], ux[4], uy[4], dx[4], dy[4], q[3];
-                elem_xy(rex, rey, x, y);
-                elem_u(rex, rey, ux, uy);
-                q4_grad_rt(x, y, rk, dx, dy);
-                strain<4>(dx, dy, ux, uy, q);
-                publish(re, s_area[re], rk, sid, q);
-            }
+    // wavefront evaluates one edge type.  Below and left are the lower-id
+    // side of the shared edge, above and right the higher-id side.
+    static_assert(NT >= 256 && TXE <= 64 && TYE <= 64, "four wavefronts for the outer ring");
+    const int og = tid >> 6, orr = tid & 63;
+    int ore = 0, ork = 0, osid = 0;
+    bool oin = false;
+    double oq[3] = {0.0, 0.0, 0.0};
+    if (og < 4 && orr < ((og < 2) ? TXE : TYE)) {
+        int rex, rey;
+        if (og == 0) {  // below the ring: its top edge
+            rex = orr + 1; rey = 0; ork = 2; osid = orr;
+        } else if (og == 1) {  // above: bottom edge
+            rex = orr + 1; rey = TYE + 1; ork = 0; osid = TYE * TXE + orr;
+        } else if (og == 2) {  // left: right edge
+            rex = 0; rey = orr + 1; ork = 1; osid = NH + orr * (TXE + 1);
+        } else {  // right: left edge
+            rex = TXE + 1; rey = orr + 1; ork = 3; osid = NH + orr * (TXE + 1) + TXE;
+        }
+        ore = rey * EX + rex;
+        if (s_split[ore] == 0) {
+            oin = true;
+            double x[4], y[4], ux[4], uy[4], dx[4], dy[4];
+            elem_xy(rex, rey, x, y);
+            elem_u(rex, rey, ux, uy);
+            q4_grad_rt(x, y, ork, dx, dy);
+            strain<4>(dx, dy, ux, uy, oq);
+            if (og == 0 || og == 2) lo_part(ore, s_area[ore], ork, osid, oq);
         }
     }
     __syncthreads();
+    if (code == 0) {
+        hi_sigma(e2, my_area, 0, sidx[0], qh0);
+        hi_sigma(e2, my_area, 3, sidx[3], qh3);
+        lo_sigma(e2, 1, sidx[1]);
+        lo_sigma(e2, 2, sidx[2]);
+    }
+    if (oin && (og == 1 || og == 3)) hi_sigma(ore, s_area[ore], ork, osid, oq);
+    __syncthreads();
 
-    // Smoothed stress at local edge k (edge slot sid) of the intact element e.
-    auto edge_sigma = [&](int e, int sid, int k, double sg[3]) {
-        double eps[3];
-        if (s_split[nbr(e, k)] == 0) {
-            const double w1 = s_w1[sid];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) eps[c] = fma(w1, s_qhi[c * NS + sid], s_qlo[c * NS + sid]);
-        } else {
-            const double *q = (k == 1 || k == 2) ? s_qlo : s_qhi;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) eps[c] = q[c * NS + sid];
+    // owned-node data for the update, loaded here so that the registers are
+    // free during the gradient phase and the latency hides behind the forces
+    double n_minv = 0.0, n_vx = 0.0, n_vy = 0.0, n_fex = 0.0, n_fey = 0.0, n_v0x = 0.0, n_v0y = 0.0;
+    unsigned n_mask = 0;
+    if (on_valid) {
+        n_minv = p.minv[on_n];
+        n_vx = p.vx[on_n];
+        n_vy = p.vy[on_n];
+        const int pidx = perimeter_index(on_i, on_j, nx, ny);
+        if (pidx >= 0) {
+            n_fex = p.fext_p[2 * pidx];
+            n_fey = p.fext_p[2 * pidx + 1];
+            n_mask = p.vmask_p[pidx];
+            n_v0x = p.v0_p[2 * pidx];
+            n_v0y = p.v0_p[2 * pidx + 1];
         }
-        hooke(p, eps, sg);
+    }
+
+    // smoothed stress at edge slot sid
+    auto edge_sigma = [&](int sid, double sg[3]) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sg[c] = s_e[c * NS + sid];
     };
 
     // ---- 4. element forces, one thread per element of the tile ring ----
@@ -586,7 +616,7 @@ __global__ __launch_bounds__(TXE *TYE) void k_step(StepParams p0, const StepPara
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             double sg[3];
-            edge_sigma(e2, sidx[k], k, sg);
+            edge_sigma(sidx[k], sg);
             const double s0 = sg[0], s1 = sg[1], s2 = sg[2];
 #pragma unroll
             for (int n = 0; n < 4; ++n) {
@@ -618,7 +648,13 @@ __global__ __launch_bounds__(TXE *TYE) void k_step(StepParams p0, const StepPara
         for (int k = 0; k < 4; ++k)
             if (s_split[nbr(e2, k)] != 0) fmask |= 1u << k;
     }
+    // split elements of the ring, listed by kind: a path between adjacent
+    // edges leaves a 3-node piece (constant-strain triangle) and a 1-node
+    // piece; a path between opposite edges leaves two 2-node pieces (bars).
+    // Corner splits fill s_splitl from the front, through splits from the back.
     const bool is_split = (code & kSplitFlag) != 0;
+    const bool is_thru = is_split && ((((code & 3) - ((code >> 2) & 3)) & 3) == 2);
+    const bool is_corner = is_split && !is_thru;
     {
         const int lane = tid & 63, wave = tid >> 6;
         const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -629,11 +665,13 @@ __global__ __launch_bounds__(TXE *TYE) void k_step(StepParams p0, const StepPara
             bal[k] = __ballot((fmask >> k) & 1u);
             wtotal += __popcll(bal[k]);
         }
-        const uint64_t bsp = __ballot(is_split);
+        const uint64_t bco = __ballot(is_corner), bth = __ballot(is_thru);
         if (lane == 0 && wtotal) s_wbase[wave] = atomicAdd(&s_ncand, wtotal);
-        if (lane == 0 && bsp) s_wbase2[wave] = atomicAdd(&s_nsplit, __popcll(bsp));
+        if (lane == 0 && bco) s_wbase2[wave] = atomicAdd(&s_ncorner, __popcll(bco));
+        if (lane == 0 && bth) s_wbase3[wave] = atomicAdd(&s_nthru, __popcll(bth));
         __syncthreads();
-        if (is_split) s_splitl[s_wbase2[wave] + __popcll(bsp & lt)] = (uint16_t)tid;
+        if (is_corner) s_splitl[s_wbase2[wave] + __popcll(bco & lt)] = (uint16_t)tid;
+        if (is_thru) s_splitl[NT - 1 - (s_wbase3[wave] + __popcll(bth & lt))] = (uint16_t)tid;
         if (fmask) {
             int off = s_wbase[wave];
 #pragma unroll
@@ -647,53 +685,67 @@ __global__ __launch_bounds__(TXE *TYE) void k_step(StepParams p0, const StepPara
     if (ncand > 0) __syncthreads();  // uniform: the list is complete
 
     // ---- 5. energy release rate and element rule of the candidates ------
+    // Four lanes per candidate: lane j < 3 evaluates G of the path to local
+    // edge a+1+j, lane 0 of the quad applies the element rule to the three
+    // values.  Node data are read from LDS at computed offsets, so no array
+    // is indexed by a run-time value.
     Cand best;
     cand_none(best);
-    for (int c = tid; c < ncand; c += NT) {
-        const int t = s_cand[c] >> 2, a = s_cand[c] & 3;
-        const int cie = t % TXE, cje = t / TXE;
-        const int cex = cie + 1, cey = cje + 1;
-        const int ce2 = cey * EX + cex;
-        const int64_t ge = (int64_t)(j0 - 1 + cje) * nx + (i0 - 1 + cie);
-        double x[4], y[4], ux[4], uy[4];
-        elem_xy(cex, cey, x, y);
-        elem_u(cex, cey, ux, uy);
-        const int n1 = a, n2 = (a + 1) & 3;
-        const double dux = ux[n2] - ux[n1], duy = uy[n2] - uy[n1];
-        const double x1 = x[n1] + ux[n1], y1 = y[n1] + uy[n1];
-        const double x2 = x[n2] + ux[n2], y2 = y[n2] + uy[n2];
-        const double lx = x2 - x1, ly = y2 - y1;
-        const double Lx = x[n2] - x[n1], Ly = y[n2] - y[n1];
-        const bool H = (lx * lx + ly * ly) > (Lx * Lx + Ly * Ly);
-        if (!H) continue;  // G = 0 on all three paths
-        int cs[4];
-        cs[0] = cje * TXE + cie;
-        cs[1] = NH + cje * (TXE + 1) + cie + 1;
-        cs[2] = (cje + 1) * TXE + cie;
-        cs[3] = NH + cje * (TXE + 1) + cie;
-        double G[3];
+    for (int c0 = 0; c0 < ncand; c0 += NT / 4) {  // same trip count in every lane
+        const int c = c0 + (tid >> 2), j = tid & 3;
+        const bool live = c < ncand;
+        double Gj = 0.0, gc = 0.0;
+        bool H = false;
+        int a = 0;
+        int64_t ge = 0;
+        if (live) {
+            const int t = s_cand[c] >> 2;
+            a = s_cand[c] & 3;
+            const int cie = t % TXE, cje = t / TXE;
+            ge = (int64_t)(j0 - 1 + cje) * nx + (i0 - 1 + cie);
+            gc = p.gc ? p.gc[ge] : p.gc_uniform;
+            const int nb0 = (cje + 1) * HX + (cie + 1);
+            const int o1 = nb0 + corner(a), o2 = nb0 + corner((a + 1) & 3);
+            const double X1 = s_X[o1], Y1 = s_Y[o1], X2 = s_X[o2], Y2 = s_Y[o2];
+            const double ux1 = s_ux[o1], uy1 = s_uy[o1], ux2 = s_ux[o2], uy2 = s_uy[o2];
+            const double dux = ux2 - ux1, duy = uy2 - uy1;
+            const double x1 = X1 + ux1, y1 = Y1 + uy1;
+            const double x2 = X2 + ux2, y2 = Y2 + uy2;
+            const double lx = x2 - x1, ly = y2 - y1;
+            const double Lx = X2 - X1, Ly = Y2 - Y1;
+            H = (lx * lx + ly * ly) > (Lx * Lx + Ly * Ly);  // else G = 0 on all three paths
+            if (H && j < 3) {
+                const int k = (a + 1 + j) & 3;
+                double sg[3], nxv, nyv, len;
+                edge_sigma(edge_slot(cie, cje, k), sg);
+                const int q0 = nb0 + corner(k), q1 = nb0 + corner((k + 1) & 3);
+                path_geom_pts(X1, Y1, X2, Y2, s_X[q0], s_Y[q0], s_X[q1], s_Y[q1], nxv, nyv, len);
+                const double spx = fma(sg[2], nyv, sg[0] * nxv);
+                const double spy = fma(sg[1], nyv, sg[2] * nxv);
+                Gj = 0.5 * fma(duy, spy, dux * spx);
+            }
+        }
+        const int qb = tid & 60;  // lane of j = 0 in this quad
+        const double G1 = __shfl(Gj, qb + 1, 64);
+        const double G2 = __shfl(Gj, qb + 2, 64);
+        if (live && H && j == 0) {
+            const double Gv[3] = {Gj, G1, G2};
+            int jb = -1;
+            double gb = 0.0;
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const int k = (a + 1 + j) & 3;
-            double sg[3], nxv, nyv, len;
-            edge_sigma(ce2, cs[k], k, sg);
-            path_geom(x, y, a, k, nxv, nyv, len);
-            const double spx = fma(sg[2], nyv, sg[0] * nxv);
-            const double spy = fma(sg[1], nyv, sg[2] * nxv);
-            G[j] = 0.5 * fma(duy, spy, dux * spx);
+            for (int q = 0; q < 3; ++q)
+                if (Gv[q] > gc && (jb < 0 || Gv[q] > gb)) {
+                    jb = q;
+                    gb = Gv[q];
+                }
+            if (jb >= 0) {
+                bool ok = true;
+#pragma unroll
+                for (int q = 0; q < 3; ++q)
+                    if (q != jb && Gv[q] > gc && !(gb > p.gamma * (gb - Gv[q]))) ok = false;
+                if (ok) cand_merge(best, gb, gb, (int)ge, a, (a + 1 + jb) & 3);
+            }
         }
-        const double gc = p.gc ? p.gc[ge] : p.gc_uniform;
-        int jb = -1;
-        for (int j = 0; j < 3; ++j)
-            if (G[j] > gc && (jb < 0 || G[j] > G[jb])) jb = j;
-        if (jb < 0) continue;
-        bool ok = true;
-        for (int j = 0; j < 3; ++j) {
-            if (j == jb || !(G[j] > gc)) continue;
-            if (!(G[jb] > p.gamma * (G[jb] - G[j]))) ok = false;
-        }
-        if (!ok) continue;
-        cand_merge(best, G[jb], G[jb], (int)ge, a, (a + 1 + jb) & 3);
     }
     if (ncand > 0) cand_block_reduce<NT>(best, s_red);  // uniform branch
     __syncthreads();  // strain slots are no longer read: reuse them for forces
@@ -706,84 +758,71 @@ __global__ __launch_bounds__(TXE *TYE) void k_step(StepParams p0, const StepPara
 #pragma unroll
         for (int c = 0; c < 8; ++c) s_fe[c * NT + tid] = fe[c];
     }
-    // split elements of the tile ring, one per lane (compacted above)
-    const int nsplit_l = s_nsplit;
-    for (int si = tid; si < nsplit_l; si += NT) {
-        const int t = s_splitl[si];
+    // Split elements of the tile ring.  Work items: one constant-strain
+    // triangle per corner split, then one bar per piece of a through split,
+    // so that a wavefront mostly runs one kind.  Each piece spans the crack
+    // segment between the midpoints of the entry and exit edges and carries
+    // its polygon area; the 1-node piece of a corner split has no stiffness.
+    const int ncorner = s_ncorner, nitems = ncorner + 2 * s_nthru;
+    for (int it = tid; it < nitems; it += NT) {
+        const bool cst = it < ncorner;
+        const int t = cst ? s_splitl[it] : s_splitl[NT - 1 - ((it - ncorner) >> 1)];
         const int sx_ = t % TXE + 1, sy_ = t / TXE + 1;
         const uint8_t scode = s_split[sy_ * EX + sx_];
-        double sfe[8];
-#pragma unroll
-        for (int c = 0; c < 8; ++c) sfe[c] = 0.0;
-        // Split element: two pieces bounded by the crack segment between the
-        // midpoints of the entry and exit edges.  3-node piece -> constant-
-        // strain triangle, 2-node piece -> bar along the uncut edge, 1-node
-        // piece -> no stiffness; each carries its polygon area.
-        double x[4], y[4], ux[4], uy[4];
-        elem_xy(sx_, sy_, x, y);
-        elem_u(sx_, sy_, ux, uy);
         const int ea = (scode >> 2) & 3, eb = scode & 3;
-        for (int piece = 0; piece < 2; ++piece) {
-            const int from = piece ? eb : ea, to = piece ? ea : eb;
-            int loc[3];
-            int np = 0;
-            for (int k = (from + 1) & 3;; k = (k + 1) & 3) {
-                loc[np++] = k;
-                if (k == to) break;
-            }
-            double px[5], py[5];
-            int nv = 0;
-            px[nv] = 0.5 * (x[from] + x[(from + 1) & 3]);
-            py[nv++] = 0.5 * (y[from] + y[(from + 1) & 3]);
-            for (int i = 0; i < np; ++i) {
-                px[nv] = x[loc[i]];
-                py[nv++] = y[loc[i]];
-            }
-            px[nv] = 0.5 * (x[to] + x[(to + 1) & 3]);
-            py[nv++] = 0.5 * (y[to] + y[(to + 1) & 3]);
-            double s = 0.0;
-            for (int i = 1; i + 1 < nv; ++i)
-                s += (px[i] - px[0]) * (py[i + 1] - py[0]) - (px[i + 1] - px[0]) * (py[i] - py[0]);
-            const double Ap = 0.5 * s;
-            if (np == 3) {
-                const double x1 = px[1], y1 = py[1], x2 = px[2], y2 = py[2], x3 = px[3], y3 = py[3];
-                const double twoA = (x2 - x1) * (y3 - y1) - (x3 - x1) * (y2 - y1);
-                const double inv = 1.0 / twoA;
-                const double b[3] = {(y2 - y3) * inv, (y3 - y1) * inv, (y1 - y2) * inv};
-                const double cc[3] = {(x3 - x2) * inv, (x1 - x3) * inv, (x2 - x1) * inv};
-                double pu[3], pv[3];
-                for (int i = 0; i < 3; ++i) {
-                    pu[i] = ux[loc[i]];
-                    pv[i] = uy[loc[i]];
-                }
-                double eps[3], sg[3];
-                strain<3>(b, cc, pu, pv, eps);
-                hooke(p, eps, sg);
-                for (int i = 0; i < 3; ++i) {
-                    const double tx = fma(cc[i], sg[2], b[i] * sg[0]);
-                    const double ty = fma(b[i], sg[2], cc[i] * sg[1]);
-                    sfe[2 * loc[i]] = Ap * tx;
-                    sfe[2 * loc[i] + 1] = Ap * ty;
-                }
-            } else if (np == 2) {
-                const int a0 = loc[0], a1 = loc[1];
-                const double dx = x[a1] - x[a0], dy = y[a1] - y[a0];
-                const double L2 = dx * dx + dy * dy;
-                const double dux = ux[a1] - ux[a0], duy = uy[a1] - uy[a0];
-                const double st = (dx * dux + dy * duy) / L2;
-                const double stress = p.E * st;
-                const double coef = Ap * stress / L2;
-                sfe[2 * a1] = coef * dx;
-                sfe[2 * a1 + 1] = coef * dy;
-                sfe[2 * a0] = -(coef * dx);
-                sfe[2 * a0 + 1] = -(coef * dy);
-            } else {
-                sfe[2 * loc[0]] = 0.0;
-                sfe[2 * loc[0] + 1] = 0.0;
-            }
-        }
+        const int nb0 = sy_ * HX + sx_;
+        // piece from edge F (first node F+1) to edge T, counter-clockwise
+        const int F = cst ? ((((eb - ea) & 3) == 3) ? ea : eb) : (((it - ncorner) & 1) ? eb : ea);
+        const int n0 = F, n1 = (F + 1) & 3, n2 = (F + 2) & 3, n3 = (F + 3) & 3;
+        const int o0 = nb0 + corner(n0), o1 = nb0 + corner(n1), o2 = nb0 + corner(n2), o3 = nb0 + corner(n3);
+        const double x0 = s_X[o0], x1 = s_X[o1], x2 = s_X[o2], x3 = s_X[o3];
+        const double y0 = s_Y[o0], y1 = s_Y[o1], y2 = s_Y[o2], y3 = s_Y[o3];
+        const double gx = 0.5 * (x0 + x1), gy = 0.5 * (y0 + y1);  // midpoint of edge F
+        if (cst) {
+            // polygon: mid(F), n1, n2, n3, mid(F+3); shoelace fanned from mid(F)
+            const double hx = 0.5 * (x3 + x0), hy = 0.5 * (y3 + y0);
+            double sa = 0.0;
+            sa += (x1 - gx) * (y2 - gy) - (x2 - gx) * (y1 - gy);
+            sa += (x2 - gx) * (y3 - gy) - (x3 - gx) * (y2 - gy);
+            sa += (x3 - gx) * (hy - gy) - (hx - gx) * (y3 - gy);
+            const double Ap = 0.5 * sa;
+            const double twoA = (x2 - x1) * (y3 - y1) - (x3 - x1) * (y2 - y1);
+            const double inv = 1.0 / twoA;
+            const double bb[3] = {(y2 - y3) * inv, (y3 - y1) * inv, (y1 - y2) * inv};
+            const double cc[3] = {(x3 - x2) * inv, (x1 - x3) * inv, (x2 - x1) * inv};
+            const double pu[3] = {s_ux[o1], s_ux[o2], s_ux[o3]};
+            const double pv[3] = {s_uy[o1], s_uy[o2], s_uy[o3]};
+            double eps[3], sg[3];
+            strain<3>(bb, cc, pu, pv, eps);
+            hooke(p, eps, sg);
+            const int nn[3] = {n1, n2, n3};
 #pragma unroll
-        for (int c = 0; c < 8; ++c) s_fe[c * NT + t] = sfe[c];
+            for (int i = 0; i < 3; ++i) {
+                const double tx = fma(cc[i], sg[2], bb[i] * sg[0]);
+                const double ty = fma(bb[i], sg[2], cc[i] * sg[1]);
+                s_fe[(2 * nn[i]) * NT + t] = Ap * tx;
+                s_fe[(2 * nn[i] + 1) * NT + t] = Ap * ty;
+            }
+            s_fe[(2 * n0) * NT + t] = 0.0;
+            s_fe[(2 * n0 + 1) * NT + t] = 0.0;
+        } else {
+            // polygon: mid(F), n1, n2, mid(F+2); bar along the uncut edge n1-n2
+            const double hx = 0.5 * (x2 + x3), hy = 0.5 * (y2 + y3);
+            double sa = 0.0;
+            sa += (x1 - gx) * (y2 - gy) - (x2 - gx) * (y1 - gy);
+            sa += (x2 - gx) * (hy - gy) - (hx - gx) * (y2 - gy);
+            const double Ap = 0.5 * sa;
+            const double dx = x2 - x1, dy = y2 - y1;
+            const double L2 = dx * dx + dy * dy;
+            const double dux = s_ux[o2] - s_ux[o1], duy = s_uy[o2] - s_uy[o1];
+            const double st = (dx * dux + dy * duy) / L2;
+            const double stress = p.E * st;
+            const double coef = Ap * stress / L2;
+            s_fe[(2 * n2) * NT + t] = coef * dx;
+            s_fe[(2 * n2 + 1) * NT + t] = coef * dy;
+            s_fe[(2 * n1) * NT + t] = -(coef * dx);
+            s_fe[(2 * n1 + 1) * NT + t] = -(coef * dy);
+        }
     }
     __syncthreads();
     if (on_valid) {
