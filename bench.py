@@ -38,12 +38,39 @@ WORKLOADS = {
 
 def bytes_per_step(cfgs) -> int:
     """Algorithmic HBM bytes of one fused step (binary64): per node read u,
-    v, X, Y, 1/m and write u, v (11 doubles); per element its split code."""
+    v, X, Y, 1/m and write u, v (11 doubles); per element its split code and
+    its area (9 bytes)."""
     total = 0
     for c in cfgs:
         nn = (c["nx"] + 1) * (c["ny"] + 1)
-        total += 88 * nn + c["nx"] * c["ny"]
+        total += 88 * nn + 9 * c["nx"] * c["ny"]
     return total
+
+
+# HBM bytes per step launch measured with rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE (KiB per dispatch, averaged over the profiled launches), each
+# scaled by the ratio of true to counted bytes of a 256 MiB device copy
+# (FETCH_SIZE x 1.99979, WRITE_SIZE x 1.0).  They hold for the kernel source
+# they were taken on (hash of the step kernel and its header) and the tile
+# shape; otherwise the traffic is reported as unknown.
+MEASURED_TRAFFIC = {
+    "kernel_sha256": "fb1c46d913a99be112220c7b6da4629b9985a97560fde24c81c0fd5aaadce5b1",
+    "plate400": {"tile": 1, "fetch_kib": 5592.0128, "write_kib": 5044.4077},
+    "batch256": {"tile": 1, "fetch_kib": 423053.46, "write_kib": 471632.16},
+}
+FETCH_SCALE, WRITE_SCALE = 262144.0 / 131086.604, 262144.0 / 262144.0
+
+
+def measured_traffic(workload: str, tile: int):
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("mct2d_step.hip", "mct2d_impl.h"):
+        with open(os.path.join(ROOT, "paper_2509_01827_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    rec = MEASURED_TRAFFIC.get(workload)
+    if rec is None or rec["tile"] != tile or h.hexdigest() != MEASURED_TRAFFIC["kernel_sha256"]:
+        return None
+    return 1024.0 * (rec["fetch_kib"] * FETCH_SCALE + rec["write_kib"] * WRITE_SCALE)
 
 
 def cpu_baseline(cfg, steps: int):
@@ -168,7 +195,8 @@ def main():
         "splits": splits,
         "dissipated_J_per_m": ud,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": bps},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(args.workload, launch["tile"]), "bytes_per_launch": bps},
     }
     m.close()
     if args.compare_plain and len(cfgs) > 1:
