@@ -203,6 +203,85 @@ int mct_autotune(mct_ctx *ctx, int trial_steps, int *tile, int *order, double *u
 /* Launch shape in use: tile index, unit order, workgroups per step. */
 int mct_get_launch(mct_ctx *ctx, int *tile, int *order, int64_t *workgroups);
 
+/* ------------------------------------------------------------------------
+ * Learned split-screen (an extension; the paper evaluates every candidate
+ * each step).  Every `period` steps the step is exact (all free-surface
+ * candidates of Sec. 2.2 evaluated) and then a small MLP scores every
+ * candidate (f, a); until the next such step, G is evaluated only for the
+ * candidates scored above tau and for candidates that appeared since.  The
+ * MCT pick (Sec. 3) stays the same over the evaluated set, so a screened run
+ * equals the plain run as long as no skipped candidate would have won.
+ *
+ * Features of a candidate, in order (h = sqrt(A_f), sigma_ref =
+ * sqrt(E Gc_f / h), sigma = mean of the four smoothed edge stresses of f):
+ *   0, 1 principal stresses of sigma / sigma_ref (larger first);
+ *   2    W h / Gc_f, W = sigma:eps / 2 with eps = D^-1 sigma (plane stress);
+ *   3    max over the three paths of G / Gc_f (0 when edge a is not
+ *        stretched);
+ *   4    feature 3 of the same candidate at the previous evaluation (0 if it
+ *        was not a candidate then);
+ *   5    min(d / h, 64) / 64, d = reference distance from the midpoint of
+ *        edge a to the nearest crack-surface tip midpoint (1 without tips);
+ *   6-9  1 where the neighbour across local edge 0..3 is split or outside.
+ *
+ * MLP (4 929 FP32 parameters, one flat host array): W1 [10][64]
+ * (input-major), b1 [64], W2 [64][64], b2 [64], w3 [64], b3; GELU (erf form)
+ * after both hidden layers; logit = h2 . w3 + b3.  Products run as bfloat16
+ * MFMA with FP32 accumulation: inputs, weights, hidden activations and
+ * backpropagated pre-activation gradients are rounded to bfloat16 (nearest,
+ * ties to even); biases, GELU, the loss and Adam are FP32.
+ * ------------------------------------------------------------------------ */
+typedef struct mct_mlp mct_mlp;
+
+/* Features of every current candidate (element order, then local edge),
+ * computed on the device from the current state; also advances the
+ * history behind feature 4 (also when the capacity is too small, so pass
+ * cap >= 4 x elements, the most candidates there can be).  Outputs are host
+ * arrays of capacity cap rows (features: 10 floats per row).  Plain contexts
+ * only (MCT_EUNSUPPORTED for a batch); MCT_ESTATE before mct_finalize. */
+int mct_screen_collect(mct_ctx *ctx, int64_t cap, float *features, int32_t *elem, uint8_t *entry,
+                       int64_t *count);
+
+/* Screened stepping with the parameters of `mlp` (copied; mlp may be
+ * destroyed afterwards), threshold tau on the logit and the exact-step
+ * period (>= 2; steps k with k % period == 0 are exact).  mct_screen_disable
+ * returns to plain stepping.  Checkpoints do not hold the screen state. */
+int mct_screen_enable(mct_ctx *ctx, const mct_mlp *mlp, float tau, int period);
+int mct_screen_disable(mct_ctx *ctx);
+
+/* Counters since the screen buffers were created: [0] exact steps followed
+ * by a screen evaluation, [1] candidates at those steps, [2] candidates
+ * flagged, [3] misses: candidates skipped by the previous screen whose
+ * max G / Gc exceeds 1 at an exact step. */
+int mct_screen_stats(mct_ctx *ctx, int64_t out[4]);
+
+/* MLP handle with its own HIP stream (NULL = library-created).  Parameters
+ * start at zero.  set_params copies 4 929 host floats and resets the Adam
+ * state; get_params copies them back. */
+int mct_mlp_create(mct_mlp **out, void *hip_stream);
+int mct_mlp_destroy(mct_mlp *mlp);
+const char *mct_mlp_last_error(const mct_mlp *mlp);
+int mct_mlp_set_params(mct_mlp *mlp, const float *params);
+int mct_mlp_get_params(mct_mlp *mlp, float *params);
+
+/* Logits of n rows: x and logits are DEVICE pointers (x: 10 floats per
+ * row).  Asynchronous on the handle's stream. */
+int mct_mlp_forward(mct_mlp *mlp, const float *x, int64_t n, float *logits);
+
+/* Loss L = (1/n) sum_i w_i (softplus(z_i) - y_i z_i), w_i = pos_weight where
+ * y_i = 1 else 1, over n rows (x, y DEVICE pointers, y in {0, 1}), and its
+ * gradient with respect to the parameters (host output, 4 929 floats;
+ * loss may be NULL).  Synchronous. */
+int mct_mlp_gradient(mct_mlp *mlp, const float *x, const float *y, int64_t n, float pos_weight, float *grad,
+                     float *loss);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on that
+ * gradient with learning rate lr.  With loss == NULL the call returns
+ * without waiting (x and y must stay valid until the stream has run it);
+ * otherwise it waits and stores the loss before the update. */
+int mct_mlp_train_step(mct_mlp *mlp, const float *x, const float *y, int64_t n, float pos_weight, float lr,
+                       float *loss);
+
 #ifdef __cplusplus
 }
 #endif

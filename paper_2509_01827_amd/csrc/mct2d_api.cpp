@@ -93,6 +93,25 @@ struct mct_ctx {
     hipGraphExec_t graph[2] = {nullptr, nullptr};  // by parity of the first step
     int graph_tile[2] = {0, 0};
     int64_t steps_enqueued = 0;  // host view of the step counter
+
+    // learned split-screen (plain contexts only)
+    bool screen_alloc = false, screen_on = false;
+    int screen_period = 50;
+    float screen_tau = 0.0f;
+    mct::ScreenDev sd{};
+    mct::MlpDev smlp{};                             // weights in use (no Adam state)
+    hipGraphExec_t sgraph[2] = {nullptr, nullptr};  // one screened period, by parity
+    int sgraph_tile[2] = {0, 0};
+};
+
+struct mct_mlp {
+    std::string err;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    mct::MlpDev d{};
+    float *grad = nullptr;      // kParams + 1 (loss last)
+    float *partials = nullptr;  // per-workgroup gradients
+    int t = 0;                  // Adam steps taken
 };
 
 namespace {
@@ -124,7 +143,39 @@ void drop_graphs(mct_ctx *c) {
     for (int i = 0; i < 2; ++i) {
         if (c->graph[i]) (void)hipGraphExecDestroy(c->graph[i]);
         c->graph[i] = nullptr;
+        if (c->sgraph[i]) (void)hipGraphExecDestroy(c->sgraph[i]);
+        c->sgraph[i] = nullptr;
     }
+}
+
+void free_mlp(mct::MlpDev &m) {
+    dfree(m.master);
+    dfree(m.m);
+    dfree(m.v);
+    dfree(m.w1b);
+    dfree(m.w2b);
+    dfree(m.w3b);
+}
+
+void free_screen(mct_ctx *c) {
+    mct::ScreenDev &s = c->sd;
+    dfree(s.ncand);
+    dfree(s.cand);
+    dfree(s.block_counts);
+    dfree(s.feat);
+    dfree(s.logits);
+    dfree(s.hist_g);
+    dfree(s.hist_t);
+    dfree(s.sweep);
+    dfree(s.screen);
+    dfree(s.tip_counts);
+    dfree(s.ntips);
+    dfree(s.tip_edge);
+    dfree(s.tip_xy);
+    dfree(s.stats);
+    free_mlp(c->smlp);
+    c->screen_alloc = false;
+    c->screen_on = false;
 }
 
 void release_device(mct_ctx *c) {
@@ -152,6 +203,7 @@ void release_device(mct_ctx *c) {
     dfree(c->dunits);
     dfree(c->dtip_counts);
     dfree(c->dtip_total);
+    free_screen(c);
     c->finalized = false;
 }
 
@@ -294,6 +346,135 @@ int build_graph(mct_ctx *c, int par0) {
     (void)hipStreamDestroy(cap);
     if (e != hipSuccess) return fail(c, MCT_EDEVICE, "graph capture: %s", hipGetErrorString(e));
     c->graph_tile[par0] = c->tile;
+    return MCT_OK;
+}
+
+// ---------------------------------------------------------------------
+// Learned split-screen: device buffers, the sweep pipeline and screened
+// stepping.
+
+int alloc_mlp(mct_ctx *c, mct::MlpDev &m, bool with_adam) {
+    HIP_TRY(c, hipMalloc((void **)&m.master, sizeof(float) * mct::kParams));
+    if (with_adam) {
+        HIP_TRY(c, hipMalloc((void **)&m.m, sizeof(float) * mct::kParams));
+        HIP_TRY(c, hipMalloc((void **)&m.v, sizeof(float) * mct::kParams));
+    }
+    HIP_TRY(c, hipMalloc((void **)&m.w1b, sizeof(uint16_t) * 32 * mct::kHidden));
+    HIP_TRY(c, hipMalloc((void **)&m.w2b, sizeof(uint16_t) * mct::kHidden * mct::kHidden));
+    HIP_TRY(c, hipMalloc((void **)&m.w3b, sizeof(uint16_t) * mct::kHidden));
+    return MCT_OK;
+}
+
+int ensure_screen(mct_ctx *c) {
+    if (c->batch) return fail(c, MCT_EUNSUPPORTED, "the split-screen runs on plain (single specimen) contexts");
+    if (!c->finalized) return fail(c, MCT_ESTATE, "finalize first");
+    if (c->screen_alloc) return MCT_OK;
+    const Spec &sp = c->specs[0];
+    const int64_t ne = sp.ne, nc = 4 * ne;
+    mct::ScreenDev &s = c->sd;
+    HIP_TRY(c, hipMalloc((void **)&s.ncand, sizeof(int32_t)));
+    HIP_TRY(c, hipMalloc((void **)&s.cand, sizeof(int32_t) * nc));
+    HIP_TRY(c, hipMalloc((void **)&s.block_counts, sizeof(int32_t) * mct::cand_nblocks(ne)));
+    HIP_TRY(c, hipMalloc((void **)&s.feat, sizeof(float) * mct::kFeat * nc));
+    HIP_TRY(c, hipMalloc((void **)&s.logits, sizeof(float) * nc));
+    HIP_TRY(c, hipMalloc((void **)&s.hist_g, sizeof(double) * nc));
+    HIP_TRY(c, hipMalloc((void **)&s.hist_t, sizeof(int32_t) * nc));
+    HIP_TRY(c, hipMalloc((void **)&s.sweep, sizeof(int32_t)));
+    HIP_TRY(c, hipMalloc((void **)&s.screen, sizeof(uint32_t) * ne));
+    HIP_TRY(c, hipMalloc((void **)&s.tip_counts, sizeof(int32_t) * mct::tips_nblocks(sp.ns)));
+    HIP_TRY(c, hipMalloc((void **)&s.ntips, sizeof(int32_t)));
+    HIP_TRY(c, hipMalloc((void **)&s.tip_edge, sizeof(int32_t) * sp.ns));
+    HIP_TRY(c, hipMalloc((void **)&s.tip_xy, sizeof(double) * 2 * sp.ns));
+    HIP_TRY(c, hipMalloc((void **)&s.stats, sizeof(unsigned long long) * 4));
+    // no evaluation yet: history stamps never match, every candidate unseen
+    HIP_TRY(c, mct::launch_fill_u32(reinterpret_cast<uint32_t *>(s.hist_t), nc, 0xFFFFFFFEu, c->stream));
+    HIP_TRY(c, hipMemsetAsync(s.sweep, 0, sizeof(int32_t), c->stream));
+    HIP_TRY(c, hipMemsetAsync(s.screen, 0, sizeof(uint32_t) * ne, c->stream));
+    HIP_TRY(c, hipMemsetAsync(s.stats, 0, sizeof(unsigned long long) * 4, c->stream));
+    int rc = alloc_mlp(c, c->smlp, false);
+    if (rc) return rc;
+    c->screen_alloc = true;
+    return MCT_OK;
+}
+
+// Candidates, tips and features of the state in u buffer `par`; with the
+// screen on, scores and screen states too.  Kernels only (capturable).
+hipError_t screen_pipeline(mct_ctx *c, int par, hipStream_t st) {
+    const StepParams &p = c->specs[0].prm;
+    const mct::ScreenDev &s = c->sd;
+    int32_t nb = 0;
+    hipError_t e = mct::launch_tips(p.nx, p.ny, p.X, p.Y, p.split, s.tip_counts, &nb, s.tip_edge, s.tip_xy,
+                                    s.ntips, st);
+    if (e == hipSuccess) e = mct::launch_screen_candidates(p, s, st);
+    if (e == hipSuccess) e = mct::launch_screen_features(p, s, par, st);
+    if (c->screen_on) {
+        if (e == hipSuccess) e = mct::launch_mlp_forward(c->smlp, s.feat, s.ncand, 0, s.logits, st);
+        if (e == hipSuccess) e = mct::launch_screen_apply(p, s, c->screen_tau, st);
+    }
+    if (e == hipSuccess) e = mct::launch_sweep_advance(s, st);
+    return e;
+}
+
+// Steps k_rel = first .. first + count - 1 of a segment starting at parity
+// par0 and global step k0: sweep steps (k % period == 0) run plain and are
+// followed by the screen pipeline, the others run screened.
+hipError_t screened_steps(mct_ctx *c, int64_t k0, int first, int count, int par0, hipStream_t st) {
+    mct::Launch Lp = launch_of(c), Ls = launch_of(c);
+    Ls.p0.screen = c->sd.screen;
+    hipError_t e = hipSuccess;
+    for (int i = first; e == hipSuccess && i < first + count; ++i) {
+        if ((k0 + i) % c->screen_period == 0) {
+            e = mct::launch_step(c->tile, Lp, i, par0, st);
+            if (e == hipSuccess) e = screen_pipeline(c, (par0 + i + 1) & 1, st);
+        } else {
+            e = mct::launch_step(c->tile, Ls, i, par0, st);
+        }
+    }
+    return e;
+}
+
+int build_screen_graph(mct_ctx *c, int par0) {
+    if (c->sgraph[par0]) (void)hipGraphExecDestroy(c->sgraph[par0]);
+    c->sgraph[par0] = nullptr;
+    hipStream_t cap;
+    HIP_TRY(c, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) e = screened_steps(c, 0, 0, c->screen_period, par0, cap);
+    if (e == hipSuccess) e = mct::launch_commit(launch_of(c), c->screen_period, cap);
+    hipError_t e2 = hipStreamEndCapture(cap, &g);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&c->sgraph[par0], g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) return fail(c, MCT_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+    c->sgraph_tile[par0] = c->tile;
+    return MCT_OK;
+}
+
+int step_screened(mct_ctx *c, int64_t n) {
+    const int P = c->screen_period;
+    int64_t left = n;
+    while (left > 0) {
+        const int64_t k0 = c->steps_enqueued;
+        const int par0 = (int)(k0 & 1);
+        const int q = (int)(k0 % P);
+        if (q == 0 && left >= P && c->use_graph) {
+            if (!c->sgraph[par0] || c->sgraph_tile[par0] != c->tile) {
+                int rc = build_screen_graph(c, par0);
+                if (rc) return rc;
+            }
+            HIP_TRY(c, hipGraphLaunch(c->sgraph[par0], c->stream));
+            left -= P;
+            c->steps_enqueued += P;
+            continue;
+        }
+        const int seg = (int)std::min<int64_t>(left, P - q);  // up to the next sweep
+        HIP_TRY(c, screened_steps(c, k0, 0, seg, par0, c->stream));
+        HIP_TRY(c, mct::launch_commit(launch_of(c), seg, c->stream));
+        left -= seg;
+        c->steps_enqueued += seg;
+    }
     return MCT_OK;
 }
 
@@ -664,6 +845,7 @@ int mct_step(mct_ctx *c, int64_t n) {
     if (!c) return MCT_EINVAL;
     if (!c->finalized) return fail(c, MCT_ESTATE, "finalize first");
     if (n < 0) return fail(c, MCT_EINVAL, "negative step count");
+    if (c->screen_on) return step_screened(c, n);
     int64_t left = n;
     if (c->use_graph) {
         while (left >= kGraphSteps) {
@@ -993,6 +1175,197 @@ int mct_get_launch(mct_ctx *c, int *tile, int *order, int64_t *workgroups) {
     if (tile) *tile = c->tile;
     if (order) *order = c->order;
     if (workgroups) *workgroups = c->batch ? c->nunits : c->specs[0].prm.nwg;
+    return MCT_OK;
+}
+
+
+// ------------------------------------------------------------- screen
+
+int mct_screen_collect(mct_ctx *c, int64_t cap, float *features, int32_t *elem, uint8_t *entry,
+                       int64_t *count) {
+    if (!c) return MCT_EINVAL;
+    if (!count || (cap > 0 && (!features || !elem || !entry))) return fail(c, MCT_EINVAL, "null output");
+    int rc = ensure_screen(c);
+    if (rc) return rc;
+    const bool on = c->screen_on;
+    c->screen_on = false;  // features only
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    hipError_t e = screen_pipeline(c, (int)(c->steps_enqueued & 1), c->stream);
+    c->screen_on = on;
+    HIP_TRY(c, e);
+    int32_t n = 0;
+    HIP_TRY(c, hipMemcpyAsync(&n, c->sd.ncand, sizeof n, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    *count = n;
+    if (n > cap) return fail(c, MCT_ECAPACITY, "%d candidates, capacity %lld", n, (long long)cap);
+    if (n == 0) return MCT_OK;
+    std::vector<int32_t> packed(n);
+    HIP_TRY(c, hipMemcpyAsync(packed.data(), c->sd.cand, sizeof(int32_t) * n, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(features, c->sd.feat, sizeof(float) * mct::kFeat * n, hipMemcpyDeviceToHost,
+                              c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (int32_t i = 0; i < n; ++i) {
+        elem[i] = packed[i] >> 2;
+        entry[i] = (uint8_t)(packed[i] & 3);
+    }
+    return MCT_OK;
+}
+
+int mct_screen_enable(mct_ctx *c, const mct_mlp *mlp, float tau, int period) {
+    if (!c) return MCT_EINVAL;
+    if (!mlp) return fail(c, MCT_EINVAL, "null model");
+    if (period < 2) return fail(c, MCT_EINVAL, "period must be at least 2");
+    int rc = ensure_screen(c);
+    if (rc) return rc;
+    HIP_TRY(c, hipStreamSynchronize(mlp->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->smlp.master, mlp->d.master, sizeof(float) * mct::kParams,
+                              hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, mct::launch_mlp_prep(c->smlp, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->screen_tau = tau;
+    c->screen_period = period;
+    c->screen_on = true;
+    drop_graphs(c);
+    return MCT_OK;
+}
+
+int mct_screen_disable(mct_ctx *c) {
+    if (!c) return MCT_EINVAL;
+    c->screen_on = false;
+    drop_graphs(c);
+    return MCT_OK;
+}
+
+int mct_screen_stats(mct_ctx *c, int64_t out[4]) {
+    if (!c || !out) return MCT_EINVAL;
+    for (int i = 0; i < 4; ++i) out[i] = 0;
+    if (!c->screen_alloc) return MCT_OK;
+    unsigned long long h[4];
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy(h, c->sd.stats, sizeof h, hipMemcpyDeviceToHost));
+    for (int i = 0; i < 4; ++i) out[i] = (int64_t)h[i];
+    return MCT_OK;
+}
+
+// ------------------------------------------------------------ screen MLP
+
+namespace {
+int mfail(mct_mlp *m, int code, const char *what) {
+    m->err = what;
+    return code;
+}
+#define MLP_TRY(m, expr)                                                                            \
+    do {                                                                                            \
+        hipError_t e_ = (expr);                                                                     \
+        if (e_ != hipSuccess) {                                                                     \
+            (m)->err = std::string(#expr) + ": " + hipGetErrorString(e_);                          \
+            return MCT_EDEVICE;                                                                     \
+        }                                                                                           \
+    } while (0)
+}  // namespace
+
+int mct_mlp_create(mct_mlp **out, void *hip_stream) {
+    if (!out) return MCT_EINVAL;
+    *out = nullptr;
+    mct_mlp *m = new (std::nothrow) mct_mlp;
+    if (!m) return MCT_ENOMEM;
+    bool ok = true;
+    if (hip_stream) {
+        m->stream = (hipStream_t)hip_stream;
+    } else {
+        ok = hipStreamCreateWithFlags(&m->stream, hipStreamNonBlocking) == hipSuccess;
+        m->own_stream = ok;
+    }
+    mct::MlpDev &d = m->d;
+    ok = ok && hipMalloc((void **)&d.master, sizeof(float) * mct::kParams) == hipSuccess;
+    ok = ok && hipMalloc((void **)&d.m, sizeof(float) * mct::kParams) == hipSuccess;
+    ok = ok && hipMalloc((void **)&d.v, sizeof(float) * mct::kParams) == hipSuccess;
+    ok = ok && hipMalloc((void **)&d.w1b, sizeof(uint16_t) * 32 * mct::kHidden) == hipSuccess;
+    ok = ok && hipMalloc((void **)&d.w2b, sizeof(uint16_t) * mct::kHidden * mct::kHidden) == hipSuccess;
+    ok = ok && hipMalloc((void **)&d.w3b, sizeof(uint16_t) * mct::kHidden) == hipSuccess;
+    ok = ok && hipMalloc((void **)&m->grad, sizeof(float) * (mct::kParams + 1)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&m->partials,
+                         sizeof(float) * (mct::kParams + 1) * (size_t)mct::mlp_train_blocks(INT64_MAX)) == hipSuccess;
+    ok = ok && hipMemsetAsync(d.master, 0, sizeof(float) * mct::kParams, m->stream) == hipSuccess;
+    ok = ok && hipMemsetAsync(d.m, 0, sizeof(float) * mct::kParams, m->stream) == hipSuccess;
+    ok = ok && hipMemsetAsync(d.v, 0, sizeof(float) * mct::kParams, m->stream) == hipSuccess;
+    ok = ok && mct::launch_mlp_prep(d, m->stream) == hipSuccess;
+    ok = ok && hipStreamSynchronize(m->stream) == hipSuccess;
+    if (!ok) {
+        mct_mlp_destroy(m);
+        return MCT_EDEVICE;
+    }
+    *out = m;
+    return MCT_OK;
+}
+
+int mct_mlp_destroy(mct_mlp *m) {
+    if (!m) return MCT_OK;
+    if (m->stream) (void)hipStreamSynchronize(m->stream);
+    free_mlp(m->d);
+    dfree(m->grad);
+    dfree(m->partials);
+    if (m->own_stream) (void)hipStreamDestroy(m->stream);
+    delete m;
+    return MCT_OK;
+}
+
+const char *mct_mlp_last_error(const mct_mlp *m) { return m ? m->err.c_str() : "null model"; }
+
+int mct_mlp_set_params(mct_mlp *m, const float *params) {
+    if (!m) return MCT_EINVAL;
+    if (!params) return mfail(m, MCT_EINVAL, "null parameters");
+    for (int i = 0; i < mct::kParams; ++i)
+        if (!std::isfinite(params[i])) return mfail(m, MCT_EINVAL, "non-finite parameter");
+    MLP_TRY(m, hipMemcpyAsync(m->d.master, params, sizeof(float) * mct::kParams, hipMemcpyHostToDevice, m->stream));
+    MLP_TRY(m, hipMemsetAsync(m->d.m, 0, sizeof(float) * mct::kParams, m->stream));
+    MLP_TRY(m, hipMemsetAsync(m->d.v, 0, sizeof(float) * mct::kParams, m->stream));
+    MLP_TRY(m, mct::launch_mlp_prep(m->d, m->stream));
+    MLP_TRY(m, hipStreamSynchronize(m->stream));
+    m->t = 0;
+    return MCT_OK;
+}
+
+int mct_mlp_get_params(mct_mlp *m, float *params) {
+    if (!m) return MCT_EINVAL;
+    if (!params) return mfail(m, MCT_EINVAL, "null output");
+    MLP_TRY(m, hipMemcpyAsync(params, m->d.master, sizeof(float) * mct::kParams, hipMemcpyDeviceToHost, m->stream));
+    MLP_TRY(m, hipStreamSynchronize(m->stream));
+    return MCT_OK;
+}
+
+int mct_mlp_forward(mct_mlp *m, const float *x, int64_t n, float *logits) {
+    if (!m) return MCT_EINVAL;
+    if (n < 0 || (n > 0 && (!x || !logits))) return mfail(m, MCT_EINVAL, "bad rows or null pointer");
+    if (n == 0) return MCT_OK;
+    MLP_TRY(m, mct::launch_mlp_forward(m->d, x, nullptr, n, logits, m->stream));
+    return MCT_OK;
+}
+
+int mct_mlp_gradient(mct_mlp *m, const float *x, const float *y, int64_t n, float pos_weight, float *grad,
+                     float *loss) {
+    if (!m) return MCT_EINVAL;
+    if (n <= 0 || !x || !y || !grad) return mfail(m, MCT_EINVAL, "bad rows or null pointer");
+    if (!(pos_weight > 0.0f)) return mfail(m, MCT_EINVAL, "pos_weight must be positive");
+    MLP_TRY(m, mct::launch_mlp_gradient(m->d, x, y, n, pos_weight, m->partials, m->grad, m->stream));
+    MLP_TRY(m, hipMemcpyAsync(grad, m->grad, sizeof(float) * mct::kParams, hipMemcpyDeviceToHost, m->stream));
+    if (loss) MLP_TRY(m, hipMemcpyAsync(loss, m->grad + mct::kParams, sizeof(float), hipMemcpyDeviceToHost, m->stream));
+    MLP_TRY(m, hipStreamSynchronize(m->stream));
+    return MCT_OK;
+}
+
+int mct_mlp_train_step(mct_mlp *m, const float *x, const float *y, int64_t n, float pos_weight, float lr,
+                       float *loss) {
+    if (!m) return MCT_EINVAL;
+    if (n <= 0 || !x || !y) return mfail(m, MCT_EINVAL, "bad rows or null pointer");
+    if (!(pos_weight > 0.0f) || !(lr > 0.0f)) return mfail(m, MCT_EINVAL, "pos_weight and lr must be positive");
+    MLP_TRY(m, mct::launch_mlp_gradient(m->d, x, y, n, pos_weight, m->partials, m->grad, m->stream));
+    m->t += 1;
+    MLP_TRY(m, mct::launch_mlp_adam(m->d, m->grad, lr, m->t, m->stream));
+    if (loss) {
+        MLP_TRY(m, hipMemcpyAsync(loss, m->grad + mct::kParams, sizeof(float), hipMemcpyDeviceToHost, m->stream));
+        MLP_TRY(m, hipStreamSynchronize(m->stream));
+    }
     return MCT_OK;
 }
 

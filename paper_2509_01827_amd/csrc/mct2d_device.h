@@ -1,0 +1,134 @@
+// Element-level device arithmetic shared by the step and screen kernels
+// (binary64, compiled with -ffp-contract=off; fma only where written).
+#pragma once
+
+#include "mct2d_impl.h"
+
+namespace mct {
+namespace dev {
+
+// natural coordinates of Q4 nodes and of the edge midpoints
+__device__ __forceinline__ double xi_n(int n) { return (n == 1 || n == 2) ? 1.0 : -1.0; }
+__device__ __forceinline__ double eta_n(int n) { return (n >= 2) ? 1.0 : -1.0; }
+__device__ __forceinline__ double xi_m(int k) { return k == 1 ? 1.0 : (k == 3 ? -1.0 : 0.0); }
+__device__ __forceinline__ double eta_m(int k) { return k == 0 ? -1.0 : (k == 2 ? 1.0 : 0.0); }
+
+// dN/dx, dN/dy of the bilinear element at the midpoint of its local edge k.
+//
+// The shape-function derivatives in natural coordinates at an edge midpoint
+// are 0, +-1/4 or +-1/2, so every product with them is exact.  The sums are
+// written over the non-zero terms only: adding a zero product to a running
+// sum, or subtracting one, leaves every non-zero value unchanged (at most
+// the sign of a zero differs), so the result equals the plain evaluation
+//   J = sum_n dN_n/d(xi,eta) * (x_n, y_n)    (fma chain from 0, n = 0..3)
+//   dN_n/dx = (J22 dN_n/dxi - J12 dN_n/deta) / det J  (as * (1/det))
+//   dN_n/dy = (J11 dN_n/deta - J21 dN_n/dxi) / det J
+// bit for bit.  With k a compile-time constant after unrolling, the zero
+// tests fold away.
+__device__ __forceinline__ double exact_dot4(const double c[4], const double v[4]) {
+    double s = 0.0;
+    bool first = true;
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        if (c[n] != 0.0) {
+            s = first ? c[n] * v[n] : fma(c[n], v[n], s);
+            first = false;
+        }
+    }
+    return s;
+}
+
+__device__ __forceinline__ void q4_grad(const double x[4], const double y[4], int k, double dndx[4],
+                                        double dndy[4]) {
+    double dxi[4], deta[4];
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        dxi[n] = 0.25 * xi_n(n) * (1.0 + eta_m(k) * eta_n(n));
+        deta[n] = 0.25 * eta_n(n) * (1.0 + xi_m(k) * xi_n(n));
+    }
+    const double j11 = exact_dot4(dxi, x);
+    const double j12 = exact_dot4(dxi, y);
+    const double j21 = exact_dot4(deta, x);
+    const double j22 = exact_dot4(deta, y);
+    const double det = j11 * j22 - j12 * j21;
+    const double inv = 1.0 / det;
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        double a, b;
+        if (dxi[n] != 0.0 && deta[n] != 0.0) {
+            a = fma(j22, dxi[n], -(j12 * deta[n]));
+            b = fma(j11, deta[n], -(j21 * dxi[n]));
+        } else if (dxi[n] != 0.0) {
+            a = j22 * dxi[n];
+            b = -(j21 * dxi[n]);
+        } else {
+            a = -(j12 * deta[n]);
+            b = j11 * deta[n];
+        }
+        dndx[n] = a * inv;
+        dndy[n] = b * inv;
+    }
+}
+
+// q4_grad with the edge index as a template argument (for runtime k).
+__device__ __forceinline__ void q4_grad_rt(const double x[4], const double y[4], int k, double dndx[4],
+                                           double dndy[4]) {
+    switch (k) {
+        case 0: q4_grad(x, y, 0, dndx, dndy); break;
+        case 1: q4_grad(x, y, 1, dndx, dndy); break;
+        case 2: q4_grad(x, y, 2, dndx, dndy); break;
+        default: q4_grad(x, y, 3, dndx, dndy); break;
+    }
+}
+
+template <int NN>
+__device__ __forceinline__ void strain(const double *dndx, const double *dndy, const double *ux,
+                                       const double *uy, double eps[3]) {
+    double exx = 0.0, eyy = 0.0, gxy = 0.0;
+#pragma unroll
+    for (int n = 0; n < NN; ++n) {
+        exx = fma(dndx[n], ux[n], exx);
+        eyy = fma(dndy[n], uy[n], eyy);
+        gxy = fma(dndy[n], ux[n], gxy);
+        gxy = fma(dndx[n], uy[n], gxy);
+    }
+    eps[0] = exx;
+    eps[1] = eyy;
+    eps[2] = gxy;
+}
+
+__device__ __forceinline__ void hooke(const StepParams &p, const double eps[3], double sig[3]) {
+    sig[0] = fma(p.D12, eps[1], p.D11 * eps[0]);
+    sig[1] = fma(p.D12, eps[0], p.D11 * eps[1]);
+    sig[2] = p.D33 * eps[2];
+}
+
+// Unit normal and length of the crack path from the midpoint of local edge
+// a (end nodes (xa0, ya0), (xa1, ya1) = n_a, n_{a+1}) to the midpoint of
+// local edge k (end nodes n_k, n_{k+1}), oriented toward node n_{a+1}
+// (reference coordinates).  Uses correctly rounded sqrt and division only.
+__device__ __forceinline__ void path_geom_pts(double xa0, double ya0, double xa1, double ya1, double xk0,
+                                              double yk0, double xk1, double yk1, double &nxo, double &nyo,
+                                              double &len) {
+    const double g0x = 0.5 * (xa0 + xa1), g0y = 0.5 * (ya0 + ya1);
+    const double gkx = 0.5 * (xk0 + xk1), gky = 0.5 * (yk0 + yk1);
+    const double dx = gkx - g0x, dy = gky - g0y;
+    const double L = sqrt(dx * dx + dy * dy);
+    double cx = dy / L, cy = -dx / L;
+    if (cx * (xa1 - g0x) + cy * (ya1 - g0y) < 0.0) {
+        cx = -cx;
+        cy = -cy;
+    }
+    nxo = cx;
+    nyo = cy;
+    len = L;
+}
+
+__device__ __forceinline__ void path_geom(const double x[4], const double y[4], int a, int k, double &nxo,
+                                          double &nyo, double &len) {
+    const int a1 = (a + 1) & 3, k1 = (k + 1) & 3;
+    path_geom_pts(x[a], y[a], x[a1], y[a1], x[k], y[k], x[k1], y[k1], nxo, nyo, len);
+}
+
+}  // namespace dev
+}  // namespace mct

@@ -53,6 +53,7 @@ struct StepParams {
     const double *minv;
     uint8_t *split;
     const double *area;  // per element (reference configuration)
+    const uint32_t *screen;  // per element, byte a = screen state of candidate (e, a); null = no screen
     const double *gc;   // per element, or nullptr for gc_uniform
     double gc_uniform;
     const double *fext_p;     // 2 per perimeter node
@@ -95,5 +96,59 @@ int tips_nblocks(int64_t n_edges);
 
 // Crack-path normals and lengths of n elements (36 doubles each).
 hipError_t launch_path_geometry(const StepParams &p, int n, const int32_t *elem, double *out, hipStream_t s);
+
+// ---------------------------------------------------------------------
+// Learned split-screen.
+
+constexpr int kFeat = 10;                 // features per candidate
+constexpr int kHidden = 64;               // hidden width of both layers
+constexpr int kParams = kFeat * kHidden + kHidden + kHidden * kHidden + kHidden + kHidden + 1;  // 4929
+constexpr int kOffB1 = kFeat * kHidden, kOffW2 = kOffB1 + kHidden, kOffB2 = kOffW2 + kHidden * kHidden;
+constexpr int kOffW3 = kOffB2 + kHidden, kOffB3 = kOffW3 + kHidden;
+static_assert(kOffB3 + 1 == kParams, "parameter layout");
+
+// screen state byte of a candidate: not seen at the last evaluation
+// (evaluated), flagged (evaluated), or screened out (skipped)
+constexpr uint8_t kScreenUnseen = 0, kScreenFlagged = 1, kScreenSkip = 2;
+enum ScreenStat { kStatSweeps = 0, kStatCands = 1, kStatFlagged = 2, kStatMisses = 3 };
+
+// Device MLP: FP32 master parameters, Adam moments, bfloat16 weight copies
+// (W1 padded to 32 input rows with zeros).
+struct MlpDev {
+    float *master, *m, *v;
+    uint16_t *w1b;  // [32][64]
+    uint16_t *w2b;  // [64][64]
+    uint16_t *w3b;  // [64]
+};
+
+// Device buffers of a model's screen.
+struct ScreenDev {
+    int32_t *ncand;         // candidate count of the last enumeration
+    int32_t *cand;          // packed e * 4 + a, element order (capacity 4 ne)
+    int32_t *block_counts;  // enumeration scan scratch
+    float *feat;            // kFeat per candidate
+    float *logits;          // one per candidate
+    double *hist_g;         // per (e, a): max path G / Gc at its last evaluation
+    int32_t *hist_t;        // per (e, a): sweep index of that evaluation
+    int32_t *sweep;         // sweeps done
+    uint32_t *screen;       // per element, one state byte per local edge
+    int32_t *tip_counts, *ntips, *tip_edge;
+    double *tip_xy;
+    unsigned long long *stats;  // ScreenStat counters
+};
+
+int cand_nblocks(int64_t ne);
+hipError_t launch_screen_candidates(const StepParams &p, const ScreenDev &s, hipStream_t st);
+hipError_t launch_screen_features(const StepParams &p, const ScreenDev &s, int par, hipStream_t st);
+hipError_t launch_sweep_advance(const ScreenDev &s, hipStream_t st);
+hipError_t launch_screen_apply(const StepParams &p, const ScreenDev &s, float tau, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t *a, int64_t n, uint32_t v, hipStream_t st);
+hipError_t launch_mlp_prep(const MlpDev &m, hipStream_t st);
+hipError_t launch_mlp_forward(const MlpDev &m, const float *x, const int32_t *n_dev, int64_t n, float *logits,
+                              hipStream_t st);
+int mlp_train_blocks(int64_t n);
+hipError_t launch_mlp_gradient(const MlpDev &m, const float *x, const float *y, int64_t n, float pos_weight,
+                               float *partials, float *grad, hipStream_t st);
+hipError_t launch_mlp_adam(const MlpDev &m, const float *grad, float lr, int t, hipStream_t st);
 
 }  // namespace mct

@@ -36,7 +36,12 @@ EXPORTS = [
     "mct_step", "mct_sync", "mct_get_info", "mct_get_crack_set", "mct_get_tips", "mct_get_field",
     "mct_get_split_codes", "mct_checkpoint", "mct_restore", "mct_set_launch", "mct_get_path_geometry",
     "mct_batch_create", "mct_batch_select", "mct_set_order", "mct_autotune", "mct_get_launch",
+    "mct_screen_collect", "mct_screen_enable", "mct_screen_disable", "mct_screen_stats",
+    "mct_mlp_create", "mct_mlp_destroy", "mct_mlp_last_error", "mct_mlp_set_params", "mct_mlp_get_params",
+    "mct_mlp_forward", "mct_mlp_gradient", "mct_mlp_train_step",
 ]
+N_FEATURES = 10
+N_PARAMS = 4929
 
 _lib = None
 
@@ -80,6 +85,19 @@ def load() -> C.CDLL:
     L.mct_set_order.argtypes = [P, C.c_int]
     L.mct_autotune.argtypes = [P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double)]
     L.mct_get_launch.argtypes = [P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int64)]
+    L.mct_screen_collect.argtypes = [P, C.c_int64, P, P, P, C.POINTER(C.c_int64)]
+    L.mct_screen_enable.argtypes = [P, P, C.c_float, C.c_int]
+    L.mct_screen_disable.argtypes = [P]
+    L.mct_screen_stats.argtypes = [P, P]
+    L.mct_mlp_create.argtypes = [C.POINTER(P), P]
+    L.mct_mlp_destroy.argtypes = [P]
+    L.mct_mlp_last_error.argtypes = [P]
+    L.mct_mlp_last_error.restype = C.c_char_p
+    L.mct_mlp_set_params.argtypes = [P, P]
+    L.mct_mlp_get_params.argtypes = [P, P]
+    L.mct_mlp_forward.argtypes = [P, P, C.c_int64, P]
+    L.mct_mlp_gradient.argtypes = [P, P, P, C.c_int64, C.c_float, P, P]
+    L.mct_mlp_train_step.argtypes = [P, P, P, C.c_int64, C.c_float, C.c_float, P]
     _lib = L
     return L
 
@@ -254,6 +272,92 @@ class Model:
     def restore(self, data: bytes):
         buf = C.create_string_buffer(data, len(data))
         self._check(self._L.mct_restore(self._h, C.cast(buf, C.c_void_p), len(data)), "restore")
+
+    # -- learned split-screen --------------------------------------------
+    def screen_collect(self):
+        """Features of every current candidate: (elem, entry, features [n][10]).
+        Each call is one evaluation for the history behind feature 4."""
+        cap = 4 * self.info()["n_elems"]  # at most four candidates per element
+        cnt = C.c_int64(0)
+        F = np.zeros((cap, N_FEATURES), np.float32)
+        el = np.zeros(cap, np.int32)
+        en = np.zeros(cap, np.uint8)
+        self._check(self._L.mct_screen_collect(self._h, cap, F.ctypes.data, el.ctypes.data, en.ctypes.data,
+                                               C.byref(cnt)), "screen_collect")
+        n = cnt.value
+        return el[:n], en[:n], F[:n]
+
+    def screen_enable(self, mlp: "Mlp", tau: float, period: int = 50):
+        self._check(self._L.mct_screen_enable(self._h, mlp._h, float(tau), int(period)), "screen_enable")
+
+    def screen_disable(self):
+        self._check(self._L.mct_screen_disable(self._h), "screen_disable")
+
+    def screen_stats(self) -> dict:
+        out = np.zeros(4, np.int64)
+        self._check(self._L.mct_screen_stats(self._h, out.ctypes.data), "screen_stats")
+        return dict(sweeps=int(out[0]), candidates=int(out[1]), flagged=int(out[2]), misses=int(out[3]))
+
+
+class Mlp:
+    """The split-screen MLP on the device (mct_mlp).  Inputs of forward,
+    gradient and train_step are device tensors (torch, float32, contiguous)."""
+
+    def __init__(self, stream: int | None = None):
+        L = load()
+        h = C.c_void_p()
+        rc = L.mct_mlp_create(C.byref(h), C.c_void_p(stream) if stream else None)
+        if rc != MCT_OK:
+            raise MctError("mlp create failed: %d" % rc)
+        self._h, self._L = h, L
+
+    def _check(self, rc, what=""):
+        if rc != MCT_OK:
+            msg = self._L.mct_mlp_last_error(self._h).decode(errors="replace")
+            raise MctError("%s failed (%d): %s" % (what, rc, msg))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.mct_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.shape == (N_PARAMS,)
+        self._check(self._L.mct_mlp_set_params(self._h, p.ctypes.data), "mlp_set_params")
+
+    def params(self):
+        p = np.zeros(N_PARAMS, np.float32)
+        self._check(self._L.mct_mlp_get_params(self._h, p.ctypes.data), "mlp_get_params")
+        return p
+
+    @staticmethod
+    def _dev(t, cols=None):
+        assert t.is_cuda and t.dtype.is_floating_point and t.is_contiguous()
+        if cols is not None:
+            assert t.dim() == 2 and t.shape[1] == cols
+        return t.data_ptr()
+
+    def forward(self, x, out):
+        n = x.shape[0]
+        self._check(self._L.mct_mlp_forward(self._h, self._dev(x, N_FEATURES), n, self._dev(out)), "mlp_forward")
+
+    def gradient(self, x, y, pos_weight=1.0):
+        g = np.zeros(N_PARAMS, np.float32)
+        loss = np.zeros(1, np.float32)
+        self._check(self._L.mct_mlp_gradient(self._h, self._dev(x, N_FEATURES), self._dev(y), x.shape[0],
+                                             float(pos_weight), g.ctypes.data, loss.ctypes.data), "mlp_gradient")
+        return float(loss[0]), g
+
+    def train_step(self, x, y, pos_weight=1.0, lr=1e-3, want_loss=False):
+        loss = np.zeros(1, np.float32)
+        self._check(self._L.mct_mlp_train_step(self._h, self._dev(x, N_FEATURES), self._dev(y), x.shape[0],
+                                               float(pos_weight), float(lr),
+                                               loss.ctypes.data if want_loss else None), "mlp_train_step")
+        return float(loss[0]) if want_loss else None
 
 
 def _setup(m: Model, cfg: dict):
