@@ -33,6 +33,7 @@ WORKLOADS = {
     "fragment2000": "fragmentation plate 2000x1000 Q4, h 0.1 mm, 5 m/s outward, Weibull(6,3) Gc",
     "batch256": "256 notched specimens 64..512 x 64..256 Q4, h 1 mm, notch U(0.2,0.6) width, "
                 "Weibull(6, U(2,4)) Gc, traction U(0.5,1.5) MPa",
+    "screen400": "branching plate 400x400 Q4 (as plate400) with the learned split-screen, exact step every 50",
 }
 
 
@@ -146,10 +147,19 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
+    screen = None
     if args.workload == "batch256":
         cfgs = W.batch_specimens()
         m = mct2d.batch_from_configs(cfgs, stream=stream.cuda_stream, tile=args.tile,
                                      use_graph=not args.no_graph)
+    elif args.workload == "screen400":
+        cfgs = [W.config2()]
+        with open(os.path.join(ROOT, "paper_2509_01827_amd", "screen_weights.json")) as f:
+            screen = json.load(f)
+        mlp = mct2d.Mlp()
+        mlp.set_params(np.asarray(screen["params"], np.float32))
+        m = mct2d.from_config(cfgs[0], stream=stream.cuda_stream, tile=args.tile, use_graph=not args.no_graph)
+        m.screen_enable(mlp, screen["tau"], screen["period"])
     else:
         cfgs = [W.config2() if args.workload == "plate400" else W.config3()]
         m = mct2d.from_config(cfgs[0], stream=stream.cuda_stream, tile=args.tile,
@@ -168,8 +178,9 @@ def main():
         assert inf["step"] == steps
         splits += inf["n_splits"]
         ud += inf["dissipated"]
-        if args.compare_plain:
+        if args.compare_plain or screen:
             logs.append(m.crack_set())
+    screen_stats = m.screen_stats() if screen else None
     ms_per_step = gpu_ms / steps
     value = ne * steps / (gpu_ms * 1e-3)
     bps = bytes_per_step(cfgs)
@@ -199,6 +210,15 @@ def main():
                      "traffic": measured_traffic(args.workload, launch["tile"]), "bytes_per_launch": bps},
     }
     m.close()
+    if screen:
+        p = mct2d.from_config(cfgs[0], stream=stream.cuda_stream, tile=args.tile, use_graph=not args.no_graph)
+        ms, _ = timed_run(p, stream, steps, args.warmup)
+        lg = p.crack_set()
+        same = all(np.array_equal(lg[k], logs[0][k]) for k in ("step", "elem", "entry", "exit", "G"))
+        p.close()
+        out["screened_vs_plain"] = {"speedup": ms / gpu_ms, "plain_ms": ms, "screened_ms": gpu_ms,
+                                    "identical_crack_sets": bool(same), "tau": screen["tau"],
+                                    "period": screen["period"], "stats": screen_stats}
     if args.compare_plain and len(cfgs) > 1:
         plain_ms = 0.0
         same = True

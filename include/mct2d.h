@@ -221,7 +221,9 @@ int mct_get_launch(mct_ctx *ctx, int *tile, int *order, int64_t *workgroups);
  *   4    feature 3 of the same candidate at the previous evaluation (0 if it
  *        was not a candidate then);
  *   5    min(d / h, 64) / 64, d = reference distance from the midpoint of
- *        edge a to the nearest crack-surface tip midpoint (1 without tips);
+ *        edge a to the nearest crack-path end, the midpoint of an entry or
+ *        exit edge of a split element whose neighbour across it is intact
+ *        (1 without such ends);
  *   6-9  1 where the neighbour across local edge 0..3 is split or outside.
  *
  * MLP (4 929 FP32 parameters, one flat host array): W1 [10][64]
@@ -235,7 +237,7 @@ typedef struct mct_mlp mct_mlp;
 
 /* Features of every current candidate (element order, then local edge),
  * computed on the device from the current state; also advances the
- * history behind feature 4 (also when the capacity is too small, so pass
+ * history behind feature 4 and clears the screen states (also when the capacity is too small, so pass
  * cap >= 4 x elements, the most candidates there can be).  Outputs are host
  * arrays of capacity cap rows (features: 10 floats per row).  Plain contexts
  * only (MCT_EUNSUPPORTED for a batch); MCT_ESTATE before mct_finalize. */
@@ -245,7 +247,8 @@ int mct_screen_collect(mct_ctx *ctx, int64_t cap, float *features, int32_t *elem
 /* Screened stepping with the parameters of `mlp` (copied; mlp may be
  * destroyed afterwards), threshold tau on the logit and the exact-step
  * period (>= 2; steps k with k % period == 0 are exact).  mct_screen_disable
- * returns to plain stepping.  Checkpoints do not hold the screen state. */
+ * returns to plain stepping.  Checkpoints do not hold the screen state:
+ * mct_restore starts the screen afresh (history, states and counters). */
 int mct_screen_enable(mct_ctx *ctx, const mct_mlp *mlp, float tau, int period);
 int mct_screen_disable(mct_ctx *ctx);
 

@@ -60,8 +60,9 @@ def features(o, cfg, g_prev=None):
       4     the same quantity at the previous evaluation (g_prev[(f, a)],
             0 when absent)
       5     min(d / h, 64) / 64, d = distance from the midpoint of edge a to
-            the nearest crack-surface tip (reference coordinates); 1 without
-            tips
+            the nearest crack-path end (reference coordinates): the midpoint
+            of an entry or exit edge of a split element whose neighbour
+            across that edge is intact; 1 without such ends
       6..9  1 where the neighbour across local edge k = 0..3 is split or
             outside the mesh, else 0
     Returns (elem, a, F [n][10], gnow dict for the next call).
@@ -70,7 +71,6 @@ def features(o, cfg, g_prev=None):
     st = o.state()
     _, _, sig, ok = o.internal_force(st["ux"], st["uy"], with_stress=True)
     cand = o.candidates()
-    tip_e, tip_xy = o.tips()
     tabs = o.tables()
     area = tabs["area"]
     ee = _element_edges(o)
@@ -78,6 +78,7 @@ def features(o, cfg, g_prev=None):
     split = st["split"]
     X, Y = np.asarray(cfg["X"], float), np.asarray(cfg["Y"], float)
     gcf = cfg.get("gc_field")
+    tip_xy = path_ends(nx, ny, X, Y, split)
     n = len(cand["elem"])
     F = np.zeros((n, N_IN))
     gnow = {}
@@ -103,7 +104,7 @@ def features(o, cfg, g_prev=None):
         nd = [j * (nx + 1) + i, j * (nx + 1) + i + 1, (j + 1) * (nx + 1) + i + 1, (j + 1) * (nx + 1) + i]
         p, q = nd[a], nd[(a + 1) % 4]
         mx, my = 0.5 * (X[p] + X[q]), 0.5 * (Y[p] + Y[q])
-        if len(tip_e):
+        if len(tip_xy):
             d = math.sqrt(min((tx - mx) ** 2 + (ty - my) ** 2 for tx, ty in tip_xy))
             fd = min(d / h, TIP_CAP) / TIP_CAP
         else:
@@ -119,6 +120,24 @@ def features(o, cfg, g_prev=None):
         F[r] = [(c + rr) / sref, (c - rr) / sref, W * h / gc, gmax, prev, fd] + flags
         gnow[(f, a)] = gmax
     return cand["elem"].astype(np.int64), cand["a"].astype(np.int64), F, gnow
+
+
+def path_ends(nx, ny, X, Y, split):
+    """Midpoints of the crack-path ends: entry or exit edges of split
+    elements whose neighbour across the edge is an intact element."""
+    out = []
+    for e in range(nx * ny):
+        c = int(split[e])
+        if c == 0:
+            continue
+        i, j = e % nx, e // nx
+        nd = [j * (nx + 1) + i, j * (nx + 1) + i + 1, (j + 1) * (nx + 1) + i + 1, (j + 1) * (nx + 1) + i]
+        for k in ((c >> 2) & 3, c & 3):
+            bi, bj = [(i, j - 1), (i + 1, j), (i, j + 1), (i - 1, j)][k]
+            if 0 <= bi < nx and 0 <= bj < ny and split[bj * nx + bi] == 0:
+                p, q = nd[k], nd[(k + 1) % 4]
+                out.append((0.5 * (X[p] + X[q]), 0.5 * (Y[p] + Y[q])))
+    return out
 
 
 # --------------------------------------------------------------- bfloat16

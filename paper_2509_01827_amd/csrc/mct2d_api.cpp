@@ -159,19 +159,18 @@ void free_mlp(mct::MlpDev &m) {
 
 void free_screen(mct_ctx *c) {
     mct::ScreenDev &s = c->sd;
-    dfree(s.ncand);
+    dfree(s.nrows);
+    dfree(s.nrows_last);
     dfree(s.cand);
-    dfree(s.block_counts);
     dfree(s.feat);
+    dfree(s.row_geo);
     dfree(s.logits);
     dfree(s.hist_g);
     dfree(s.hist_t);
     dfree(s.sweep);
     dfree(s.screen);
-    dfree(s.tip_counts);
-    dfree(s.ntips);
-    dfree(s.tip_edge);
-    dfree(s.tip_xy);
+    dfree(s.nfront);
+    dfree(s.front_xy);
     dfree(s.stats);
     free_mlp(c->smlp);
     c->screen_alloc = false;
@@ -372,23 +371,25 @@ int ensure_screen(mct_ctx *c) {
     const Spec &sp = c->specs[0];
     const int64_t ne = sp.ne, nc = 4 * ne;
     mct::ScreenDev &s = c->sd;
-    HIP_TRY(c, hipMalloc((void **)&s.ncand, sizeof(int32_t)));
+    HIP_TRY(c, hipMalloc((void **)&s.nrows, sizeof(int32_t)));
+    HIP_TRY(c, hipMalloc((void **)&s.nrows_last, sizeof(int32_t)));
     HIP_TRY(c, hipMalloc((void **)&s.cand, sizeof(int32_t) * nc));
-    HIP_TRY(c, hipMalloc((void **)&s.block_counts, sizeof(int32_t) * mct::cand_nblocks(ne)));
     HIP_TRY(c, hipMalloc((void **)&s.feat, sizeof(float) * mct::kFeat * nc));
+    HIP_TRY(c, hipMalloc((void **)&s.row_geo, sizeof(double) * 3 * nc));
     HIP_TRY(c, hipMalloc((void **)&s.logits, sizeof(float) * nc));
     HIP_TRY(c, hipMalloc((void **)&s.hist_g, sizeof(double) * nc));
     HIP_TRY(c, hipMalloc((void **)&s.hist_t, sizeof(int32_t) * nc));
     HIP_TRY(c, hipMalloc((void **)&s.sweep, sizeof(int32_t)));
     HIP_TRY(c, hipMalloc((void **)&s.screen, sizeof(uint32_t) * ne));
-    HIP_TRY(c, hipMalloc((void **)&s.tip_counts, sizeof(int32_t) * mct::tips_nblocks(sp.ns)));
-    HIP_TRY(c, hipMalloc((void **)&s.ntips, sizeof(int32_t)));
-    HIP_TRY(c, hipMalloc((void **)&s.tip_edge, sizeof(int32_t) * sp.ns));
-    HIP_TRY(c, hipMalloc((void **)&s.tip_xy, sizeof(double) * 2 * sp.ns));
+    HIP_TRY(c, hipMalloc((void **)&s.nfront, sizeof(int32_t)));
+    HIP_TRY(c, hipMalloc((void **)&s.front_xy, sizeof(double) * 4 * ne));
     HIP_TRY(c, hipMalloc((void **)&s.stats, sizeof(unsigned long long) * 4));
     // no evaluation yet: history stamps never match, every candidate unseen
     HIP_TRY(c, mct::launch_fill_u32(reinterpret_cast<uint32_t *>(s.hist_t), nc, 0xFFFFFFFEu, c->stream));
     HIP_TRY(c, hipMemsetAsync(s.sweep, 0, sizeof(int32_t), c->stream));
+    HIP_TRY(c, hipMemsetAsync(s.nrows, 0, sizeof(int32_t), c->stream));
+    HIP_TRY(c, hipMemsetAsync(s.nrows_last, 0, sizeof(int32_t), c->stream));
+    HIP_TRY(c, hipMemsetAsync(s.nfront, 0, sizeof(int32_t), c->stream));
     HIP_TRY(c, hipMemsetAsync(s.screen, 0, sizeof(uint32_t) * ne, c->stream));
     HIP_TRY(c, hipMemsetAsync(s.stats, 0, sizeof(unsigned long long) * 4, c->stream));
     int rc = alloc_mlp(c, c->smlp, false);
@@ -397,20 +398,16 @@ int ensure_screen(mct_ctx *c) {
     return MCT_OK;
 }
 
-// Candidates, tips and features of the state in u buffer `par`; with the
-// screen on, scores and screen states too.  Kernels only (capturable).
+// Crack-path ends, candidate rows and features of the state in u buffer
+// `par` (every screen state cleared); with the screen on, logits and the
+// new screen states too.  Kernels only (capturable).
 hipError_t screen_pipeline(mct_ctx *c, int par, hipStream_t st) {
     const StepParams &p = c->specs[0].prm;
     const mct::ScreenDev &s = c->sd;
-    int32_t nb = 0;
-    hipError_t e = mct::launch_tips(p.nx, p.ny, p.X, p.Y, p.split, s.tip_counts, &nb, s.tip_edge, s.tip_xy,
-                                    s.ntips, st);
-    if (e == hipSuccess) e = mct::launch_screen_candidates(p, s, st);
-    if (e == hipSuccess) e = mct::launch_screen_features(p, s, par, st);
-    if (c->screen_on) {
-        if (e == hipSuccess) e = mct::launch_mlp_forward(c->smlp, s.feat, s.ncand, 0, s.logits, st);
-        if (e == hipSuccess) e = mct::launch_screen_apply(p, s, c->screen_tau, st);
-    }
+    hipError_t e = mct::launch_screen_evaluate(p, s, par, st);
+    if (c->screen_on && e == hipSuccess)
+        e = mct::launch_mlp_forward(c->smlp, s.feat, s.nrows, 0, s.logits, s.cand, s.screen, c->screen_tau,
+                                    s.stats, st);
     if (e == hipSuccess) e = mct::launch_sweep_advance(s, st);
     return e;
 }
@@ -1109,6 +1106,14 @@ int mct_restore(mct_ctx *c, const void *buf, int64_t bytes) {
         if (nlog) HIP_TRY(c, hipMemcpyAsync(sp.prm.log, p, sizeof(LogRec) * nlog, hipMemcpyHostToDevice, c->stream));
         p += sizeof(LogRec) * nlog;
     }
+    if (c->screen_alloc) {  // the screen starts afresh from a restored state
+        const mct::ScreenDev &sd = c->sd;
+        const int64_t ne = c->specs[0].ne;
+        HIP_TRY(c, mct::launch_fill_u32(reinterpret_cast<uint32_t *>(sd.hist_t), 4 * ne, 0xFFFFFFFEu, c->stream));
+        HIP_TRY(c, hipMemsetAsync(sd.screen, 0, sizeof(uint32_t) * ne, c->stream));
+        HIP_TRY(c, hipMemsetAsync(sd.sweep, 0, sizeof(int32_t), c->stream));
+        HIP_TRY(c, hipMemsetAsync(sd.stats, 0, sizeof(unsigned long long) * 4, c->stream));
+    }
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->steps_enqueued = hs[0].base;
     return MCT_OK;
@@ -1194,19 +1199,27 @@ int mct_screen_collect(mct_ctx *c, int64_t cap, float *features, int32_t *elem, 
     c->screen_on = on;
     HIP_TRY(c, e);
     int32_t n = 0;
-    HIP_TRY(c, hipMemcpyAsync(&n, c->sd.ncand, sizeof n, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(&n, c->sd.nrows_last, sizeof n, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     *count = n;
     if (n > cap) return fail(c, MCT_ECAPACITY, "%d candidates, capacity %lld", n, (long long)cap);
     if (n == 0) return MCT_OK;
     std::vector<int32_t> packed(n);
+    std::vector<float> rows((size_t)mct::kFeat * n);
     HIP_TRY(c, hipMemcpyAsync(packed.data(), c->sd.cand, sizeof(int32_t) * n, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(features, c->sd.feat, sizeof(float) * mct::kFeat * n, hipMemcpyDeviceToHost,
+    HIP_TRY(c, hipMemcpyAsync(rows.data(), c->sd.feat, sizeof(float) * rows.size(), hipMemcpyDeviceToHost,
                               c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    // rows come in any order: return them by element, then local edge
+    std::vector<int32_t> ord(n);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return packed[a] < packed[b]; });
     for (int32_t i = 0; i < n; ++i) {
-        elem[i] = packed[i] >> 2;
-        entry[i] = (uint8_t)(packed[i] & 3);
+        const int32_t r = ord[i];
+        elem[i] = packed[r] >> 2;
+        entry[i] = (uint8_t)(packed[r] & 3);
+        std::copy(rows.begin() + (size_t)mct::kFeat * r, rows.begin() + (size_t)mct::kFeat * (r + 1),
+                  features + (size_t)mct::kFeat * i);
     }
     return MCT_OK;
 }
@@ -1338,7 +1351,7 @@ int mct_mlp_forward(mct_mlp *m, const float *x, int64_t n, float *logits) {
     if (!m) return MCT_EINVAL;
     if (n < 0 || (n > 0 && (!x || !logits))) return mfail(m, MCT_EINVAL, "bad rows or null pointer");
     if (n == 0) return MCT_OK;
-    MLP_TRY(m, mct::launch_mlp_forward(m->d, x, nullptr, n, logits, m->stream));
+    MLP_TRY(m, mct::launch_mlp_forward(m->d, x, nullptr, n, logits, nullptr, nullptr, 0.0f, nullptr, m->stream));
     return MCT_OK;
 }
 

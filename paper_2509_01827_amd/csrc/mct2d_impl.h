@@ -123,28 +123,29 @@ struct MlpDev {
 
 // Device buffers of a model's screen.
 struct ScreenDev {
-    int32_t *ncand;         // candidate count of the last enumeration
-    int32_t *cand;          // packed e * 4 + a, element order (capacity 4 ne)
-    int32_t *block_counts;  // enumeration scan scratch
-    float *feat;            // kFeat per candidate
-    float *logits;          // one per candidate
+    int32_t *nrows;         // candidate rows appended by the running evaluation
+    int32_t *nrows_last;    // row count of the last completed evaluation
+    int32_t *cand;          // packed e * 4 + a per row (capacity 4 ne), any order
+    float *feat;            // kFeat per row
+    double *row_geo;        // per row: midpoint x, y of edge a and h (for feature 5)
+    float *logits;          // one per row
     double *hist_g;         // per (e, a): max path G / Gc at its last evaluation
     int32_t *hist_t;        // per (e, a): sweep index of that evaluation
     int32_t *sweep;         // sweeps done
     uint32_t *screen;       // per element, one state byte per local edge
-    int32_t *tip_counts, *ntips, *tip_edge;
-    double *tip_xy;
+    int32_t *nfront;        // crack-path ends of the running evaluation
+    double *front_xy;       // their midpoints (capacity 2 ne)
     unsigned long long *stats;  // ScreenStat counters
 };
 
-int cand_nblocks(int64_t ne);
-hipError_t launch_screen_candidates(const StepParams &p, const ScreenDev &s, hipStream_t st);
-hipError_t launch_screen_features(const StepParams &p, const ScreenDev &s, int par, hipStream_t st);
+hipError_t launch_screen_evaluate(const StepParams &p, const ScreenDev &s, int par, hipStream_t st);
 hipError_t launch_sweep_advance(const ScreenDev &s, hipStream_t st);
-hipError_t launch_screen_apply(const StepParams &p, const ScreenDev &s, float tau, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *a, int64_t n, uint32_t v, hipStream_t st);
 hipError_t launch_mlp_prep(const MlpDev &m, hipStream_t st);
+// logits of n rows (n_dev: device count, else n); with `screen` set, also
+// the screen state byte of each row's candidate (flagged when logit > tau)
 hipError_t launch_mlp_forward(const MlpDev &m, const float *x, const int32_t *n_dev, int64_t n, float *logits,
+                              const int32_t *cand, uint32_t *screen, float tau, unsigned long long *stats,
                               hipStream_t st);
 int mlp_train_blocks(int64_t n);
 hipError_t launch_mlp_gradient(const MlpDev &m, const float *x, const float *y, int64_t n, float pos_weight,

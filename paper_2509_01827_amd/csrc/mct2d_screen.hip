@@ -8,11 +8,12 @@
 // kernel evaluates G only for candidates scored above a threshold or created
 // since.  The pick of every step stays the MCT pick over the evaluated set.
 //
-//   k_cand_count / k_cand_scan / k_cand_write   candidate list (element order)
-//   k_features                                  10 features per candidate
-//   k_mlp_fwd                                   logits, 32 rows per wavefront
-//   k_screen_apply                              per-candidate screen state
-//   k_mlp_train, k_grad_reduce, k_adam          training (gradient + Adam)
+//   k_front        crack-path ends (midpoints)
+//   k_features     per element: screen state reset, candidate rows with
+//                  their 10 features
+//   k_mlp_fwd      logits, 32 rows per wavefront, and the screen state of
+//                  each row's candidate
+//   k_mlp_train, k_grad_reduce, k_adam    training (gradient + Adam)
 #include <algorithm>
 
 #include "mct2d_device.h"
@@ -41,73 +42,6 @@ __device__ __forceinline__ unsigned cand_mask(const StepParams &p, int64_t e) {
     if (j == p.ny - 1 || p.split[e + p.nx] != 0) m |= 4u;
     if (i == 0 || p.split[e - 1] != 0) m |= 8u;
     return m;
-}
-
-// inclusive prefix sum over the wavefront
-__device__ __forceinline__ int wave_scan(int v) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int t = __shfl_up(v, off, 64);
-        if (lane >= off) v += t;
-    }
-    return v;
-}
-
-__global__ __launch_bounds__(kBlk) void k_cand_count(StepParams p, int32_t *counts) {
-    __shared__ int s_w[kBlk / 64];
-    const int64_t ne = (int64_t)p.nx * p.ny;
-    const int64_t e = (int64_t)blockIdx.x * kBlk + threadIdx.x;
-    const int c = (e < ne) ? __popc(cand_mask(p, e)) : 0;
-    const int inc = wave_scan(c);
-    if ((threadIdx.x & 63) == 63) s_w[threadIdx.x >> 6] = inc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int t = 0;
-        for (int w = 0; w < kBlk / 64; ++w) t += s_w[w];
-        counts[blockIdx.x] = t;
-    }
-}
-
-// exclusive scan of the block counts in place (one workgroup), total out
-__global__ __launch_bounds__(1024) void k_cand_scan(int32_t *counts, int nblocks, int32_t *total) {
-    __shared__ int s_v[1024];
-    __shared__ int s_carry;
-    if (threadIdx.x == 0) s_carry = 0;
-    __syncthreads();
-    for (int base = 0; base < nblocks; base += 1024) {
-        const int i = base + threadIdx.x;
-        const int v = (i < nblocks) ? counts[i] : 0;
-        s_v[threadIdx.x] = v;
-        __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
-            const int t = (threadIdx.x >= off) ? s_v[threadIdx.x - off] : 0;
-            __syncthreads();
-            s_v[threadIdx.x] += t;
-            __syncthreads();
-        }
-        if (i < nblocks) counts[i] = s_carry + s_v[threadIdx.x] - v;
-        __syncthreads();
-        if (threadIdx.x == 0) s_carry += s_v[1023];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *total = s_carry;
-}
-
-__global__ __launch_bounds__(kBlk) void k_cand_write(StepParams p, const int32_t *offsets, int32_t *cand) {
-    __shared__ int s_w[kBlk / 64];
-    const int64_t ne = (int64_t)p.nx * p.ny;
-    const int64_t e = (int64_t)blockIdx.x * kBlk + threadIdx.x;
-    const unsigned m = (e < ne) ? cand_mask(p, e) : 0u;
-    const int c = __popc(m);
-    const int inc = wave_scan(c);
-    const int wave = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 63) s_w[wave] = inc;
-    __syncthreads();
-    int off = offsets[blockIdx.x] + inc - c;
-    for (int w = 0; w < wave; ++w) off += s_w[w];
-    for (int k = 0; k < 4; ++k)
-        if ((m >> k) & 1u) cand[off++] = (int32_t)(e * 4 + k);
 }
 
 // ---------------------------------------------------------------- features
@@ -142,17 +76,14 @@ __device__ __forceinline__ int64_t neighbour(const StepParams &p, int64_t e, int
 // Smoothed stress of local edge k of intact element e: the edge strain
 // eps = w_hi (B u)_hi + w_lo (B u)_lo over the intact neighbours of the edge
 // (lower element id first, w_j = A_j / (A_lo + A_hi)), then plane stress.
-__device__ void edge_stress(const StepParams &p, const double *ux, const double *uy, int64_t e,
-                            const ElemData &d, int k, double sg[3]) {
+__device__ __forceinline__ void edge_stress(const StepParams &p, int64_t e, const ElemData &d, int k, int64_t nb,
+                                            bool nb_intact, const ElemData &dn, double sg[3]) {
     double gx[4], gy[4], qf[3], eps[3];
-    q4_grad_rt(d.x, d.y, k, gx, gy);
+    q4_grad(d.x, d.y, k, gx, gy);
     strain<4>(gx, gy, d.ux, d.uy, qf);
-    const int64_t nb = neighbour(p, e, k);
-    if (nb >= 0 && p.split[nb] == 0) {
-        ElemData dn;
-        load_elem(p, ux, uy, nb, dn);
+    if (nb_intact) {
         double qn[3];
-        q4_grad_rt(dn.x, dn.y, (k + 2) & 3, gx, gy);
+        q4_grad(dn.x, dn.y, (k + 2) & 3, gx, gy);
         strain<4>(gx, gy, dn.ux, dn.uy, qn);
         const double Af = p.area[e], An = p.area[nb];
         if (k == 1 || k == 2) {  // e has the lower id
@@ -173,27 +104,61 @@ __device__ void edge_stress(const StepParams &p, const double *ux, const double 
 
 constexpr double kTipCap = 64.0;
 
-// Ten features of candidate (e, a) (principal stresses and energy density of
-// the element's mean edge stress, G / Gc now and at the previous sweep, tip
-// distance, neighbour flags), see the model description in the header.
+// Crack-path ends: entry or exit edge of a split element whose neighbour
+// across it is intact; appended in any order (only the nearest matters).
+__global__ __launch_bounds__(kBlk) void k_front(StepParams p, ScreenDev s) {
+    const int64_t ne = (int64_t)p.nx * p.ny;
+    for (int64_t e = (int64_t)blockIdx.x * kBlk + threadIdx.x; e < ne; e += (int64_t)gridDim.x * kBlk) {
+        const uint8_t c = p.split[e];
+        if (c == 0) continue;
+        const int ks[2] = {(c >> 2) & 3, c & 3};
+        for (int q = 0; q < 2; ++q) {
+            const int k = ks[q];
+            const int64_t nb = neighbour(p, e, k);
+            if (nb < 0 || p.split[nb] != 0) continue;
+            const int64_t i = e % p.nx, j = e / p.nx;
+            const int64_t n0 = j * (p.nx + 1) + i;
+            const int64_t nd[4] = {n0, n0 + 1, n0 + p.nx + 2, n0 + p.nx + 1};
+            const int64_t a0 = nd[k], a1 = nd[(k + 1) & 3];
+            const int idx = atomicAdd(s.nfront, 1);
+            s.front_xy[2 * idx] = 0.5 * (p.X[a0] + p.X[a1]);
+            s.front_xy[2 * idx + 1] = 0.5 * (p.Y[a0] + p.Y[a1]);
+        }
+    }
+}
+
+// One thread per element: clears the element's screen state and, for an
+// element with candidates, appends one row per candidate (e, a) with its
+// ten features (principal stresses and energy density of the element's mean
+// edge stress, G / Gc now and at the previous sweep, distance to the nearest
+// crack-path end, neighbour flags; definitions in the C header).
 __global__ __launch_bounds__(kBlk) void k_features(StepParams p, ScreenDev s, const double *ux,
                                                    const double *uy) {
-    const int n = *s.ncand;
+    const int64_t ne = (int64_t)p.nx * p.ny;
     const int sweep = *s.sweep;
-    const int ntips = *s.ntips;
     const double nu = p.D12 / p.D11;
-    for (int c = blockIdx.x * kBlk + threadIdx.x; c < n; c += gridDim.x * kBlk) {
-        const int64_t e = s.cand[c] >> 2;
-        const int a = s.cand[c] & 3;
-        ElemData d;
+    for (int64_t e = (int64_t)blockIdx.x * kBlk + threadIdx.x; e < ne; e += (int64_t)gridDim.x * kBlk) {
+        const uint32_t w_old = s.screen[e];
+        if (w_old) s.screen[e] = 0u;
+        const unsigned mask = cand_mask(p, e);
+        if (!mask) continue;
+        // the element and its four neighbours, all loads issued together
+        ElemData d, dn[4];
+        int64_t nbs[4];
+        bool nbi[4];
         load_elem(p, ux, uy, e, d);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            nbs[k] = neighbour(p, e, k);
+            nbi[k] = nbs[k] >= 0 && p.split[nbs[k]] == 0;
+            load_elem(p, ux, uy, nbi[k] ? nbs[k] : e, dn[k]);
+        }
         double sig[4][3];
-        for (int k = 0; k < 4; ++k) edge_stress(p, ux, uy, e, d, k, sig[k]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) edge_stress(p, e, d, k, nbs[k], nbi[k], dn[k], sig[k]);
         double sm[3];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) sm[q] = (((0.0 + sig[0][q]) + sig[1][q]) + sig[2][q]) + sig[3][q];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) sm[q] = sm[q] / 4.0;
+        for (int q = 0; q < 3; ++q) sm[q] = ((((0.0 + sig[0][q]) + sig[1][q]) + sig[2][q]) + sig[3][q]) / 4.0;
         const double cc = 0.5 * (sm[0] + sm[1]);
         const double hd = 0.5 * (sm[0] - sm[1]);
         const double rr = sqrt(hd * hd + sm[2] * sm[2]);
@@ -201,87 +166,114 @@ __global__ __launch_bounds__(kBlk) void k_features(StepParams p, ScreenDev s, co
         const double eyy = (sm[1] - nu * sm[0]) / p.E;
         const double gxy = 2.0 * (1.0 + nu) * sm[2] / p.E;
         const double Wd = 0.5 * (sm[0] * exx + sm[1] * eyy + sm[2] * gxy);
-        // G of the three paths (zero when the edge is not stretched)
-        const int a1 = (a + 1) & 3;
-        const double dux = d.ux[a1] - d.ux[a], duy = d.uy[a1] - d.uy[a];
-        const double x1 = d.x[a] + d.ux[a], y1 = d.y[a] + d.uy[a];
-        const double x2 = d.x[a1] + d.ux[a1], y2 = d.y[a1] + d.uy[a1];
-        const double lx = x2 - x1, ly = y2 - y1;
-        const double Lx = d.x[a1] - d.x[a], Ly = d.y[a1] - d.y[a];
-        const bool H = (lx * lx + ly * ly) > (Lx * Lx + Ly * Ly);
-        double gmax = 0.0;
-        if (H) {
-            for (int j = 0; j < 3; ++j) {
-                const int k = (a + 1 + j) & 3;
-                double cx, cy, len;
-                path_geom(d.x, d.y, a, k, cx, cy, len);
-                const double spx = fma(sig[k][2], cy, sig[k][0] * cx);
-                const double spy = fma(sig[k][1], cy, sig[k][2] * cx);
-                const double G = 0.5 * fma(duy, spy, dux * spx);
-                if (j == 0 || G > gmax) gmax = G;
-            }
-        }
         const double gc = p.gc ? p.gc[e] : p.gc_uniform;
         const double h = sqrt(p.area[e]);
         const double sref = sqrt(p.E * gc / h);
-        const double g_now = gmax / gc;
-        const int64_t hk = e * 4 + a;
-        const double g_prev = (s.hist_t[hk] == sweep - 1) ? s.hist_g[hk] : 0.0;
-        s.hist_g[hk] = g_now;
-        s.hist_t[hk] = sweep;
-        // nearest crack-surface tip from the midpoint of edge a
-        double fd = 1.0;
-        if (ntips > 0) {
-            const double mx = 0.5 * (d.x[a] + d.x[a1]), my = 0.5 * (d.y[a] + d.y[a1]);
-            double d2 = __builtin_inf();
-            for (int t = 0; t < ntips; ++t) {
-                const double dx = s.tip_xy[2 * t] - mx, dy = s.tip_xy[2 * t + 1] - my;
-                const double q = dx * dx + dy * dy;
-                if (q < d2) d2 = q;
+        float fl[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) fl[k] = nbi[k] ? 0.0f : 1.0f;
+        int row = atomicAdd(s.nrows, __popc(mask));
+        for (int a = 0; a < 4; ++a) {
+            if (!((mask >> a) & 1u)) continue;
+            // G of the three paths (zero when edge a is not stretched)
+            const int a1 = (a + 1) & 3;
+            const double dux = d.ux[a1] - d.ux[a], duy = d.uy[a1] - d.uy[a];
+            const double x1 = d.x[a] + d.ux[a], y1 = d.y[a] + d.uy[a];
+            const double x2 = d.x[a1] + d.ux[a1], y2 = d.y[a1] + d.uy[a1];
+            const double lx = x2 - x1, ly = y2 - y1;
+            const double Lx = d.x[a1] - d.x[a], Ly = d.y[a1] - d.y[a];
+            const bool H = (lx * lx + ly * ly) > (Lx * Lx + Ly * Ly);
+            double gmax = 0.0;
+            if (H) {
+                for (int j = 0; j < 3; ++j) {
+                    const int k = (a + 1 + j) & 3;
+                    double cx, cy, len;
+                    path_geom(d.x, d.y, a, k, cx, cy, len);
+                    const double spx = fma(sig[k][2], cy, sig[k][0] * cx);
+                    const double spy = fma(sig[k][1], cy, sig[k][2] * cx);
+                    const double G = 0.5 * fma(duy, spy, dux * spx);
+                    if (j == 0 || G > gmax) gmax = G;
+                }
             }
-            fd = fmin(sqrt(d2) / h, kTipCap) / kTipCap;
+            const double g_now = gmax / gc;
+            const int64_t hk = e * 4 + a;
+            const double g_prev = (s.hist_t[hk] == sweep - 1) ? s.hist_g[hk] : 0.0;
+            s.hist_g[hk] = g_now;
+            s.hist_t[hk] = sweep;
+            // feature 5 is filled in by k_front_distance from these
+            s.row_geo[3 * (int64_t)row] = 0.5 * (d.x[a] + d.x[a1]);
+            s.row_geo[3 * (int64_t)row + 1] = 0.5 * (d.y[a] + d.y[a1]);
+            s.row_geo[3 * (int64_t)row + 2] = h;
+            s.cand[row] = (int32_t)hk;
+            float *f = s.feat + (int64_t)row * kFeat;
+            f[0] = (float)((cc + rr) / sref);
+            f[1] = (float)((cc - rr) / sref);
+            f[2] = (float)(Wd * h / gc);
+            f[3] = (float)g_now;
+            f[4] = (float)g_prev;
+            f[5] = 1.0f;
+            f[6] = fl[0];
+            f[7] = fl[1];
+            f[8] = fl[2];
+            f[9] = fl[3];
+            ++row;
+            // a candidate the previous screen skipped although G > Gc now
+            if (((w_old >> (8 * a)) & 0xFFu) == kScreenSkip && g_now > 1.0)
+                atomicAdd(&s.stats[kStatMisses], 1ull);
         }
-        float *f = s.feat + (int64_t)c * kFeat;
-        f[0] = (float)((cc + rr) / sref);
-        f[1] = (float)((cc - rr) / sref);
-        f[2] = (float)(Wd * h / gc);
-        f[3] = (float)g_now;
-        f[4] = (float)g_prev;
-        f[5] = (float)fd;
-        for (int k = 0; k < 4; ++k) {
-            const int64_t nb = neighbour(p, e, k);
-            f[6 + k] = (nb < 0 || p.split[nb] != 0) ? 1.0f : 0.0f;
-        }
-        // a candidate the previous screen skipped although G > Gc now
-        const uint32_t w = s.screen[e];
-        if (((w >> (8 * a)) & 0xFFu) == kScreenSkip && g_now > 1.0)
-            atomicAdd(&s.stats[kStatMisses], 1ull);
     }
 }
 
+// Feature 5 of every row: distance from the row's edge midpoint to the
+// nearest crack-path end, over h, capped.  The ends are staged through LDS
+// in chunks shared by the workgroup's rows.
+constexpr int kFrontChunk = 512;
+
+__global__ __launch_bounds__(kBlk) void k_front_distance(ScreenDev s) {
+    __shared__ double s_xy[2 * kFrontChunk];
+    const int n = *s.nrows, nfront = *s.nfront;
+    if (nfront == 0) return;  // feature stays 1 (uniform over the grid)
+    for (int r0 = blockIdx.x * kBlk; r0 < n; r0 += gridDim.x * kBlk) {
+        const int r = r0 + threadIdx.x;
+        double mx = 0.0, my = 0.0;
+        if (r < n) {
+            mx = s.row_geo[3 * (int64_t)r];
+            my = s.row_geo[3 * (int64_t)r + 1];
+        }
+        double d2 = __builtin_inf();
+        for (int c0 = 0; c0 < nfront; c0 += kFrontChunk) {
+            const int cn = min(kFrontChunk, nfront - c0);
+            __syncthreads();
+            for (int i = threadIdx.x; i < 2 * cn; i += kBlk) s_xy[i] = s.front_xy[2 * (int64_t)c0 + i];
+            __syncthreads();
+            for (int t = 0; t < cn; ++t) {
+                const double dx = s_xy[2 * t] - mx, dy = s_xy[2 * t + 1] - my;
+                const double q = dx * dx + dy * dy;
+                d2 = (q < d2) ? q : d2;
+            }
+        }
+        if (r < n) {
+            const double h = s.row_geo[3 * (int64_t)r + 2];
+            s.feat[(int64_t)r * kFeat + 5] = (float)(fmin(sqrt(d2) / h, kTipCap) / kTipCap);
+        }
+    }
+}
+
+// Close an evaluation: count it, keep its row count, reset the counters.
 __global__ void k_sweep_advance(ScreenDev s) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const int n = *s.nrows;
         *s.sweep = *s.sweep + 1;
         s.stats[kStatSweeps] += 1ull;
-        s.stats[kStatCands] += (unsigned long long)*s.ncand;
+        s.stats[kStatCands] += (unsigned long long)n;
+        *s.nrows_last = n;
+        *s.nrows = 0;
+        *s.nfront = 0;
     }
 }
 
 __global__ __launch_bounds__(kBlk) void k_fill_u32(uint32_t *a, int64_t n, uint32_t v) {
     for (int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlk) a[i] = v;
-}
-
-// Screen state of each candidate from its logit; the state array was
-// cleared before (unseen), so only candidates write.
-__global__ __launch_bounds__(kBlk) void k_screen_apply(ScreenDev s, float tau) {
-    const int n = *s.ncand;
-    uint8_t *bytes = reinterpret_cast<uint8_t *>(s.screen);
-    for (int c = blockIdx.x * kBlk + threadIdx.x; c < n; c += gridDim.x * kBlk) {
-        const bool flag = s.logits[c] > tau;
-        bytes[s.cand[c]] = flag ? kScreenFlagged : kScreenSkip;
-        const uint64_t b = __ballot(flag);
-        if ((threadIdx.x & 63) == 0 && b) atomicAdd(&s.stats[kStatFlagged], (unsigned long long)__popcll(b));
-    }
 }
 
 // --------------------------------------------------------------------- MLP
@@ -308,8 +300,8 @@ __device__ __forceinline__ __bf16 to_bf(float v) { return (__bf16)v; }
 __device__ __forceinline__ float from_bf(__bf16 v) { return (float)v; }
 
 struct MlpShared {
-    __bf16 w1[kIn * kHidden];      // [k][n]
-    __bf16 w2[kHidden * kHidden];  // [m][n]
+    alignas(16) __bf16 w1[kIn * kHidden];      // [k][n]
+    alignas(16) __bf16 w2[kHidden * kHidden];  // [m][n]
     __bf16 w3[kHidden];
     float b1[kHidden], b2[kHidden];
     float b3;
@@ -319,11 +311,14 @@ struct MlpShared {
 };
 
 __device__ void load_weights(const MlpDev &m, MlpShared &sh) {
-    const __bf16 *w1 = reinterpret_cast<const __bf16 *>(m.w1b);
-    const __bf16 *w2 = reinterpret_cast<const __bf16 *>(m.w2b);
+    // 16-byte copies (8 bfloat16 each); the arrays are 256-byte aligned
+    const uint4 *w1 = reinterpret_cast<const uint4 *>(m.w1b);
+    const uint4 *w2 = reinterpret_cast<const uint4 *>(m.w2b);
+    uint4 *s1 = reinterpret_cast<uint4 *>(sh.w1);
+    uint4 *s2 = reinterpret_cast<uint4 *>(sh.w2);
+    for (int i = threadIdx.x; i < kIn * kHidden / 8; i += blockDim.x) s1[i] = w1[i];
+    for (int i = threadIdx.x; i < kHidden * kHidden / 8; i += blockDim.x) s2[i] = w2[i];
     const __bf16 *w3 = reinterpret_cast<const __bf16 *>(m.w3b);
-    for (int i = threadIdx.x; i < kIn * kHidden; i += blockDim.x) sh.w1[i] = w1[i];
-    for (int i = threadIdx.x; i < kHidden * kHidden; i += blockDim.x) sh.w2[i] = w2[i];
     for (int i = threadIdx.x; i < kHidden; i += blockDim.x) {
         sh.w3[i] = w3[i];
         sh.b1[i] = m.master[kOffB1 + i];
@@ -410,25 +405,40 @@ __device__ void forward_tile(MlpShared &sh, Fwd &f) {
 }
 
 __global__ __launch_bounds__(64) void k_mlp_fwd(MlpDev m, const float *X, const int32_t *n_dev, int64_t n_host,
-                                                float *logits) {
+                                                float *logits, const int32_t *cand, uint32_t *screen, float tau,
+                                                unsigned long long *stats) {
     __shared__ MlpShared sh;
     const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
     load_weights(m, sh);
     const int l = threadIdx.x, r16 = l & 15, rq = 4 * (l >> 4);
+    uint8_t *bytes = reinterpret_cast<uint8_t *>(screen);
     for (int64_t r0 = (int64_t)blockIdx.x * kRows; r0 < n; r0 += (int64_t)gridDim.x * kRows) {
         __syncthreads();  // weights loaded / previous tile consumed
         load_rows(X, r0, n, sh);
         __syncthreads();
         Fwd f;
         forward_tile(sh, f);
+        int flagged = 0;
         if (r16 == 0) {
 #pragma unroll
             for (int h = 0; h < 2; ++h)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int64_t r = r0 + 16 * h + rq + i;
-                    if (r < n) logits[r] = f.z3[h][i];
+                    if (r >= n) continue;
+                    const float z = f.z3[h][i];
+                    logits[r] = z;
+                    if (screen) {
+                        const bool flag = z > tau;
+                        bytes[cand[r]] = flag ? kScreenFlagged : kScreenSkip;
+                        flagged += flag;
+                    }
                 }
+        }
+        if (screen) {
+#pragma unroll
+            for (int off = 16; off < 64; off <<= 1) flagged += __shfl_xor(flagged, off, 64);
+            if (l == 0 && flagged) atomicAdd(&stats[kStatFlagged], (unsigned long long)flagged);
         }
     }
 }
@@ -628,26 +638,17 @@ __global__ __launch_bounds__(kBlk) void k_adam(MlpDev m, const float *grad, floa
     refresh_bf16(m, q);
 }
 
-constexpr int kFeatGrid = 512;
-
 }  // namespace
 
-int cand_nblocks(int64_t ne) { return (int)((ne + kBlk - 1) / kBlk); }
-
-hipError_t launch_screen_candidates(const StepParams &p, const ScreenDev &s, hipStream_t st) {
+hipError_t launch_screen_evaluate(const StepParams &p, const ScreenDev &s, int par, hipStream_t st) {
     (void)hipGetLastError();
-    const int nb = cand_nblocks((int64_t)p.nx * p.ny);
-    k_cand_count<<<nb, kBlk, 0, st>>>(p, s.block_counts);
-    k_cand_scan<<<1, 1024, 0, st>>>(s.block_counts, nb, s.ncand);
-    k_cand_write<<<nb, kBlk, 0, st>>>(p, s.block_counts, s.cand);
-    return hipGetLastError();
-}
-
-hipError_t launch_screen_features(const StepParams &p, const ScreenDev &s, int par, hipStream_t st) {
-    (void)hipGetLastError();
+    const int64_t ne = (int64_t)p.nx * p.ny;
+    const int nb = (int)std::min<int64_t>((ne + kBlk - 1) / kBlk, 2048);
     const double *ux = par ? p.ux1 : p.ux0;
     const double *uy = par ? p.uy1 : p.uy0;
-    k_features<<<kFeatGrid, kBlk, 0, st>>>(p, s, ux, uy);
+    k_front<<<nb, kBlk, 0, st>>>(p, s);
+    k_features<<<nb, kBlk, 0, st>>>(p, s, ux, uy);
+    k_front_distance<<<64, kBlk, 0, st>>>(s);
     return hipGetLastError();
 }
 
@@ -664,14 +665,6 @@ hipError_t launch_fill_u32(uint32_t *a, int64_t n, uint32_t v, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_screen_apply(const StepParams &p, const ScreenDev &s, float tau, hipStream_t st) {
-    (void)hipGetLastError();
-    hipError_t e = launch_fill_u32(s.screen, (int64_t)p.nx * p.ny, 0u, st);
-    if (e != hipSuccess) return e;
-    k_screen_apply<<<kFeatGrid, kBlk, 0, st>>>(s, tau);
-    return hipGetLastError();
-}
-
 hipError_t launch_mlp_prep(const MlpDev &m, hipStream_t st) {
     (void)hipGetLastError();
     k_mlp_prep<<<(kParams + kBlk - 1) / kBlk, kBlk, 0, st>>>(m);
@@ -679,11 +672,12 @@ hipError_t launch_mlp_prep(const MlpDev &m, hipStream_t st) {
 }
 
 hipError_t launch_mlp_forward(const MlpDev &m, const float *x, const int32_t *n_dev, int64_t n, float *logits,
+                              const int32_t *cand, uint32_t *screen, float tau, unsigned long long *stats,
                               hipStream_t st) {
     (void)hipGetLastError();
-    int grid = 1024;
+    int grid = 128;  // device-side row count: each workgroup strides over the tiles
     if (!n_dev) grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + kRows - 1) / kRows, 1024));
-    k_mlp_fwd<<<grid, 64, 0, st>>>(m, x, n_dev, n, logits);
+    k_mlp_fwd<<<grid, 64, 0, st>>>(m, x, n_dev, n, logits, cand, screen, tau, stats);
     return hipGetLastError();
 }
 

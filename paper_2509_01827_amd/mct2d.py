@@ -46,6 +46,18 @@ N_PARAMS = 4929
 _lib = None
 
 
+def _init_torch_first() -> None:
+    """torch brings its own HIP runtime libraries; when this library's HIP
+    runtime is loaded and used first, torch later finds no device.  So torch
+    initialises its GPU context before the library is loaded."""
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.is_available():
+        torch.cuda.init()
+
+
 def load() -> C.CDLL:
     """Load the HIP library; raises if it was not built."""
     global _lib
@@ -53,6 +65,7 @@ def load() -> C.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise MctError("libmct2d.so is not built (run python -m paper_2509_01827_amd.build)")
+    _init_torch_first()
     L = C.CDLL(LIB_PATH)
     P = C.c_void_p
     dp = np.ctypeslib.ndpointer(np.float64, flags="C")

@@ -167,16 +167,24 @@ def test_features_tips_flags_and_history(oracle_mod):
     _set_u(o, 1e-4 * X, 1e-4 * Y)
     elem, a, F, g1 = S.features(o, c)
     key = {(int(e), int(k)): r for r, (e, k) in enumerate(zip(elem, a))}
+    # path ends: the left and right edges of the split element (entry 3,
+    # exit 1), midpoints (5h, 2.5h) and (6h, 2.5h)
+    h = 1e-3
+    np.testing.assert_allclose(S.path_ends(nx, ny, c["X"], c["Y"], codes), [(5 * h, 2.5 * h), (6 * h, 2.5 * h)],
+                               rtol=1e-14)
     # the four neighbours of the split element see it across the facing edge
-    for (ni, nj, k) in ((i0, j0 - 1, 2), (i0 + 1, j0, 3), (i0, j0 + 1, 0), (i0 - 1, j0, 1)):
+    for (ni, nj, k, dist) in ((i0, j0 - 1, 2, math.sqrt(0.5)), (i0 + 1, j0, 3, 0.0),
+                              (i0, j0 + 1, 0, math.sqrt(0.5)), (i0 - 1, j0, 1, 0.0)):
         r = key[(nj * nx + ni, k)]
-        assert F[r, 5] == 0.0                   # the candidate edge is itself a tip
+        assert F[r, 5] == pytest.approx(dist / 64.0, rel=1e-12, abs=1e-15)
         assert F[r, 6 + k] == 1.0
-    # element 0, bottom edge midpoint (0.5h, 0); tips: the split element's
-    # edge midpoints (5.5h, 2h), (6h, 2.5h), (5.5h, 3h), (5h, 2.5h); nearest
-    # is the left one
+    # element 0, bottom edge midpoint (0.5h, 0); nearest end (5h, 2.5h)
     r = key[(0, 0)]
     assert F[r, 5] == pytest.approx(math.hypot(4.5, 2.5) / 64.0, rel=1e-12)
+    # a crack reaching the domain boundary has no end there
+    codes2 = np.zeros(nx * ny, np.uint8)
+    codes2[0] = 0x80 | (3 << 2) | 1            # element 0, left (boundary) -> right
+    assert len(S.path_ends(nx, ny, c["X"], c["Y"], codes2)) == 1
     # the previous-evaluation feature carries the last call's G / Gc
     _, _, F2, _ = S.features(o, c, g_prev=g1)
     np.testing.assert_array_equal(F2[:, 4], F[:, 3])
