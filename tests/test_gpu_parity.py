@@ -1,6 +1,6 @@
 """GPU parity: the HIP library through its C ABI against the CPU oracle.
 
-Bar (BASELINE the benchmark spec): identical crack topology (split log, split codes,
+Bar: identical crack topology (split log, split codes,
 tip list: bit-exact integers) and nodal fields within 1e-9 relative in FP64.
 Both codes follow one binary64 expression order, so the fields are expected
 to agree bit for bit; the test asserts the 1e-9 bar and records the bitwise
