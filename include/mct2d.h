@@ -60,10 +60,19 @@ enum {
     MCT_ECAPACITY = -3,  /* output capacity too small, *count holds the need */
     MCT_EDEVICE = -4,    /* HIP runtime or kernel launch failure */
     MCT_ENOMEM = -5,     /* device or host allocation failed */
-    MCT_EUNSUPPORTED = -6
+    MCT_EUNSUPPORTED = -6, /* precision 32, or the screen on a batch */
+    MCT_ESTABILITY = -7, /* dt above the stability limit of the explicit step */
+    MCT_ENUMERIC = -8    /* non-finite displacement or velocity */
 };
 
-enum { MCT_FIELD_U = 0, MCT_FIELD_V = 1 };
+enum {
+    MCT_FIELD_U = 0,
+    MCT_FIELD_V = 1,
+    MCT_FIELD_A = 2,
+    MCT_FIELD_FINT = 3,
+    MCT_FIELD_SIGMA_EDGE = 4,
+    MCT_FIELD_PRINCIPAL = 5
+};
 
 typedef struct mct_ctx mct_ctx;
 
@@ -75,6 +84,7 @@ typedef struct {
     double dissipated;   /* U_d = sum over splits of Gc * crack-path length */
     int32_t log_overflow;/* 1 if more splits happened than the log can hold */
     int32_t precision;
+    double dt_limit;     /* stability limit 2 / omega_max of the set-up mesh */
 } mct_info;
 
 /* Create an empty context.  precision: 64 (binary64 state and arithmetic).
@@ -125,15 +135,23 @@ int mct_set_notch(mct_ctx *ctx, int64_t n, const int32_t *elem, const uint8_t *e
 int mct_set_time(mct_ctx *ctx, double dt, double cfl_fraction);
 
 /* Build the derived arrays (lumped mass, equivalent nodal forces, time
- * step), upload everything and zero the state (u = v = 0, step 0).  Errors: MCT_ESTATE if mesh or material is missing,
- * MCT_ENOMEM / MCT_EDEVICE on device failures. */
+ * step), upload everything and zero the state (u = v = 0, step 0).  Then
+ * estimate the stability limit of central differences, 2 / omega_max with
+ * omega_max^2 the largest eigenvalue of M^-1 K over the free components
+ * (power iteration on the GPU with the set-up split state; the estimate
+ * approaches omega_max from below, so the limit is an upper estimate;
+ * reported in mct_info.dt_limit).  Errors: MCT_ESTATE if mesh or material is
+ * missing, MCT_ESTABILITY if dt exceeds the limit, MCT_ENOMEM /
+ * MCT_EDEVICE on device failures. */
 int mct_finalize(mct_ctx *ctx);
 
 /* Enqueue n_steps time steps; asynchronous.  Each step splits at most one
  * element (the MCT pick) and the split acts from the next step on. */
 int mct_step(mct_ctx *ctx, int64_t n_steps);
 
-/* Wait for the enqueued work; reports asynchronous device errors. */
+/* Wait for the enqueued work; reports asynchronous device errors, and
+ * MCT_ENUMERIC if any displacement or velocity of the current step is not
+ * finite. */
 int mct_sync(mct_ctx *ctx);
 
 int mct_get_info(mct_ctx *ctx, mct_info *out);
@@ -149,10 +167,28 @@ int mct_get_crack_set(mct_ctx *ctx, int64_t cap, int32_t *step, int32_t *elem, u
  * id; xy = reference midpoint (2 per tip).  Computed on the GPU. */
 int mct_get_tips(mct_ctx *ctx, int64_t cap, int32_t *edge, double *xy, int64_t *count);
 
-/* Nodal field at the current step: MCT_FIELD_U (u^k) or MCT_FIELD_V
- * (v^{k-1/2}, v^0 at k = 0), written as [x of all nodes, y of all nodes]
- * (2 n_nodes values). */
+/* Field of the current step k (evaluated on the GPU from u^k):
+ *   MCT_FIELD_U          u^k, [x of all nodes, y of all nodes] (2 n_nodes);
+ *   MCT_FIELD_V          v^{k-1/2} (v^0 at k = 0), same layout;
+ *   MCT_FIELD_A          a^k = (f_ext - f_int(u^k)) / m, prescribed
+ *                        components 0, same layout;
+ *   MCT_FIELD_FINT       f_int(u^k) (Eqs. QUAD_fint_discretization and the
+ *                        split pieces, summed in colour order), same layout;
+ *   MCT_FIELD_SIGMA_EDGE smoothed plane stress of every edge (Sec. 2.1),
+ *                        [sxx of all edges, syy ..., sxy ...] (3 n_edges),
+ *                        NaN where the edge has no intact neighbour;
+ *   MCT_FIELD_PRINCIPAL  per element, the maximum principal stress of the
+ *                        mean of its four edge stresses (the stress fields
+ *                        of Sec. 4), NaN for split elements (n_elems). */
 int mct_get_field(mct_ctx *ctx, int which, int64_t cap, double *out);
+
+/* Energies at t_k (J/m): [0] kinetic sum m |v^k|^2 / 2 with
+ * v^k = v^{k-1/2} + dt a^k / 2 for free components after the first step;
+ * [1] strain: edge smoothing domains (area sum of intact A_j / 4) times
+ * sigma:eps / 2 plus the split pieces; [2] external work f_ext . u^k
+ * (constant tractions); [3] dissipated U_d.  Sums are FP64, deterministic
+ * run to run. */
+int mct_get_energies(mct_ctx *ctx, double out[4]);
 
 /* Crack-path geometry of n elements (Sec. 2.2, Fig. 2-3: the three paths
  * from the midpoint G0 of tip edge a to the midpoints Gk of the other edges)

@@ -14,7 +14,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "libmct2d.so")
 SOURCES = [os.path.join(CSRC, "mct2d_api.cpp"), os.path.join(CSRC, "mct2d_step.hip"),
-           os.path.join(CSRC, "mct2d_screen.hip")]
+           os.path.join(CSRC, "mct2d_screen.hip"), os.path.join(CSRC, "mct2d_state.hip")]
 HEADERS = [os.path.join(CSRC, "mct2d_impl.h"), os.path.join(CSRC, "mct2d_device.h"),
            os.path.join(ROOT, "include", "mct2d.h")]
 

@@ -54,6 +54,7 @@ struct Spec {
     double dt_in = 0, cfl = 0.5;
     // derived
     double dt = 0;
+    double dt_limit = 0;  // 2 / omega_max of the set-up mesh (power iteration)
     int64_t nn = 0, ne = 0, ns = 0, np = 0;
     int64_t node_off = 0, elem_off = 0, perim_off = 0, tile_base = 0;
     StepParams prm{};
@@ -93,6 +94,12 @@ struct mct_ctx {
     hipGraphExec_t graph[2] = {nullptr, nullptr};  // by parity of the first step
     int graph_tile[2] = {0, 0};
     int64_t steps_enqueued = 0;  // host view of the step counter
+
+    // state queries
+    bool ev_alloc = false;
+    mct::EvalDev ev{};
+    double *dpow = nullptr;    // power iteration: y, u, z, scratch (2 nn_max each)
+    int32_t *dflag = nullptr;  // non-finite watchdog
 
     // learned split-screen (plain contexts only)
     bool screen_alloc = false, screen_on = false;
@@ -157,6 +164,22 @@ void free_mlp(mct::MlpDev &m) {
     dfree(m.w3b);
 }
 
+void free_eval(mct_ctx *c) {
+    mct::EvalDev &d = c->ev;
+    dfree(d.sig);
+    dfree(d.es);
+    dfree(d.fe);
+    dfree(d.pe);
+    dfree(d.fint);
+    dfree(d.acc);
+    dfree(d.node_e);
+    dfree(d.part);
+    dfree(d.sums);
+    dfree(c->dpow);
+    dfree(c->dflag);
+    c->ev_alloc = false;
+}
+
 void free_screen(mct_ctx *c) {
     mct::ScreenDev &s = c->sd;
     dfree(s.nrows);
@@ -203,6 +226,7 @@ void release_device(mct_ctx *c) {
     dfree(c->dtip_counts);
     dfree(c->dtip_total);
     free_screen(c);
+    free_eval(c);
     c->finalized = false;
 }
 
@@ -472,6 +496,77 @@ int step_screened(mct_ctx *c, int64_t n) {
         left -= seg;
         c->steps_enqueued += seg;
     }
+    return MCT_OK;
+}
+
+// ---------------------------------------------------------------------
+// State queries: evaluation buffers, the stability limit.
+
+int ensure_eval(mct_ctx *c) {
+    if (c->ev_alloc) return MCT_OK;
+    int64_t nn = 0, ne = 0, ns = 0;
+    for (const Spec &s : c->specs) {
+        nn = std::max(nn, s.nn);
+        ne = std::max(ne, s.ne);
+        ns = std::max(ns, s.ns);
+    }
+    mct::EvalDev &d = c->ev;
+    HIP_TRY(c, hipMalloc((void **)&d.sig, sizeof(double) * 3 * ns));
+    HIP_TRY(c, hipMalloc((void **)&d.es, sizeof(double) * ns));
+    HIP_TRY(c, hipMalloc((void **)&d.fe, sizeof(double) * 8 * ne));
+    HIP_TRY(c, hipMalloc((void **)&d.pe, sizeof(double) * ne));
+    HIP_TRY(c, hipMalloc((void **)&d.fint, sizeof(double) * 2 * nn));
+    HIP_TRY(c, hipMalloc((void **)&d.acc, sizeof(double) * 2 * nn));
+    HIP_TRY(c, hipMalloc((void **)&d.node_e, sizeof(double) * 2 * nn));
+    HIP_TRY(c, hipMalloc((void **)&d.part, sizeof(double) * mct::eval_partials()));
+    HIP_TRY(c, hipMalloc((void **)&d.sums, sizeof(double) * 8));
+    HIP_TRY(c, hipMalloc((void **)&c->dpow, sizeof(double) * 8 * nn));
+    HIP_TRY(c, hipMalloc((void **)&c->dflag, sizeof(int32_t)));
+    c->ev_alloc = true;
+    return MCT_OK;
+}
+
+// Largest eigenvalue of M^-1 K over the free components by power iteration
+// on M^-1/2 K M^-1/2 (K u = internal force of u, split elements as set up),
+// started from the alternating pattern that the highest mode of a grid
+// resembles plus a small deterministic perturbation.  The Rayleigh quotient
+// approaches lambda_max from below, so 2 / sqrt(lambda) is an upper estimate
+// of the stability limit of central differences.
+int stability_limit(mct_ctx *c, Spec &s) {
+    int rc = ensure_eval(c);
+    if (rc) return rc;
+    const int64_t nn = s.nn;
+    std::vector<double> y(2 * nn);
+    double norm = 0.0;
+    uint64_t h = 0x9E3779B97F4A7C15ull;
+    for (int j = 0; j <= s.ny; ++j)
+        for (int i = 0; i <= s.nx; ++i) {
+            const int64_t g = node_of(s, i, j);
+            h ^= h >> 33;
+            h *= 0xFF51AFD7ED558CCDull;
+            const double r = (double)(h >> 11) * 0x1.0p-53;
+            const double sgn = ((i + j) & 1) ? -1.0 : 1.0;
+            y[g] = sgn * (1.0 + 0.05 * r);
+            y[nn + g] = -sgn * (1.0 + 0.05 * (1.0 - r));
+            norm += y[g] * y[g] + y[nn + g] * y[nn + g];
+        }
+    norm = std::sqrt(norm);
+    for (double &v : y) v /= norm;
+    double *dy = c->dpow, *du = c->dpow + 2 * nn, *dz = c->dpow + 4 * nn, *dw = c->dpow + 6 * nn;
+    HIP_TRY(c, hipMemcpyAsync(dy, y.data(), sizeof(double) * 2 * nn, hipMemcpyHostToDevice, c->stream));
+    double lam = 0.0, prev = 0.0;
+    for (int it = 1; it <= 2000; ++it) {
+        HIP_TRY(c, mct::launch_power_step(s.prm, c->ev, dy, du, dz, dw, c->ev.sums, c->stream));
+        if (it % 20 == 0) {
+            HIP_TRY(c, hipMemcpyAsync(&lam, c->ev.sums, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            if (!(lam > 0.0) || !std::isfinite(lam))
+                return fail(c, MCT_ENUMERIC, "stability estimate failed (Rayleigh quotient %g)", lam);
+            if (std::fabs(lam - prev) <= 1e-7 * lam) break;
+            prev = lam;
+        }
+    }
+    s.dt_limit = 2.0 / std::sqrt(lam);
     return MCT_OK;
 }
 
@@ -834,6 +929,18 @@ int mct_finalize(mct_ctx *c) {
         return rc;
     }
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (size_t q = 0; q < c->specs.size(); ++q) {
+        Spec &sp = c->specs[q];
+        if ((rc = stability_limit(c, sp))) {
+            c->finalized = false;
+            return rc;
+        }
+        if (sp.dt > sp.dt_limit) {
+            c->finalized = false;
+            return fail(c, MCT_ESTABILITY, "specimen %zu: dt = %g exceeds the stability limit 2/omega_max = %g", q,
+                        sp.dt, sp.dt_limit);
+        }
+    }
     c->steps_enqueued = 0;
     return MCT_OK;
 }
@@ -871,6 +978,22 @@ int mct_step(mct_ctx *c, int64_t n) {
 
 int mct_sync(mct_ctx *c) {
     if (!c) return MCT_EINVAL;
+    if (c->finalized) {
+        // watchdog: every displacement and velocity of the current step finite
+        int rc = ensure_eval(c);
+        if (rc) return rc;
+        int64_t nn = 0;
+        for (const Spec &s : c->specs) nn += s.nn;
+        const int par = (int)(c->steps_enqueued & 1);
+        int32_t flag = 0;
+        HIP_TRY(c, hipMemsetAsync(c->dflag, 0, sizeof(int32_t), c->stream));
+        HIP_TRY(c, mct::launch_check_finite(c->dux[par], c->duy[par], c->dvx, c->dvy, nn, c->dflag, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(&flag, c->dflag, sizeof flag, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        if (flag) return fail(c, MCT_ENUMERIC, "non-finite displacement or velocity after step %lld",
+                              (long long)c->steps_enqueued);
+        return MCT_OK;
+    }
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return MCT_OK;
 }
@@ -883,6 +1006,7 @@ int mct_get_info(mct_ctx *c, mct_info *out) {
     out->n_elems = s.ne;
     out->n_edges = s.ns;
     out->dt = s.dt;
+    out->dt_limit = s.dt_limit;
     out->precision = c->precision;
     if (!c->finalized) return MCT_OK;
     Control h;
@@ -957,23 +1081,70 @@ int mct_get_field(mct_ctx *c, int which, int64_t cap, double *out) {
     if (!c || !out) return MCT_EINVAL;
     if (!c->finalized) return fail(c, MCT_ESTATE, "finalize first");
     const Spec &s = cur(c);
-    if (cap < 2 * s.nn) return fail(c, MCT_ECAPACITY, "field needs %lld values", (long long)(2 * s.nn));
+    int64_t need;
+    switch (which) {
+        case MCT_FIELD_U: case MCT_FIELD_V: case MCT_FIELD_A: case MCT_FIELD_FINT: need = 2 * s.nn; break;
+        case MCT_FIELD_SIGMA_EDGE: need = 3 * s.ns; break;
+        case MCT_FIELD_PRINCIPAL: need = s.ne; break;
+        default: return fail(c, MCT_EINVAL, "unknown field %d", which);
+    }
+    if (cap < need) return fail(c, MCT_ECAPACITY, "field needs %lld values", (long long)need);
     Control h;
     int rc = read_control(c, c->sel, &h);
     if (rc) return rc;
+    if (which >= MCT_FIELD_A) {
+        if ((rc = ensure_eval(c))) return rc;
+        const double *ux = (h.base & 1) ? s.prm.ux1 : s.prm.ux0, *uy = (h.base & 1) ? s.prm.uy1 : s.prm.uy0;
+        HIP_TRY(c, mct::launch_eval(s.prm, ux, uy, s.prm.vx, s.prm.vy, h.base, c->ev, c->stream));
+        if (which == MCT_FIELD_A || which == MCT_FIELD_FINT) {
+            const double *src = which == MCT_FIELD_A ? c->ev.acc : c->ev.fint;
+            HIP_TRY(c, hipMemcpyAsync(out, src, sizeof(double) * 2 * s.nn, hipMemcpyDeviceToHost, c->stream));
+        } else if (which == MCT_FIELD_SIGMA_EDGE) {
+            std::vector<double> sg(3 * s.ns);
+            HIP_TRY(c, hipMemcpyAsync(sg.data(), c->ev.sig, sizeof(double) * 3 * s.ns, hipMemcpyDeviceToHost,
+                                      c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            for (int64_t e = 0; e < s.ns; ++e)
+                for (int q = 0; q < 3; ++q) out[q * s.ns + e] = sg[3 * e + q];
+        } else {
+            HIP_TRY(c, mct::launch_principal(s.prm, c->ev, c->ev.fe, c->stream));  // fe reused as output
+            HIP_TRY(c, hipMemcpyAsync(out, c->ev.fe, sizeof(double) * s.ne, hipMemcpyDeviceToHost, c->stream));
+        }
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        return MCT_OK;
+    }
     const double *sx, *sy;
     if (which == MCT_FIELD_U) {
         sx = (h.base & 1) ? s.prm.ux1 : s.prm.ux0;
         sy = (h.base & 1) ? s.prm.uy1 : s.prm.uy0;
-    } else if (which == MCT_FIELD_V) {
+    } else {
         sx = s.prm.vx;
         sy = s.prm.vy;
-    } else {
-        return fail(c, MCT_EINVAL, "unknown field %d", which);
     }
     HIP_TRY(c, hipMemcpyAsync(out, sx, sizeof(double) * s.nn, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipMemcpyAsync(out + s.nn, sy, sizeof(double) * s.nn, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return MCT_OK;
+}
+
+int mct_get_energies(mct_ctx *c, double out[4]) {
+    if (!c || !out) return MCT_EINVAL;
+    if (!c->finalized) return fail(c, MCT_ESTATE, "finalize first");
+    int rc = ensure_eval(c);
+    if (rc) return rc;
+    const Spec &s = cur(c);
+    Control h;
+    if ((rc = read_control(c, c->sel, &h))) return rc;
+    const double *ux = (h.base & 1) ? s.prm.ux1 : s.prm.ux0, *uy = (h.base & 1) ? s.prm.uy1 : s.prm.uy0;
+    HIP_TRY(c, mct::launch_eval(s.prm, ux, uy, s.prm.vx, s.prm.vy, h.base, c->ev, c->stream));
+    HIP_TRY(c, mct::launch_energies(s.prm, c->ev, c->ev.sums, c->stream));
+    double r[8];
+    HIP_TRY(c, hipMemcpyAsync(r, c->ev.sums, sizeof r, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    out[0] = r[0];
+    out[1] = r[3] + r[4];
+    out[2] = r[2];
+    out[3] = h.Ud;
     return MCT_OK;
 }
 

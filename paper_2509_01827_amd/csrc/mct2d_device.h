@@ -130,5 +130,57 @@ __device__ __forceinline__ void path_geom(const double x[4], const double y[4], 
     path_geom_pts(x[a], y[a], x[a1], y[a1], x[k], y[k], x[k1], y[k1], nxo, nyo, len);
 }
 
+
+// Edge s of the structured grid (ids in ascending (smaller node, larger
+// node) order): its nodes and its neighbour elements (e0 the lower id, -1
+// outside the mesh).
+struct EdgeInfo {
+    int lo, hi;    // node ids
+    int e0, e1;    // neighbour elements (-1 if none)
+};
+
+__device__ __forceinline__ EdgeInfo edge_info(int64_t s, int nx, int ny) {
+    EdgeInfo r;
+    const int64_t row = 2 * (int64_t)nx + 1;
+    int i, j;
+    bool horiz;
+    if (s < (int64_t)ny * row) {
+        j = (int)(s / row);
+        const int q = (int)(s % row);
+        if (q < 2 * nx) {
+            i = q >> 1;
+            horiz = (q & 1) == 0;
+        } else {
+            i = nx;
+            horiz = false;
+        }
+    } else {
+        j = ny;
+        i = (int)(s - (int64_t)ny * row);
+        horiz = true;
+    }
+    r.lo = j * (nx + 1) + i;
+    if (horiz) {
+        r.hi = r.lo + 1;
+        r.e0 = (j > 0) ? (j - 1) * nx + i : -1;
+        r.e1 = (j < ny) ? j * nx + i : -1;
+    } else {
+        r.hi = r.lo + nx + 1;
+        r.e0 = (i > 0) ? j * nx + i - 1 : -1;
+        r.e1 = (i < nx) ? j * nx + i : -1;
+    }
+    return r;
+}
+
+// Id of the horizontal edge starting at node (i, j) and of the vertical one.
+__device__ __forceinline__ int64_t edge_h(int64_t i, int64_t j, int nx, int ny) {
+    const int64_t row = 2 * (int64_t)nx + 1;
+    return j < ny ? j * row + 2 * i : (int64_t)ny * row + i;
+}
+__device__ __forceinline__ int64_t edge_v(int64_t i, int64_t j, int nx) {
+    const int64_t row = 2 * (int64_t)nx + 1;
+    return j * row + (i < nx ? 2 * i + 1 : 2 * (int64_t)nx);
+}
+
 }  // namespace dev
 }  // namespace mct

@@ -98,6 +98,31 @@ int tips_nblocks(int64_t n_edges);
 hipError_t launch_path_geometry(const StepParams &p, int n, const int32_t *elem, double *out, hipStream_t s);
 
 // ---------------------------------------------------------------------
+// State queries (fields, energies, stability limit, finiteness).
+
+struct EvalDev {
+    double *sig;     // 3 per edge (NaN without an intact neighbour)
+    double *es;      // per edge: strain energy of its smoothing domain
+    double *fe;      // 8 per element
+    double *pe;      // per element: strain energy of split pieces
+    double *fint;    // per node, x then y (2 nn)
+    double *acc;     // per node, x then y (2 nn)
+    double *node_e;  // per node: kinetic energy, external work
+    double *part;    // partial sums (eval_partials())
+    double *sums;    // 8 results: [0] kinetic, [2] external work, [3] edges, [4] pieces
+};
+
+int eval_partials();
+hipError_t launch_eval(const StepParams &p, const double *ux, const double *uy, const double *vx,
+                       const double *vy, int64_t step, const EvalDev &d, hipStream_t st);
+hipError_t launch_energies(const StepParams &p, const EvalDev &d, double *out, hipStream_t st);
+hipError_t launch_principal(const StepParams &p, const EvalDev &d, double *out, hipStream_t st);
+hipError_t launch_power_step(const StepParams &p, const EvalDev &d, double *y, double *u, double *z,
+                             double *scratch2, double *sums, hipStream_t st);
+hipError_t launch_check_finite(const double *a, const double *b, const double *c, const double *d, int64_t n,
+                               int32_t *flag, hipStream_t st);
+
+// ---------------------------------------------------------------------
 // Learned split-screen.
 
 constexpr int kFeat = 10;                 // features per candidate

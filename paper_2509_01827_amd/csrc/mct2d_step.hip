@@ -829,44 +829,6 @@ namespace {
 using namespace dev;
 constexpr int kTipBlock = 256;
 
-struct EdgeInfo {
-    int lo, hi;    // node ids
-    int e0, e1;    // neighbour elements (-1 if none)
-};
-
-__device__ __forceinline__ EdgeInfo edge_info(int64_t s, int nx, int ny) {
-    EdgeInfo r;
-    const int64_t row = 2 * (int64_t)nx + 1;
-    int i, j;
-    bool horiz;
-    if (s < (int64_t)ny * row) {
-        j = (int)(s / row);
-        const int q = (int)(s % row);
-        if (q < 2 * nx) {
-            i = q >> 1;
-            horiz = (q & 1) == 0;
-        } else {
-            i = nx;
-            horiz = false;
-        }
-    } else {
-        j = ny;
-        i = (int)(s - (int64_t)ny * row);
-        horiz = true;
-    }
-    r.lo = j * (nx + 1) + i;
-    if (horiz) {
-        r.hi = r.lo + 1;
-        r.e0 = (j > 0) ? (j - 1) * nx + i : -1;
-        r.e1 = (j < ny) ? j * nx + i : -1;
-    } else {
-        r.hi = r.lo + nx + 1;
-        r.e0 = (i > 0) ? j * nx + i - 1 : -1;
-        r.e1 = (i < nx) ? j * nx + i : -1;
-    }
-    return r;
-}
-
 __device__ __forceinline__ bool is_tip(const EdgeInfo &ei, const uint8_t *split) {
     if (ei.e0 < 0 || ei.e1 < 0) return false;
     return ((split[ei.e0] == 0) + (split[ei.e1] == 0)) == 1;

@@ -18,6 +18,12 @@ MCT_OK = 0
 MCT_ECAPACITY = -3
 FIELD_U = 0
 FIELD_V = 1
+FIELD_A = 2
+FIELD_FINT = 3
+FIELD_SIGMA_EDGE = 4
+FIELD_PRINCIPAL = 5
+MCT_ESTABILITY = -7
+MCT_ENUMERIC = -8
 
 
 class MctError(RuntimeError):
@@ -27,7 +33,8 @@ class MctError(RuntimeError):
 class Info(C.Structure):
     _fields_ = [("n_nodes", C.c_int64), ("n_elems", C.c_int64), ("n_edges", C.c_int64),
                 ("step", C.c_int64), ("n_splits", C.c_int64), ("dt", C.c_double),
-                ("dissipated", C.c_double), ("log_overflow", C.c_int32), ("precision", C.c_int32)]
+                ("dissipated", C.c_double), ("log_overflow", C.c_int32), ("precision", C.c_int32),
+                ("dt_limit", C.c_double)]
 
 
 EXPORTS = [
@@ -38,7 +45,7 @@ EXPORTS = [
     "mct_batch_create", "mct_batch_select", "mct_set_order", "mct_autotune", "mct_get_launch",
     "mct_screen_collect", "mct_screen_enable", "mct_screen_disable", "mct_screen_stats",
     "mct_mlp_create", "mct_mlp_destroy", "mct_mlp_last_error", "mct_mlp_set_params", "mct_mlp_get_params",
-    "mct_mlp_forward", "mct_mlp_gradient", "mct_mlp_train_step",
+    "mct_mlp_forward", "mct_mlp_gradient", "mct_mlp_train_step", "mct_get_energies",
 ]
 N_FEATURES = 10
 N_PARAMS = 4929
@@ -88,6 +95,7 @@ def load() -> C.CDLL:
     L.mct_get_crack_set.argtypes = [P, C.c_int64, P, P, P, P, P, C.POINTER(C.c_int64)]
     L.mct_get_tips.argtypes = [P, C.c_int64, P, P, C.POINTER(C.c_int64)]
     L.mct_get_field.argtypes = [P, C.c_int, C.c_int64, dp]
+    L.mct_get_energies.argtypes = [P, dp]
     L.mct_get_split_codes.argtypes = [P, C.c_int64, bp]
     L.mct_checkpoint.argtypes = [P, P, C.c_int64, C.POINTER(C.c_int64)]
     L.mct_restore.argtypes = [P, P, C.c_int64]
@@ -256,10 +264,23 @@ class Model:
         return edge, xy.reshape(-1, 2)
 
     def field(self, which=FIELD_U):
-        nn = self.info()["n_nodes"]
-        out = np.zeros(2 * nn)
-        self._check(self._L.mct_get_field(self._h, int(which), 2 * nn, out), "get_field")
+        """Nodal fields (U, V, A, FINT) as (x, y); SIGMA_EDGE as [n_edges][3];
+        PRINCIPAL as [n_elems]."""
+        inf = self.info()
+        nn, ne, ns = inf["n_nodes"], inf["n_elems"], inf["n_edges"]
+        n = {FIELD_SIGMA_EDGE: 3 * ns, FIELD_PRINCIPAL: ne}.get(which, 2 * nn)
+        out = np.zeros(n)
+        self._check(self._L.mct_get_field(self._h, int(which), n, out), "get_field")
+        if which == FIELD_SIGMA_EDGE:
+            return out.reshape(3, ns).T.copy()
+        if which == FIELD_PRINCIPAL:
+            return out
         return out[:nn], out[nn:]
+
+    def energies(self) -> dict:
+        out = np.zeros(4)
+        self._check(self._L.mct_get_energies(self._h, out), "get_energies")
+        return dict(kin=out[0], strain=out[1], wext=out[2], Ud=out[3])
 
     def path_geometry(self, elems):
         """Crack-path normals and lengths as the GPU step computes them:

@@ -1,0 +1,144 @@
+"""GPU state queries against the CPU oracle: internal force, edge stresses,
+acceleration, principal stress and energies of a cracked state; the
+stability limit against a dense eigenvalue computation; the non-finite
+watchdog.  The query kernels follow the step's arithmetic, so forces and
+stresses agree to the last bits; sums (energies) differ in order only:
+1e-12 relative."""
+import math
+import struct
+
+import numpy as np
+import pytest
+
+from paper_2509_01827_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2509_01827_amd import mct2d
+    mct2d.load()
+    return mct2d
+
+
+def _element_edges(tabs, ne):
+    ee = np.full((ne, 4), -1, np.int64)
+    for s in range(len(tabs["edge_elem"])):
+        for side in range(2):
+            e = tabs["edge_elem"][s, side]
+            if e >= 0:
+                ee[e, tabs["edge_loc"][s, side]] = s
+    return ee
+
+
+@pytest.mark.parametrize("name", ["plate70x37_jitter", "fragment97x45"])
+def test_fields_and_energies_match_oracle(gpu, oracle_mod, name):
+    cfg = W.small_cases()[name]
+    steps = 450
+    m = gpu.from_config(cfg)
+    o = oracle_mod.Oracle(cfg)
+    m.step(steps)
+    o.step(steps)
+    st = o.state()
+    assert len(o.log()["elem"]) > 0
+    fx, fy, sig, ok = o.internal_force(st["ux"], st["uy"], with_stress=True)
+    tabs = o.tables()
+    scale = max(np.abs(fx).max(), np.abs(fy).max())
+    gx, gy = m.field(gpu.FIELD_FINT)
+    assert np.abs(gx - fx).max() <= 1e-12 * scale and np.abs(gy - fy).max() <= 1e-12 * scale
+    gs = m.field(gpu.FIELD_SIGMA_EDGE)
+    okb = ok.astype(bool)
+    assert np.all(np.isnan(gs[~okb]))
+    smax = np.abs(sig[okb]).max()
+    assert np.abs(gs[okb] - sig[okb]).max() <= 1e-12 * smax
+    # acceleration: (f_ext - f_int) / m, prescribed components zero
+    fe = tabs["fext"]
+    ax = (fe[:, 0] - fx) / tabs["mass"]
+    ay = (fe[:, 1] - fy) / tabs["mass"]
+    nodes, masks, _ = cfg["vbc"]
+    for n, mk in zip(nodes, masks):
+        if mk & 1:
+            ax[n] = 0.0
+        if mk & 2:
+            ay[n] = 0.0
+    ga, gb = m.field(gpu.FIELD_A)
+    amax = max(np.abs(ax).max(), np.abs(ay).max())
+    assert np.abs(ga - ax).max() <= 1e-11 * amax and np.abs(gb - ay).max() <= 1e-11 * amax
+    # principal stress of the mean edge stress, NaN on split elements
+    ne = cfg["nx"] * cfg["ny"]
+    ee = _element_edges(tabs, ne)
+    split = st["split"]
+    gp = m.field(gpu.FIELD_PRINCIPAL)
+    assert np.all(np.isnan(gp[split != 0]))
+    intact = np.where(split == 0)[0]
+    mean = sig[ee[intact]].sum(axis=1) / 4.0
+    c = 0.5 * (mean[:, 0] + mean[:, 1])
+    r = np.sqrt((0.5 * (mean[:, 0] - mean[:, 1])) ** 2 + mean[:, 2] ** 2)
+    np.testing.assert_allclose(gp[intact], c + r, rtol=1e-12, atol=1e-12 * smax)
+    # energies
+    ge, oe = m.energies(), o.energies()
+    print(name, ge, oe, flush=True)
+    for k in ("kin", "strain", "wext"):
+        assert ge[k] == pytest.approx(oe[k], rel=1e-12, abs=1e-300), k
+    assert ge["Ud"] == pytest.approx(oe["Ud"], rel=1e-12)
+
+
+def _dense_limit(oracle_mod, cfg):
+    """2 / omega_max from the dense M^-1 K over the free components (K by
+    columns of the oracle's internal force)."""
+    o = oracle_mod.Oracle(cfg)
+    nn = (cfg["nx"] + 1) * (cfg["ny"] + 1)
+    mass = o.tables()["mass"]
+    free = np.ones(2 * nn, bool)
+    nodes, masks, _ = cfg["vbc"]
+    for n, mk in zip(nodes, masks):
+        if mk & 1:
+            free[n] = False
+        if mk & 2:
+            free[nn + n] = False
+    K = np.zeros((2 * nn, 2 * nn))
+    for col in range(2 * nn):
+        u = np.zeros(2 * nn)
+        u[col] = 1.0
+        fx, fy = o.internal_force(u[:nn], u[nn:])
+        K[:, col] = np.concatenate([fx, fy])
+    minv = 1.0 / np.concatenate([mass, mass])
+    A = (minv[:, None] * K)[np.ix_(free, free)]
+    lam = np.max(np.real(np.linalg.eigvals(A)))
+    return 2.0 / math.sqrt(lam)
+
+
+@pytest.mark.parametrize("kind", ["notched_jitter", "velocity_bc"])
+def test_stability_limit_matches_dense_eigenvalue(gpu, oracle_mod, kind):
+    if kind == "notched_jitter":
+        cfg = W.plate(9, 7, 0.009, 0.007, jitter=0.1, seed=W.BASE_SEED + 31, notch_len=4, steps=10)
+    else:
+        cfg = W.fragmentation(8, 6, 1e-3, seed=W.BASE_SEED + 32, steps=10)
+    want = _dense_limit(oracle_mod, cfg)
+    m = gpu.from_config(cfg)
+    got = m.info()["dt_limit"]
+    print(kind, "dt", m.info()["dt"], "limit", got, "dense", want, flush=True)
+    assert got == pytest.approx(want, rel=2e-3)
+    assert got >= want * (1 - 1e-9)  # the Rayleigh quotient approaches from below
+    bad = dict(cfg, dt=1.02 * want)
+    with pytest.raises(gpu.MctError, match="stability"):
+        gpu.from_config(bad)
+    gpu.from_config(dict(cfg, dt=0.97 * want)).close()
+
+
+def test_nonfinite_state_is_reported(gpu):
+    cfg = W.config1(steps=10)
+    m = gpu.from_config(cfg)
+    m.step(5)
+    m.sync()
+    ck = bytearray(m.checkpoint())
+    # layout: 16-byte header, 16-byte specimen header, 48-byte control block, then u_x
+    struct.pack_into("<d", ck, 16 + 16 + 48 + 8 * 100, float("nan"))
+    m.restore(bytes(ck))
+    m.step(3)
+    with pytest.raises(gpu.MctError, match="non-finite"):
+        m.sync()
