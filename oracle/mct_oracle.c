@@ -26,6 +26,9 @@
  *   - Crack patterns I (adjacent edge) and II (opposite edge): Fig. 2-3.
  *   - Multiple Crack-tips Tracking: Sec. 3 and its pick criterion (the
  *     unnumbered inequalities G2 > gamma (G2 - Gi)), Fig. 3-1(b).
+ *   - Single crack-tip tracking (the SCT mode): Sec. 3 first paragraph and
+ *     Fig. 3-1(a): only the current tip quadrature point is evaluated; when
+ *     its element splits the tip moves to the exit edge.
  *   - Explicit formulation: Sec. 2 opening sentence.
  *
  * Readings where the paper is silent (each is listed in the design doc):
@@ -102,6 +105,10 @@ typedef struct {
     orc_split_t *log;
     int nlog, caplog;
     double Ud;
+    /* tracking: 0 = multiple crack tips, 1 = single crack tip; tip =
+     * element * 4 + local edge of the intact element at the current tip, or
+     * -1 (start tip: -2 = derive from the pre-notch at finalize) */
+    int sct, tip;
     /* scratch */
     double *sig;            /* 3 per edge */
     double *eps;            /* 3 per edge: smoothed strain */
@@ -476,7 +483,56 @@ static int edge_candidate(const orc_model_t *m, int s, int *f, int *a) {
 }
 
 /* a5 + a6: evaluate every free-surface quadrature point, pick, split. */
+/* Neighbour element across local edge k of element e, or -1. */
+static int neighbour(const orc_model_t *m, int e, int k) {
+    int s = m->elem_edge[4 * e + k];
+    int e0 = m->edge_elem[2 * s], e1 = m->edge_elem[2 * s + 1];
+    return e0 == e ? e1 : e0;
+}
+
+/* The tip after element f split with exit edge k: the element across k
+ * with the same edge, if it exists and is intact; else none. */
+static int tip_after(const orc_model_t *m, int f, int k) {
+    int nb = neighbour(m, f, k);
+    if (nb < 0 || !is_intact(m, nb)) return -1;
+    int s = m->elem_edge[4 * f + k];
+    int loc = m->edge_elem[2 * s] == nb ? m->edge_loc[2 * s] : m->edge_loc[2 * s + 1];
+    return 4 * nb + loc;
+}
+
+static void record_split(orc_model_t *m, int f, int a, int k, double G) {
+    m->split[f] = (unsigned char)(SPLIT_FLAG | (unsigned)(a << 2) | (unsigned)k);
+    if (m->nlog == m->caplog) {
+        m->caplog = m->caplog ? 2 * m->caplog : 1024;
+        m->log = realloc(m->log, sizeof(orc_split_t) * (size_t)m->caplog);
+    }
+    orc_split_t rec = {(int)m->step, f, a, k, G};
+    m->log[m->nlog++] = rec;
+    double nx, ny, len;
+    path_normal(m, f, a, k, &nx, &ny, &len);
+    m->Ud += m->Gc[f] * len;
+}
+
+/* Single crack-tip tracking: the element rule at the current tip only. */
+static void sct_phase(orc_model_t *m) {
+    if (m->tip < 0) return;
+    int f = m->tip >> 2, a = m->tip & 3;
+    int s = m->elem_edge[4 * f + a], ff, aa;
+    if (!edge_candidate(m, s, &ff, &aa) || ff != f) return;
+    double G[3];
+    candidate_G(m, f, a, G);
+    int j = orc_element_rule(G, m->Gc[f], m->gamma);
+    if (j < 0) return;
+    int k = (a + 1 + j) & 3;
+    record_split(m, f, a, k, G[j]);
+    m->tip = tip_after(m, f, k);
+}
+
 static void fracture_phase(orc_model_t *m) {
+    if (m->sct) {
+        sct_phase(m);
+        return;
+    }
     int cap = m->ns;
     double *cG = malloc(sizeof(double) * (size_t)cap);
     int *cE = malloc(sizeof(int) * (size_t)cap), *cA = malloc(sizeof(int) * (size_t)cap);
@@ -511,19 +567,7 @@ static void fracture_phase(orc_model_t *m) {
     free(acc);
     free(accG);
     int c = orc_mct_pick(nc, cG, cE, cA, m->gamma);
-    if (c >= 0) {
-        int f = cE[c], a = cA[c], k = cK[c];
-        m->split[f] = (unsigned char)(SPLIT_FLAG | (unsigned)(a << 2) | (unsigned)k);
-        if (m->nlog == m->caplog) {
-            m->caplog = m->caplog ? 2 * m->caplog : 1024;
-            m->log = realloc(m->log, sizeof(orc_split_t) * (size_t)m->caplog);
-        }
-        orc_split_t rec = {(int)m->step, f, a, k, cG[c]};
-        m->log[m->nlog++] = rec;
-        double nx, ny, len;
-        path_normal(m, f, a, k, &nx, &ny, &len);
-        m->Ud += m->Gc[f] * len;
-    }
+    if (c >= 0) record_split(m, cE[c], cA[c], cK[c], cG[c]);
     free(cG);
     free(cE);
     free(cA);
@@ -600,6 +644,7 @@ void orc_destroy(orc_model_t *m) {
 orc_model_t *orc_create(int nx, int ny, const double *X, const double *Y) {
     if (nx < 2 || ny < 2) return NULL;
     orc_model_t *m = zalloc(sizeof(orc_model_t));
+    if (m) m->tip = -1;
     m->nx = nx;
     m->ny = ny;
     m->nn = (nx + 1) * (ny + 1);
@@ -816,9 +861,40 @@ int orc_finalize(orc_model_t *m) {
         double cd = sqrt(m->E / (m->rho * (1.0 - m->nu * m->nu)));
         m->dt = m->cfl * hmin / cd;
     }
+    if (m->sct && m->tip == -2) {
+        /* the start tip: the one path end of the pre-notch (an entry or exit
+         * edge of a split element whose neighbour is intact) */
+        int found = -1, count = 0;
+        for (int e = 0; e < m->ne; ++e) {
+            if (!m->split[e]) continue;
+            int ks[2] = {(m->split[e] >> 2) & 3, m->split[e] & 3};
+            for (int q = 0; q < 2; ++q) {
+                int t = tip_after(m, e, ks[q]);
+                if (t >= 0) {
+                    found = t;
+                    count++;
+                }
+            }
+        }
+        if (count != 1) return ORC_EINVAL;
+        m->tip = found;
+    }
     m->finalized = 1;
     return ORC_OK;
 }
+
+/* Tracking mode: 0 multiple crack tips (default), 1 single crack tip with
+ * start tip (element, local edge), or elem < 0 to take the pre-notch's one
+ * path end at finalize. */
+int orc_set_tracking(orc_model_t *m, int mode, int elem, int edge) {
+    if (mode != 0 && mode != 1) return ORC_EINVAL;
+    if (mode == 1 && elem >= 0 && (elem >= m->ne || edge < 0 || edge > 3)) return ORC_EINVAL;
+    m->sct = mode;
+    m->tip = mode == 1 ? (elem >= 0 ? 4 * elem + edge : -2) : -1;
+    return ORC_OK;
+}
+
+int orc_get_tip(const orc_model_t *m) { return m->tip; }
 
 int orc_step(orc_model_t *m, long n) {
     if (!m->finalized) return ORC_ESTATE;

@@ -63,6 +63,9 @@ def lib():
         _lib.orc_split_codes.argtypes = [P, bp]
         _lib.orc_element_rule.argtypes = [dp, C.c_double, C.c_double]
         _lib.orc_mct_pick.argtypes = [C.c_int, dp, ip, ip, C.c_double]
+        _lib.orc_set_tracking.argtypes = [P, C.c_int, C.c_int, C.c_int]
+        _lib.orc_get_tip.argtypes = [P]
+        _lib.orc_get_tip.restype = C.c_int
         _lib.orc_set_threads.argtypes = [C.c_int]
         _lib.orc_get_threads.restype = C.c_int
     return _lib
@@ -122,6 +125,9 @@ class Oracle:
         ne_, en_, ex_ = cfg["notch"]
         self._check(L.orc_set_notch(self.h, len(ne_), _i32(ne_), _u8(en_), _u8(ex_)))
         self._check(L.orc_set_time(self.h, float(cfg.get("dt", 0.0)), float(cfg.get("cfl", 0.5))))
+        trk = cfg.get("tracking")
+        if trk is not None:  # ("sct", elem or -1, edge)
+            self._check(L.orc_set_tracking(self.h, 1 if trk[0] == "sct" else 0, int(trk[1]), int(trk[2])))
         if finalize:
             self._check(L.orc_finalize(self.h))
 
@@ -220,6 +226,11 @@ class Oracle:
         G = np.zeros(3)
         H = lib().orc_candidate_G(self.h, int(e), int(a), G)
         return G, H
+
+    def tip(self):
+        """Current single-crack tip as (element, local edge), or None."""
+        t = lib().orc_get_tip(self.h)
+        return None if t < 0 else (t >> 2, t & 3)
 
     def path_normal(self, e, a, k):
         out = np.zeros(3)

@@ -585,3 +585,69 @@ def test_oracle_thread_count_independent(oracle_mod):
     for k in ("ux", "uy", "vx", "vy", "split"):
         assert np.array_equal(s1[k], s2[k])
     assert np.array_equal(l1["elem"], l2["elem"]) and np.array_equal(l1["G"], l2["G"])
+
+
+# ---------------------------------------------------------------------------
+# Single crack-tip tracking (Sec. 3, Fig. 3-1(a))
+
+def _sct(cfg, elem=-1, edge=0):
+    c = dict(cfg)
+    c["tracking"] = ("sct", elem, edge)
+    return c
+
+
+def test_sct_start_tip_is_the_notch_end(oracle_mod):
+    o = oracle_mod.Oracle(_sct(W.config1()))
+    assert o.tip() == (20 * 40 + 20, 3)   # element right of the last notch element, its left edge
+
+
+def test_sct_path_is_continuous_and_ends_at_the_boundary(oracle_mod):
+    cfg = W.small_cases()["plate70x37_jitter"]
+    o = oracle_mod.Oracle(_sct(cfg))
+    start = o.tip()
+    o.step(cfg["steps"])
+    lg = o.log()
+    n = len(lg["elem"])
+    assert n > 10
+    nx, ny = cfg["nx"], cfg["ny"]
+    assert (lg["elem"][0], lg["entry"][0]) == start
+    for r in range(1, n):
+        e, k = int(lg["elem"][r - 1]), int(lg["exit"][r - 1])
+        i, j = e % nx, e // nx
+        ni, nj = [(i, j - 1), (i + 1, j), (i, j + 1), (i - 1, j)][k]
+        assert lg["elem"][r] == nj * nx + ni            # enters the element across the last exit
+        assert lg["entry"][r] == (k + 2) % 4            # through that same edge
+        assert lg["step"][r] > lg["step"][r - 1]
+    # the last exit edge lies on the domain boundary: tracking has ended
+    e, k = int(lg["elem"][-1]), int(lg["exit"][-1])
+    i, j = e % nx, e // nx
+    ni, nj = [(i, j - 1), (i + 1, j), (i, j + 1), (i - 1, j)][k]
+    assert not (0 <= ni < nx and 0 <= nj < ny)
+    assert o.tip() is None
+    o.step(300)
+    assert len(o.log()["elem"]) == n
+
+
+def test_sct_matches_mct_while_mct_picks_the_tip(oracle_mod):
+    """Where the multi-tip pick happens to take the single tip, both modes
+    split the same element with the same path and G at the same step (two
+    separate code paths: the global pick and the tip rule)."""
+    cfg = W.config1(steps=260)
+    a = oracle_mod.run(cfg, 260)
+    b = oracle_mod.run(_sct(cfg), 260)
+    la, lb = a.log(), b.log()
+    assert len(la["elem"]) >= 3
+    for r in range(3):
+        for k in ("step", "elem", "entry", "exit", "G"):
+            assert la[k][r] == lb[k][r], (r, k)
+
+
+def test_sct_explicit_tip_and_errors(oracle_mod):
+    cfg = W.config1()
+    o = oracle_mod.Oracle(_sct(cfg, 20 * 40 + 20, 3))
+    assert o.tip() == (820, 3)
+    with pytest.raises(Exception):
+        oracle_mod.Oracle(_sct(cfg, 1600, 0))     # element out of range
+    frag = W.small_cases()["fragment97x45"]       # no pre-notch: no start tip
+    with pytest.raises(Exception):
+        oracle_mod.Oracle(_sct(frag))
