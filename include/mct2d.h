@@ -85,6 +85,8 @@ typedef struct {
     int32_t log_overflow;/* 1 if more splits happened than the log can hold */
     int32_t precision;
     double dt_limit;     /* stability limit 2 / omega_max of the set-up mesh */
+    int64_t tip;         /* single-tip tracking: current tip element * 4 + local
+                            edge (-1: none, or multi-tip tracking) */
 } mct_info;
 
 /* Create an empty context.  precision: 64 (binary64 state and arithmetic).
@@ -129,6 +131,18 @@ int mct_set_velocity_bc(mct_ctx *ctx, int64_t n, const int32_t *node, const uint
  * local edges (entry != exit, both 0..3).  Not counted in U_d or the log. */
 int mct_set_notch(mct_ctx *ctx, int64_t n, const int32_t *elem, const uint8_t *entry,
                   const uint8_t *exit);
+
+/* Crack tracking (Sec. 3).  MCT_TRACK_MCT (default): every free-surface
+ * candidate is evaluated each step and the pick takes the largest G
+ * (Multiple Crack-tips Tracking).  MCT_TRACK_SCT: single crack-tip tracking
+ * (Fig. 3-1(a)), only the current tip is evaluated; when its element splits
+ * the tip moves to the element across the exit edge (tracking ends at the
+ * domain boundary or at a split element).  The start tip is element
+ * tip_elem, local edge tip_edge (facing the crack), or with tip_elem < 0 the
+ * one path end of the pre-notch (MCT_EINVAL at mct_finalize if it has none
+ * or several).  Per specimen. */
+enum { MCT_TRACK_MCT = 0, MCT_TRACK_SCT = 1 };
+int mct_set_tracking(mct_ctx *ctx, int mode, int32_t tip_elem, int tip_edge);
 
 /* Time step: dt > 0 is used as given; otherwise dt = cfl_fraction *
  * (shortest edge) / c_d with c_d = sqrt(E / (rho (1 - nu^2))). */

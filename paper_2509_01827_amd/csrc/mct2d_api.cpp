@@ -52,6 +52,9 @@ struct Spec {
     std::vector<int32_t> notch_elem;
     std::vector<uint8_t> notch_code;
     double dt_in = 0, cfl = 0.5;
+    int sct = 0;             // single crack-tip tracking
+    int32_t sct_elem = -1;   // start tip (element, local edge); -1: the pre-notch's path end
+    int sct_edge = 0;
     // derived
     double dt = 0;
     double dt_limit = 0;  // 2 / omega_max of the set-up mesh (power iteration)
@@ -570,6 +573,37 @@ int stability_limit(mct_ctx *c, Spec &s) {
     return MCT_OK;
 }
 
+// Start tip of single-tip tracking: the given one, or the one path end of
+// the pre-notch (an entry or exit edge of a notch element whose neighbour
+// across it is intact), as element * 4 + local edge.
+int start_tip(mct_ctx *c, size_t q, int32_t *tip) {
+    const Spec &s = c->specs[q];
+    if (s.sct_elem >= 0) {
+        *tip = s.sct_elem * 4 + s.sct_edge;
+        return MCT_OK;
+    }
+    std::vector<uint8_t> split(s.ne, 0);
+    for (size_t i = 0; i < s.notch_elem.size(); ++i) split[s.notch_elem[i]] = s.notch_code[i];
+    int found = 0;
+    for (size_t i = 0; i < s.notch_elem.size(); ++i) {
+        const int32_t e = s.notch_elem[i];
+        const int ks[2] = {(s.notch_code[i] >> 2) & 3, s.notch_code[i] & 3};
+        for (int k : ks) {
+            const int ei = e % s.nx, ej = e / s.nx;
+            const int ni = k == 1 ? ei + 1 : k == 3 ? ei - 1 : ei, nj = k == 2 ? ej + 1 : k == 0 ? ej - 1 : ej;
+            if (ni < 0 || ni >= s.nx || nj < 0 || nj >= s.ny) continue;
+            const int32_t nb = nj * s.nx + ni;
+            if (split[nb] != 0) continue;
+            *tip = nb * 4 + ((k + 2) & 3);
+            ++found;
+        }
+    }
+    if (found != 1)
+        return fail(c, MCT_EINVAL, "specimen %zu: single-tip tracking needs a start tip (the pre-notch has %d path ends)",
+                    q, found);
+    return MCT_OK;
+}
+
 int create_ctx(mct_ctx **out, int nspec, bool batch, int precision, void *hip_stream) {
     if (!out) return MCT_EINVAL;
     *out = nullptr;
@@ -751,6 +785,20 @@ int mct_set_notch(mct_ctx *c, int64_t n, const int32_t *elem, const uint8_t *ent
     return MCT_OK;
 }
 
+int mct_set_tracking(mct_ctx *c, int mode, int32_t tip_elem, int tip_edge) {
+    if (!c) return MCT_EINVAL;
+    Spec &s = cur(c);
+    if (!s.nx) return fail(c, MCT_ESTATE, "set the mesh first");
+    if (mode != MCT_TRACK_MCT && mode != MCT_TRACK_SCT) return fail(c, MCT_EINVAL, "unknown tracking mode %d", mode);
+    if (mode == MCT_TRACK_SCT && tip_elem >= 0 && (tip_elem >= s.ne || tip_edge < 0 || tip_edge > 3))
+        return fail(c, MCT_EINVAL, "start tip out of range");
+    s.sct = mode == MCT_TRACK_SCT;
+    s.sct_elem = tip_elem;
+    s.sct_edge = tip_edge;
+    c->finalized = false;
+    return MCT_OK;
+}
+
 int mct_set_time(mct_ctx *c, double dt, double cfl_fraction) {
     if (!c) return MCT_EINVAL;
     if (!(dt > 0) && !(cfl_fraction > 0)) return fail(c, MCT_EINVAL, "need dt > 0 or cfl_fraction > 0");
@@ -882,7 +930,16 @@ int mct_finalize(mct_ctx *c) {
     HIP_TRY(c, hipMemsetAsync(c->dvx, 0, sizeof(double) * nn, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->dvy, 0, sizeof(double) * nn, c->stream));
     HIP_TRY(c, hipMalloc((void **)&c->dctl, sizeof(Control) * c->specs.size()));
-    HIP_TRY(c, hipMemsetAsync(c->dctl, 0, sizeof(Control) * c->specs.size(), c->stream));
+    {
+        std::vector<Control> h0(c->specs.size());
+        std::memset(h0.data(), 0, sizeof(Control) * h0.size());
+        for (size_t q = 0; q < c->specs.size(); ++q) {
+            int32_t tip = -1;
+            if (c->specs[q].sct && (rc = start_tip(c, q, &tip))) return rc;
+            h0[q].tip0 = h0[q].tip1 = tip;
+        }
+        HIP_TRY(c, hipMemcpy(c->dctl, h0.data(), sizeof(Control) * h0.size(), hipMemcpyHostToDevice));
+    }
     // the log of a specimen holds up to one split per element
     HIP_TRY(c, hipMalloc((void **)&c->dlog, sizeof(LogRec) * (size_t)std::max<int64_t>(ne, 1)));
     int64_t max_ns = 0;
@@ -919,6 +976,7 @@ int mct_finalize(mct_ctx *c) {
         p.dt = s.dt;
         p.t_ramp = s.t_ramp;
         p.gamma = s.gamma;
+        p.sct = s.sct;
         p.ctl = c->dctl + q;
         p.log = c->dlog + s.elem_off;
     }
@@ -1016,6 +1074,7 @@ int mct_get_info(mct_ctx *c, mct_info *out) {
     out->n_splits = h.nsplit;
     out->dissipated = h.Ud;
     out->log_overflow = h.overflow;
+    out->tip = s.sct ? ((((h.base - 1) & 1) != 0) ? h.tip1 : h.tip0) : -1;
     return MCT_OK;
 }
 

@@ -33,12 +33,13 @@ struct Slot {
 struct Control {
     int64_t base;         // steps completed before the running segment
     uint32_t nslots[3];   // slots written by steps k_rel = 0, 1, 2 (mod 3)
-    uint32_t pad0;
-    int64_t nsplit;    // splits made so far (log length if no overflow)
-    double Ud;         // dissipated energy, sum of Gc * path length
-    int32_t overflow;  // 1 when a split could not be logged
-    int32_t pad;
+    int32_t tip0;         // single-tip mode: tip (e * 4 + a, -1 none) at the start of
+    int64_t nsplit;       //   the last even step (tip0) / odd step (tip1)
+    double Ud;            // dissipated energy, sum of Gc * path length
+    int32_t overflow;     // 1 when a split could not be logged
+    int32_t tip1;
 };
+static_assert(sizeof(Control) == 48, "Control layout");
 
 // One specimen as the kernels see it: sizes, constants and pointers already
 // offset to the specimen's part of the batch arrays.
@@ -54,6 +55,7 @@ struct StepParams {
     uint8_t *split;
     const double *area;  // per element (reference configuration)
     const uint32_t *screen;  // per element, byte a = screen state of candidate (e, a); null = no screen
+    int32_t sct;             // 1: single crack-tip tracking (only the tip is a candidate)
     const double *gc;   // per element, or nullptr for gc_uniform
     double gc_uniform;
     const double *fext_p;     // 2 per perimeter node

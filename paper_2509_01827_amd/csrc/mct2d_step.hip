@@ -168,6 +168,19 @@ __device__ __forceinline__ void apply_split(const StepParams &p, const Cand &g, 
     ctl->Ud = ctl->Ud + gc * L;
 }
 
+// Single-tip mode: the tip after element g.e split with exit edge g.k is
+// the same edge seen from the element across it, if that element exists
+// and is intact (the only split of a step is g.e's own).
+__device__ __forceinline__ int32_t tip_after(const StepParams &p, const Cand &g) {
+    const int i = g.e % p.nx, j = g.e / p.nx;
+    const int ni = (g.k == 1) ? i + 1 : (g.k == 3) ? i - 1 : i;
+    const int nj = (g.k == 2) ? j + 1 : (g.k == 0) ? j - 1 : j;
+    if (ni < 0 || ni >= p.nx || nj < 0 || nj >= p.ny) return -1;
+    const int64_t nb = (int64_t)nj * p.nx + ni;
+    if (p.split[nb] != 0) return -1;
+    return (int32_t)(nb * 4 + ((g.k + 2) & 3));
+}
+
 // One time step.  Steps run in segments (a captured graph or a run of direct
 // launches) closed by k_commit; k_rel is the index inside the segment and
 // par0 the parity of the segment's first step (u^k lives in buffer k & 1).
@@ -204,6 +217,7 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
     __shared__ uint16_t s_cand[4 * TX * TY];
     __shared__ uint16_t s_splitl[NT];
     __shared__ int s_ncand, s_ncorner, s_nthru;
+    __shared__ int32_t s_tip;
     __shared__ int s_wbase[NT / 64], s_wbase2[NT / 64], s_wbase3[NT / 64];
     __shared__ Cand s_red[NT / 64];
 
@@ -228,6 +242,8 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
     double *uy_n = par ? p.uy0 : p.uy1;
     const int set_w = k_rel % 3, set_r = (k_rel + 2) % 3, set_c = (k_rel + 1) % 3;
     const int64_t base = p.ctl->base;  // needed late (time, first step, log)
+    // single-tip mode: the tip at the start of the previous step (slot by parity)
+    const int32_t tip_prev = p.sct ? ((((base + k_rel - 1) & 1) != 0) ? p.ctl->tip1 : p.ctl->tip0) : -1;
 
     // ---- 1. stage nodes and split codes; prefetch owned-node data ------
     // Every global load of the phase is issued before the first LDS write,
@@ -296,6 +312,7 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
         s_ncand = 0;
         s_ncorner = 0;
         s_nthru = 0;
+        s_tip = tip_prev;
     }
 
     // ---- 2. the pick of the previous step -------------------------------
@@ -305,10 +322,19 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
             const int fx = g.e % nx - (i0 - 2), fy = g.e / nx - (j0 - 2);
             if (fx >= 0 && fx < EX && fy >= 0 && fy < EY)
                 s_split[fy * EX + fx] = (uint8_t)(kSplitFlag | (g.a << 2) | g.k);
+            if (p.sct) s_tip = tip_after(p, g);
             if (leader) apply_split(p, g, base + k_rel - 1);
         }
     }
-    if (tid == 0 && leader) p.ctl->nslots[set_c] = 0;
+    if (tid == 0 && leader) {
+        p.ctl->nslots[set_c] = 0;
+        if (p.sct) {
+            if (((base + k_rel) & 1) != 0)
+                p.ctl->tip1 = s_tip;
+            else
+                p.ctl->tip0 = s_tip;
+        }
+    }
     __syncthreads();
 
     auto elem_xy = [&](int ex, int ey, double x[4], double y[4]) {
@@ -532,6 +558,11 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
 #pragma unroll
         for (int k = 0; k < 4; ++k)
             if (s_split[nbr(e2, k)] != 0 && ((scr >> (8 * k)) & 0xFFu) != kScreenSkip) fmask |= 1u << k;
+        if (p.sct) {  // single-tip mode: the tip is the only candidate
+            const int32_t tip = s_tip;
+            const int64_t ge = (int64_t)(j0 - 1 + je) * nx + (i0 - 1 + ie);
+            fmask = (tip >= 0 && (tip >> 2) == ge) ? (fmask & (1u << (tip & 3))) : 0u;
+        }
     }
     // split elements of the ring, listed by kind: a path between adjacent
     // edges leaves a 3-node piece (constant-strain triangle) and a 1-node
@@ -777,7 +808,18 @@ __global__ __launch_bounds__(kCommitThreads) void k_commit(StepParams p0, const 
     const Cand g = reduce_slots<kCommitThreads>(p, set, p.ctl->nslots[set], s_red);
     if (threadIdx.x != 0) return;
     const int64_t base = p.ctl->base;
-    if (n > 0 && pick_accepted(p, g)) apply_split(p, g, base + n - 1);
+    const bool acc = n > 0 && pick_accepted(p, g);
+    if (p.sct && n > 0) {
+        // the tip at the start of step base + n goes where that step reads the
+        // previous step's tip
+        const bool odd = ((base + n - 1) & 1) != 0;
+        const int32_t t = acc ? tip_after(p, g) : (odd ? p.ctl->tip1 : p.ctl->tip0);
+        if (odd)
+            p.ctl->tip1 = t;
+        else
+            p.ctl->tip0 = t;
+    }
+    if (acc) apply_split(p, g, base + n - 1);
     p.ctl->nslots[0] = 0;
     p.ctl->nslots[1] = 0;
     p.ctl->nslots[2] = 0;

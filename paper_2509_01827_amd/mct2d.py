@@ -34,7 +34,7 @@ class Info(C.Structure):
     _fields_ = [("n_nodes", C.c_int64), ("n_elems", C.c_int64), ("n_edges", C.c_int64),
                 ("step", C.c_int64), ("n_splits", C.c_int64), ("dt", C.c_double),
                 ("dissipated", C.c_double), ("log_overflow", C.c_int32), ("precision", C.c_int32),
-                ("dt_limit", C.c_double)]
+                ("dt_limit", C.c_double), ("tip", C.c_int64)]
 
 
 EXPORTS = [
@@ -45,7 +45,7 @@ EXPORTS = [
     "mct_batch_create", "mct_batch_select", "mct_set_order", "mct_autotune", "mct_get_launch",
     "mct_screen_collect", "mct_screen_enable", "mct_screen_disable", "mct_screen_stats",
     "mct_mlp_create", "mct_mlp_destroy", "mct_mlp_last_error", "mct_mlp_set_params", "mct_mlp_get_params",
-    "mct_mlp_forward", "mct_mlp_gradient", "mct_mlp_train_step", "mct_get_energies",
+    "mct_mlp_forward", "mct_mlp_gradient", "mct_mlp_train_step", "mct_get_energies", "mct_set_tracking",
 ]
 N_FEATURES = 10
 N_PARAMS = 4929
@@ -88,6 +88,7 @@ def load() -> C.CDLL:
     L.mct_set_velocity_bc.argtypes = [P, C.c_int64, ip, bp, dp, C.c_double]
     L.mct_set_notch.argtypes = [P, C.c_int64, ip, bp, bp]
     L.mct_set_time.argtypes = [P, C.c_double, C.c_double]
+    L.mct_set_tracking.argtypes = [P, C.c_int, C.c_int32, C.c_int]
     L.mct_finalize.argtypes = [P]
     L.mct_step.argtypes = [P, C.c_int64]
     L.mct_sync.argtypes = [P]
@@ -202,6 +203,15 @@ class Model:
 
     def set_time(self, dt=0.0, cfl=0.5):
         self._check(self._L.mct_set_time(self._h, float(dt), float(cfl)), "set_time")
+
+    def set_tracking(self, mode="mct", tip_elem=-1, tip_edge=0):
+        m = {"mct": 0, "sct": 1}[mode]
+        self._check(self._L.mct_set_tracking(self._h, m, int(tip_elem), int(tip_edge)), "set_tracking")
+
+    def tip(self):
+        """Single-tip tracking: current tip (element, local edge) or None."""
+        t = self.info()["tip"]
+        return None if t < 0 else (t >> 2, t & 3)
 
     def set_launch(self, tile=0, use_graph=True):
         self._check(self._L.mct_set_launch(self._h, int(tile), int(bool(use_graph))), "set_launch")
@@ -404,6 +414,9 @@ def _setup(m: Model, cfg: dict):
     ne_, en_, ex_ = cfg["notch"]
     m.set_notch(ne_, en_, ex_)
     m.set_time(cfg.get("dt", 0.0), cfg.get("cfl", 0.5))
+    trk = cfg.get("tracking")
+    if trk is not None:  # ("sct", elem or -1, edge)
+        m.set_tracking(trk[0], trk[1], trk[2])
 
 
 def from_config(cfg: dict, stream: int | None = None, tile: int = 0, use_graph: bool = True) -> Model:
