@@ -93,6 +93,10 @@ typedef struct {
     unsigned char *vmask; /* per node: bit0 = x prescribed, bit1 = y */
     double *v0;           /* 2 per node */
     double t_ramp;
+    /* traction load curve: phi(t) piecewise linear through (curve_t[i],
+     * curve_phi[i]), constant beyond the ends; ncurve = 0: phi = 1 */
+    int ncurve;
+    double *curve_t, *curve_phi;
     double dt_in, cfl;
     /* derived */
     double *mass, *minv, *fext;
@@ -583,12 +587,26 @@ static double prescribed(const orc_model_t *m, double v0, double t) {
     return v0;
 }
 
+/* Load factor of the tractions at time t (the pressure history of Sec. 4.4
+ * is supplied as such a curve). */
+double orc_load_factor(const orc_model_t *m, double t) {
+    if (m->ncurve == 0) return 1.0;
+    if (t <= m->curve_t[0]) return m->curve_phi[0];
+    int n = m->ncurve;
+    if (t >= m->curve_t[n - 1]) return m->curve_phi[n - 1];
+    int i = 0;
+    while (m->curve_t[i + 1] <= t) i++;
+    double slope = (m->curve_phi[i + 1] - m->curve_phi[i]) / (m->curve_t[i + 1] - m->curve_t[i]);
+    return m->curve_phi[i] + (t - m->curve_t[i]) * slope;
+}
+
 static void one_step(orc_model_t *m) {
     internal_forces(m);
+    double phi = orc_load_factor(m, (double)m->step * m->dt);
 #pragma omp parallel for schedule(static)
     for (int i = 0; i < m->nn; ++i) {
-        m->ax[i] = (m->fext[2 * i] - m->fx[i]) * m->minv[i];
-        m->ay[i] = (m->fext[2 * i + 1] - m->fy[i]) * m->minv[i];
+        m->ax[i] = (phi * m->fext[2 * i] - m->fx[i]) * m->minv[i];
+        m->ay[i] = (phi * m->fext[2 * i + 1] - m->fy[i]) * m->minv[i];
         if (m->vmask[i] & 1) m->ax[i] = 0.0;
         if (m->vmask[i] & 2) m->ay[i] = 0.0;
     }
@@ -633,7 +651,8 @@ void orc_destroy(orc_model_t *m) {
     void *ptrs[] = {m->X, m->Y, m->conn, m->edge_node, m->edge_elem, m->edge_loc, m->elem_edge,
                     m->color, m->area, m->Gc, m->edge_trac, m->edge_loaded, m->vmask, m->v0,
                     m->mass, m->minv, m->fext, m->split, m->ux, m->uy, m->vx, m->vy, m->log,
-                    m->sig, m->eps, m->sig_ok, m->fe, m->fx, m->fy, m->ax, m->ay};
+                    m->sig, m->eps, m->sig_ok, m->fe, m->fx, m->fy, m->ax, m->ay, m->curve_t,
+                    m->curve_phi};
     for (size_t i = 0; i < sizeof(ptrs) / sizeof(ptrs[0]); ++i) free(ptrs[i]);
     free(m);
 }
@@ -896,6 +915,24 @@ int orc_set_tracking(orc_model_t *m, int mode, int elem, int edge) {
 
 int orc_get_tip(const orc_model_t *m) { return m->tip; }
 
+/* Traction load curve (n >= 2 points, t strictly increasing), n = 0 clears. */
+int orc_set_load_curve(orc_model_t *m, int n, const double *t, const double *phi) {
+    if (n != 0 && n < 2) return ORC_EINVAL;
+    for (int i = 0; i + 1 < n; ++i)
+        if (!(t[i + 1] > t[i])) return ORC_EINVAL;
+    free(m->curve_t);
+    free(m->curve_phi);
+    m->curve_t = m->curve_phi = NULL;
+    m->ncurve = n;
+    if (n) {
+        m->curve_t = malloc(sizeof(double) * (size_t)n);
+        m->curve_phi = malloc(sizeof(double) * (size_t)n);
+        memcpy(m->curve_t, t, sizeof(double) * (size_t)n);
+        memcpy(m->curve_phi, phi, sizeof(double) * (size_t)n);
+    }
+    return ORC_OK;
+}
+
 int orc_step(orc_model_t *m, long n) {
     if (!m->finalized) return ORC_ESTATE;
     for (long i = 0; i < n; ++i) one_step(m);
@@ -1018,20 +1055,22 @@ int orc_tips(const orc_model_t *m, int cap, int *edge, double *xy, int *count) {
 
 /* Energies at t_k: kinetic (v^k = v^{k-1/2} + dt/2 a^k; v^0 at k = 0),
  * strain (edge smoothing domains A_s = sum of intact A_j/4, plus split
- * pieces), external work f_ext . u (constant tractions), dissipated Ud. */
+ * pieces), external work f_ext(t_k) . u (load curve times the constant
+ * tractions), dissipated Ud. */
 void orc_energies(orc_model_t *m, double out[4]) {
     internal_forces(m);
     double ekin = 0.0, estr = 0.0, wext = 0.0;
+    double phi = orc_load_factor(m, (double)m->step * m->dt);
     for (int i = 0; i < m->nn; ++i) {
-        double ax = (m->fext[2 * i] - m->fx[i]) * m->minv[i];
-        double ay = (m->fext[2 * i + 1] - m->fy[i]) * m->minv[i];
+        double ax = (phi * m->fext[2 * i] - m->fx[i]) * m->minv[i];
+        double ay = (phi * m->fext[2 * i + 1] - m->fy[i]) * m->minv[i];
         double vx = m->vx[i], vy = m->vy[i];
         if (m->step > 0) {
             if (!(m->vmask[i] & 1)) vx = vx + 0.5 * m->dt * ax;
             if (!(m->vmask[i] & 2)) vy = vy + 0.5 * m->dt * ay;
         }
         ekin += 0.5 * m->mass[i] * (vx * vx + vy * vy);
-        wext += m->fext[2 * i] * m->ux[i] + m->fext[2 * i + 1] * m->uy[i];
+        wext += phi * m->fext[2 * i] * m->ux[i] + phi * m->fext[2 * i + 1] * m->uy[i];
     }
     for (int s = 0; s < m->ns; ++s) {
         if (!m->sig_ok[s]) continue;

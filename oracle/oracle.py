@@ -66,6 +66,9 @@ def lib():
         _lib.orc_set_tracking.argtypes = [P, C.c_int, C.c_int, C.c_int]
         _lib.orc_get_tip.argtypes = [P]
         _lib.orc_get_tip.restype = C.c_int
+        _lib.orc_set_load_curve.argtypes = [P, C.c_int, dp, dp]
+        _lib.orc_load_factor.argtypes = [P, C.c_double]
+        _lib.orc_load_factor.restype = C.c_double
         _lib.orc_set_threads.argtypes = [C.c_int]
         _lib.orc_get_threads.restype = C.c_int
     return _lib
@@ -125,6 +128,10 @@ class Oracle:
         ne_, en_, ex_ = cfg["notch"]
         self._check(L.orc_set_notch(self.h, len(ne_), _i32(ne_), _u8(en_), _u8(ex_)))
         self._check(L.orc_set_time(self.h, float(cfg.get("dt", 0.0)), float(cfg.get("cfl", 0.5))))
+        lc = cfg.get("load_curve")
+        if lc is not None:  # (t, phi)
+            self._lc = (_f64(lc[0]), _f64(lc[1]))
+            self._check(L.orc_set_load_curve(self.h, len(self._lc[0]), self._lc[0], self._lc[1]))
         trk = cfg.get("tracking")
         if trk is not None:  # ("sct", elem or -1, edge)
             self._check(L.orc_set_tracking(self.h, 1 if trk[0] == "sct" else 0, int(trk[1]), int(trk[2])))
@@ -226,6 +233,9 @@ class Oracle:
         G = np.zeros(3)
         H = lib().orc_candidate_G(self.h, int(e), int(a), G)
         return G, H
+
+    def load_factor(self, t):
+        return lib().orc_load_factor(self.h, float(t))
 
     def tip(self):
         """Current single-crack tip as (element, local edge), or None."""

@@ -678,7 +678,8 @@ const char *mct_last_error(const mct_ctx *c) { return c ? c->err.c_str() : "null
 int mct_set_mesh_grid(mct_ctx *c, int32_t nx, int32_t ny, const double *X, const double *Y) {
     if (!c) return MCT_EINVAL;
     if (nx < 2 || ny < 2 || !X || !Y) return fail(c, MCT_EINVAL, "grid needs nx, ny >= 2 and coordinates");
-    if ((int64_t)nx * ny > (int64_t)1 << 30) return fail(c, MCT_EINVAL, "grid too large");
+    // element ids, and element * 4 + local edge keys, stay in int32
+    if ((int64_t)nx * ny > (int64_t)1 << 29) return fail(c, MCT_EINVAL, "grid too large (more than 2^29 elements)");
     release_device(c);
     Spec s;
     s.nx = nx;

@@ -166,6 +166,26 @@ def plate(nx, ny, lx, ly, *, traction=1.0e6, jitter=0.0, seed=None,
                 notch=notch, dt=0.0, cfl=cfl, steps=steps)
 
 
+def pressure_pulse(t0=1.0e-6, tau=100.0e-6, t_end=400.0e-6, n=401):
+    """Load history of the pressured cylinder of Sec. 4.4, normalised to its
+    peak: linear rise to 1 at t0, then exp(-(t - t0) / tau) (the printed
+    decay constant "100" read as microseconds, like t0), sampled at n
+    points on [0, t_end] plus t0 itself.  Returns (t, phi)."""
+    t = np.unique(np.concatenate([np.linspace(0.0, t_end, n), [t0]]))
+    phi = np.where(t <= t0, t / t0, np.exp(-(t - t0) / tau))
+    return np.ascontiguousarray(t), np.ascontiguousarray(phi)
+
+
+def pulse_plate(nx, ny, lx, ly, *, peak=2.0e6, jitter=0.01, seed=BASE_SEED + 61, notch_len=None, steps=1000,
+                t0=1.0e-6, tau=100.0e-6, name="pulse_plate"):
+    """The notched plate with its edge tractions following the pressure
+    pulse of Sec. 4.4 (peak traction ``peak`` Pa)."""
+    c = plate(nx, ny, lx, ly, traction=peak, jitter=jitter, seed=seed,
+              notch_len=notch_len if notch_len is not None else nx // 2, steps=steps, name=name)
+    c["load_curve"] = pressure_pulse(t0=t0, tau=tau)
+    return c
+
+
 def config1(steps=2000):
     """40x40 Q4 plate, 40x40 mm, notch from the left edge to the centre
     along mid-height, 1 MPa traction, deterministic."""

@@ -127,3 +127,27 @@ def test_batch_select_out_of_range(gpu):
         m.select(3)
     with pytest.raises(gpu.MctError):
         m.finalize()  # specimens not set up
+
+
+def test_batch_with_different_time_steps(gpu, oracle_mod):
+    """Specimens with different element sizes, materials and loads step with
+    their own dt in one launch."""
+    cfgs = [W.plate(20, 14, 0.02, 0.014, jitter=0.02, seed=W.BASE_SEED + 51, notch_len=8, steps=400),
+            W.plate(17, 23, 0.034, 0.023, jitter=0.01, seed=W.BASE_SEED + 52, notch_len=7, traction=1.4e6,
+                    steps=400),
+            W.fragmentation(25, 12, 2.5e-3, seed=W.BASE_SEED + 53, steps=400)]
+    m = gpu.batch_from_configs(cfgs)
+    m.step(400)
+    dts = set()
+    for s, cfg in enumerate(cfgs):
+        o = oracle_mod.run(cfg, 400)
+        snap = _snapshot(m, s)
+        dts.add(snap["info"]["dt"])
+        assert snap["info"]["dt"] == o.info()["dt"]
+        ol, st = o.log(), o.state()
+        for k in ("step", "elem", "entry", "exit"):
+            assert np.array_equal(snap["log"][k].astype(np.int64), ol[k].astype(np.int64)), (s, k)
+        assert np.array_equal(snap["codes"], st["split"]), s
+        for a, b in zip(snap["u"] + snap["v"], (st["ux"], st["uy"], st["vx"], st["vy"])):
+            assert np.array_equal(a, b), s
+    assert len(dts) == 3

@@ -15,6 +15,7 @@ a wrong sign or index, a transposed operand, a wrong weight) fails it:
   * rule tables for the element decision and the MCT pick (Sec. 2.2 and
     Sec. 3 inequalities, gamma in {1, 2}, ties, strict '>' at Gc).
 """
+import math
 import os
 
 import numpy as np
@@ -651,3 +652,51 @@ def test_sct_explicit_tip_and_errors(oracle_mod):
     frag = W.small_cases()["fragment97x45"]       # no pre-notch: no start tip
     with pytest.raises(Exception):
         oracle_mod.Oracle(_sct(frag))
+
+
+# ---------------------------------------------------------------------------
+# Traction load curve (the pressure history of Sec. 4.4 as a sampled curve)
+
+def test_load_factor_interpolates_and_clamps(oracle_mod):
+    c = _cfg(4, 3, 0.004, 0.003, traction=1e6)
+    c["load_curve"] = (np.array([1.0, 2.0, 4.0]), np.array([0.5, 1.5, -0.5]))
+    o = oracle_mod.Oracle(c)
+    assert o.load_factor(0.0) == 0.5 and o.load_factor(1.0) == 0.5
+    assert o.load_factor(1.5) == 1.0 and o.load_factor(2.0) == 1.5
+    assert o.load_factor(3.0) == 0.5 and o.load_factor(4.0) == -0.5 and o.load_factor(9.0) == -0.5
+    t, phi = W.pressure_pulse()
+    assert phi[0] == 0.0 and phi.max() == 1.0 and t[np.argmax(phi)] == 1.0e-6
+    assert phi[-1] == pytest.approx(math.exp(-399.0 / 100.0), rel=1e-12)
+
+
+def test_unit_curve_changes_nothing_and_zero_curve_keeps_rest(oracle_mod):
+    cfg = W.small_cases()["plate70x37_jitter"]
+    a = oracle_mod.run(cfg, 300)
+    c1 = dict(cfg, load_curve=(np.array([0.0, 1.0]), np.array([1.0, 1.0])))
+    b = oracle_mod.run(c1, 300)
+    sa, sb = a.state(), b.state()
+    assert all(np.array_equal(sa[k], sb[k]) for k in ("ux", "uy", "vx", "vy", "split"))
+    c0 = dict(cfg, load_curve=(np.array([0.0, 1.0]), np.array([0.0, 0.0])))
+    z = oracle_mod.run(c0, 300)
+    assert not np.any(z.state()["ux"]) and not np.any(z.state()["uy"]) and len(z.log()["elem"]) == 0
+
+
+def test_centre_of_mass_under_a_ramped_traction(oracle_mod):
+    """phi(t) = t / T applied at t_k = k dt: with self-equilibrated internal
+    forces the mass-weighted mean displacement after n steps is
+    c dt^3 (n-1) n (n+1) / 6, c = F / (M T) (half first step, v^{1/2} = 0)."""
+    nx, ny = 12, 9
+    c = _cfg(nx, ny, 0.012, 0.009, jitter=0.05, seed=4, gc=1e30)
+    c["traction_nodes"], c["traction"] = W.edge_traction(nx, ny, 1e6, 0.0)
+    Tr = 5e-6
+    c["load_curve"] = (np.array([0.0, Tr]), np.array([0.0, 1.0]))
+    o = oracle_mod.Oracle(c)
+    t = o.tables()
+    M, F = t["mass"].sum(), t["fext"][:, 1].sum()
+    n = 23
+    dt = o.info()["dt"]
+    assert n * dt < Tr
+    o.step(n)
+    uy = o.state()["uy"]
+    want = F / (M * Tr) * dt ** 3 * (n - 1) * n * (n + 1) / 6.0
+    assert (t["mass"] * uy).sum() / M == pytest.approx(want, rel=1e-9)
