@@ -132,6 +132,14 @@ int mct_set_velocity_bc(mct_ctx *ctx, int64_t n, const int32_t *node, const uint
 int mct_set_notch(mct_ctx *ctx, int64_t n, const int32_t *elem, const uint8_t *entry,
                   const uint8_t *exit);
 
+/* Time history of the tractions: they are multiplied by the load factor
+ * phi(t), piecewise linear through the n points (t[i], phi[i]) (t strictly
+ * increasing), constant beyond the ends, evaluated at t_k = k dt; n = 0
+ * restores constant tractions.  The pressure history of Sec. 4.4 (linear
+ * rise, exponential decay) is passed as such a sampled curve.  Per
+ * specimen; host arrays copied. */
+int mct_set_load_curve(mct_ctx *ctx, int64_t n, const double *t, const double *phi);
+
 /* Crack tracking (Sec. 3).  MCT_TRACK_MCT (default): every free-surface
  * candidate is evaluated each step and the pick takes the largest G
  * (Multiple Crack-tips Tracking).  MCT_TRACK_SCT: single crack-tip tracking
@@ -184,7 +192,7 @@ int mct_get_tips(mct_ctx *ctx, int64_t cap, int32_t *edge, double *xy, int64_t *
 /* Field of the current step k (evaluated on the GPU from u^k):
  *   MCT_FIELD_U          u^k, [x of all nodes, y of all nodes] (2 n_nodes);
  *   MCT_FIELD_V          v^{k-1/2} (v^0 at k = 0), same layout;
- *   MCT_FIELD_A          a^k = (f_ext - f_int(u^k)) / m, prescribed
+ *   MCT_FIELD_A          a^k = (phi(t_k) f_ext - f_int(u^k)) / m, prescribed
  *                        components 0, same layout;
  *   MCT_FIELD_FINT       f_int(u^k) (Eqs. QUAD_fint_discretization and the
  *                        split pieces, summed in colour order), same layout;
@@ -199,8 +207,9 @@ int mct_get_field(mct_ctx *ctx, int which, int64_t cap, double *out);
 /* Energies at t_k (J/m): [0] kinetic sum m |v^k|^2 / 2 with
  * v^k = v^{k-1/2} + dt a^k / 2 for free components after the first step;
  * [1] strain: edge smoothing domains (area sum of intact A_j / 4) times
- * sigma:eps / 2 plus the split pieces; [2] external work f_ext . u^k
- * (constant tractions); [3] dissipated U_d.  Sums are FP64, deterministic
+ * sigma:eps / 2 plus the split pieces; [2] phi(t_k) f_ext . u^k (the work of
+ * constant tractions; with a load curve, the current load times u^k);
+ * [3] dissipated U_d.  Sums are FP64, deterministic
  * run to run. */
 int mct_get_energies(mct_ctx *ctx, double out[4]);
 

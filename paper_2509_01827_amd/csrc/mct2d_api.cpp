@@ -52,6 +52,8 @@ struct Spec {
     std::vector<int32_t> notch_elem;
     std::vector<uint8_t> notch_code;
     double dt_in = 0, cfl = 0.5;
+    std::vector<double> curve_t, curve_phi;  // traction load curve (empty: constant)
+    int64_t curve_off = 0;
     int sct = 0;             // single crack-tip tracking
     int32_t sct_elem = -1;   // start tip (element, local edge); -1: the pre-notch's path end
     int sct_edge = 0;
@@ -84,7 +86,7 @@ struct mct_ctx {
     // device arrays, specimens concatenated
     double *dX = nullptr, *dY = nullptr, *dux[2] = {nullptr, nullptr}, *duy[2] = {nullptr, nullptr};
     double *dvx = nullptr, *dvy = nullptr, *dminv = nullptr, *dgc = nullptr, *darea = nullptr;
-    double *dfext = nullptr, *dv0 = nullptr;
+    double *dfext = nullptr, *dv0 = nullptr, *dcurve = nullptr;
     uint8_t *dvmask = nullptr, *dsplit = nullptr;
     Control *dctl = nullptr;
     Slot *dslots = nullptr;
@@ -218,6 +220,7 @@ void release_device(mct_ctx *c) {
     dfree(c->dgc);
     dfree(c->darea);
     dfree(c->dfext);
+    dfree(c->dcurve);
     dfree(c->dv0);
     dfree(c->dvmask);
     dfree(c->dsplit);
@@ -573,6 +576,18 @@ int stability_limit(mct_ctx *c, Spec &s) {
     return MCT_OK;
 }
 
+// Traction load factor at t, evaluated like the device helper.
+double load_factor_host(const Spec &s, double t) {
+    const size_t n = s.curve_t.size();
+    if (n == 0) return 1.0;
+    if (t <= s.curve_t[0]) return s.curve_phi[0];
+    if (t >= s.curve_t[n - 1]) return s.curve_phi[n - 1];
+    size_t i = 0;
+    while (s.curve_t[i + 1] <= t) ++i;
+    const double slope = (s.curve_phi[i + 1] - s.curve_phi[i]) / (s.curve_t[i + 1] - s.curve_t[i]);
+    return s.curve_phi[i] + (t - s.curve_t[i]) * slope;
+}
+
 // Start tip of single-tip tracking: the given one, or the one path end of
 // the pre-notch (an entry or exit edge of a notch element whose neighbour
 // across it is intact), as element * 4 + local edge.
@@ -786,6 +801,20 @@ int mct_set_notch(mct_ctx *c, int64_t n, const int32_t *elem, const uint8_t *ent
     return MCT_OK;
 }
 
+int mct_set_load_curve(mct_ctx *c, int64_t n, const double *t, const double *phi) {
+    if (!c) return MCT_EINVAL;
+    Spec &s = cur(c);
+    if (n != 0 && (n < 2 || n > (1 << 20) || !t || !phi)) return fail(c, MCT_EINVAL, "load curve needs 2..2^20 points");
+    for (int64_t i = 0; i < n; ++i) {
+        if (!std::isfinite(t[i]) || !std::isfinite(phi[i])) return fail(c, MCT_EINVAL, "non-finite load curve");
+        if (i > 0 && !(t[i] > t[i - 1])) return fail(c, MCT_EINVAL, "load curve times must increase");
+    }
+    s.curve_t.assign(t, t + n);
+    s.curve_phi.assign(phi, phi + n);
+    c->finalized = false;
+    return MCT_OK;
+}
+
 int mct_set_tracking(mct_ctx *c, int mode, int32_t tip_elem, int tip_edge) {
     if (!c) return MCT_EINVAL;
     Spec &s = cur(c);
@@ -832,9 +861,11 @@ int mct_finalize(mct_ctx *c) {
             return fail(c, MCT_ESTATE, "specimen %zu: mesh and material are required", q);
     release_device(c);
 
-    int64_t nn = 0, ne = 0, np = 0;
+    int64_t nn = 0, ne = 0, np = 0, ncv = 0;
     bool any_gc = false;
     for (Spec &s : c->specs) {
+        s.curve_off = ncv;
+        ncv += (int64_t)s.curve_t.size();
         s.node_off = nn;
         s.elem_off = ne;
         s.perim_off = np;
@@ -919,6 +950,14 @@ int mct_finalize(mct_ctx *c) {
     if ((rc = upload(c, c->dvmask, vmask))) return rc;
     if ((rc = upload(c, c->dsplit, split))) return rc;
     if ((rc = upload(c, c->darea, area_all))) return rc;
+    if (ncv) {
+        std::vector<double> curves(2 * ncv);
+        for (const Spec &s : c->specs) {
+            std::copy(s.curve_t.begin(), s.curve_t.end(), curves.begin() + s.curve_off);
+            std::copy(s.curve_phi.begin(), s.curve_phi.end(), curves.begin() + ncv + s.curve_off);
+        }
+        if ((rc = upload(c, c->dcurve, curves))) return rc;
+    }
     if (any_gc && (rc = upload(c, c->dgc, gc))) return rc;
     for (int i = 0; i < 2; ++i) {
         HIP_TRY(c, hipMalloc((void **)&c->dux[i], sizeof(double) * nn));
@@ -978,6 +1017,9 @@ int mct_finalize(mct_ctx *c) {
         p.t_ramp = s.t_ramp;
         p.gamma = s.gamma;
         p.sct = s.sct;
+        p.ncurve = (int32_t)s.curve_t.size();
+        p.curve_t = p.ncurve ? c->dcurve + s.curve_off : nullptr;
+        p.curve_phi = p.ncurve ? c->dcurve + ncv + s.curve_off : nullptr;
         p.ctl = c->dctl + q;
         p.log = c->dlog + s.elem_off;
     }
@@ -1155,7 +1197,8 @@ int mct_get_field(mct_ctx *c, int which, int64_t cap, double *out) {
     if (which >= MCT_FIELD_A) {
         if ((rc = ensure_eval(c))) return rc;
         const double *ux = (h.base & 1) ? s.prm.ux1 : s.prm.ux0, *uy = (h.base & 1) ? s.prm.uy1 : s.prm.uy0;
-        HIP_TRY(c, mct::launch_eval(s.prm, ux, uy, s.prm.vx, s.prm.vy, h.base, c->ev, c->stream));
+        HIP_TRY(c, mct::launch_eval(s.prm, ux, uy, s.prm.vx, s.prm.vy, h.base,
+                                    load_factor_host(s, (double)h.base * s.dt), c->ev, c->stream));
         if (which == MCT_FIELD_A || which == MCT_FIELD_FINT) {
             const double *src = which == MCT_FIELD_A ? c->ev.acc : c->ev.fint;
             HIP_TRY(c, hipMemcpyAsync(out, src, sizeof(double) * 2 * s.nn, hipMemcpyDeviceToHost, c->stream));
@@ -1196,7 +1239,8 @@ int mct_get_energies(mct_ctx *c, double out[4]) {
     Control h;
     if ((rc = read_control(c, c->sel, &h))) return rc;
     const double *ux = (h.base & 1) ? s.prm.ux1 : s.prm.ux0, *uy = (h.base & 1) ? s.prm.uy1 : s.prm.uy0;
-    HIP_TRY(c, mct::launch_eval(s.prm, ux, uy, s.prm.vx, s.prm.vy, h.base, c->ev, c->stream));
+    HIP_TRY(c, mct::launch_eval(s.prm, ux, uy, s.prm.vx, s.prm.vy, h.base,
+                                load_factor_host(s, (double)h.base * s.dt), c->ev, c->stream));
     HIP_TRY(c, mct::launch_energies(s.prm, c->ev, c->ev.sums, c->stream));
     double r[8];
     HIP_TRY(c, hipMemcpyAsync(r, c->ev.sums, sizeof r, hipMemcpyDeviceToHost, c->stream));

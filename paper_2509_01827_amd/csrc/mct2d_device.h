@@ -182,5 +182,18 @@ __device__ __forceinline__ int64_t edge_v(int64_t i, int64_t j, int nx) {
     return j * row + (i < nx ? 2 * i + 1 : 2 * (int64_t)nx);
 }
 
+// Load factor of the tractions at time t: piecewise linear through the
+// curve points, constant beyond its ends, 1 without a curve.
+__device__ __forceinline__ double load_factor(const StepParams &p, double t) {
+    if (p.ncurve == 0) return 1.0;
+    if (t <= p.curve_t[0]) return p.curve_phi[0];
+    const int n = p.ncurve;
+    if (t >= p.curve_t[n - 1]) return p.curve_phi[n - 1];
+    int i = 0;
+    while (p.curve_t[i + 1] <= t) ++i;
+    const double slope = (p.curve_phi[i + 1] - p.curve_phi[i]) / (p.curve_t[i + 1] - p.curve_t[i]);
+    return p.curve_phi[i] + (t - p.curve_t[i]) * slope;
+}
+
 }  // namespace dev
 }  // namespace mct

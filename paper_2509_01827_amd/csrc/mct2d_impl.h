@@ -56,6 +56,8 @@ struct StepParams {
     const double *area;  // per element (reference configuration)
     const uint32_t *screen;  // per element, byte a = screen state of candidate (e, a); null = no screen
     int32_t sct;             // 1: single crack-tip tracking (only the tip is a candidate)
+    int32_t ncurve;          // traction load curve points (0: constant tractions)
+    const double *curve_t, *curve_phi;
     const double *gc;   // per element, or nullptr for gc_uniform
     double gc_uniform;
     const double *fext_p;     // 2 per perimeter node
@@ -116,7 +118,7 @@ struct EvalDev {
 
 int eval_partials();
 hipError_t launch_eval(const StepParams &p, const double *ux, const double *uy, const double *vx,
-                       const double *vy, int64_t step, const EvalDev &d, hipStream_t st);
+                       const double *vy, int64_t step, double phi, const EvalDev &d, hipStream_t st);
 hipError_t launch_energies(const StepParams &p, const EvalDev &d, double *out, hipStream_t st);
 hipError_t launch_principal(const StepParams &p, const EvalDev &d, double *out, hipStream_t st);
 hipError_t launch_power_step(const StepParams &p, const EvalDev &d, double *y, double *u, double *z,

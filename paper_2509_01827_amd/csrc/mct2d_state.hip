@@ -207,12 +207,13 @@ __device__ __forceinline__ int perimeter(int i, int j, int nx, int ny) {
 }
 
 // Nodal internal force (sum over the node's elements in colour order,
-// colour (i mod 2) + 2 (j mod 2)), acceleration (f_ext - f_int) / m with
+// colour (i mod 2) + 2 (j mod 2)), acceleration (phi f_ext - f_int) / m with
 // prescribed components zero, and per node: kinetic energy at t_k
 // (v^k = v^{k-1/2} + dt/2 a^k for free components after the first step)
 // and external work f_ext . u.
 __global__ __launch_bounds__(kB) void k_eval_nodes(StepParams p, const double *ux, const double *uy,
-                                                   const double *vx, const double *vy, int64_t step, EvalDev d) {
+                                                   const double *vx, const double *vy, int64_t step, double phi,
+                                                   EvalDev d) {
     const int64_t nn = (int64_t)(p.nx + 1) * (p.ny + 1);
     const int64_t g = (int64_t)blockIdx.x * kB + threadIdx.x;
     if (g >= nn) return;
@@ -237,7 +238,7 @@ __global__ __launch_bounds__(kB) void k_eval_nodes(StepParams p, const double *u
         mask = p.vmask_p[pidx];
     }
     const double minv = p.minv[g];
-    const double ax = (fex - fx) * minv, ay = (fey - fy) * minv;
+    const double ax = (phi * fex - fx) * minv, ay = (phi * fey - fy) * minv;
     d.fint[g] = fx;
     d.fint[nn + g] = fy;
     d.acc[g] = (mask & 1u) ? 0.0 : ax;
@@ -248,7 +249,7 @@ __global__ __launch_bounds__(kB) void k_eval_nodes(StepParams p, const double *u
         if (!(mask & 2u)) wy = wy + 0.5 * p.dt * ay;
     }
     d.node_e[2 * g] = 0.5 * (wx * wx + wy * wy) / minv;
-    d.node_e[2 * g + 1] = fex * ux[g] + fey * uy[g];
+    d.node_e[2 * g + 1] = phi * fex * ux[g] + phi * fey * uy[g];
 }
 
 // Maximum principal stress of the mean of an intact element's four edge
@@ -359,13 +360,13 @@ hipError_t sum_into(const double *x, int64_t n, int stride, int off, double *par
 int eval_partials() { return kSumBlocks; }
 
 hipError_t launch_eval(const StepParams &p, const double *ux, const double *uy, const double *vx,
-                       const double *vy, int64_t step, const EvalDev &d, hipStream_t st) {
+                       const double *vy, int64_t step, double phi, const EvalDev &d, hipStream_t st) {
     (void)hipGetLastError();
     const int64_t nn = (int64_t)(p.nx + 1) * (p.ny + 1), ne = (int64_t)p.nx * p.ny;
     const int64_t ns = 2 * ne + p.nx + p.ny;
     k_eval_edges<<<nb_of(ns), kB, 0, st>>>(p, ux, uy, d);
     k_eval_elements<<<nb_of(ne), kB, 0, st>>>(p, ux, uy, d);
-    k_eval_nodes<<<nb_of(nn), kB, 0, st>>>(p, ux, uy, vx, vy, step, d);
+    k_eval_nodes<<<nb_of(nn), kB, 0, st>>>(p, ux, uy, vx, vy, step, phi, d);
     return hipGetLastError();
 }
 
@@ -391,7 +392,7 @@ hipError_t launch_power_step(const StepParams &p, const EvalDev &d, double *y, d
     (void)hipGetLastError();
     const int64_t nn = (int64_t)(p.nx + 1) * (p.ny + 1);
     k_scale_in<<<nb_of(nn), kB, 0, st>>>(p, y, u);
-    hipError_t e = launch_eval(p, u, u + nn, nullptr, nullptr, 0, d, st);
+    hipError_t e = launch_eval(p, u, u + nn, nullptr, nullptr, 0, 1.0, d, st);
     if (e != hipSuccess) return e;
     k_scale_out<<<nb_of(nn), kB, 0, st>>>(p, d, y, z, scratch2);
     e = sum_into(scratch2, nn, 2, 0, d.part, sums, st);      // y . z

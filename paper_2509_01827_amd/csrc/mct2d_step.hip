@@ -218,6 +218,7 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
     __shared__ uint16_t s_splitl[NT];
     __shared__ int s_ncand, s_ncorner, s_nthru;
     __shared__ int32_t s_tip;
+    __shared__ double s_phi;
     __shared__ int s_wbase[NT / 64], s_wbase2[NT / 64], s_wbase3[NT / 64];
     __shared__ Cand s_red[NT / 64];
 
@@ -313,6 +314,7 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
         s_ncorner = 0;
         s_nthru = 0;
         s_tip = tip_prev;
+        s_phi = load_factor(p, (double)(base + k_rel) * p.dt);  // traction factor at t_k
     }
 
     // ---- 2. the pick of the previous step -------------------------------
@@ -759,8 +761,9 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
         // ---- 7. central-difference update of the owned node --------------
         const int64_t kabs = base + k_rel;
         const int hidx = (on_m + 2) * HX + (on_l + 2);
-        double ax = (n_fex - fx) * n_minv;
-        double ay = (n_fey - fy) * n_minv;
+        const double phi = s_phi;
+        double ax = (phi * n_fex - fx) * n_minv;
+        double ay = (phi * n_fey - fy) * n_minv;
         if (n_mask & 1u) ax = 0.0;
         if (n_mask & 2u) ay = 0.0;
         const double dtv = (kabs == 0) ? 0.5 * p.dt : p.dt;

@@ -46,6 +46,7 @@ EXPORTS = [
     "mct_screen_collect", "mct_screen_enable", "mct_screen_disable", "mct_screen_stats",
     "mct_mlp_create", "mct_mlp_destroy", "mct_mlp_last_error", "mct_mlp_set_params", "mct_mlp_get_params",
     "mct_mlp_forward", "mct_mlp_gradient", "mct_mlp_train_step", "mct_get_energies", "mct_set_tracking",
+    "mct_set_load_curve",
 ]
 N_FEATURES = 10
 N_PARAMS = 4929
@@ -89,6 +90,7 @@ def load() -> C.CDLL:
     L.mct_set_notch.argtypes = [P, C.c_int64, ip, bp, bp]
     L.mct_set_time.argtypes = [P, C.c_double, C.c_double]
     L.mct_set_tracking.argtypes = [P, C.c_int, C.c_int32, C.c_int]
+    L.mct_set_load_curve.argtypes = [P, C.c_int64, dp, dp]
     L.mct_finalize.argtypes = [P]
     L.mct_step.argtypes = [P, C.c_int64]
     L.mct_sync.argtypes = [P]
@@ -203,6 +205,10 @@ class Model:
 
     def set_time(self, dt=0.0, cfl=0.5):
         self._check(self._L.mct_set_time(self._h, float(dt), float(cfl)), "set_time")
+
+    def set_load_curve(self, t, phi):
+        t, phi = _f64(t), _f64(phi)
+        self._check(self._L.mct_set_load_curve(self._h, len(t), t, phi), "set_load_curve")
 
     def set_tracking(self, mode="mct", tip_elem=-1, tip_edge=0):
         m = {"mct": 0, "sct": 1}[mode]
@@ -417,6 +423,9 @@ def _setup(m: Model, cfg: dict):
     trk = cfg.get("tracking")
     if trk is not None:  # ("sct", elem or -1, edge)
         m.set_tracking(trk[0], trk[1], trk[2])
+    lc = cfg.get("load_curve")
+    if lc is not None:  # (t, phi)
+        m.set_load_curve(lc[0], lc[1])
 
 
 def from_config(cfg: dict, stream: int | None = None, tile: int = 0, use_graph: bool = True) -> Model:
