@@ -72,14 +72,14 @@ typedef struct {
 } orc_split_t;
 
 typedef struct {
-    /* mesh */
-    int nx, ny, nn, ne, ns;
+    /* mesh: nv = 4 (Q4, structured grid) or 3 (CST, unstructured) */
+    int nv, nx, ny, nn, ne, ns;
     double *X, *Y;
-    int *conn;       /* 4 per element, counter-clockwise */
+    int *conn;       /* nv per element at stride 4, counter-clockwise */
     int *edge_node;  /* 2 per edge: (smaller node id, larger node id) */
     int *edge_elem;  /* 2 per edge: smaller element id first, -1 = none */
     int *edge_loc;   /* 2 per edge: local edge index inside that element */
-    int *elem_edge;  /* 4 per element: global edge id of local edge k */
+    int *elem_edge;  /* nv per element at stride 4: global edge id of local edge k */
     int *color;
     int ncolor;
     double *area;
@@ -157,6 +157,19 @@ static void q4_grad_at_edge(const double x[4], const double y[4], int k,
     }
 }
 
+/* Gradients of the linear shape functions of a triangle (x[3], y[3]),
+ * constant over the element (Eq. CST_strain_discretization). */
+static void tri_grad(const double x[3], const double y[3], double dndx[3], double dndy[3]) {
+    double twoA = (x[1] - x[0]) * (y[2] - y[0]) - (x[2] - x[0]) * (y[1] - y[0]);
+    double inv = 1.0 / twoA;
+    dndx[0] = (y[1] - y[2]) * inv;
+    dndx[1] = (y[2] - y[0]) * inv;
+    dndx[2] = (y[0] - y[1]) * inv;
+    dndy[0] = (x[2] - x[1]) * inv;
+    dndy[1] = (x[0] - x[2]) * inv;
+    dndy[2] = (x[1] - x[0]) * inv;
+}
+
 /* strain (exx, eyy, gxy) = B u for an element with nn nodes */
 static void strain_from_grad(int nn, const double *dndx, const double *dndy,
                              const double *ux, const double *uy, double eps[3]) {
@@ -180,17 +193,22 @@ static void stress_from_strain(const orc_model_t *m, const double eps[3], double
 }
 
 static void elem_coords(const orc_model_t *m, int e, double x[4], double y[4]) {
-    for (int n = 0; n < 4; ++n) {
+    for (int n = 0; n < m->nv; ++n) {
         x[n] = m->X[m->conn[4 * e + n]];
         y[n] = m->Y[m->conn[4 * e + n]];
     }
 }
 
 static void elem_disp(const orc_model_t *m, int e, double ux[4], double uy[4]) {
-    for (int n = 0; n < 4; ++n) {
+    for (int n = 0; n < m->nv; ++n) {
         ux[n] = m->ux[m->conn[4 * e + n]];
         uy[n] = m->uy[m->conn[4 * e + n]];
     }
+}
+
+/* triangle area: half the cross product of two edges from node 0 */
+static double tri_area(const double x[3], const double y[3]) {
+    return 0.5 * ((x[1] - x[0]) * (y[2] - y[0]) - (x[2] - x[0]) * (y[1] - y[0]));
 }
 
 /* quadrilateral area: half the cross product of the diagonals */
@@ -208,6 +226,17 @@ static double polygon_area(int nv, const double *px, const double *py) {
 
 static int is_intact(const orc_model_t *m, int e) { return e >= 0 && m->split[e] == 0; }
 
+/* B of element e at the quadrature point of its local edge k: the Q4
+ * gradient at the edge midpoint, or the constant CST gradient */
+static void elem_grad_at_edge(const orc_model_t *m, int e, int k, double dndx[4], double dndy[4]) {
+    double x[4], y[4];
+    elem_coords(m, e, x, y);
+    if (m->nv == 4)
+        q4_grad_at_edge(x, y, k, dndx, dndy);
+    else
+        tri_grad(x, y, dndx, dndy);
+}
+
 /* ------------------------------------------------------------------ */
 /* a1: ES-FEM smoothed strain and stress at every edge                  */
 /* ------------------------------------------------------------------ */
@@ -220,11 +249,10 @@ static void edge_stresses(orc_model_t *m) {
         for (int side = 0; side < 2; ++side) {
             int e = m->edge_elem[2 * s + side];
             if (!is_intact(m, e)) continue;
-            double x[4], y[4], ux[4], uy[4], dndx[4], dndy[4];
-            elem_coords(m, e, x, y);
+            double ux[4], uy[4], dndx[4], dndy[4];
             elem_disp(m, e, ux, uy);
-            q4_grad_at_edge(x, y, m->edge_loc[2 * s + side], dndx, dndy);
-            strain_from_grad(4, dndx, dndy, ux, uy, q[cnt]);
+            elem_grad_at_edge(m, e, m->edge_loc[2 * s + side], dndx, dndy);
+            strain_from_grad(m->nv, dndx, dndy, ux, uy, q[cnt]);
             A[cnt] = m->area[e];
             cnt++;
         }
@@ -256,7 +284,28 @@ static void edge_stresses(orc_model_t *m) {
 /* a2: element internal forces (intact Q4 and split pieces)             */
 /* ------------------------------------------------------------------ */
 
+/* CST (Eq. CST_fint_discretization): element e receives (A_e/3) B_e^T
+ * sigma_s from each of its three edges; B_e is constant, so the three edge
+ * stresses are summed first (local edge order). */
+static void intact_force_tri(const orc_model_t *m, int e, double f[8]) {
+    double dndx[4], dndy[4], S[3];
+    elem_grad_at_edge(m, e, 0, dndx, dndy);
+    const double *s0 = &m->sig[3 * m->elem_edge[4 * e]];
+    const double *s1 = &m->sig[3 * m->elem_edge[4 * e + 1]];
+    const double *s2 = &m->sig[3 * m->elem_edge[4 * e + 2]];
+    for (int c = 0; c < 3; ++c) S[c] = (s0[c] + s1[c]) + s2[c];
+    double coef = m->area[e] / 3.0;
+    for (int n = 0; n < 3; ++n) {
+        f[2 * n] = coef * fma(dndy[n], S[2], dndx[n] * S[0]);
+        f[2 * n + 1] = coef * fma(dndx[n], S[2], dndy[n] * S[1]);
+    }
+}
+
 static void intact_force(const orc_model_t *m, int e, double f[8]) {
+    if (m->nv == 3) {
+        intact_force_tri(m, e, f);
+        return;
+    }
     double x[4], y[4];
     elem_coords(m, e, x, y);
     double sx[4] = {0, 0, 0, 0}, sy[4] = {0, 0, 0, 0};
@@ -290,17 +339,18 @@ static void intact_force(const orc_model_t *m, int e, double f[8]) {
 static double piece_force(const orc_model_t *m, int e, int entry_edge, int exit_edge,
                           double f[8]) {
     const int *cn = &m->conn[4 * e];
+    const int nvert = m->nv;
     int loc[3];
     int np = 0;
-    for (int k = (entry_edge + 1) & 3;; k = (k + 1) & 3) {
+    for (int k = (entry_edge + 1) % nvert;; k = (k + 1) % nvert) {
         loc[np++] = k;
         if (k == exit_edge) break;
     }
     /* polygon: M_entry, nodes..., M_exit */
     double px[5], py[5];
     int nv = 0;
-    int a0 = cn[entry_edge], a1 = cn[(entry_edge + 1) & 3];
-    int b0 = cn[exit_edge], b1 = cn[(exit_edge + 1) & 3];
+    int a0 = cn[entry_edge], a1 = cn[(entry_edge + 1) % nvert];
+    int b0 = cn[exit_edge], b1 = cn[(exit_edge + 1) % nvert];
     px[nv] = 0.5 * (m->X[a0] + m->X[a1]);
     py[nv++] = 0.5 * (m->Y[a0] + m->Y[a1]);
     for (int i = 0; i < np; ++i) {
@@ -313,11 +363,8 @@ static double piece_force(const orc_model_t *m, int e, int entry_edge, int exit_
 
     if (np == 3) {
         /* constant-strain triangle over the three nodes */
-        double x1 = px[1], y1 = py[1], x2 = px[2], y2 = py[2], x3 = px[3], y3 = py[3];
-        double twoA = (x2 - x1) * (y3 - y1) - (x3 - x1) * (y2 - y1);
-        double inv = 1.0 / twoA;
-        double b[3] = {(y2 - y3) * inv, (y3 - y1) * inv, (y1 - y2) * inv};
-        double c[3] = {(x3 - x2) * inv, (x1 - x3) * inv, (x2 - x1) * inv};
+        double b[3], c[3];
+        tri_grad(&px[1], &py[1], b, c);
         double ux[3], uy[3];
         for (int i = 0; i < 3; ++i) {
             ux[i] = m->ux[cn[loc[i]]];
@@ -380,7 +427,7 @@ static void internal_forces(orc_model_t *m) {
 #pragma omp parallel for schedule(static)
         for (int e = 0; e < m->ne; ++e) {
             if (m->color[e] != c) continue;
-            for (int n = 0; n < 4; ++n) {
+            for (int n = 0; n < m->nv; ++n) {
                 int g = m->conn[4 * e + n];
                 m->fx[g] = m->fx[g] + m->fe[8 * e + 2 * n];
                 m->fy[g] = m->fy[g] + m->fe[8 * e + 2 * n + 1];
@@ -398,7 +445,7 @@ static void internal_forces(orc_model_t *m) {
 static void path_normal(const orc_model_t *m, int e, int a, int k, double *nx,
                         double *ny, double *len) {
     const int *cn = &m->conn[4 * e];
-    int p0 = cn[a], p1 = cn[(a + 1) & 3], q0 = cn[k], q1 = cn[(k + 1) & 3];
+    int p0 = cn[a], p1 = cn[(a + 1) % m->nv], q0 = cn[k], q1 = cn[(k + 1) % m->nv];
     double g0x = 0.5 * (m->X[p0] + m->X[p1]), g0y = 0.5 * (m->Y[p0] + m->Y[p1]);
     double gkx = 0.5 * (m->X[q0] + m->X[q1]), gky = 0.5 * (m->Y[q0] + m->Y[q1]);
     double dx = gkx - g0x, dy = gky - g0y;
@@ -413,11 +460,12 @@ static void path_normal(const orc_model_t *m, int e, int a, int k, double *nx,
     *len = L;
 }
 
-/* G of the three paths of candidate (element e, crack-tip edge a), for
- * k = a+1, a+2, a+3 (CCW).  Returns the Heaviside gate H. */
+/* G of the paths of candidate (element e, crack-tip edge a): k = a+1, a+2,
+ * a+3 (CCW) for Q4, k = a+1, a+2 for CST (then G[2] = 0).  Returns the
+ * Heaviside gate H. */
 static int candidate_G(const orc_model_t *m, int e, int a, double G[3]) {
     const int *cn = &m->conn[4 * e];
-    int n1 = cn[a], n2 = cn[(a + 1) & 3];
+    int n1 = cn[a], n2 = cn[(a + 1) % m->nv];
     double dux = m->ux[n2] - m->ux[n1], duy = m->uy[n2] - m->uy[n1];
     /* H(|x2-x1|/|X2-X1| - 1) as a comparison of squared lengths */
     double x1 = m->X[n1] + m->ux[n1], y1 = m->Y[n1] + m->uy[n1];
@@ -425,12 +473,13 @@ static int candidate_G(const orc_model_t *m, int e, int a, double G[3]) {
     double lx = x2 - x1, ly = y2 - y1;
     double Lx = m->X[n2] - m->X[n1], Ly = m->Y[n2] - m->Y[n1];
     int H = (lx * lx + ly * ly) > (Lx * Lx + Ly * Ly);
-    for (int j = 0; j < 3; ++j) {
+    G[2] = 0.0;
+    for (int j = 0; j < m->nv - 1; ++j) {
         if (!H) {
             G[j] = 0.0;
             continue;
         }
-        int k = (a + 1 + j) & 3;
+        int k = (a + 1 + j) % m->nv;
         const double *sg = &m->sig[3 * m->elem_edge[4 * e + k]];
         double nx, ny, len;
         path_normal(m, e, a, k, &nx, &ny, &len);
@@ -441,18 +490,23 @@ static int candidate_G(const orc_model_t *m, int e, int a, double G[3]) {
     return H;
 }
 
-/* Q4 element decision over the three candidate paths (Sec. 2.2).  Returns
+/* Element decision over the n candidate paths (Sec. 2.2: n = 2 for CST,
+ * the list after Fig. 2-2; n = 3 for Q4, the list after Fig. 2-3).  Returns
  * the chosen path index j (k = a+1+j) or -1. */
-int orc_element_rule(const double G[3], double Gc, double gamma) {
+int orc_element_rule_n(int n, const double *G, double Gc, double gamma) {
     int best = -1;
-    for (int j = 0; j < 3; ++j)
+    for (int j = 0; j < n; ++j)
         if (G[j] > Gc && (best < 0 || G[j] > G[best])) best = j;
     if (best < 0) return -1;
-    for (int j = 0; j < 3; ++j) {
+    for (int j = 0; j < n; ++j) {
         if (j == best || !(G[j] > Gc)) continue;
         if (!(G[best] > gamma * (G[best] - G[j]))) return -1;
     }
     return best;
+}
+
+int orc_element_rule(const double G[3], double Gc, double gamma) {
+    return orc_element_rule_n(3, G, Gc, gamma);
 }
 
 /* MCT pick (Sec. 3): the candidate with the largest G (ties: lower element
@@ -525,9 +579,9 @@ static void sct_phase(orc_model_t *m) {
     if (!edge_candidate(m, s, &ff, &aa) || ff != f) return;
     double G[3];
     candidate_G(m, f, a, G);
-    int j = orc_element_rule(G, m->Gc[f], m->gamma);
+    int j = orc_element_rule_n(m->nv - 1, G, m->Gc[f], m->gamma);
     if (j < 0) return;
-    int k = (a + 1 + j) & 3;
+    int k = (a + 1 + j) % m->nv;
     record_split(m, f, a, k, G[j]);
     m->tip = tip_after(m, f, k);
 }
@@ -551,7 +605,7 @@ static void fracture_phase(orc_model_t *m) {
         if (!edge_candidate(m, s, &f, &a)) continue;
         double G[3];
         candidate_G(m, f, a, G);
-        int j = orc_element_rule(G, m->Gc[f], m->gamma);
+        int j = orc_element_rule_n(m->nv - 1, G, m->Gc[f], m->gamma);
         if (j < 0) continue;
         acc[s] = j;
         accG[s] = G[j];
@@ -565,7 +619,7 @@ static void fracture_phase(orc_model_t *m) {
         cG[nc] = accG[s];
         cE[nc] = f;
         cA[nc] = a;
-        cK[nc] = (a + 1 + acc[s]) & 3;
+        cK[nc] = (a + 1 + acc[s]) % m->nv;
         nc++;
     }
     free(acc);
@@ -657,46 +711,32 @@ void orc_destroy(orc_model_t *m) {
     free(m);
 }
 
-/* Structured nx x ny Q4 grid with the given node coordinates (node (i,j) has
- * id j*(nx+1)+i; element (i,j) id j*nx+i with CCW nodes (i,j),(i+1,j),
- * (i+1,j+1),(i,j+1)).  Tables are then built generically from conn. */
-orc_model_t *orc_create(int nx, int ny, const double *X, const double *Y) {
-    if (nx < 2 || ny < 2) return NULL;
-    orc_model_t *m = zalloc(sizeof(orc_model_t));
-    if (m) m->tip = -1;
-    m->nx = nx;
-    m->ny = ny;
-    m->nn = (nx + 1) * (ny + 1);
-    m->ne = nx * ny;
-    m->X = zalloc(sizeof(double) * m->nn);
-    m->Y = zalloc(sizeof(double) * m->nn);
-    memcpy(m->X, X, sizeof(double) * m->nn);
-    memcpy(m->Y, Y, sizeof(double) * m->nn);
-    m->conn = zalloc(sizeof(int) * 4 * m->ne);
-    for (int j = 0; j < ny; ++j)
-        for (int i = 0; i < nx; ++i) {
-            int e = j * nx + i;
-            m->conn[4 * e + 0] = j * (nx + 1) + i;
-            m->conn[4 * e + 1] = j * (nx + 1) + i + 1;
-            m->conn[4 * e + 2] = (j + 1) * (nx + 1) + i + 1;
-            m->conn[4 * e + 3] = (j + 1) * (nx + 1) + i;
-        }
+/* Edge table, element->edge map, greedy colouring, areas and the per-node
+ * and per-edge arrays of a model whose nv, nn, ne, X, Y and conn are set.
+ * Returns 0, or ORC_EINVAL for a mesh that is not a valid 2-manifold with
+ * consistently oriented elements (an edge used by more than two elements, or
+ * twice in the same direction). */
+static int build_tables(orc_model_t *m) {
+    const int nv = m->nv;
     /* edge table: every (element, local edge) keyed by its sorted node pair */
     edge_rec_t *r = zalloc(sizeof(edge_rec_t) * 4 * m->ne);
     for (int e = 0; e < m->ne; ++e)
-        for (int k = 0; k < 4; ++k) {
-            int a = m->conn[4 * e + k], b = m->conn[4 * e + ((k + 1) & 3)];
+        for (int k = 0; k < nv; ++k) {
+            int a = m->conn[4 * e + k], b = m->conn[4 * e + (k + 1) % nv];
             edge_rec_t t = {a < b ? a : b, a < b ? b : a, e, k};
-            r[4 * e + k] = t;
+            r[nv * e + k] = t;
         }
-    qsort(r, 4 * (size_t)m->ne, sizeof(edge_rec_t), cmp_edge_rec);
-    m->edge_node = zalloc(sizeof(int) * 8 * m->ne);
-    m->edge_elem = zalloc(sizeof(int) * 8 * m->ne);
-    m->edge_loc = zalloc(sizeof(int) * 8 * m->ne);
+    qsort(r, (size_t)nv * m->ne, sizeof(edge_rec_t), cmp_edge_rec);
+    m->edge_node = zalloc(sizeof(int) * 2 * nv * m->ne);
+    m->edge_elem = zalloc(sizeof(int) * 2 * nv * m->ne);
+    m->edge_loc = zalloc(sizeof(int) * 2 * nv * m->ne);
     m->elem_edge = zalloc(sizeof(int) * 4 * m->ne);
-    int ns = 0;
-    for (int i = 0; i < 4 * m->ne; ++i) {
+    int ns = 0, bad = 0;
+    for (int i = 0; i < nv * m->ne; ++i) {
         if (i > 0 && r[i].lo == r[i - 1].lo && r[i].hi == r[i - 1].hi) {
+            if (m->edge_elem[2 * (ns - 1) + 1] >= 0) bad = 1; /* third use */
+            int e0 = m->edge_elem[2 * (ns - 1)], k0 = m->edge_loc[2 * (ns - 1)];
+            if (m->conn[4 * e0 + k0] == m->conn[4 * r[i].e + r[i].k]) bad = 1; /* same direction */
             m->edge_elem[2 * (ns - 1) + 1] = r[i].e;
             m->edge_loc[2 * (ns - 1) + 1] = r[i].k;
         } else {
@@ -717,25 +757,26 @@ orc_model_t *orc_create(int nx, int ny, const double *X, const double *Y) {
     m->color = zalloc(sizeof(int) * m->ne);
     int *node_cnt = zalloc(sizeof(int) * (m->nn + 1));
     for (int e = 0; e < m->ne; ++e)
-        for (int n = 0; n < 4; ++n) node_cnt[m->conn[4 * e + n] + 1]++;
+        for (int n = 0; n < nv; ++n) node_cnt[m->conn[4 * e + n] + 1]++;
     for (int i = 0; i < m->nn; ++i) node_cnt[i + 1] += node_cnt[i];
-    int *node_el = zalloc(sizeof(int) * 4 * m->ne);
+    int *node_el = zalloc(sizeof(int) * nv * m->ne);
     int *fill = zalloc(sizeof(int) * m->nn);
     for (int e = 0; e < m->ne; ++e)
-        for (int n = 0; n < 4; ++n) {
+        for (int n = 0; n < nv; ++n) {
             int g = m->conn[4 * e + n];
             node_el[node_cnt[g] + fill[g]++] = e;
         }
     m->ncolor = 0;
-    for (int e = 0; e < m->ne; ++e) {
-        unsigned used = 0;
-        for (int n = 0; n < 4; ++n) {
+    for (int e = 0; e < m->ne && !bad; ++e) {
+        unsigned long long used = 0;
+        for (int n = 0; n < nv; ++n) {
             int g = m->conn[4 * e + n];
             for (int t = node_cnt[g]; t < node_cnt[g + 1]; ++t)
-                if (node_el[t] < e) used |= 1u << m->color[node_el[t]];
+                if (node_el[t] < e) used |= 1ull << m->color[node_el[t]];
         }
         int c = 0;
-        while (used & (1u << c)) c++;
+        while (c < 64 && (used & (1ull << c))) c++;
+        if (c == 64) bad = 1;
         m->color[e] = c;
         if (c + 1 > m->ncolor) m->ncolor = c + 1;
     }
@@ -746,7 +787,7 @@ orc_model_t *orc_create(int nx, int ny, const double *X, const double *Y) {
     for (int e = 0; e < m->ne; ++e) {
         double x[4], y[4];
         elem_coords(m, e, x, y);
-        m->area[e] = quad_area(x, y);
+        m->area[e] = nv == 4 ? quad_area(x, y) : tri_area(x, y);
     }
     m->Gc = zalloc(sizeof(double) * m->ne);
     m->edge_trac = zalloc(sizeof(double) * 2 * ns);
@@ -771,6 +812,64 @@ orc_model_t *orc_create(int nx, int ny, const double *X, const double *Y) {
     m->ay = zalloc(sizeof(double) * m->nn);
     m->gamma = 1.0;
     m->cfl = 0.5;
+    return bad ? ORC_EINVAL : ORC_OK;
+}
+
+static orc_model_t *new_model(int nv, int nn, int ne, const double *X, const double *Y) {
+    orc_model_t *m = zalloc(sizeof(orc_model_t));
+    m->tip = -1;
+    m->nv = nv;
+    m->nn = nn;
+    m->ne = ne;
+    m->X = zalloc(sizeof(double) * nn);
+    m->Y = zalloc(sizeof(double) * nn);
+    memcpy(m->X, X, sizeof(double) * nn);
+    memcpy(m->Y, Y, sizeof(double) * nn);
+    m->conn = zalloc(sizeof(int) * 4 * ne);
+    return m;
+}
+
+/* Structured nx x ny Q4 grid with the given node coordinates (node (i,j) has
+ * id j*(nx+1)+i; element (i,j) id j*nx+i with CCW nodes (i,j),(i+1,j),
+ * (i+1,j+1),(i,j+1)).  Tables are then built generically from conn. */
+orc_model_t *orc_create(int nx, int ny, const double *X, const double *Y) {
+    if (nx < 2 || ny < 2) return NULL;
+    orc_model_t *m = new_model(4, (nx + 1) * (ny + 1), nx * ny, X, Y);
+    m->nx = nx;
+    m->ny = ny;
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            int e = j * nx + i;
+            m->conn[4 * e + 0] = j * (nx + 1) + i;
+            m->conn[4 * e + 1] = j * (nx + 1) + i + 1;
+            m->conn[4 * e + 2] = (j + 1) * (nx + 1) + i + 1;
+            m->conn[4 * e + 3] = (j + 1) * (nx + 1) + i;
+        }
+    build_tables(m);
+    return m;
+}
+
+/* Unstructured CST mesh: nn nodes, ne triangles with counter-clockwise node
+ * triples conn[3 e + 0..2].  Returns NULL for an index out of range, a
+ * repeated node in one triangle, or a mesh build_tables rejects.  Positive
+ * areas are checked at finalize. */
+orc_model_t *orc_create_tri(int nn, const double *X, const double *Y, int ne, const int *conn) {
+    if (nn < 3 || ne < 1) return NULL;
+    for (int e = 0; e < ne; ++e) {
+        const int *c = &conn[3 * e];
+        for (int n = 0; n < 3; ++n)
+            if (c[n] < 0 || c[n] >= nn) return NULL;
+        if (c[0] == c[1] || c[1] == c[2] || c[0] == c[2]) return NULL;
+    }
+    orc_model_t *m = new_model(3, nn, ne, X, Y);
+    for (int e = 0; e < ne; ++e) {
+        for (int n = 0; n < 3; ++n) m->conn[4 * e + n] = conn[3 * e + n];
+        m->conn[4 * e + 3] = -1;
+    }
+    if (build_tables(m) != ORC_OK) {
+        orc_destroy(m);
+        return NULL;
+    }
     return m;
 }
 
@@ -830,7 +929,8 @@ int orc_set_velocity_bc(orc_model_t *m, int n, const int *node, const unsigned c
 int orc_set_notch(orc_model_t *m, int n, const int *elem, const unsigned char *entry,
                   const unsigned char *exitp) {
     for (int i = 0; i < n; ++i) {
-        if (elem[i] < 0 || elem[i] >= m->ne || entry[i] > 3 || exitp[i] > 3 || entry[i] == exitp[i])
+        if (elem[i] < 0 || elem[i] >= m->ne || entry[i] >= m->nv || exitp[i] >= m->nv ||
+            entry[i] == exitp[i])
             return ORC_EINVAL;
         m->split[elem[i]] = (unsigned char)(SPLIT_FLAG | (unsigned)(entry[i] << 2) | exitp[i]);
     }
@@ -849,10 +949,13 @@ int orc_finalize(orc_model_t *m) {
     for (int i = 0; i < m->nn; ++i) m->mass[i] = 0.0;
     for (int e = 0; e < m->ne; ++e) {
         if (!(m->area[e] > 0.0)) return ORC_EINVAL;
-        double me = m->rho * m->area[e] / 4.0;
-        for (int n = 0; n < 4; ++n) m->mass[m->conn[4 * e + n]] += me;
+        double me = m->rho * m->area[e] / (double)m->nv;
+        for (int n = 0; n < m->nv; ++n) m->mass[m->conn[4 * e + n]] += me;
     }
-    for (int i = 0; i < m->nn; ++i) m->minv[i] = 1.0 / m->mass[i];
+    for (int i = 0; i < m->nn; ++i) {
+        if (!(m->mass[i] > 0.0)) return ORC_EINVAL; /* a node in no element */
+        m->minv[i] = 1.0 / m->mass[i];
+    }
     /* consistent nodal forces of the edge tractions, edge-id order */
     for (int i = 0; i < 2 * m->nn; ++i) m->fext[i] = 0.0;
     for (int s = 0; s < m->ns; ++s) {
@@ -907,7 +1010,7 @@ int orc_finalize(orc_model_t *m) {
  * path end at finalize. */
 int orc_set_tracking(orc_model_t *m, int mode, int elem, int edge) {
     if (mode != 0 && mode != 1) return ORC_EINVAL;
-    if (mode == 1 && elem >= 0 && (elem >= m->ne || edge < 0 || edge > 3)) return ORC_EINVAL;
+    if (mode == 1 && elem >= 0 && (elem >= m->ne || edge < 0 || edge >= m->nv)) return ORC_EINVAL;
     m->sct = mode;
     m->tip = mode == 1 ? (elem >= 0 ? 4 * elem + edge : -2) : -1;
     return ORC_OK;
@@ -943,13 +1046,14 @@ int orc_step(orc_model_t *m, long n) {
 /* queries and test hooks                                               */
 /* ------------------------------------------------------------------ */
 
-void orc_info(const orc_model_t *m, int *ints /*nn,ne,ns,ncolor,nlog*/, double *dbls /*dt,Ud*/,
-              long *step) {
+void orc_info(const orc_model_t *m, int *ints /*nn,ne,ns,ncolor,nlog,nv*/,
+              double *dbls /*dt,Ud*/, long *step) {
     ints[0] = m->nn;
     ints[1] = m->ne;
     ints[2] = m->ns;
     ints[3] = m->ncolor;
     ints[4] = m->nlog;
+    ints[5] = m->nv;
     dbls[0] = m->dt;
     dbls[1] = m->Ud;
     *step = m->step;
@@ -1024,7 +1128,7 @@ int orc_candidates(orc_model_t *m, int cap, int *edge, int *elem, int *a, double
             elem[nc] = f;
             a[nc] = la;
             candidate_G(m, f, la, &G3[3 * nc]);
-            dec[nc] = orc_element_rule(&G3[3 * nc], m->Gc[f], m->gamma);
+            dec[nc] = orc_element_rule_n(m->nv - 1, &G3[3 * nc], m->Gc[f], m->gamma);
         }
         nc++;
     }
@@ -1077,7 +1181,7 @@ void orc_energies(orc_model_t *m, double out[4]) {
         double As = 0.0;
         for (int side = 0; side < 2; ++side) {
             int e = m->edge_elem[2 * s + side];
-            if (is_intact(m, e)) As += m->area[e] / 4.0;
+            if (is_intact(m, e)) As += m->area[e] / (double)m->nv;
         }
         const double *sg = &m->sig[3 * s], *ep = &m->eps[3 * s];
         estr += 0.5 * As * (sg[0] * ep[0] + sg[1] * ep[1] + sg[2] * ep[2]);

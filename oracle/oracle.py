@@ -40,6 +40,8 @@ def lib():
         bp = np.ctypeslib.ndpointer(np.uint8, flags="C")
         _lib.orc_create.restype = P
         _lib.orc_create.argtypes = [C.c_int, C.c_int, dp, dp]
+        _lib.orc_create_tri.restype = P
+        _lib.orc_create_tri.argtypes = [C.c_int, dp, dp, C.c_int, ip]
         _lib.orc_destroy.argtypes = [P]
         _lib.orc_set_material.argtypes = [P, C.c_double, C.c_double, C.c_double, C.c_void_p,
                                           C.c_double, C.c_double]
@@ -62,6 +64,7 @@ def lib():
         _lib.orc_path_normal.argtypes = [P, C.c_int, C.c_int, C.c_int, dp]
         _lib.orc_split_codes.argtypes = [P, bp]
         _lib.orc_element_rule.argtypes = [dp, C.c_double, C.c_double]
+        _lib.orc_element_rule_n.argtypes = [C.c_int, dp, C.c_double, C.c_double]
         _lib.orc_mct_pick.argtypes = [C.c_int, dp, ip, ip, C.c_double]
         _lib.orc_set_tracking.argtypes = [P, C.c_int, C.c_int, C.c_int]
         _lib.orc_get_tip.argtypes = [P]
@@ -99,21 +102,34 @@ def element_rule(G3, Gc, gamma):
     return lib().orc_element_rule(_f64(G3), float(Gc), float(gamma))
 
 
+def element_rule_n(G, Gc, gamma):
+    """Element decision over len(G) candidate paths (2: CST, 3: Q4)."""
+    G = _f64(G)
+    return lib().orc_element_rule_n(len(G), G, float(Gc), float(gamma))
+
+
 def mct_pick(G, elem, a, gamma):
     G = _f64(G)
     return lib().orc_mct_pick(len(G), G, _i32(elem), _i32(a), float(gamma))
 
 
 class Oracle:
-    """One structured-grid model run by the plain CPU oracle."""
+    """One model run by the plain CPU oracle: a structured Q4 grid (cfg keys
+    nx, ny) or an unstructured CST mesh (cfg key conn, [ne][3] CCW)."""
 
     def __init__(self, cfg: dict, *, finalize: bool = True):
         L = lib()
         self.cfg = cfg
-        self.nx, self.ny = int(cfg["nx"]), int(cfg["ny"])
-        self.h = L.orc_create(self.nx, self.ny, _f64(cfg["X"]), _f64(cfg["Y"]))
+        if cfg.get("conn") is not None:
+            self.nx = self.ny = 0
+            conn = _i32(np.asarray(cfg["conn"]).reshape(-1))
+            X = _f64(cfg["X"])
+            self.h = L.orc_create_tri(len(X), X, _f64(cfg["Y"]), len(conn) // 3, conn)
+        else:
+            self.nx, self.ny = int(cfg["nx"]), int(cfg["ny"])
+            self.h = L.orc_create(self.nx, self.ny, _f64(cfg["X"]), _f64(cfg["Y"]))
         if not self.h:
-            raise ValueError("oracle: bad grid")
+            raise ValueError("oracle: bad mesh")
         gcf = cfg.get("gc_field")
         self._gc = None if gcf is None else _f64(gcf)
         rc = L.orc_set_material(self.h, cfg["E"], cfg["nu"], cfg["rho"],
@@ -149,12 +165,13 @@ class Oracle:
             self.h = None
 
     def info(self):
-        ints = np.zeros(5, np.int32)
+        ints = np.zeros(6, np.int32)
         dbls = np.zeros(2)
         st = C.c_long(0)
         lib().orc_info(self.h, ints, dbls, C.byref(st))
         return dict(nn=int(ints[0]), ne=int(ints[1]), ns=int(ints[2]), ncolor=int(ints[3]),
-                    nlog=int(ints[4]), dt=float(dbls[0]), Ud=float(dbls[1]), step=int(st.value))
+                    nlog=int(ints[4]), nv=int(ints[5]), dt=float(dbls[0]), Ud=float(dbls[1]),
+                    step=int(st.value))
 
     def step(self, n):
         self._check(lib().orc_step(self.h, int(n)))

@@ -263,3 +263,208 @@ def small_batch(n=12, steps=600):
     """A batch the oracle finishes in seconds (parity tests)."""
     return batch_specimens(n, seed=BASE_SEED + 40, steps=steps, nx_range=(8, 48),
                            ny_range=(6, 40))
+
+
+# --------------------------------------------------------------------------
+# Unstructured triangle (CST) meshes
+#
+# A CST model is described by the same dictionary with ``conn`` ([ne][3]
+# int32, counter-clockwise node triples) in place of ``nx``/``ny``.  Meshes
+# are Delaunay triangulations (scipy) of seeded jittered point sets; the
+# triangles are handed over in Morton order of their centroids so that
+# neighbouring elements have nearby ids (the library keeps the caller's
+# numbering).
+
+E_STEEL = 210.0e9
+NU_STEEL = 0.3
+RHO_STEEL = 7850.0
+GC_STEEL = 2000.0
+
+
+def _triangulate(X, Y, h):
+    """Delaunay triangles of the points, each counter-clockwise and rotated
+    to start at its smallest node id, sorted by the Morton code of the
+    centroid on a grid of spacing h (ties: lexicographic node triple)."""
+    from scipy.spatial import Delaunay
+    T = Delaunay(np.stack([X, Y], axis=1)).simplices.astype(np.int64)
+    a2 = (X[T[:, 1]] - X[T[:, 0]]) * (Y[T[:, 2]] - Y[T[:, 0]]) - \
+         (X[T[:, 2]] - X[T[:, 0]]) * (Y[T[:, 1]] - Y[T[:, 0]])
+    T[a2 < 0] = T[a2 < 0][:, [0, 2, 1]]
+    r = np.argmin(T, axis=1)
+    T = np.stack([T[np.arange(len(T)), (r + q) % 3] for q in range(3)], axis=1)
+    return T, _morton_sort(T, X, Y, h)
+
+
+def _morton_sort(T, X, Y, h):
+    cx = (X[T[:, 0]] + X[T[:, 1]] + X[T[:, 2]]) / 3.0
+    cy = (Y[T[:, 0]] + Y[T[:, 1]] + Y[T[:, 2]]) / 3.0
+    ix = np.floor((cx - cx.min()) / h).astype(np.uint64)
+    iy = np.floor((cy - cy.min()) / h).astype(np.uint64)
+    key = np.zeros(len(T), np.uint64)
+    for b in range(21):
+        key |= ((ix >> np.uint64(b)) & np.uint64(1)) << np.uint64(2 * b)
+        key |= ((iy >> np.uint64(b)) & np.uint64(1)) << np.uint64(2 * b + 1)
+    order = np.lexsort((T[:, 2], T[:, 1], T[:, 0], key))
+    return np.ascontiguousarray(T[order].astype(np.int32))
+
+
+def _edge_map(T):
+    """{(lo, hi): [(triangle, local edge), ...]} of a triangle list."""
+    m = {}
+    for t in range(len(T)):
+        for k in range(3):
+            a, b = int(T[t, k]), int(T[t, (k + 1) % 3])
+            m.setdefault((min(a, b), max(a, b)), []).append((t, k))
+    return m
+
+
+def boundary_edges(T):
+    """Edges used by one triangle, as (a, b) in that triangle's CCW
+    direction (the domain lies to the left of a -> b)."""
+    out = []
+    for (lo, hi), uses in _edge_map(T).items():
+        if len(uses) == 1:
+            t, k = uses[0]
+            out.append((int(T[t, k]), int(T[t, (k + 1) % 3])))
+    out.sort()
+    return np.asarray(out, np.int64).reshape(-1, 2)
+
+
+def strip_notch(X, Y, T, y_c, x_end):
+    """Pre-notch along the line y = y_c from the left boundary (x = 0) to
+    x_end: the strip of triangles the line crosses, walked from the boundary
+    edge through each triangle's other crossed edge while that crossing lies
+    at x <= x_end.  Node sides: above means Y > y_c.  Returns (elem, entry,
+    exit) with local edge indices."""
+    above = Y > y_c
+    em = _edge_map(T)
+
+    def crossing_x(a, b):
+        return X[a] + (y_c - Y[a]) / (Y[b] - Y[a]) * (X[b] - X[a])
+
+    start = None
+    for (lo, hi), uses in em.items():
+        if len(uses) == 1 and X[lo] == 0.0 and X[hi] == 0.0 and above[lo] != above[hi]:
+            start = uses[0]
+    assert start is not None, "no boundary edge crosses the notch line"
+    elems, ent, ext = [], [], []
+    t, ke = start
+    while True:
+        ks = [k for k in range(3) if k != ke and above[T[t, k]] != above[T[t, (k + 1) % 3]]]
+        kx = ks[0]
+        a, b = int(T[t, kx]), int(T[t, (kx + 1) % 3])
+        if crossing_x(a, b) > x_end:
+            break
+        elems.append(t); ent.append(ke); ext.append(kx)
+        uses = em[(min(a, b), max(a, b))]
+        if len(uses) == 1:
+            break
+        t, ke = [u for u in uses if u[0] != t][0]
+    return (np.asarray(elems, np.int32), np.asarray(ent, np.uint8), np.asarray(ext, np.uint8))
+
+
+def tri_plate(nx, ny, lx, ly, *, traction=1.0e6, jitter=0.3, seed=BASE_SEED + 70,
+              notch_len=None, gc=GC_PLATE, gc_field=None, gamma=1.0, steps=2000, cfl=0.5,
+              name="tri_plate"):
+    """The Neumann branching plate on an unstructured CST mesh: Delaunay
+    triangulation of an (nx+1) x (ny+1) point grid with +/-``jitter`` h
+    seeded moves (boundary points slide along their edge), 1 MPa normal
+    traction on the upper and lower edges, pre-notch of length
+    ``notch_len`` (m) along mid-height from the left edge."""
+    X, Y = grid_coords(nx, ny, lx, ly, jitter, seed)
+    T = _triangulate(X, Y, min(lx / nx, ly / ny))[1]
+    be = boundary_edges(T)
+    top = (Y[be[:, 0]] == ly) & (Y[be[:, 1]] == ly)
+    bot = (Y[be[:, 0]] == 0.0) & (Y[be[:, 1]] == 0.0)
+    tn = np.concatenate([be[bot], be[top]]).astype(np.int32)
+    tt = np.zeros((len(tn), 2))
+    tt[:bot.sum(), 1] = -traction
+    tt[bot.sum():, 1] = traction
+    notch = strip_notch(X, Y, T, 0.5 * ly, notch_len) if notch_len else _empty_notch()
+    return dict(name=name, conn=T, X=X, Y=Y, E=E_PLATE, nu=NU_PLATE, rho=RHO_PLATE,
+                gc_uniform=gc, gc_field=gc_field, gamma=gamma,
+                traction_nodes=np.ascontiguousarray(tn), traction=np.ascontiguousarray(tt),
+                vbc=_empty_bc(), t_ramp=0.0, notch=notch, dt=0.0, cfl=cfl, steps=steps)
+
+
+def ring_points(r_in, r_out, h, *, jitter=0.2, seed=BASE_SEED + 80):
+    """Points of an annulus: rings at radii r_in + k dr (dr ~ h sqrt(3)/2),
+    ring k with round(2 pi r_k / h) equally spaced points at a random angular
+    offset; the inner and outer rings are exact circles, the others move
+    radially by +/-``jitter`` dr.  Returns (X, Y, ring index)."""
+    nr = max(1, int(round((r_out - r_in) / (h * np.sqrt(3.0) / 2.0))))
+    dr = (r_out - r_in) / nr
+    u = uniform01(seed, 2 * (nr + 1)).reshape(nr + 1, 2)
+    xs, ys, ks = [], [], []
+    for k in range(nr + 1):
+        r = r_in + k * dr
+        n = max(3, int(round(2.0 * np.pi * r / h)))
+        th = 2.0 * np.pi * (np.arange(n) + u[k, 0]) / n
+        rr = r + (0.0 if k in (0, nr) else (2.0 * u[k, 1] - 1.0) * jitter * dr)
+        xs.append(rr * np.cos(th)); ys.append(rr * np.sin(th)); ks.append(np.full(n, k))
+    return np.concatenate(xs), np.concatenate(ys), np.concatenate(ks)
+
+
+def tri_cylinder(r_in=0.05, r_out=0.1, h=1.0e-3, *, p0=400.0e6, t0=1.0e-6, tau=100.0e-6, seed=BASE_SEED + 80,
+                 gamma=1.0, steps=4000, cfl=0.5, name="tri_cylinder"):
+    """The pressure-loaded hollow cylinder of Sec. 4.4 on a CST mesh: steel
+    (E 210 GPa, nu 0.3, rho 7850, Gc 2000 N/m), internal pressure p0 times
+    the pulse history (rise to 1 at t0, decay exp(-(t - t0)/tau)) as a
+    normal traction on the inner boundary edges; no pre-notch.  The default
+    size (about 27 000 nodes / 53 000 triangles) is that of the paper's fine
+    mesh; its radii are not printed and are a reading."""
+    X, Y, ring = ring_points(r_in, r_out, h, seed=seed)
+    T, Ts = _triangulate(X, Y, h)
+    cx = (X[Ts[:, 0]] + X[Ts[:, 1]] + X[Ts[:, 2]]) / 3.0
+    cy = (Y[Ts[:, 0]] + Y[Ts[:, 1]] + Y[Ts[:, 2]]) / 3.0
+    Ts = np.ascontiguousarray(Ts[np.hypot(cx, cy) > r_in])  # drop the hole
+    assert len(np.unique(Ts)) == len(X), "a point fell out of the annulus mesh"
+    be = boundary_edges(Ts)
+    inner = (ring[be[:, 0]] == 0) & (ring[be[:, 1]] == 0)
+    tn = be[inner].astype(np.int32)
+    dx = X[tn[:, 1]] - X[tn[:, 0]]
+    dy = Y[tn[:, 1]] - Y[tn[:, 0]]
+    L = np.hypot(dx, dy)
+    tt = np.stack([-dy / L, dx / L], axis=1) * p0  # pushes the inner wall outward
+    return dict(name=name, conn=Ts, X=X, Y=Y, E=E_STEEL, nu=NU_STEEL, rho=RHO_STEEL,
+                gc_uniform=GC_STEEL, gc_field=None, gamma=gamma,
+                traction_nodes=np.ascontiguousarray(tn), traction=np.ascontiguousarray(tt),
+                vbc=_empty_bc(), t_ramp=0.0, notch=_empty_notch(), dt=0.0, cfl=cfl, steps=steps,
+                load_curve=pressure_pulse(t0=t0, tau=tau))
+
+
+def tri_small_cases():
+    """CST cases the oracle finishes in seconds."""
+    return {
+        "tri_plate40x16": tri_plate(40, 16, 0.1, 0.04, notch_len=0.05, steps=1500, name="tri_plate40x16"),
+        "tri_cylinder_coarse": tri_cylinder(h=5.0e-3, steps=1500, name="tri_cylinder_coarse"),
+        "tri_fragment": tri_fragment(36, 30, 1.0e-3, steps=600, name="tri_fragment"),
+    }
+
+
+def tri_fragment(nx, ny, h, *, v=5.0, seed=BASE_SEED + 90, steps=2000, name="tri_fragment"):
+    """Un-notched CST plate with outward normal velocity on all edges and a
+    Weibull(6, 3 N/m) Gc field (the Dirichlet fragmentation set-up)."""
+    X, Y = grid_coords(nx, ny, nx * h, ny * h, 0.3, seed)
+    T = _triangulate(X, Y, h)[1]
+    lx, ly = nx * h, ny * h
+    nodes, masks, vel = [], [], []
+    for i in range(len(X)):
+        m, vx, vy = 0, 0.0, 0.0
+        if X[i] == 0.0:
+            m |= 1; vx = -v
+        if X[i] == lx:
+            m |= 1; vx = v
+        if Y[i] == 0.0:
+            m |= 2; vy = -v
+        if Y[i] == ly:
+            m |= 2; vy = v
+        if m:
+            nodes.append(i); masks.append(m); vel.append((vx, vy))
+    gcf = weibull_gc(seed + 1, len(T), 6.0, GC_PLATE)
+    return dict(name=name, conn=T, X=X, Y=Y, E=E_PLATE, nu=NU_PLATE, rho=RHO_PLATE,
+                gc_uniform=0.0, gc_field=gcf, gamma=1.0,
+                traction_nodes=np.zeros((0, 2), np.int32), traction=np.zeros((0, 2)),
+                vbc=(np.asarray(nodes, np.int32), np.asarray(masks, np.uint8),
+                     np.ascontiguousarray(np.asarray(vel, np.float64).reshape(-1, 2))),
+                t_ramp=0.0, notch=_empty_notch(), dt=0.0, cfl=0.5, steps=steps)

@@ -1,0 +1,440 @@
+"""Pins of the CPU oracle's CST (unstructured triangle) path against what
+the paper and the mathematics fix.
+
+Each test is chosen so that a plausible slip (a wrong smoothing weight, the
+Q4 factor A/4 in place of A/3, a transposed B, a wrong path orientation or
+piece topology, a wrong element rule for two candidates) fails one of them:
+
+  * mesh tables: Euler's relation, manifold orientation, valid colouring,
+    total area / mass / traction resultant;
+  * patch test: exact edge strain of a linear field and the boundary
+    integral of a constant stress as the nodal force;
+  * stiffness built column by column equals the textbook edge-based ES-FEM
+    stiffness (smoothing domains of one third of each neighbour, shape
+    function gradients from the inverse of the [1 x y] matrix);
+  * static uniaxial solve -> uniform stress equal to the applied traction;
+  * rigid-body invariance with split pieces, strain-energy identity
+    E = u . f(u) / 2, energy conservation of the explicit step;
+  * closed-form G of both CST paths under a uniform stress, the Heaviside
+    gate, the two-candidate element rule (Sec. 2.2 list after Fig. 2-2);
+  * bar piece force of a split triangle in closed form;
+  * crack-log invariants of MCT and SCT runs (free-surface entries, one
+    split per step, U_d bookkeeping, a continuous single-tip path).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2509_01827_amd import workloads as W
+
+
+def _tri(nx=8, ny=5, lx=0.008, ly=0.005, *, traction=0.0, notch=None, jitter=0.3, seed=W.BASE_SEED + 71,
+         gc=3.0, gamma=1.0):
+    c = W.tri_plate(nx, ny, lx, ly, traction=traction, jitter=jitter, seed=seed, notch_len=notch, gc=gc,
+                    gamma=gamma)
+    if traction == 0.0:
+        c["traction_nodes"] = np.zeros((0, 2), np.int32)
+        c["traction"] = np.zeros((0, 2))
+    return c
+
+
+def _stiffness(o):
+    nn = o.info()["nn"]
+    K = np.zeros((2 * nn, 2 * nn))
+    for d in range(2 * nn):
+        u = np.zeros(2 * nn)
+        u[d] = 1.0
+        fx, fy = o.internal_force(u[0::2].copy(), u[1::2].copy())
+        K[0::2, d] = fx
+        K[1::2, d] = fy
+    return K
+
+
+def _D(c):
+    E, nu = c["E"], c["nu"]
+    return E / (1 - nu * nu) * np.array([[1, nu, 0], [nu, 1, 0], [0, 0, (1 - nu) / 2]])
+
+
+def _grad_by_inverse(x, y):
+    """dN/dx, dN/dy of the linear triangle from the inverse of [1 x y]."""
+    M = np.stack([np.ones(3), x, y], axis=1)
+    C = np.linalg.inv(M)
+    return C[1], C[2]
+
+
+def _boundary_normals(c):
+    """Boundary edges (a, b) with the domain on the left and their outward
+    normal times length."""
+    be = W.boundary_edges(c["conn"])
+    X, Y = c["X"], c["Y"]
+    dx = X[be[:, 1]] - X[be[:, 0]]
+    dy = Y[be[:, 1]] - Y[be[:, 0]]
+    return be, np.stack([dy, -dx], axis=1)
+
+
+# ---------------------------------------------------------------- tables
+def test_tri_mesh_tables(oracle_mod):
+    c = _tri(9, 6, 0.009, 0.006, traction=1e6)
+    o = oracle_mod.Oracle(c)
+    inf, t = o.info(), o.tables()
+    assert inf["nv"] == 3
+    assert inf["ns"] == inf["nn"] + inf["ne"] - 1  # Euler, simply connected
+    T = c["conn"]
+    # interior edges: two triangles that run the edge in opposite directions
+    ee, el = t["edge_elem"], t["edge_loc"]
+    both = ee[:, 1] >= 0
+    for s in np.where(both)[0]:
+        e0, e1 = ee[s]
+        k0, k1 = el[s]
+        assert T[e0, k0] == T[e1, (k1 + 1) % 3] and T[e0, (k0 + 1) % 3] == T[e1, k1]
+    assert (~both).sum() == len(W.boundary_edges(T))
+    # colouring: no two elements of one colour share a node
+    col = t["color"]
+    for n in range(inf["nn"]):
+        touching = np.where((T == n).any(axis=1))[0]
+        assert len(set(col[touching])) == len(touching)
+    assert t["area"].min() > 0
+    assert t["area"].sum() == pytest.approx(0.009 * 0.006, rel=1e-13)
+    assert t["mass"].sum() == pytest.approx(c["rho"] * 0.009 * 0.006, rel=1e-13)
+    fy = t["fext"][:, 1]
+    top = np.where(c["Y"] == 0.006)[0]
+    assert fy[top].sum() == pytest.approx(1e6 * 0.009, rel=1e-13)
+    assert np.abs(t["fext"].sum(axis=0)).max() < 1e-9
+    # time step from the shortest edge
+    en = t["edge_node"]
+    X, Y = c["X"], c["Y"]
+    L = np.hypot(X[en[:, 1]] - X[en[:, 0]], Y[en[:, 1]] - Y[en[:, 0]])
+    cd = np.sqrt(c["E"] / (c["rho"] * (1 - c["nu"] ** 2)))
+    assert inf["dt"] == pytest.approx(0.5 * L.min() / cd, rel=1e-14)
+    # lumped mass: one third of each touching triangle
+    A = t["area"]
+    m = np.zeros(inf["nn"])
+    for e in range(inf["ne"]):
+        m[T[e]] += c["rho"] * A[e] / 3.0
+    np.testing.assert_allclose(t["mass"], m, rtol=1e-13)
+
+
+def test_tri_cylinder_tables_and_pressure_resultant(oracle_mod):
+    c = W.tri_cylinder(h=6e-3)
+    o = oracle_mod.Oracle(c)
+    inf, t = o.info(), o.tables()
+    assert inf["ns"] == inf["nn"] + inf["ne"]  # one hole
+    X, Y, ring = W.ring_points(0.05, 0.1, 6e-3)
+
+    def poly_area(sel):
+        th = np.arctan2(Y[sel], X[sel])
+        o_ = np.argsort(th)
+        x, y = X[sel][o_], Y[sel][o_]
+        return 0.5 * np.sum(x * np.roll(y, -1) - np.roll(x, -1) * y)
+
+    A = poly_area(ring == ring.max()) - poly_area(ring == 0)
+    assert t["area"].sum() == pytest.approx(A, rel=1e-12)
+    # the internal pressure is self-equilibrated; its radial resultant per
+    # unit angle is p r
+    fe = t["fext"]
+    assert np.abs(fe.sum(axis=0)).max() < 1e-6 * 400e6 * 0.05
+    inner = np.where(ring == 0)[0]
+    radial = (fe[inner, 0] * X[inner] + fe[inner, 1] * Y[inner]) / np.hypot(X[inner], Y[inner])
+    assert radial.sum() == pytest.approx(400e6 * 2 * np.pi * 0.05, rel=5e-3)
+    assert (radial > 0).all()
+
+
+# ------------------------------------------------------------ patch tests
+def test_tri_patch_linear_field(oracle_mod):
+    c = _tri(9, 6, 0.009, 0.006)
+    o = oracle_mod.Oracle(c)
+    X, Y = c["X"], c["Y"]
+    a = (1e-4, 2e-3, -3e-3)
+    b = (-2e-4, 1.5e-3, 4e-3)
+    ux = a[0] + a[1] * X + a[2] * Y
+    uy = b[0] + b[1] * X + b[2] * Y
+    fx, fy, sig, ok = o.internal_force(ux, uy, with_stress=True)
+    eps = np.array([a[1], b[2], a[2] + b[1]])
+    s_exp = _D(c) @ eps
+    assert ok.all()
+    np.testing.assert_allclose(sig, np.broadcast_to(s_exp, sig.shape), rtol=1e-9,
+                               atol=1e-9 * np.abs(s_exp).max())
+    # f_int = boundary integral of N^T sigma n: each boundary edge gives
+    # (sigma n) L / 2 to both of its nodes, interior nodes get nothing
+    be, nL = _boundary_normals(c)
+    S = np.array([[s_exp[0], s_exp[2]], [s_exp[2], s_exp[1]]])
+    want = np.zeros((len(X), 2))
+    for (p, q), v in zip(be, nL):
+        want[p] += 0.5 * S @ v
+        want[q] += 0.5 * S @ v
+    got = np.stack([fx, fy], axis=1)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-9 * np.abs(want).max())
+
+
+def test_tri_rigid_body_motion_gives_zero_force(oracle_mod):
+    c = _tri(9, 7, 0.009, 0.007, notch=0.005)
+    assert len(c["notch"][0]) >= 3
+    o = oracle_mod.Oracle(c)
+    X, Y = c["X"], c["Y"]
+    fmag = np.abs(np.concatenate(o.internal_force(1e-3 * X, 0 * Y))).max()
+    for ux, uy in [(np.full_like(X, 1e-4), np.full_like(X, -2e-4)),
+                   (-1e-3 * (Y - 0.003), 1e-3 * (X - 0.0045))]:
+        fx, fy = o.internal_force(ux, uy)
+        assert np.abs(np.concatenate([fx, fy])).max() < 1e-11 * fmag
+
+
+def test_tri_stiffness_equals_edge_based_esfem(oracle_mod):
+    c = _tri(6, 4, 0.006, 0.004)
+    o = oracle_mod.Oracle(c)
+    K = _stiffness(o)
+    X, Y, T = c["X"], c["Y"], c["conn"]
+    nn = len(X)
+    D = _D(c)
+    A = np.array([0.5 * abs(np.linalg.det(np.stack([np.ones(3), X[t], Y[t]], axis=1))) for t in T])
+    # textbook ES-FEM: smoothing domain of edge s = one third of each
+    # neighbouring triangle; smoothed B = area-weighted mean of the B_j
+    edges = {}
+    for e, t in enumerate(T):
+        for k in range(3):
+            key = tuple(sorted((int(t[k]), int(t[(k + 1) % 3]))))
+            edges.setdefault(key, []).append(e)
+    Kr = np.zeros((2 * nn, 2 * nn))
+    for key, els in edges.items():
+        As = sum(A[e] / 3.0 for e in els)
+        Bs = np.zeros((3, 2 * nn))
+        for e in els:
+            bx, by = _grad_by_inverse(X[T[e]], Y[T[e]])
+            w = (A[e] / 3.0) / As
+            for n in range(3):
+                g = T[e, n]
+                Bs[0, 2 * g] += w * bx[n]
+                Bs[1, 2 * g + 1] += w * by[n]
+                Bs[2, 2 * g] += w * by[n]
+                Bs[2, 2 * g + 1] += w * bx[n]
+        Kr += As * Bs.T @ D @ Bs
+    assert np.abs(K - Kr).max() <= 1e-11 * np.abs(Kr).max()
+    lam = np.linalg.eigvalsh(0.5 * (K + K.T))
+    assert (np.abs(lam) < 1e-9 * lam.max()).sum() == 3
+    assert lam.min() > -1e-9 * lam.max()
+
+
+def test_tri_uniaxial_static_stress(oracle_mod):
+    sig0 = 1.0e6
+    c = _tri(7, 5, 0.007, 0.005, traction=sig0)
+    o = oracle_mod.Oracle(c)
+    K = _stiffness(o)
+    f = o.tables()["fext"].reshape(-1)
+    # remove the rigid modes: fix x and y of node 0 (corner (0, 0)) and y of
+    # node 7 (corner (lx, 0)), which the uniform solution leaves at rest
+    fix = [0, 1, 2 * 7 + 1]
+    free = np.setdiff1d(np.arange(len(f)), fix)
+    u = np.zeros(len(f))
+    u[free] = np.linalg.solve(K[np.ix_(free, free)], f[free])
+    _, _, sig, ok = o.internal_force(u[0::2].copy(), u[1::2].copy(), with_stress=True)
+    assert ok.all()
+    np.testing.assert_allclose(sig[:, 1], sig0, rtol=1e-8)
+    assert np.abs(sig[:, [0, 2]]).max() < 1e-8 * sig0
+
+
+# ------------------------------------------------------------- energies
+def test_tri_strain_energy_identity(oracle_mod):
+    for notch in (None, 0.005):
+        c = _tri(9, 7, 0.009, 0.007, notch=notch)
+        o = oracle_mod.Oracle(c)
+        rng = np.random.default_rng(3)
+        ux = rng.standard_normal(len(c["X"])) * 1e-6
+        uy = rng.standard_normal(len(c["X"])) * 1e-6
+        o.set_state(ux, uy, np.zeros_like(ux), np.zeros_like(ux))
+        fx, fy = o.internal_force(ux, uy)
+        e = o.energies()
+        assert e["strain"] == pytest.approx(0.5 * (ux @ fx + uy @ fy), rel=1e-12)
+        assert e["kin"] == 0.0
+
+
+def test_tri_energy_conservation(oracle_mod):
+    c = _tri(10, 6, 0.01, 0.006, gc=1e12)
+    drift = []
+    for refine in (1, 2):
+        o = oracle_mod.Oracle(dict(c, cfl=0.5 / refine))
+        X, Y = c["X"], c["Y"]
+        vx = 0.3 * np.sin(np.pi * X / 0.01) * np.cos(np.pi * Y / 0.006)
+        vy = -0.2 * np.cos(np.pi * X / 0.01) * np.sin(2 * np.pi * Y / 0.006)
+        o.set_state(np.zeros_like(X), np.zeros_like(X), vx, vy)
+        e0 = o.energies()
+        E0 = e0["kin"] + e0["strain"]
+        dev = 0.0
+        for _ in range(10):
+            o.step(40 * refine)
+            e = o.energies()
+            dev = max(dev, abs(e["kin"] + e["strain"] - E0) / E0)
+        drift.append(dev)
+    assert drift[0] < 5e-3
+    assert drift[1] < drift[0] / 2.5  # second order in dt
+
+
+# ------------------------------------------------------ fracture pieces
+RULE2 = [
+    ([1.0, 2.0], 3.0, 1.0, -1),  # neither over Gc
+    ([4.0, 2.0], 3.0, 1.0, 0),  # only G1
+    ([2.0, 4.0], 3.0, 1.0, 1),  # only G2
+    ([5.0, 4.0], 3.0, 1.0, 0),  # both: 5 > 1*(5-4) -> G1
+    ([5.0, 4.0], 3.0, 6.0, -1),  # both: 5 > 6*1 fails -> none
+    ([5.0, 4.0], 3.0, 4.0, 0),  # 5 > 4*1 -> G1
+    ([4.0, 4.0], 3.0, 1.0, 0),  # tie: first path (5 > 0 holds)
+    ([3.0, 3.0 + 1e-12], 3.0, 1.0, 1),  # strict '>' at Gc
+]
+
+
+@pytest.mark.parametrize("G,Gc,gamma,exp", RULE2)
+def test_tri_element_rule_two_paths(oracle_mod, G, Gc, gamma, exp):
+    assert oracle_mod.element_rule_n(G, Gc, gamma) == exp
+    # a third, absent path (G = 0) never changes the two-path decision
+    assert oracle_mod.element_rule(G + [0.0], Gc, gamma) == exp
+
+
+def _midpoint(X, Y, p, q):
+    return np.array([0.5 * (X[p] + X[q]), 0.5 * (Y[p] + Y[q])])
+
+
+def test_tri_G_closed_form_uniform_stress(oracle_mod):
+    c = _tri(9, 7, 0.009, 0.007, notch=0.005)
+    o = oracle_mod.Oracle(c)
+    X, Y, T = c["X"], c["Y"], c["conn"]
+    eps = np.array([1e-3, 2.5e-3, 0.8e-3])
+    ux = eps[0] * X + 0.5 * eps[2] * Y
+    uy = eps[1] * Y + 0.5 * eps[2] * X
+    o.set_state(ux, uy, np.zeros_like(X), np.zeros_like(X))
+    s = _D(c) @ eps
+    S = np.array([[s[0], s[2]], [s[2], s[1]]])
+    cand = o.candidates()
+    assert len(cand["elem"]) > 10
+    checked = 0
+    for f, a, G in zip(cand["elem"], cand["a"], cand["G"]):
+        n1, n2 = T[f, a], T[f, (a + 1) % 3]
+        d = np.array([ux[n2] - ux[n1], uy[n2] - uy[n1]])
+        stretched = np.hypot(X[n2] + ux[n2] - X[n1] - ux[n1], Y[n2] + uy[n2] - Y[n1] - uy[n1]) > \
+            np.hypot(X[n2] - X[n1], Y[n2] - Y[n1])
+        g0 = _midpoint(X, Y, n1, n2)
+        for j in range(2):
+            k = (a + 1 + j) % 3
+            gk = _midpoint(X, Y, T[f, k], T[f, (k + 1) % 3])
+            t = gk - g0
+            n = np.array([t[1], -t[0]]) / np.hypot(*t)
+            if n @ (np.array([X[n2], Y[n2]]) - g0) < 0:
+                n = -n
+            want = 0.5 * d @ (S @ n) if stretched else 0.0
+            assert G[j] == pytest.approx(want, rel=1e-9, abs=1e-12 * abs(s).max() * 1e-3)
+        assert G[2] == 0.0
+        checked += stretched
+    assert checked > 5
+    # compression closes every gate
+    o.set_state(-ux, -uy, np.zeros_like(X), np.zeros_like(X))
+    assert np.all(o.candidates()["G"] == 0.0)
+
+
+def test_tri_split_triangle_pieces(oracle_mod):
+    X = np.array([0.0, 2e-3, 0.6e-3])
+    Y = np.array([0.0, 0.3e-3, 1.7e-3])
+    A = 0.5 * ((X[1] - X[0]) * (Y[2] - Y[0]) - (X[2] - X[0]) * (Y[1] - Y[0]))
+    E = W.E_PLATE
+    for a in range(3):
+        for k in range(3):
+            if k == a:
+                continue
+            c = dict(name="one", conn=np.array([[0, 1, 2]], np.int32), X=X, Y=Y, E=E, nu=0.2, rho=2450.0,
+                     gc_uniform=3.0, gc_field=None, gamma=1.0, traction_nodes=np.zeros((0, 2), np.int32),
+                     traction=np.zeros((0, 2)), vbc=W._empty_bc(), t_ramp=0.0,
+                     notch=(np.array([0], np.int32), np.array([a], np.uint8), np.array([k], np.uint8)),
+                     dt=0.0, cfl=0.5, steps=1)
+            o = oracle_mod.Oracle(c)
+            # the lone node: the node shared by edges a and k
+            lone = k if (a + 1) % 3 == k else a
+            p, q = [n for n in range(3) if n != lone]
+            d = np.array([X[q] - X[p], Y[q] - Y[p]])
+            L = np.hypot(*d)
+            delta = 1e-6
+            ux = np.zeros(3)
+            uy = np.zeros(3)
+            ux[q], uy[q] = delta * d / L
+            fx, fy = o.internal_force(ux, uy)
+            F = E * (0.75 * A) * delta / L ** 2
+            np.testing.assert_allclose([fx[q], fy[q]], F * d / L, rtol=1e-12)
+            np.testing.assert_allclose([fx[p], fy[p]], -F * d / L, rtol=1e-12)
+            assert fx[lone] == 0.0 and fy[lone] == 0.0
+            # rigid motions of the pieces give no force
+            for rx, ry in [(np.full(3, 1e-5), np.full(3, -3e-6)), (-1e-3 * Y, 1e-3 * X)]:
+                gx, gy = o.internal_force(rx, ry)
+                assert np.abs(np.concatenate([gx, gy])).max() < 1e-10 * F
+
+
+# ------------------------------------------------------- run invariants
+def _path_len(X, Y, T, f, a, k):
+    g0 = _midpoint(X, Y, T[f, a], T[f, (a + 1) % 3])
+    g1 = _midpoint(X, Y, T[f, k], T[f, (k + 1) % 3])
+    return math.hypot(*(g1 - g0))
+
+
+def _nbr(T):
+    m = {}
+    for e, t in enumerate(T):
+        for k in range(3):
+            m.setdefault(tuple(sorted((int(t[k]), int(t[(k + 1) % 3])))), []).append((e, k))
+    return m
+
+
+def test_tri_mct_crack_log_invariants(oracle_mod):
+    c = W.tri_small_cases()["tri_plate40x16"]
+    o = oracle_mod.run(c, 600)
+    lg = o.log()
+    X, Y, T = c["X"], c["Y"], c["conn"]
+    assert len(lg["elem"]) > 20
+    assert np.all(np.diff(lg["step"]) > 0)  # one split per step
+    split_at = {int(e): -1 for e in c["notch"][0]}
+    for s, e in zip(lg["step"], lg["elem"]):
+        split_at[int(e)] = int(s)
+    em = _nbr(T)
+    Ud = 0.0
+    for s, e, a, k, G in zip(lg["step"], lg["elem"], lg["entry"], lg["exit"], lg["G"]):
+        assert G > c["gc_uniform"] and a != k
+        key = tuple(sorted((int(T[e, a]), int(T[e, (a + 1) % 3]))))
+        others = [u for u, _ in em[key] if u != e]
+        # entry edge was a free surface: boundary, or the neighbour split earlier
+        assert not others or (others[0] in split_at and split_at[others[0]] < s)
+        Ud += c["gc_uniform"] * _path_len(X, Y, T, e, a, k)
+    assert o.info()["Ud"] == pytest.approx(Ud, rel=1e-12)
+
+
+def test_tri_sct_path_is_continuous(oracle_mod):
+    c = dict(W.tri_small_cases()["tri_plate40x16"], tracking=("sct", -1, 0))
+    o = oracle_mod.Oracle(c)
+    T = c["conn"]
+    em = _nbr(T)
+    ne_, en_, ex_ = c["notch"]
+    last = (int(ne_[-1]), int(ex_[-1]))
+    tip = o.tip()
+    key = tuple(sorted((int(T[last[0], last[1]]), int(T[last[0], (last[1] + 1) % 3]))))
+    assert tip in [u for u in em[key] if u[0] != last[0]]
+    o.step(1500)
+    lg = o.log()
+    assert len(lg["elem"]) > 3
+    prev = last
+    for e, a, k in zip(lg["elem"], lg["entry"], lg["exit"]):
+        key = tuple(sorted((int(T[prev[0], prev[1]]), int(T[prev[0], (prev[1] + 1) % 3]))))
+        assert (int(e), int(a)) in em[key]
+        prev = (int(e), int(k))
+
+
+def test_tri_invalid_meshes_rejected(oracle_mod):
+    X = np.array([0.0, 1.0, 1.0, 0.0, 0.5])
+    Y = np.array([0.0, 0.0, 1.0, 1.0, 0.5])
+    base = dict(name="bad", X=X, Y=Y, E=1e9, nu=0.2, rho=1000.0, gc_uniform=1.0, gc_field=None, gamma=1.0,
+                traction_nodes=np.zeros((0, 2), np.int32), traction=np.zeros((0, 2)), vbc=W._empty_bc(),
+                t_ramp=0.0, notch=W._empty_notch(), dt=0.0, cfl=0.5, steps=1)
+    good = np.array([[0, 1, 4], [1, 2, 4], [2, 3, 4], [3, 0, 4]], np.int32)
+    oracle_mod.Oracle(dict(base, conn=good))
+    for conn in (good[:, [0, 2, 1]],  # clockwise: negative areas
+                 np.array([[0, 1, 1]] + good[1:].tolist(), np.int32),  # repeated node
+                 np.array([[0, 1, 4], [0, 1, 4], [2, 3, 4], [3, 0, 4]], np.int32),  # edge twice one way
+                 np.array([[0, 1, 4], [1, 2, 4], [2, 3, 4], [3, 0, 4], [0, 1, 2]], np.int32)):  # third use
+        with pytest.raises(ValueError):
+            oracle_mod.Oracle(dict(base, conn=conn))
+    X5 = np.append(X, 2.0)
+    Y5 = np.append(Y, 2.0)
+    with pytest.raises(ValueError):  # a node in no element
+        oracle_mod.Oracle(dict(base, X=X5, Y=Y5, conn=good))
