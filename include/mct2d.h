@@ -106,6 +106,27 @@ const char *mct_last_error(const mct_ctx *ctx);
  * Resets material, loads, notch and time settings. */
 int mct_set_mesh_grid(mct_ctx *ctx, int32_t nx, int32_t ny, const double *X, const double *Y);
 
+/* Mesh of constant-strain triangles (CST, the element of the paper's
+ * examples; Sec. 2.1, Eqs. CST_strain_discretization and
+ * CST_fint_discretization; Sec. 2.2, the two-path rule after Fig. 2-2):
+ * n_nodes reference coordinates X, Y and n_elems counter-clockwise node
+ * triples conn[3 e + 0..2] of an unstructured mesh (plain contexts only).
+ * Local edge k joins local nodes k and (k+1) % 3; split codes and crack
+ * records use these local edges (entry/exit in 0..2).  Element ids, edge
+ * ids (sorted node pairs) and node ids are the caller's; the library does
+ * not renumber, so a locality-preserving element order (e.g. along a
+ * space-filling curve) is the caller's choice and pays in cache reuse.
+ * After this call the context runs the CST path: every set-up call, step
+ * and query below applies to the triangle mesh, except the tile shapes
+ * (mct_set_launch accepts tile 0 only), mct_autotune, mct_get_path_geometry
+ * and the split-screen (MCT_EUNSUPPORTED).  Velocity conditions may be
+ * prescribed at any node.  Errors: MCT_EINVAL for an index out of range, a
+ * repeated node, a non-positive area (clockwise or degenerate), an edge
+ * used by more than two triangles or twice in one direction, a node in no
+ * triangle; MCT_EUNSUPPORTED on a batch context. */
+int mct_set_mesh_tri(mct_ctx *ctx, int64_t n_nodes, const double *X, const double *Y, int64_t n_elems,
+                     const int32_t *conn);
+
 /* Linear elastic plane-stress material (Young's modulus E, Poisson ratio
  * nu, density rho) and critical energy release rate: Gc[e] per element
  * (n_elems values) or, if Gc is NULL, Gc_uniform everywhere.  gamma is the

@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "mct2d_impl.h"
+#include "mct2d_tri_host.h"
 
 using mct::Control;
 using mct::LogRec;
@@ -106,6 +107,10 @@ struct mct_ctx {
     double *dpow = nullptr;    // power iteration: y, u, z, scratch (2 nn_max each)
     int32_t *dflag = nullptr;  // non-finite watchdog
 
+    // CST path: set by mct_set_mesh_tri (plain contexts only); the ABI
+    // forwards every call of such a context to it
+    mct::tri::Model *tri = nullptr;
+
     // learned split-screen (plain contexts only)
     bool screen_alloc = false, screen_on = false;
     int screen_period = 50;
@@ -143,6 +148,20 @@ int fail(mct_ctx *c, int code, const char *fmt, ...) {
         hipError_t e_ = (expr);                                                                     \
         if (e_ != hipSuccess)                                                                       \
             return fail((ctx), MCT_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));               \
+    } while (0)
+
+// Forward a call of a CST context to the triangle path.
+#define TRI_FWD(c, fn, ...)                                               \
+    do {                                                                 \
+        if ((c)->tri) return mct::tri::fn(*(c)->tri, mct::tri::Host{(c)->err, (c)->stream}, __VA_ARGS__); \
+    } while (0)
+#define TRI_FWD0(c, fn)                                                  \
+    do {                                                                 \
+        if ((c)->tri) return mct::tri::fn(*(c)->tri, mct::tri::Host{(c)->err, (c)->stream}); \
+    } while (0)
+#define TRI_UNSUPPORTED(c, what)                                                     \
+    do {                                                                             \
+        if ((c)->tri) return fail((c), MCT_EUNSUPPORTED, "%s: not for a triangle mesh", what); \
     } while (0)
 
 template <typename T>
@@ -682,6 +701,11 @@ int mct_batch_select(mct_ctx *c, int64_t s) {
 
 int mct_destroy(mct_ctx *c) {
     if (!c) return MCT_OK;
+    if (c->tri) {
+        mct::tri::release(*c->tri);
+        delete c->tri;
+        c->tri = nullptr;
+    }
     release_device(c);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
@@ -690,8 +714,31 @@ int mct_destroy(mct_ctx *c) {
 
 const char *mct_last_error(const mct_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
+int mct_set_mesh_tri(mct_ctx *c, int64_t n_nodes, const double *X, const double *Y, int64_t n_elems,
+                     const int32_t *conn) {
+    if (!c) return MCT_EINVAL;
+    if (c->batch) return fail(c, MCT_EUNSUPPORTED, "triangle meshes need a plain context");
+    release_device(c);
+    c->specs.assign(1, Spec{});
+    c->finalized = false;
+    if (!c->tri) c->tri = new (std::nothrow) mct::tri::Model;
+    if (!c->tri) return MCT_ENOMEM;
+    const int rc = mct::tri::set_mesh(*c->tri, mct::tri::Host{c->err, c->stream}, n_nodes, X, Y, n_elems, conn);
+    if (rc) {
+        mct::tri::release(*c->tri);
+        delete c->tri;
+        c->tri = nullptr;
+    }
+    return rc;
+}
+
 int mct_set_mesh_grid(mct_ctx *c, int32_t nx, int32_t ny, const double *X, const double *Y) {
     if (!c) return MCT_EINVAL;
+    if (c->tri) {
+        mct::tri::release(*c->tri);
+        delete c->tri;
+        c->tri = nullptr;
+    }
     if (nx < 2 || ny < 2 || !X || !Y) return fail(c, MCT_EINVAL, "grid needs nx, ny >= 2 and coordinates");
     // element ids, and element * 4 + local edge keys, stay in int32
     if ((int64_t)nx * ny > (int64_t)1 << 29) return fail(c, MCT_EINVAL, "grid too large (more than 2^29 elements)");
@@ -715,6 +762,7 @@ int mct_set_mesh_grid(mct_ctx *c, int32_t nx, int32_t ny, const double *X, const
 int mct_set_material(mct_ctx *c, double E, double nu, double rho, const double *Gc, double Gc_uniform,
                      double gamma) {
     if (!c) return MCT_EINVAL;
+    TRI_FWD(c, set_material, E, nu, rho, Gc, Gc_uniform, gamma);
     Spec &s = cur(c);
     if (!s.nx) return fail(c, MCT_ESTATE, "set the mesh first");
     if (!(E > 0) || !(nu > -1.0 && nu < 0.5) || !(rho > 0) || !(gamma > 0))
@@ -739,6 +787,7 @@ int mct_set_material(mct_ctx *c, double E, double nu, double rho, const double *
 
 int mct_set_traction(mct_ctx *c, int64_t n, const int32_t *edge_nodes, const double *t) {
     if (!c) return MCT_EINVAL;
+    TRI_FWD(c, set_traction, n, edge_nodes, t);
     Spec &s = cur(c);
     if (!s.nx) return fail(c, MCT_ESTATE, "set the mesh first");
     if (n < 0 || (n && (!edge_nodes || !t))) return fail(c, MCT_EINVAL, "bad traction arrays");
@@ -763,6 +812,7 @@ int mct_set_traction(mct_ctx *c, int64_t n, const int32_t *edge_nodes, const dou
 int mct_set_velocity_bc(mct_ctx *c, int64_t n, const int32_t *node, const uint8_t *dof_mask, const double *v0,
                         double t_ramp) {
     if (!c) return MCT_EINVAL;
+    TRI_FWD(c, set_velocity_bc, n, node, dof_mask, v0, t_ramp);
     Spec &s = cur(c);
     if (!s.nx) return fail(c, MCT_ESTATE, "set the mesh first");
     if (n < 0 || (n && (!node || !dof_mask || !v0)) || !(t_ramp >= 0))
@@ -784,6 +834,7 @@ int mct_set_velocity_bc(mct_ctx *c, int64_t n, const int32_t *node, const uint8_
 
 int mct_set_notch(mct_ctx *c, int64_t n, const int32_t *elem, const uint8_t *entry, const uint8_t *exit) {
     if (!c) return MCT_EINVAL;
+    TRI_FWD(c, set_notch, n, elem, entry, exit);
     Spec &s = cur(c);
     if (!s.nx) return fail(c, MCT_ESTATE, "set the mesh first");
     if (n < 0 || (n && (!elem || !entry || !exit))) return fail(c, MCT_EINVAL, "bad notch arrays");
@@ -803,6 +854,7 @@ int mct_set_notch(mct_ctx *c, int64_t n, const int32_t *elem, const uint8_t *ent
 
 int mct_set_load_curve(mct_ctx *c, int64_t n, const double *t, const double *phi) {
     if (!c) return MCT_EINVAL;
+    TRI_FWD(c, set_load_curve, n, t, phi);
     Spec &s = cur(c);
     if (n != 0 && (n < 2 || n > (1 << 20) || !t || !phi)) return fail(c, MCT_EINVAL, "load curve needs 2..2^20 points");
     for (int64_t i = 0; i < n; ++i) {
@@ -817,6 +869,7 @@ int mct_set_load_curve(mct_ctx *c, int64_t n, const double *t, const double *phi
 
 int mct_set_tracking(mct_ctx *c, int mode, int32_t tip_elem, int tip_edge) {
     if (!c) return MCT_EINVAL;
+    TRI_FWD(c, set_tracking, mode, tip_elem, tip_edge);
     Spec &s = cur(c);
     if (!s.nx) return fail(c, MCT_ESTATE, "set the mesh first");
     if (mode != MCT_TRACK_MCT && mode != MCT_TRACK_SCT) return fail(c, MCT_EINVAL, "unknown tracking mode %d", mode);
@@ -831,6 +884,7 @@ int mct_set_tracking(mct_ctx *c, int mode, int32_t tip_elem, int tip_edge) {
 
 int mct_set_time(mct_ctx *c, double dt, double cfl_fraction) {
     if (!c) return MCT_EINVAL;
+    TRI_FWD(c, set_time, dt, cfl_fraction);
     if (!(dt > 0) && !(cfl_fraction > 0)) return fail(c, MCT_EINVAL, "need dt > 0 or cfl_fraction > 0");
     Spec &s = cur(c);
     s.dt_in = dt;
@@ -841,6 +895,12 @@ int mct_set_time(mct_ctx *c, double dt, double cfl_fraction) {
 
 int mct_set_launch(mct_ctx *c, int tile, int use_graph) {
     if (!c) return MCT_EINVAL;
+    if (c->tri) {
+        // one launch shape (a thread per element / node); tile 0 only
+        if (tile != 0) return fail(c, MCT_EINVAL, "a triangle mesh has no tile shapes (tile 0 only)");
+        c->tri->use_graph = use_graph != 0;
+        return MCT_OK;
+    }
     if (tile < 0 || tile > mct::kNumTiles) return fail(c, MCT_EINVAL, "tile index out of range");
     c->tile_req = tile;
     c->use_graph = use_graph != 0;
@@ -849,6 +909,7 @@ int mct_set_launch(mct_ctx *c, int tile, int use_graph) {
 
 int mct_set_order(mct_ctx *c, int order) {
     if (!c) return MCT_EINVAL;
+    if (c->tri) return order == -1 || order == 0 ? MCT_OK : fail(c, MCT_EINVAL, "order out of range");
     if (order < -1 || order >= kNumOrders) return fail(c, MCT_EINVAL, "order out of range");
     c->order_req = order;
     return set_launch_geometry(c);
@@ -856,6 +917,7 @@ int mct_set_order(mct_ctx *c, int order) {
 
 int mct_finalize(mct_ctx *c) {
     if (!c) return MCT_EINVAL;
+    TRI_FWD0(c, finalize);
     for (size_t q = 0; q < c->specs.size(); ++q)
         if (!c->specs[q].nx || !c->specs[q].have_material)
             return fail(c, MCT_ESTATE, "specimen %zu: mesh and material are required", q);
@@ -1048,6 +1110,7 @@ int mct_finalize(mct_ctx *c) {
 
 int mct_step(mct_ctx *c, int64_t n) {
     if (!c) return MCT_EINVAL;
+    TRI_FWD(c, step, n);
     if (!c->finalized) return fail(c, MCT_ESTATE, "finalize first");
     if (n < 0) return fail(c, MCT_EINVAL, "negative step count");
     if (c->screen_on) return step_screened(c, n);
@@ -1079,6 +1142,7 @@ int mct_step(mct_ctx *c, int64_t n) {
 
 int mct_sync(mct_ctx *c) {
     if (!c) return MCT_EINVAL;
+    TRI_FWD0(c, sync);
     if (c->finalized) {
         // watchdog: every displacement and velocity of the current step finite
         int rc = ensure_eval(c);
@@ -1101,6 +1165,7 @@ int mct_sync(mct_ctx *c) {
 
 int mct_get_info(mct_ctx *c, mct_info *out) {
     if (!c || !out) return MCT_EINVAL;
+    TRI_FWD(c, get_info, out);
     std::memset(out, 0, sizeof *out);
     const Spec &s = cur(c);
     out->n_nodes = s.nn;
@@ -1124,6 +1189,7 @@ int mct_get_info(mct_ctx *c, mct_info *out) {
 int mct_get_crack_set(mct_ctx *c, int64_t cap, int32_t *step, int32_t *elem, uint8_t *entry, uint8_t *exit,
                       double *G, int64_t *count) {
     if (!c || !count) return MCT_EINVAL;
+    TRI_FWD(c, get_crack_set, cap, step, elem, entry, exit, G, count);
     if (!c->finalized) return fail(c, MCT_ESTATE, "finalize first");
     const Spec &s = cur(c);
     Control h;
@@ -1149,6 +1215,7 @@ int mct_get_crack_set(mct_ctx *c, int64_t cap, int32_t *step, int32_t *elem, uin
 
 int mct_get_tips(mct_ctx *c, int64_t cap, int32_t *edge, double *xy, int64_t *count) {
     if (!c || !count) return MCT_EINVAL;
+    TRI_FWD(c, get_tips, cap, edge, xy, count);
     if (!c->finalized) return fail(c, MCT_ESTATE, "finalize first");
     const Spec &s = cur(c);
     int32_t nb = 0, total = 0;
@@ -1181,6 +1248,7 @@ int mct_get_tips(mct_ctx *c, int64_t cap, int32_t *edge, double *xy, int64_t *co
 
 int mct_get_field(mct_ctx *c, int which, int64_t cap, double *out) {
     if (!c || !out) return MCT_EINVAL;
+    TRI_FWD(c, get_field, which, cap, out);
     if (!c->finalized) return fail(c, MCT_ESTATE, "finalize first");
     const Spec &s = cur(c);
     int64_t need;
@@ -1232,6 +1300,7 @@ int mct_get_field(mct_ctx *c, int which, int64_t cap, double *out) {
 
 int mct_get_energies(mct_ctx *c, double out[4]) {
     if (!c || !out) return MCT_EINVAL;
+    TRI_FWD(c, get_energies, out);
     if (!c->finalized) return fail(c, MCT_ESTATE, "finalize first");
     int rc = ensure_eval(c);
     if (rc) return rc;
@@ -1254,6 +1323,7 @@ int mct_get_energies(mct_ctx *c, double out[4]) {
 
 int mct_get_path_geometry(mct_ctx *c, int64_t n, const int32_t *elem, double *out) {
     if (!c || n < 0 || (n && (!elem || !out))) return MCT_EINVAL;
+    TRI_UNSUPPORTED(c, "path geometry");
     if (!c->finalized) return fail(c, MCT_ESTATE, "finalize first");
     const Spec &s = cur(c);
     if (n > INT32_MAX / 36) return fail(c, MCT_EINVAL, "too many elements");
@@ -1280,6 +1350,7 @@ int mct_get_path_geometry(mct_ctx *c, int64_t n, const int32_t *elem, double *ou
 
 int mct_get_split_codes(mct_ctx *c, int64_t cap, uint8_t *out) {
     if (!c || !out) return MCT_EINVAL;
+    TRI_FWD(c, get_split_codes, cap, out);
     if (!c->finalized) return fail(c, MCT_ESTATE, "finalize first");
     const Spec &s = cur(c);
     if (cap < s.ne) return fail(c, MCT_ECAPACITY, "need %lld bytes", (long long)s.ne);
@@ -1294,6 +1365,7 @@ static const uint64_t kMagic = 0x4d43543244434b32ull;  // "MCT2DCK2"
 
 int mct_checkpoint(mct_ctx *c, void *buf, int64_t cap, int64_t *bytes) {
     if (!c || !bytes) return MCT_EINVAL;
+    TRI_FWD(c, checkpoint, buf, cap, bytes);
     if (!c->finalized) return fail(c, MCT_ESTATE, "finalize first");
     const int S = (int)c->specs.size();
     std::vector<Control> h(S);
@@ -1337,6 +1409,7 @@ int mct_checkpoint(mct_ctx *c, void *buf, int64_t cap, int64_t *bytes) {
 
 int mct_restore(mct_ctx *c, const void *buf, int64_t bytes) {
     if (!c || !buf) return MCT_EINVAL;
+    TRI_FWD(c, restore, buf, bytes);
     if (!c->finalized) return fail(c, MCT_ESTATE, "finalize first");
     const char *p = (const char *)buf, *end = p + bytes;
     const int S = (int)c->specs.size();
@@ -1396,6 +1469,7 @@ int mct_restore(mct_ctx *c, const void *buf, int64_t bytes) {
 
 int mct_autotune(mct_ctx *c, int trial_steps, int *tile_out, int *order_out, double *us_per_step_out) {
     if (!c) return MCT_EINVAL;
+    TRI_UNSUPPORTED(c, "autotune");
     if (!c->finalized) return fail(c, MCT_ESTATE, "finalize first");
     if (trial_steps < 1) return fail(c, MCT_EINVAL, "trial_steps must be positive");
     int64_t bytes = 0;
@@ -1452,6 +1526,12 @@ int mct_autotune(mct_ctx *c, int trial_steps, int *tile_out, int *order_out, dou
 
 int mct_get_launch(mct_ctx *c, int *tile, int *order, int64_t *workgroups) {
     if (!c) return MCT_EINVAL;
+    if (c->tri) {
+        if (tile) *tile = 0;
+        if (order) *order = 0;
+        if (workgroups) *workgroups = (c->tri->ne + 255) / 256;
+        return MCT_OK;
+    }
     if (tile) *tile = c->tile;
     if (order) *order = c->order;
     if (workgroups) *workgroups = c->batch ? c->nunits : c->specs[0].prm.nwg;
@@ -1464,6 +1544,7 @@ int mct_get_launch(mct_ctx *c, int *tile, int *order, int64_t *workgroups) {
 int mct_screen_collect(mct_ctx *c, int64_t cap, float *features, int32_t *elem, uint8_t *entry,
                        int64_t *count) {
     if (!c) return MCT_EINVAL;
+    TRI_UNSUPPORTED(c, "the split-screen");
     if (!count || (cap > 0 && (!features || !elem || !entry))) return fail(c, MCT_EINVAL, "null output");
     int rc = ensure_screen(c);
     if (rc) return rc;
@@ -1501,6 +1582,7 @@ int mct_screen_collect(mct_ctx *c, int64_t cap, float *features, int32_t *elem, 
 
 int mct_screen_enable(mct_ctx *c, const mct_mlp *mlp, float tau, int period) {
     if (!c) return MCT_EINVAL;
+    TRI_UNSUPPORTED(c, "the split-screen");
     if (!mlp) return fail(c, MCT_EINVAL, "null model");
     if (period < 2) return fail(c, MCT_EINVAL, "period must be at least 2");
     int rc = ensure_screen(c);

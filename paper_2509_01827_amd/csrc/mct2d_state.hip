@@ -7,6 +7,7 @@
 
 #include "mct2d_device.h"
 #include "mct2d_impl.h"
+#include "mct2d_tri.h"
 
 namespace mct {
 
@@ -358,6 +359,12 @@ hipError_t sum_into(const double *x, int64_t n, int stride, int off, double *par
 }  // namespace
 
 int eval_partials() { return kSumBlocks; }
+int sum_partials() { return kSumBlocks; }
+
+hipError_t launch_sum(const double *x, int64_t n, int stride, int off, double *part, double *out, hipStream_t st) {
+    (void)hipGetLastError();
+    return sum_into(x, n, stride, off, part, out, st);
+}
 
 hipError_t launch_eval(const StepParams &p, const double *ux, const double *uy, const double *vx,
                        const double *vy, int64_t step, double phi, const EvalDev &d, hipStream_t st) {

@@ -1,0 +1,108 @@
+// Internal declarations of the CST (unstructured triangle mesh) path of the
+// MCT-2D-CEM library: the device view of one mesh, its control block and
+// the kernel launchers (mct2d_tri.hip), used by the host side
+// (mct2d_tri_host.cpp).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "mct2d_impl.h"
+
+namespace mct {
+namespace tri {
+
+// One accepted candidate of a step: G of its chosen path, the element and
+// (tip edge a) << 2 | (exit edge k).
+struct Cand {
+    double G;
+    int32_t elem;
+    int32_t ak;
+};
+static_assert(sizeof(Cand) == 16, "Cand layout");
+
+// Device-resident control block.
+struct Ctl {
+    int64_t base;      // steps completed before the running segment
+    int64_t nsplit;    // splits made by the tracking
+    double Ud;         // sum of Gc * crack-path length
+    int32_t nacc;      // accepted candidates appended by the running step
+    int32_t tip;       // single-tip tracking: element * 4 + local edge, or -1
+    int32_t overflow;  // 1 when a split could not be logged
+    int32_t pad;
+};
+static_assert(sizeof(Ctl) == 40, "Ctl layout");
+
+// Node flags (one byte per node).
+constexpr uint8_t kFixX = 1, kFixY = 2, kLoaded = 4;
+
+// The kernels' view of one CST mesh.  Nodal vectors are interleaved
+// (x, y) pairs so that one 16-byte load fetches both components.
+struct Params {
+    int32_t nn, ne;
+    int32_t log_cap;
+    int32_t sct;     // 1: single crack-tip tracking
+    int32_t ncurve;  // traction load curve points (0: constant tractions)
+    int32_t pad;
+    const int4 *conn;    // per element: nodes n0 n1 n2 (CCW), .w unused
+    const int4 *nbr;     // per element: neighbour across local edge k = 0, 1, 2 (-1: none);
+                         // .w: local index of that edge in the neighbour, 2 bits per k
+    const double *geo;   // 8 per element: dN/dx of n0..n2, dN/dy of n0..n2, area, 0
+    const double2 *xy;   // reference coordinates
+    double2 *u, *v;      // displacement, velocity
+    const double *minv;
+    const double2 *fext; // read where kLoaded
+    const double2 *v0;   // read where kFixX / kFixY
+    const uint8_t *nflag;
+    uint8_t *split;      // 0 intact, else kSplitFlag | entry << 2 | exit
+    const double *gc;    // per element
+    double2 *fe;         // 3 per element: force on local node n
+    const int32_t *csr_off;  // nn + 1
+    const int32_t *csr_ent;  // element * 3 + local node, by element colour per node
+    Cand *cand;          // 3 ne
+    LogRec *log;
+    Ctl *ctl;
+    const double *curve_t, *curve_phi;
+    double D11, D12, D33, E;
+    double dt, t_ramp, gamma;
+};
+
+// Evaluation outputs of the query kernels (nullptr = skip).
+struct Eval {
+    double *sig_ek;     // 9 per element: stress at local edge k (NaN where no intact neighbour)
+    double *es_ek;      // 3 per element: 1/2 A_s sigma:eps of local edge k where this element
+                        // owns the edge (lower-id intact neighbour), else 0
+    double *pe;         // per element: strain energy of the split pieces
+    double *principal;  // per element: largest principal stress of the mean edge stress (NaN split)
+    double *fint;       // 2 nn: x block, then y block
+    double *acc;        // 2 nn: x block, then y block
+    double *node_e;     // 2 per node: 1/2 m v.v, phi f_ext . u
+};
+
+// One time step j of the running segment (step index ctl->base + j):
+// element forces and candidates, then nodal gather, update and the pick.
+hipError_t launch_step(const Params &p, int j, hipStream_t st);
+// Close a segment of n steps (ctl->base += n).
+hipError_t launch_commit(const Params &p, int n, hipStream_t st);
+// Internal force, edge stresses, energy terms and principal stresses of
+// displacement u (interleaved) with velocity v (may be null) at step k with
+// load factor phi: no candidates, no update.
+hipError_t launch_eval(const Params &p, const double2 *u, const double2 *v, int64_t k, double phi,
+                       const double *mass, const Eval &ev, hipStream_t st);
+// Crack-surface tip flags of the edges (edge_elem: 2 per edge, in edge
+// order): 1 where one neighbour is intact and the other split.
+hipError_t launch_tip_flags(const Params &p, const int32_t *edge_elem, int64_t ns, uint8_t *flag, hipStream_t st);
+// One power-iteration step of M^-1/2 K M^-1/2 over the free components:
+// y -> z / |z| with sums[0] = y . z, sums[1] = z . z (y, z: x block then
+// y block; u: interleaved scratch of nn pairs).
+hipError_t launch_power_step(const Params &p, const Eval &ev, double *y, double2 *u, double *z, double *yz_zz,
+                             double *part, double *sums, hipStream_t st);
+
+}  // namespace tri
+
+// Deterministic sum of x[off + stride * i], i < n, into *out (two passes).
+hipError_t launch_sum(const double *x, int64_t n, int stride, int off, double *part, double *out, hipStream_t st);
+int sum_partials();
+
+}  // namespace mct

@@ -1,0 +1,597 @@
+// HIP kernels (gfx950) of the CST path: ES-FEM with constant-strain
+// triangles on an unstructured mesh (Sec. 2.1, Eq. CST_strain_discretization
+// and Eq. CST_fint_discretization), the CST energy release rates and the
+// two-path element rule (Sec. 2.2, the list after Fig. 2-2), the MCT pick
+// (Sec. 3) and the central-difference update.
+//
+// One time step is two launches:
+//   k_force  one thread per element.  An intact element computes its own
+//            strain B u and that of each intact neighbour (recomputed
+//            rather than stored: the neighbour's B and nodes are cache
+//            hits), smooths the strain of its three edges with
+//            w_j = A_j / (A_lo + A_hi) (lower element id first), applies
+//            Hooke's law, and writes its nodal forces
+//            (A/3) B^T (sigma_0 + sigma_1 + sigma_2).  Free-surface edges of
+//            the element are evaluated as crack-tip candidates; accepted
+//            ones are appended to a list.  A split element writes the
+//            forces of its two pieces (a bar and a free node).
+//   k_node   one thread per node: gather of the element forces in element
+//            colour order (CSR), acceleration, velocity and displacement
+//            update; workgroup 0 first picks the split of the step from the
+//            candidate list and applies it (it acts from the next step).
+// Every value is computed in one thread in the order of the plain
+// definition; results are bitwise reproducible and independent of the
+// launch geometry.
+#include <cmath>
+
+#include "mct2d_tri.h"
+
+namespace mct {
+namespace tri {
+namespace {
+
+constexpr int kB = 256;
+
+int nb_of(int64_t n) { return (int)((n + kB - 1) / kB > 0 ? (n + kB - 1) / kB : 1); }
+
+struct Geo {
+    double bx[3], by[3], A;
+};
+
+__device__ __forceinline__ Geo load_geo(const double *geo, int e) {
+    const double2 *g = reinterpret_cast<const double2 *>(geo + 8 * (int64_t)e);
+    const double2 a = g[0], b = g[1], c = g[2], d = g[3];
+    Geo r;
+    r.bx[0] = a.x;
+    r.bx[1] = a.y;
+    r.bx[2] = b.x;
+    r.by[0] = b.y;
+    r.by[1] = c.x;
+    r.by[2] = c.y;
+    r.A = d.x;
+    return r;
+}
+
+__device__ __forceinline__ int node_of(const int4 &c, int n) { return n == 0 ? c.x : (n == 1 ? c.y : c.z); }
+
+// element n of three values by selects (no indexed private arrays)
+template <typename T>
+__device__ __forceinline__ T sel3(int n, const T &a, const T &b, const T &c) {
+    return n == 0 ? a : (n == 1 ? b : c);
+}
+
+struct Sig {
+    double s[3];
+};
+
+// B u of a triangle: terms of nodes 0, 1, 2 accumulated with fma from zero.
+__device__ __forceinline__ void strain(const Geo &g, const double2 u[3], double q[3]) {
+    double exx = 0.0, eyy = 0.0, gxy = 0.0;
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+        exx = fma(g.bx[n], u[n].x, exx);
+        eyy = fma(g.by[n], u[n].y, eyy);
+        gxy = fma(g.by[n], u[n].x, gxy);
+        gxy = fma(g.bx[n], u[n].y, gxy);
+    }
+    q[0] = exx;
+    q[1] = eyy;
+    q[2] = gxy;
+}
+
+// plane-stress Hooke law, engineering shear strain
+__device__ __forceinline__ void hooke(const Params &p, const double e[3], double s[3]) {
+    s[0] = fma(p.D12, e[1], p.D11 * e[0]);
+    s[1] = fma(p.D12, e[0], p.D11 * e[1]);
+    s[2] = p.D33 * e[2];
+}
+
+__device__ __forceinline__ void load_u(const double2 *u, const int4 &c, double2 out[3]) {
+    out[0] = u[c.x];
+    out[1] = u[c.y];
+    out[2] = u[c.z];
+}
+
+// Smoothed strain of local edge k of intact element e (own strain q, area
+// A); two_out reports whether the neighbour across k is intact.
+__device__ __forceinline__ void edge_strain(const Params &p, const double2 *u, int e, int nb, const double q[3],
+                                            double A, double eps[3], bool &two_out) {
+    const bool two = nb >= 0 && p.split[nb] == 0;
+    two_out = two;
+    if (!two) {
+        eps[0] = q[0];
+        eps[1] = q[1];
+        eps[2] = q[2];
+        return;
+    }
+    const int4 c2 = p.conn[nb];
+    const Geo g2 = load_geo(p.geo, nb);
+    double2 u2[3];
+    load_u(u, c2, u2);
+    double q2[3];
+    strain(g2, u2, q2);
+    const bool self_lo = e < nb;
+    const double Alo = self_lo ? A : g2.A, Ahi = self_lo ? g2.A : A;
+    const double sum = Alo + Ahi;
+    const double w0 = Alo / sum, w1 = Ahi / sum;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double lo = self_lo ? q[c] : q2[c], hi = self_lo ? q2[c] : q[c];
+        eps[c] = fma(w1, hi, w0 * lo);
+    }
+}
+
+// Unit normal of the crack path from the midpoint of local edge a to the
+// midpoint of local edge k, oriented toward node n_{a+1}, and its length.
+__device__ __forceinline__ void path_geom(const Params &p, const int4 &c, int a, int k, double &nx, double &ny,
+                                          double &len) {
+    const double2 P0 = p.xy[node_of(c, a)], P1 = p.xy[node_of(c, (a + 1) % 3)];
+    const double2 Q0 = p.xy[node_of(c, k)], Q1 = p.xy[node_of(c, (k + 1) % 3)];
+    const double g0x = 0.5 * (P0.x + P1.x), g0y = 0.5 * (P0.y + P1.y);
+    const double gkx = 0.5 * (Q0.x + Q1.x), gky = 0.5 * (Q0.y + Q1.y);
+    const double dx = gkx - g0x, dy = gky - g0y;
+    const double L = sqrt(dx * dx + dy * dy);
+    double cx = dy / L, cy = -dx / L;
+    if (cx * (P1.x - g0x) + cy * (P1.y - g0y) < 0.0) {
+        cx = -cx;
+        cy = -cy;
+    }
+    nx = cx;
+    ny = cy;
+    len = L;
+}
+
+// Crack-tip candidate (intact element e, free-surface local edge a): G of
+// the two paths k = a+1, a+2 with the Heaviside edge-stretch gate, then the
+// two-path element rule.  Returns the accepted path index j or -1.
+__device__ __forceinline__ int candidate(const Params &p, int e, const int4 &c, const double2 &ua, const double2 &ub,
+                                         const Sig &s0, const Sig &s1, const Sig &s2, int a, double &Gsel) {
+    const int i1 = a, i2 = (a + 1) % 3;
+    const double2 X1 = p.xy[node_of(c, i1)], X2 = p.xy[node_of(c, i2)];
+    const double dux = ub.x - ua.x, duy = ub.y - ua.y;
+    const double x1 = X1.x + ua.x, y1 = X1.y + ua.y;
+    const double x2 = X2.x + ub.x, y2 = X2.y + ub.y;
+    const double lx = x2 - x1, ly = y2 - y1;
+    const double Lx = X2.x - X1.x, Ly = X2.y - X1.y;
+    if (!((lx * lx + ly * ly) > (Lx * Lx + Ly * Ly))) return -1;  // H = 0: every G is 0
+    double G[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int k = (a + 1 + j) % 3;
+        double nx, ny, len;
+        path_geom(p, c, a, k, nx, ny, len);
+        const Sig sg = sel3(k, s0, s1, s2);
+        const double spx = fma(sg.s[2], ny, sg.s[0] * nx);
+        const double spy = fma(sg.s[1], ny, sg.s[2] * nx);
+        G[j] = 0.5 * fma(duy, spy, dux * spx);
+    }
+    const double Gc = p.gc[e];
+    int best = -1;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+        if (G[j] > Gc && (best < 0 || G[j] > G[best])) best = j;
+    if (best < 0) return -1;
+    const int other = 1 - best;
+    if (G[other] > Gc && !(G[best] > p.gamma * (G[best] - G[other]))) return -1;
+    Gsel = G[best];
+    return best;
+}
+
+// One piece of a split triangle: the local nodes after the entry edge up to
+// the exit edge, closed by the two crack midpoints.  Two nodes (l0, l1): a
+// bar along them with cross-section A_piece / L, force F on l1 and -F on
+// l0; one node: nothing.
+struct Piece {
+    int l0, l1;  // l1 < 0: one-node piece
+    double2 F;
+    double w;    // strain energy
+};
+
+__device__ __forceinline__ Piece piece(const Params &p, const double2 *u, const int4 &c, int entry, int exit) {
+    Piece r;
+    r.l0 = (entry + 1) % 3;
+    r.l1 = -1;
+    r.F = make_double2(0.0, 0.0);
+    r.w = 0.0;
+    if (r.l0 == exit) return r;
+    r.l1 = exit;
+    const double2 A0 = p.xy[node_of(c, entry)], A1 = p.xy[node_of(c, (entry + 1) % 3)];
+    const double2 B0 = p.xy[node_of(c, exit)], B1 = p.xy[node_of(c, (exit + 1) % 3)];
+    const double2 P = p.xy[node_of(c, r.l0)], Q = p.xy[node_of(c, r.l1)];
+    // polygon M_entry, P, Q, M_exit; area by a fan from its first vertex
+    const double px0 = 0.5 * (A0.x + A1.x), py0 = 0.5 * (A0.y + A1.y);
+    const double px3 = 0.5 * (B0.x + B1.x), py3 = 0.5 * (B0.y + B1.y);
+    double s = 0.0;
+    s += (P.x - px0) * (Q.y - py0) - (Q.x - px0) * (P.y - py0);
+    s += (Q.x - px0) * (py3 - py0) - (px3 - px0) * (Q.y - py0);
+    const double Ap = 0.5 * s;
+    const double dx = Q.x - P.x, dy = Q.y - P.y;
+    const double L2 = dx * dx + dy * dy;
+    const double2 up = u[node_of(c, r.l0)], uq = u[node_of(c, r.l1)];
+    const double dux = uq.x - up.x, duy = uq.y - up.y;
+    const double str = (dx * dux + dy * duy) / L2;
+    const double stress = p.E * str;
+    const double coef = Ap * stress / L2;
+    r.F = make_double2(coef * dx, coef * dy);
+    r.w = 0.5 * Ap * stress * str;
+    return r;
+}
+
+__device__ __forceinline__ double2 piece_force_at(const Piece &a, const Piece &b, int n) {
+    if (a.l1 >= 0 && n == a.l1) return a.F;
+    if (a.l1 >= 0 && n == a.l0) return make_double2(-a.F.x, -a.F.y);
+    if (b.l1 >= 0 && n == b.l1) return b.F;
+    if (b.l1 >= 0 && n == b.l0) return make_double2(-b.F.x, -b.F.y);
+    return make_double2(0.0, 0.0);
+}
+
+// Element pass.  eval: query mode (u given, outputs in ev, no candidates).
+template <bool EVAL>
+__global__ __launch_bounds__(kB) void k_force(Params p, const double2 *u, Eval ev) {
+    const int e = blockIdx.x * kB + threadIdx.x;
+    if (e >= p.ne) return;
+    const int4 c = p.conn[e];
+    const uint8_t code = p.split[e];
+    double2 *fe = p.fe + 3 * (int64_t)e;
+    if (code) {
+        const Piece pa = piece(p, u, c, (code >> 2) & 3, code & 3);
+        const Piece pb = piece(p, u, c, code & 3, (code >> 2) & 3);
+        double w = pa.w;
+        w += pb.w;
+        fe[0] = piece_force_at(pa, pb, 0);
+        fe[1] = piece_force_at(pa, pb, 1);
+        fe[2] = piece_force_at(pa, pb, 2);
+        if constexpr (EVAL) {
+            if (ev.pe) ev.pe[e] = w;
+            if (ev.es_ek)
+                for (int k = 0; k < 3; ++k) ev.es_ek[3 * (int64_t)e + k] = 0.0;
+            if (ev.principal) ev.principal[e] = NAN;
+            // stresses of the edges seen from a split element: the intact
+            // neighbour (if any) writes them; mark this side absent
+            if (ev.sig_ek)
+                for (int k = 0; k < 9; ++k) ev.sig_ek[9 * (int64_t)e + k] = NAN;
+        }
+        return;
+    }
+    const Geo g = load_geo(p.geo, e);
+    double2 ue[3];
+    load_u(u, c, ue);
+    double q[3];
+    strain(g, ue, q);
+    const int4 nb = p.nbr[e];
+    double sig[3][3];
+    bool two[3];
+    double eps[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        edge_strain(p, u, e, k == 0 ? nb.x : (k == 1 ? nb.y : nb.z), q, g.A, eps[k], two[k]);
+        hooke(p, eps[k], sig[k]);
+    }
+    double S[3];
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) S[cc] = (sig[0][cc] + sig[1][cc]) + sig[2][cc];
+    const double coef = g.A / 3.0;
+#pragma unroll
+    for (int n = 0; n < 3; ++n)
+        fe[n] = make_double2(coef * fma(g.by[n], S[2], g.bx[n] * S[0]), coef * fma(g.bx[n], S[2], g.by[n] * S[1]));
+    if constexpr (EVAL) {
+        if (ev.pe) ev.pe[e] = 0.0;
+        if (ev.sig_ek)
+            for (int k = 0; k < 3; ++k)
+                for (int cc = 0; cc < 3; ++cc) ev.sig_ek[9 * (int64_t)e + 3 * k + cc] = sig[k][cc];
+        if (ev.es_ek) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int n = k == 0 ? nb.x : (k == 1 ? nb.y : nb.z);
+                double term = 0.0;
+                if (!two[k] || e < n) {
+                    // smoothing domain: one third of each intact neighbour,
+                    // lower element id first
+                    double As = 0.0;
+                    if (two[k]) {
+                        const double An = load_geo(p.geo, n).A;
+                        As += g.A / 3.0;
+                        As += An / 3.0;
+                    } else {
+                        As += g.A / 3.0;
+                    }
+                    term = 0.5 * As * (sig[k][0] * eps[k][0] + sig[k][1] * eps[k][1] + sig[k][2] * eps[k][2]);
+                }
+                ev.es_ek[3 * (int64_t)e + k] = term;
+            }
+        }
+        if (ev.principal) {
+            const double m0 = S[0] / 3.0, m1 = S[1] / 3.0, m2 = S[2] / 3.0;
+            const double cc = 0.5 * (m0 + m1);
+            const double hd = 0.5 * (m0 - m1);
+            ev.principal[e] = cc + sqrt(hd * hd + m2 * m2);
+        }
+        return;
+    } else {
+        const bool any_free = !(two[0] && two[1] && two[2]);
+        if (!any_free) return;
+        const int tip = p.sct ? p.ctl->tip : -1;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (two[a]) continue;
+            if (p.sct && tip != 4 * e + a) continue;
+            double G;
+            const Sig s0 = {{sig[0][0], sig[0][1], sig[0][2]}}, s1 = {{sig[1][0], sig[1][1], sig[1][2]}},
+                      s2 = {{sig[2][0], sig[2][1], sig[2][2]}};
+            const int j = candidate(p, e, c, sel3(a, ue[0], ue[1], ue[2]), sel3((a + 1) % 3, ue[0], ue[1], ue[2]),
+                                    s0, s1, s2, a, G);
+            if (j < 0) continue;
+            const int k = (a + 1 + j) % 3;
+            const int slot = atomicAdd(&p.ctl->nacc, 1);
+            Cand cd;
+            cd.G = G;
+            cd.elem = e;
+            cd.ak = (a << 2) | k;
+            p.cand[slot] = cd;
+        }
+    }
+}
+
+__device__ __forceinline__ double load_factor(const Params &p, double t) {
+    if (p.ncurve == 0) return 1.0;
+    if (t <= p.curve_t[0]) return p.curve_phi[0];
+    const int n = p.ncurve;
+    if (t >= p.curve_t[n - 1]) return p.curve_phi[n - 1];
+    // largest i with curve_t[i] <= t
+    int lo = 0, hi = n - 1;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (p.curve_t[mid] <= t)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const int i = lo;
+    const double slope = (p.curve_phi[i + 1] - p.curve_phi[i]) / (p.curve_t[i + 1] - p.curve_t[i]);
+    return p.curve_phi[i] + (t - p.curve_t[i]) * slope;
+}
+
+// better(a, b): larger G, ties to the lower element id, then the lower tip edge
+__device__ __forceinline__ bool better(const Cand &a, const Cand &b) {
+    if (a.G != b.G) return a.G > b.G;
+    if (a.elem != b.elem) return a.elem < b.elem;
+    return (a.ak >> 2) < (b.ak >> 2);
+}
+
+// MCT pick of step k over the candidate list (whole workgroup), then the
+// split, its log record, U_d and the single tip.
+__device__ void pick(const Params &p, int64_t k) {
+    __shared__ Cand s_best[kB];
+    __shared__ double s_min[kB];
+    Ctl *ctl = p.ctl;
+    const int n = ctl->nacc;
+    if (n == 0) return;  // uniform over the workgroup
+    Cand best;
+    best.G = -1.0;
+    best.elem = 0x7fffffff;
+    best.ak = 0;
+    double gmin = INFINITY;
+    for (int t = threadIdx.x; t < n; t += kB) {
+        const Cand cd = p.cand[t];
+        if (better(cd, best)) best = cd;
+        gmin = fmin(gmin, cd.G);
+    }
+    s_best[threadIdx.x] = best;
+    s_min[threadIdx.x] = gmin;
+    __syncthreads();
+    for (int w = kB / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            if (better(s_best[threadIdx.x + w], s_best[threadIdx.x])) s_best[threadIdx.x] = s_best[threadIdx.x + w];
+            s_min[threadIdx.x] = fmin(s_min[threadIdx.x], s_min[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const Cand b = s_best[0];
+        const double Gmin = s_min[0];
+        ctl->nacc = 0;
+        // split-ratio test against every other accepted candidate; the
+        // smallest G is the hardest one to pass
+        if (b.G > p.gamma * (b.G - Gmin)) {
+            const int e = b.elem, a = b.ak >> 2, kx = b.ak & 3;
+            p.split[e] = (uint8_t)(kSplitFlag | b.ak);
+            const int64_t ns = ctl->nsplit;
+            if (ns < p.log_cap) {
+                LogRec r;
+                r.step = (int32_t)k;
+                r.elem = e;
+                r.entry = (uint8_t)a;
+                r.exit = (uint8_t)kx;
+                r.pad0 = r.pad1 = 0;
+                r.pad2 = 0;
+                r.G = b.G;
+                p.log[ns] = r;
+            } else {
+                ctl->overflow = 1;
+            }
+            ctl->nsplit = ns + 1;
+            const int4 c = p.conn[e];
+            double nx, ny, len;
+            path_geom(p, c, a, kx, nx, ny, len);
+            ctl->Ud = ctl->Ud + p.gc[e] * len;
+            if (p.sct) {
+                const int4 nb = p.nbr[e];
+                const int m = kx == 0 ? nb.x : (kx == 1 ? nb.y : nb.z);
+                ctl->tip = (m < 0 || p.split[m] != 0) ? -1 : 4 * m + ((nb.w >> (2 * kx)) & 3);
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ double prescribed(const Params &p, double v0, double t) {
+    if (p.t_ramp > 0.0 && t < p.t_ramp) return v0 * (t / p.t_ramp);
+    return v0;
+}
+
+__device__ __forceinline__ double2 gather(const Params &p, int i) {
+    double fx = 0.0, fy = 0.0;
+    const int t1 = p.csr_off[i + 1];
+    for (int t = p.csr_off[i]; t < t1; ++t) {
+        const double2 f = p.fe[p.csr_ent[t]];
+        fx = fx + f.x;
+        fy = fy + f.y;
+    }
+    return make_double2(fx, fy);
+}
+
+__global__ __launch_bounds__(kB) void k_node(Params p, int j) {
+    __shared__ double s_phi;
+    const int64_t k = p.ctl->base + j;
+    if (blockIdx.x == 0) pick(p, k);
+    if (threadIdx.x == 0) s_phi = load_factor(p, (double)k * p.dt);
+    __syncthreads();
+    const int i = blockIdx.x * kB + threadIdx.x;
+    if (i >= p.nn) return;
+    const double2 f = gather(p, i);
+    const uint8_t fl = p.nflag[i];
+    const double2 fx = (fl & kLoaded) ? p.fext[i] : make_double2(0.0, 0.0);
+    const double phi = s_phi, mi = p.minv[i];
+    double ax = (phi * fx.x - f.x) * mi;
+    double ay = (phi * fx.y - f.y) * mi;
+    if (fl & kFixX) ax = 0.0;
+    if (fl & kFixY) ay = 0.0;
+    const double dtv = (k == 0) ? 0.5 * p.dt : p.dt;
+    const double th = ((double)k + 0.5) * p.dt;
+    double2 v = p.v[i];
+    double vx = v.x + dtv * ax;
+    double vy = v.y + dtv * ay;
+    if (fl & (kFixX | kFixY)) {
+        const double2 v0 = p.v0[i];
+        if (fl & kFixX) vx = prescribed(p, v0.x, th);
+        if (fl & kFixY) vy = prescribed(p, v0.y, th);
+    }
+    p.v[i] = make_double2(vx, vy);
+    const double2 u = p.u[i];
+    p.u[i] = make_double2(u.x + p.dt * vx, u.y + p.dt * vy);
+}
+
+__global__ void k_commit(Params p, int n) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) p.ctl->base = p.ctl->base + n;
+}
+
+// Query: internal force, acceleration and energy terms per node.
+__global__ __launch_bounds__(kB) void k_eval_nodes(Params p, const double2 *u, const double2 *v, int64_t k,
+                                                   double phi, const double *mass, Eval ev) {
+    const int i = blockIdx.x * kB + threadIdx.x;
+    if (i >= p.nn) return;
+    const double2 f = gather(p, i);
+    if (ev.fint) {
+        ev.fint[i] = f.x;
+        ev.fint[p.nn + i] = f.y;
+    }
+    const uint8_t fl = p.nflag[i];
+    const double2 fx = (fl & kLoaded) ? p.fext[i] : make_double2(0.0, 0.0);
+    const double mi = p.minv[i];
+    double ax = (phi * fx.x - f.x) * mi;
+    double ay = (phi * fx.y - f.y) * mi;
+    if (fl & kFixX) ax = 0.0;
+    if (fl & kFixY) ay = 0.0;
+    if (ev.acc) {
+        ev.acc[i] = ax;
+        ev.acc[p.nn + i] = ay;
+    }
+    if (ev.node_e && v) {
+        double2 vv = v[i];
+        double vx = vv.x, vy = vv.y;
+        if (k > 0) {
+            if (!(fl & kFixX)) vx = vx + 0.5 * p.dt * ax;
+            if (!(fl & kFixY)) vy = vy + 0.5 * p.dt * ay;
+        }
+        const double2 uu = u[i];
+        ev.node_e[2 * (int64_t)i] = 0.5 * mass[i] * (vx * vx + vy * vy);
+        ev.node_e[2 * (int64_t)i + 1] = phi * fx.x * uu.x + phi * fx.y * uu.y;
+    }
+}
+
+__global__ __launch_bounds__(kB) void k_tip_flags(Params p, const int32_t *edge_elem, int64_t ns, uint8_t *flag) {
+    const int64_t s = (int64_t)blockIdx.x * kB + threadIdx.x;
+    if (s >= ns) return;
+    const int e0 = edge_elem[2 * s], e1 = edge_elem[2 * s + 1];
+    uint8_t r = 0;
+    if (e0 >= 0 && e1 >= 0) {
+        const int i0 = p.split[e0] == 0, i1 = p.split[e1] == 0;
+        r = (i0 + i1 == 1) ? 1 : 0;
+    }
+    flag[s] = r;
+}
+
+// Power iteration on M^-1/2 K M^-1/2 over the free components.
+__global__ __launch_bounds__(kB) void k_scale_in(Params p, const double *y, double2 *u) {
+    const int i = blockIdx.x * kB + threadIdx.x;
+    if (i >= p.nn) return;
+    const uint8_t fl = p.nflag[i];
+    const double r = sqrt(p.minv[i]);
+    u[i] = make_double2((fl & kFixX) ? 0.0 : y[i] * r, (fl & kFixY) ? 0.0 : y[p.nn + i] * r);
+}
+
+__global__ __launch_bounds__(kB) void k_scale_out(Params p, const double *fint, const double *y, double *z,
+                                                  double *yz_zz) {
+    const int i = blockIdx.x * kB + threadIdx.x;
+    if (i >= p.nn) return;
+    const uint8_t fl = p.nflag[i];
+    const double r = sqrt(p.minv[i]);
+    const double zx = (fl & kFixX) ? 0.0 : fint[i] * r;
+    const double zy = (fl & kFixY) ? 0.0 : fint[p.nn + i] * r;
+    z[i] = zx;
+    z[p.nn + i] = zy;
+    yz_zz[2 * (int64_t)i] = y[i] * zx + y[p.nn + i] * zy;
+    yz_zz[2 * (int64_t)i + 1] = zx * zx + zy * zy;
+}
+
+__global__ __launch_bounds__(kB) void k_normalize(int64_t n, const double *z, const double *zz, double *y) {
+    const int64_t t = (int64_t)blockIdx.x * kB + threadIdx.x;
+    if (t >= n) return;
+    const double s = sqrt(*zz);
+    y[t] = s > 0.0 ? z[t] / s : 0.0;
+}
+
+}  // namespace
+
+hipError_t launch_step(const Params &p, int j, hipStream_t st) {
+    k_force<false><<<nb_of(p.ne), kB, 0, st>>>(p, p.u, Eval{});
+    k_node<<<nb_of(p.nn), kB, 0, st>>>(p, j);
+    return hipGetLastError();
+}
+
+hipError_t launch_commit(const Params &p, int n, hipStream_t st) {
+    k_commit<<<1, 64, 0, st>>>(p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_eval(const Params &p, const double2 *u, const double2 *v, int64_t k, double phi,
+                       const double *mass, const Eval &ev, hipStream_t st) {
+    (void)hipGetLastError();
+    k_force<true><<<nb_of(p.ne), kB, 0, st>>>(p, u, ev);
+    k_eval_nodes<<<nb_of(p.nn), kB, 0, st>>>(p, u, v, k, phi, mass, ev);
+    return hipGetLastError();
+}
+
+hipError_t launch_tip_flags(const Params &p, const int32_t *edge_elem, int64_t ns, uint8_t *flag, hipStream_t st) {
+    (void)hipGetLastError();
+    k_tip_flags<<<nb_of(ns), kB, 0, st>>>(p, edge_elem, ns, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_power_step(const Params &p, const Eval &ev, double *y, double2 *u, double *z, double *yz_zz,
+                             double *part, double *sums, hipStream_t st) {
+    (void)hipGetLastError();
+    k_scale_in<<<nb_of(p.nn), kB, 0, st>>>(p, y, u);
+    Eval e2{};
+    e2.fint = ev.fint;
+    hipError_t e = launch_eval(p, u, nullptr, 0, 1.0, nullptr, e2, st);
+    if (e != hipSuccess) return e;
+    k_scale_out<<<nb_of(p.nn), kB, 0, st>>>(p, ev.fint, y, z, yz_zz);
+    e = launch_sum(yz_zz, p.nn, 2, 0, part, sums, st);
+    if (e == hipSuccess) e = launch_sum(yz_zz, p.nn, 2, 1, part, sums + 1, st);
+    if (e != hipSuccess) return e;
+    k_normalize<<<nb_of(2 * (int64_t)p.nn), kB, 0, st>>>(2 * (int64_t)p.nn, z, sums + 1, y);
+    return hipGetLastError();
+}
+
+}  // namespace tri
+}  // namespace mct

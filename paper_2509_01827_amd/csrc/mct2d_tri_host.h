@@ -1,0 +1,100 @@
+// Host side of the CST (unstructured triangle mesh) path: the model a
+// context holds after mct_set_mesh_tri, and the functions the C ABI
+// forwards to for such a context.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mct2d.h"
+#include "mct2d_tri.h"
+
+namespace mct {
+namespace tri {
+
+struct Model {
+    // mesh (as given) and its tables, built by set_mesh
+    int64_t nn = 0, ne = 0, ns = 0;
+    std::vector<double> X, Y;
+    std::vector<int32_t> conn;       // 3 per element
+    std::vector<int32_t> edge_node;  // 2 per edge (lower node id first), edges sorted by node pair
+    std::vector<int32_t> edge_elem;  // 2 per edge (lower element id first, -1 none)
+    std::vector<int32_t> elem_edge;  // 3 per element
+    std::vector<int32_t> nbr;        // 4 per element: neighbours across k = 0..2, packed local edges
+    std::vector<double> area;
+    // material and loads
+    bool have_material = false;
+    double E = 0, nu = 0, rho = 0, gamma = 1, gc_uniform = 0;
+    std::vector<double> gc;
+    std::vector<int64_t> trac_edge;  // sorted edge ids
+    std::vector<double> trac;        // 2 per traction edge
+    std::vector<int32_t> vbc_node;
+    std::vector<uint8_t> vbc_mask;
+    std::vector<double> vbc_v0;
+    double t_ramp = 0;
+    std::vector<int32_t> notch_elem;
+    std::vector<uint8_t> notch_code;
+    double dt_in = 0, cfl = 0.5;
+    std::vector<double> curve_t, curve_phi;
+    int sct = 0;
+    int32_t sct_elem = -1;
+    int sct_edge = 0;
+    bool use_graph = true;
+    // derived at finalize
+    bool finalized = false;
+    double dt = 0, dt_limit = 0;
+    std::vector<double> mass;
+    Params prm{};
+    // device memory
+    int4 *dconn = nullptr, *dnbr = nullptr;
+    double *dgeo = nullptr, *dminv = nullptr, *dgc = nullptr, *dcurve = nullptr, *dmass = nullptr;
+    double2 *dxy = nullptr, *du = nullptr, *dv = nullptr, *dfext = nullptr, *dv0 = nullptr, *dfe = nullptr;
+    uint8_t *dflag = nullptr, *dsplit = nullptr;
+    int32_t *dcsr_off = nullptr, *dcsr_ent = nullptr, *dedge_elem = nullptr, *dwatch = nullptr;
+    Cand *dcand = nullptr;
+    LogRec *dlog = nullptr;
+    Ctl *dctl = nullptr;
+    // query buffers (allocated on first use)
+    Eval ev{};
+    double *dpart = nullptr, *dsums = nullptr, *dpow = nullptr;
+    uint8_t *dtipflag = nullptr;
+    hipGraphExec_t graph = nullptr;
+    int64_t steps_enqueued = 0;
+};
+
+// Every function returns an mct status and writes a message to err on
+// failure.
+struct Host {
+    std::string &err;
+    hipStream_t stream;
+};
+
+void release(Model &m);
+int set_mesh(Model &m, Host h, int64_t nn, const double *X, const double *Y, int64_t ne, const int32_t *conn);
+int set_material(Model &m, Host h, double E, double nu, double rho, const double *Gc, double Gc_uniform,
+                 double gamma);
+int set_traction(Model &m, Host h, int64_t n, const int32_t *edge_nodes, const double *t);
+int set_velocity_bc(Model &m, Host h, int64_t n, const int32_t *node, const uint8_t *mask, const double *v0,
+                    double t_ramp);
+int set_notch(Model &m, Host h, int64_t n, const int32_t *elem, const uint8_t *entry, const uint8_t *exit);
+int set_load_curve(Model &m, Host h, int64_t n, const double *t, const double *phi);
+int set_tracking(Model &m, Host h, int mode, int32_t elem, int edge);
+int set_time(Model &m, Host h, double dt, double cfl);
+int finalize(Model &m, Host h);
+int step(Model &m, Host h, int64_t n);
+int sync(Model &m, Host h);
+int get_info(Model &m, Host h, mct_info *out);
+int get_crack_set(Model &m, Host h, int64_t cap, int32_t *step, int32_t *elem, uint8_t *entry, uint8_t *exit,
+                  double *G, int64_t *count);
+int get_tips(Model &m, Host h, int64_t cap, int32_t *edge, double *xy, int64_t *count);
+int get_field(Model &m, Host h, int which, int64_t cap, double *out);
+int get_energies(Model &m, Host h, double out[4]);
+int get_split_codes(Model &m, Host h, int64_t cap, uint8_t *out);
+int checkpoint(Model &m, Host h, void *buf, int64_t cap, int64_t *bytes);
+int restore(Model &m, Host h, const void *buf, int64_t bytes);
+
+}  // namespace tri
+}  // namespace mct

@@ -46,7 +46,7 @@ EXPORTS = [
     "mct_screen_collect", "mct_screen_enable", "mct_screen_disable", "mct_screen_stats",
     "mct_mlp_create", "mct_mlp_destroy", "mct_mlp_last_error", "mct_mlp_set_params", "mct_mlp_get_params",
     "mct_mlp_forward", "mct_mlp_gradient", "mct_mlp_train_step", "mct_get_energies", "mct_set_tracking",
-    "mct_set_load_curve",
+    "mct_set_load_curve", "mct_set_mesh_tri",
 ]
 N_FEATURES = 10
 N_PARAMS = 4929
@@ -84,6 +84,7 @@ def load() -> C.CDLL:
     L.mct_last_error.argtypes = [P]
     L.mct_last_error.restype = C.c_char_p
     L.mct_set_mesh_grid.argtypes = [P, C.c_int32, C.c_int32, dp, dp]
+    L.mct_set_mesh_tri.argtypes = [P, C.c_int64, dp, dp, C.c_int64, ip]
     L.mct_set_material.argtypes = [P, C.c_double, C.c_double, C.c_double, P, C.c_double, C.c_double]
     L.mct_set_traction.argtypes = [P, C.c_int64, ip, dp]
     L.mct_set_velocity_bc.argtypes = [P, C.c_int64, ip, bp, dp, C.c_double]
@@ -181,6 +182,12 @@ class Model:
     # -- set-up ---------------------------------------------------------
     def set_mesh_grid(self, nx, ny, X, Y):
         self._check(self._L.mct_set_mesh_grid(self._h, int(nx), int(ny), _f64(X), _f64(Y)), "set_mesh_grid")
+
+    def set_mesh_tri(self, X, Y, conn):
+        """Unstructured CST mesh: node coordinates and [ne][3] CCW triangles."""
+        conn = _i32(np.asarray(conn).reshape(-1))
+        X = _f64(X)
+        self._check(self._L.mct_set_mesh_tri(self._h, len(X), X, _f64(Y), len(conn) // 3, conn), "set_mesh_tri")
 
     def set_material(self, E, nu, rho, gc=None, gc_uniform=0.0, gamma=1.0):
         self._gc = None if gc is None else _f64(gc)
@@ -411,7 +418,10 @@ class Mlp:
 
 
 def _setup(m: Model, cfg: dict):
-    m.set_mesh_grid(cfg["nx"], cfg["ny"], cfg["X"], cfg["Y"])
+    if cfg.get("conn") is not None:
+        m.set_mesh_tri(cfg["X"], cfg["Y"], cfg["conn"])
+    else:
+        m.set_mesh_grid(cfg["nx"], cfg["ny"], cfg["X"], cfg["Y"])
     m.set_material(cfg["E"], cfg["nu"], cfg["rho"], cfg.get("gc_field"), cfg.get("gc_uniform", 0.0),
                    cfg.get("gamma", 1.0))
     m.set_traction(cfg["traction_nodes"], cfg["traction"])

@@ -433,6 +433,15 @@ def tri_cylinder(r_in=0.05, r_out=0.1, h=1.0e-3, *, p0=400.0e6, t0=1.0e-6, tau=1
                 load_curve=pressure_pulse(t0=t0, tau=tau))
 
 
+def tri_plate320k(steps=20000):
+    """The 100 x 40 mm Neumann branching plate on a Delaunay CST mesh of
+    633 x 254 jittered points (h = 0.158 mm, about 320 000 triangles), half-
+    length pre-notch: the CST workload at the size of the 400 x 400 Q4
+    plate's edge count."""
+    return tri_plate(632, 253, 0.1, 0.04, jitter=0.3, seed=BASE_SEED + 72, notch_len=0.05, steps=steps,
+                     name="tri_plate320k")
+
+
 def tri_small_cases():
     """CST cases the oracle finishes in seconds."""
     return {
