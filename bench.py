@@ -34,42 +34,66 @@ WORKLOADS = {
     "batch256": "256 notched specimens 64..512 x 64..256 Q4, h 1 mm, notch U(0.2,0.6) width, "
                 "Weibull(6, U(2,4)) Gc, traction U(0.5,1.5) MPa",
     "screen400": "branching plate 400x400 Q4 (as plate400) with the learned split-screen, exact step every 50",
+    "tri320k": "branching plate 100x40 mm on an unstructured CST mesh (Delaunay of 633x254 jittered points, "
+               "319792 triangles), notch 50 mm, 1 MPa",
+    "cylinder53k": "pressured hollow cylinder r 50/100 mm on an unstructured CST mesh (h 1 mm, ~53000 triangles), "
+                   "steel, 400 MPa pulse",
 }
 
 
+def n_elems(c) -> int:
+    return len(c["conn"]) if c.get("conn") is not None else c["nx"] * c["ny"]
+
+
+def n_nodes(c) -> int:
+    return len(c["X"])
+
+
 def bytes_per_step(cfgs) -> int:
-    """Algorithmic HBM bytes of one fused step (binary64): per node read u,
-    v, X, Y, 1/m and write u, v (11 doubles); per element its split code and
-    its area (9 bytes)."""
+    """Algorithmic HBM bytes of one step (binary64): per node read u, v, X,
+    Y, 1/m and write u, v (11 doubles); per Q4 element its split code and its
+    area (9 bytes; the structured grid needs no connectivity); per CST
+    element its split code and its three node ids (13 bytes)."""
     total = 0
     for c in cfgs:
-        nn = (c["nx"] + 1) * (c["ny"] + 1)
-        total += 88 * nn + 9 * c["nx"] * c["ny"]
+        total += 88 * n_nodes(c) + (13 if c.get("conn") is not None else 9) * n_elems(c)
     return total
 
 
-# HBM bytes per step launch measured with rocprofv3 --pmc FETCH_SIZE and
-# WRITE_SIZE (KiB per dispatch, averaged over the profiled launches), each
-# scaled by the ratio of true to counted bytes of a 256 MiB device copy
-# (FETCH_SIZE x 1.99979, WRITE_SIZE x 1.0).  They hold for the kernel source
-# they were taken on (hash of the step kernel and its header) and the tile
+# HBM bytes per time step measured with rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE (KiB per dispatch, averaged over the profiled launches and summed
+# over the step's kernels), each scaled by the ratio of true to counted bytes
+# of a 256 MiB device copy (FETCH_SIZE x 1.99979, WRITE_SIZE x 1.0).  A figure
+# holds for the kernel sources it was taken on (their hash) and the tile
 # shape; otherwise the traffic is reported as unknown.
 MEASURED_TRAFFIC = {
-    "kernel_sha256": "fb1c46d913a99be112220c7b6da4629b9985a97560fde24c81c0fd5aaadce5b1",
-    "plate400": {"tile": 1, "fetch_kib": 5592.0128, "write_kib": 5044.4077},
-    "batch256": {"tile": 1, "fetch_kib": 423053.46, "write_kib": 471632.16},
+    "plate400": {"sources": ("mct2d_step.hip", "mct2d_impl.h", "mct2d_device.h"),
+                 "sha256": "0bf7db7be35ea7425312cf2e357f174b99363e1f1e426c7a7b51b857cb032a9e",
+                 "tile": 1, "fetch_kib": 5597.0134, "write_kib": 5044.4109},
+    "batch256": {"sources": ("mct2d_step.hip", "mct2d_impl.h", "mct2d_device.h"),
+                 "sha256": "0bf7db7be35ea7425312cf2e357f174b99363e1f1e426c7a7b51b857cb032a9e",
+                 "tile": 1, "fetch_kib": 423141.03, "write_kib": 474325.76},
+    # two launches per step: k_force (15 119.40 / 19 971.80) + k_node (17 014.51 / 5 024.44)
+    "tri320k": {"sources": ("mct2d_tri.hip", "mct2d_tri.h"),
+                "sha256": "7854e892448c80b379a2a89e19993b4091e4ea5c7537f87754d581451dad2b86",
+                "tile": 0, "fetch_kib": 32133.91, "write_kib": 24996.24},
 }
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131086.604, 262144.0 / 262144.0
 
 
-def measured_traffic(workload: str, tile: int):
+def kernel_sha256(sources) -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ("mct2d_step.hip", "mct2d_impl.h"):
+    for f in sources:
         with open(os.path.join(ROOT, "paper_2509_01827_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, tile: int):
     rec = MEASURED_TRAFFIC.get(workload)
-    if rec is None or rec["tile"] != tile or h.hexdigest() != MEASURED_TRAFFIC["kernel_sha256"]:
+    if rec is None or rec["fetch_kib"] is None or rec["tile"] != tile or \
+            kernel_sha256(rec["sources"]) != rec["sha256"]:
         return None
     return 1024.0 * (rec["fetch_kib"] * FETCH_SCALE + rec["write_kib"] * WRITE_SCALE)
 
@@ -81,10 +105,10 @@ def cpu_baseline(cfg, steps: int):
     t0 = time.perf_counter()
     o.step(steps)
     dt = time.perf_counter() - t0
-    ne = cfg["nx"] * cfg["ny"]
+    ne = n_elems(cfg)
     return {"value": ne * steps / dt, "unit": "element-updates/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d time steps of the same %dx%d plate (single-threaded C oracle, %.1f s)"
-                      % (steps, cfg["nx"], cfg["ny"], dt)}
+            "sample": "first %d time steps of the same %s (%d elements; single-threaded C oracle, %.1f s)"
+                      % (steps, cfg["name"], ne, dt)}
 
 
 def timed_run(m, stream, steps, warmup):
@@ -122,10 +146,15 @@ def main():
     ap.add_argument("--workload", default="plate400", choices=sorted(WORKLOADS))
     ap.add_argument("--compare-plain", action="store_true",
                     help="batch256: also run each specimen alone and compare")
+    ap.add_argument("--kernel-hash", action="store_true",
+                    help="only print the source hashes the measured traffic figures are keyed on")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (three times), "
                          "to calibrate the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
+    if args.kernel_hash:
+        print(json.dumps({w: kernel_sha256(r["sources"]) for w, r in MEASURED_TRAFFIC.items()}))
+        return
     if args.copy_probe:
         import torch
         n = args.copy_probe * (1 << 20) // 8
@@ -161,14 +190,15 @@ def main():
         m = mct2d.from_config(cfgs[0], stream=stream.cuda_stream, tile=args.tile, use_graph=not args.no_graph)
         m.screen_enable(mlp, screen["tau"], screen["period"])
     else:
-        cfgs = [W.config2() if args.workload == "plate400" else W.config3()]
+        cfgs = [{"plate400": W.config2, "fragment2000": W.config3, "tri320k": W.tri_plate320k,
+                 "cylinder53k": lambda: W.tri_cylinder(steps=2000, name="cylinder53k")}[args.workload]()]
         m = mct2d.from_config(cfgs[0], stream=stream.cuda_stream, tile=args.tile,
                               use_graph=not args.no_graph)
     steps = args.steps if args.steps is not None else cfgs[0]["steps"]
     tune = m.autotune(trial_steps=20) if args.autotune else None
     gpu_ms, wall = timed_run(m, stream, steps, args.warmup)
     launch = m.launch()
-    ne = sum(c["nx"] * c["ny"] for c in cfgs)
+    ne = sum(n_elems(c) for c in cfgs)
     splits, ud = 0, 0.0
     logs = []
     for s in range(len(cfgs)):

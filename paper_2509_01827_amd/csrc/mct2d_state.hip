@@ -294,13 +294,22 @@ __global__ __launch_bounds__(kB) void k_partial_sum(const double *x, int64_t n, 
     if (threadIdx.x == 0) part[blockIdx.x] = s_v[0];
 }
 
-__global__ void k_final_sum(const double *part, int nparts, double *out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double s = 0.0;
-        for (int b = 0; b < nparts; ++b) s += part[b];
-        *out = s;
+// One wave: lane l sums partials l*c .. l*c+c-1 in order (c = nparts / 64,
+// nparts a multiple of 64), lane 0 then sums the 64 lane sums in order.
+__global__ __launch_bounds__(64) void k_final_sum(const double *part, int nparts, double *out) {
+    __shared__ double s_l[64];
+    const int c = nparts / 64;
+    double s = 0.0;
+    for (int b = 0; b < c; ++b) s += part[threadIdx.x * c + b];
+    s_l[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int l = 0; l < 64; ++l) t += s_l[l];
+        *out = t;
     }
 }
+static_assert(kSumBlocks % 64 == 0, "final sum splits the partials over one wave");
 
 // Power iteration on M^-1/2 K M^-1/2 over the free components: u = y m^-1/2
 // (prescribed components zero), and after f = K u (k_eval_*): z = f m^-1/2.

@@ -48,7 +48,7 @@ struct Params {
     const int4 *conn;    // per element: nodes n0 n1 n2 (CCW), .w unused
     const int4 *nbr;     // per element: neighbour across local edge k = 0, 1, 2 (-1: none);
                          // .w: local index of that edge in the neighbour, 2 bits per k
-    const double *geo;   // 8 per element: dN/dx of n0..n2, dN/dy of n0..n2, area, 0
+    const int4 *opp;     // per element: the neighbour's node off the shared edge k (-1: none)
     const double2 *xy;   // reference coordinates
     double2 *u, *v;      // displacement, velocity
     const double *minv;
@@ -57,9 +57,12 @@ struct Params {
     const uint8_t *nflag;
     uint8_t *split;      // 0 intact, else kSplitFlag | entry << 2 | exit
     const double *gc;    // per element
-    double2 *fe;         // 3 per element: force on local node n
+    double2 *fe;         // 3 ne: force on local node n of element e at [n ne + e]
     const int32_t *csr_off;  // nn + 1
-    const int32_t *csr_ent;  // element * 3 + local node, by element colour per node
+    const int32_t *csr_ent;  // force slot n * ne + e, by element colour per node
+    const int32_t *nlist;    // the same lists padded to nlist_w slots (-1), node-major [nn][w];
+    int32_t nlist_w;         //   null when a node touches more than 16 elements (CSR is used)
+    int32_t pad2;
     Cand *cand;          // 3 ne
     LogRec *log;
     Ctl *ctl;

@@ -38,17 +38,20 @@ struct Geo {
     double bx[3], by[3], A;
 };
 
-__device__ __forceinline__ Geo load_geo(const double *geo, int e) {
-    const double2 *g = reinterpret_cast<const double2 *>(geo + 8 * (int64_t)e);
-    const double2 a = g[0], b = g[1], c = g[2], d = g[3];
+// Gradients of the linear shape functions and area of the triangle with
+// corners a, b, c (in its local node order); recomputed from the node
+// coordinates rather than stored.
+__device__ __forceinline__ Geo make_geo(const double2 &a, const double2 &b, const double2 &c) {
+    const double twoA = (b.x - a.x) * (c.y - a.y) - (c.x - a.x) * (b.y - a.y);
+    const double inv = 1.0 / twoA;
     Geo r;
-    r.bx[0] = a.x;
-    r.bx[1] = a.y;
-    r.bx[2] = b.x;
-    r.by[0] = b.y;
-    r.by[1] = c.x;
-    r.by[2] = c.y;
-    r.A = d.x;
+    r.bx[0] = (b.y - c.y) * inv;
+    r.bx[1] = (c.y - a.y) * inv;
+    r.bx[2] = (a.y - b.y) * inv;
+    r.by[0] = (c.x - b.x) * inv;
+    r.by[1] = (a.x - c.x) * inv;
+    r.by[2] = (b.x - a.x) * inv;
+    r.A = 0.5 * twoA;
     return r;
 }
 
@@ -86,30 +89,40 @@ __device__ __forceinline__ void hooke(const Params &p, const double e[3], double
     s[2] = p.D33 * e[2];
 }
 
-__device__ __forceinline__ void load_u(const double2 *u, const int4 &c, double2 out[3]) {
+__device__ __forceinline__ void load_u(const double2 *u, const int4 &c, double2 out[3]) {  // or coordinates
     out[0] = u[c.x];
     out[1] = u[c.y];
     out[2] = u[c.z];
 }
 
 // Smoothed strain of local edge k of intact element e (own strain q, area
-// A); two_out reports whether the neighbour across k is intact.
-__device__ __forceinline__ void edge_strain(const Params &p, const double2 *u, int e, int nb, const double q[3],
-                                            double A, double eps[3], bool &two_out) {
+// A).  The neighbour nb across k runs the shared edge backwards: its local
+// node loc is our node k+1 (xb, ub), loc+1 is our node k (xa, ua) and
+// loc+2 is its third node (xo, uo); its strain is recomputed in its own
+// node order.  two_out: the neighbour is intact; An: its area.
+__device__ __forceinline__ void edge_strain(const Params &p, int e, int nb, int loc, const double2 &xa,
+                                            const double2 &xb, const double2 &xo, const double2 &ua,
+                                            const double2 &ub, const double2 &uo, const double q[3], double A,
+                                            double eps[3], bool &two_out, double &An) {
     const bool two = nb >= 0 && p.split[nb] == 0;
     two_out = two;
+    An = 0.0;
     if (!two) {
         eps[0] = q[0];
         eps[1] = q[1];
         eps[2] = q[2];
         return;
     }
-    const int4 c2 = p.conn[nb];
-    const Geo g2 = load_geo(p.geo, nb);
-    double2 u2[3];
-    load_u(u, c2, u2);
+    double2 u2[3], x2[3];
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+        u2[n] = sel3((n - loc + 3) % 3, ub, ua, uo);
+        x2[n] = sel3((n - loc + 3) % 3, xb, xa, xo);
+    }
+    const Geo g2 = make_geo(x2[0], x2[1], x2[2]);
     double q2[3];
     strain(g2, u2, q2);
+    An = g2.A;
     const bool self_lo = e < nb;
     const double Alo = self_lo ? A : g2.A, Ahi = self_lo ? g2.A : A;
     const double sum = Alo + Ahi;
@@ -232,15 +245,17 @@ __global__ __launch_bounds__(kB) void k_force(Params p, const double2 *u, Eval e
     if (e >= p.ne) return;
     const int4 c = p.conn[e];
     const uint8_t code = p.split[e];
-    double2 *fe = p.fe + 3 * (int64_t)e;
+    // slot-major element forces: node slot n of element e at fe[n ne + e]
+    double2 *fe = p.fe + e;
+    const int64_t fs = p.ne;
     if (code) {
         const Piece pa = piece(p, u, c, (code >> 2) & 3, code & 3);
         const Piece pb = piece(p, u, c, code & 3, (code >> 2) & 3);
         double w = pa.w;
         w += pb.w;
         fe[0] = piece_force_at(pa, pb, 0);
-        fe[1] = piece_force_at(pa, pb, 1);
-        fe[2] = piece_force_at(pa, pb, 2);
+        fe[fs] = piece_force_at(pa, pb, 1);
+        fe[2 * fs] = piece_force_at(pa, pb, 2);
         if constexpr (EVAL) {
             if (ev.pe) ev.pe[e] = w;
             if (ev.es_ek)
@@ -253,18 +268,28 @@ __global__ __launch_bounds__(kB) void k_force(Params p, const double2 *u, Eval e
         }
         return;
     }
-    const Geo g = load_geo(p.geo, e);
-    double2 ue[3];
+    const int4 nb = p.nbr[e];
+    const int4 op = p.opp[e];
+    double2 ue[3], uo[3], xe[3], xo[3];
     load_u(u, c, ue);
+    load_u(p.xy, c, xe);
+    const double2 z2 = make_double2(0.0, 0.0);
+    uo[0] = op.x >= 0 ? u[op.x] : z2;
+    uo[1] = op.y >= 0 ? u[op.y] : z2;
+    uo[2] = op.z >= 0 ? u[op.z] : z2;
+    xo[0] = op.x >= 0 ? p.xy[op.x] : z2;
+    xo[1] = op.y >= 0 ? p.xy[op.y] : z2;
+    xo[2] = op.z >= 0 ? p.xy[op.z] : z2;
+    const Geo g = make_geo(xe[0], xe[1], xe[2]);
     double q[3];
     strain(g, ue, q);
-    const int4 nb = p.nbr[e];
     double sig[3][3];
     bool two[3];
-    double eps[3][3];
+    double eps[3][3], An[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        edge_strain(p, u, e, k == 0 ? nb.x : (k == 1 ? nb.y : nb.z), q, g.A, eps[k], two[k]);
+        edge_strain(p, e, k == 0 ? nb.x : (k == 1 ? nb.y : nb.z), (nb.w >> (2 * k)) & 3, xe[k], xe[(k + 1) % 3],
+                    xo[k], ue[k], ue[(k + 1) % 3], uo[k], q, g.A, eps[k], two[k], An[k]);
         hooke(p, eps[k], sig[k]);
     }
     double S[3];
@@ -273,7 +298,7 @@ __global__ __launch_bounds__(kB) void k_force(Params p, const double2 *u, Eval e
     const double coef = g.A / 3.0;
 #pragma unroll
     for (int n = 0; n < 3; ++n)
-        fe[n] = make_double2(coef * fma(g.by[n], S[2], g.bx[n] * S[0]), coef * fma(g.bx[n], S[2], g.by[n] * S[1]));
+        fe[n * fs] = make_double2(coef * fma(g.by[n], S[2], g.bx[n] * S[0]), coef * fma(g.bx[n], S[2], g.by[n] * S[1]));
     if constexpr (EVAL) {
         if (ev.pe) ev.pe[e] = 0.0;
         if (ev.sig_ek)
@@ -289,9 +314,8 @@ __global__ __launch_bounds__(kB) void k_force(Params p, const double2 *u, Eval e
                     // lower element id first
                     double As = 0.0;
                     if (two[k]) {
-                        const double An = load_geo(p.geo, n).A;
                         As += g.A / 3.0;
-                        As += An / 3.0;
+                        As += An[k] / 3.0;
                     } else {
                         As += g.A / 3.0;
                     }
@@ -428,17 +452,37 @@ __device__ __forceinline__ double prescribed(const Params &p, double v0, double 
     return v0;
 }
 
+// Sum of the element forces on node i in colour order.  W > 0: padded
+// slot-major lists of width W (all loads issued before the adds); W = 0:
+// the CSR lists.
+template <int W>
 __device__ __forceinline__ double2 gather(const Params &p, int i) {
     double fx = 0.0, fy = 0.0;
-    const int t1 = p.csr_off[i + 1];
-    for (int t = p.csr_off[i]; t < t1; ++t) {
-        const double2 f = p.fe[p.csr_ent[t]];
-        fx = fx + f.x;
-        fy = fy + f.y;
+    if constexpr (W > 0) {
+        int ent[W];
+        double2 f[W];
+#pragma unroll
+        for (int d = 0; d < W; ++d) ent[d] = p.nlist[(int64_t)i * W + d];
+#pragma unroll
+        for (int d = 0; d < W; ++d) f[d] = ent[d] >= 0 ? p.fe[ent[d]] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int d = 0; d < W; ++d)
+            if (ent[d] >= 0) {
+                fx = fx + f[d].x;
+                fy = fy + f[d].y;
+            }
+    } else {
+        const int t1 = p.csr_off[i + 1];
+        for (int t = p.csr_off[i]; t < t1; ++t) {
+            const double2 f = p.fe[p.csr_ent[t]];
+            fx = fx + f.x;
+            fy = fy + f.y;
+        }
     }
     return make_double2(fx, fy);
 }
 
+template <int W>
 __global__ __launch_bounds__(kB) void k_node(Params p, int j) {
     __shared__ double s_phi;
     const int64_t k = p.ctl->base + j;
@@ -447,7 +491,7 @@ __global__ __launch_bounds__(kB) void k_node(Params p, int j) {
     __syncthreads();
     const int i = blockIdx.x * kB + threadIdx.x;
     if (i >= p.nn) return;
-    const double2 f = gather(p, i);
+    const double2 f = gather<W>(p, i);
     const uint8_t fl = p.nflag[i];
     const double2 fx = (fl & kLoaded) ? p.fext[i] : make_double2(0.0, 0.0);
     const double phi = s_phi, mi = p.minv[i];
@@ -479,7 +523,7 @@ __global__ __launch_bounds__(kB) void k_eval_nodes(Params p, const double2 *u, c
                                                    double phi, const double *mass, Eval ev) {
     const int i = blockIdx.x * kB + threadIdx.x;
     if (i >= p.nn) return;
-    const double2 f = gather(p, i);
+    const double2 f = gather<0>(p, i);
     if (ev.fint) {
         ev.fint[i] = f.x;
         ev.fint[p.nn + i] = f.y;
@@ -554,7 +598,14 @@ __global__ __launch_bounds__(kB) void k_normalize(int64_t n, const double *z, co
 
 hipError_t launch_step(const Params &p, int j, hipStream_t st) {
     k_force<false><<<nb_of(p.ne), kB, 0, st>>>(p, p.u, Eval{});
-    k_node<<<nb_of(p.nn), kB, 0, st>>>(p, j);
+    const int nb = nb_of(p.nn);
+    switch (p.nlist ? p.nlist_w : 0) {
+        case 4: k_node<4><<<nb, kB, 0, st>>>(p, j); break;
+        case 8: k_node<8><<<nb, kB, 0, st>>>(p, j); break;
+        case 12: k_node<12><<<nb, kB, 0, st>>>(p, j); break;
+        case 16: k_node<16><<<nb, kB, 0, st>>>(p, j); break;
+        default: k_node<0><<<nb, kB, 0, st>>>(p, j); break;
+    }
     return hipGetLastError();
 }
 

@@ -170,7 +170,8 @@ void release(Model &m) {
     m.graph = nullptr;
     dfree(m.dconn);
     dfree(m.dnbr);
-    dfree(m.dgeo);
+    dfree(m.dopp);
+    dfree(m.dnlist);
     dfree(m.dminv);
     dfree(m.dgc);
     dfree(m.dcurve);
@@ -407,23 +408,6 @@ int finalize(Model &m, Host h) {
     if (need_mesh(m) || !m.have_material) return fail(h, MCT_ESTATE, "mesh and material are required");
     const int64_t nn = m.nn, ne = m.ne, ns = m.ns;
     release(m);  // device state only; the host tables stay
-    // element geometry: gradients of the linear shape functions and area
-    std::vector<double> geo(8 * ne, 0.0);
-    for (int64_t e = 0; e < ne; ++e) {
-        const int32_t *c = &m.conn[3 * e];
-        const double x0 = m.X[c[0]], x1 = m.X[c[1]], x2 = m.X[c[2]];
-        const double y0 = m.Y[c[0]], y1 = m.Y[c[1]], y2 = m.Y[c[2]];
-        const double twoA = (x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0);
-        const double inv = 1.0 / twoA;
-        double *g = &geo[8 * e];
-        g[0] = (y1 - y2) * inv;
-        g[1] = (y2 - y0) * inv;
-        g[2] = (y0 - y1) * inv;
-        g[3] = (x2 - x1) * inv;
-        g[4] = (x0 - x2) * inv;
-        g[5] = (x1 - x0) * inv;
-        g[6] = m.area[e];
-    }
     // lumped mass rho A / 3, element-id order per node
     m.mass.assign(nn, 0.0);
     for (int64_t e = 0; e < ne; ++e) {
@@ -499,11 +483,37 @@ int finalize(Model &m, Host h) {
     for (int64_t i = 0; i < nn; ++i)
         std::sort(nel.begin() + noff[i], nel.begin() + noff[i + 1],
                   [&](int32_t p, int32_t q) { return color[p / 3] < color[q / 3]; });
+    // gather entries name force slots n * ne + e (slot-major element forces)
+    for (int32_t &v : nel) v = (v % 3) * (int32_t)ne + v / 3;
     // device arrays
-    std::vector<int4> c4(ne), n4(ne);
+    // per element: neighbours, and each neighbour's node off the shared edge
+    // (the neighbour runs the edge backwards, so its local node loc + 2)
+    std::vector<int4> c4(ne), n4(ne), o4(ne);
     for (int64_t e = 0; e < ne; ++e) {
         c4[e] = make_int4(m.conn[3 * e], m.conn[3 * e + 1], m.conn[3 * e + 2], 0);
         n4[e] = make_int4(m.nbr[4 * e], m.nbr[4 * e + 1], m.nbr[4 * e + 2], m.nbr[4 * e + 3]);
+        int32_t o[3];
+        for (int k = 0; k < 3; ++k) {
+            const int32_t nb = m.nbr[4 * e + k];
+            o[k] = -1;
+            if (nb < 0) continue;
+            const int loc = (m.nbr[4 * e + 3] >> (2 * k)) & 3;
+            if (m.conn[3 * (int64_t)nb + loc] != m.conn[3 * e + (k + 1) % 3] ||
+                m.conn[3 * (int64_t)nb + (loc + 1) % 3] != m.conn[3 * e + k])
+                return fail(h, MCT_EINVAL, "inconsistent neighbour table at element %lld", (long long)e);
+            o[k] = m.conn[3 * (int64_t)nb + (loc + 2) % 3];
+        }
+        o4[e] = make_int4(o[0], o[1], o[2], 0);
+    }
+    // padded gather lists (node-major, W slots) when every node touches <= 16 elements
+    int32_t maxdeg = 0;
+    for (int64_t i = 0; i < nn; ++i) maxdeg = std::max(maxdeg, noff[i + 1] - noff[i]);
+    const int32_t W = (maxdeg + 3) / 4 * 4;
+    std::vector<int32_t> nlist;
+    if (W <= 16) {
+        nlist.assign((size_t)W * nn, -1);
+        for (int64_t i = 0; i < nn; ++i)
+            for (int32_t t = noff[i]; t < noff[i + 1]; ++t) nlist[(size_t)i * W + (t - noff[i])] = nel[t];
     }
     std::vector<double> xy(2 * nn);
     for (int64_t i = 0; i < nn; ++i) {
@@ -517,7 +527,8 @@ int finalize(Model &m, Host h) {
     int rc;
     if ((rc = upload<int4>(h, m.dconn, c4.data(), ne))) return rc;
     if ((rc = upload<int4>(h, m.dnbr, n4.data(), ne))) return rc;
-    if ((rc = upload<double>(h, m.dgeo, geo.data(), geo.size()))) return rc;
+    if ((rc = upload<int4>(h, m.dopp, o4.data(), ne))) return rc;
+    if (!nlist.empty() && (rc = upload<int32_t>(h, m.dnlist, nlist.data(), nlist.size()))) return rc;
     if ((rc = upload<double>(h, m.dminv, minv.data(), nn))) return rc;
     if ((rc = upload<double>(h, m.dmass, m.mass.data(), nn))) return rc;
     if ((rc = upload<double>(h, m.dgc, gc.data(), ne))) return rc;
@@ -579,7 +590,9 @@ int finalize(Model &m, Host h) {
     p.ncurve = (int32_t)ncv;
     p.conn = m.dconn;
     p.nbr = m.dnbr;
-    p.geo = m.dgeo;
+    p.opp = m.dopp;
+    p.nlist = m.dnlist;
+    p.nlist_w = m.dnlist ? W : 0;
     p.xy = m.dxy;
     p.u = m.du;
     p.v = m.dv;

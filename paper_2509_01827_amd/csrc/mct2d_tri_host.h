@@ -49,11 +49,11 @@ struct Model {
     std::vector<double> mass;
     Params prm{};
     // device memory
-    int4 *dconn = nullptr, *dnbr = nullptr;
-    double *dgeo = nullptr, *dminv = nullptr, *dgc = nullptr, *dcurve = nullptr, *dmass = nullptr;
+    int4 *dconn = nullptr, *dnbr = nullptr, *dopp = nullptr;
+    double *dminv = nullptr, *dgc = nullptr, *dcurve = nullptr, *dmass = nullptr;
     double2 *dxy = nullptr, *du = nullptr, *dv = nullptr, *dfext = nullptr, *dv0 = nullptr, *dfe = nullptr;
     uint8_t *dflag = nullptr, *dsplit = nullptr;
-    int32_t *dcsr_off = nullptr, *dcsr_ent = nullptr, *dedge_elem = nullptr, *dwatch = nullptr;
+    int32_t *dcsr_off = nullptr, *dcsr_ent = nullptr, *dnlist = nullptr, *dedge_elem = nullptr, *dwatch = nullptr;
     Cand *dcand = nullptr;
     LogRec *dlog = nullptr;
     Ctl *dctl = nullptr;

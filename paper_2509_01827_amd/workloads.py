@@ -270,10 +270,9 @@ def small_batch(n=12, steps=600):
 #
 # A CST model is described by the same dictionary with ``conn`` ([ne][3]
 # int32, counter-clockwise node triples) in place of ``nx``/``ny``.  Meshes
-# are Delaunay triangulations (scipy) of seeded jittered point sets; the
-# triangles are handed over in Morton order of their centroids so that
-# neighbouring elements have nearby ids (the library keeps the caller's
-# numbering).
+# are Delaunay triangulations (scipy) of seeded jittered point sets; nodes
+# and triangles (by centroid) are numbered along a Morton curve so that
+# neighbours have nearby ids (the library keeps the caller's numbering).
 
 E_STEEL = 210.0e9
 NU_STEEL = 0.3
@@ -295,15 +294,26 @@ def _triangulate(X, Y, h):
     return T, _morton_sort(T, X, Y, h)
 
 
-def _morton_sort(T, X, Y, h):
-    cx = (X[T[:, 0]] + X[T[:, 1]] + X[T[:, 2]]) / 3.0
-    cy = (Y[T[:, 0]] + Y[T[:, 1]] + Y[T[:, 2]]) / 3.0
-    ix = np.floor((cx - cx.min()) / h).astype(np.uint64)
-    iy = np.floor((cy - cy.min()) / h).astype(np.uint64)
-    key = np.zeros(len(T), np.uint64)
+def _morton_key(x, y, h):
+    ix = np.floor((x - x.min()) / h).astype(np.uint64)
+    iy = np.floor((y - y.min()) / h).astype(np.uint64)
+    key = np.zeros(len(x), np.uint64)
     for b in range(21):
         key |= ((ix >> np.uint64(b)) & np.uint64(1)) << np.uint64(2 * b)
         key |= ((iy >> np.uint64(b)) & np.uint64(1)) << np.uint64(2 * b + 1)
+    return key
+
+
+def morton_nodes(X, Y, h):
+    """Node order along a Morton curve on a grid of spacing h (ties: the
+    given order); returns the permutation (new id -> old id)."""
+    return np.argsort(_morton_key(X, Y, h), kind="stable")
+
+
+def _morton_sort(T, X, Y, h):
+    cx = (X[T[:, 0]] + X[T[:, 1]] + X[T[:, 2]]) / 3.0
+    cy = (Y[T[:, 0]] + Y[T[:, 1]] + Y[T[:, 2]]) / 3.0
+    key = _morton_key(cx, cy, h)
     order = np.lexsort((T[:, 2], T[:, 1], T[:, 0], key))
     return np.ascontiguousarray(T[order].astype(np.int32))
 
@@ -372,7 +382,10 @@ def tri_plate(nx, ny, lx, ly, *, traction=1.0e6, jitter=0.3, seed=BASE_SEED + 70
     traction on the upper and lower edges, pre-notch of length
     ``notch_len`` (m) along mid-height from the left edge."""
     X, Y = grid_coords(nx, ny, lx, ly, jitter, seed)
-    T = _triangulate(X, Y, min(lx / nx, ly / ny))[1]
+    h = min(lx / nx, ly / ny)
+    perm = morton_nodes(X, Y, h)
+    X, Y = np.ascontiguousarray(X[perm]), np.ascontiguousarray(Y[perm])
+    T = _triangulate(X, Y, h)[1]
     be = boundary_edges(T)
     top = (Y[be[:, 0]] == ly) & (Y[be[:, 1]] == ly)
     bot = (Y[be[:, 0]] == 0.0) & (Y[be[:, 1]] == 0.0)
@@ -414,6 +427,8 @@ def tri_cylinder(r_in=0.05, r_out=0.1, h=1.0e-3, *, p0=400.0e6, t0=1.0e-6, tau=1
     size (about 27 000 nodes / 53 000 triangles) is that of the paper's fine
     mesh; its radii are not printed and are a reading."""
     X, Y, ring = ring_points(r_in, r_out, h, seed=seed)
+    perm = morton_nodes(X, Y, h)
+    X, Y, ring = np.ascontiguousarray(X[perm]), np.ascontiguousarray(Y[perm]), ring[perm]
     T, Ts = _triangulate(X, Y, h)
     cx = (X[Ts[:, 0]] + X[Ts[:, 1]] + X[Ts[:, 2]]) / 3.0
     cy = (Y[Ts[:, 0]] + Y[Ts[:, 1]] + Y[Ts[:, 2]]) / 3.0
@@ -455,6 +470,8 @@ def tri_fragment(nx, ny, h, *, v=5.0, seed=BASE_SEED + 90, steps=2000, name="tri
     """Un-notched CST plate with outward normal velocity on all edges and a
     Weibull(6, 3 N/m) Gc field (the Dirichlet fragmentation set-up)."""
     X, Y = grid_coords(nx, ny, nx * h, ny * h, 0.3, seed)
+    perm = morton_nodes(X, Y, h)
+    X, Y = np.ascontiguousarray(X[perm]), np.ascontiguousarray(Y[perm])
     T = _triangulate(X, Y, h)[1]
     lx, ly = nx * h, ny * h
     nodes, masks, vel = [], [], []
