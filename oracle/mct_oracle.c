@@ -113,6 +113,9 @@ typedef struct {
      * element * 4 + local edge of the intact element at the current tip, or
      * -1 (start tip: -2 = derive from the pre-notch at finalize) */
     int sct, tip;
+    /* per-front pick (a variant of the Sec. 3 pick): front_r2 = rho^2 > 0
+     * enables it; 0 = the global pick */
+    double front_r2;
     /* scratch */
     double *sig;            /* 3 per edge */
     double *eps;            /* 3 per edge: smoothed strain */
@@ -527,6 +530,55 @@ int orc_mct_pick(int n, const double *G, const int *elem, const int *a, double g
     return best;
 }
 
+/* Reference midpoint of the tip edge a of element e (the quadrature point
+ * G0 of the candidate). */
+static void tip_midpoint(const orc_model_t *m, int e, int a, double *x, double *y) {
+    int p = m->conn[4 * e + a], q = m->conn[4 * e + (a + 1) % m->nv];
+    *x = 0.5 * (m->X[p] + m->X[q]);
+    *y = 0.5 * (m->Y[p] + m->Y[q]);
+}
+
+/* key order of the pick: larger G, then lower element id, then lower tip edge */
+static int better_key(double G1, int e1, int a1, double G2, int e2, int a2) {
+    if (G1 != G2) return G1 > G2;
+    if (e1 != e2) return e1 < e2;
+    return a1 < a2;
+}
+
+/* Per-front pick (variant): candidate c splits iff, against every other
+ * accepted candidate c' it competes with -- the same element, or a tip point
+ * closer than rho (squared distance < rho^2) -- it has the better key and
+ * passes the split-ratio test G_c > gamma (G_c - G_c').  With rho = infinity
+ * this is the global pick.  Picked candidates never compete with each
+ * other, so their elements are distinct.  Writes the picked indices, in key
+ * order, to out; returns their count. */
+int orc_front_pick(int n, const double *G, const int *elem, const int *a, const double *x, const double *y,
+                   double gamma, double rho2, int *out) {
+    int np = 0;
+    for (int c = 0; c < n; ++c) {
+        int ok = 1;
+        for (int d = 0; d < n && ok; ++d) {
+            if (d == c) continue;
+            double dx = x[c] - x[d], dy = y[c] - y[d];
+            int compete = elem[c] == elem[d] || dx * dx + dy * dy < rho2;
+            if (!compete) continue;
+            if (!better_key(G[c], elem[c], a[c], G[d], elem[d], a[d])) ok = 0;
+            if (!(G[c] > gamma * (G[c] - G[d]))) ok = 0;
+        }
+        if (ok) out[np++] = c;
+    }
+    /* key order (insertion sort, small sets) */
+    for (int i = 1; i < np; ++i) {
+        int v = out[i], j = i - 1;
+        while (j >= 0 && better_key(G[v], elem[v], a[v], G[out[j]], elem[out[j]], a[out[j]])) {
+            out[j + 1] = out[j];
+            j--;
+        }
+        out[j + 1] = v;
+    }
+    return np;
+}
+
 /* Free-surface candidate (R: edge with exactly one intact neighbour, i.e. a
  * domain-boundary edge of an intact element or an edge shared with a split
  * element).  Sets the intact element f and the local index a of the edge in
@@ -624,8 +676,20 @@ static void fracture_phase(orc_model_t *m) {
     }
     free(acc);
     free(accG);
-    int c = orc_mct_pick(nc, cG, cE, cA, m->gamma);
-    if (c >= 0) record_split(m, cE[c], cA[c], cK[c], cG[c]);
+    if (m->front_r2 > 0.0) {
+        double *px = malloc(sizeof(double) * (size_t)(nc ? nc : 1));
+        double *py = malloc(sizeof(double) * (size_t)(nc ? nc : 1));
+        int *pick = malloc(sizeof(int) * (size_t)(nc ? nc : 1));
+        for (int i = 0; i < nc; ++i) tip_midpoint(m, cE[i], cA[i], &px[i], &py[i]);
+        int np = orc_front_pick(nc, cG, cE, cA, px, py, m->gamma, m->front_r2, pick);
+        for (int i = 0; i < np; ++i) record_split(m, cE[pick[i]], cA[pick[i]], cK[pick[i]], cG[pick[i]]);
+        free(px);
+        free(py);
+        free(pick);
+    } else {
+        int c = orc_mct_pick(nc, cG, cE, cA, m->gamma);
+        if (c >= 0) record_split(m, cE[c], cA[c], cK[c], cG[c]);
+    }
     free(cG);
     free(cE);
     free(cA);
@@ -1017,6 +1081,14 @@ int orc_set_tracking(orc_model_t *m, int mode, int elem, int edge) {
 }
 
 int orc_get_tip(const orc_model_t *m) { return m->tip; }
+
+/* Per-front pick with competition radius rho (> 0; infinity = the global
+ * pick); rho = 0 restores the global pick.  Not with single-tip tracking. */
+int orc_set_front_pick(orc_model_t *m, double rho) {
+    if (!(rho >= 0.0)) return ORC_EINVAL;
+    m->front_r2 = rho * rho;
+    return ORC_OK;
+}
 
 /* Traction load curve (n >= 2 points, t strictly increasing), n = 0 clears. */
 int orc_set_load_curve(orc_model_t *m, int n, const double *t, const double *phi) {

@@ -67,6 +67,8 @@ def lib():
         _lib.orc_element_rule_n.argtypes = [C.c_int, dp, C.c_double, C.c_double]
         _lib.orc_mct_pick.argtypes = [C.c_int, dp, ip, ip, C.c_double]
         _lib.orc_set_tracking.argtypes = [P, C.c_int, C.c_int, C.c_int]
+        _lib.orc_set_front_pick.argtypes = [P, C.c_double]
+        _lib.orc_front_pick.argtypes = [C.c_int, dp, ip, ip, dp, dp, C.c_double, C.c_double, ip]
         _lib.orc_get_tip.argtypes = [P]
         _lib.orc_get_tip.restype = C.c_int
         _lib.orc_set_load_curve.argtypes = [P, C.c_int, dp, dp]
@@ -106,6 +108,15 @@ def element_rule_n(G, Gc, gamma):
     """Element decision over len(G) candidate paths (2: CST, 3: Q4)."""
     G = _f64(G)
     return lib().orc_element_rule_n(len(G), G, float(Gc), float(gamma))
+
+
+def front_pick(G, elem, a, x, y, gamma, rho):
+    """Indices of the candidates the per-front pick splits, in key order."""
+    G = _f64(G)
+    out = np.zeros(max(len(G), 1), np.int32)
+    n = lib().orc_front_pick(len(G), G, _i32(elem), _i32(a), _f64(x), _f64(y), float(gamma),
+                             float(rho) ** 2, out)
+    return out[:n]
 
 
 def mct_pick(G, elem, a, gamma):
@@ -151,6 +162,8 @@ class Oracle:
         trk = cfg.get("tracking")
         if trk is not None:  # ("sct", elem or -1, edge)
             self._check(L.orc_set_tracking(self.h, 1 if trk[0] == "sct" else 0, int(trk[1]), int(trk[2])))
+        if cfg.get("front_radius"):  # per-front pick with this competition radius (m)
+            self._check(L.orc_set_front_pick(self.h, float(cfg["front_radius"])))
         if finalize:
             self._check(L.orc_finalize(self.h))
 
