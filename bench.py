@@ -68,8 +68,8 @@ def bytes_per_step(cfgs) -> int:
 # shape; otherwise the traffic is reported as unknown.
 MEASURED_TRAFFIC = {
     "plate400": {"sources": ("mct2d_step.hip", "mct2d_impl.h", "mct2d_device.h"),
-                 "sha256": "0bf7db7be35ea7425312cf2e357f174b99363e1f1e426c7a7b51b857cb032a9e",
-                 "tile": 1, "fetch_kib": 5597.0134, "write_kib": 5044.4109},
+                 "sha256": "7b5f2e0b164696a218cd468b9b26e0990f98598c6c29d329c190f08a15da8c8a",
+                 "tile": 1, "fetch_kib": 5607.0269, "write_kib": 5044.4092},
     "batch256": {"sources": ("mct2d_step.hip", "mct2d_impl.h", "mct2d_device.h"),
                  "sha256": "0bf7db7be35ea7425312cf2e357f174b99363e1f1e426c7a7b51b857cb032a9e",
                  "tile": 1, "fetch_kib": 423141.03, "write_kib": 474325.76},

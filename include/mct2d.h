@@ -173,6 +173,20 @@ int mct_set_load_curve(mct_ctx *ctx, int64_t n, const double *t, const double *p
 enum { MCT_TRACK_MCT = 0, MCT_TRACK_SCT = 1 };
 int mct_set_tracking(mct_ctx *ctx, int mode, int32_t tip_elem, int tip_edge);
 
+/* Per-front pick, a variant of the Multiple Crack-tips Tracking pick
+ * (Sec. 3): an accepted candidate (one that passed the element rule) splits
+ * iff, against every other accepted candidate it competes with -- the same
+ * element, or a tip point (reference midpoint of the tip edge) closer than
+ * rho -- it has the larger G (ties: lower element id, then lower tip edge)
+ * and passes G > gamma (G - G_other).  Fronts farther apart than rho then
+ * advance in the same step; picked candidates never compete, so each
+ * element splits at most once; the splits of a step are logged in that key
+ * order.  rho = +infinity gives the global pick exactly; rho = 0 (default)
+ * selects the global pick.  Plain contexts (Q4 grid or CST mesh);
+ * MCT_EUNSUPPORTED on a batch or with the split-screen, MCT_EINVAL at
+ * finalize together with single-tip tracking. */
+int mct_set_front_pick(mct_ctx *ctx, double rho);
+
 /* Time step: dt > 0 is used as given; otherwise dt = cfl_fraction *
  * (shortest edge) / c_d with c_d = sqrt(E / (rho (1 - nu^2))). */
 int mct_set_time(mct_ctx *ctx, double dt, double cfl_fraction);

@@ -58,6 +58,7 @@ struct Spec {
     int sct = 0;             // single crack-tip tracking
     int32_t sct_elem = -1;   // start tip (element, local edge); -1: the pre-notch's path end
     int sct_edge = 0;
+    double front_rho = 0;    // per-front pick radius (0: the global pick)
     // derived
     double dt = 0;
     double dt_limit = 0;  // 2 / omega_max of the set-up mesh (power iteration)
@@ -92,6 +93,13 @@ struct mct_ctx {
     Control *dctl = nullptr;
     Slot *dslots = nullptr;
     LogRec *dlog = nullptr;
+    // per-front pick buffers (plain contexts)
+    mct::AccCand *dfcand = nullptr;
+    uint32_t *dfcount = nullptr;
+    double2 *dfmid = nullptr;
+    double *dflen = nullptr;
+    int32_t *dforder = nullptr;
+    uint8_t *dfpicked = nullptr;
     StepParams *dviews = nullptr;
     int2 *dunits = nullptr;
     int nunits = 0;
@@ -246,6 +254,12 @@ void release_device(mct_ctx *c) {
     dfree(c->dctl);
     dfree(c->dslots);
     dfree(c->dlog);
+    dfree(c->dfcand);
+    dfree(c->dfcount);
+    dfree(c->dfmid);
+    dfree(c->dflen);
+    dfree(c->dforder);
+    dfree(c->dfpicked);
     dfree(c->dviews);
     dfree(c->dunits);
     dfree(c->dtip_counts);
@@ -882,6 +896,18 @@ int mct_set_tracking(mct_ctx *c, int mode, int32_t tip_elem, int tip_edge) {
     return MCT_OK;
 }
 
+int mct_set_front_pick(mct_ctx *c, double rho) {
+    if (!c) return MCT_EINVAL;
+    TRI_FWD(c, set_front_pick, rho);
+    if (!(rho >= 0)) return fail(c, MCT_EINVAL, "front radius must be >= 0 (0: the global pick)");
+    if (c->batch && rho > 0) return fail(c, MCT_EUNSUPPORTED, "the per-front pick needs a plain context");
+    Spec &s = cur(c);
+    if (!s.nx) return fail(c, MCT_ESTATE, "set the mesh first");
+    s.front_rho = rho;
+    c->finalized = false;
+    return MCT_OK;
+}
+
 int mct_set_time(mct_ctx *c, double dt, double cfl_fraction) {
     if (!c) return MCT_EINVAL;
     TRI_FWD(c, set_time, dt, cfl_fraction);
@@ -1044,6 +1070,19 @@ int mct_finalize(mct_ctx *c) {
     }
     // the log of a specimen holds up to one split per element
     HIP_TRY(c, hipMalloc((void **)&c->dlog, sizeof(LogRec) * (size_t)std::max<int64_t>(ne, 1)));
+    const bool front = !c->batch && c->specs[0].front_rho > 0;
+    if (front) {
+        if (c->specs[0].sct) return fail(c, MCT_EINVAL, "per-front pick and single-tip tracking exclude each other");
+        if (c->screen_on) return fail(c, MCT_EUNSUPPORTED, "per-front pick with the split-screen");
+        const size_t cap = 4 * (size_t)std::max<int64_t>(ne, 1);  // up to four candidates per element
+        HIP_TRY(c, hipMalloc((void **)&c->dfcand, sizeof(mct::AccCand) * cap));
+        HIP_TRY(c, hipMalloc((void **)&c->dfcount, sizeof(uint32_t)));
+        HIP_TRY(c, hipMemsetAsync(c->dfcount, 0, sizeof(uint32_t), c->stream));
+        HIP_TRY(c, hipMalloc((void **)&c->dfmid, sizeof(double2) * cap));
+        HIP_TRY(c, hipMalloc((void **)&c->dflen, sizeof(double) * cap));
+        HIP_TRY(c, hipMalloc((void **)&c->dforder, sizeof(int32_t) * cap));
+        HIP_TRY(c, hipMalloc((void **)&c->dfpicked, cap));
+    }
     int64_t max_ns = 0;
     for (const Spec &s : c->specs) max_ns = std::max(max_ns, s.ns);
     HIP_TRY(c, hipMalloc((void **)&c->dtip_counts, sizeof(int32_t) * (size_t)mct::tips_nblocks(max_ns)));
@@ -1084,6 +1123,15 @@ int mct_finalize(mct_ctx *c) {
         p.curve_phi = p.ncurve ? c->dcurve + ncv + s.curve_off : nullptr;
         p.ctl = c->dctl + q;
         p.log = c->dlog + s.elem_off;
+        p.front = front ? 1 : 0;
+        p.fcap = front ? (int32_t)(4 * s.ne) : 0;
+        p.front_r2 = front ? s.front_rho * s.front_rho : 0.0;
+        p.fcand = c->dfcand;
+        p.fcount = c->dfcount;
+        p.fmid = c->dfmid;
+        p.flen = c->dflen;
+        p.forder = c->dforder;
+        p.fpicked = c->dfpicked;
     }
     c->finalized = true;  // the launch geometry below needs the device arrays
     rc = set_launch_geometry(c);
@@ -1584,6 +1632,7 @@ int mct_screen_enable(mct_ctx *c, const mct_mlp *mlp, float tau, int period) {
     if (!c) return MCT_EINVAL;
     TRI_UNSUPPORTED(c, "the split-screen");
     if (!mlp) return fail(c, MCT_EINVAL, "null model");
+    if (!c->batch && cur(c).front_rho > 0) return fail(c, MCT_EUNSUPPORTED, "the split-screen with the per-front pick");
     if (period < 2) return fail(c, MCT_EINVAL, "period must be at least 2");
     int rc = ensure_screen(c);
     if (rc) return rc;

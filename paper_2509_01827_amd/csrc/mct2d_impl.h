@@ -21,6 +21,15 @@ struct LogRec {
 };
 static_assert(sizeof(LogRec) == 24, "LogRec layout");
 
+// One accepted candidate of a step (per-front pick): G of its chosen path,
+// the element, (tip edge a) << 2 | (exit edge k).
+struct AccCand {
+    double G;
+    int32_t elem;
+    int32_t ak;
+};
+static_assert(sizeof(AccCand) == 16, "AccCand layout");
+
 // Per-workgroup best candidate of one step (only workgroups with an
 // accepted candidate write one).
 struct Slot {
@@ -68,6 +77,17 @@ struct StepParams {
     Control *ctl;
     Slot *slots;        // 3 sets of nwg slots
     LogRec *log;
+    // per-front pick (plain models): every accepted candidate of a step is
+    // appended to fcand and a separate kernel picks; front_r2 = rho^2
+    int32_t front;
+    int32_t fcap;
+    double front_r2;
+    AccCand *fcand;
+    uint32_t *fcount;
+    double2 *fmid;
+    double *flen;
+    int32_t *forder;
+    uint8_t *fpicked;
 };
 
 // Tile shapes (elements per workgroup in x and y; nodes owned = one less).

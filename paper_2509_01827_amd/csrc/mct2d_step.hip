@@ -28,6 +28,7 @@
 // on the tile shape or on the schedule.
 #include "mct2d_device.h"
 #include "mct2d_impl.h"
+#include "mct2d_front.h"
 
 #include <climits>
 
@@ -662,6 +663,14 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
                 for (int q = 0; q < 3; ++q)
                     if (q != jb && Gv[q] > gc && !(gb > p.gamma * (gb - Gv[q]))) ok = false;
                 if (ok) cand_merge(best, gb, gb, (int)ge, a, (a + 1 + jb) & 3);
+                if (ok && p.front) {  // per-front pick: every accepted candidate
+                    const uint32_t slot = atomicAdd(p.fcount, 1u);
+                    AccCand ac;
+                    ac.G = gb;
+                    ac.elem = (int32_t)ge;
+                    ac.ak = (a << 2) | ((a + 1 + jb) & 3);
+                    p.fcand[slot] = ac;
+                }
             }
         }
     }
@@ -781,7 +790,7 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
     // ---- 8. publish the workgroup's best candidate -----------------------
     // Read by the next step after the kernel boundary; no fence here (a
     // device-scope release would write back the whole L2 of the XCD).
-    if (tid == 0 && best.G >= 0.0) {
+    if (tid == 0 && best.G >= 0.0 && !p.front) {
         const uint32_t slot = atomicAdd(&p.ctl->nslots[set_w], 1u);
         Slot sl;
         sl.G = best.G;
@@ -837,6 +846,68 @@ TileShape tile_shape(int tile) {
     }
 }
 
+// Per-front pick of a plain Q4 model (one workgroup), after k_step.
+constexpr int kFrontThreads = 1024;
+
+struct Q4Geom {
+    int nx;
+    const double *X, *Y;
+    __device__ void nodes(int e, int64_t nd[4]) const {
+        const int64_t i = e % nx, j = e / nx;
+        const int64_t n0 = j * (nx + 1) + i;
+        nd[0] = n0;
+        nd[1] = n0 + 1;
+        nd[2] = n0 + nx + 2;
+        nd[3] = n0 + nx + 1;
+    }
+    __device__ double2 tip(int e, int a) const {
+        int64_t nd[4];
+        nodes(e, nd);
+        const int64_t pa = a == 0 ? nd[0] : a == 1 ? nd[1] : a == 2 ? nd[2] : nd[3];
+        const int64_t pb = a == 0 ? nd[1] : a == 1 ? nd[2] : a == 2 ? nd[3] : nd[0];
+        return make_double2(0.5 * (X[pa] + X[pb]), 0.5 * (Y[pa] + Y[pb]));
+    }
+    __device__ double path_len(int e, int a, int k) const {
+        int64_t nd[4];
+        nodes(e, nd);
+        double x[4], y[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            x[q] = X[nd[q]];
+            y[q] = Y[nd[q]];
+        }
+        double cx, cy, L;
+        dev::path_geom(x, y, a, k, cx, cy, L);
+        return L;
+    }
+};
+
+__global__ __launch_bounds__(kFrontThreads) void k_front(StepParams p, int k_rel) {
+    FrontView v;
+    v.cand = p.fcand;
+    v.count = p.fcount;
+    v.mid = p.fmid;
+    v.len = p.flen;
+    v.order = p.forder;
+    v.picked = p.fpicked;
+    v.split = p.split;
+    v.log = p.log;
+    v.log_cap = p.log_cap;
+    v.nsplit = &p.ctl->nsplit;
+    v.Ud = &p.ctl->Ud;
+    v.overflow = &p.ctl->overflow;
+    v.base = &p.ctl->base;
+    v.gc = p.gc;
+    v.gc_uniform = p.gc_uniform;
+    v.gamma = p.gamma;
+    v.rho2 = p.front_r2;
+    Q4Geom g;
+    g.nx = p.nx;
+    g.X = p.X;
+    g.Y = p.Y;
+    front_pick_block<kFrontThreads>(v, g, k_rel);
+}
+
 hipError_t launch_step(int tile, const Launch &L, int k_rel, int par0, hipStream_t s) {
     (void)hipGetLastError();  // report only this launch's error below
     const StepParams &p = L.p0;
@@ -852,6 +923,7 @@ hipError_t launch_step(int tile, const Launch &L, int k_rel, int par0, hipStream
             case 2: k_step<32, 8, false><<<p.nwg, 256, 0, s>>>(p, nullptr, nullptr, k_rel, par0); break;
             default: k_step<32, 16, false><<<p.nwg, 512, 0, s>>>(p, nullptr, nullptr, k_rel, par0); break;
         }
+        if (p.front) k_front<<<1, kFrontThreads, 0, s>>>(p, k_rel);
     }
     return hipGetLastError();
 }

@@ -13,14 +13,8 @@
 namespace mct {
 namespace tri {
 
-// One accepted candidate of a step: G of its chosen path, the element and
-// (tip edge a) << 2 | (exit edge k).
-struct Cand {
-    double G;
-    int32_t elem;
-    int32_t ak;
-};
-static_assert(sizeof(Cand) == 16, "Cand layout");
+// One accepted candidate of a step (the layout of the per-front pick's).
+using Cand = AccCand;
 
 // Device-resident control block.
 struct Ctl {
@@ -69,6 +63,13 @@ struct Params {
     const double *curve_t, *curve_phi;
     double D11, D12, D33, E;
     double dt, t_ramp, gamma;
+    // per-front pick: front_r2 = rho^2 > 0 replaces the global pick by a
+    // separate pick kernel over the candidate list (scratch per candidate)
+    double front_r2;
+    double2 *fmid;
+    double *flen;
+    int32_t *forder;
+    uint8_t *fpicked;
 };
 
 // Evaluation outputs of the query kernels (nullptr = skip).

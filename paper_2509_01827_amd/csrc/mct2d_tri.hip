@@ -24,6 +24,7 @@
 // launch geometry.
 #include <cmath>
 
+#include "mct2d_front.h"
 #include "mct2d_tri.h"
 
 namespace mct {
@@ -594,10 +595,60 @@ __global__ __launch_bounds__(kB) void k_normalize(int64_t n, const double *z, co
     y[t] = s > 0.0 ? z[t] / s : 0.0;
 }
 
+// Per-front pick (variant of the Sec. 3 pick) over the step's candidate
+// list, one workgroup, between k_force and k_node (whose own pick then sees
+// an empty list).
+constexpr int kFrontThreads = 1024;
+
+struct TriGeom {
+    const int4 *conn;
+    const double2 *xy;
+    __device__ double2 tip(int e, int a) const {
+        const int4 c = conn[e];
+        const double2 P = xy[node_of(c, a)], Q = xy[node_of(c, (a + 1) % 3)];
+        return make_double2(0.5 * (P.x + Q.x), 0.5 * (P.y + Q.y));
+    }
+    __device__ double path_len(int e, int a, int k) const {
+        const int4 c = conn[e];
+        const double2 P0 = xy[node_of(c, a)], P1 = xy[node_of(c, (a + 1) % 3)];
+        const double2 Q0 = xy[node_of(c, k)], Q1 = xy[node_of(c, (k + 1) % 3)];
+        const double g0x = 0.5 * (P0.x + P1.x), g0y = 0.5 * (P0.y + P1.y);
+        const double gkx = 0.5 * (Q0.x + Q1.x), gky = 0.5 * (Q0.y + Q1.y);
+        const double dx = gkx - g0x, dy = gky - g0y;
+        return sqrt(dx * dx + dy * dy);
+    }
+};
+
+__global__ __launch_bounds__(kFrontThreads) void k_front(Params p, int j) {
+    FrontView v;
+    v.cand = p.cand;
+    v.count = reinterpret_cast<uint32_t *>(&p.ctl->nacc);
+    v.mid = p.fmid;
+    v.len = p.flen;
+    v.order = p.forder;
+    v.picked = p.fpicked;
+    v.split = p.split;
+    v.log = p.log;
+    v.log_cap = p.log_cap;
+    v.nsplit = &p.ctl->nsplit;
+    v.Ud = &p.ctl->Ud;
+    v.overflow = &p.ctl->overflow;
+    v.base = &p.ctl->base;
+    v.gc = p.gc;
+    v.gc_uniform = 0.0;
+    v.gamma = p.gamma;
+    v.rho2 = p.front_r2;
+    TriGeom g;
+    g.conn = p.conn;
+    g.xy = p.xy;
+    front_pick_block<kFrontThreads>(v, g, j);
+}
+
 }  // namespace
 
 hipError_t launch_step(const Params &p, int j, hipStream_t st) {
     k_force<false><<<nb_of(p.ne), kB, 0, st>>>(p, p.u, Eval{});
+    if (p.front_r2 > 0.0) k_front<<<1, kFrontThreads, 0, st>>>(p, j);
     const int nb = nb_of(p.nn);
     switch (p.nlist ? p.nlist_w : 0) {
         case 4: k_node<4><<<nb, kB, 0, st>>>(p, j); break;

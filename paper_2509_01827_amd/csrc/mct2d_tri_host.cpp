@@ -189,6 +189,10 @@ void release(Model &m) {
     dfree(m.dedge_elem);
     dfree(m.dwatch);
     dfree(m.dcand);
+    dfree(m.dfmid);
+    dfree(m.dflen);
+    dfree(m.dforder);
+    dfree(m.dfpicked);
     dfree(m.dlog);
     dfree(m.dctl);
     dfree(m.ev.sig_ek);
@@ -396,6 +400,14 @@ int set_tracking(Model &m, Host h, int mode, int32_t elem, int edge) {
     return MCT_OK;
 }
 
+int set_front_pick(Model &m, Host h, double rho) {
+    if (need_mesh(m)) return fail(h, MCT_ESTATE, "set the mesh first");
+    if (!(rho >= 0)) return fail(h, MCT_EINVAL, "front radius must be >= 0 (0: the global pick)");
+    m.front_rho = rho;
+    invalidate(m);
+    return MCT_OK;
+}
+
 int set_time(Model &m, Host h, double dt, double cfl) {
     if (!(dt > 0) && !(cfl > 0)) return fail(h, MCT_EINVAL, "need dt > 0 or cfl_fraction > 0");
     m.dt_in = dt;
@@ -552,6 +564,13 @@ int finalize(Model &m, Host h) {
     TRY(h, hipMemsetAsync(m.dv, 0, sizeof(double2) * nn, h.stream));
     TRY(h, hipMalloc((void **)&m.dfe, sizeof(double2) * 3 * ne));
     TRY(h, hipMalloc((void **)&m.dcand, sizeof(Cand) * 3 * ne));
+    if (m.front_rho > 0) {
+        if (m.sct) return fail(h, MCT_EINVAL, "per-front pick and single-tip tracking exclude each other");
+        TRY(h, hipMalloc((void **)&m.dfmid, sizeof(double2) * 3 * ne));
+        TRY(h, hipMalloc((void **)&m.dflen, sizeof(double) * 3 * ne));
+        TRY(h, hipMalloc((void **)&m.dforder, sizeof(int32_t) * 3 * ne));
+        TRY(h, hipMalloc((void **)&m.dfpicked, 3 * ne));
+    }
     TRY(h, hipMalloc((void **)&m.dlog, sizeof(LogRec) * ne));
     TRY(h, hipMalloc((void **)&m.dctl, sizeof(Ctl)));
     // start tip of single-tip tracking: given, or the one path end of the
@@ -617,6 +636,11 @@ int finalize(Model &m, Host h) {
     p.dt = m.dt;
     p.t_ramp = m.t_ramp;
     p.gamma = m.gamma;
+    p.front_r2 = m.front_rho > 0 ? m.front_rho * m.front_rho : 0.0;
+    p.fmid = m.dfmid;
+    p.flen = m.dflen;
+    p.forder = m.dforder;
+    p.fpicked = m.dfpicked;
     TRY(h, hipStreamSynchronize(h.stream));
     if ((rc = stability_limit(m, h))) return rc;
     if (m.dt > m.dt_limit)

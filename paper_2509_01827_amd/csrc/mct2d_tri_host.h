@@ -43,6 +43,7 @@ struct Model {
     int32_t sct_elem = -1;
     int sct_edge = 0;
     bool use_graph = true;
+    double front_rho = 0;  // per-front pick radius (0: the global pick)
     // derived at finalize
     bool finalized = false;
     double dt = 0, dt_limit = 0;
@@ -55,6 +56,10 @@ struct Model {
     uint8_t *dflag = nullptr, *dsplit = nullptr;
     int32_t *dcsr_off = nullptr, *dcsr_ent = nullptr, *dnlist = nullptr, *dedge_elem = nullptr, *dwatch = nullptr;
     Cand *dcand = nullptr;
+    double2 *dfmid = nullptr;
+    double *dflen = nullptr;
+    int32_t *dforder = nullptr;
+    uint8_t *dfpicked = nullptr;
     LogRec *dlog = nullptr;
     Ctl *dctl = nullptr;
     // query buffers (allocated on first use)
@@ -83,6 +88,7 @@ int set_notch(Model &m, Host h, int64_t n, const int32_t *elem, const uint8_t *e
 int set_load_curve(Model &m, Host h, int64_t n, const double *t, const double *phi);
 int set_tracking(Model &m, Host h, int mode, int32_t elem, int edge);
 int set_time(Model &m, Host h, double dt, double cfl);
+int set_front_pick(Model &m, Host h, double rho);
 int finalize(Model &m, Host h);
 int step(Model &m, Host h, int64_t n);
 int sync(Model &m, Host h);

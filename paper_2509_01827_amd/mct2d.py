@@ -46,7 +46,7 @@ EXPORTS = [
     "mct_screen_collect", "mct_screen_enable", "mct_screen_disable", "mct_screen_stats",
     "mct_mlp_create", "mct_mlp_destroy", "mct_mlp_last_error", "mct_mlp_set_params", "mct_mlp_get_params",
     "mct_mlp_forward", "mct_mlp_gradient", "mct_mlp_train_step", "mct_get_energies", "mct_set_tracking",
-    "mct_set_load_curve", "mct_set_mesh_tri",
+    "mct_set_load_curve", "mct_set_mesh_tri", "mct_set_front_pick",
 ]
 N_FEATURES = 10
 N_PARAMS = 4929
@@ -92,6 +92,7 @@ def load() -> C.CDLL:
     L.mct_set_time.argtypes = [P, C.c_double, C.c_double]
     L.mct_set_tracking.argtypes = [P, C.c_int, C.c_int32, C.c_int]
     L.mct_set_load_curve.argtypes = [P, C.c_int64, dp, dp]
+    L.mct_set_front_pick.argtypes = [P, C.c_double]
     L.mct_finalize.argtypes = [P]
     L.mct_step.argtypes = [P, C.c_int64]
     L.mct_sync.argtypes = [P]
@@ -216,6 +217,10 @@ class Model:
     def set_load_curve(self, t, phi):
         t, phi = _f64(t), _f64(phi)
         self._check(self._L.mct_set_load_curve(self._h, len(t), t, phi), "set_load_curve")
+
+    def set_front_pick(self, rho):
+        """Per-front pick with competition radius rho (m); 0 = the global pick."""
+        self._check(self._L.mct_set_front_pick(self._h, float(rho)), "set_front_pick")
 
     def set_tracking(self, mode="mct", tip_elem=-1, tip_edge=0):
         m = {"mct": 0, "sct": 1}[mode]
@@ -436,6 +441,8 @@ def _setup(m: Model, cfg: dict):
     lc = cfg.get("load_curve")
     if lc is not None:  # (t, phi)
         m.set_load_curve(lc[0], lc[1])
+    if cfg.get("front_radius"):
+        m.set_front_pick(cfg["front_radius"])
 
 
 def from_config(cfg: dict, stream: int | None = None, tile: int = 0, use_graph: bool = True) -> Model:

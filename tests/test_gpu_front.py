@@ -1,0 +1,116 @@
+"""Per-front pick on the GPU against the CPU oracle (Q4 grid and CST mesh):
+split logs, codes and fields bit-identical, with graph and direct launches;
+rho = infinity equals the global pick; errors for the combinations the
+variant excludes."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2509_01827_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2509_01827_amd import mct2d
+    mct2d.load()
+    return mct2d
+
+
+def _same(m, o, label):
+    lg, ol = m.crack_set(), o.log()
+    for k in ("step", "elem", "entry", "exit", "G"):
+        assert np.array_equal(lg[k], ol[k].astype(lg[k].dtype)), (label, k)
+    st = o.state()
+    assert np.array_equal(m.split_codes(), st["split"]), label
+    (ux, uy), (vx, vy) = m.field(0), m.field(1)
+    assert np.array_equal(ux, st["ux"]) and np.array_equal(uy, st["uy"]), label
+    assert np.array_equal(vx, st["vx"]) and np.array_equal(vy, st["vy"]), label
+    assert m.info()["dissipated"] == o.info()["Ud"], label
+
+
+def _double_notch(nx=40, ny=21, h=1e-3, ln=10, steps=700):
+    c = W.plate(nx, ny, nx * h, ny * h, steps=steps, name="double_notch")
+    row = ny // 2
+    el = [row * nx + i for i in range(ln)] + [row * nx + nx - 1 - i for i in range(ln)]
+    c["notch"] = (np.array(el, np.int32), np.array([3] * ln + [1] * ln, np.uint8),
+                  np.array([1] * ln + [3] * ln, np.uint8))
+    return c
+
+
+CASES = {
+    "q4_fragment": (lambda: dict(W.small_cases()["fragment97x45"], front_radius=3e-3), (1, 99, 200)),
+    "q4_double_notch": (lambda: dict(_double_notch(), front_radius=8e-3), (64, 300, 336)),
+    "cst_fragment": (lambda: dict(W.tri_small_cases()["tri_fragment"], front_radius=3e-3), (1, 99, 200)),
+    "cst_cylinder": (lambda: dict(W.tri_small_cases()["tri_cylinder_coarse"], front_radius=2e-2), (64, 136, 200)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_front_pick_matches_oracle(gpu, oracle_mod, name):
+    make, chunks = CASES[name]
+    cfg = make()
+    o = oracle_mod.Oracle(cfg)
+    models = [gpu.from_config(cfg, use_graph=g) for g in (True, False)]
+    done = 0
+    for ch in chunks:
+        o.step(ch)
+        done += ch
+        for m in models:
+            m.step(ch)
+            m.sync()
+            _same(m, o, (name, done))
+    lg = o.log()
+    assert len(lg["elem"]) > 5
+    assert np.any(np.diff(lg["step"]) == 0), "several splits in one step"
+    print(name, "splits", len(lg["elem"]), "steps with splits", len(np.unique(lg["step"])), flush=True)
+
+
+@pytest.mark.parametrize("kind", ["q4", "cst"])
+def test_infinite_radius_is_the_global_pick(gpu, oracle_mod, kind):
+    cfg = W.small_cases()["fragment97x45"] if kind == "q4" else W.tri_small_cases()["tri_fragment"]
+    g = gpu.from_config(cfg)
+    f = gpu.from_config(dict(cfg, front_radius=math.inf))
+    g.step(300)
+    f.step(300)
+    lg, lf = g.crack_set(), f.crack_set()
+    assert len(lg["elem"]) > 20
+    for k in ("step", "elem", "entry", "exit", "G"):
+        assert np.array_equal(lg[k], lf[k])
+    assert np.array_equal(g.field(0)[0], f.field(0)[0])
+
+
+def test_front_pick_checkpoint(gpu):
+    cfg = dict(W.small_cases()["fragment97x45"], front_radius=3e-3)
+    a = gpu.from_config(cfg)
+    a.step(100)
+    ck = a.checkpoint()
+    a.step(150)
+    b = gpu.from_config(cfg)
+    b.restore(ck)
+    b.step(150)
+    la, lb = a.crack_set(), b.crack_set()
+    for k in ("step", "elem", "entry", "exit", "G"):
+        assert np.array_equal(la[k], lb[k])
+    assert np.array_equal(a.field(0)[1], b.field(0)[1])
+
+
+def test_front_pick_errors(gpu):
+    cfg = W.config1()
+    m = gpu.Model()
+    m.set_mesh_grid(cfg["nx"], cfg["ny"], cfg["X"], cfg["Y"])
+    with pytest.raises(gpu.MctError):
+        m.set_front_pick(-1.0)
+    with pytest.raises(gpu.MctError, match="single-tip"):
+        gpu.from_config(dict(cfg, front_radius=1e-3, tracking=("sct", -1, 0)))
+    with pytest.raises(gpu.MctError, match="single-tip"):
+        gpu.from_config(dict(W.tri_small_cases()["tri_plate40x16"], front_radius=1e-3, tracking=("sct", -1, 0)))
+    b = gpu.Model(n_specimens=2)
+    b.set_mesh_grid(cfg["nx"], cfg["ny"], cfg["X"], cfg["Y"])
+    with pytest.raises(gpu.MctError):
+        b.set_front_pick(1e-3)
