@@ -116,6 +116,9 @@ typedef struct {
     /* per-front pick (a variant of the Sec. 3 pick): front_r2 = rho^2 > 0
      * enables it; 0 = the global pick */
     double front_r2;
+    /* Q4 edge smoothing: 0 = the point rule (B of element j at the midpoint
+     * of the edge), 1 = sub-cells (the triangle edge + centroid of j) */
+    int subcell;
     /* scratch */
     double *sig;            /* 3 per edge */
     double *eps;            /* 3 per edge: smoothed strain */
@@ -244,6 +247,36 @@ static void elem_grad_at_edge(const orc_model_t *m, int e, int k, double dndx[4]
 /* a1: ES-FEM smoothed strain and stress at every edge                  */
 /* ------------------------------------------------------------------ */
 
+/* Sub-cell of Q4 element e at its local edge k: the triangle (n_k, n_k+1,
+ * c) with c the vertex centroid of e; the displacement at c is the mean of
+ * the four nodal displacements.  Fills the three corner coordinates and
+ * displacements (corner order n_k, n_k+1, c) and returns the area.  This is
+ * the smoothing-domain part of standard edge-based smoothing over triangular
+ * sub-cells (divergence theorem with a linear displacement along the
+ * sub-cell boundary), the alternative to the point rule. */
+static double subcell(const orc_model_t *m, int e, int k, const double *ux_all, const double *uy_all,
+                      double x[3], double y[3], double ux[3], double uy[3]) {
+    double ex[4], ey[4];
+    elem_coords(m, e, ex, ey);
+    int a = m->conn[4 * e + k], b = m->conn[4 * e + ((k + 1) & 3)];
+    x[0] = ex[k];
+    y[0] = ey[k];
+    x[1] = ex[(k + 1) & 3];
+    y[1] = ey[(k + 1) & 3];
+    x[2] = 0.25 * (((ex[0] + ex[1]) + ex[2]) + ex[3]);
+    y[2] = 0.25 * (((ey[0] + ey[1]) + ey[2]) + ey[3]);
+    if (ux_all) {
+        const int *cn = &m->conn[4 * e];
+        ux[0] = ux_all[a];
+        uy[0] = uy_all[a];
+        ux[1] = ux_all[b];
+        uy[1] = uy_all[b];
+        ux[2] = 0.25 * (((ux_all[cn[0]] + ux_all[cn[1]]) + ux_all[cn[2]]) + ux_all[cn[3]]);
+        uy[2] = 0.25 * (((uy_all[cn[0]] + uy_all[cn[1]]) + uy_all[cn[2]]) + uy_all[cn[3]]);
+    }
+    return tri_area(x, y);
+}
+
 static void edge_stresses(orc_model_t *m) {
 #pragma omp parallel for schedule(static)
     for (int s = 0; s < m->ns; ++s) {
@@ -252,6 +285,14 @@ static void edge_stresses(orc_model_t *m) {
         for (int side = 0; side < 2; ++side) {
             int e = m->edge_elem[2 * s + side];
             if (!is_intact(m, e)) continue;
+            if (m->nv == 4 && m->subcell) {
+                double x[3], y[3], ux[3], uy[3], dndx[3], dndy[3];
+                A[cnt] = subcell(m, e, m->edge_loc[2 * s + side], m->ux, m->uy, x, y, ux, uy);
+                tri_grad(x, y, dndx, dndy);
+                strain_from_grad(3, dndx, dndy, ux, uy, q[cnt]);
+                cnt++;
+                continue;
+            }
             double ux[4], uy[4], dndx[4], dndy[4];
             elem_disp(m, e, ux, uy);
             elem_grad_at_edge(m, e, m->edge_loc[2 * s + side], dndx, dndy);
@@ -304,9 +345,50 @@ static void intact_force_tri(const orc_model_t *m, int e, double f[8]) {
     }
 }
 
+/* Q4 element force with sub-cells: each local edge k contributes
+ * A_T B_T^T sigma_k of its sub-cell; the centroid corner's share goes a
+ * quarter to each node.  Per node n and edge k the bracket is
+ * t_a + t_c / 4 (n = k), t_b + t_c / 4 (n = k + 1) or t_c / 4, scaled by
+ * A_T and summed over k = 0..3. */
+static void intact_force_subcell(const orc_model_t *m, int e, double f[8]) {
+    for (int k = 0; k < 4; ++k) {
+        double x[3], y[3], b[3], c[3];
+        double AT = subcell(m, e, k, NULL, NULL, x, y, NULL, NULL);
+        tri_grad(x, y, b, c);
+        const double *sg = &m->sig[3 * m->elem_edge[4 * e + k]];
+        double tx[3], ty[3];
+        for (int i = 0; i < 3; ++i) {
+            tx[i] = fma(c[i], sg[2], b[i] * sg[0]);
+            ty[i] = fma(b[i], sg[2], c[i] * sg[1]);
+        }
+        for (int n = 0; n < 4; ++n) {
+            double gx = 0.25 * tx[2], gy = 0.25 * ty[2];
+            if (n == k) {
+                gx = tx[0] + 0.25 * tx[2];
+                gy = ty[0] + 0.25 * ty[2];
+            } else if (n == ((k + 1) & 3)) {
+                gx = tx[1] + 0.25 * tx[2];
+                gy = ty[1] + 0.25 * ty[2];
+            }
+            double vx = AT * gx, vy = AT * gy;
+            if (k == 0) {
+                f[2 * n] = vx;
+                f[2 * n + 1] = vy;
+            } else {
+                f[2 * n] = f[2 * n] + vx;
+                f[2 * n + 1] = f[2 * n + 1] + vy;
+            }
+        }
+    }
+}
+
 static void intact_force(const orc_model_t *m, int e, double f[8]) {
     if (m->nv == 3) {
         intact_force_tri(m, e, f);
+        return;
+    }
+    if (m->subcell) {
+        intact_force_subcell(m, e, f);
         return;
     }
     double x[4], y[4];
@@ -1082,6 +1164,13 @@ int orc_set_tracking(orc_model_t *m, int mode, int elem, int edge) {
 
 int orc_get_tip(const orc_model_t *m) { return m->tip; }
 
+/* Q4 edge smoothing: 0 the point rule (default), 1 sub-cells. */
+int orc_set_smoothing(orc_model_t *m, int mode) {
+    if (mode != 0 && mode != 1) return ORC_EINVAL;
+    m->subcell = mode;
+    return ORC_OK;
+}
+
 /* Per-front pick with competition radius rho (> 0; infinity = the global
  * pick); rho = 0 restores the global pick.  Not with single-tip tracking. */
 int orc_set_front_pick(orc_model_t *m, double rho) {
@@ -1253,7 +1342,13 @@ void orc_energies(orc_model_t *m, double out[4]) {
         double As = 0.0;
         for (int side = 0; side < 2; ++side) {
             int e = m->edge_elem[2 * s + side];
-            if (is_intact(m, e)) As += m->area[e] / (double)m->nv;
+            if (!is_intact(m, e)) continue;
+            if (m->nv == 4 && m->subcell) {
+                double x[3], y[3];
+                As += subcell(m, e, m->edge_loc[2 * s + side], NULL, NULL, x, y, NULL, NULL);
+            } else {
+                As += m->area[e] / (double)m->nv;
+            }
         }
         const double *sg = &m->sig[3 * s], *ep = &m->eps[3 * s];
         estr += 0.5 * As * (sg[0] * ep[0] + sg[1] * ep[1] + sg[2] * ep[2]);

@@ -68,6 +68,7 @@ def lib():
         _lib.orc_mct_pick.argtypes = [C.c_int, dp, ip, ip, C.c_double]
         _lib.orc_set_tracking.argtypes = [P, C.c_int, C.c_int, C.c_int]
         _lib.orc_set_front_pick.argtypes = [P, C.c_double]
+        _lib.orc_set_smoothing.argtypes = [P, C.c_int]
         _lib.orc_front_pick.argtypes = [C.c_int, dp, ip, ip, dp, dp, C.c_double, C.c_double, ip]
         _lib.orc_get_tip.argtypes = [P]
         _lib.orc_get_tip.restype = C.c_int
@@ -164,6 +165,8 @@ class Oracle:
             self._check(L.orc_set_tracking(self.h, 1 if trk[0] == "sct" else 0, int(trk[1]), int(trk[2])))
         if cfg.get("front_radius"):  # per-front pick with this competition radius (m)
             self._check(L.orc_set_front_pick(self.h, float(cfg["front_radius"])))
+        if cfg.get("smoothing") == "subcell":  # Q4 edge smoothing over triangular sub-cells
+            self._check(L.orc_set_smoothing(self.h, 1))
         if finalize:
             self._check(L.orc_finalize(self.h))
 
