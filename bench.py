@@ -144,6 +144,10 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="plate400", choices=sorted(WORKLOADS))
+    ap.add_argument("--smoothing", default="point", choices=("point", "subcell"),
+                    help="Q4 edge smoothing (plain Q4 workloads)")
+    ap.add_argument("--front-radius", type=float, default=0.0,
+                    help="per-front pick with this competition radius in m (plain workloads; 0: global pick)")
     ap.add_argument("--compare-plain", action="store_true",
                     help="batch256: also run each specimen alone and compare")
     ap.add_argument("--kernel-hash", action="store_true",
@@ -192,6 +196,10 @@ def main():
     else:
         cfgs = [{"plate400": W.config2, "fragment2000": W.config3, "tri320k": W.tri_plate320k,
                  "cylinder53k": lambda: W.tri_cylinder(steps=2000, name="cylinder53k")}[args.workload]()]
+        if args.smoothing != "point":
+            cfgs[0]["smoothing"] = args.smoothing
+        if args.front_radius > 0:
+            cfgs[0]["front_radius"] = args.front_radius
         m = mct2d.from_config(cfgs[0], stream=stream.cuda_stream, tile=args.tile,
                               use_graph=not args.no_graph)
     steps = args.steps if args.steps is not None else cfgs[0]["steps"]
@@ -231,6 +239,7 @@ def main():
         "config": {"workload": WORKLOADS[args.workload], "specimens": len(cfgs), "elements": ne,
                    "time_steps": steps, "tile": launch["tile"], "order": launch["order"],
                    "workgroups": launch["workgroups"], "graph": not args.no_graph,
+                   "smoothing": args.smoothing, "front_radius": args.front_radius,
                    "autotuned": tune is not None},
         "wall_s": wall,
         "splits": splits,

@@ -187,6 +187,21 @@ int mct_set_tracking(mct_ctx *ctx, int mode, int32_t tip_elem, int tip_edge);
  * finalize together with single-tip tracking. */
 int mct_set_front_pick(mct_ctx *ctx, double rho);
 
+/* Edge smoothing of Q4 elements.  MCT_SMOOTH_POINT (default): B of a
+ * neighbouring element evaluated at the midpoint of the edge in its natural
+ * coordinates, weights A_j / (A_lo + A_hi) (Eq. QUAD_strain_discretization
+ * with Eq. disp_ES_FEM; the paper leaves the evaluation point open).
+ * MCT_SMOOTH_SUBCELL: the edge's smoothing domain is the union of the
+ * triangles (edge, vertex centroid of each intact neighbour), the
+ * displacement at a centroid the mean of the element's nodal displacements,
+ * weights and element forces from those triangles' areas and gradients --
+ * edge-based smoothing over triangular sub-cells, which passes the patch
+ * test on any quadrilateral mesh (the point rule only on parallelograms,
+ * where the two coincide).  Plain Q4 contexts; MCT_EUNSUPPORTED on a batch,
+ * with the split-screen, or for a CST mesh (whose smoothing is exact). */
+enum { MCT_SMOOTH_POINT = 0, MCT_SMOOTH_SUBCELL = 1 };
+int mct_set_smoothing(mct_ctx *ctx, int mode);
+
 /* Time step: dt > 0 is used as given; otherwise dt = cfl_fraction *
  * (shortest edge) / c_d with c_d = sqrt(E / (rho (1 - nu^2))). */
 int mct_set_time(mct_ctx *ctx, double dt, double cfl_fraction);

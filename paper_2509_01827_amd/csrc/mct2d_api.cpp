@@ -59,6 +59,7 @@ struct Spec {
     int32_t sct_elem = -1;   // start tip (element, local edge); -1: the pre-notch's path end
     int sct_edge = 0;
     double front_rho = 0;    // per-front pick radius (0: the global pick)
+    int subcell = 0;         // Q4 edge smoothing over triangular sub-cells
     // derived
     double dt = 0;
     double dt_limit = 0;  // 2 / omega_max of the set-up mesh (power iteration)
@@ -908,6 +909,23 @@ int mct_set_front_pick(mct_ctx *c, double rho) {
     return MCT_OK;
 }
 
+int mct_set_smoothing(mct_ctx *c, int mode) {
+    if (!c) return MCT_EINVAL;
+    if (mode != MCT_SMOOTH_POINT && mode != MCT_SMOOTH_SUBCELL) return fail(c, MCT_EINVAL, "unknown smoothing %d", mode);
+    if (c->tri) {
+        if (mode == MCT_SMOOTH_SUBCELL)
+            return fail(c, MCT_EUNSUPPORTED, "sub-cell smoothing is for Q4 grids (CST smoothing is exact)");
+        return MCT_OK;
+    }
+    if (c->batch && mode == MCT_SMOOTH_SUBCELL)
+        return fail(c, MCT_EUNSUPPORTED, "sub-cell smoothing needs a plain context");
+    Spec &s = cur(c);
+    if (!s.nx) return fail(c, MCT_ESTATE, "set the mesh first");
+    s.subcell = mode == MCT_SMOOTH_SUBCELL;
+    c->finalized = false;
+    return MCT_OK;
+}
+
 int mct_set_time(mct_ctx *c, double dt, double cfl_fraction) {
     if (!c) return MCT_EINVAL;
     TRI_FWD(c, set_time, dt, cfl_fraction);
@@ -1123,6 +1141,7 @@ int mct_finalize(mct_ctx *c) {
         p.curve_phi = p.ncurve ? c->dcurve + ncv + s.curve_off : nullptr;
         p.ctl = c->dctl + q;
         p.log = c->dlog + s.elem_off;
+        p.subcell = s.subcell;
         p.front = front ? 1 : 0;
         p.fcap = front ? (int32_t)(4 * s.ne) : 0;
         p.front_r2 = front ? s.front_rho * s.front_rho : 0.0;
@@ -1633,6 +1652,7 @@ int mct_screen_enable(mct_ctx *c, const mct_mlp *mlp, float tau, int period) {
     TRI_UNSUPPORTED(c, "the split-screen");
     if (!mlp) return fail(c, MCT_EINVAL, "null model");
     if (!c->batch && cur(c).front_rho > 0) return fail(c, MCT_EUNSUPPORTED, "the split-screen with the per-front pick");
+    if (!c->batch && cur(c).subcell) return fail(c, MCT_EUNSUPPORTED, "the split-screen with sub-cell smoothing");
     if (period < 2) return fail(c, MCT_EINVAL, "period must be at least 2");
     int rc = ensure_screen(c);
     if (rc) return rc;

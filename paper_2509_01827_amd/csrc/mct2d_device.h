@@ -81,6 +81,92 @@ __device__ __forceinline__ void q4_grad_rt(const double x[4], const double y[4],
     }
 }
 
+// Sub-cell of a Q4 element at its local edge k: the triangle (n_k, n_k+1,
+// c), c the vertex centroid; the displacement at c is the mean of the four
+// nodal displacements.  Gradients b (d/dx), c (d/dy) of the triangle's
+// linear shape functions in corner order (n_k, n_k+1, c), the strain of
+// its corner displacements, and its area (returned).
+template <int K>
+__device__ __forceinline__ double subcell(const double x[4], const double y[4], const double ux[4],
+                                          const double uy[4], double b[3], double c[3], double q[3]) {
+    constexpr int K1 = (K + 1) & 3;
+    const double xa = x[K], ya = y[K], xb = x[K1], yb = y[K1];
+    const double xc = 0.25 * (((x[0] + x[1]) + x[2]) + x[3]);
+    const double yc = 0.25 * (((y[0] + y[1]) + y[2]) + y[3]);
+    const double twoA = (xb - xa) * (yc - ya) - (xc - xa) * (yb - ya);
+    const double inv = 1.0 / twoA;
+    b[0] = (yb - yc) * inv;
+    b[1] = (yc - ya) * inv;
+    b[2] = (ya - yb) * inv;
+    c[0] = (xc - xb) * inv;
+    c[1] = (xa - xc) * inv;
+    c[2] = (xb - xa) * inv;
+    if (ux) {
+        const double pu[3] = {ux[K], ux[K1], 0.25 * (((ux[0] + ux[1]) + ux[2]) + ux[3])};
+        const double pv[3] = {uy[K], uy[K1], 0.25 * (((uy[0] + uy[1]) + uy[2]) + uy[3])};
+        double exx = 0.0, eyy = 0.0, gxy = 0.0;
+#pragma unroll
+        for (int n = 0; n < 3; ++n) {
+            exx = fma(b[n], pu[n], exx);
+            eyy = fma(c[n], pv[n], eyy);
+            gxy = fma(c[n], pu[n], gxy);
+            gxy = fma(b[n], pv[n], gxy);
+        }
+        q[0] = exx;
+        q[1] = eyy;
+        q[2] = gxy;
+    }
+    return 0.5 * twoA;
+}
+
+// subcell with the edge index at run time
+__device__ __forceinline__ double subcell_rt(const double x[4], const double y[4], const double ux[4],
+                                             const double uy[4], int k, double b[3], double c[3], double q[3]) {
+    switch (k) {
+        case 0: return subcell<0>(x, y, ux, uy, b, c, q);
+        case 1: return subcell<1>(x, y, ux, uy, b, c, q);
+        case 2: return subcell<2>(x, y, ux, uy, b, c, q);
+        default: return subcell<3>(x, y, ux, uy, b, c, q);
+    }
+}
+
+// Force of an intact Q4 element with sub-cell smoothing: sum over its edges
+// k of A_T B_T^T sigma_k, the centroid corner's share a quarter to each
+// node; per node and edge the bracket t_a + t_c/4 (node k), t_b + t_c/4
+// (node k+1) or t_c/4, scaled by A_T, summed over k = 0..3 in order.
+__device__ __forceinline__ void subcell_force(const double bb[4][3], const double cb[4][3], const double AT[4],
+                                              const double sig[4][3], double fe[8]) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double s0 = sig[k][0], s1 = sig[k][1], s2 = sig[k][2];
+        double tx[3], ty[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            tx[i] = fma(cb[k][i], s2, bb[k][i] * s0);
+            ty[i] = fma(bb[k][i], s2, cb[k][i] * s1);
+        }
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            double gx = 0.25 * tx[2], gy = 0.25 * ty[2];
+            if (n == k) {
+                gx = tx[0] + 0.25 * tx[2];
+                gy = ty[0] + 0.25 * ty[2];
+            } else if (n == ((k + 1) & 3)) {
+                gx = tx[1] + 0.25 * tx[2];
+                gy = ty[1] + 0.25 * ty[2];
+            }
+            const double vx = AT[k] * gx, vy = AT[k] * gy;
+            if (k == 0) {
+                fe[2 * n] = vx;
+                fe[2 * n + 1] = vy;
+            } else {
+                fe[2 * n] = fe[2 * n] + vx;
+                fe[2 * n + 1] = fe[2 * n + 1] + vy;
+            }
+        }
+    }
+}
+
 template <int NN>
 __device__ __forceinline__ void strain(const double *dndx, const double *dndy, const double *ux,
                                        const double *uy, double eps[3]) {

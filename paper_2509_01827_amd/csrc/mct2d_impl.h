@@ -77,6 +77,9 @@ struct StepParams {
     Control *ctl;
     Slot *slots;        // 3 sets of nwg slots
     LogRec *log;
+    // Q4 edge smoothing: 0 the point rule, 1 triangular sub-cells (plain models)
+    int32_t subcell;
+    int32_t pad_sc;
     // per-front pick (plain models): every accepted candidate of a step is
     // appended to fcand and a separate kernel picks; front_r2 = rho^2
     int32_t front;

@@ -51,10 +51,17 @@ __global__ __launch_bounds__(kB) void k_eval_edges(StepParams p, const double *u
             u[n] = ux[nd[n]];
             v[n] = uy[nd[n]];
         }
-        q4_grad_rt(x, y, k, gx, gy);
-        strain<4>(gx, gy, u, v, q[cnt]);
-        A[cnt] = p.area[e];
-        As += p.area[e] / 4.0;
+        if (p.subcell) {
+            // sub-cell smoothing: the sub-cell's strain and area
+            double b3[3], c3[3];
+            A[cnt] = subcell_rt(x, y, u, v, k, b3, c3, q[cnt]);
+            As += A[cnt];
+        } else {
+            q4_grad_rt(x, y, k, gx, gy);
+            strain<4>(gx, gy, u, v, q[cnt]);
+            A[cnt] = p.area[e];
+            As += p.area[e] / 4.0;
+        }
         ++cnt;
     }
     double *sg = d.sig + 3 * s;
@@ -161,7 +168,20 @@ __global__ __launch_bounds__(kB) void k_eval_elements(StepParams p, const double
     }
     double f[8];
     const uint8_t code = p.split[e];
-    if (code == 0) {
+    if (code == 0 && p.subcell) {
+        const int64_t i = e % p.nx, j = e / p.nx;
+        const int64_t sid[4] = {edge_h(i, j, p.nx, p.ny), edge_v(i + 1, j, p.nx), edge_h(i, j + 1, p.nx, p.ny),
+                                edge_v(i, j, p.nx)};
+        double bb[4][3], cb[4][3], at[4], sg[4][3];
+        at[0] = subcell<0>(x, y, nullptr, nullptr, bb[0], cb[0], nullptr);
+        at[1] = subcell<1>(x, y, nullptr, nullptr, bb[1], cb[1], nullptr);
+        at[2] = subcell<2>(x, y, nullptr, nullptr, bb[2], cb[2], nullptr);
+        at[3] = subcell<3>(x, y, nullptr, nullptr, bb[3], cb[3], nullptr);
+        for (int k = 0; k < 4; ++k)
+            for (int c = 0; c < 3; ++c) sg[k][c] = d.sig[3 * sid[k] + c];
+        subcell_force(bb, cb, at, sg, f);
+        d.pe[e] = 0.0;
+    } else if (code == 0) {
         const int64_t i = e % p.nx, j = e / p.nx;
         const int64_t sid[4] = {edge_h(i, j, p.nx, p.ny), edge_v(i + 1, j, p.nx), edge_h(i, j + 1, p.nx, p.ny),
                                 edge_v(i, j, p.nx)};

@@ -193,7 +193,7 @@ __device__ __forceinline__ int32_t tip_after(const StepParams &p, const Cand &g)
 // unit b = (specimen, tile) comes from `units` and the specimen's view (its
 // sizes, constants and pre-offset pointers) from `views`.  Otherwise the one
 // view `p0` is passed by value and workgroups map to tiles XCD-banded.
-template <int TXE, int TYE, bool BATCHED>
+template <int TXE, int TYE, bool BATCHED, bool SC = false>
 __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepParams *views, const int2 *units,
                                                    int k_rel, int par0) {
     constexpr int NT = TXE * TYE;
@@ -206,7 +206,9 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
     static_assert(TX * TY <= NT, "one thread per owned node");
 
     constexpr int NS = NH + NV;  // component stride of the per-edge array
-    constexpr int NQ = (3 * NS > 8 * NT) ? 3 * NS : 8 * NT;
+    // SC (sub-cell smoothing): a fourth component holds the lower-id side's
+    // sub-cell area
+    constexpr int NQ = ((SC ? 4 : 3) * NS > 8 * NT) ? (SC ? 4 : 3) * NS : 8 * NT;
     __shared__ double s_ux[HX * HY], s_uy[HX * HY], s_X[HX * HY], s_Y[HX * HY];
     // per edge and component (stride NS): first the strain part of the
     // lower-id element, then the smoothed stress; after the force phase the
@@ -395,10 +397,14 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
     sidx[3] = NH + je * (TXE + 1) + ie;
     const uint8_t code = s_split[e2];
     auto nbr = [&](int e, int k) { return (k == 0) ? e - EX : (k == 1) ? e + 1 : (k == 2) ? e + EX : e - 1; };
-    // stage A, lower-id element e (area A) at its edge k = 1 or 2
+    // stage A, lower-id element e (area A; SC: sub-cell area) at its edge k = 1 or 2
     auto lo_part = [&](int e, double A, int k, int sid, const double q[3]) {
         const int nb = nbr(e, k);
-        if (s_split[nb] == 0) {
+        if constexpr (SC) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) s_e[c * NS + sid] = q[c];
+            s_e[3 * NS + sid] = A;
+        } else if (s_split[nb] == 0) {
             const double w0 = A / (A + s_area[nb]);
 #pragma unroll
             for (int c = 0; c < 3; ++c) s_e[c * NS + sid] = w0 * q[c];
@@ -407,14 +413,22 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
             for (int c = 0; c < 3; ++c) s_e[c * NS + sid] = q[c];
         }
     };
-    // stage B, intact higher-id element e (area A) at its edge k = 0 or 3
+    // stage B, intact higher-id element e (area A; SC: sub-cell area) at its edge k = 0 or 3
     auto hi_sigma = [&](int e, double A, int k, int sid, const double q[3]) {
         const int nb = nbr(e, k);
         double eps[3], sg[3];
         if (s_split[nb] == 0) {
-            const double w1 = A / (s_area[nb] + A);
+            if constexpr (SC) {
+                const double Alo = s_e[3 * NS + sid];
+                const double sum = Alo + A;
+                const double w0 = Alo / sum, w1 = A / sum;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) eps[c] = fma(w1, q[c], s_e[c * NS + sid]);
+                for (int c = 0; c < 3; ++c) eps[c] = fma(w1, q[c], w0 * s_e[c * NS + sid]);
+            } else {
+                const double w1 = A / (s_area[nb] + A);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) eps[c] = fma(w1, q[c], s_e[c * NS + sid]);
+            }
         } else {
 #pragma unroll
             for (int c = 0; c < 3; ++c) eps[c] = q[c];
@@ -434,7 +448,9 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
             for (int c = 0; c < 3; ++c) s_e[c * NS + sid] = sg[c];
         }
     };
-    double gx[4][4], gy[4][4];
+    // point rule: Q4 gradients at the edge midpoints; SC: sub-cell
+    // gradients (gx[k][0..2], gy[k][0..2]) and areas at[k]
+    double gx[4][4], gy[4][4], at[4];
     double qh0[3], qh3[3];
     const double my_area = s_area[e2];
     if (code == 0) {
@@ -444,15 +460,24 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
         elem_u(ex, ey, ux, uy);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            q4_grad(x, y, k, gx[k], gy[k]);
             double q[3];
-            strain<4>(gx[k], gy[k], ux, uy, q);
+            if constexpr (SC) {
+                switch (k) {
+                    case 0: at[0] = subcell<0>(x, y, ux, uy, gx[0], gy[0], q); break;
+                    case 1: at[1] = subcell<1>(x, y, ux, uy, gx[1], gy[1], q); break;
+                    case 2: at[2] = subcell<2>(x, y, ux, uy, gx[2], gy[2], q); break;
+                    default: at[3] = subcell<3>(x, y, ux, uy, gx[3], gy[3], q); break;
+                }
+            } else {
+                q4_grad(x, y, k, gx[k], gy[k]);
+                strain<4>(gx[k], gy[k], ux, uy, q);
+            }
             if (k == 0) {
                 qh0[0] = q[0]; qh0[1] = q[1]; qh0[2] = q[2];
             } else if (k == 3) {
                 qh3[0] = q[0]; qh3[1] = q[1]; qh3[2] = q[2];
             } else {
-                lo_part(e2, my_area, k, sidx[k], q);
+                lo_part(e2, SC ? at[k] : my_area, k, sidx[k], q);
             }
         }
     }
@@ -465,6 +490,7 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
     int ore = 0, ork = 0, osid = 0;
     bool oin = false;
     double oq[3] = {0.0, 0.0, 0.0};
+    double oat = 0.0;  // SC: the outer element's sub-cell area at the shared edge
     if (og < 4 && orr < ((og < 2) ? TXE : TYE)) {
         int rex, rey;
         if (og == 0) {  // below the ring: its top edge
@@ -482,19 +508,23 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
             double x[4], y[4], ux[4], uy[4], dx[4], dy[4];
             elem_xy(rex, rey, x, y);
             elem_u(rex, rey, ux, uy);
-            q4_grad_rt(x, y, ork, dx, dy);
-            strain<4>(dx, dy, ux, uy, oq);
-            if (og == 0 || og == 2) lo_part(ore, s_area[ore], ork, osid, oq);
+            if constexpr (SC) {
+                oat = subcell_rt(x, y, ux, uy, ork, dx, dy, oq);
+            } else {
+                q4_grad_rt(x, y, ork, dx, dy);
+                strain<4>(dx, dy, ux, uy, oq);
+            }
+            if (og == 0 || og == 2) lo_part(ore, SC ? oat : s_area[ore], ork, osid, oq);
         }
     }
     __syncthreads();
     if (code == 0) {
-        hi_sigma(e2, my_area, 0, sidx[0], qh0);
-        hi_sigma(e2, my_area, 3, sidx[3], qh3);
+        hi_sigma(e2, SC ? at[0] : my_area, 0, sidx[0], qh0);
+        hi_sigma(e2, SC ? at[3] : my_area, 3, sidx[3], qh3);
         lo_sigma(e2, 1, sidx[1]);
         lo_sigma(e2, 2, sidx[2]);
     }
-    if (oin && (og == 1 || og == 3)) hi_sigma(ore, s_area[ore], ork, osid, oq);
+    if (oin && (og == 1 || og == 3)) hi_sigma(ore, SC ? oat : s_area[ore], ork, osid, oq);
     __syncthreads();
 
     // owned-node data for the update, loaded here so that the registers are
@@ -525,7 +555,19 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
     double fe[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) fe[c] = 0.0;
-    if (code == 0) {
+    if (SC && code == 0) {
+        double bb[4][3], cb[4][3], sgk[4][3];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            edge_sigma(sidx[k], sgk[k]);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                bb[k][i] = gx[k][i];
+                cb[k][i] = gy[k][i];
+            }
+        }
+        subcell_force(bb, cb, at, sgk, fe);
+    } else if (code == 0) {
         double sx[4], sy[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -919,9 +961,24 @@ hipError_t launch_step(int tile, const Launch &L, int k_rel, int par0, hipStream
         }
     } else {
         switch (tile) {
-            case 1: k_step<16, 16, false><<<p.nwg, 256, 0, s>>>(p, nullptr, nullptr, k_rel, par0); break;
-            case 2: k_step<32, 8, false><<<p.nwg, 256, 0, s>>>(p, nullptr, nullptr, k_rel, par0); break;
-            default: k_step<32, 16, false><<<p.nwg, 512, 0, s>>>(p, nullptr, nullptr, k_rel, par0); break;
+            case 1:
+                if (p.subcell)
+                    k_step<16, 16, false, true><<<p.nwg, 256, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
+                else
+                    k_step<16, 16, false><<<p.nwg, 256, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
+                break;
+            case 2:
+                if (p.subcell)
+                    k_step<32, 8, false, true><<<p.nwg, 256, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
+                else
+                    k_step<32, 8, false><<<p.nwg, 256, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
+                break;
+            default:
+                if (p.subcell)
+                    k_step<32, 16, false, true><<<p.nwg, 512, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
+                else
+                    k_step<32, 16, false><<<p.nwg, 512, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
+                break;
         }
         if (p.front) k_front<<<1, kFrontThreads, 0, s>>>(p, k_rel);
     }

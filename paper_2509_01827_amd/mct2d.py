@@ -47,6 +47,7 @@ EXPORTS = [
     "mct_mlp_create", "mct_mlp_destroy", "mct_mlp_last_error", "mct_mlp_set_params", "mct_mlp_get_params",
     "mct_mlp_forward", "mct_mlp_gradient", "mct_mlp_train_step", "mct_get_energies", "mct_set_tracking",
     "mct_set_load_curve", "mct_set_mesh_tri", "mct_set_front_pick",
+    "mct_set_smoothing",
 ]
 N_FEATURES = 10
 N_PARAMS = 4929
@@ -93,6 +94,7 @@ def load() -> C.CDLL:
     L.mct_set_tracking.argtypes = [P, C.c_int, C.c_int32, C.c_int]
     L.mct_set_load_curve.argtypes = [P, C.c_int64, dp, dp]
     L.mct_set_front_pick.argtypes = [P, C.c_double]
+    L.mct_set_smoothing.argtypes = [P, C.c_int]
     L.mct_finalize.argtypes = [P]
     L.mct_step.argtypes = [P, C.c_int64]
     L.mct_sync.argtypes = [P]
@@ -217,6 +219,11 @@ class Model:
     def set_load_curve(self, t, phi):
         t, phi = _f64(t), _f64(phi)
         self._check(self._L.mct_set_load_curve(self._h, len(t), t, phi), "set_load_curve")
+
+    def set_smoothing(self, mode="point"):
+        """Q4 edge smoothing: "point" (default) or "subcell"."""
+        m = {"point": 0, "subcell": 1}[mode]
+        self._check(self._L.mct_set_smoothing(self._h, m), "set_smoothing")
 
     def set_front_pick(self, rho):
         """Per-front pick with competition radius rho (m); 0 = the global pick."""
@@ -443,6 +450,8 @@ def _setup(m: Model, cfg: dict):
         m.set_load_curve(lc[0], lc[1])
     if cfg.get("front_radius"):
         m.set_front_pick(cfg["front_radius"])
+    if cfg.get("smoothing"):
+        m.set_smoothing(cfg["smoothing"])
 
 
 def from_config(cfg: dict, stream: int | None = None, tile: int = 0, use_graph: bool = True) -> Model:
