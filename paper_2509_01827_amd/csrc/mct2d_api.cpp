@@ -99,8 +99,8 @@ struct mct_ctx {
     uint32_t *dfcount = nullptr;
     double2 *dfmid = nullptr;
     double *dflen = nullptr;
-    int32_t *dforder = nullptr;
-    uint8_t *dfpicked = nullptr;
+    int32_t *dforder = nullptr, *dfbucket = nullptr, *dfsorted = nullptr, *dfplist = nullptr;
+    double front_cell = 0.0;
     StepParams *dviews = nullptr;
     int2 *dunits = nullptr;
     int nunits = 0;
@@ -260,7 +260,9 @@ void release_device(mct_ctx *c) {
     dfree(c->dfmid);
     dfree(c->dflen);
     dfree(c->dforder);
-    dfree(c->dfpicked);
+    dfree(c->dfbucket);
+    dfree(c->dfsorted);
+    dfree(c->dfplist);
     dfree(c->dviews);
     dfree(c->dunits);
     dfree(c->dtip_counts);
@@ -1099,7 +1101,22 @@ int mct_finalize(mct_ctx *c) {
         HIP_TRY(c, hipMalloc((void **)&c->dfmid, sizeof(double2) * cap));
         HIP_TRY(c, hipMalloc((void **)&c->dflen, sizeof(double) * cap));
         HIP_TRY(c, hipMalloc((void **)&c->dforder, sizeof(int32_t) * cap));
-        HIP_TRY(c, hipMalloc((void **)&c->dfpicked, cap));
+        HIP_TRY(c, hipMalloc((void **)&c->dfbucket, sizeof(int32_t) * cap));
+        HIP_TRY(c, hipMalloc((void **)&c->dfsorted, sizeof(int32_t) * cap));
+        HIP_TRY(c, hipMalloc((void **)&c->dfplist, sizeof(int32_t) * cap));
+        // hash cell: at least rho and the largest distance between two nodes
+        // of an element (so same-element candidates are neighbours too)
+        const Spec &s0 = c->specs[0];
+        double dmax = 0.0;
+        for (int j = 0; j < s0.ny; ++j)
+            for (int i = 0; i < s0.nx; ++i) {
+                const int64_t nd[4] = {node_of(s0, i, j), node_of(s0, i + 1, j), node_of(s0, i + 1, j + 1),
+                                       node_of(s0, i, j + 1)};
+                for (int a = 0; a < 4; ++a)
+                    for (int b = a + 1; b < 4; ++b)
+                        dmax = std::max(dmax, std::hypot(s0.X[nd[a]] - s0.X[nd[b]], s0.Y[nd[a]] - s0.Y[nd[b]]));
+            }
+        c->front_cell = std::max(s0.front_rho, dmax) * (1.0 + 1e-9);
     }
     int64_t max_ns = 0;
     for (const Spec &s : c->specs) max_ns = std::max(max_ns, s.ns);
@@ -1150,7 +1167,10 @@ int mct_finalize(mct_ctx *c) {
         p.fmid = c->dfmid;
         p.flen = c->dflen;
         p.forder = c->dforder;
-        p.fpicked = c->dfpicked;
+        p.fbucket = c->dfbucket;
+        p.fsorted = c->dfsorted;
+        p.fplist = c->dfplist;
+        p.fcell = c->front_cell;
     }
     c->finalized = true;  // the launch geometry below needs the device arrays
     rc = set_launch_geometry(c);

@@ -90,7 +90,8 @@ struct StepParams {
     double2 *fmid;
     double *flen;
     int32_t *forder;
-    uint8_t *fpicked;
+    int32_t *fbucket, *fsorted, *fplist;
+    double fcell;  // hash cell of the pick: >= rho and the largest element diameter
 };
 
 // Tile shapes (elements per workgroup in x and y; nodes owned = one less).

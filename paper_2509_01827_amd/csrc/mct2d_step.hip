@@ -931,7 +931,10 @@ __global__ __launch_bounds__(kFrontThreads) void k_front(StepParams p, int k_rel
     v.mid = p.fmid;
     v.len = p.flen;
     v.order = p.forder;
-    v.picked = p.fpicked;
+    v.bucket = p.fbucket;
+    v.sorted = p.fsorted;
+    v.plist = p.fplist;
+    v.cell = p.fcell;
     v.split = p.split;
     v.log = p.log;
     v.log_cap = p.log_cap;

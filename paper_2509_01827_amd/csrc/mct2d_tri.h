@@ -69,7 +69,8 @@ struct Params {
     double2 *fmid;
     double *flen;
     int32_t *forder;
-    uint8_t *fpicked;
+    int32_t *fbucket, *fsorted, *fplist;
+    double fcell;  // hash cell of the pick: >= rho and the largest element diameter
 };
 
 // Evaluation outputs of the query kernels (nullptr = skip).

@@ -192,7 +192,9 @@ void release(Model &m) {
     dfree(m.dfmid);
     dfree(m.dflen);
     dfree(m.dforder);
-    dfree(m.dfpicked);
+    dfree(m.dfbucket);
+    dfree(m.dfsorted);
+    dfree(m.dfplist);
     dfree(m.dlog);
     dfree(m.dctl);
     dfree(m.ev.sig_ek);
@@ -569,7 +571,9 @@ int finalize(Model &m, Host h) {
         TRY(h, hipMalloc((void **)&m.dfmid, sizeof(double2) * 3 * ne));
         TRY(h, hipMalloc((void **)&m.dflen, sizeof(double) * 3 * ne));
         TRY(h, hipMalloc((void **)&m.dforder, sizeof(int32_t) * 3 * ne));
-        TRY(h, hipMalloc((void **)&m.dfpicked, 3 * ne));
+        TRY(h, hipMalloc((void **)&m.dfbucket, sizeof(int32_t) * 3 * ne));
+        TRY(h, hipMalloc((void **)&m.dfsorted, sizeof(int32_t) * 3 * ne));
+        TRY(h, hipMalloc((void **)&m.dfplist, sizeof(int32_t) * 3 * ne));
     }
     TRY(h, hipMalloc((void **)&m.dlog, sizeof(LogRec) * ne));
     TRY(h, hipMalloc((void **)&m.dctl, sizeof(Ctl)));
@@ -640,7 +644,19 @@ int finalize(Model &m, Host h) {
     p.fmid = m.dfmid;
     p.flen = m.dflen;
     p.forder = m.dforder;
-    p.fpicked = m.dfpicked;
+    p.fbucket = m.dfbucket;
+    p.fsorted = m.dfsorted;
+    p.fplist = m.dfplist;
+    {
+        // hash cell: at least rho and the longest edge (the largest distance
+        // between two nodes of a triangle)
+        double dmax = 0.0;
+        for (int64_t s = 0; s < ns; ++s) {
+            const int32_t a = m.edge_node[2 * s], b = m.edge_node[2 * s + 1];
+            dmax = std::max(dmax, std::hypot(m.X[b] - m.X[a], m.Y[b] - m.Y[a]));
+        }
+        p.fcell = std::max(m.front_rho, dmax) * (1.0 + 1e-9);
+    }
     TRY(h, hipStreamSynchronize(h.stream));
     if ((rc = stability_limit(m, h))) return rc;
     if (m.dt > m.dt_limit)

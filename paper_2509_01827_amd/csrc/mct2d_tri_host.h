@@ -58,8 +58,7 @@ struct Model {
     Cand *dcand = nullptr;
     double2 *dfmid = nullptr;
     double *dflen = nullptr;
-    int32_t *dforder = nullptr;
-    uint8_t *dfpicked = nullptr;
+    int32_t *dforder = nullptr, *dfbucket = nullptr, *dfsorted = nullptr, *dfplist = nullptr;
     LogRec *dlog = nullptr;
     Ctl *dctl = nullptr;
     // query buffers (allocated on first use)
