@@ -118,7 +118,7 @@ int mct_set_mesh_grid(mct_ctx *ctx, int32_t nx, int32_t ny, const double *X, con
  * space-filling curve) is the caller's choice and pays in cache reuse.
  * After this call the context runs the CST path: every set-up call, step
  * and query below applies to the triangle mesh, except the tile shapes
- * (mct_set_launch accepts tile 0 only), mct_autotune, mct_get_path_geometry
+ * (mct_set_launch selects the step kernels instead), mct_autotune, mct_get_path_geometry
  * and the split-screen (MCT_EUNSUPPORTED).  Velocity conditions may be
  * prescribed at any node.  Errors: MCT_EINVAL for an index out of range, a
  * repeated node, a non-positive area (clockwise or degenerate), an edge
@@ -283,8 +283,15 @@ int mct_restore(mct_ctx *ctx, const void *host_buf, int64_t bytes);
 
 /* Launch tuning: tile shape index (0 = automatic, which is 16x16; 1 = 16x16, 2 = 32x8,
  * 3 = 32x16 elements per workgroup) and whether mct_step replays captured
- * HIP graphs (1, default) or launches kernel by kernel (0).  Results do not
- * depend on either (fixed summation orders). */
+ * HIP graphs (1, default) or launches kernel by kernel (0).  On a triangle
+ * mesh the tile index selects the step kernels: 1 = an element kernel and a
+ * node kernel; 2, 3, 4 = one fused kernel over patches of 64, 128, 256
+ * consecutive nodes (element forces summed in LDS; used when its tables fit:
+ * at most 16 elements at a node and 1024 in a patch, else the split
+ * kernels); 0 = automatic (fused on 64-node patches below 2^18 triangles,
+ * split above).  Results do not depend on any of these choices
+ * (fixed summation orders).  Errors: MCT_EINVAL for a tile index out of
+ * range. */
 int mct_set_launch(mct_ctx *ctx, int tile, int use_graph);
 
 /* Batch of independent specimens (same step, one launch per time step over
@@ -309,7 +316,9 @@ int mct_set_order(mct_ctx *ctx, int order);
  * order and its time per step in microseconds. */
 int mct_autotune(mct_ctx *ctx, int trial_steps, int *tile, int *order, double *us_per_step);
 
-/* Launch shape in use: tile index, unit order, workgroups per step. */
+/* Launch shape in use: tile index, unit order, workgroups per step (on a
+ * triangle mesh: the step kernels in use, 1 split or 2..4 fused, never 0;
+ * the workgroups of the fused kernel or of the element kernel). */
 int mct_get_launch(mct_ctx *ctx, int *tile, int *order, int64_t *workgroups);
 
 /* ------------------------------------------------------------------------

@@ -942,10 +942,10 @@ int mct_set_time(mct_ctx *c, double dt, double cfl_fraction) {
 int mct_set_launch(mct_ctx *c, int tile, int use_graph) {
     if (!c) return MCT_EINVAL;
     if (c->tri) {
-        // one launch shape (a thread per element / node); tile 0 only
-        if (tile != 0) return fail(c, MCT_EINVAL, "a triangle mesh has no tile shapes (tile 0 only)");
+        // tile = step kernels: 0 automatic, 1 split, 2..4 fused on 64..256-node patches
+        if (tile < 0 || tile > 4) return fail(c, MCT_EINVAL, "a triangle mesh takes tile 0..4 (step kernels)");
         c->tri->use_graph = use_graph != 0;
-        return MCT_OK;
+        return mct::tri::set_kernels(*c->tri, mct::tri::Host{c->err, c->stream}, tile);
     }
     if (tile < 0 || tile > mct::kNumTiles) return fail(c, MCT_EINVAL, "tile index out of range");
     c->tile_req = tile;
@@ -1614,9 +1614,12 @@ int mct_autotune(mct_ctx *c, int trial_steps, int *tile_out, int *order_out, dou
 int mct_get_launch(mct_ctx *c, int *tile, int *order, int64_t *workgroups) {
     if (!c) return MCT_EINVAL;
     if (c->tri) {
-        if (tile) *tile = 0;
+        // the kernels in use: 1 split (workgroups of the element kernel),
+        // 2/3/4 fused on 64/128/256-node patches (workgroups = patches)
+        const int P = c->tri->prm.patch_emax > 0 ? c->tri->prm.patch_nodes : 0;
+        if (tile) *tile = P == 64 ? 2 : P == 128 ? 3 : P == 256 ? 4 : 1;
         if (order) *order = 0;
-        if (workgroups) *workgroups = (c->tri->ne + 255) / 256;
+        if (workgroups) *workgroups = P ? (c->tri->nn + P - 1) / P : (c->tri->ne + 255) / 256;
         return MCT_OK;
     }
     if (tile) *tile = c->tile;

@@ -28,6 +28,9 @@ struct Ctl {
 };
 static_assert(sizeof(Ctl) == 40, "Ctl layout");
 
+constexpr int64_t kFusedMaxElems = 1 << 18;  // automatic choice: fused step below this size
+constexpr int32_t kOwned = 1 << 30;    // patch element flag: evaluate its candidates here
+
 // Node flags (one byte per node).
 constexpr uint8_t kFixX = 1, kFixY = 2, kLoaded = 4;
 
@@ -44,7 +47,8 @@ struct Params {
                          // .w: local index of that edge in the neighbour, 2 bits per k
     const int4 *opp;     // per element: the neighbour's node off the shared edge k (-1: none)
     const double2 *xy;   // reference coordinates
-    double2 *u, *v;      // displacement, velocity
+    double2 *u0, *u1;    // displacement u^k in buffer k & 1 (ping-pong: a step reads one, writes the other)
+    double2 *v;          // velocity
     const double *minv;
     const double2 *fext; // read where kLoaded
     const double2 *v0;   // read where kFixX / kFixY
@@ -56,7 +60,15 @@ struct Params {
     const int32_t *csr_ent;  // force slot n * ne + e, by element colour per node
     const int32_t *nlist;    // the same lists padded to nlist_w slots (-1), node-major [nn][w];
     int32_t nlist_w;         //   null when a node touches more than 16 elements (CSR is used)
-    int32_t pad2;
+    // fused step (one workgroup per patch of patch_nodes consecutive nodes):
+    // the patch's elements (id | kOwned for the one patch that evaluates
+    // their candidates) and per owned node its force slots in the patch's LDS
+    // (3 slot + local node, 0xffff = none), node-major, nlist_w per node
+    int32_t patch_emax;      // largest patch element count (0: fused step off)
+    int32_t patch_nodes;     // 64, 128 or 256
+    const int32_t *patch_off;
+    const int32_t *patch_elem;
+    const uint16_t *patch_slots;
     Cand *cand;          // 3 ne
     LogRec *log;
     Ctl *ctl;

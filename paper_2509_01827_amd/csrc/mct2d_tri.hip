@@ -239,11 +239,93 @@ __device__ __forceinline__ double2 piece_force_at(const Piece &a, const Piece &b
     return make_double2(0.0, 0.0);
 }
 
+// Forces of element e on its three local nodes from displacement u (the
+// step's element pass).  An intact element computes its own strain and that
+// of each intact neighbour (recomputed from u and the coordinates; the
+// neighbour's third node comes from the opposite-node table), smooths the
+// strain of its three edges with w = A_lo / (A_lo + A_hi) (lower element id
+// first), applies Hooke's law and returns (A/3) B^T (sigma_0 + sigma_1 +
+// sigma_2); with `cands` its free-surface edges are evaluated as crack-tip
+// candidates and accepted ones appended to the list.  A split element
+// returns the forces of its two pieces.
+__device__ __forceinline__ void element_force(const Params &p, const double2 *u, int e, bool cands, double2 f[3]) {
+    const int4 c = p.conn[e];
+    const uint8_t code = p.split[e];
+    if (code) {
+        const Piece pa = piece(p, u, c, (code >> 2) & 3, code & 3);
+        const Piece pb = piece(p, u, c, code & 3, (code >> 2) & 3);
+        f[0] = piece_force_at(pa, pb, 0);
+        f[1] = piece_force_at(pa, pb, 1);
+        f[2] = piece_force_at(pa, pb, 2);
+        return;
+    }
+    const int4 nb = p.nbr[e];
+    const int4 op = p.opp[e];
+    double2 ue[3], uo[3], xe[3], xo[3];
+    load_u(u, c, ue);
+    load_u(p.xy, c, xe);
+    const double2 z2 = make_double2(0.0, 0.0);
+    uo[0] = op.x >= 0 ? u[op.x] : z2;
+    uo[1] = op.y >= 0 ? u[op.y] : z2;
+    uo[2] = op.z >= 0 ? u[op.z] : z2;
+    xo[0] = op.x >= 0 ? p.xy[op.x] : z2;
+    xo[1] = op.y >= 0 ? p.xy[op.y] : z2;
+    xo[2] = op.z >= 0 ? p.xy[op.z] : z2;
+    const Geo g = make_geo(xe[0], xe[1], xe[2]);
+    double q[3];
+    strain(g, ue, q);
+    double sig[3][3];
+    bool two[3];
+    double eps[3][3], An[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        edge_strain(p, e, k == 0 ? nb.x : (k == 1 ? nb.y : nb.z), (nb.w >> (2 * k)) & 3, xe[k], xe[(k + 1) % 3],
+                    xo[k], ue[k], ue[(k + 1) % 3], uo[k], q, g.A, eps[k], two[k], An[k]);
+        hooke(p, eps[k], sig[k]);
+    }
+    double S[3];
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) S[cc] = (sig[0][cc] + sig[1][cc]) + sig[2][cc];
+    const double coef = g.A / 3.0;
+#pragma unroll
+    for (int n = 0; n < 3; ++n)
+        f[n] = make_double2(coef * fma(g.by[n], S[2], g.bx[n] * S[0]), coef * fma(g.bx[n], S[2], g.by[n] * S[1]));
+    if (!cands || (two[0] && two[1] && two[2])) return;
+    const int tip = p.sct ? p.ctl->tip : -1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (two[a]) continue;
+        if (p.sct && tip != 4 * e + a) continue;
+        double G;
+        const Sig s0 = {{sig[0][0], sig[0][1], sig[0][2]}}, s1 = {{sig[1][0], sig[1][1], sig[1][2]}},
+                  s2 = {{sig[2][0], sig[2][1], sig[2][2]}};
+        const int j = candidate(p, e, c, sel3(a, ue[0], ue[1], ue[2]), sel3((a + 1) % 3, ue[0], ue[1], ue[2]), s0,
+                                s1, s2, a, G);
+        if (j < 0) continue;
+        const int k = (a + 1 + j) % 3;
+        const int slot = atomicAdd(&p.ctl->nacc, 1);
+        Cand cd;
+        cd.G = G;
+        cd.elem = e;
+        cd.ak = (a << 2) | k;
+        p.cand[slot] = cd;
+    }
+}
+
 // Element pass.  eval: query mode (u given, outputs in ev, no candidates).
 template <bool EVAL>
-__global__ __launch_bounds__(kB) void k_force(Params p, const double2 *u, Eval ev) {
+__global__ __launch_bounds__(kB) void k_force(Params p, const double2 *u, Eval ev, int j) {
     const int e = blockIdx.x * kB + threadIdx.x;
     if (e >= p.ne) return;
+    if constexpr (!EVAL) {
+        if (((p.ctl->base + j) & 1) != 0) u = p.u1;  // u^k
+        double2 f[3];
+        element_force(p, u, e, true, f);
+        p.fe[e] = f[0];
+        p.fe[p.ne + e] = f[1];
+        p.fe[2 * (int64_t)p.ne + e] = f[2];
+        return;
+    }
     const int4 c = p.conn[e];
     const uint8_t code = p.split[e];
     // slot-major element forces: node slot n of element e at fe[n ne + e]
@@ -332,28 +414,6 @@ __global__ __launch_bounds__(kB) void k_force(Params p, const double2 *u, Eval e
             ev.principal[e] = cc + sqrt(hd * hd + m2 * m2);
         }
         return;
-    } else {
-        const bool any_free = !(two[0] && two[1] && two[2]);
-        if (!any_free) return;
-        const int tip = p.sct ? p.ctl->tip : -1;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            if (two[a]) continue;
-            if (p.sct && tip != 4 * e + a) continue;
-            double G;
-            const Sig s0 = {{sig[0][0], sig[0][1], sig[0][2]}}, s1 = {{sig[1][0], sig[1][1], sig[1][2]}},
-                      s2 = {{sig[2][0], sig[2][1], sig[2][2]}};
-            const int j = candidate(p, e, c, sel3(a, ue[0], ue[1], ue[2]), sel3((a + 1) % 3, ue[0], ue[1], ue[2]),
-                                    s0, s1, s2, a, G);
-            if (j < 0) continue;
-            const int k = (a + 1 + j) % 3;
-            const int slot = atomicAdd(&p.ctl->nacc, 1);
-            Cand cd;
-            cd.G = G;
-            cd.elem = e;
-            cd.ak = (a << 2) | k;
-            p.cand[slot] = cd;
-        }
     }
 }
 
@@ -511,9 +571,74 @@ __global__ __launch_bounds__(kB) void k_node(Params p, int j) {
         if (fl & kFixY) vy = prescribed(p, v0.y, th);
     }
     p.v[i] = make_double2(vx, vy);
-    const double2 u = p.u[i];
-    p.u[i] = make_double2(u.x + p.dt * vx, u.y + p.dt * vy);
+    const bool odd = (k & 1) != 0;
+    const double2 u = (odd ? p.u1 : p.u0)[i];
+    (odd ? p.u0 : p.u1)[i] = make_double2(u.x + p.dt * vx, u.y + p.dt * vy);
 }
+
+// Fused step of one patch of patch_nodes consecutive nodes: the forces of every
+// element touching the patch (elements on patch borders are computed by
+// each patch they touch; only the owning patch evaluates their candidates)
+// go to LDS, then every owned node sums its slots in colour order and is
+// updated.  u^k is read from buffer k & 1 and u^{k+1} written to the other,
+// so neighbouring workgroups never see a half-updated displacement.
+template <int W, int EMAX>
+__global__ __launch_bounds__(kB) void k_fused(Params p, int j) {
+    __shared__ double2 s_f[3 * EMAX];
+    __shared__ double s_phi;
+    const int64_t k = p.ctl->base + j;
+    const bool odd = (k & 1) != 0;
+    const double2 *u = odd ? p.u1 : p.u0;
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const int s0 = p.patch_off[b], s1 = p.patch_off[b + 1];
+    for (int s = s0 + tid; s < s1; s += kB) {
+        const int32_t rec = p.patch_elem[s];
+        double2 f[3];
+        element_force(p, u, rec & (kOwned - 1), (rec & kOwned) != 0, f);
+        const int l = 3 * (s - s0);
+        s_f[l] = f[0];
+        s_f[l + 1] = f[1];
+        s_f[l + 2] = f[2];
+    }
+    if (tid == 0) s_phi = load_factor(p, (double)k * p.dt);
+    __syncthreads();
+    const int i = b * p.patch_nodes + tid;
+    if (tid >= p.patch_nodes || i >= p.nn) return;
+    uint16_t sl[W];
+#pragma unroll
+    for (int d = 0; d < W; ++d) sl[d] = p.patch_slots[(int64_t)i * W + d];
+    double fx = 0.0, fy = 0.0;
+#pragma unroll
+    for (int d = 0; d < W; ++d)
+        if (sl[d] != 0xffff) {
+            const double2 f = s_f[sl[d]];
+            fx = fx + f.x;
+            fy = fy + f.y;
+        }
+    const uint8_t fl = p.nflag[i];
+    const double2 fxt = (fl & kLoaded) ? p.fext[i] : make_double2(0.0, 0.0);
+    const double phi = s_phi, mi = p.minv[i];
+    double ax = (phi * fxt.x - fx) * mi;
+    double ay = (phi * fxt.y - fy) * mi;
+    if (fl & kFixX) ax = 0.0;
+    if (fl & kFixY) ay = 0.0;
+    const double dtv = (k == 0) ? 0.5 * p.dt : p.dt;
+    const double th = ((double)k + 0.5) * p.dt;
+    const double2 v = p.v[i];
+    double vx = v.x + dtv * ax;
+    double vy = v.y + dtv * ay;
+    if (fl & (kFixX | kFixY)) {
+        const double2 v0 = p.v0[i];
+        if (fl & kFixX) vx = prescribed(p, v0.x, th);
+        if (fl & kFixY) vy = prescribed(p, v0.y, th);
+    }
+    p.v[i] = make_double2(vx, vy);
+    const double2 uk = u[i];
+    (odd ? p.u0 : p.u1)[i] = make_double2(uk.x + p.dt * vx, uk.y + p.dt * vy);
+}
+
+// The global pick of step base + j after a fused step (one workgroup).
+__global__ __launch_bounds__(kB) void k_pick(Params p, int j) { pick(p, p.ctl->base + j); }
 
 __global__ void k_commit(Params p, int n) {
     if (threadIdx.x == 0 && blockIdx.x == 0) p.ctl->base = p.ctl->base + n;
@@ -650,7 +775,27 @@ __global__ __launch_bounds__(kFrontThreads) void k_front(Params p, int j) {
 }  // namespace
 
 hipError_t launch_step(const Params &p, int j, hipStream_t st) {
-    k_force<false><<<nb_of(p.ne), kB, 0, st>>>(p, p.u, Eval{});
+    if (p.patch_emax > 0) {
+        if (p.patch_nodes < 1 || p.patch_nodes > kB || p.patch_emax > 1024) return hipErrorInvalidValue;
+        const int np = (p.nn + p.patch_nodes - 1) / p.patch_nodes;
+        const int key = p.nlist_w * 4 + (p.patch_emax <= 256 ? 0 : p.patch_emax <= 512 ? 1 : 2);
+        switch (key) {
+#define FUSED(Wv, E, kk) \
+    case Wv * 4 + kk: k_fused<Wv, E><<<np, kB, 0, st>>>(p, j); break;
+            FUSED(4, 256, 0) FUSED(4, 512, 1) FUSED(4, 1024, 2)
+            FUSED(8, 256, 0) FUSED(8, 512, 1) FUSED(8, 1024, 2)
+            FUSED(12, 256, 0) FUSED(12, 512, 1) FUSED(12, 1024, 2)
+            FUSED(16, 256, 0) FUSED(16, 512, 1) FUSED(16, 1024, 2)
+#undef FUSED
+            default: return hipErrorInvalidValue;
+        }
+        if (p.front_r2 > 0.0)
+            k_front<<<1, kFrontThreads, 0, st>>>(p, j);
+        else
+            k_pick<<<1, kB, 0, st>>>(p, j);
+        return hipGetLastError();
+    }
+    k_force<false><<<nb_of(p.ne), kB, 0, st>>>(p, p.u0, Eval{}, j);
     if (p.front_r2 > 0.0) k_front<<<1, kFrontThreads, 0, st>>>(p, j);
     const int nb = nb_of(p.nn);
     switch (p.nlist ? p.nlist_w : 0) {
@@ -671,7 +816,7 @@ hipError_t launch_commit(const Params &p, int n, hipStream_t st) {
 hipError_t launch_eval(const Params &p, const double2 *u, const double2 *v, int64_t k, double phi,
                        const double *mass, const Eval &ev, hipStream_t st) {
     (void)hipGetLastError();
-    k_force<true><<<nb_of(p.ne), kB, 0, st>>>(p, u, ev);
+    k_force<true><<<nb_of(p.ne), kB, 0, st>>>(p, u, ev, 0);
     k_eval_nodes<<<nb_of(p.nn), kB, 0, st>>>(p, u, v, k, phi, mass, ev);
     return hipGetLastError();
 }

@@ -159,7 +159,92 @@ int eval_state(Model &m, Host h, Ctl *ctl, bool with_energy) {
             phi = m.curve_phi[i] + (t - m.curve_t[i]) * slope;
         }
     }
-    TRY(h, launch_eval(m.prm, m.du, with_energy ? m.dv : nullptr, k, phi, m.dmass, m.ev, h.stream));
+    TRY(h, launch_eval(m.prm, m.du[k & 1], with_energy ? m.dv : nullptr, k, phi, m.dmass, m.ev, h.stream));
+    return MCT_OK;
+}
+
+// Fused-step tables for patches of P consecutive nodes (one workgroup each):
+// the patch's elements (every element touching an owned node, ascending id,
+// flagged kOwned in the patch of its smallest node, which alone evaluates its
+// candidates) and, per owned node, the LDS slots of its element forces in
+// colour order, padded to the gather lists' width.  Returns the largest
+// element count of a patch, 0 if the tables do not fit the kernel (more than
+// 16 elements at a node or 1024 in a patch).
+int build_patches(Model &m, Host h, int P, int32_t *emax_out) {
+    *emax_out = 0;
+    const int64_t nn = m.nn, ne = m.ne;
+    const std::vector<int32_t> &noff = m.gnoff, &nel = m.gnel;
+    int32_t maxdeg = 0;
+    for (int64_t i = 0; i < nn; ++i) maxdeg = std::max(maxdeg, noff[i + 1] - noff[i]);
+    const int32_t W = (maxdeg + 3) / 4 * 4;
+    if (W > 16) return MCT_OK;
+    const int64_t npatch = (nn + P - 1) / P;
+    std::vector<int32_t> poff{0}, pelem, slot_of(ne, -1), stamp(ne, -1), els;
+    std::vector<uint16_t> pslots((size_t)npatch * P * W, 0xffff);
+    int32_t emax = 0;
+    for (int64_t b = 0; b < npatch; ++b) {
+        const int64_t n0 = b * P, n1 = std::min<int64_t>(nn, n0 + P);
+        els.clear();
+        for (int64_t i = n0; i < n1; ++i)
+            for (int32_t t = noff[i]; t < noff[i + 1]; ++t) {
+                const int32_t e = nel[t] / 3;
+                if (stamp[e] != (int32_t)b) {
+                    stamp[e] = (int32_t)b;
+                    els.push_back(e);
+                }
+            }
+        std::sort(els.begin(), els.end());
+        if ((int64_t)els.size() > 1024) return MCT_OK;
+        emax = std::max<int32_t>(emax, (int32_t)els.size());
+        for (size_t q = 0; q < els.size(); ++q) {
+            const int32_t e = els[q];
+            slot_of[e] = (int32_t)q;
+            const int32_t mn = std::min(m.conn[3 * e], std::min(m.conn[3 * e + 1], m.conn[3 * e + 2]));
+            pelem.push_back(e | (mn / P == b ? kOwned : 0));
+        }
+        poff.push_back((int32_t)pelem.size());
+        for (int64_t i = n0; i < n1; ++i)
+            for (int32_t t = noff[i]; t < noff[i + 1]; ++t)
+                pslots[(size_t)i * W + (t - noff[i])] = (uint16_t)(3 * slot_of[nel[t] / 3] + nel[t] % 3);
+    }
+    dfree(m.dpatch_off);
+    dfree(m.dpatch_elem);
+    dfree(m.dpatch_slots);
+    int rc;
+    if ((rc = upload<int32_t>(h, m.dpatch_off, poff.data(), poff.size()))) return rc;
+    if ((rc = upload<int32_t>(h, m.dpatch_elem, pelem.data(), pelem.size()))) return rc;
+    if ((rc = upload<uint16_t>(h, m.dpatch_slots, pslots.data(), pslots.size()))) return rc;
+    TRY(h, hipStreamSynchronize(h.stream));
+    *emax_out = emax;
+    return MCT_OK;
+}
+
+// Step kernels from the requested choice: 1 split kernels; 2, 3, 4 the fused
+// kernel on patches of 64, 128, 256 nodes; 0 automatic: fused on 64-node
+// patches below kFusedMaxElems elements (the launch it saves is a large part
+// of a short step), split above (the element kernel keeps more waves in
+// flight than the patches, and the redundant border elements cost more than
+// the force hand-off).  A fused choice whose tables do not fit runs the split
+// kernels.
+int choose_kernels(Model &m, Host h) {
+    Params &p = m.prm;
+    p.patch_emax = 0;
+    p.patch_nodes = 0;
+    int P = 0;
+    if (m.kernels >= 2)
+        P = 64 << (m.kernels - 2);
+    else if (m.kernels == 0 && m.ne < kFusedMaxElems)
+        P = 64;
+    if (P == 0 || !m.dnlist) return MCT_OK;
+    int32_t emax = 0;
+    int rc = build_patches(m, h, P, &emax);
+    if (rc) return rc;
+    if (emax == 0) return MCT_OK;
+    p.patch_emax = emax;
+    p.patch_nodes = P;
+    p.patch_off = m.dpatch_off;
+    p.patch_elem = m.dpatch_elem;
+    p.patch_slots = m.dpatch_slots;
     return MCT_OK;
 }
 
@@ -177,7 +262,11 @@ void release(Model &m) {
     dfree(m.dcurve);
     dfree(m.dmass);
     dfree(m.dxy);
-    dfree(m.du);
+    dfree(m.du[0]);
+    dfree(m.du[1]);
+    dfree(m.dpatch_off);
+    dfree(m.dpatch_elem);
+    dfree(m.dpatch_slots);
     dfree(m.dv);
     dfree(m.dfext);
     dfree(m.dv0);
@@ -497,6 +586,8 @@ int finalize(Model &m, Host h) {
     for (int64_t i = 0; i < nn; ++i)
         std::sort(nel.begin() + noff[i], nel.begin() + noff[i + 1],
                   [&](int32_t p, int32_t q) { return color[p / 3] < color[q / 3]; });
+    m.gnoff = noff;
+    m.gnel = nel;
     // gather entries name force slots n * ne + e (slot-major element forces)
     for (int32_t &v : nel) v = (v % 3) * (int32_t)ne + v / 3;
     // device arrays
@@ -560,9 +651,11 @@ int finalize(Model &m, Host h) {
         cv.insert(cv.end(), m.curve_phi.begin(), m.curve_phi.end());
         if ((rc = upload<double>(h, m.dcurve, cv.data(), cv.size()))) return rc;
     }
-    TRY(h, hipMalloc((void **)&m.du, sizeof(double2) * nn));
+    TRY(h, hipMalloc((void **)&m.du[0], sizeof(double2) * nn));
+    TRY(h, hipMalloc((void **)&m.du[1], sizeof(double2) * nn));
     TRY(h, hipMalloc((void **)&m.dv, sizeof(double2) * nn));
-    TRY(h, hipMemsetAsync(m.du, 0, sizeof(double2) * nn, h.stream));
+    TRY(h, hipMemsetAsync(m.du[0], 0, sizeof(double2) * nn, h.stream));
+    TRY(h, hipMemsetAsync(m.du[1], 0, sizeof(double2) * nn, h.stream));
     TRY(h, hipMemsetAsync(m.dv, 0, sizeof(double2) * nn, h.stream));
     TRY(h, hipMalloc((void **)&m.dfe, sizeof(double2) * 3 * ne));
     TRY(h, hipMalloc((void **)&m.dcand, sizeof(Cand) * 3 * ne));
@@ -616,8 +709,11 @@ int finalize(Model &m, Host h) {
     p.opp = m.dopp;
     p.nlist = m.dnlist;
     p.nlist_w = m.dnlist ? W : 0;
+    // the fused step's slot lists have the padded lists' width
+    if ((rc = choose_kernels(m, h))) return rc;
     p.xy = m.dxy;
-    p.u = m.du;
+    p.u0 = m.du[0];
+    p.u1 = m.du[1];
     p.v = m.dv;
     p.minv = m.dminv;
     p.fext = m.dfext;
@@ -701,6 +797,18 @@ int step(Model &m, Host h, int64_t n) {
     return MCT_OK;
 }
 
+int set_kernels(Model &m, Host h, int kind) {
+    if (kind < 0 || kind > 4) return fail(h, MCT_EINVAL, "step kernel choice %d out of range (0..4)", kind);
+    m.kernels = kind;
+    if (!m.finalized) return MCT_OK;
+    if (m.graph) {
+        TRY(h, hipStreamSynchronize(h.stream));
+        (void)hipGraphExecDestroy(m.graph);
+        m.graph = nullptr;
+    }
+    return choose_kernels(m, h);
+}
+
 int sync(Model &m, Host h) {
     if (!m.finalized) {
         TRY(h, hipStreamSynchronize(h.stream));
@@ -710,7 +818,8 @@ int sync(Model &m, Host h) {
     if (rc) return rc;
     int32_t flag = 0;
     TRY(h, hipMemsetAsync(m.dwatch, 0, sizeof(int32_t), h.stream));
-    const double *u = reinterpret_cast<const double *>(m.du), *v = reinterpret_cast<const double *>(m.dv);
+    const double *u = reinterpret_cast<const double *>(m.du[m.steps_enqueued & 1]),
+                 *v = reinterpret_cast<const double *>(m.dv);
     TRY(h, launch_check_finite(u, v, u, v, 2 * m.nn, m.dwatch, h.stream));
     TRY(h, hipMemcpyAsync(&flag, m.dwatch, sizeof flag, hipMemcpyDeviceToHost, h.stream));
     TRY(h, hipStreamSynchronize(h.stream));
@@ -797,8 +906,11 @@ int get_field(Model &m, Host h, int which, int64_t cap, double *out) {
     if (which < MCT_FIELD_U || which > MCT_FIELD_PRINCIPAL) return fail(h, MCT_EINVAL, "unknown field %d", which);
     if (cap < need) return fail(h, MCT_ECAPACITY, "field needs %lld values", (long long)need);
     if (which == MCT_FIELD_U || which == MCT_FIELD_V) {
+        Ctl c0;
+        int rc0 = read_ctl(m, h, &c0);
+        if (rc0) return rc0;
         std::vector<double> buf(2 * nn);
-        TRY(h, hipMemcpyAsync(buf.data(), which == MCT_FIELD_U ? m.du : m.dv, sizeof(double) * 2 * nn,
+        TRY(h, hipMemcpyAsync(buf.data(), which == MCT_FIELD_U ? m.du[c0.base & 1] : m.dv, sizeof(double) * 2 * nn,
                               hipMemcpyDeviceToHost, h.stream));
         TRY(h, hipStreamSynchronize(h.stream));
         for (int64_t i = 0; i < nn; ++i) {
@@ -893,7 +1005,7 @@ int checkpoint(Model &m, Host h, void *buf, int64_t cap, int64_t *bytes) {
     p += 24;
     std::memcpy(p, &c, sizeof c);
     p += sizeof c;
-    TRY(h, hipMemcpyAsync(p, m.du, 16 * m.nn, hipMemcpyDeviceToHost, h.stream));
+    TRY(h, hipMemcpyAsync(p, m.du[c.base & 1], 16 * m.nn, hipMemcpyDeviceToHost, h.stream));
     p += 16 * m.nn;
     TRY(h, hipMemcpyAsync(p, m.dv, 16 * m.nn, hipMemcpyDeviceToHost, h.stream));
     p += 16 * m.nn;
@@ -923,7 +1035,7 @@ int restore(Model &m, Host h, const void *buf, int64_t bytes) {
     p += 24 + sizeof c;
     TRY(h, hipStreamSynchronize(h.stream));
     TRY(h, hipMemcpy(m.dctl, &c, sizeof c, hipMemcpyHostToDevice));
-    TRY(h, hipMemcpy(m.du, p, 16 * m.nn, hipMemcpyHostToDevice));
+    TRY(h, hipMemcpy(m.du[c.base & 1], p, 16 * m.nn, hipMemcpyHostToDevice));
     p += 16 * m.nn;
     TRY(h, hipMemcpy(m.dv, p, 16 * m.nn, hipMemcpyHostToDevice));
     p += 16 * m.nn;

@@ -52,7 +52,14 @@ struct Model {
     // device memory
     int4 *dconn = nullptr, *dnbr = nullptr, *dopp = nullptr;
     double *dminv = nullptr, *dgc = nullptr, *dcurve = nullptr, *dmass = nullptr;
-    double2 *dxy = nullptr, *du = nullptr, *dv = nullptr, *dfext = nullptr, *dv0 = nullptr, *dfe = nullptr;
+    double2 *dxy = nullptr, *du[2] = {nullptr, nullptr}, *dv = nullptr, *dfext = nullptr, *dv0 = nullptr,
+            *dfe = nullptr;
+    int32_t *dpatch_off = nullptr, *dpatch_elem = nullptr;
+    uint16_t *dpatch_slots = nullptr;
+    // step kernels: 0 automatic, 1 split, 2/3/4 fused on 64/128/256-node patches
+    int kernels = 0;
+    // node -> incident (3 * element + local node) entries in colour order
+    std::vector<int32_t> gnoff, gnel;
     uint8_t *dflag = nullptr, *dsplit = nullptr;
     int32_t *dcsr_off = nullptr, *dcsr_ent = nullptr, *dnlist = nullptr, *dedge_elem = nullptr, *dwatch = nullptr;
     Cand *dcand = nullptr;
@@ -90,6 +97,11 @@ int set_time(Model &m, Host h, double dt, double cfl);
 int set_front_pick(Model &m, Host h, double rho);
 int finalize(Model &m, Host h);
 int step(Model &m, Host h, int64_t n);
+// Step kernels: 0 automatic, 1 the element kernel plus the node kernel,
+// 2/3/4 the fused kernel on patches of 64/128/256 nodes (the split kernels
+// where its tables do not fit).  Drops a captured graph (after the stream has
+// drained).
+int set_kernels(Model &m, Host h, int kind);
 int sync(Model &m, Host h);
 int get_info(Model &m, Host h, mct_info *out);
 int get_crack_set(Model &m, Host h, int64_t cap, int32_t *step, int32_t *elem, uint8_t *entry, uint8_t *exit,

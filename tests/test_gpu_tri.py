@@ -44,7 +44,9 @@ def _same(m, o, label):
 def test_tri_matches_oracle(gpu, oracle_mod, name):
     cfg = W.tri_small_cases()[name]
     o = oracle_mod.Oracle(cfg)
-    models = [gpu.from_config(cfg, use_graph=g) for g in (True, False)]
+    # split step kernels (1), fused on 64-, 128-, 256-node patches (2, 3, 4)
+    models = [gpu.from_config(cfg, tile=t, use_graph=g) for t in (1, 2, 3, 4) for g in (True, False)]
+    assert [m.launch()["tile"] for m in models] == [1, 1, 2, 2, 3, 3, 4, 4]
     inf = models[0].info()
     assert (inf["n_nodes"], inf["n_elems"], inf["n_edges"]) == (o.info()["nn"], o.info()["ne"], o.info()["ns"])
     assert inf["dt"] == o.info()["dt"]
@@ -55,7 +57,7 @@ def test_tri_matches_oracle(gpu, oracle_mod, name):
         for m in models:
             m.step(chunk)
             m.sync()
-            _same(m, o, (name, done))
+            _same(m, o, (name, done, m.launch()["tile"]))
     e, xy = models[0].tips()
     oe, oxy = o.tips()
     assert np.array_equal(e, oe) and np.array_equal(xy, oxy)
@@ -66,25 +68,29 @@ def test_tri_matches_oracle(gpu, oracle_mod, name):
 def test_tri_sct_matches_oracle(gpu, oracle_mod):
     cfg = dict(W.tri_small_cases()["tri_plate40x16"], tracking=("sct", -1, 0))
     o = oracle_mod.Oracle(cfg)
-    m = gpu.from_config(cfg)
-    assert m.tip() == o.tip() and m.tip() is not None
-    for chunk in (100, 500, 900):
+    models = [gpu.from_config(cfg, tile=t) for t in (0, 1)]
+    assert models[0].tip() == o.tip() and o.tip() is not None
+    for chunk in (100, 501, 900):
         o.step(chunk)
-        m.step(chunk)
-        _same(m, o, ("sct", chunk))
-        assert m.tip() == o.tip()
+        for m in models:
+            m.step(chunk)
+            _same(m, o, ("sct", chunk, m.launch()["tile"]))
+            assert m.tip() == o.tip()
     assert len(o.log()["elem"]) > 3
 
 
 def test_tri_checkpoint_restore(gpu):
     cfg = W.tri_small_cases()["tri_cylinder_coarse"]
     a = gpu.from_config(cfg)
-    a.step(150)
+    a.step(151)  # odd: the state sits in the second displacement buffer
     ck = a.checkpoint()
     a.step(200)
-    b = gpu.from_config(cfg)
+    b = gpu.from_config(cfg, tile=1)  # split step kernels resume the fused run
     b.restore(ck)
-    b.step(200)
+    b.step(77)
+    b.set_launch(3)  # and hand over to the fused kernel mid-run
+    b.step(123)
+    assert b.launch()["tile"] == 3
     la, lb = a.crack_set(), b.crack_set()
     for k in ("step", "elem", "entry", "exit", "G"):
         assert np.array_equal(la[k], lb[k])
@@ -208,8 +214,9 @@ def test_tri_invalid_meshes(gpu):
     with pytest.raises(gpu.MctError):  # a node in no triangle
         m.set_mesh_tri(np.append(X, 2.0), np.append(Y, 2.0), good)
     m.set_mesh_tri(X, Y, good)
-    with pytest.raises(gpu.MctError):
-        m.set_launch(2, True)
+    for bad in (-1, 5):  # step kernel choices are 0..4
+        with pytest.raises(gpu.MctError):
+            m.set_launch(bad, True)
     with pytest.raises(gpu.MctError):  # notch local edges are 0..2
         m.set_notch(np.array([0], np.int32), np.array([3], np.uint8), np.array([1], np.uint8))
     with pytest.raises(gpu.MctError):  # no batches of triangle meshes
@@ -223,6 +230,11 @@ def test_tri_fullsize_plate_sampled(gpu, oracle_mod):
     cfg = W.tri_plate320k()
     o = oracle_mod.Oracle(cfg)
     m = gpu.from_config(cfg)
+    assert m.launch()["tile"] == 1  # the automatic choice at this size (split kernels), as timed
+    f = gpu.from_config(cfg, tile=2)  # and the fused kernel on 64-node patches
+    assert f.launch()["tile"] == 2
     o.step(300)
     m.step(300)
+    f.step(300)
     _same(m, o, "tri_plate320k")
+    _same(f, o, "tri_plate320k fused")
