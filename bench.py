@@ -49,14 +49,16 @@ def n_nodes(c) -> int:
     return len(c["X"])
 
 
-def bytes_per_step(cfgs) -> int:
-    """Algorithmic HBM bytes of one step (binary64): per node read u, v, X,
-    Y, 1/m and write u, v (11 doubles); per Q4 element its split code and its
-    area (9 bytes; the structured grid needs no connectivity); per CST
-    element its split code and its three node ids (13 bytes)."""
+def bytes_per_step(cfgs, precision: int = 64) -> int:
+    """Algorithmic HBM bytes of one step: per node read u, v, X, Y, 1/m and
+    write u, v (11 values: 88 bytes in binary64, 44 in binary32); per Q4
+    element its split code and its area (9 bytes, 5 in binary32; the
+    structured grid needs no connectivity); per CST element its split code
+    and its three node ids (13 bytes)."""
+    w = 8 if precision == 64 else 4
     total = 0
     for c in cfgs:
-        total += 88 * n_nodes(c) + (13 if c.get("conn") is not None else 9) * n_elems(c)
+        total += 11 * w * n_nodes(c) + (13 if c.get("conn") is not None else 1 + w) * n_elems(c)
     return total
 
 
@@ -101,14 +103,14 @@ def measured_traffic(workload: str, tile: int):
 def cpu_baseline(cfg, steps: int):
     from oracle import oracle
     oracle.set_threads(1)
-    o = oracle.Oracle(cfg)
+    o = oracle.Oracle(cfg)  # the binary32 build for a binary32 workload
     t0 = time.perf_counter()
     o.step(steps)
     dt = time.perf_counter() - t0
     ne = n_elems(cfg)
     return {"value": ne * steps / dt, "unit": "element-updates/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d time steps of the same %s (%d elements; single-threaded C oracle, %.1f s)"
-                      % (steps, cfg["name"], ne, dt)}
+            "sample": "first %d time steps of the same %s (%d elements; single-threaded C oracle, binary%d, %.1f s)"
+                      % (steps, cfg["name"], ne, int(cfg.get("precision", 64)), dt)}
 
 
 def timed_run(m, stream, steps, warmup):
@@ -148,6 +150,8 @@ def main():
                     help="Q4 edge smoothing (plain Q4 workloads)")
     ap.add_argument("--front-radius", type=float, default=0.0,
                     help="per-front pick with this competition radius in m (plain workloads; 0: global pick)")
+    ap.add_argument("--precision", type=int, default=64, choices=(64, 32),
+                    help="32: the binary32 step (plate400 and fragment2000)")
     ap.add_argument("--compare-plain", action="store_true",
                     help="batch256: also run each specimen alone and compare")
     ap.add_argument("--kernel-hash", action="store_true",
@@ -200,6 +204,11 @@ def main():
             cfgs[0]["smoothing"] = args.smoothing
         if args.front_radius > 0:
             cfgs[0]["front_radius"] = args.front_radius
+        if args.precision == 32:
+            if args.workload not in ("plate400", "fragment2000"):
+                print("--precision 32 is for the Q4 workloads plate400 and fragment2000", file=sys.stderr)
+                sys.exit(2)
+            cfgs[0]["precision"] = 32
         m = mct2d.from_config(cfgs[0], stream=stream.cuda_stream, tile=args.tile,
                               use_graph=not args.no_graph)
     steps = args.steps if args.steps is not None else cfgs[0]["steps"]
@@ -221,7 +230,8 @@ def main():
     screen_stats = m.screen_stats() if screen else None
     ms_per_step = gpu_ms / steps
     value = ne * steps / (gpu_ms * 1e-3)
-    bps = bytes_per_step(cfgs)
+    bps = bytes_per_step(cfgs, args.precision)
+    traffic_key = args.workload + ("_f32" if args.precision == 32 else "")
     achieved = bps / (ms_per_step * 1e-3) / 1e9
     out = {
         "metric": "element-updates/s",
@@ -234,19 +244,19 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32" if args.precision == 32 else "f64",
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "specimens": len(cfgs), "elements": ne,
                    "time_steps": steps, "tile": launch["tile"], "order": launch["order"],
                    "workgroups": launch["workgroups"], "graph": not args.no_graph,
-                   "smoothing": args.smoothing, "front_radius": args.front_radius,
+                   "smoothing": args.smoothing, "front_radius": args.front_radius, "precision": args.precision,
                    "autotuned": tune is not None},
         "wall_s": wall,
         "splits": splits,
         "dissipated_J_per_m": ud,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(args.workload, launch["tile"]), "bytes_per_launch": bps},
+                     "traffic": measured_traffic(traffic_key, launch["tile"]), "bytes_per_launch": bps},
     }
     m.close()
     if screen:

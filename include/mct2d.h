@@ -60,7 +60,7 @@ enum {
     MCT_ECAPACITY = -3,  /* output capacity too small, *count holds the need */
     MCT_EDEVICE = -4,    /* HIP runtime or kernel launch failure */
     MCT_ENOMEM = -5,     /* device or host allocation failed */
-    MCT_EUNSUPPORTED = -6, /* precision 32, or the screen on a batch */
+    MCT_EUNSUPPORTED = -6, /* a combination the library does not offer (see the calls) */
     MCT_ESTABILITY = -7, /* dt above the stability limit of the explicit step */
     MCT_ENUMERIC = -8    /* non-finite displacement or velocity */
 };
@@ -89,7 +89,18 @@ typedef struct {
                             edge (-1: none, or multi-tip tracking) */
 } mct_info;
 
-/* Create an empty context.  precision: 64 (binary64 state and arithmetic).
+/* Create an empty context.  precision: 64 (binary64 state and arithmetic)
+ * or 32: the binary32 step on a structured Q4 grid (the set-up -- areas,
+ * lumped masses, equivalent nodal forces, D, dt -- is computed in binary64
+ * and each value rounded once to binary32; state, strains, stresses,
+ * forces, G, the element rule and the pick are binary32; times and the load
+ * curve binary64; U_d accumulates the binary32 products Gc * L in binary64).
+ * A binary32 context reports u, v, split codes, the crack set (G exact in
+ * binary64) and tips as computed; the derived fields and energies are
+ * evaluated in binary64 from its state; checkpoints hold that state and
+ * restore only into a binary32 context.  Not for binary32: triangle meshes,
+ * batches, the split-screen, sub-cell smoothing, the per-front pick
+ * (MCT_EUNSUPPORTED from the call that asks for them).
  * hip_stream: a hipStream_t to enqueue on, or NULL for a library stream.
  * Errors: MCT_EINVAL (out NULL), MCT_EUNSUPPORTED (precision), MCT_EDEVICE. */
 int mct_create(mct_ctx **out, int precision, void *hip_stream);
@@ -300,7 +311,8 @@ int mct_set_launch(mct_ctx *ctx, int tile, int use_graph);
  * every query and set-up call acts on the selected specimen.  Specimens may
  * differ in mesh, material, Gc field, loads, notch and time step.  A plain
  * context (mct_create) is a batch of one.  Errors: MCT_EINVAL for
- * n_specimens < 1 or s out of range. */
+ * n_specimens < 1 or s out of range; MCT_EUNSUPPORTED for a precision other
+ * than 64. */
 int mct_batch_create(mct_ctx **out, int64_t n_specimens, int precision, void *hip_stream);
 int mct_batch_select(mct_ctx *ctx, int64_t s);
 

@@ -47,6 +47,15 @@
  * FP contract (binds the HIP library as well): IEEE binary64, round to
  * nearest, compiled with -ffp-contract=off; fma() only where written.
  *
+ * Binary32 build (ORC_FP32 defined; liboracle32.so): the set-up (areas,
+ * lumped masses, equivalent nodal forces, D, dt, the tables) stays binary64
+ * exactly as above; the step reads every set-up value rounded once to
+ * binary32 and computes in binary32 (state, strains, stresses, forces, G,
+ * the element rule and the pick); times t_k and the load factor are
+ * evaluated in binary64 and rounded; a split adds its Gc * L (a binary32
+ * product) to U_d in binary64.  `real` is the step's type; R() makes a
+ * constant a real.
+ *
  * Loops whose iterations write disjoint outputs (edges, elements, elements
  * of one colour, nodes, candidate evaluation) may run on several OpenMP
  * threads; every value is still computed by one thread in the order written
@@ -54,6 +63,7 @@
  */
 #include <math.h>
 #include <omp.h>
+#include <float.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -65,6 +75,17 @@
 #define ORC_ECAPACITY (-3)
 
 #define SPLIT_FLAG 0x80u
+
+#ifdef ORC_FP32
+typedef float real;
+#define rfma fmaf
+#define rsqrt sqrtf
+#else
+typedef double real;
+#define rfma fma
+#define rsqrt sqrt
+#endif
+#define R(x) ((real)(x))
 
 typedef struct {
     int step, elem, entry, exit;
@@ -104,7 +125,7 @@ typedef struct {
     int finalized;
     /* state */
     unsigned char *split;
-    double *ux, *uy, *vx, *vy;
+    real *ux, *uy, *vx, *vy;
     long step;
     orc_split_t *log;
     int nlog, caplog;
@@ -120,18 +141,24 @@ typedef struct {
      * of the edge), 1 = sub-cells (the triangle edge + centroid of j) */
     int subcell;
     /* scratch */
-    double *sig;            /* 3 per edge */
-    double *eps;            /* 3 per edge: smoothed strain */
+    real *sig;              /* 3 per edge */
+    real *eps;              /* 3 per edge: smoothed strain */
     unsigned char *sig_ok;  /* edge has >= 1 intact neighbour */
-    double *fe;             /* 8 per element */
-    double *fx, *fy, *ax, *ay;
+    real *fe;               /* 8 per element */
+    real *fx, *fy, *ax, *ay;
 } orc_model_t;
 
+/* set-up values as the step reads them (binary64 rounded once to real) */
+static real rX(const orc_model_t *m, int n) { return (real)m->X[n]; }
+static real rY(const orc_model_t *m, int n) { return (real)m->Y[n]; }
+static real r_area(const orc_model_t *m, int e) { return (real)m->area[e]; }
+static real r_gc(const orc_model_t *m, int e) { return (real)m->Gc[e]; }
+
 /* natural coordinates of the Q4 nodes and of the four edge midpoints */
-static const double XI_N[4] = {-1.0, 1.0, 1.0, -1.0};
-static const double ETA_N[4] = {-1.0, -1.0, 1.0, 1.0};
-static const double XI_M[4] = {0.0, 1.0, 0.0, -1.0};
-static const double ETA_M[4] = {-1.0, 0.0, 1.0, 0.0};
+static const real XI_N[4] = {-1.0, 1.0, 1.0, -1.0};
+static const real ETA_N[4] = {-1.0, -1.0, 1.0, 1.0};
+static const real XI_M[4] = {0.0, 1.0, 0.0, -1.0};
+static const real ETA_M[4] = {-1.0, 0.0, 1.0, 0.0};
 
 /* ------------------------------------------------------------------ */
 /* element kinematics                                                   */
@@ -141,22 +168,22 @@ static const double ETA_M[4] = {-1.0, 0.0, 1.0, 0.0};
  * element with node coordinates (x[4], y[4]) at the midpoint of its local
  * edge k (Eq. QUAD_strain_discretization evaluated at the edge quadrature
  * point). */
-static void q4_grad_at_edge(const double x[4], const double y[4], int k,
-                            double dndx[4], double dndy[4]) {
-    double dxi[4], deta[4];
+static void q4_grad_at_edge(const real x[4], const real y[4], int k,
+                            real dndx[4], real dndy[4]) {
+    real dxi[4], deta[4];
     for (int n = 0; n < 4; ++n) {
-        dxi[n] = 0.25 * XI_N[n] * (1.0 + ETA_M[k] * ETA_N[n]);
-        deta[n] = 0.25 * ETA_N[n] * (1.0 + XI_M[k] * XI_N[n]);
+        dxi[n] = R(0.25) * XI_N[n] * (R(1.0) + ETA_M[k] * ETA_N[n]);
+        deta[n] = R(0.25) * ETA_N[n] * (R(1.0) + XI_M[k] * XI_N[n]);
     }
-    double j11 = 0.0, j12 = 0.0, j21 = 0.0, j22 = 0.0;
+    real j11 = 0.0, j12 = 0.0, j21 = 0.0, j22 = 0.0;
     for (int n = 0; n < 4; ++n) {
-        j11 = fma(dxi[n], x[n], j11);
-        j12 = fma(dxi[n], y[n], j12);
-        j21 = fma(deta[n], x[n], j21);
-        j22 = fma(deta[n], y[n], j22);
+        j11 = rfma(dxi[n], x[n], j11);
+        j12 = rfma(dxi[n], y[n], j12);
+        j21 = rfma(deta[n], x[n], j21);
+        j22 = rfma(deta[n], y[n], j22);
     }
-    double det = j11 * j22 - j12 * j21;
-    double inv = 1.0 / det;
+    real det = j11 * j22 - j12 * j21;
+    real inv = R(1.0) / det;
     for (int n = 0; n < 4; ++n) {
         dndx[n] = (j22 * dxi[n] - j12 * deta[n]) * inv;
         dndy[n] = (j11 * deta[n] - j21 * dxi[n]) * inv;
@@ -165,9 +192,9 @@ static void q4_grad_at_edge(const double x[4], const double y[4], int k,
 
 /* Gradients of the linear shape functions of a triangle (x[3], y[3]),
  * constant over the element (Eq. CST_strain_discretization). */
-static void tri_grad(const double x[3], const double y[3], double dndx[3], double dndy[3]) {
-    double twoA = (x[1] - x[0]) * (y[2] - y[0]) - (x[2] - x[0]) * (y[1] - y[0]);
-    double inv = 1.0 / twoA;
+static void tri_grad(const real x[3], const real y[3], real dndx[3], real dndy[3]) {
+    real twoA = (x[1] - x[0]) * (y[2] - y[0]) - (x[2] - x[0]) * (y[1] - y[0]);
+    real inv = R(1.0) / twoA;
     dndx[0] = (y[1] - y[2]) * inv;
     dndx[1] = (y[2] - y[0]) * inv;
     dndx[2] = (y[0] - y[1]) * inv;
@@ -177,14 +204,14 @@ static void tri_grad(const double x[3], const double y[3], double dndx[3], doubl
 }
 
 /* strain (exx, eyy, gxy) = B u for an element with nn nodes */
-static void strain_from_grad(int nn, const double *dndx, const double *dndy,
-                             const double *ux, const double *uy, double eps[3]) {
-    double exx = 0.0, eyy = 0.0, gxy = 0.0;
+static void strain_from_grad(int nn, const real *dndx, const real *dndy,
+                             const real *ux, const real *uy, real eps[3]) {
+    real exx = 0.0, eyy = 0.0, gxy = 0.0;
     for (int n = 0; n < nn; ++n) {
-        exx = fma(dndx[n], ux[n], exx);
-        eyy = fma(dndy[n], uy[n], eyy);
-        gxy = fma(dndy[n], ux[n], gxy);
-        gxy = fma(dndx[n], uy[n], gxy);
+        exx = rfma(dndx[n], ux[n], exx);
+        eyy = rfma(dndy[n], uy[n], eyy);
+        gxy = rfma(dndy[n], ux[n], gxy);
+        gxy = rfma(dndx[n], uy[n], gxy);
     }
     eps[0] = exx;
     eps[1] = eyy;
@@ -192,50 +219,64 @@ static void strain_from_grad(int nn, const double *dndx, const double *dndy,
 }
 
 /* plane-stress Hooke law, engineering shear strain */
-static void stress_from_strain(const orc_model_t *m, const double eps[3], double sig[3]) {
-    sig[0] = fma(m->D12, eps[1], m->D11 * eps[0]);
-    sig[1] = fma(m->D12, eps[0], m->D11 * eps[1]);
-    sig[2] = m->D33 * eps[2];
+static void stress_from_strain(const orc_model_t *m, const real eps[3], real sig[3]) {
+    const real D11 = (real)m->D11, D12 = (real)m->D12, D33 = (real)m->D33;
+    sig[0] = rfma(D12, eps[1], D11 * eps[0]);
+    sig[1] = rfma(D12, eps[0], D11 * eps[1]);
+    sig[2] = D33 * eps[2];
 }
 
-static void elem_coords(const orc_model_t *m, int e, double x[4], double y[4]) {
+static void elem_coords(const orc_model_t *m, int e, real x[4], real y[4]) {
+    for (int n = 0; n < m->nv; ++n) {
+        x[n] = rX(m, m->conn[4 * e + n]);
+        y[n] = rY(m, m->conn[4 * e + n]);
+    }
+}
+
+/* binary64 corner coordinates (set-up: areas) */
+static void elem_coords_d(const orc_model_t *m, int e, double x[4], double y[4]) {
     for (int n = 0; n < m->nv; ++n) {
         x[n] = m->X[m->conn[4 * e + n]];
         y[n] = m->Y[m->conn[4 * e + n]];
     }
 }
 
-static void elem_disp(const orc_model_t *m, int e, double ux[4], double uy[4]) {
+static void elem_disp(const orc_model_t *m, int e, real ux[4], real uy[4]) {
     for (int n = 0; n < m->nv; ++n) {
         ux[n] = m->ux[m->conn[4 * e + n]];
         uy[n] = m->uy[m->conn[4 * e + n]];
     }
 }
 
-/* triangle area: half the cross product of two edges from node 0 */
-static double tri_area(const double x[3], const double y[3]) {
+/* triangle area: half the cross product of two edges from node 0 (the
+ * step's sub-cells, in real; tri_area_d: set-up, binary64) */
+static real tri_area(const real x[3], const real y[3]) {
+    return R(0.5) * ((x[1] - x[0]) * (y[2] - y[0]) - (x[2] - x[0]) * (y[1] - y[0]));
+}
+
+static double tri_area_d(const double x[3], const double y[3]) {
     return 0.5 * ((x[1] - x[0]) * (y[2] - y[0]) - (x[2] - x[0]) * (y[1] - y[0]));
 }
 
-/* quadrilateral area: half the cross product of the diagonals */
+/* quadrilateral area: half the cross product of the diagonals (set-up) */
 static double quad_area(const double x[4], const double y[4]) {
     return 0.5 * ((x[2] - x[0]) * (y[3] - y[1]) - (x[3] - x[1]) * (y[2] - y[0]));
 }
 
 /* polygon area by a fan from the first vertex */
-static double polygon_area(int nv, const double *px, const double *py) {
-    double s = 0.0;
+static real polygon_area(int nv, const real *px, const real *py) {
+    real s = 0.0;
     for (int i = 1; i + 1 < nv; ++i)
         s += (px[i] - px[0]) * (py[i + 1] - py[0]) - (px[i + 1] - px[0]) * (py[i] - py[0]);
-    return 0.5 * s;
+    return R(0.5) * s;
 }
 
 static int is_intact(const orc_model_t *m, int e) { return e >= 0 && m->split[e] == 0; }
 
 /* B of element e at the quadrature point of its local edge k: the Q4
  * gradient at the edge midpoint, or the constant CST gradient */
-static void elem_grad_at_edge(const orc_model_t *m, int e, int k, double dndx[4], double dndy[4]) {
-    double x[4], y[4];
+static void elem_grad_at_edge(const orc_model_t *m, int e, int k, real dndx[4], real dndy[4]) {
+    real x[4], y[4];
     elem_coords(m, e, x, y);
     if (m->nv == 4)
         q4_grad_at_edge(x, y, k, dndx, dndy);
@@ -254,25 +295,25 @@ static void elem_grad_at_edge(const orc_model_t *m, int e, int k, double dndx[4]
  * the smoothing-domain part of standard edge-based smoothing over triangular
  * sub-cells (divergence theorem with a linear displacement along the
  * sub-cell boundary), the alternative to the point rule. */
-static double subcell(const orc_model_t *m, int e, int k, const double *ux_all, const double *uy_all,
-                      double x[3], double y[3], double ux[3], double uy[3]) {
-    double ex[4], ey[4];
+static real subcell(const orc_model_t *m, int e, int k, const real *ux_all, const real *uy_all,
+                    real x[3], real y[3], real ux[3], real uy[3]) {
+    real ex[4], ey[4];
     elem_coords(m, e, ex, ey);
     int a = m->conn[4 * e + k], b = m->conn[4 * e + ((k + 1) & 3)];
     x[0] = ex[k];
     y[0] = ey[k];
     x[1] = ex[(k + 1) & 3];
     y[1] = ey[(k + 1) & 3];
-    x[2] = 0.25 * (((ex[0] + ex[1]) + ex[2]) + ex[3]);
-    y[2] = 0.25 * (((ey[0] + ey[1]) + ey[2]) + ey[3]);
+    x[2] = R(0.25) * (((ex[0] + ex[1]) + ex[2]) + ex[3]);
+    y[2] = R(0.25) * (((ey[0] + ey[1]) + ey[2]) + ey[3]);
     if (ux_all) {
         const int *cn = &m->conn[4 * e];
         ux[0] = ux_all[a];
         uy[0] = uy_all[a];
         ux[1] = ux_all[b];
         uy[1] = uy_all[b];
-        ux[2] = 0.25 * (((ux_all[cn[0]] + ux_all[cn[1]]) + ux_all[cn[2]]) + ux_all[cn[3]]);
-        uy[2] = 0.25 * (((uy_all[cn[0]] + uy_all[cn[1]]) + uy_all[cn[2]]) + uy_all[cn[3]]);
+        ux[2] = R(0.25) * (((ux_all[cn[0]] + ux_all[cn[1]]) + ux_all[cn[2]]) + ux_all[cn[3]]);
+        uy[2] = R(0.25) * (((uy_all[cn[0]] + uy_all[cn[1]]) + uy_all[cn[2]]) + uy_all[cn[3]]);
     }
     return tri_area(x, y);
 }
@@ -280,27 +321,27 @@ static double subcell(const orc_model_t *m, int e, int k, const double *ux_all, 
 static void edge_stresses(orc_model_t *m) {
 #pragma omp parallel for schedule(static)
     for (int s = 0; s < m->ns; ++s) {
-        double q[2][3], A[2];
+        real q[2][3], A[2];
         int cnt = 0;
         for (int side = 0; side < 2; ++side) {
             int e = m->edge_elem[2 * s + side];
             if (!is_intact(m, e)) continue;
             if (m->nv == 4 && m->subcell) {
-                double x[3], y[3], ux[3], uy[3], dndx[3], dndy[3];
+                real x[3], y[3], ux[3], uy[3], dndx[3], dndy[3];
                 A[cnt] = subcell(m, e, m->edge_loc[2 * s + side], m->ux, m->uy, x, y, ux, uy);
                 tri_grad(x, y, dndx, dndy);
                 strain_from_grad(3, dndx, dndy, ux, uy, q[cnt]);
                 cnt++;
                 continue;
             }
-            double ux[4], uy[4], dndx[4], dndy[4];
+            real ux[4], uy[4], dndx[4], dndy[4];
             elem_disp(m, e, ux, uy);
             elem_grad_at_edge(m, e, m->edge_loc[2 * s + side], dndx, dndy);
             strain_from_grad(m->nv, dndx, dndy, ux, uy, q[cnt]);
-            A[cnt] = m->area[e];
+            A[cnt] = r_area(m, e);
             cnt++;
         }
-        double eps[3];
+        real eps[3];
         if (cnt == 0) {
             m->sig_ok[s] = 0;
             m->sig[3 * s] = m->sig[3 * s + 1] = m->sig[3 * s + 2] = 0.0;
@@ -314,9 +355,9 @@ static void edge_stresses(orc_model_t *m) {
             eps[2] = q[0][2];
         } else {
             /* w_j = A_j / sum A, lower element id first */
-            double sum = A[0] + A[1];
-            double w0 = A[0] / sum, w1 = A[1] / sum;
-            for (int c = 0; c < 3; ++c) eps[c] = fma(w1, q[1][c], w0 * q[0][c]);
+            real sum = A[0] + A[1];
+            real w0 = A[0] / sum, w1 = A[1] / sum;
+            for (int c = 0; c < 3; ++c) eps[c] = rfma(w1, q[1][c], w0 * q[0][c]);
         }
         stress_from_strain(m, eps, &m->sig[3 * s]);
         for (int c = 0; c < 3; ++c) m->eps[3 * s + c] = eps[c];
@@ -331,17 +372,17 @@ static void edge_stresses(orc_model_t *m) {
 /* CST (Eq. CST_fint_discretization): element e receives (A_e/3) B_e^T
  * sigma_s from each of its three edges; B_e is constant, so the three edge
  * stresses are summed first (local edge order). */
-static void intact_force_tri(const orc_model_t *m, int e, double f[8]) {
-    double dndx[4], dndy[4], S[3];
+static void intact_force_tri(const orc_model_t *m, int e, real f[8]) {
+    real dndx[4], dndy[4], S[3];
     elem_grad_at_edge(m, e, 0, dndx, dndy);
-    const double *s0 = &m->sig[3 * m->elem_edge[4 * e]];
-    const double *s1 = &m->sig[3 * m->elem_edge[4 * e + 1]];
-    const double *s2 = &m->sig[3 * m->elem_edge[4 * e + 2]];
+    const real *s0 = &m->sig[3 * m->elem_edge[4 * e]];
+    const real *s1 = &m->sig[3 * m->elem_edge[4 * e + 1]];
+    const real *s2 = &m->sig[3 * m->elem_edge[4 * e + 2]];
     for (int c = 0; c < 3; ++c) S[c] = (s0[c] + s1[c]) + s2[c];
-    double coef = m->area[e] / 3.0;
+    real coef = r_area(m, e) / R(3.0);
     for (int n = 0; n < 3; ++n) {
-        f[2 * n] = coef * fma(dndy[n], S[2], dndx[n] * S[0]);
-        f[2 * n + 1] = coef * fma(dndx[n], S[2], dndy[n] * S[1]);
+        f[2 * n] = coef * rfma(dndy[n], S[2], dndx[n] * S[0]);
+        f[2 * n + 1] = coef * rfma(dndx[n], S[2], dndy[n] * S[1]);
     }
 }
 
@@ -350,27 +391,27 @@ static void intact_force_tri(const orc_model_t *m, int e, double f[8]) {
  * quarter to each node.  Per node n and edge k the bracket is
  * t_a + t_c / 4 (n = k), t_b + t_c / 4 (n = k + 1) or t_c / 4, scaled by
  * A_T and summed over k = 0..3. */
-static void intact_force_subcell(const orc_model_t *m, int e, double f[8]) {
+static void intact_force_subcell(const orc_model_t *m, int e, real f[8]) {
     for (int k = 0; k < 4; ++k) {
-        double x[3], y[3], b[3], c[3];
-        double AT = subcell(m, e, k, NULL, NULL, x, y, NULL, NULL);
+        real x[3], y[3], b[3], c[3];
+        real AT = subcell(m, e, k, NULL, NULL, x, y, NULL, NULL);
         tri_grad(x, y, b, c);
-        const double *sg = &m->sig[3 * m->elem_edge[4 * e + k]];
-        double tx[3], ty[3];
+        const real *sg = &m->sig[3 * m->elem_edge[4 * e + k]];
+        real tx[3], ty[3];
         for (int i = 0; i < 3; ++i) {
-            tx[i] = fma(c[i], sg[2], b[i] * sg[0]);
-            ty[i] = fma(b[i], sg[2], c[i] * sg[1]);
+            tx[i] = rfma(c[i], sg[2], b[i] * sg[0]);
+            ty[i] = rfma(b[i], sg[2], c[i] * sg[1]);
         }
         for (int n = 0; n < 4; ++n) {
-            double gx = 0.25 * tx[2], gy = 0.25 * ty[2];
+            real gx = R(0.25) * tx[2], gy = R(0.25) * ty[2];
             if (n == k) {
-                gx = tx[0] + 0.25 * tx[2];
-                gy = ty[0] + 0.25 * ty[2];
+                gx = tx[0] + R(0.25) * tx[2];
+                gy = ty[0] + R(0.25) * ty[2];
             } else if (n == ((k + 1) & 3)) {
-                gx = tx[1] + 0.25 * tx[2];
-                gy = ty[1] + 0.25 * ty[2];
+                gx = tx[1] + R(0.25) * tx[2];
+                gy = ty[1] + R(0.25) * ty[2];
             }
-            double vx = AT * gx, vy = AT * gy;
+            real vx = AT * gx, vy = AT * gy;
             if (k == 0) {
                 f[2 * n] = vx;
                 f[2 * n + 1] = vy;
@@ -382,7 +423,7 @@ static void intact_force_subcell(const orc_model_t *m, int e, double f[8]) {
     }
 }
 
-static void intact_force(const orc_model_t *m, int e, double f[8]) {
+static void intact_force(const orc_model_t *m, int e, real f[8]) {
     if (m->nv == 3) {
         intact_force_tri(m, e, f);
         return;
@@ -391,16 +432,16 @@ static void intact_force(const orc_model_t *m, int e, double f[8]) {
         intact_force_subcell(m, e, f);
         return;
     }
-    double x[4], y[4];
+    real x[4], y[4];
     elem_coords(m, e, x, y);
-    double sx[4] = {0, 0, 0, 0}, sy[4] = {0, 0, 0, 0};
+    real sx[4] = {0, 0, 0, 0}, sy[4] = {0, 0, 0, 0};
     for (int k = 0; k < 4; ++k) {
-        double dndx[4], dndy[4];
+        real dndx[4], dndy[4];
         q4_grad_at_edge(x, y, k, dndx, dndy);
-        const double *sg = &m->sig[3 * m->elem_edge[4 * e + k]];
+        const real *sg = &m->sig[3 * m->elem_edge[4 * e + k]];
         for (int n = 0; n < 4; ++n) {
-            double tx = fma(dndy[n], sg[2], dndx[n] * sg[0]);
-            double ty = fma(dndx[n], sg[2], dndy[n] * sg[1]);
+            real tx = rfma(dndy[n], sg[2], dndx[n] * sg[0]);
+            real ty = rfma(dndx[n], sg[2], dndy[n] * sg[1]);
             if (k == 0) {
                 sx[n] = tx;
                 sy[n] = ty;
@@ -410,7 +451,7 @@ static void intact_force(const orc_model_t *m, int e, double f[8]) {
             }
         }
     }
-    double c = 0.25 * m->area[e];
+    real c = R(0.25) * r_area(m, e);
     for (int n = 0; n < 4; ++n) {
         f[2 * n] = c * sx[n];
         f[2 * n + 1] = c * sy[n];
@@ -421,8 +462,8 @@ static void intact_force(const orc_model_t *m, int e, double f[8]) {
  * the crack midpoints of edges `exit_edge` (after last) and `entry_edge`
  * (before first).  Adds its nodal forces into f[8] (each node belongs to one
  * piece only).  Returns the piece strain energy. */
-static double piece_force(const orc_model_t *m, int e, int entry_edge, int exit_edge,
-                          double f[8]) {
+static real piece_force(const orc_model_t *m, int e, int entry_edge, int exit_edge,
+                        real f[8]) {
     const int *cn = &m->conn[4 * e];
     const int nvert = m->nv;
     int loc[3];
@@ -432,54 +473,54 @@ static double piece_force(const orc_model_t *m, int e, int entry_edge, int exit_
         if (k == exit_edge) break;
     }
     /* polygon: M_entry, nodes..., M_exit */
-    double px[5], py[5];
+    real px[5], py[5];
     int nv = 0;
     int a0 = cn[entry_edge], a1 = cn[(entry_edge + 1) % nvert];
     int b0 = cn[exit_edge], b1 = cn[(exit_edge + 1) % nvert];
-    px[nv] = 0.5 * (m->X[a0] + m->X[a1]);
-    py[nv++] = 0.5 * (m->Y[a0] + m->Y[a1]);
+    px[nv] = R(0.5) * (rX(m, a0) + rX(m, a1));
+    py[nv++] = R(0.5) * (rY(m, a0) + rY(m, a1));
     for (int i = 0; i < np; ++i) {
-        px[nv] = m->X[cn[loc[i]]];
-        py[nv++] = m->Y[cn[loc[i]]];
+        px[nv] = rX(m, cn[loc[i]]);
+        py[nv++] = rY(m, cn[loc[i]]);
     }
-    px[nv] = 0.5 * (m->X[b0] + m->X[b1]);
-    py[nv++] = 0.5 * (m->Y[b0] + m->Y[b1]);
-    double Ap = polygon_area(nv, px, py);
+    px[nv] = R(0.5) * (rX(m, b0) + rX(m, b1));
+    py[nv++] = R(0.5) * (rY(m, b0) + rY(m, b1));
+    real Ap = polygon_area(nv, px, py);
 
     if (np == 3) {
         /* constant-strain triangle over the three nodes */
-        double b[3], c[3];
+        real b[3], c[3];
         tri_grad(&px[1], &py[1], b, c);
-        double ux[3], uy[3];
+        real ux[3], uy[3];
         for (int i = 0; i < 3; ++i) {
             ux[i] = m->ux[cn[loc[i]]];
             uy[i] = m->uy[cn[loc[i]]];
         }
-        double eps[3], sg[3];
+        real eps[3], sg[3];
         strain_from_grad(3, b, c, ux, uy, eps);
         stress_from_strain(m, eps, sg);
         for (int i = 0; i < 3; ++i) {
-            double tx = fma(c[i], sg[2], b[i] * sg[0]);
-            double ty = fma(b[i], sg[2], c[i] * sg[1]);
+            real tx = rfma(c[i], sg[2], b[i] * sg[0]);
+            real ty = rfma(b[i], sg[2], c[i] * sg[1]);
             f[2 * loc[i]] = Ap * tx;
             f[2 * loc[i] + 1] = Ap * ty;
         }
-        return 0.5 * Ap * (sg[0] * eps[0] + sg[1] * eps[1] + sg[2] * eps[2]);
+        return R(0.5) * Ap * (sg[0] * eps[0] + sg[1] * eps[1] + sg[2] * eps[2]);
     }
     if (np == 2) {
         /* bar along the two nodes, cross-section Ap / L */
         int p = cn[loc[0]], q = cn[loc[1]];
-        double dx = m->X[q] - m->X[p], dy = m->Y[q] - m->Y[p];
-        double L2 = dx * dx + dy * dy;
-        double dux = m->ux[q] - m->ux[p], duy = m->uy[q] - m->uy[p];
-        double strain = (dx * dux + dy * duy) / L2;
-        double stress = m->E * strain;
-        double coef = Ap * stress / L2;
+        real dx = rX(m, q) - rX(m, p), dy = rY(m, q) - rY(m, p);
+        real L2 = dx * dx + dy * dy;
+        real dux = m->ux[q] - m->ux[p], duy = m->uy[q] - m->uy[p];
+        real strain = (dx * dux + dy * duy) / L2;
+        real stress = (real)m->E * strain;
+        real coef = Ap * stress / L2;
         f[2 * loc[1]] = coef * dx;
         f[2 * loc[1] + 1] = coef * dy;
         f[2 * loc[0]] = -(coef * dx);
         f[2 * loc[0] + 1] = -(coef * dy);
-        return 0.5 * Ap * stress * strain;
+        return R(0.5) * Ap * stress * strain;
     }
     /* one node: a free corner carries no stiffness */
     f[2 * loc[0]] = 0.0;
@@ -487,9 +528,9 @@ static double piece_force(const orc_model_t *m, int e, int entry_edge, int exit_
     return 0.0;
 }
 
-static double split_force(const orc_model_t *m, int e, double f[8]) {
+static real split_force(const orc_model_t *m, int e, real f[8]) {
     int a = (m->split[e] >> 2) & 3, b = m->split[e] & 3;
-    double w = piece_force(m, e, a, b, f);
+    real w = piece_force(m, e, a, b, f);
     w += piece_force(m, e, b, a, f);
     return w;
 }
@@ -527,16 +568,16 @@ static void internal_forces(orc_model_t *m) {
 /* Unit normal and length of the crack path from the midpoint G0 of local
  * edge a to the midpoint Gk of local edge k, oriented toward node N2 = n_{a+1}
  * (reference configuration). */
-static void path_normal(const orc_model_t *m, int e, int a, int k, double *nx,
-                        double *ny, double *len) {
+static void path_normal(const orc_model_t *m, int e, int a, int k, real *nx,
+                        real *ny, real *len) {
     const int *cn = &m->conn[4 * e];
     int p0 = cn[a], p1 = cn[(a + 1) % m->nv], q0 = cn[k], q1 = cn[(k + 1) % m->nv];
-    double g0x = 0.5 * (m->X[p0] + m->X[p1]), g0y = 0.5 * (m->Y[p0] + m->Y[p1]);
-    double gkx = 0.5 * (m->X[q0] + m->X[q1]), gky = 0.5 * (m->Y[q0] + m->Y[q1]);
-    double dx = gkx - g0x, dy = gky - g0y;
-    double L = sqrt(dx * dx + dy * dy);
-    double cx = dy / L, cy = -dx / L;
-    if (cx * (m->X[p1] - g0x) + cy * (m->Y[p1] - g0y) < 0.0) {
+    real g0x = R(0.5) * (rX(m, p0) + rX(m, p1)), g0y = R(0.5) * (rY(m, p0) + rY(m, p1));
+    real gkx = R(0.5) * (rX(m, q0) + rX(m, q1)), gky = R(0.5) * (rY(m, q0) + rY(m, q1));
+    real dx = gkx - g0x, dy = gky - g0y;
+    real L = rsqrt(dx * dx + dy * dy);
+    real cx = dy / L, cy = -dx / L;
+    if (cx * (rX(m, p1) - g0x) + cy * (rY(m, p1) - g0y) < R(0.0)) {
         cx = -cx;
         cy = -cy;
     }
@@ -548,15 +589,15 @@ static void path_normal(const orc_model_t *m, int e, int a, int k, double *nx,
 /* G of the paths of candidate (element e, crack-tip edge a): k = a+1, a+2,
  * a+3 (CCW) for Q4, k = a+1, a+2 for CST (then G[2] = 0).  Returns the
  * Heaviside gate H. */
-static int candidate_G(const orc_model_t *m, int e, int a, double G[3]) {
+static int candidate_G(const orc_model_t *m, int e, int a, real G[3]) {
     const int *cn = &m->conn[4 * e];
     int n1 = cn[a], n2 = cn[(a + 1) % m->nv];
-    double dux = m->ux[n2] - m->ux[n1], duy = m->uy[n2] - m->uy[n1];
+    real dux = m->ux[n2] - m->ux[n1], duy = m->uy[n2] - m->uy[n1];
     /* H(|x2-x1|/|X2-X1| - 1) as a comparison of squared lengths */
-    double x1 = m->X[n1] + m->ux[n1], y1 = m->Y[n1] + m->uy[n1];
-    double x2 = m->X[n2] + m->ux[n2], y2 = m->Y[n2] + m->uy[n2];
-    double lx = x2 - x1, ly = y2 - y1;
-    double Lx = m->X[n2] - m->X[n1], Ly = m->Y[n2] - m->Y[n1];
+    real x1 = rX(m, n1) + m->ux[n1], y1 = rY(m, n1) + m->uy[n1];
+    real x2 = rX(m, n2) + m->ux[n2], y2 = rY(m, n2) + m->uy[n2];
+    real lx = x2 - x1, ly = y2 - y1;
+    real Lx = rX(m, n2) - rX(m, n1), Ly = rY(m, n2) - rY(m, n1);
     int H = (lx * lx + ly * ly) > (Lx * Lx + Ly * Ly);
     G[2] = 0.0;
     for (int j = 0; j < m->nv - 1; ++j) {
@@ -565,12 +606,12 @@ static int candidate_G(const orc_model_t *m, int e, int a, double G[3]) {
             continue;
         }
         int k = (a + 1 + j) % m->nv;
-        const double *sg = &m->sig[3 * m->elem_edge[4 * e + k]];
-        double nx, ny, len;
+        const real *sg = &m->sig[3 * m->elem_edge[4 * e + k]];
+        real nx, ny, len;
         path_normal(m, e, a, k, &nx, &ny, &len);
-        double spx = fma(sg[2], ny, sg[0] * nx);
-        double spy = fma(sg[1], ny, sg[2] * nx);
-        G[j] = 0.5 * fma(duy, spy, dux * spx);
+        real spx = rfma(sg[2], ny, sg[0] * nx);
+        real spy = rfma(sg[1], ny, sg[2] * nx);
+        G[j] = R(0.5) * rfma(duy, spy, dux * spx);
     }
     return H;
 }
@@ -578,7 +619,7 @@ static int candidate_G(const orc_model_t *m, int e, int a, double G[3]) {
 /* Element decision over the n candidate paths (Sec. 2.2: n = 2 for CST,
  * the list after Fig. 2-2; n = 3 for Q4, the list after Fig. 2-3).  Returns
  * the chosen path index j (k = a+1+j) or -1. */
-int orc_element_rule_n(int n, const double *G, double Gc, double gamma) {
+static int element_rule(int n, const real *G, real Gc, real gamma) {
     int best = -1;
     for (int j = 0; j < n; ++j)
         if (G[j] > Gc && (best < 0 || G[j] > G[best])) best = j;
@@ -590,6 +631,14 @@ int orc_element_rule_n(int n, const double *G, double Gc, double gamma) {
     return best;
 }
 
+/* exported form (values rounded to real) */
+int orc_element_rule_n(int n, const double *G, double Gc, double gamma) {
+    real g[3] = {0, 0, 0};
+    if (n < 1 || n > 3) return -1;
+    for (int j = 0; j < n; ++j) g[j] = (real)G[j];
+    return element_rule(n, g, (real)Gc, (real)gamma);
+}
+
 int orc_element_rule(const double G[3], double Gc, double gamma) {
     return orc_element_rule_n(3, G, Gc, gamma);
 }
@@ -597,7 +646,7 @@ int orc_element_rule(const double G[3], double Gc, double gamma) {
 /* MCT pick (Sec. 3): the candidate with the largest G (ties: lower element
  * id, then lower tip edge) provided it passes the split-ratio test against
  * every other candidate.  Returns its index or -1. */
-int orc_mct_pick(int n, const double *G, const int *elem, const int *a, double gamma) {
+static int mct_pick(int n, const real *G, const int *elem, const int *a, real gamma) {
     int best = -1;
     for (int c = 0; c < n; ++c) {
         if (best < 0 || G[c] > G[best] ||
@@ -612,6 +661,15 @@ int orc_mct_pick(int n, const double *G, const int *elem, const int *a, double g
     return best;
 }
 
+/* exported form (values rounded to real) */
+int orc_mct_pick(int n, const double *G, const int *elem, const int *a, double gamma) {
+    real *g = malloc(sizeof(real) * (size_t)(n > 0 ? n : 1));
+    for (int c = 0; c < n; ++c) g[c] = (real)G[c];
+    int r = mct_pick(n, g, elem, a, (real)gamma);
+    free(g);
+    return r;
+}
+
 /* Reference midpoint of the tip edge a of element e (the quadrature point
  * G0 of the candidate). */
 static void tip_midpoint(const orc_model_t *m, int e, int a, double *x, double *y) {
@@ -621,7 +679,7 @@ static void tip_midpoint(const orc_model_t *m, int e, int a, double *x, double *
 }
 
 /* key order of the pick: larger G, then lower element id, then lower tip edge */
-static int better_key(double G1, int e1, int a1, double G2, int e2, int a2) {
+static int better_key(real G1, int e1, int a1, real G2, int e2, int a2) {
     if (G1 != G2) return G1 > G2;
     if (e1 != e2) return e1 < e2;
     return a1 < a2;
@@ -634,8 +692,8 @@ static int better_key(double G1, int e1, int a1, double G2, int e2, int a2) {
  * this is the global pick.  Picked candidates never compete with each
  * other, so their elements are distinct.  Writes the picked indices, in key
  * order, to out; returns their count. */
-int orc_front_pick(int n, const double *G, const int *elem, const int *a, const double *x, const double *y,
-                   double gamma, double rho2, int *out) {
+static int front_pick(int n, const real *G, const int *elem, const int *a, const double *x, const double *y,
+                      real gamma, double rho2, int *out) {
     int np = 0;
     for (int c = 0; c < n; ++c) {
         int ok = 1;
@@ -659,6 +717,16 @@ int orc_front_pick(int n, const double *G, const int *elem, const int *a, const 
         out[j + 1] = v;
     }
     return np;
+}
+
+/* exported form (values rounded to real) */
+int orc_front_pick(int n, const double *G, const int *elem, const int *a, const double *x, const double *y,
+                   double gamma, double rho2, int *out) {
+    real *g = malloc(sizeof(real) * (size_t)(n > 0 ? n : 1));
+    for (int c = 0; c < n; ++c) g[c] = (real)G[c];
+    int r = front_pick(n, g, elem, a, x, y, (real)gamma, rho2, out);
+    free(g);
+    return r;
 }
 
 /* Free-surface candidate (R: edge with exactly one intact neighbour, i.e. a
@@ -692,17 +760,17 @@ static int tip_after(const orc_model_t *m, int f, int k) {
     return 4 * nb + loc;
 }
 
-static void record_split(orc_model_t *m, int f, int a, int k, double G) {
+static void record_split(orc_model_t *m, int f, int a, int k, real G) {
     m->split[f] = (unsigned char)(SPLIT_FLAG | (unsigned)(a << 2) | (unsigned)k);
     if (m->nlog == m->caplog) {
         m->caplog = m->caplog ? 2 * m->caplog : 1024;
         m->log = realloc(m->log, sizeof(orc_split_t) * (size_t)m->caplog);
     }
-    orc_split_t rec = {(int)m->step, f, a, k, G};
+    orc_split_t rec = {(int)m->step, f, a, k, (double)G};
     m->log[m->nlog++] = rec;
-    double nx, ny, len;
+    real nx, ny, len;
     path_normal(m, f, a, k, &nx, &ny, &len);
-    m->Ud += m->Gc[f] * len;
+    m->Ud += (double)(r_gc(m, f) * len);
 }
 
 /* Single crack-tip tracking: the element rule at the current tip only. */
@@ -711,9 +779,9 @@ static void sct_phase(orc_model_t *m) {
     int f = m->tip >> 2, a = m->tip & 3;
     int s = m->elem_edge[4 * f + a], ff, aa;
     if (!edge_candidate(m, s, &ff, &aa) || ff != f) return;
-    double G[3];
+    real G[3];
     candidate_G(m, f, a, G);
-    int j = orc_element_rule_n(m->nv - 1, G, m->Gc[f], m->gamma);
+    int j = element_rule(m->nv - 1, G, r_gc(m, f), (real)m->gamma);
     if (j < 0) return;
     int k = (a + 1 + j) % m->nv;
     record_split(m, f, a, k, G[j]);
@@ -726,20 +794,20 @@ static void fracture_phase(orc_model_t *m) {
         return;
     }
     int cap = m->ns;
-    double *cG = malloc(sizeof(double) * (size_t)cap);
+    real *cG = malloc(sizeof(real) * (size_t)cap);
     int *cE = malloc(sizeof(int) * (size_t)cap), *cA = malloc(sizeof(int) * (size_t)cap);
     int *cK = malloc(sizeof(int) * (size_t)cap);
     /* per edge: accepted path index or -1 (evaluated independently) */
     int *acc = malloc(sizeof(int) * (size_t)cap);
-    double *accG = malloc(sizeof(double) * (size_t)cap);
+    real *accG = malloc(sizeof(real) * (size_t)cap);
 #pragma omp parallel for schedule(dynamic, 4096)
     for (int s = 0; s < m->ns; ++s) {
         int f, a;
         acc[s] = -1;
         if (!edge_candidate(m, s, &f, &a)) continue;
-        double G[3];
+        real G[3];
         candidate_G(m, f, a, G);
-        int j = orc_element_rule_n(m->nv - 1, G, m->Gc[f], m->gamma);
+        int j = element_rule(m->nv - 1, G, r_gc(m, f), (real)m->gamma);
         if (j < 0) continue;
         acc[s] = j;
         accG[s] = G[j];
@@ -763,13 +831,13 @@ static void fracture_phase(orc_model_t *m) {
         double *py = malloc(sizeof(double) * (size_t)(nc ? nc : 1));
         int *pick = malloc(sizeof(int) * (size_t)(nc ? nc : 1));
         for (int i = 0; i < nc; ++i) tip_midpoint(m, cE[i], cA[i], &px[i], &py[i]);
-        int np = orc_front_pick(nc, cG, cE, cA, px, py, m->gamma, m->front_r2, pick);
+        int np = front_pick(nc, cG, cE, cA, px, py, (real)m->gamma, m->front_r2, pick);
         for (int i = 0; i < np; ++i) record_split(m, cE[pick[i]], cA[pick[i]], cK[pick[i]], cG[pick[i]]);
         free(px);
         free(py);
         free(pick);
     } else {
-        int c = orc_mct_pick(nc, cG, cE, cA, m->gamma);
+        int c = mct_pick(nc, cG, cE, cA, (real)m->gamma);
         if (c >= 0) record_split(m, cE[c], cA[c], cK[c], cG[c]);
     }
     free(cG);
@@ -782,8 +850,9 @@ static void fracture_phase(orc_model_t *m) {
 /* a4: central-difference step                                          */
 /* ------------------------------------------------------------------ */
 
-static double prescribed(const orc_model_t *m, double v0, double t) {
-    if (m->t_ramp > 0.0 && t < m->t_ramp) return v0 * (t / m->t_ramp);
+/* v0 times the ramp factor t / t_ramp (binary64, rounded to real) */
+static real prescribed(const orc_model_t *m, real v0, double t) {
+    if (m->t_ramp > 0.0 && t < m->t_ramp) return v0 * (real)(t / m->t_ramp);
     return v0;
 }
 
@@ -802,28 +871,30 @@ double orc_load_factor(const orc_model_t *m, double t) {
 
 static void one_step(orc_model_t *m) {
     internal_forces(m);
-    double phi = orc_load_factor(m, (double)m->step * m->dt);
+    const real phi = (real)orc_load_factor(m, (double)m->step * m->dt);
 #pragma omp parallel for schedule(static)
     for (int i = 0; i < m->nn; ++i) {
-        m->ax[i] = (phi * m->fext[2 * i] - m->fx[i]) * m->minv[i];
-        m->ay[i] = (phi * m->fext[2 * i + 1] - m->fy[i]) * m->minv[i];
+        const real mi = (real)m->minv[i];
+        m->ax[i] = (phi * (real)m->fext[2 * i] - m->fx[i]) * mi;
+        m->ay[i] = (phi * (real)m->fext[2 * i + 1] - m->fy[i]) * mi;
         if (m->vmask[i] & 1) m->ax[i] = 0.0;
         if (m->vmask[i] & 2) m->ay[i] = 0.0;
     }
     /* fracture on (u^k, sigma^k); the split acts from step k+1 */
     fracture_phase(m);
-    double dtv = (m->step == 0) ? 0.5 * m->dt : m->dt;
-    double th = ((double)m->step + 0.5) * m->dt;
+    const real dt = (real)m->dt;
+    const real dtv = (m->step == 0) ? R(0.5) * dt : dt;
+    const double th = ((double)m->step + 0.5) * m->dt;
 #pragma omp parallel for schedule(static)
     for (int i = 0; i < m->nn; ++i) {
-        double vx = m->vx[i] + dtv * m->ax[i];
-        double vy = m->vy[i] + dtv * m->ay[i];
-        if (m->vmask[i] & 1) vx = prescribed(m, m->v0[2 * i], th);
-        if (m->vmask[i] & 2) vy = prescribed(m, m->v0[2 * i + 1], th);
+        real vx = m->vx[i] + dtv * m->ax[i];
+        real vy = m->vy[i] + dtv * m->ay[i];
+        if (m->vmask[i] & 1) vx = prescribed(m, (real)m->v0[2 * i], th);
+        if (m->vmask[i] & 2) vy = prescribed(m, (real)m->v0[2 * i + 1], th);
         m->vx[i] = vx;
         m->vy[i] = vy;
-        m->ux[i] = m->ux[i] + m->dt * vx;
-        m->uy[i] = m->uy[i] + m->dt * vy;
+        m->ux[i] = m->ux[i] + dt * vx;
+        m->uy[i] = m->uy[i] + dt * vy;
     }
     m->step++;
 }
@@ -932,8 +1003,8 @@ static int build_tables(orc_model_t *m) {
     m->area = zalloc(sizeof(double) * m->ne);
     for (int e = 0; e < m->ne; ++e) {
         double x[4], y[4];
-        elem_coords(m, e, x, y);
-        m->area[e] = nv == 4 ? quad_area(x, y) : tri_area(x, y);
+        elem_coords_d(m, e, x, y);
+        m->area[e] = nv == 4 ? quad_area(x, y) : tri_area_d(x, y);
     }
     m->Gc = zalloc(sizeof(double) * m->ne);
     m->edge_trac = zalloc(sizeof(double) * 2 * ns);
@@ -944,18 +1015,18 @@ static int build_tables(orc_model_t *m) {
     m->minv = zalloc(sizeof(double) * m->nn);
     m->fext = zalloc(sizeof(double) * 2 * m->nn);
     m->split = zalloc(m->ne);
-    m->ux = zalloc(sizeof(double) * m->nn);
-    m->uy = zalloc(sizeof(double) * m->nn);
-    m->vx = zalloc(sizeof(double) * m->nn);
-    m->vy = zalloc(sizeof(double) * m->nn);
-    m->sig = zalloc(sizeof(double) * 3 * ns);
-    m->eps = zalloc(sizeof(double) * 3 * ns);
+    m->ux = zalloc(sizeof(real) * m->nn);
+    m->uy = zalloc(sizeof(real) * m->nn);
+    m->vx = zalloc(sizeof(real) * m->nn);
+    m->vy = zalloc(sizeof(real) * m->nn);
+    m->sig = zalloc(sizeof(real) * 3 * ns);
+    m->eps = zalloc(sizeof(real) * 3 * ns);
     m->sig_ok = zalloc(ns);
-    m->fe = zalloc(sizeof(double) * 8 * m->ne);
-    m->fx = zalloc(sizeof(double) * m->nn);
-    m->fy = zalloc(sizeof(double) * m->nn);
-    m->ax = zalloc(sizeof(double) * m->nn);
-    m->ay = zalloc(sizeof(double) * m->nn);
+    m->fe = zalloc(sizeof(real) * 8 * m->ne);
+    m->fx = zalloc(sizeof(real) * m->nn);
+    m->fy = zalloc(sizeof(real) * m->nn);
+    m->ax = zalloc(sizeof(real) * m->nn);
+    m->ay = zalloc(sizeof(real) * m->nn);
     m->gamma = 1.0;
     m->cfl = 0.5;
     return bad ? ORC_EINVAL : ORC_OK;
@@ -1220,21 +1291,33 @@ void orc_info(const orc_model_t *m, int *ints /*nn,ne,ns,ncolor,nlog,nv*/,
     *step = m->step;
 }
 
+/* binary32 build: the state and the step's results are exact in binary64;
+ * inputs given in binary64 are rounded */
+static void to_double(int n, const real *a, double *out) {
+    for (int i = 0; i < n; ++i) out[i] = (double)a[i];
+}
+
+static void to_real(int n, const double *a, real *out) {
+    for (int i = 0; i < n; ++i) out[i] = (real)a[i];
+}
+
+int orc_precision(void) { return (int)(8 * sizeof(real)); }
+
 void orc_get_state(const orc_model_t *m, double *ux, double *uy, double *vx, double *vy,
                    unsigned char *split) {
-    memcpy(ux, m->ux, sizeof(double) * m->nn);
-    memcpy(uy, m->uy, sizeof(double) * m->nn);
-    memcpy(vx, m->vx, sizeof(double) * m->nn);
-    memcpy(vy, m->vy, sizeof(double) * m->nn);
+    to_double(m->nn, m->ux, ux);
+    to_double(m->nn, m->uy, uy);
+    to_double(m->nn, m->vx, vx);
+    to_double(m->nn, m->vy, vy);
     memcpy(split, m->split, m->ne);
 }
 
 void orc_set_state(orc_model_t *m, const double *ux, const double *uy, const double *vx,
                    const double *vy) {
-    memcpy(m->ux, ux, sizeof(double) * m->nn);
-    memcpy(m->uy, uy, sizeof(double) * m->nn);
-    memcpy(m->vx, vx, sizeof(double) * m->nn);
-    memcpy(m->vy, vy, sizeof(double) * m->nn);
+    to_real(m->nn, ux, m->ux);
+    to_real(m->nn, uy, m->uy);
+    to_real(m->nn, vx, m->vx);
+    to_real(m->nn, vy, m->vy);
 }
 
 void orc_get_log(const orc_model_t *m, int *step, int *elem, int *entry, int *exitp, double *G) {
@@ -1262,15 +1345,20 @@ void orc_get_tables(const orc_model_t *m, int *edge_node, int *edge_elem, int *e
  * (the stored state is restored afterwards) */
 void orc_internal_force(orc_model_t *m, const double *ux, const double *uy, double *fx,
                         double *fy, double *sig, unsigned char *sig_ok) {
-    double *sx = m->ux, *sy = m->uy;
-    m->ux = (double *)ux;
-    m->uy = (double *)uy;
+    real *sx = m->ux, *sy = m->uy;
+    real *tx = malloc(sizeof(real) * (size_t)m->nn), *ty = malloc(sizeof(real) * (size_t)m->nn);
+    to_real(m->nn, ux, tx);
+    to_real(m->nn, uy, ty);
+    m->ux = tx;
+    m->uy = ty;
     internal_forces(m);
     m->ux = sx;
     m->uy = sy;
-    memcpy(fx, m->fx, sizeof(double) * m->nn);
-    memcpy(fy, m->fy, sizeof(double) * m->nn);
-    if (sig) memcpy(sig, m->sig, sizeof(double) * 3 * m->ns);
+    free(tx);
+    free(ty);
+    to_double(m->nn, m->fx, fx);
+    to_double(m->nn, m->fy, fy);
+    if (sig) to_double(3 * m->ns, m->sig, sig);
     if (sig_ok) memcpy(sig_ok, m->sig_ok, m->ns);
 }
 
@@ -1285,11 +1373,13 @@ int orc_candidates(orc_model_t *m, int cap, int *edge, int *elem, int *a, double
         int f, la;
         if (!edge_candidate(m, s, &f, &la)) continue;
         if (nc < cap) {
+            real g[3];
             edge[nc] = s;
             elem[nc] = f;
             a[nc] = la;
-            candidate_G(m, f, la, &G3[3 * nc]);
-            dec[nc] = orc_element_rule_n(m->nv - 1, &G3[3 * nc], m->Gc[f], m->gamma);
+            candidate_G(m, f, la, g);
+            to_double(3, g, &G3[3 * nc]);
+            dec[nc] = element_rule(m->nv - 1, g, r_gc(m, f), (real)m->gamma);
         }
         nc++;
     }
@@ -1322,20 +1412,22 @@ int orc_tips(const orc_model_t *m, int cap, int *edge, double *xy, int *count) {
  * strain (edge smoothing domains A_s = sum of intact A_j/4, plus split
  * pieces), external work f_ext(t_k) . u (load curve times the constant
  * tractions), dissipated Ud. */
+/* (binary32 build: the sums run in binary64 over the binary32 forces,
+ * stresses and state) */
 void orc_energies(orc_model_t *m, double out[4]) {
     internal_forces(m);
     double ekin = 0.0, estr = 0.0, wext = 0.0;
     double phi = orc_load_factor(m, (double)m->step * m->dt);
     for (int i = 0; i < m->nn; ++i) {
-        double ax = (phi * m->fext[2 * i] - m->fx[i]) * m->minv[i];
-        double ay = (phi * m->fext[2 * i + 1] - m->fy[i]) * m->minv[i];
+        double ax = (phi * m->fext[2 * i] - (double)m->fx[i]) * m->minv[i];
+        double ay = (phi * m->fext[2 * i + 1] - (double)m->fy[i]) * m->minv[i];
         double vx = m->vx[i], vy = m->vy[i];
         if (m->step > 0) {
             if (!(m->vmask[i] & 1)) vx = vx + 0.5 * m->dt * ax;
             if (!(m->vmask[i] & 2)) vy = vy + 0.5 * m->dt * ay;
         }
         ekin += 0.5 * m->mass[i] * (vx * vx + vy * vy);
-        wext += phi * m->fext[2 * i] * m->ux[i] + phi * m->fext[2 * i + 1] * m->uy[i];
+        wext += phi * m->fext[2 * i] * (double)m->ux[i] + phi * m->fext[2 * i + 1] * (double)m->uy[i];
     }
     for (int s = 0; s < m->ns; ++s) {
         if (!m->sig_ok[s]) continue;
@@ -1344,18 +1436,19 @@ void orc_energies(orc_model_t *m, double out[4]) {
             int e = m->edge_elem[2 * s + side];
             if (!is_intact(m, e)) continue;
             if (m->nv == 4 && m->subcell) {
-                double x[3], y[3];
-                As += subcell(m, e, m->edge_loc[2 * s + side], NULL, NULL, x, y, NULL, NULL);
+                real x[3], y[3];
+                As += (double)subcell(m, e, m->edge_loc[2 * s + side], NULL, NULL, x, y, NULL, NULL);
             } else {
                 As += m->area[e] / (double)m->nv;
             }
         }
-        const double *sg = &m->sig[3 * s], *ep = &m->eps[3 * s];
-        estr += 0.5 * As * (sg[0] * ep[0] + sg[1] * ep[1] + sg[2] * ep[2]);
+        const real *sg = &m->sig[3 * s], *ep = &m->eps[3 * s];
+        estr += 0.5 * As *
+                ((double)sg[0] * (double)ep[0] + (double)sg[1] * (double)ep[1] + (double)sg[2] * (double)ep[2]);
     }
-    double tmp[8];
+    real tmp[8];
     for (int e = 0; e < m->ne; ++e)
-        if (m->split[e]) estr += split_force(m, e, tmp);
+        if (m->split[e]) estr += (double)split_force(m, e, tmp);
     out[0] = ekin;
     out[1] = estr;
     out[2] = wext;
@@ -1364,12 +1457,19 @@ void orc_energies(orc_model_t *m, double out[4]) {
 
 /* G of one candidate of the current state (fresh edge stresses). */
 int orc_candidate_G(orc_model_t *m, int e, int a, double G[3]) {
+    real g[3];
     edge_stresses(m);
-    return candidate_G(m, e, a, G);
+    int H = candidate_G(m, e, a, g);
+    to_double(3, g, G);
+    return H;
 }
 
 int orc_path_normal(const orc_model_t *m, int e, int a, int k, double out[3]) {
-    path_normal(m, e, a, k, &out[0], &out[1], &out[2]);
+    real nx, ny, len;
+    path_normal(m, e, a, k, &nx, &ny, &len);
+    out[0] = (double)nx;
+    out[1] = (double)ny;
+    out[2] = (double)len;
     return ORC_OK;
 }
 

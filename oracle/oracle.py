@@ -1,4 +1,6 @@
-"""ctypes wrapper of the plain FP64 CPU oracle (mct_oracle.c).
+"""ctypes wrapper of the plain CPU oracle (mct_oracle.c): the binary64 build
+(liboracle.so) and the binary32 build of the same source (liboracle32.so,
+the step in binary32 over binary64 set-up values rounded once).
 
 TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
 CPU-baseline leg of the benchmark.  The product package never imports it.
@@ -13,27 +15,38 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mct_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+_LIBS = {64: os.path.join(_HERE, "liboracle.so"), 32: os.path.join(_HERE, "liboracle32.so")}
 
 CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math", "-fopenmp"]
 
 
-def build(force: bool = False) -> str:
-    """Compile liboracle.so with gcc (plain C, no FMA contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+def build(force: bool = False, precision: int = 64) -> str:
+    """Compile liboracle.so (or liboracle32.so) with gcc (plain C, no FMA
+    contraction)."""
+    path = _LIBS[precision]
+    if force or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+        tmp = path + ".tmp%d" % os.getpid()
+        extra = ["-DORC_FP32"] if precision == 32 else []
+        subprocess.check_call(["gcc", *CFLAGS, *extra, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, path)
+    return path
 
 
-_lib = None
+def build_all(force: bool = False) -> None:
+    for prec in _LIBS:
+        build(force, prec)
 
 
-def lib():
-    global _lib
+_libs = {}
+
+
+def lib(precision: int = 64):
+    if precision not in _LIBS:
+        raise ValueError("oracle precision is 64 or 32")
+    _lib = _libs.get(precision)
     if _lib is None:
-        _lib = C.CDLL(build())
+        _lib = C.CDLL(build(precision=precision))
+        _libs[precision] = _lib
         P = C.c_void_p
         dp = np.ctypeslib.ndpointer(np.float64, flags="C")
         ip = np.ctypeslib.ndpointer(np.int32, flags="C")
@@ -77,6 +90,8 @@ def lib():
         _lib.orc_load_factor.restype = C.c_double
         _lib.orc_set_threads.argtypes = [C.c_int]
         _lib.orc_get_threads.restype = C.c_int
+        _lib.orc_precision.restype = C.c_int
+        assert _lib.orc_precision() == precision
     return _lib
 
 
@@ -101,36 +116,38 @@ def get_threads() -> int:
     return int(lib().orc_get_threads())
 
 
-def element_rule(G3, Gc, gamma):
-    return lib().orc_element_rule(_f64(G3), float(Gc), float(gamma))
+def element_rule(G3, Gc, gamma, precision=64):
+    return lib(precision).orc_element_rule(_f64(G3), float(Gc), float(gamma))
 
 
-def element_rule_n(G, Gc, gamma):
+def element_rule_n(G, Gc, gamma, precision=64):
     """Element decision over len(G) candidate paths (2: CST, 3: Q4)."""
     G = _f64(G)
-    return lib().orc_element_rule_n(len(G), G, float(Gc), float(gamma))
+    return lib(precision).orc_element_rule_n(len(G), G, float(Gc), float(gamma))
 
 
-def front_pick(G, elem, a, x, y, gamma, rho):
+def front_pick(G, elem, a, x, y, gamma, rho, precision=64):
     """Indices of the candidates the per-front pick splits, in key order."""
     G = _f64(G)
     out = np.zeros(max(len(G), 1), np.int32)
-    n = lib().orc_front_pick(len(G), G, _i32(elem), _i32(a), _f64(x), _f64(y), float(gamma),
-                             float(rho) ** 2, out)
+    n = lib(precision).orc_front_pick(len(G), G, _i32(elem), _i32(a), _f64(x), _f64(y), float(gamma),
+                                      float(rho) ** 2, out)
     return out[:n]
 
 
-def mct_pick(G, elem, a, gamma):
+def mct_pick(G, elem, a, gamma, precision=64):
     G = _f64(G)
-    return lib().orc_mct_pick(len(G), G, _i32(elem), _i32(a), float(gamma))
+    return lib(precision).orc_mct_pick(len(G), G, _i32(elem), _i32(a), float(gamma))
 
 
 class Oracle:
     """One model run by the plain CPU oracle: a structured Q4 grid (cfg keys
-    nx, ny) or an unstructured CST mesh (cfg key conn, [ne][3] CCW)."""
+    nx, ny) or an unstructured CST mesh (cfg key conn, [ne][3] CCW); cfg key
+    precision 32 runs the binary32 build."""
 
     def __init__(self, cfg: dict, *, finalize: bool = True):
-        L = lib()
+        self.precision = int(cfg.get("precision", 64))
+        L = self._L = lib(self.precision)
         self.cfg = cfg
         if cfg.get("conn") is not None:
             self.nx = self.ny = 0
@@ -177,40 +194,40 @@ class Oracle:
 
     def __del__(self):
         if getattr(self, "h", None):
-            lib().orc_destroy(self.h)
+            self._L.orc_destroy(self.h)
             self.h = None
 
     def info(self):
         ints = np.zeros(6, np.int32)
         dbls = np.zeros(2)
         st = C.c_long(0)
-        lib().orc_info(self.h, ints, dbls, C.byref(st))
+        self._L.orc_info(self.h, ints, dbls, C.byref(st))
         return dict(nn=int(ints[0]), ne=int(ints[1]), ns=int(ints[2]), ncolor=int(ints[3]),
                     nlog=int(ints[4]), nv=int(ints[5]), dt=float(dbls[0]), Ud=float(dbls[1]),
                     step=int(st.value))
 
     def step(self, n):
-        self._check(lib().orc_step(self.h, int(n)))
+        self._check(self._L.orc_step(self.h, int(n)))
 
     def state(self):
         inf = self.info()
         nn, ne = inf["nn"], inf["ne"]
         ux, uy, vx, vy = (np.zeros(nn) for _ in range(4))
         sp = np.zeros(ne, np.uint8)
-        lib().orc_get_state(self.h, ux, uy, vx, vy, sp)
+        self._L.orc_get_state(self.h, ux, uy, vx, vy, sp)
         return dict(ux=ux, uy=uy, vx=vx, vy=vy, split=sp)
 
     def set_state(self, ux, uy, vx, vy):
-        lib().orc_set_state(self.h, _f64(ux), _f64(uy), _f64(vx), _f64(vy))
+        self._L.orc_set_state(self.h, _f64(ux), _f64(uy), _f64(vx), _f64(vy))
 
     def set_split_codes(self, codes):
-        lib().orc_split_codes(self.h, _u8(codes))
+        self._L.orc_split_codes(self.h, _u8(codes))
 
     def log(self):
         n = self.info()["nlog"]
         st, el, en, ex = (np.zeros(n, np.int32) for _ in range(4))
         G = np.zeros(n)
-        lib().orc_get_log(self.h, st, el, en, ex, G)
+        self._L.orc_get_log(self.h, st, el, en, ex, G)
         return dict(step=st, elem=el, entry=en, exit=ex, G=G)
 
     def tables(self):
@@ -223,7 +240,7 @@ class Oracle:
         area = np.zeros(ne)
         mass = np.zeros(nn)
         fext = np.zeros(2 * nn)
-        lib().orc_get_tables(self.h, en, ee, el, col, area, mass, fext)
+        self._L.orc_get_tables(self.h, en, ee, el, col, area, mass, fext)
         return dict(edge_node=en.reshape(-1, 2), edge_elem=ee.reshape(-1, 2),
                     edge_loc=el.reshape(-1, 2), color=col, area=area, mass=mass,
                     fext=fext.reshape(-1, 2))
@@ -234,7 +251,7 @@ class Oracle:
         fx, fy = np.zeros(nn), np.zeros(nn)
         sig = np.zeros(3 * ns)
         ok = np.zeros(ns, np.uint8)
-        lib().orc_internal_force(self.h, _f64(ux), _f64(uy), fx, fy, sig.ctypes.data, ok.ctypes.data)
+        self._L.orc_internal_force(self.h, _f64(ux), _f64(uy), fx, fy, sig.ctypes.data, ok.ctypes.data)
         if with_stress:
             return fx, fy, sig.reshape(-1, 3), ok
         return fx, fy
@@ -244,7 +261,7 @@ class Oracle:
         edge, elem, a, dec = (np.zeros(ns, np.int32) for _ in range(4))
         G3 = np.zeros(3 * ns)
         cnt = np.zeros(1, np.int32)
-        self._check(lib().orc_candidates(self.h, ns, edge, elem, a, G3, dec, cnt))
+        self._check(self._L.orc_candidates(self.h, ns, edge, elem, a, G3, dec, cnt))
         n = int(cnt[0])
         return dict(edge=edge[:n], elem=elem[:n], a=a[:n], G=G3.reshape(-1, 3)[:n], dec=dec[:n])
 
@@ -253,31 +270,31 @@ class Oracle:
         edge = np.zeros(ns, np.int32)
         xy = np.zeros(2 * ns)
         cnt = np.zeros(1, np.int32)
-        self._check(lib().orc_tips(self.h, ns, edge, xy, cnt))
+        self._check(self._L.orc_tips(self.h, ns, edge, xy, cnt))
         n = int(cnt[0])
         return edge[:n], xy.reshape(-1, 2)[:n]
 
     def energies(self):
         out = np.zeros(4)
-        lib().orc_energies(self.h, out)
+        self._L.orc_energies(self.h, out)
         return dict(kin=out[0], strain=out[1], wext=out[2], Ud=out[3])
 
     def candidate_G(self, e, a):
         G = np.zeros(3)
-        H = lib().orc_candidate_G(self.h, int(e), int(a), G)
+        H = self._L.orc_candidate_G(self.h, int(e), int(a), G)
         return G, H
 
     def load_factor(self, t):
-        return lib().orc_load_factor(self.h, float(t))
+        return self._L.orc_load_factor(self.h, float(t))
 
     def tip(self):
         """Current single-crack tip as (element, local edge), or None."""
-        t = lib().orc_get_tip(self.h)
+        t = self._L.orc_get_tip(self.h)
         return None if t < 0 else (t >> 2, t & 3)
 
     def path_normal(self, e, a, k):
         out = np.zeros(3)
-        lib().orc_path_normal(self.h, int(e), int(a), int(k), out)
+        self._L.orc_path_normal(self.h, int(e), int(a), int(k), out)
         return out
 
 

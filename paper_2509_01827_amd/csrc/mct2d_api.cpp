@@ -66,6 +66,7 @@ struct Spec {
     int64_t nn = 0, ne = 0, ns = 0, np = 0;
     int64_t node_off = 0, elem_off = 0, perim_off = 0, tile_base = 0;
     StepParams prm{};
+    mct::StepParamsF prmf{};  // binary32 contexts: the view the step kernels take
 };
 
 }  // namespace
@@ -90,6 +91,11 @@ struct mct_ctx {
     double *dX = nullptr, *dY = nullptr, *dux[2] = {nullptr, nullptr}, *duy[2] = {nullptr, nullptr};
     double *dvx = nullptr, *dvy = nullptr, *dminv = nullptr, *dgc = nullptr, *darea = nullptr;
     double *dfext = nullptr, *dv0 = nullptr, *dcurve = nullptr;
+    // binary32 contexts: the step's arrays (set-up values rounded once, the
+    // state); the binary64 arrays above mirror them for the queries
+    float *fX = nullptr, *fY = nullptr, *fux[2] = {nullptr, nullptr}, *fuy[2] = {nullptr, nullptr};
+    float *fvx = nullptr, *fvy = nullptr, *fminv = nullptr, *fgc = nullptr, *farea = nullptr;
+    float *ffext = nullptr, *fv0 = nullptr;
     uint8_t *dvmask = nullptr, *dsplit = nullptr;
     Control *dctl = nullptr;
     Slot *dslots = nullptr;
@@ -241,9 +247,20 @@ void release_device(mct_ctx *c) {
     for (int i = 0; i < 2; ++i) {
         dfree(c->dux[i]);
         dfree(c->duy[i]);
+        dfree(c->fux[i]);
+        dfree(c->fuy[i]);
     }
     dfree(c->dvx);
     dfree(c->dvy);
+    dfree(c->fX);
+    dfree(c->fY);
+    dfree(c->fvx);
+    dfree(c->fvy);
+    dfree(c->fminv);
+    dfree(c->fgc);
+    dfree(c->farea);
+    dfree(c->ffext);
+    dfree(c->fv0);
     dfree(c->dminv);
     dfree(c->dgc);
     dfree(c->darea);
@@ -348,6 +365,8 @@ std::vector<int2> build_units(const mct_ctx *c, int order) {
     return out;
 }
 
+void refresh_f32(mct_ctx *c);
+
 // (Re)build tile geometry, slot sets, views and work units for the chosen
 // tile shape and order.  Device state is untouched.
 int set_launch_geometry(mct_ctx *c) {
@@ -366,6 +385,7 @@ int set_launch_geometry(mct_ctx *c) {
     dfree(c->dslots);
     HIP_TRY(c, hipMalloc((void **)&c->dslots, 3 * sizeof(Slot) * (size_t)std::max<int64_t>(base, 1)));
     for (Spec &s : c->specs) s.prm.slots = c->dslots + 3 * s.tile_base;
+    refresh_f32(c);
     if (c->batch) {
         std::vector<StepParams> views;
         for (const Spec &s : c->specs) views.push_back(s.prm);
@@ -381,10 +401,81 @@ int set_launch_geometry(mct_ctx *c) {
     return MCT_OK;
 }
 
+// The binary32 view of a plain context: the binary64 view's sizes, tables
+// and control pointers with the binary32 arrays and constants (the binary64
+// set-up values rounded once).
+void refresh_f32(mct_ctx *c) {
+    if (c->precision != 32 || !c->finalized) return;
+    Spec &s = c->specs[0];
+    const StepParams &p = s.prm;
+    mct::StepParamsF &f = s.prmf;
+    f = mct::StepParamsF{};
+    f.nx = p.nx;
+    f.ny = p.ny;
+    f.ntx = p.ntx;
+    f.nty = p.nty;
+    f.nwg = p.nwg;
+    f.log_cap = p.log_cap;
+    f.X = c->fX;
+    f.Y = c->fY;
+    f.ux0 = c->fux[0];
+    f.uy0 = c->fuy[0];
+    f.ux1 = c->fux[1];
+    f.uy1 = c->fuy[1];
+    f.vx = c->fvx;
+    f.vy = c->fvy;
+    f.minv = c->fminv;
+    f.split = p.split;
+    f.area = c->farea;
+    f.screen = nullptr;
+    f.sct = p.sct;
+    f.ncurve = p.ncurve;
+    f.curve_t = p.curve_t;
+    f.curve_phi = p.curve_phi;
+    f.gc = p.gc ? c->fgc : nullptr;
+    f.gc_uniform = (float)p.gc_uniform;
+    f.fext_p = c->ffext;
+    f.vmask_p = p.vmask_p;
+    f.v0_p = c->fv0;
+    f.D11 = (float)p.D11;
+    f.D12 = (float)p.D12;
+    f.D33 = (float)p.D33;
+    f.E = (float)p.E;
+    f.dt = p.dt;
+    f.t_ramp = p.t_ramp;
+    f.dts = (float)p.dt;
+    f.gamma = (float)p.gamma;
+    f.ctl = p.ctl;
+    f.slots = p.slots;
+    f.log = p.log;
+}
+
+// Binary32 contexts: copy the state into its binary64 mirror (exact) before
+// a query reads it, and back after a restore wrote the mirror.
+int widen_state(mct_ctx *c) {
+    if (c->precision != 32 || !c->finalized) return MCT_OK;
+    const int64_t nn = c->specs[0].nn;
+    const float *src[6] = {c->fux[0], c->fuy[0], c->fux[1], c->fuy[1], c->fvx, c->fvy};
+    double *dst[6] = {c->dux[0], c->duy[0], c->dux[1], c->duy[1], c->dvx, c->dvy};
+    HIP_TRY(c, mct::launch_widen(src, dst, 6, nn, c->stream));
+    return MCT_OK;
+}
+
+int narrow_state(mct_ctx *c) {
+    if (c->precision != 32 || !c->finalized) return MCT_OK;
+    const int64_t nn = c->specs[0].nn;
+    const double *src[6] = {c->dux[0], c->duy[0], c->dux[1], c->duy[1], c->dvx, c->dvy};
+    float *dst[6] = {c->fux[0], c->fuy[0], c->fux[1], c->fuy[1], c->fvx, c->fvy};
+    HIP_TRY(c, mct::launch_narrow(src, dst, 6, nn, c->stream));
+    return MCT_OK;
+}
+
 mct::Launch launch_of(const mct_ctx *c) {
     mct::Launch L;
     L.batched = c->batch;
     L.p0 = c->specs[0].prm;
+    L.f32 = c->precision == 32;
+    L.p0f = c->specs[0].prmf;
     L.views = c->dviews;
     L.units = c->dunits;
     L.nunits = c->nunits;
@@ -658,7 +749,8 @@ int start_tip(mct_ctx *c, size_t q, int32_t *tip) {
 int create_ctx(mct_ctx **out, int nspec, bool batch, int precision, void *hip_stream) {
     if (!out) return MCT_EINVAL;
     *out = nullptr;
-    if (precision != 64) return MCT_EUNSUPPORTED;
+    // binary32: plain contexts only
+    if (precision != 64 && !(precision == 32 && !batch)) return MCT_EUNSUPPORTED;
     if (nspec < 1 || nspec > (1 << 20)) return MCT_EINVAL;
     mct_ctx *c = new (std::nothrow) mct_ctx;
     if (!c) return MCT_ENOMEM;
@@ -735,6 +827,7 @@ int mct_set_mesh_tri(mct_ctx *c, int64_t n_nodes, const double *X, const double 
                      const int32_t *conn) {
     if (!c) return MCT_EINVAL;
     if (c->batch) return fail(c, MCT_EUNSUPPORTED, "triangle meshes need a plain context");
+    if (c->precision == 32) return fail(c, MCT_EUNSUPPORTED, "triangle meshes need a binary64 context");
     release_device(c);
     c->specs.assign(1, Spec{});
     c->finalized = false;
@@ -904,6 +997,7 @@ int mct_set_front_pick(mct_ctx *c, double rho) {
     TRI_FWD(c, set_front_pick, rho);
     if (!(rho >= 0)) return fail(c, MCT_EINVAL, "front radius must be >= 0 (0: the global pick)");
     if (c->batch && rho > 0) return fail(c, MCT_EUNSUPPORTED, "the per-front pick needs a plain context");
+    if (c->precision == 32 && rho > 0) return fail(c, MCT_EUNSUPPORTED, "the per-front pick needs binary64");
     Spec &s = cur(c);
     if (!s.nx) return fail(c, MCT_ESTATE, "set the mesh first");
     s.front_rho = rho;
@@ -921,6 +1015,8 @@ int mct_set_smoothing(mct_ctx *c, int mode) {
     }
     if (c->batch && mode == MCT_SMOOTH_SUBCELL)
         return fail(c, MCT_EUNSUPPORTED, "sub-cell smoothing needs a plain context");
+    if (c->precision == 32 && mode == MCT_SMOOTH_SUBCELL)
+        return fail(c, MCT_EUNSUPPORTED, "sub-cell smoothing needs binary64");
     Spec &s = cur(c);
     if (!s.nx) return fail(c, MCT_ESTATE, "set the mesh first");
     s.subcell = mode == MCT_SMOOTH_SUBCELL;
@@ -1077,6 +1173,25 @@ int mct_finalize(mct_ctx *c) {
     HIP_TRY(c, hipMalloc((void **)&c->dvy, sizeof(double) * nn));
     HIP_TRY(c, hipMemsetAsync(c->dvx, 0, sizeof(double) * nn, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->dvy, 0, sizeof(double) * nn, c->stream));
+    if (c->precision == 32) {
+        // the binary32 step's arrays: the binary64 set-up values rounded once
+        auto to_f32 = [](const std::vector<double> &v) { return std::vector<float>(v.begin(), v.end()); };
+        const std::vector<float> fX = to_f32(X), fY = to_f32(Y), fminv = to_f32(minv), ffext = to_f32(fext),
+                                 fv0 = to_f32(v0), farea = to_f32(area_all), fgc = to_f32(gc);
+        if ((rc = upload(c, c->fX, fX))) return rc;
+        if ((rc = upload(c, c->fY, fY))) return rc;
+        if ((rc = upload(c, c->fminv, fminv))) return rc;
+        if ((rc = upload(c, c->ffext, ffext))) return rc;
+        if ((rc = upload(c, c->fv0, fv0))) return rc;
+        if ((rc = upload(c, c->farea, farea))) return rc;
+        if (any_gc && (rc = upload(c, c->fgc, fgc))) return rc;
+        float **zs[6] = {&c->fux[0], &c->fuy[0], &c->fux[1], &c->fuy[1], &c->fvx, &c->fvy};
+        for (float **z : zs) {
+            HIP_TRY(c, hipMalloc((void **)z, sizeof(float) * nn));
+            HIP_TRY(c, hipMemsetAsync(*z, 0, sizeof(float) * nn, c->stream));
+        }
+        HIP_TRY(c, hipStreamSynchronize(c->stream));  // before the host vectors go
+    }
     HIP_TRY(c, hipMalloc((void **)&c->dctl, sizeof(Control) * c->specs.size()));
     {
         std::vector<Control> h0(c->specs.size());
@@ -1150,6 +1265,7 @@ int mct_finalize(mct_ctx *c) {
         p.D33 = s.E / (2.0 * (1.0 + s.nu));
         p.E = s.E;
         p.dt = s.dt;
+        p.dts = s.dt;
         p.t_ramp = s.t_ramp;
         p.gamma = s.gamma;
         p.sct = s.sct;
@@ -1238,6 +1354,7 @@ int mct_sync(mct_ctx *c) {
         for (const Spec &s : c->specs) nn += s.nn;
         const int par = (int)(c->steps_enqueued & 1);
         int32_t flag = 0;
+        if ((rc = widen_state(c))) return rc;
         HIP_TRY(c, hipMemsetAsync(c->dflag, 0, sizeof(int32_t), c->stream));
         HIP_TRY(c, mct::launch_check_finite(c->dux[par], c->duy[par], c->dvx, c->dvy, nn, c->dflag, c->stream));
         HIP_TRY(c, hipMemcpyAsync(&flag, c->dflag, sizeof flag, hipMemcpyDeviceToHost, c->stream));
@@ -1346,9 +1463,10 @@ int mct_get_field(mct_ctx *c, int which, int64_t cap, double *out) {
         default: return fail(c, MCT_EINVAL, "unknown field %d", which);
     }
     if (cap < need) return fail(c, MCT_ECAPACITY, "field needs %lld values", (long long)need);
-    Control h;
-    int rc = read_control(c, c->sel, &h);
+    int rc = widen_state(c);
     if (rc) return rc;
+    Control h;
+    if ((rc = read_control(c, c->sel, &h))) return rc;
     if (which >= MCT_FIELD_A) {
         if ((rc = ensure_eval(c))) return rc;
         const double *ux = (h.base & 1) ? s.prm.ux1 : s.prm.ux0, *uy = (h.base & 1) ? s.prm.uy1 : s.prm.uy0;
@@ -1392,6 +1510,7 @@ int mct_get_energies(mct_ctx *c, double out[4]) {
     int rc = ensure_eval(c);
     if (rc) return rc;
     const Spec &s = cur(c);
+    if ((rc = widen_state(c))) return rc;
     Control h;
     if ((rc = read_control(c, c->sel, &h))) return rc;
     const double *ux = (h.base & 1) ? s.prm.ux1 : s.prm.ux0, *uy = (h.base & 1) ? s.prm.uy1 : s.prm.uy0;
@@ -1447,14 +1566,19 @@ int mct_get_split_codes(mct_ctx *c, int64_t cap, uint8_t *out) {
 }
 
 // checkpoint layout: magic, number of specimens, then per specimen: nodes,
-// elements, Control, u, v (x then y), split codes, log records
-static const uint64_t kMagic = 0x4d43543244434b32ull;  // "MCT2DCK2"
+// elements, Control, u, v (x then y, binary64; a binary32 context's values
+// are exact in them), split codes, log records.  The magic differs by
+// precision, so a state moves only between contexts of one precision.
+static const uint64_t kMagic = 0x4d43543244434b32ull;    // "MCT2DCK2"
+static const uint64_t kMagic32 = 0x4d43543246434b32ull;  // "MCT2FCK2"
 
 int mct_checkpoint(mct_ctx *c, void *buf, int64_t cap, int64_t *bytes) {
     if (!c || !bytes) return MCT_EINVAL;
     TRI_FWD(c, checkpoint, buf, cap, bytes);
     if (!c->finalized) return fail(c, MCT_ESTATE, "finalize first");
     const int S = (int)c->specs.size();
+    int rc = widen_state(c);
+    if (rc) return rc;
     std::vector<Control> h(S);
     HIP_TRY(c, hipMemcpyAsync(h.data(), c->dctl, sizeof(Control) * S, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -1468,7 +1592,7 @@ int mct_checkpoint(mct_ctx *c, void *buf, int64_t cap, int64_t *bytes) {
     if (!buf) return MCT_OK;
     if (cap < need) return fail(c, MCT_ECAPACITY, "checkpoint needs %lld bytes", (long long)need);
     char *p = (char *)buf;
-    const uint64_t hdr[2] = {kMagic, (uint64_t)S};
+    const uint64_t hdr[2] = {c->precision == 32 ? kMagic32 : kMagic, (uint64_t)S};
     std::memcpy(p, hdr, sizeof hdr);
     p += sizeof hdr;
     for (int q = 0; q < S; ++q) {
@@ -1504,7 +1628,8 @@ int mct_restore(mct_ctx *c, const void *buf, int64_t bytes) {
     uint64_t hdr[2];
     std::memcpy(hdr, p, sizeof hdr);
     p += sizeof hdr;
-    if (hdr[0] != kMagic || (int64_t)hdr[1] != S) return fail(c, MCT_EINVAL, "checkpoint does not match this context");
+    if (hdr[0] != (c->precision == 32 ? kMagic32 : kMagic) || (int64_t)hdr[1] != S)
+        return fail(c, MCT_EINVAL, "checkpoint does not match this context (specimens or precision)");
     // validate the whole buffer before touching the device
     const char *q = p;
     std::vector<Control> hs(S);
@@ -1541,6 +1666,7 @@ int mct_restore(mct_ctx *c, const void *buf, int64_t bytes) {
         if (nlog) HIP_TRY(c, hipMemcpyAsync(sp.prm.log, p, sizeof(LogRec) * nlog, hipMemcpyHostToDevice, c->stream));
         p += sizeof(LogRec) * nlog;
     }
+    if (int rc = narrow_state(c)) return rc;
     if (c->screen_alloc) {  // the screen starts afresh from a restored state
         const mct::ScreenDev &sd = c->sd;
         const int64_t ne = c->specs[0].ne;
@@ -1635,6 +1761,7 @@ int mct_screen_collect(mct_ctx *c, int64_t cap, float *features, int32_t *elem, 
                        int64_t *count) {
     if (!c) return MCT_EINVAL;
     TRI_UNSUPPORTED(c, "the split-screen");
+    if (c->precision == 32) return fail(c, MCT_EUNSUPPORTED, "the split-screen needs binary64");
     if (!count || (cap > 0 && (!features || !elem || !entry))) return fail(c, MCT_EINVAL, "null output");
     int rc = ensure_screen(c);
     if (rc) return rc;
@@ -1673,6 +1800,7 @@ int mct_screen_collect(mct_ctx *c, int64_t cap, float *features, int32_t *elem, 
 int mct_screen_enable(mct_ctx *c, const mct_mlp *mlp, float tau, int period) {
     if (!c) return MCT_EINVAL;
     TRI_UNSUPPORTED(c, "the split-screen");
+    if (c->precision == 32) return fail(c, MCT_EUNSUPPORTED, "the split-screen needs binary64");
     if (!mlp) return fail(c, MCT_EINVAL, "null model");
     if (!c->batch && cur(c).front_rho > 0) return fail(c, MCT_EUNSUPPORTED, "the split-screen with the per-front pick");
     if (!c->batch && cur(c).subcell) return fail(c, MCT_EUNSUPPORTED, "the split-screen with sub-cell smoothing");

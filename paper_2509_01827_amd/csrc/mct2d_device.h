@@ -1,5 +1,6 @@
 // Element-level device arithmetic shared by the step and screen kernels
-// (binary64, compiled with -ffp-contract=off; fma only where written).
+// (binary64 or binary32, compiled with -ffp-contract=off; fma only where
+// written).
 #pragma once
 
 #include "mct2d_impl.h"
@@ -13,6 +14,29 @@ __device__ __forceinline__ double eta_n(int n) { return (n >= 2) ? 1.0 : -1.0; }
 __device__ __forceinline__ double xi_m(int k) { return k == 1 ? 1.0 : (k == 3 ? -1.0 : 0.0); }
 __device__ __forceinline__ double eta_m(int k) { return k == 0 ? -1.0 : (k == 2 ? 1.0 : 0.0); }
 
+// Pointer parameters that may receive nullptr take their type from another
+// argument.
+template <class T>
+struct Same {
+    using type = T;
+};
+
+// The helpers below are templates over the arithmetic type T (double for
+// the binary64 step, float for the binary32 step); every constant is a T,
+// so an expression never widens to double.
+
+// Fused multiply-add of one rounding in T.  The overloaded fma can resolve
+// to the binary64 version for float arguments inside a generic lambda, so
+// templated code calls this one.
+template <class T>
+__device__ __forceinline__ T fmat(T a, T b, T c) {
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "float or double");
+    if constexpr (sizeof(T) == 4)
+        return __builtin_fmaf(a, b, c);
+    else
+        return __builtin_fma(a, b, c);
+}
+
 // dN/dx, dN/dy of the bilinear element at the midpoint of its local edge k.
 //
 // The shape-function derivatives in natural coordinates at an edge midpoint
@@ -25,40 +49,41 @@ __device__ __forceinline__ double eta_m(int k) { return k == 0 ? -1.0 : (k == 2 
 //   dN_n/dy = (J11 dN_n/deta - J21 dN_n/dxi) / det J
 // bit for bit.  With k a compile-time constant after unrolling, the zero
 // tests fold away.
-__device__ __forceinline__ double exact_dot4(const double c[4], const double v[4]) {
-    double s = 0.0;
+template <class T>
+__device__ __forceinline__ T exact_dot4(const T c[4], const T v[4]) {
+    T s = T(0);
     bool first = true;
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
-        if (c[n] != 0.0) {
-            s = first ? c[n] * v[n] : fma(c[n], v[n], s);
+        if (c[n] != T(0)) {
+            s = first ? c[n] * v[n] : fmat(c[n], v[n], s);
             first = false;
         }
     }
     return s;
 }
 
-__device__ __forceinline__ void q4_grad(const double x[4], const double y[4], int k, double dndx[4],
-                                        double dndy[4]) {
-    double dxi[4], deta[4];
+template <class T>
+__device__ __forceinline__ void q4_grad(const T x[4], const T y[4], int k, T dndx[4], T dndy[4]) {
+    T dxi[4], deta[4];
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
-        dxi[n] = 0.25 * xi_n(n) * (1.0 + eta_m(k) * eta_n(n));
-        deta[n] = 0.25 * eta_n(n) * (1.0 + xi_m(k) * xi_n(n));
+        dxi[n] = T(0.25) * T(xi_n(n)) * (T(1) + T(eta_m(k)) * T(eta_n(n)));
+        deta[n] = T(0.25) * T(eta_n(n)) * (T(1) + T(xi_m(k)) * T(xi_n(n)));
     }
-    const double j11 = exact_dot4(dxi, x);
-    const double j12 = exact_dot4(dxi, y);
-    const double j21 = exact_dot4(deta, x);
-    const double j22 = exact_dot4(deta, y);
-    const double det = j11 * j22 - j12 * j21;
-    const double inv = 1.0 / det;
+    const T j11 = exact_dot4(dxi, x);
+    const T j12 = exact_dot4(dxi, y);
+    const T j21 = exact_dot4(deta, x);
+    const T j22 = exact_dot4(deta, y);
+    const T det = j11 * j22 - j12 * j21;
+    const T inv = T(1) / det;
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
-        double a, b;
-        if (dxi[n] != 0.0 && deta[n] != 0.0) {
-            a = fma(j22, dxi[n], -(j12 * deta[n]));
-            b = fma(j11, deta[n], -(j21 * dxi[n]));
-        } else if (dxi[n] != 0.0) {
+        T a, b;
+        if (dxi[n] != T(0) && deta[n] != T(0)) {
+            a = fmat(j22, dxi[n], -(j12 * deta[n]));
+            b = fmat(j11, deta[n], -(j21 * dxi[n]));
+        } else if (dxi[n] != T(0)) {
             a = j22 * dxi[n];
             b = -(j21 * dxi[n]);
         } else {
@@ -71,8 +96,8 @@ __device__ __forceinline__ void q4_grad(const double x[4], const double y[4], in
 }
 
 // q4_grad with the edge index as a template argument (for runtime k).
-__device__ __forceinline__ void q4_grad_rt(const double x[4], const double y[4], int k, double dndx[4],
-                                           double dndy[4]) {
+template <class T>
+__device__ __forceinline__ void q4_grad_rt(const T x[4], const T y[4], int k, T dndx[4], T dndy[4]) {
     switch (k) {
         case 0: q4_grad(x, y, 0, dndx, dndy); break;
         case 1: q4_grad(x, y, 1, dndx, dndy); break;
@@ -86,15 +111,16 @@ __device__ __forceinline__ void q4_grad_rt(const double x[4], const double y[4],
 // nodal displacements.  Gradients b (d/dx), c (d/dy) of the triangle's
 // linear shape functions in corner order (n_k, n_k+1, c), the strain of
 // its corner displacements, and its area (returned).
-template <int K>
-__device__ __forceinline__ double subcell(const double x[4], const double y[4], const double ux[4],
-                                          const double uy[4], double b[3], double c[3], double q[3]) {
+template <int K, class T>
+__device__ __forceinline__ T subcell(const T x[4], const T y[4], const typename Same<T>::type *ux,
+                                     const typename Same<T>::type *uy, T b[3], T c[3],
+                                     typename Same<T>::type *q) {
     constexpr int K1 = (K + 1) & 3;
-    const double xa = x[K], ya = y[K], xb = x[K1], yb = y[K1];
-    const double xc = 0.25 * (((x[0] + x[1]) + x[2]) + x[3]);
-    const double yc = 0.25 * (((y[0] + y[1]) + y[2]) + y[3]);
-    const double twoA = (xb - xa) * (yc - ya) - (xc - xa) * (yb - ya);
-    const double inv = 1.0 / twoA;
+    const T xa = x[K], ya = y[K], xb = x[K1], yb = y[K1];
+    const T xc = T(0.25) * (((x[0] + x[1]) + x[2]) + x[3]);
+    const T yc = T(0.25) * (((y[0] + y[1]) + y[2]) + y[3]);
+    const T twoA = (xb - xa) * (yc - ya) - (xc - xa) * (yb - ya);
+    const T inv = T(1) / twoA;
     b[0] = (yb - yc) * inv;
     b[1] = (yc - ya) * inv;
     b[2] = (ya - yb) * inv;
@@ -102,26 +128,28 @@ __device__ __forceinline__ double subcell(const double x[4], const double y[4], 
     c[1] = (xa - xc) * inv;
     c[2] = (xb - xa) * inv;
     if (ux) {
-        const double pu[3] = {ux[K], ux[K1], 0.25 * (((ux[0] + ux[1]) + ux[2]) + ux[3])};
-        const double pv[3] = {uy[K], uy[K1], 0.25 * (((uy[0] + uy[1]) + uy[2]) + uy[3])};
-        double exx = 0.0, eyy = 0.0, gxy = 0.0;
+        const T pu[3] = {ux[K], ux[K1], T(0.25) * (((ux[0] + ux[1]) + ux[2]) + ux[3])};
+        const T pv[3] = {uy[K], uy[K1], T(0.25) * (((uy[0] + uy[1]) + uy[2]) + uy[3])};
+        T exx = T(0), eyy = T(0), gxy = T(0);
 #pragma unroll
         for (int n = 0; n < 3; ++n) {
-            exx = fma(b[n], pu[n], exx);
-            eyy = fma(c[n], pv[n], eyy);
-            gxy = fma(c[n], pu[n], gxy);
-            gxy = fma(b[n], pv[n], gxy);
+            exx = fmat(b[n], pu[n], exx);
+            eyy = fmat(c[n], pv[n], eyy);
+            gxy = fmat(c[n], pu[n], gxy);
+            gxy = fmat(b[n], pv[n], gxy);
         }
         q[0] = exx;
         q[1] = eyy;
         q[2] = gxy;
     }
-    return 0.5 * twoA;
+    return T(0.5) * twoA;
 }
 
 // subcell with the edge index at run time
-__device__ __forceinline__ double subcell_rt(const double x[4], const double y[4], const double ux[4],
-                                             const double uy[4], int k, double b[3], double c[3], double q[3]) {
+template <class T>
+__device__ __forceinline__ T subcell_rt(const T x[4], const T y[4], const typename Same<T>::type *ux,
+                                        const typename Same<T>::type *uy, int k, T b[3], T c[3],
+                                        typename Same<T>::type *q) {
     switch (k) {
         case 0: return subcell<0>(x, y, ux, uy, b, c, q);
         case 1: return subcell<1>(x, y, ux, uy, b, c, q);
@@ -134,28 +162,29 @@ __device__ __forceinline__ double subcell_rt(const double x[4], const double y[4
 // k of A_T B_T^T sigma_k, the centroid corner's share a quarter to each
 // node; per node and edge the bracket t_a + t_c/4 (node k), t_b + t_c/4
 // (node k+1) or t_c/4, scaled by A_T, summed over k = 0..3 in order.
-__device__ __forceinline__ void subcell_force(const double bb[4][3], const double cb[4][3], const double AT[4],
-                                              const double sig[4][3], double fe[8]) {
+template <class T>
+__device__ __forceinline__ void subcell_force(const T bb[4][3], const T cb[4][3], const T AT[4],
+                                              const T sig[4][3], T fe[8]) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const double s0 = sig[k][0], s1 = sig[k][1], s2 = sig[k][2];
-        double tx[3], ty[3];
+        const T s0 = sig[k][0], s1 = sig[k][1], s2 = sig[k][2];
+        T tx[3], ty[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            tx[i] = fma(cb[k][i], s2, bb[k][i] * s0);
-            ty[i] = fma(bb[k][i], s2, cb[k][i] * s1);
+            tx[i] = fmat(cb[k][i], s2, bb[k][i] * s0);
+            ty[i] = fmat(bb[k][i], s2, cb[k][i] * s1);
         }
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
-            double gx = 0.25 * tx[2], gy = 0.25 * ty[2];
+            T gx = T(0.25) * tx[2], gy = T(0.25) * ty[2];
             if (n == k) {
-                gx = tx[0] + 0.25 * tx[2];
-                gy = ty[0] + 0.25 * ty[2];
+                gx = tx[0] + T(0.25) * tx[2];
+                gy = ty[0] + T(0.25) * ty[2];
             } else if (n == ((k + 1) & 3)) {
-                gx = tx[1] + 0.25 * tx[2];
-                gy = ty[1] + 0.25 * ty[2];
+                gx = tx[1] + T(0.25) * tx[2];
+                gy = ty[1] + T(0.25) * ty[2];
             }
-            const double vx = AT[k] * gx, vy = AT[k] * gy;
+            const T vx = AT[k] * gx, vy = AT[k] * gy;
             if (k == 0) {
                 fe[2 * n] = vx;
                 fe[2 * n + 1] = vy;
@@ -167,25 +196,25 @@ __device__ __forceinline__ void subcell_force(const double bb[4][3], const doubl
     }
 }
 
-template <int NN>
-__device__ __forceinline__ void strain(const double *dndx, const double *dndy, const double *ux,
-                                       const double *uy, double eps[3]) {
-    double exx = 0.0, eyy = 0.0, gxy = 0.0;
+template <int NN, class T>
+__device__ __forceinline__ void strain(const T *dndx, const T *dndy, const T *ux, const T *uy, T eps[3]) {
+    T exx = T(0), eyy = T(0), gxy = T(0);
 #pragma unroll
     for (int n = 0; n < NN; ++n) {
-        exx = fma(dndx[n], ux[n], exx);
-        eyy = fma(dndy[n], uy[n], eyy);
-        gxy = fma(dndy[n], ux[n], gxy);
-        gxy = fma(dndx[n], uy[n], gxy);
+        exx = fmat(dndx[n], ux[n], exx);
+        eyy = fmat(dndy[n], uy[n], eyy);
+        gxy = fmat(dndy[n], ux[n], gxy);
+        gxy = fmat(dndx[n], uy[n], gxy);
     }
     eps[0] = exx;
     eps[1] = eyy;
     eps[2] = gxy;
 }
 
-__device__ __forceinline__ void hooke(const StepParams &p, const double eps[3], double sig[3]) {
-    sig[0] = fma(p.D12, eps[1], p.D11 * eps[0]);
-    sig[1] = fma(p.D12, eps[0], p.D11 * eps[1]);
+template <class T>
+__device__ __forceinline__ void hooke(const StepParamsT<T> &p, const T eps[3], T sig[3]) {
+    sig[0] = fmat(p.D12, eps[1], p.D11 * eps[0]);
+    sig[1] = fmat(p.D12, eps[0], p.D11 * eps[1]);
     sig[2] = p.D33 * eps[2];
 }
 
@@ -193,15 +222,15 @@ __device__ __forceinline__ void hooke(const StepParams &p, const double eps[3], 
 // a (end nodes (xa0, ya0), (xa1, ya1) = n_a, n_{a+1}) to the midpoint of
 // local edge k (end nodes n_k, n_{k+1}), oriented toward node n_{a+1}
 // (reference coordinates).  Uses correctly rounded sqrt and division only.
-__device__ __forceinline__ void path_geom_pts(double xa0, double ya0, double xa1, double ya1, double xk0,
-                                              double yk0, double xk1, double yk1, double &nxo, double &nyo,
-                                              double &len) {
-    const double g0x = 0.5 * (xa0 + xa1), g0y = 0.5 * (ya0 + ya1);
-    const double gkx = 0.5 * (xk0 + xk1), gky = 0.5 * (yk0 + yk1);
-    const double dx = gkx - g0x, dy = gky - g0y;
-    const double L = sqrt(dx * dx + dy * dy);
-    double cx = dy / L, cy = -dx / L;
-    if (cx * (xa1 - g0x) + cy * (ya1 - g0y) < 0.0) {
+template <class T>
+__device__ __forceinline__ void path_geom_pts(T xa0, T ya0, T xa1, T ya1, T xk0, T yk0, T xk1, T yk1, T &nxo,
+                                              T &nyo, T &len) {
+    const T g0x = T(0.5) * (xa0 + xa1), g0y = T(0.5) * (ya0 + ya1);
+    const T gkx = T(0.5) * (xk0 + xk1), gky = T(0.5) * (yk0 + yk1);
+    const T dx = gkx - g0x, dy = gky - g0y;
+    const T L = sqrt(dx * dx + dy * dy);
+    T cx = dy / L, cy = -dx / L;
+    if (cx * (xa1 - g0x) + cy * (ya1 - g0y) < T(0)) {
         cx = -cx;
         cy = -cy;
     }
@@ -210,8 +239,8 @@ __device__ __forceinline__ void path_geom_pts(double xa0, double ya0, double xa1
     len = L;
 }
 
-__device__ __forceinline__ void path_geom(const double x[4], const double y[4], int a, int k, double &nxo,
-                                          double &nyo, double &len) {
+template <class T>
+__device__ __forceinline__ void path_geom(const T x[4], const T y[4], int a, int k, T &nxo, T &nyo, T &len) {
     const int a1 = (a + 1) & 3, k1 = (k + 1) & 3;
     path_geom_pts(x[a], y[a], x[a1], y[a1], x[k], y[k], x[k1], y[k1], nxo, nyo, len);
 }
@@ -270,7 +299,8 @@ __device__ __forceinline__ int64_t edge_v(int64_t i, int64_t j, int nx) {
 
 // Load factor of the tractions at time t: piecewise linear through the
 // curve points, constant beyond its ends, 1 without a curve.
-__device__ __forceinline__ double load_factor(const StepParams &p, double t) {
+template <class T>
+__device__ __forceinline__ double load_factor(const StepParamsT<T> &p, double t) {
     if (p.ncurve == 0) return 1.0;
     if (t <= p.curve_t[0]) return p.curve_phi[0];
     const int n = p.ncurve;

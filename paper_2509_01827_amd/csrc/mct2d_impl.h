@@ -51,29 +51,35 @@ struct Control {
 static_assert(sizeof(Control) == 48, "Control layout");
 
 // One specimen as the kernels see it: sizes, constants and pointers already
-// offset to the specimen's part of the batch arrays.
-struct StepParams {
+// offset to the specimen's part of the batch arrays.  T is the arithmetic
+// and storage type of the step (double, or float for the binary32 step,
+// whose set-up values are the binary64 ones rounded once); times, the load
+// curve, the log, U_d and the pick variant's buffers stay binary64.
+template <class T>
+struct StepParamsT {
     int32_t nx, ny;     // elements per direction
     int32_t ntx, nty;   // tiles per direction
     int32_t nwg;        // ntx * nty (also the stride of the three slot sets)
     int32_t log_cap;
-    const double *X, *Y;
-    double *ux0, *uy0, *ux1, *uy1;  // displacement ping-pong, u^k in (k & 1)
-    double *vx, *vy;
-    const double *minv;
+    const T *X, *Y;
+    T *ux0, *uy0, *ux1, *uy1;  // displacement ping-pong, u^k in (k & 1)
+    T *vx, *vy;
+    const T *minv;
     uint8_t *split;
-    const double *area;  // per element (reference configuration)
+    const T *area;  // per element (reference configuration)
     const uint32_t *screen;  // per element, byte a = screen state of candidate (e, a); null = no screen
     int32_t sct;             // 1: single crack-tip tracking (only the tip is a candidate)
     int32_t ncurve;          // traction load curve points (0: constant tractions)
     const double *curve_t, *curve_phi;
-    const double *gc;   // per element, or nullptr for gc_uniform
-    double gc_uniform;
-    const double *fext_p;     // 2 per perimeter node
+    const T *gc;   // per element, or nullptr for gc_uniform
+    T gc_uniform;
+    const T *fext_p;          // 2 per perimeter node
     const uint8_t *vmask_p;   // 1 per perimeter node
-    const double *v0_p;       // 2 per perimeter node
-    double D11, D12, D33, E;
-    double dt, t_ramp, gamma;
+    const T *v0_p;            // 2 per perimeter node
+    T D11, D12, D33, E;
+    double dt, t_ramp;  // time step (for times t_k) and velocity ramp
+    T dts;              // time step of the update (dt rounded to T)
+    T gamma;
     Control *ctl;
     Slot *slots;        // 3 sets of nwg slots
     LogRec *log;
@@ -93,6 +99,8 @@ struct StepParams {
     int32_t *fbucket, *fsorted, *fplist;
     double fcell;  // hash cell of the pick: >= rho and the largest element diameter
 };
+using StepParams = StepParamsT<double>;
+using StepParamsF = StepParamsT<float>;
 
 // Tile shapes (elements per workgroup in x and y; nodes owned = one less).
 struct TileShape {
@@ -103,12 +111,15 @@ TileShape tile_shape(int tile);  // tile in 1..kNumTiles
 
 // What one step launch covers: a single specimen (p0, nwg tiles) or a batch
 // (nunits work units (specimen, tile) over nspec device-resident views).
+// f32: a single binary32 specimen, p0f (p0 holds its binary64 mirror).
 struct Launch {
     bool batched;
     StepParams p0;
     const StepParams *views;
     const int2 *units;
     int nunits, nspec;
+    bool f32;
+    StepParamsF p0f;
 };
 
 // One step of a segment (k_rel = index in the segment, par0 = parity of the
@@ -149,6 +160,10 @@ hipError_t launch_power_step(const StepParams &p, const EvalDev &d, double *y, d
                              double *scratch2, double *sums, hipStream_t st);
 hipError_t launch_check_finite(const double *a, const double *b, const double *c, const double *d, int64_t n,
                                int32_t *flag, hipStream_t st);
+// Binary32 state <-> its binary64 mirror (n values each of up to 6 arrays;
+// widening is exact, narrowing rounds to nearest).
+hipError_t launch_widen(const float *const src[6], double *const dst[6], int count, int64_t n, hipStream_t st);
+hipError_t launch_narrow(const double *const src[6], float *const dst[6], int count, int64_t n, hipStream_t st);
 
 // ---------------------------------------------------------------------
 // Learned split-screen.

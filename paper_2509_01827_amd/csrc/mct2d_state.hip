@@ -379,6 +379,19 @@ __global__ __launch_bounds__(kB) void k_check_finite(const double *a, const doub
 
 int nb_of(int64_t n) { return (int)std::max<int64_t>(1, (n + kB - 1) / kB); }
 
+// Up to six arrays of n values converted between binary32 and binary64.
+struct Arrays6 {
+    const void *src[6];
+    void *dst[6];
+};
+
+template <class S, class D>
+__global__ __launch_bounds__(kB) void k_convert(Arrays6 a, int count, int64_t n) {
+    for (int64_t t = (int64_t)blockIdx.x * kB + threadIdx.x; t < n; t += (int64_t)gridDim.x * kB)
+        for (int q = 0; q < count; ++q)
+            static_cast<D *>(a.dst[q])[t] = (D) static_cast<const S *>(a.src[q])[t];
+}
+
 hipError_t sum_into(const double *x, int64_t n, int stride, int off, double *part, double *out, hipStream_t st) {
     k_partial_sum<<<kSumBlocks, kB, 0, st>>>(x, n, stride, off, part);
     k_final_sum<<<1, 64, 0, st>>>(part, kSumBlocks, out);
@@ -443,6 +456,32 @@ hipError_t launch_check_finite(const double *a, const double *b, const double *c
     (void)hipGetLastError();
     const int nb = (int)std::min<int64_t>(nb_of(n), 2048);
     k_check_finite<<<nb, kB, 0, st>>>(a, b, c, d4, n, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_widen(const float *const src[6], double *const dst[6], int count, int64_t n, hipStream_t st) {
+    (void)hipGetLastError();
+    if (count < 1 || count > 6) return hipErrorInvalidValue;
+    Arrays6 a{};
+    for (int q = 0; q < count; ++q) {
+        a.src[q] = src[q];
+        a.dst[q] = dst[q];
+    }
+    const int nb = (int)std::min<int64_t>(nb_of(n), 2048);
+    k_convert<float, double><<<nb, kB, 0, st>>>(a, count, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_narrow(const double *const src[6], float *const dst[6], int count, int64_t n, hipStream_t st) {
+    (void)hipGetLastError();
+    if (count < 1 || count > 6) return hipErrorInvalidValue;
+    Arrays6 a{};
+    for (int q = 0; q < count; ++q) {
+        a.src[q] = src[q];
+        a.dst[q] = dst[q];
+    }
+    const int nb = (int)std::min<int64_t>(nb_of(n), 2048);
+    k_convert<double, float><<<nb, kB, 0, st>>>(a, count, n);
     return hipGetLastError();
 }
 

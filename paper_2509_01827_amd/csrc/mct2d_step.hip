@@ -23,9 +23,10 @@
 //      (Sec. 3) to its staged split codes; workgroup 0 records the split.
 //      k_commit does the same for the last step of a launch segment.
 //
-// Arithmetic follows one fixed expression order (binary64, compiled with
-// -ffp-contract=off; fma only where written), so the result does not depend
-// on the tile shape or on the schedule.
+// Arithmetic follows one fixed expression order (binary64, or binary32 for
+// the binary32 step: every value of the step in T, times and the load curve
+// in binary64; compiled with -ffp-contract=off; fma only where written), so
+// the result does not depend on the tile shape or on the schedule.
 #include "mct2d_device.h"
 #include "mct2d_impl.h"
 #include "mct2d_front.h"
@@ -38,24 +39,29 @@ namespace {
 using namespace dev;
 
 // Best-candidate order: larger G, then smaller element id, then smaller a.
-__device__ __forceinline__ bool better(double g1, int e1, int a1, double g2, int e2, int a2) {
+template <class T>
+__device__ __forceinline__ bool better(T g1, int e1, int a1, T g2, int e2, int a2) {
     return g1 > g2 || (g1 == g2 && (e1 < e2 || (e1 == e2 && a1 < a2)));
 }
 
-struct Cand {
-    double G, Gmin;
+template <class T>
+struct CandT {
+    T G, Gmin;
     int e, a, k;
 };
+using Cand = CandT<double>;
 
-__device__ __forceinline__ void cand_none(Cand &c) {
-    c.G = -1.0;
-    c.Gmin = __builtin_inf();
+template <class T>
+__device__ __forceinline__ void cand_none(CandT<T> &c) {
+    c.G = T(-1);
+    c.Gmin = T(__builtin_inff());
     c.e = INT_MAX;
     c.a = 4;
     c.k = 0;
 }
 
-__device__ __forceinline__ void cand_merge(Cand &c, double G, double Gmin, int e, int a, int k) {
+template <class T>
+__device__ __forceinline__ void cand_merge(CandT<T> &c, T G, T Gmin, int e, int a, int k) {
     if (better(G, e, a, c.G, c.e, c.a)) {
         c.G = G;
         c.e = e;
@@ -65,11 +71,12 @@ __device__ __forceinline__ void cand_merge(Cand &c, double G, double Gmin, int e
     if (Gmin < c.Gmin) c.Gmin = Gmin;
 }
 
-__device__ __forceinline__ void cand_wave_reduce(Cand &c) {
+template <class T>
+__device__ __forceinline__ void cand_wave_reduce(CandT<T> &c) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
-        double G = __shfl_xor(c.G, off, 64);
-        double Gm = __shfl_xor(c.Gmin, off, 64);
+        T G = __shfl_xor(c.G, off, 64);
+        T Gm = __shfl_xor(c.Gmin, off, 64);
         int e = __shfl_xor(c.e, off, 64);
         int a = __shfl_xor(c.a, off, 64);
         int k = __shfl_xor(c.k, off, 64);
@@ -78,8 +85,8 @@ __device__ __forceinline__ void cand_wave_reduce(Cand &c) {
 }
 
 // Workgroup-wide reduction; the result is valid in thread 0.
-template <int NT>
-__device__ __forceinline__ void cand_block_reduce(Cand &c, Cand *red) {
+template <int NT, class T>
+__device__ __forceinline__ void cand_block_reduce(CandT<T> &c, CandT<T> *red) {
     cand_wave_reduce(c);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) red[wave] = c;
@@ -89,8 +96,11 @@ __device__ __forceinline__ void cand_block_reduce(Cand &c, Cand *red) {
     }
 }
 
-__device__ __forceinline__ double prescribed(double v0, double t, double t_ramp) {
-    if (t_ramp > 0.0 && t < t_ramp) return v0 * (t / t_ramp);
+// Prescribed velocity at time t: v0 times the ramp factor t / t_ramp
+// (evaluated in binary64 and rounded to T) while t < t_ramp.
+template <class T>
+__device__ __forceinline__ T prescribed(T v0, double t, double t_ramp) {
+    if (t_ramp > 0.0 && t < t_ramp) return v0 * T(t / t_ramp);
     return v0;
 }
 
@@ -115,14 +125,15 @@ __device__ __forceinline__ int xcd_tile(int b, int nwg) {
 
 // Reduce the candidates published in slot set `set` with the whole
 // workgroup; thread 0 receives the result.  Every thread must call it.
-template <int NT>
-__device__ __forceinline__ Cand reduce_slots(const StepParams &p, int set, uint32_t n, Cand *red) {
+// Slots hold binary64 values; a binary32 step's values are exact in them.
+template <int NT, class T>
+__device__ __forceinline__ CandT<T> reduce_slots(const StepParamsT<T> &p, int set, uint32_t n, CandT<T> *red) {
     const Slot *sl = p.slots + (size_t)set * p.nwg;
-    Cand g;
+    CandT<T> g;
     cand_none(g);
     for (uint32_t s = threadIdx.x; s < n; s += NT) {
         const Slot x = sl[s];
-        cand_merge(g, x.G, x.Gmin, x.elem, x.a, x.k);
+        cand_merge(g, T(x.G), T(x.Gmin), x.elem, x.a, x.k);
     }
     cand_block_reduce<NT>(g, red);
     return g;
@@ -131,13 +142,16 @@ __device__ __forceinline__ Cand reduce_slots(const StepParams &p, int set, uint3
 // MCT pick: the largest G must pass G* > gamma (G* - G_c) against every other
 // accepted candidate; (G* - G_c) grows as G_c shrinks and rounding is
 // monotone, so the smallest accepted G decides.
-__device__ __forceinline__ bool pick_accepted(const StepParams &p, const Cand &g) {
-    return g.G >= 0.0 && g.G > p.gamma * (g.G - g.Gmin);
+template <class T>
+__device__ __forceinline__ bool pick_accepted(const StepParamsT<T> &p, const CandT<T> &g) {
+    return g.G >= T(0) && g.G > p.gamma * (g.G - g.Gmin);
 }
 
 // Split the picked element (acts from the next step), log it and add
-// Gc * crack-path length to U_d.  One thread of one workgroup.
-__device__ __forceinline__ void apply_split(const StepParams &p, const Cand &g, int64_t kdecided) {
+// Gc * crack-path length (a T product, accumulated in binary64) to U_d.
+// One thread of one workgroup.
+template <class T>
+__device__ __forceinline__ void apply_split(const StepParamsT<T> &p, const CandT<T> &g, int64_t kdecided) {
     Control *ctl = p.ctl;
     p.split[g.e] = (uint8_t)(kSplitFlag | (g.a << 2) | g.k);
     const int64_t n = ctl->nsplit;
@@ -149,7 +163,7 @@ __device__ __forceinline__ void apply_split(const StepParams &p, const Cand &g, 
         r.exit = (uint8_t)g.k;
         r.pad0 = r.pad1 = 0;
         r.pad2 = 0;
-        r.G = g.G;
+        r.G = (double)g.G;
         p.log[n] = r;
     } else {
         ctl->overflow = 1;
@@ -158,21 +172,22 @@ __device__ __forceinline__ void apply_split(const StepParams &p, const Cand &g, 
     const int64_t i = g.e % p.nx, j = g.e / p.nx;
     const int64_t n0 = j * (p.nx + 1) + i;
     const int64_t nd[4] = {n0, n0 + 1, n0 + p.nx + 2, n0 + p.nx + 1};
-    double x[4], y[4];
+    T x[4], y[4];
     for (int q = 0; q < 4; ++q) {
         x[q] = p.X[nd[q]];
         y[q] = p.Y[nd[q]];
     }
-    double cx, cy, L;
+    T cx, cy, L;
     path_geom(x, y, g.a, g.k, cx, cy, L);
-    const double gc = p.gc ? p.gc[g.e] : p.gc_uniform;
-    ctl->Ud = ctl->Ud + gc * L;
+    const T gc = p.gc ? p.gc[g.e] : p.gc_uniform;
+    ctl->Ud = ctl->Ud + (double)(gc * L);
 }
 
 // Single-tip mode: the tip after element g.e split with exit edge g.k is
 // the same edge seen from the element across it, if that element exists
 // and is intact (the only split of a step is g.e's own).
-__device__ __forceinline__ int32_t tip_after(const StepParams &p, const Cand &g) {
+template <class T>
+__device__ __forceinline__ int32_t tip_after(const StepParamsT<T> &p, const CandT<T> &g) {
     const int i = g.e % p.nx, j = g.e / p.nx;
     const int ni = (g.k == 1) ? i + 1 : (g.k == 3) ? i - 1 : i;
     const int nj = (g.k == 2) ? j + 1 : (g.k == 0) ? j - 1 : j;
@@ -193,9 +208,9 @@ __device__ __forceinline__ int32_t tip_after(const StepParams &p, const Cand &g)
 // unit b = (specimen, tile) comes from `units` and the specimen's view (its
 // sizes, constants and pre-offset pointers) from `views`.  Otherwise the one
 // view `p0` is passed by value and workgroups map to tiles XCD-banded.
-template <int TXE, int TYE, bool BATCHED, bool SC = false>
-__global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepParams *views, const int2 *units,
-                                                   int k_rel, int par0) {
+template <class T, int TXE, int TYE, bool BATCHED, bool SC = false>
+__global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParamsT<T> p0, const StepParamsT<T> *views,
+                                                   const int2 *units, int k_rel, int par0) {
     constexpr int NT = TXE * TYE;
     constexpr int TX = TXE - 1, TY = TYE - 1;  // owned nodes
     constexpr int HX = TXE + 3, HY = TYE + 3;  // staged nodes
@@ -209,25 +224,25 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
     // SC (sub-cell smoothing): a fourth component holds the lower-id side's
     // sub-cell area
     constexpr int NQ = ((SC ? 4 : 3) * NS > 8 * NT) ? (SC ? 4 : 3) * NS : 8 * NT;
-    __shared__ double s_ux[HX * HY], s_uy[HX * HY], s_X[HX * HY], s_Y[HX * HY];
+    __shared__ T s_ux[HX * HY], s_uy[HX * HY], s_X[HX * HY], s_Y[HX * HY];
     // per edge and component (stride NS): first the strain part of the
     // lower-id element, then the smoothed stress; after the force phase the
     // same memory holds the element forces [8][NT]
-    __shared__ double s_e[NQ];
-    __shared__ double s_area[EX * EY];
-    double *const s_fe = s_e;
+    __shared__ T s_e[NQ];
+    __shared__ T s_area[EX * EY];
+    T *const s_fe = s_e;
     __shared__ uint8_t s_split[EX * EY];
     __shared__ uint16_t s_cand[4 * TX * TY];
     __shared__ uint16_t s_splitl[NT];
     __shared__ int s_ncand, s_ncorner, s_nthru;
     __shared__ int32_t s_tip;
-    __shared__ double s_phi;
+    __shared__ T s_phi;
     __shared__ int s_wbase[NT / 64], s_wbase2[NT / 64], s_wbase3[NT / 64];
-    __shared__ Cand s_red[NT / 64];
+    __shared__ CandT<T> s_red[NT / 64];
 
     const int tid = threadIdx.x;
     int tile;
-    StepParams p;
+    StepParamsT<T> p;
     if constexpr (BATCHED) {
         const int2 u = units[blockIdx.x];
         p = views[u.x];
@@ -240,10 +255,10 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
     const int nx = p.nx, ny = p.ny;
     const int i0 = (tile % p.ntx) * TX, j0 = (tile / p.ntx) * TY;
     const int par = (par0 + k_rel) & 1;
-    const double *ux_c = par ? p.ux1 : p.ux0;
-    const double *uy_c = par ? p.uy1 : p.uy0;
-    double *ux_n = par ? p.ux0 : p.ux1;
-    double *uy_n = par ? p.uy0 : p.uy1;
+    const T *ux_c = par ? p.ux1 : p.ux0;
+    const T *uy_c = par ? p.uy1 : p.uy0;
+    T *ux_n = par ? p.ux0 : p.ux1;
+    T *uy_n = par ? p.uy0 : p.uy1;
     const int set_w = k_rel % 3, set_r = (k_rel + 2) % 3, set_c = (k_rel + 1) % 3;
     const int64_t base = p.ctl->base;  // needed late (time, first step, log)
     // single-tip mode: the tip at the start of the previous step (slot by parity)
@@ -255,12 +270,12 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
     constexpr int NHALO = HX * HY, RH = (NHALO + NT - 1) / NT;
     constexpr int NE2 = EX * EY, RE = (NE2 + NT - 1) / NT;
     const uint32_t nprev = p.ctl->nslots[set_r];
-    double ra[RH], rb[RH], rc[RH], rd[RH];
+    T ra[RH], rb[RH], rc[RH], rd[RH];
 #pragma unroll
     for (int r = 0; r < RH; ++r) {
         const int idx = tid + r * NT;
         const int gi = i0 - 2 + idx % HX, gj = j0 - 2 + idx / HX;
-        ra[r] = rb[r] = rc[r] = rd[r] = 0.0;
+        ra[r] = rb[r] = rc[r] = rd[r] = T(0);
         if (idx < NHALO && gi >= 0 && gi <= nx && gj >= 0 && gj <= ny) {
             const int64_t n = (int64_t)gj * (nx + 1) + gi;
             ra[r] = ux_c[n];
@@ -270,13 +285,13 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
         }
     }
     uint8_t rs[RE];
-    double rarea[RE];
+    T rarea[RE];
 #pragma unroll
     for (int r = 0; r < RE; ++r) {
         const int idx = tid + r * NT;
         const int gi = i0 - 2 + idx % EX, gj = j0 - 2 + idx / EX;
         rs[r] = kAbsent;
-        rarea[r] = 0.0;
+        rarea[r] = T(0);
         if (idx < NE2 && gi >= 0 && gi < nx && gj >= 0 && gj < ny) {
             const int64_t e = (int64_t)gj * nx + gi;
             rs[r] = p.split[e];
@@ -317,12 +332,12 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
         s_ncorner = 0;
         s_nthru = 0;
         s_tip = tip_prev;
-        s_phi = load_factor(p, (double)(base + k_rel) * p.dt);  // traction factor at t_k
+        s_phi = T(load_factor(p, (double)(base + k_rel) * p.dt));  // traction factor at t_k
     }
 
     // ---- 2. the pick of the previous step -------------------------------
     if (nprev > 0) {  // uniform over the workgroup
-        const Cand g = reduce_slots<NT>(p, set_r, nprev, s_red);  // contains a barrier
+        const CandT<T> g = reduce_slots<NT>(p, set_r, nprev, s_red);  // contains a barrier
         if (tid == 0 && pick_accepted(p, g)) {
             const int fx = g.e % nx - (i0 - 2), fy = g.e / nx - (j0 - 2);
             if (fx >= 0 && fx < EX && fy >= 0 && fy < EY)
@@ -342,7 +357,7 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
     }
     __syncthreads();
 
-    auto elem_xy = [&](int ex, int ey, double x[4], double y[4]) {
+    auto elem_xy = [&](int ex, int ey, T x[4], T y[4]) {
         const int b = ey * HX + ex;
         x[0] = s_X[b];
         x[1] = s_X[b + 1];
@@ -353,7 +368,7 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
         y[2] = s_Y[b + HX + 1];
         y[3] = s_Y[b + HX];
     };
-    auto elem_u = [&](int ex, int ey, double ux[4], double uy[4]) {
+    auto elem_u = [&](int ex, int ey, T ux[4], T uy[4]) {
         const int b = ey * HX + ex;
         ux[0] = s_ux[b];
         ux[1] = s_ux[b + 1];
@@ -398,14 +413,14 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
     const uint8_t code = s_split[e2];
     auto nbr = [&](int e, int k) { return (k == 0) ? e - EX : (k == 1) ? e + 1 : (k == 2) ? e + EX : e - 1; };
     // stage A, lower-id element e (area A; SC: sub-cell area) at its edge k = 1 or 2
-    auto lo_part = [&](int e, double A, int k, int sid, const double q[3]) {
+    auto lo_part = [&](int e, T A, int k, int sid, const T q[3]) {
         const int nb = nbr(e, k);
         if constexpr (SC) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) s_e[c * NS + sid] = q[c];
             s_e[3 * NS + sid] = A;
         } else if (s_split[nb] == 0) {
-            const double w0 = A / (A + s_area[nb]);
+            const T w0 = A / (A + s_area[nb]);
 #pragma unroll
             for (int c = 0; c < 3; ++c) s_e[c * NS + sid] = w0 * q[c];
         } else {
@@ -414,20 +429,20 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
         }
     };
     // stage B, intact higher-id element e (area A; SC: sub-cell area) at its edge k = 0 or 3
-    auto hi_sigma = [&](int e, double A, int k, int sid, const double q[3]) {
+    auto hi_sigma = [&](int e, T A, int k, int sid, const T q[3]) {
         const int nb = nbr(e, k);
-        double eps[3], sg[3];
+        T eps[3], sg[3];
         if (s_split[nb] == 0) {
             if constexpr (SC) {
-                const double Alo = s_e[3 * NS + sid];
-                const double sum = Alo + A;
-                const double w0 = Alo / sum, w1 = A / sum;
+                const T Alo = s_e[3 * NS + sid];
+                const T sum = Alo + A;
+                const T w0 = Alo / sum, w1 = A / sum;
 #pragma unroll
-                for (int c = 0; c < 3; ++c) eps[c] = fma(w1, q[c], w0 * s_e[c * NS + sid]);
+                for (int c = 0; c < 3; ++c) eps[c] = fmat(w1, q[c], w0 * s_e[c * NS + sid]);
             } else {
-                const double w1 = A / (s_area[nb] + A);
+                const T w1 = A / (s_area[nb] + A);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) eps[c] = fma(w1, q[c], s_e[c * NS + sid]);
+                for (int c = 0; c < 3; ++c) eps[c] = fmat(w1, q[c], s_e[c * NS + sid]);
             }
         } else {
 #pragma unroll
@@ -440,7 +455,7 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
     // stage B, lower-id element e at its edge k = 1 or 2 when the other side is not intact
     auto lo_sigma = [&](int e, int k, int sid) {
         if (s_split[nbr(e, k)] != 0) {
-            double eps[3], sg[3];
+            T eps[3], sg[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) eps[c] = s_e[c * NS + sid];
             hooke(p, eps, sg);
@@ -450,17 +465,17 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
     };
     // point rule: Q4 gradients at the edge midpoints; SC: sub-cell
     // gradients (gx[k][0..2], gy[k][0..2]) and areas at[k]
-    double gx[4][4], gy[4][4], at[4];
-    double qh0[3], qh3[3];
-    const double my_area = s_area[e2];
+    T gx[4][4], gy[4][4], at[4];
+    T qh0[3], qh3[3];
+    const T my_area = s_area[e2];
     if (code == 0) {
-        double x[4], y[4];
+        T x[4], y[4];
         elem_xy(ex, ey, x, y);
-        double ux[4], uy[4];
+        T ux[4], uy[4];
         elem_u(ex, ey, ux, uy);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            double q[3];
+            T q[3];
             if constexpr (SC) {
                 switch (k) {
                     case 0: at[0] = subcell<0>(x, y, ux, uy, gx[0], gy[0], q); break;
@@ -489,8 +504,8 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
     const int og = tid >> 6, orr = tid & 63;
     int ore = 0, ork = 0, osid = 0;
     bool oin = false;
-    double oq[3] = {0.0, 0.0, 0.0};
-    double oat = 0.0;  // SC: the outer element's sub-cell area at the shared edge
+    T oq[3] = {T(0), T(0), T(0)};
+    T oat = T(0);  // SC: the outer element's sub-cell area at the shared edge
     if (og < 4 && orr < ((og < 2) ? TXE : TYE)) {
         int rex, rey;
         if (og == 0) {  // below the ring: its top edge
@@ -505,7 +520,7 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
         ore = rey * EX + rex;
         if (s_split[ore] == 0) {
             oin = true;
-            double x[4], y[4], ux[4], uy[4], dx[4], dy[4];
+            T x[4], y[4], ux[4], uy[4], dx[4], dy[4];
             elem_xy(rex, rey, x, y);
             elem_u(rex, rey, ux, uy);
             if constexpr (SC) {
@@ -529,7 +544,7 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
 
     // owned-node data for the update, loaded here so that the registers are
     // free during the gradient phase and the latency hides behind the forces
-    double n_minv = 0.0, n_vx = 0.0, n_vy = 0.0, n_fex = 0.0, n_fey = 0.0, n_v0x = 0.0, n_v0y = 0.0;
+    T n_minv = T(0), n_vx = T(0), n_vy = T(0), n_fex = T(0), n_fey = T(0), n_v0x = T(0), n_v0y = T(0);
     unsigned n_mask = 0;
     if (on_valid) {
         n_minv = p.minv[on_n];
@@ -546,17 +561,17 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
     }
 
     // smoothed stress at edge slot sid
-    auto edge_sigma = [&](int sid, double sg[3]) {
+    auto edge_sigma = [&](int sid, T sg[3]) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) sg[c] = s_e[c * NS + sid];
     };
 
     // ---- 4. element forces, one thread per element of the tile ring ----
-    double fe[8];
+    T fe[8];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) fe[c] = 0.0;
+    for (int c = 0; c < 8; ++c) fe[c] = T(0);
     if (SC && code == 0) {
-        double bb[4][3], cb[4][3], sgk[4][3];
+        T bb[4][3], cb[4][3], sgk[4][3];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             edge_sigma(sidx[k], sgk[k]);
@@ -568,16 +583,16 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
         }
         subcell_force(bb, cb, at, sgk, fe);
     } else if (code == 0) {
-        double sx[4], sy[4];
+        T sx[4], sy[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            double sg[3];
+            T sg[3];
             edge_sigma(sidx[k], sg);
-            const double s0 = sg[0], s1 = sg[1], s2 = sg[2];
+            const T s0 = sg[0], s1 = sg[1], s2 = sg[2];
 #pragma unroll
             for (int n = 0; n < 4; ++n) {
-                const double tx = fma(gy[k][n], s2, gx[k][n] * s0);
-                const double ty = fma(gx[k][n], s2, gy[k][n] * s1);
+                const T tx = fmat(gy[k][n], s2, gx[k][n] * s0);
+                const T ty = fmat(gx[k][n], s2, gy[k][n] * s1);
                 if (k == 0) {
                     sx[n] = tx;
                     sy[n] = ty;
@@ -587,7 +602,7 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
                 }
             }
         }
-        const double c = 0.25 * my_area;
+        const T c = T(0.25) * my_area;
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
             fe[2 * n] = c * sx[n];
@@ -650,12 +665,12 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
     // edge a+1+j, lane 0 of the quad applies the element rule to the three
     // values.  Node data are read from LDS at computed offsets, so no array
     // is indexed by a run-time value.
-    Cand best;
+    CandT<T> best;
     cand_none(best);
     for (int c0 = 0; c0 < ncand; c0 += NT / 4) {  // same trip count in every lane
         const int c = c0 + (tid >> 2), j = tid & 3;
         const bool live = c < ncand;
-        double Gj = 0.0, gc = 0.0;
+        T Gj = T(0), gc = T(0);
         bool H = false;
         int a = 0;
         int64_t ge = 0;
@@ -667,32 +682,32 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
             gc = p.gc ? p.gc[ge] : p.gc_uniform;
             const int nb0 = (cje + 1) * HX + (cie + 1);
             const int o1 = nb0 + corner(a), o2 = nb0 + corner((a + 1) & 3);
-            const double X1 = s_X[o1], Y1 = s_Y[o1], X2 = s_X[o2], Y2 = s_Y[o2];
-            const double ux1 = s_ux[o1], uy1 = s_uy[o1], ux2 = s_ux[o2], uy2 = s_uy[o2];
-            const double dux = ux2 - ux1, duy = uy2 - uy1;
-            const double x1 = X1 + ux1, y1 = Y1 + uy1;
-            const double x2 = X2 + ux2, y2 = Y2 + uy2;
-            const double lx = x2 - x1, ly = y2 - y1;
-            const double Lx = X2 - X1, Ly = Y2 - Y1;
+            const T X1 = s_X[o1], Y1 = s_Y[o1], X2 = s_X[o2], Y2 = s_Y[o2];
+            const T ux1 = s_ux[o1], uy1 = s_uy[o1], ux2 = s_ux[o2], uy2 = s_uy[o2];
+            const T dux = ux2 - ux1, duy = uy2 - uy1;
+            const T x1 = X1 + ux1, y1 = Y1 + uy1;
+            const T x2 = X2 + ux2, y2 = Y2 + uy2;
+            const T lx = x2 - x1, ly = y2 - y1;
+            const T Lx = X2 - X1, Ly = Y2 - Y1;
             H = (lx * lx + ly * ly) > (Lx * Lx + Ly * Ly);  // else G = 0 on all three paths
             if (H && j < 3) {
                 const int k = (a + 1 + j) & 3;
-                double sg[3], nxv, nyv, len;
+                T sg[3], nxv, nyv, len;
                 edge_sigma(edge_slot(cie, cje, k), sg);
                 const int q0 = nb0 + corner(k), q1 = nb0 + corner((k + 1) & 3);
                 path_geom_pts(X1, Y1, X2, Y2, s_X[q0], s_Y[q0], s_X[q1], s_Y[q1], nxv, nyv, len);
-                const double spx = fma(sg[2], nyv, sg[0] * nxv);
-                const double spy = fma(sg[1], nyv, sg[2] * nxv);
-                Gj = 0.5 * fma(duy, spy, dux * spx);
+                const T spx = fmat(sg[2], nyv, sg[0] * nxv);
+                const T spy = fmat(sg[1], nyv, sg[2] * nxv);
+                Gj = T(0.5) * fmat(duy, spy, dux * spx);
             }
         }
         const int qb = tid & 60;  // lane of j = 0 in this quad
-        const double G1 = __shfl(Gj, qb + 1, 64);
-        const double G2 = __shfl(Gj, qb + 2, 64);
+        const T G1 = __shfl(Gj, qb + 1, 64);
+        const T G2 = __shfl(Gj, qb + 2, 64);
         if (live && H && j == 0) {
-            const double Gv[3] = {Gj, G1, G2};
+            const T Gv[3] = {Gj, G1, G2};
             int jb = -1;
-            double gb = 0.0;
+            T gb = T(0);
 #pragma unroll
             for (int q = 0; q < 3; ++q)
                 if (Gv[q] > gc && (jb < 0 || Gv[q] > gb)) {
@@ -708,7 +723,7 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
                 if (ok && p.front) {  // per-front pick: every accepted candidate
                     const uint32_t slot = atomicAdd(p.fcount, 1u);
                     AccCand ac;
-                    ac.G = gb;
+                    ac.G = (double)gb;
                     ac.elem = (int32_t)ge;
                     ac.ak = (a << 2) | ((a + 1 + jb) & 3);
                     p.fcand[slot] = ac;
@@ -744,49 +759,49 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
         const int F = cst ? ((((eb - ea) & 3) == 3) ? ea : eb) : (((it - ncorner) & 1) ? eb : ea);
         const int n0 = F, n1 = (F + 1) & 3, n2 = (F + 2) & 3, n3 = (F + 3) & 3;
         const int o0 = nb0 + corner(n0), o1 = nb0 + corner(n1), o2 = nb0 + corner(n2), o3 = nb0 + corner(n3);
-        const double x0 = s_X[o0], x1 = s_X[o1], x2 = s_X[o2], x3 = s_X[o3];
-        const double y0 = s_Y[o0], y1 = s_Y[o1], y2 = s_Y[o2], y3 = s_Y[o3];
-        const double gx = 0.5 * (x0 + x1), gy = 0.5 * (y0 + y1);  // midpoint of edge F
+        const T x0 = s_X[o0], x1 = s_X[o1], x2 = s_X[o2], x3 = s_X[o3];
+        const T y0 = s_Y[o0], y1 = s_Y[o1], y2 = s_Y[o2], y3 = s_Y[o3];
+        const T gx = T(0.5) * (x0 + x1), gy = T(0.5) * (y0 + y1);  // midpoint of edge F
         if (cst) {
             // polygon: mid(F), n1, n2, n3, mid(F+3); shoelace fanned from mid(F)
-            const double hx = 0.5 * (x3 + x0), hy = 0.5 * (y3 + y0);
-            double sa = 0.0;
+            const T hx = T(0.5) * (x3 + x0), hy = T(0.5) * (y3 + y0);
+            T sa = T(0);
             sa += (x1 - gx) * (y2 - gy) - (x2 - gx) * (y1 - gy);
             sa += (x2 - gx) * (y3 - gy) - (x3 - gx) * (y2 - gy);
             sa += (x3 - gx) * (hy - gy) - (hx - gx) * (y3 - gy);
-            const double Ap = 0.5 * sa;
-            const double twoA = (x2 - x1) * (y3 - y1) - (x3 - x1) * (y2 - y1);
-            const double inv = 1.0 / twoA;
-            const double bb[3] = {(y2 - y3) * inv, (y3 - y1) * inv, (y1 - y2) * inv};
-            const double cc[3] = {(x3 - x2) * inv, (x1 - x3) * inv, (x2 - x1) * inv};
-            const double pu[3] = {s_ux[o1], s_ux[o2], s_ux[o3]};
-            const double pv[3] = {s_uy[o1], s_uy[o2], s_uy[o3]};
-            double eps[3], sg[3];
+            const T Ap = T(0.5) * sa;
+            const T twoA = (x2 - x1) * (y3 - y1) - (x3 - x1) * (y2 - y1);
+            const T inv = T(1) / twoA;
+            const T bb[3] = {(y2 - y3) * inv, (y3 - y1) * inv, (y1 - y2) * inv};
+            const T cc[3] = {(x3 - x2) * inv, (x1 - x3) * inv, (x2 - x1) * inv};
+            const T pu[3] = {s_ux[o1], s_ux[o2], s_ux[o3]};
+            const T pv[3] = {s_uy[o1], s_uy[o2], s_uy[o3]};
+            T eps[3], sg[3];
             strain<3>(bb, cc, pu, pv, eps);
             hooke(p, eps, sg);
             const int nn[3] = {n1, n2, n3};
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                const double tx = fma(cc[i], sg[2], bb[i] * sg[0]);
-                const double ty = fma(bb[i], sg[2], cc[i] * sg[1]);
+                const T tx = fmat(cc[i], sg[2], bb[i] * sg[0]);
+                const T ty = fmat(bb[i], sg[2], cc[i] * sg[1]);
                 s_fe[(2 * nn[i]) * NT + t] = Ap * tx;
                 s_fe[(2 * nn[i] + 1) * NT + t] = Ap * ty;
             }
-            s_fe[(2 * n0) * NT + t] = 0.0;
-            s_fe[(2 * n0 + 1) * NT + t] = 0.0;
+            s_fe[(2 * n0) * NT + t] = T(0);
+            s_fe[(2 * n0 + 1) * NT + t] = T(0);
         } else {
             // polygon: mid(F), n1, n2, mid(F+2); bar along the uncut edge n1-n2
-            const double hx = 0.5 * (x2 + x3), hy = 0.5 * (y2 + y3);
-            double sa = 0.0;
+            const T hx = T(0.5) * (x2 + x3), hy = T(0.5) * (y2 + y3);
+            T sa = T(0);
             sa += (x1 - gx) * (y2 - gy) - (x2 - gx) * (y1 - gy);
             sa += (x2 - gx) * (hy - gy) - (hx - gx) * (y2 - gy);
-            const double Ap = 0.5 * sa;
-            const double dx = x2 - x1, dy = y2 - y1;
-            const double L2 = dx * dx + dy * dy;
-            const double dux = s_ux[o2] - s_ux[o1], duy = s_uy[o2] - s_uy[o1];
-            const double st = (dx * dux + dy * duy) / L2;
-            const double stress = p.E * st;
-            const double coef = Ap * stress / L2;
+            const T Ap = T(0.5) * sa;
+            const T dx = x2 - x1, dy = y2 - y1;
+            const T L2 = dx * dx + dy * dy;
+            const T dux = s_ux[o2] - s_ux[o1], duy = s_uy[o2] - s_uy[o1];
+            const T st = (dx * dux + dy * duy) / L2;
+            const T stress = p.E * st;
+            const T coef = Ap * stress / L2;
             s_fe[(2 * n2) * NT + t] = coef * dx;
             s_fe[(2 * n2 + 1) * NT + t] = coef * dy;
             s_fe[(2 * n1) * NT + t] = -(coef * dx);
@@ -795,7 +810,7 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
     }
     __syncthreads();
     if (on_valid) {
-        double fx = 0.0, fy = 0.0;
+        T fx = T(0), fy = T(0);
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             const int dx = ((c & 1) - (i0 - 1 + on_l)) & 1;
@@ -812,31 +827,31 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
         // ---- 7. central-difference update of the owned node --------------
         const int64_t kabs = base + k_rel;
         const int hidx = (on_m + 2) * HX + (on_l + 2);
-        const double phi = s_phi;
-        double ax = (phi * n_fex - fx) * n_minv;
-        double ay = (phi * n_fey - fy) * n_minv;
-        if (n_mask & 1u) ax = 0.0;
-        if (n_mask & 2u) ay = 0.0;
-        const double dtv = (kabs == 0) ? 0.5 * p.dt : p.dt;
+        const T phi = s_phi;
+        T ax = (phi * n_fex - fx) * n_minv;
+        T ay = (phi * n_fey - fy) * n_minv;
+        if (n_mask & 1u) ax = T(0);
+        if (n_mask & 2u) ay = T(0);
+        const T dtv = (kabs == 0) ? T(0.5) * p.dts : p.dts;
         const double th = ((double)kabs + 0.5) * p.dt;
-        double vx = n_vx + dtv * ax;
-        double vy = n_vy + dtv * ay;
+        T vx = n_vx + dtv * ax;
+        T vy = n_vy + dtv * ay;
         if (n_mask & 1u) vx = prescribed(n_v0x, th, p.t_ramp);
         if (n_mask & 2u) vy = prescribed(n_v0y, th, p.t_ramp);
         p.vx[on_n] = vx;
         p.vy[on_n] = vy;
-        ux_n[on_n] = s_ux[hidx] + p.dt * vx;
-        uy_n[on_n] = s_uy[hidx] + p.dt * vy;
+        ux_n[on_n] = s_ux[hidx] + p.dts * vx;
+        uy_n[on_n] = s_uy[hidx] + p.dts * vy;
     }
 
     // ---- 8. publish the workgroup's best candidate -----------------------
     // Read by the next step after the kernel boundary; no fence here (a
     // device-scope release would write back the whole L2 of the XCD).
-    if (tid == 0 && best.G >= 0.0 && !p.front) {
+    if (tid == 0 && best.G >= T(0) && !p.front) {
         const uint32_t slot = atomicAdd(&p.ctl->nslots[set_w], 1u);
         Slot sl;
-        sl.G = best.G;
-        sl.Gmin = best.Gmin;
+        sl.G = (double)best.G;
+        sl.Gmin = (double)best.Gmin;
         sl.elem = best.e;
         sl.a = best.a;
         sl.k = best.k;
@@ -850,16 +865,16 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParams p0, const StepP
 constexpr int kCommitThreads = 256;
 
 // One workgroup per specimen.
-template <bool BATCHED>
-__global__ __launch_bounds__(kCommitThreads) void k_commit(StepParams p0, const StepParams *views, int n) {
-    __shared__ Cand s_red[kCommitThreads / 64];
-    StepParams p;
+template <class T, bool BATCHED>
+__global__ __launch_bounds__(kCommitThreads) void k_commit(StepParamsT<T> p0, const StepParamsT<T> *views, int n) {
+    __shared__ CandT<T> s_red[kCommitThreads / 64];
+    StepParamsT<T> p;
     if constexpr (BATCHED)
         p = views[blockIdx.x];
     else
         p = p0;
     const int set = (n + 2) % 3;
-    const Cand g = reduce_slots<kCommitThreads>(p, set, p.ctl->nslots[set], s_red);
+    const CandT<T> g = reduce_slots<kCommitThreads>(p, set, p.ctl->nslots[set], s_red);
     if (threadIdx.x != 0) return;
     const int64_t base = p.ctl->base;
     const bool acc = n > 0 && pick_accepted(p, g);
@@ -955,32 +970,45 @@ __global__ __launch_bounds__(kFrontThreads) void k_front(StepParams p, int k_rel
 
 hipError_t launch_step(int tile, const Launch &L, int k_rel, int par0, hipStream_t s) {
     (void)hipGetLastError();  // report only this launch's error below
+    if (L.f32) {
+        // binary32 step: plain models with the point rule and the global or
+        // single-tip pick
+        const StepParamsF &p = L.p0f;
+        switch (tile) {
+            case 1: k_step<float, 16, 16, false><<<p.nwg, 256, 0, s>>>(p, nullptr, nullptr, k_rel, par0); break;
+            case 2: k_step<float, 32, 8, false><<<p.nwg, 256, 0, s>>>(p, nullptr, nullptr, k_rel, par0); break;
+            default: k_step<float, 32, 16, false><<<p.nwg, 512, 0, s>>>(p, nullptr, nullptr, k_rel, par0); break;
+        }
+        return hipGetLastError();
+    }
     const StepParams &p = L.p0;
     if (L.batched) {
         switch (tile) {
-            case 1: k_step<16, 16, true><<<L.nunits, 256, 0, s>>>(p, L.views, L.units, k_rel, par0); break;
-            case 2: k_step<32, 8, true><<<L.nunits, 256, 0, s>>>(p, L.views, L.units, k_rel, par0); break;
-            default: k_step<32, 16, true><<<L.nunits, 512, 0, s>>>(p, L.views, L.units, k_rel, par0); break;
+            case 1: k_step<double, 16, 16, true><<<L.nunits, 256, 0, s>>>(p, L.views, L.units, k_rel, par0); break;
+            case 2: k_step<double, 32, 8, true><<<L.nunits, 256, 0, s>>>(p, L.views, L.units, k_rel, par0); break;
+            default:
+                k_step<double, 32, 16, true><<<L.nunits, 512, 0, s>>>(p, L.views, L.units, k_rel, par0);
+                break;
         }
     } else {
         switch (tile) {
             case 1:
                 if (p.subcell)
-                    k_step<16, 16, false, true><<<p.nwg, 256, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
+                    k_step<double, 16, 16, false, true><<<p.nwg, 256, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
                 else
-                    k_step<16, 16, false><<<p.nwg, 256, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
+                    k_step<double, 16, 16, false><<<p.nwg, 256, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
                 break;
             case 2:
                 if (p.subcell)
-                    k_step<32, 8, false, true><<<p.nwg, 256, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
+                    k_step<double, 32, 8, false, true><<<p.nwg, 256, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
                 else
-                    k_step<32, 8, false><<<p.nwg, 256, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
+                    k_step<double, 32, 8, false><<<p.nwg, 256, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
                 break;
             default:
                 if (p.subcell)
-                    k_step<32, 16, false, true><<<p.nwg, 512, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
+                    k_step<double, 32, 16, false, true><<<p.nwg, 512, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
                 else
-                    k_step<32, 16, false><<<p.nwg, 512, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
+                    k_step<double, 32, 16, false><<<p.nwg, 512, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
                 break;
         }
         if (p.front) k_front<<<1, kFrontThreads, 0, s>>>(p, k_rel);
@@ -990,10 +1018,12 @@ hipError_t launch_step(int tile, const Launch &L, int k_rel, int par0, hipStream
 
 hipError_t launch_commit(const Launch &L, int n, hipStream_t s) {
     (void)hipGetLastError();
-    if (L.batched)
-        k_commit<true><<<L.nspec, kCommitThreads, 0, s>>>(L.p0, L.views, n);
+    if (L.f32)
+        k_commit<float, false><<<1, kCommitThreads, 0, s>>>(L.p0f, nullptr, n);
+    else if (L.batched)
+        k_commit<double, true><<<L.nspec, kCommitThreads, 0, s>>>(L.p0, L.views, n);
     else
-        k_commit<false><<<1, kCommitThreads, 0, s>>>(L.p0, nullptr, n);
+        k_commit<double, false><<<1, kCommitThreads, 0, s>>>(L.p0, nullptr, n);
     return hipGetLastError();
 }
 

@@ -456,8 +456,9 @@ def _setup(m: Model, cfg: dict):
 
 def from_config(cfg: dict, stream: int | None = None, tile: int = 0, use_graph: bool = True) -> Model:
     """Build and finalize a model from a workload dictionary
-    (paper_2509_01827_amd.workloads)."""
-    m = Model(64, stream)
+    (paper_2509_01827_amd.workloads); cfg key precision 32 selects the
+    binary32 step."""
+    m = Model(int(cfg.get("precision", 64)), stream)
     _setup(m, cfg)
     m.set_launch(tile, use_graph)
     m.finalize()

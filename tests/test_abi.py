@@ -39,7 +39,8 @@ def test_null_handles_are_rejected():
     assert lib.mct_finalize(None) == -1
     assert lib.mct_create(None, 64, None) == -1
     h = ctypes.c_void_p()
-    assert lib.mct_create(ctypes.byref(h), 32, None) == -6   # binary32 not offered
+    assert lib.mct_create(ctypes.byref(h), 16, None) == -6   # precisions are 64 and 32
+    assert lib.mct_batch_create(ctypes.byref(h), 2, 32, None) == -6  # binary32: plain contexts only
     assert b"null" in lib.mct_last_error(None)
 
 

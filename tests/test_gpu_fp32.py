@@ -1,0 +1,150 @@
+"""The binary32 step on the GPU against the oracle's binary32 build.
+
+Bar: bit-exact.  Both run the same expression order in binary32 (set-up
+values computed in binary64 and rounded once), so the split log (G exact in
+binary64), split codes, tips, u, v and U_d must be identical, for every tile
+shape and both launch modes.  Derived fields of a binary32 context are
+evaluated in binary64 from its state: compared with the binary64 oracle given
+that state and crack set (1e-12).  Energies against the binary32 oracle's:
+1e-5 relative (its internal forces are binary32, the library's binary64).
+"""
+import numpy as np
+import pytest
+
+from paper_2509_01827_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2509_01827_amd import mct2d
+    mct2d.load()
+    return mct2d
+
+
+def _f32(cfg):
+    return dict(cfg, precision=32)
+
+
+def _same(m, o, label):
+    lg, ol = m.crack_set(), o.log()
+    assert len(lg["elem"]) == len(ol["elem"]), label
+    for k in ("step", "elem", "entry", "exit"):
+        assert np.array_equal(lg[k].astype(np.int64), ol[k].astype(np.int64)), (label, k)
+    assert np.array_equal(lg["G"], ol["G"]), label
+    st = o.state()
+    assert np.array_equal(m.split_codes(), st["split"]), label
+    (ux, uy), (vx, vy) = m.field(0), m.field(1)
+    for a, b, n in ((ux, st["ux"], "ux"), (uy, st["uy"], "uy"), (vx, st["vx"], "vx"), (vy, st["vy"], "vy")):
+        assert np.array_equal(a, b), (label, n, np.abs(a - b).max())
+    te, txy = m.tips()
+    oe, oxy = o.tips()
+    assert np.array_equal(te, oe) and np.array_equal(txy, oxy), label
+    inf = m.info()
+    assert inf["precision"] == 32
+    assert inf["dissipated"] == o.info()["Ud"], label
+
+
+@pytest.mark.parametrize("name", sorted(W.small_cases()))
+def test_fp32_matches_oracle(gpu, oracle_mod, name):
+    cfg = _f32(W.small_cases()[name])
+    o = oracle_mod.Oracle(cfg)
+    models = [gpu.from_config(cfg, tile=t, use_graph=g) for t in (1, 2, 3) for g in (True, False)]
+    done = 0
+    for chunk in (1, 63, 136, 600):
+        o.step(chunk)
+        done += chunk
+        for m in models:
+            m.step(chunk)
+            m.sync()
+            _same(m, o, (name, done, m.launch()["tile"]))
+    assert len(o.log()["elem"]) > 5
+    print(name, "splits", len(o.log()["elem"]), flush=True)
+
+
+def test_fp32_sct_ramp_and_pulse(gpu, oracle_mod):
+    cases = [dict(W.small_cases()["plate40x40"], tracking=("sct", -1, 0)),
+             dict(W.fragmentation(61, 33, 1e-3, seed=W.BASE_SEED + 17, steps=300), t_ramp=5e-6),
+             W.pulse_plate(48, 32, 0.048, 0.032, peak=2e6, steps=900, t0=2e-5, tau=4e-5)]
+    for i, c in enumerate(cases):
+        cfg = _f32(c)
+        o = oracle_mod.Oracle(cfg)
+        m = gpu.from_config(cfg)
+        for chunk in (100, 236, 300):
+            o.step(chunk)
+            m.step(chunk)
+            _same(m, o, ("case", i, chunk))
+        if i == 0:
+            assert m.tip() == o.tip()
+        assert len(o.log()["elem"]) > 0, i
+
+
+def test_fp32_fullsize_plate(gpu, oracle_mod):
+    """The 400 x 400 branching plate in binary32, 300 steps: bit-identical."""
+    cfg = _f32(W.config2(steps=300))
+    o = oracle_mod.Oracle(cfg)
+    m = gpu.from_config(cfg)
+    o.step(300)
+    m.step(300)
+    _same(m, o, "plate400 fp32")
+
+
+def test_fp32_queries(gpu, oracle_mod):
+    cfg = _f32(W.small_cases()["plate70x37_jitter"])
+    m = gpu.from_config(cfg)
+    o32 = oracle_mod.Oracle(cfg)
+    m.step(700)
+    o32.step(700)
+    _same(m, o32, "queries")
+    (ux, uy), codes = m.field(0), m.split_codes()
+    o64 = oracle_mod.Oracle(W.small_cases()["plate70x37_jitter"])
+    o64.set_split_codes(codes)
+    fx, fy, sig, ok = o64.internal_force(ux, uy, with_stress=True)
+    gx, gy = m.field(gpu.FIELD_FINT)
+    scale = max(np.abs(fx).max(), np.abs(fy).max())
+    assert np.abs(gx - fx).max() <= 1e-12 * scale and np.abs(gy - fy).max() <= 1e-12 * scale
+    gs = m.field(gpu.FIELD_SIGMA_EDGE)
+    okb = ok.astype(bool)
+    assert np.abs(gs[okb] - sig[okb]).max() <= 1e-12 * np.abs(sig[okb]).max()
+    ge, oe = m.energies(), o32.energies()
+    for k in ("kin", "strain", "wext"):
+        assert ge[k] == pytest.approx(oe[k], rel=1e-5), k
+    assert ge["Ud"] == oe["Ud"]
+
+
+def test_fp32_checkpoint(gpu):
+    cfg = _f32(W.small_cases()["fragment97x45"])
+    a = gpu.from_config(cfg)
+    a.step(151)
+    ck = a.checkpoint()
+    a.step(200)
+    b = gpu.from_config(cfg, tile=2)
+    b.restore(ck)
+    b.step(200)
+    la, lb = a.crack_set(), b.crack_set()
+    for k in ("step", "elem", "entry", "exit", "G"):
+        assert np.array_equal(la[k], lb[k])
+    assert np.array_equal(a.field(0)[0], b.field(0)[0]) and np.array_equal(a.field(1)[1], b.field(1)[1])
+    c64 = gpu.from_config(W.small_cases()["fragment97x45"])
+    with pytest.raises(gpu.MctError):  # states move between contexts of one precision
+        c64.restore(ck)
+    with pytest.raises(gpu.MctError):
+        b.restore(c64.checkpoint())
+
+
+def test_fp32_unsupported(gpu):
+    cfg = _f32(W.small_cases()["plate40x40"])
+    with pytest.raises(gpu.MctError):
+        gpu.from_config(dict(cfg, smoothing="subcell"))
+    with pytest.raises(gpu.MctError):
+        gpu.from_config(dict(cfg, front_radius=1e-3))
+    t = W.tri_small_cases()["tri_plate40x16"]
+    m = gpu.Model(precision=32)
+    with pytest.raises(gpu.MctError):
+        m.set_mesh_tri(t["X"], t["Y"], t["conn"])
+    with pytest.raises(gpu.MctError):
+        gpu.Model(precision=32, n_specimens=2)
