@@ -70,6 +70,14 @@ struct Params {
     const int32_t *patch_elem;
     const uint16_t *patch_slots;
     Cand *cand;          // 3 ne
+    // fused step with the global pick folded in (multi-tip tracking): the
+    // accepted candidates of segment step j go to set j mod 3 of fold_cand
+    // (3 sets of 3 ne), counted in fold_n[j mod 3]; every workgroup of step
+    // j + 1 takes their pick, and the segment's commit takes the last step's
+    int32_t fold;
+    int32_t pad_fold;
+    int32_t *fold_n;     // 3 counters
+    Cand *fold_cand;     // 9 ne
     LogRec *log;
     Ctl *ctl;
     const double *curve_t, *curve_phi;

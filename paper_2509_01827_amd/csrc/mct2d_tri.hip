@@ -96,16 +96,27 @@ __device__ __forceinline__ void load_u(const double2 *u, const int4 &c, double2 
     out[2] = u[c.z];
 }
 
+// Split codes as a step sees them: the array, with one pending split (the
+// previous step's pick, not yet visible in the array to every workgroup)
+// applied on top.
+struct SplitView {
+    const uint8_t *split;
+    int pe;         // pending element, or -1
+    uint8_t pcode;  // its code
+    __device__ __forceinline__ uint8_t operator()(int e) const { return e == pe ? pcode : split[e]; }
+};
+
 // Smoothed strain of local edge k of intact element e (own strain q, area
 // A).  The neighbour nb across k runs the shared edge backwards: its local
 // node loc is our node k+1 (xb, ub), loc+1 is our node k (xa, ua) and
 // loc+2 is its third node (xo, uo); its strain is recomputed in its own
 // node order.  two_out: the neighbour is intact; An: its area.
-__device__ __forceinline__ void edge_strain(const Params &p, int e, int nb, int loc, const double2 &xa,
+__device__ __forceinline__ void edge_strain(const Params &p, const SplitView &sv, int e, int nb, int loc,
+                                            const double2 &xa,
                                             const double2 &xb, const double2 &xo, const double2 &ua,
                                             const double2 &ub, const double2 &uo, const double q[3], double A,
                                             double eps[3], bool &two_out, double &An) {
-    const bool two = nb >= 0 && p.split[nb] == 0;
+    const bool two = nb >= 0 && sv(nb) == 0;
     two_out = two;
     An = 0.0;
     if (!two) {
@@ -247,10 +258,12 @@ __device__ __forceinline__ double2 piece_force_at(const Piece &a, const Piece &b
 // first), applies Hooke's law and returns (A/3) B^T (sigma_0 + sigma_1 +
 // sigma_2); with `cands` its free-surface edges are evaluated as crack-tip
 // candidates and accepted ones appended to the list.  A split element
-// returns the forces of its two pieces.
-__device__ __forceinline__ void element_force(const Params &p, const double2 *u, int e, bool cands, double2 f[3]) {
+// returns the forces of its two pieces.  Candidates go to clist, counted
+// by *ccount.
+__device__ __forceinline__ void element_force(const Params &p, const SplitView &sv, const double2 *u, int e,
+                                              bool cands, Cand *clist, int32_t *ccount, double2 f[3]) {
     const int4 c = p.conn[e];
-    const uint8_t code = p.split[e];
+    const uint8_t code = sv(e);
     if (code) {
         const Piece pa = piece(p, u, c, (code >> 2) & 3, code & 3);
         const Piece pb = piece(p, u, c, code & 3, (code >> 2) & 3);
@@ -279,7 +292,7 @@ __device__ __forceinline__ void element_force(const Params &p, const double2 *u,
     double eps[3][3], An[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        edge_strain(p, e, k == 0 ? nb.x : (k == 1 ? nb.y : nb.z), (nb.w >> (2 * k)) & 3, xe[k], xe[(k + 1) % 3],
+        edge_strain(p, sv, e, k == 0 ? nb.x : (k == 1 ? nb.y : nb.z), (nb.w >> (2 * k)) & 3, xe[k], xe[(k + 1) % 3],
                     xo[k], ue[k], ue[(k + 1) % 3], uo[k], q, g.A, eps[k], two[k], An[k]);
         hooke(p, eps[k], sig[k]);
     }
@@ -303,12 +316,12 @@ __device__ __forceinline__ void element_force(const Params &p, const double2 *u,
                                 s1, s2, a, G);
         if (j < 0) continue;
         const int k = (a + 1 + j) % 3;
-        const int slot = atomicAdd(&p.ctl->nacc, 1);
+        const int slot = atomicAdd(ccount, 1);
         Cand cd;
         cd.G = G;
         cd.elem = e;
         cd.ak = (a << 2) | k;
-        p.cand[slot] = cd;
+        clist[slot] = cd;
     }
 }
 
@@ -320,7 +333,7 @@ __global__ __launch_bounds__(kB) void k_force(Params p, const double2 *u, Eval e
     if constexpr (!EVAL) {
         if (((p.ctl->base + j) & 1) != 0) u = p.u1;  // u^k
         double2 f[3];
-        element_force(p, u, e, true, f);
+        element_force(p, SplitView{p.split, -1, 0}, u, e, true, p.cand, &p.ctl->nacc, f);
         p.fe[e] = f[0];
         p.fe[p.ne + e] = f[1];
         p.fe[2 * (int64_t)p.ne + e] = f[2];
@@ -371,7 +384,7 @@ __global__ __launch_bounds__(kB) void k_force(Params p, const double2 *u, Eval e
     double eps[3][3], An[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        edge_strain(p, e, k == 0 ? nb.x : (k == 1 ? nb.y : nb.z), (nb.w >> (2 * k)) & 3, xe[k], xe[(k + 1) % 3],
+        edge_strain(p, SplitView{p.split, -1, 0}, e, k == 0 ? nb.x : (k == 1 ? nb.y : nb.z), (nb.w >> (2 * k)) & 3, xe[k], xe[(k + 1) % 3],
                     xo[k], ue[k], ue[(k + 1) % 3], uo[k], q, g.A, eps[k], two[k], An[k]);
         hooke(p, eps[k], sig[k]);
     }
@@ -445,19 +458,19 @@ __device__ __forceinline__ bool better(const Cand &a, const Cand &b) {
 
 // MCT pick of step k over the candidate list (whole workgroup), then the
 // split, its log record, U_d and the single tip.
-__device__ void pick(const Params &p, int64_t k) {
+// Best of n accepted candidates (largest G, then lower element, then lower
+// tip edge) and the smallest G, by the whole workgroup; valid in thread 0.
+// n is uniform over the workgroup.
+__device__ __forceinline__ void best_of(const Cand *list, int n, Cand &best_out, double &gmin_out) {
     __shared__ Cand s_best[kB];
     __shared__ double s_min[kB];
-    Ctl *ctl = p.ctl;
-    const int n = ctl->nacc;
-    if (n == 0) return;  // uniform over the workgroup
     Cand best;
     best.G = -1.0;
     best.elem = 0x7fffffff;
     best.ak = 0;
     double gmin = INFINITY;
     for (int t = threadIdx.x; t < n; t += kB) {
-        const Cand cd = p.cand[t];
+        const Cand cd = list[t];
         if (better(cd, best)) best = cd;
         gmin = fmin(gmin, cd.G);
     }
@@ -471,42 +484,59 @@ __device__ void pick(const Params &p, int64_t k) {
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        const Cand b = s_best[0];
-        const double Gmin = s_min[0];
-        ctl->nacc = 0;
-        // split-ratio test against every other accepted candidate; the
-        // smallest G is the hardest one to pass
-        if (b.G > p.gamma * (b.G - Gmin)) {
-            const int e = b.elem, a = b.ak >> 2, kx = b.ak & 3;
-            p.split[e] = (uint8_t)(kSplitFlag | b.ak);
-            const int64_t ns = ctl->nsplit;
-            if (ns < p.log_cap) {
-                LogRec r;
-                r.step = (int32_t)k;
-                r.elem = e;
-                r.entry = (uint8_t)a;
-                r.exit = (uint8_t)kx;
-                r.pad0 = r.pad1 = 0;
-                r.pad2 = 0;
-                r.G = b.G;
-                p.log[ns] = r;
-            } else {
-                ctl->overflow = 1;
-            }
-            ctl->nsplit = ns + 1;
-            const int4 c = p.conn[e];
-            double nx, ny, len;
-            path_geom(p, c, a, kx, nx, ny, len);
-            ctl->Ud = ctl->Ud + p.gc[e] * len;
-            if (p.sct) {
-                const int4 nb = p.nbr[e];
-                const int m = kx == 0 ? nb.x : (kx == 1 ? nb.y : nb.z);
-                ctl->tip = (m < 0 || p.split[m] != 0) ? -1 : 4 * m + ((nb.w >> (2 * kx)) & 3);
-            }
-        }
+    best_out = s_best[0];
+    gmin_out = s_min[0];
+}
+
+// Record the split of step k picked from candidate b: its code, the log,
+// U_d (Gc * crack-path length) and, in single-tip tracking, the next tip.
+// One thread.
+__device__ void apply_pick(const Params &p, const Cand &b, int64_t k) {
+    Ctl *ctl = p.ctl;
+    const int e = b.elem, a = b.ak >> 2, kx = b.ak & 3;
+    p.split[e] = (uint8_t)(kSplitFlag | b.ak);
+    const int64_t ns = ctl->nsplit;
+    if (ns < p.log_cap) {
+        LogRec r;
+        r.step = (int32_t)k;
+        r.elem = e;
+        r.entry = (uint8_t)a;
+        r.exit = (uint8_t)kx;
+        r.pad0 = r.pad1 = 0;
+        r.pad2 = 0;
+        r.G = b.G;
+        p.log[ns] = r;
+    } else {
+        ctl->overflow = 1;
+    }
+    ctl->nsplit = ns + 1;
+    const int4 c = p.conn[e];
+    double nx, ny, len;
+    path_geom(p, c, a, kx, nx, ny, len);
+    ctl->Ud = ctl->Ud + p.gc[e] * len;
+    if (p.sct) {
+        const int4 nb = p.nbr[e];
+        const int m = kx == 0 ? nb.x : (kx == 1 ? nb.y : nb.z);
+        ctl->tip = (m < 0 || p.split[m] != 0) ? -1 : 4 * m + ((nb.w >> (2 * kx)) & 3);
     }
 }
+
+// The global pick of step k over the accepted candidates list[0..*count):
+// the best one splits if it passes the split-ratio test against every
+// other (the smallest G is the hardest one to pass); *count is reset.
+__device__ void pick_from(const Params &p, const Cand *list, int32_t *count, int64_t k) {
+    const int n = *count;
+    if (n == 0) return;  // uniform over the workgroup
+    Cand b;
+    double Gmin;
+    best_of(list, n, b, Gmin);
+    if (threadIdx.x == 0) {
+        *count = 0;
+        if (b.G > p.gamma * (b.G - Gmin)) apply_pick(p, b, k);
+    }
+}
+
+__device__ __forceinline__ void pick(const Params &p, int64_t k) { pick_from(p, p.cand, &p.ctl->nacc, k); }
 
 __device__ __forceinline__ double prescribed(const Params &p, double v0, double t) {
     if (p.t_ramp > 0.0 && t < p.t_ramp) return v0 * (t / p.t_ramp);
@@ -586,15 +616,43 @@ template <int W, int EMAX>
 __global__ __launch_bounds__(kB) void k_fused(Params p, int j) {
     __shared__ double2 s_f[3 * EMAX];
     __shared__ double s_phi;
+    __shared__ int s_pe;
+    __shared__ uint8_t s_pcode;
     const int64_t k = p.ctl->base + j;
     const bool odd = (k & 1) != 0;
     const double2 *u = odd ? p.u1 : p.u0;
     const int b = blockIdx.x, tid = threadIdx.x;
+    Cand *clist = p.cand;
+    int32_t *ccount = &p.ctl->nacc;
+    if (p.fold) {
+        // the pick of the segment's previous step, from its candidates (set
+        // (j - 1) mod 3), taken alike by every workgroup; workgroup 0 records
+        // it, the others see it through the split view
+        const int prev = (j + 2) % 3;
+        const int n = j > 0 ? p.fold_n[prev] : 0;  // uniform
+        if (tid == 0) s_pe = -1;
+        if (n > 0) {
+            Cand bst;
+            double gmin;
+            best_of(p.fold_cand + (int64_t)prev * 3 * p.ne, n, bst, gmin);
+            if (tid == 0 && bst.G > p.gamma * (bst.G - gmin)) {
+                s_pe = bst.elem;
+                s_pcode = (uint8_t)(kSplitFlag | bst.ak);
+                if (b == 0) apply_pick(p, bst, k - 1);
+            }
+        }
+        // set (j + 1) mod 3 was last read by step j - 1: clear it for step j + 1
+        if (b == 0 && tid == 0) p.fold_n[(j + 1) % 3] = 0;
+        __syncthreads();
+        clist = p.fold_cand + (int64_t)(j % 3) * 3 * p.ne;
+        ccount = p.fold_n + j % 3;
+    }
+    const SplitView sv{p.split, p.fold ? s_pe : -1, p.fold ? s_pcode : (uint8_t)0};
     const int s0 = p.patch_off[b], s1 = p.patch_off[b + 1];
     for (int s = s0 + tid; s < s1; s += kB) {
         const int32_t rec = p.patch_elem[s];
         double2 f[3];
-        element_force(p, u, rec & (kOwned - 1), (rec & kOwned) != 0, f);
+        element_force(p, sv, u, rec & (kOwned - 1), (rec & kOwned) != 0, clist, ccount, f);
         const int l = 3 * (s - s0);
         s_f[l] = f[0];
         s_f[l + 1] = f[1];
@@ -642,6 +700,23 @@ __global__ __launch_bounds__(kB) void k_pick(Params p, int j) { pick(p, p.ctl->b
 
 __global__ void k_commit(Params p, int n) {
     if (threadIdx.x == 0 && blockIdx.x == 0) p.ctl->base = p.ctl->base + n;
+}
+
+// Segment close with the folded pick: the pick of the segment's last step,
+// then every candidate set cleared and the step counter advanced.
+__global__ __launch_bounds__(kB) void k_commit_fold(Params p, int n) {
+    const int64_t base = p.ctl->base;
+    if (n > 0) {
+        const int set = (n + 2) % 3;
+        pick_from(p, p.fold_cand + (int64_t)set * 3 * p.ne, p.fold_n + set, base + n - 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        p.fold_n[0] = 0;
+        p.fold_n[1] = 0;
+        p.fold_n[2] = 0;
+        p.ctl->base = base + n;
+    }
 }
 
 // Query: internal force, acceleration and energy terms per node.
@@ -789,6 +864,7 @@ hipError_t launch_step(const Params &p, int j, hipStream_t st) {
 #undef FUSED
             default: return hipErrorInvalidValue;
         }
+        if (p.fold) return hipGetLastError();  // the next step (or the commit) picks
         if (p.front_r2 > 0.0)
             k_front<<<1, kFrontThreads, 0, st>>>(p, j);
         else
@@ -809,7 +885,10 @@ hipError_t launch_step(const Params &p, int j, hipStream_t st) {
 }
 
 hipError_t launch_commit(const Params &p, int n, hipStream_t st) {
-    k_commit<<<1, 64, 0, st>>>(p, n);
+    if (p.fold)
+        k_commit_fold<<<1, kB, 0, st>>>(p, n);
+    else
+        k_commit<<<1, 64, 0, st>>>(p, n);
     return hipGetLastError();
 }
 

@@ -230,6 +230,7 @@ int choose_kernels(Model &m, Host h) {
     Params &p = m.prm;
     p.patch_emax = 0;
     p.patch_nodes = 0;
+    p.fold = 0;
     int P = 0;
     if (m.kernels >= 2)
         P = 64 << (m.kernels - 2);
@@ -245,6 +246,18 @@ int choose_kernels(Model &m, Host h) {
     p.patch_off = m.dpatch_off;
     p.patch_elem = m.dpatch_elem;
     p.patch_slots = m.dpatch_slots;
+    // the global multi-tip pick folds into the next fused step
+    if (!m.sct && !(m.front_rho > 0)) {
+        if (!m.dfold_n) {
+            TRY(h, hipMalloc((void **)&m.dfold_n, 3 * sizeof(int32_t)));
+            TRY(h, hipMemsetAsync(m.dfold_n, 0, 3 * sizeof(int32_t), h.stream));
+            TRY(h, hipMalloc((void **)&m.dfold_cand, sizeof(Cand) * 9 * (size_t)std::max<int64_t>(m.ne, 1)));
+            TRY(h, hipStreamSynchronize(h.stream));
+        }
+        p.fold = 1;
+        p.fold_n = m.dfold_n;
+        p.fold_cand = m.dfold_cand;
+    }
     return MCT_OK;
 }
 
@@ -267,6 +280,8 @@ void release(Model &m) {
     dfree(m.dpatch_off);
     dfree(m.dpatch_elem);
     dfree(m.dpatch_slots);
+    dfree(m.dfold_n);
+    dfree(m.dfold_cand);
     dfree(m.dv);
     dfree(m.dfext);
     dfree(m.dv0);
@@ -1035,6 +1050,7 @@ int restore(Model &m, Host h, const void *buf, int64_t bytes) {
     p += 24 + sizeof c;
     TRY(h, hipStreamSynchronize(h.stream));
     TRY(h, hipMemcpy(m.dctl, &c, sizeof c, hipMemcpyHostToDevice));
+    if (m.dfold_n) TRY(h, hipMemset(m.dfold_n, 0, 3 * sizeof(int32_t)));
     TRY(h, hipMemcpy(m.du[c.base & 1], p, 16 * m.nn, hipMemcpyHostToDevice));
     p += 16 * m.nn;
     TRY(h, hipMemcpy(m.dv, p, 16 * m.nn, hipMemcpyHostToDevice));

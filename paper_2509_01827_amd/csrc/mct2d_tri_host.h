@@ -55,6 +55,8 @@ struct Model {
     double2 *dxy = nullptr, *du[2] = {nullptr, nullptr}, *dv = nullptr, *dfext = nullptr, *dv0 = nullptr,
             *dfe = nullptr;
     int32_t *dpatch_off = nullptr, *dpatch_elem = nullptr;
+    int32_t *dfold_n = nullptr;     // folded pick: 3 candidate counters
+    Cand *dfold_cand = nullptr;     //   and 3 candidate sets of 3 ne
     uint16_t *dpatch_slots = nullptr;
     // step kernels: 0 automatic, 1 split, 2/3/4 fused on 64/128/256-node patches
     int kernels = 0;
