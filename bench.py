@@ -70,15 +70,22 @@ def bytes_per_step(cfgs, precision: int = 64) -> int:
 # shape; otherwise the traffic is reported as unknown.
 MEASURED_TRAFFIC = {
     "plate400": {"sources": ("mct2d_step.hip", "mct2d_impl.h", "mct2d_device.h"),
-                 "sha256": "7b5f2e0b164696a218cd468b9b26e0990f98598c6c29d329c190f08a15da8c8a",
-                 "tile": 1, "fetch_kib": 5607.0269, "write_kib": 5044.4092},
+                 "sha256": "d86a269d08859568f10637c75fc5e875f6a647b1415e7eff82eea0e9ae238e87",
+                 "tile": 1, "fetch_kib": 5599.51375, "write_kib": 5044.40625},
+    "plate400_f32": {"sources": ("mct2d_step.hip", "mct2d_impl.h", "mct2d_device.h"),
+                     "sha256": "d86a269d08859568f10637c75fc5e875f6a647b1415e7eff82eea0e9ae238e87",
+                     "tile": 1, "fetch_kib": 2971.135, "write_kib": 2534.78125},
     "batch256": {"sources": ("mct2d_step.hip", "mct2d_impl.h", "mct2d_device.h"),
-                 "sha256": "0bf7db7be35ea7425312cf2e357f174b99363e1f1e426c7a7b51b857cb032a9e",
-                 "tile": 1, "fetch_kib": 423141.03, "write_kib": 474325.76},
-    # two launches per step: k_force (15 119.40 / 19 971.80) + k_node (17 014.51 / 5 024.44)
+                 "sha256": "d86a269d08859568f10637c75fc5e875f6a647b1415e7eff82eea0e9ae238e87",
+                 "tile": 1, "fetch_kib": 424165.6375, "write_kib": 487135.1203125},
+    # two launches per step: k_force (15 001.02 / 14 990.25) + k_node (17 013.19 / 5 024.44)
     "tri320k": {"sources": ("mct2d_tri.hip", "mct2d_tri.h"),
-                "sha256": "7854e892448c80b379a2a89e19993b4091e4ea5c7537f87754d581451dad2b86",
-                "tile": 0, "fetch_kib": 32133.91, "write_kib": 24996.24},
+                "sha256": "81c2fe21c54c33547fa36ee98a02446b3e471d84241525efb584a2ed1f2f553f",
+                "tile": 1, "fetch_kib": 32014.2128125, "write_kib": 20014.6875},
+    # one launch per step: k_fused on 64-node patches (the commit, once per 64 steps, is negligible)
+    "cylinder53k": {"sources": ("mct2d_tri.hip", "mct2d_tri.h"),
+                    "sha256": "81c2fe21c54c33547fa36ee98a02446b3e471d84241525efb584a2ed1f2f553f",
+                    "tile": 2, "fetch_kib": 5298.39875, "write_kib": 868.84375},
 }
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131086.604, 262144.0 / 262144.0
 
@@ -100,12 +107,17 @@ def measured_traffic(workload: str, tile: int):
     return 1024.0 * (rec["fetch_kib"] * FETCH_SCALE + rec["write_kib"] * WRITE_SCALE)
 
 
-def cpu_baseline(cfg, steps: int):
+def cpu_baseline(cfg, seconds: float):
+    """The oracle, single-threaded, on the first time steps of the workload:
+    chunks of 10 steps until `seconds` of CPU work (a bounded sample)."""
     from oracle import oracle
     oracle.set_threads(1)
     o = oracle.Oracle(cfg)  # the binary32 build for a binary32 workload
     t0 = time.perf_counter()
-    o.step(steps)
+    steps = 0
+    while time.perf_counter() - t0 < seconds and steps < cfg["steps"]:
+        o.step(10)
+        steps += 10
     dt = time.perf_counter() - t0
     ne = n_elems(cfg)
     return {"value": ne * steps / dt, "unit": "element-updates/s", "cores": 1, "kind": "oracle",
@@ -143,7 +155,8 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="pick tile/order by measurement first")
-    ap.add_argument("--cpu-steps", type=int, default=300)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="CPU-baseline sample: oracle steps from t = 0 for about this long")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="plate400", choices=sorted(WORKLOADS))
     ap.add_argument("--smoothing", default="point", choices=("point", "subcell"),
@@ -281,7 +294,7 @@ def main():
         out["batched_vs_plain"] = {"speedup": plain_ms / gpu_ms, "plain_ms_total": plain_ms,
                                    "batched_ms": gpu_ms, "identical_crack_sets": bool(same)}
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(cfgs[0], args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(cfgs[0], args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
