@@ -107,11 +107,11 @@ def measured_traffic(workload: str, tile: int):
     return 1024.0 * (rec["fetch_kib"] * FETCH_SCALE + rec["write_kib"] * WRITE_SCALE)
 
 
-def cpu_baseline(cfg, seconds: float):
-    """The oracle, single-threaded, on the first time steps of the workload:
-    chunks of 10 steps until `seconds` of CPU work (a bounded sample)."""
+def _oracle_rate(cfg, seconds: float, threads: int):
+    """Element-updates/s of the oracle with `threads` OpenMP threads on the
+    first time steps of the workload: chunks of 10 steps until `seconds`."""
     from oracle import oracle
-    oracle.set_threads(1)
+    oracle.set_threads(threads)
     o = oracle.Oracle(cfg)  # the binary32 build for a binary32 workload
     t0 = time.perf_counter()
     steps = 0
@@ -119,10 +119,26 @@ def cpu_baseline(cfg, seconds: float):
         o.step(10)
         steps += 10
     dt = time.perf_counter() - t0
+    return n_elems(cfg) * steps / dt, steps, dt
+
+
+def cpu_baseline(cfg, seconds: float):
+    """The oracle on the host's cores (its OpenMP loops, results independent
+    of the thread count), and single-threaded beside it, each on a bounded
+    sample of the workload's first time steps."""
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, int(os.environ.get("OMP_NUM_THREADS", cores)), 16))
+    rate, steps, dt = _oracle_rate(cfg, seconds, cores)
+    rate1, steps1, dt1 = _oracle_rate(cfg, seconds, 1)
     ne = n_elems(cfg)
-    return {"value": ne * steps / dt, "unit": "element-updates/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d time steps of the same %s (%d elements; single-threaded C oracle, binary%d, %.1f s)"
-                      % (steps, cfg["name"], ne, int(cfg.get("precision", 64)), dt)}
+    return {"value": rate, "unit": "element-updates/s", "cores": cores, "kind": "oracle",
+            "sample": "first %d time steps of the same %s (%d elements; C oracle, binary%d, %d threads, %.1f s)"
+                      % (steps, cfg["name"], ne, int(cfg.get("precision", 64)), cores, dt),
+            "single_thread": {"value": rate1, "cores": 1,
+                              "sample": "first %d time steps, 1 thread, %.1f s" % (steps1, dt1)}}
 
 
 def timed_run(m, stream, steps, warmup):
