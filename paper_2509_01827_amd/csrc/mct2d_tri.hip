@@ -4,7 +4,12 @@
 // two-path element rule (Sec. 2.2, the list after Fig. 2-2), the MCT pick
 // (Sec. 3) and the central-difference update.
 //
-// One time step is two launches:
+// One time step is one fused launch or two split launches (the host picks).
+// Fused: k_fused, one workgroup per patch of consecutive nodes: the forces of
+// the patch's elements go to LDS, each owned node sums its slots in colour
+// order and is updated; u is double-buffered by step parity; with the
+// global multi-tip pick every workgroup first takes the previous step's pick
+// from its candidate set (the commit takes a segment's last).  Split:
 //   k_force  one thread per element.  An intact element computes its own
 //            strain B u and that of each intact neighbour (recomputed
 //            rather than stored: the neighbour's B and nodes are cache
