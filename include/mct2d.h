@@ -41,8 +41,12 @@
  *   - Device work is enqueued on the HIP stream given to mct_create (or on a
  *     stream the library creates when it is NULL).  mct_step returns without
  *     waiting; every query synchronises that stream first.
- *   - FP64: results are bit-reproducible run to run (fixed summation
- *     orders, no floating-point atomics).
+ *   - Binary64 (and binary32, mct_create): results are bit-reproducible run
+ *     to run and independent of the launch shape (fixed summation orders, no
+ *     floating-point atomics).
+ *   - Triangle meshes (mct_set_mesh_tri) run the same step with
+ *     constant-strain triangles (Sec. 2.1, Eqs. CST_strain_discretization,
+ *     CST_fint_discretization; the two-path rule after Fig. 2-2).
  */
 #ifndef MCT2D_H
 #define MCT2D_H
@@ -129,8 +133,8 @@ int mct_set_mesh_grid(mct_ctx *ctx, int32_t nx, int32_t ny, const double *X, con
  * space-filling curve) is the caller's choice and pays in cache reuse.
  * After this call the context runs the CST path: every set-up call, step
  * and query below applies to the triangle mesh, except the tile shapes
- * (mct_set_launch selects the step kernels instead), mct_autotune, mct_get_path_geometry
- * and the split-screen (MCT_EUNSUPPORTED).  Velocity conditions may be
+ * (mct_set_launch selects the step kernels instead), mct_autotune,
+ * mct_get_path_geometry and the split-screen (MCT_EUNSUPPORTED).  Velocity conditions may be
  * prescribed at any node.  Errors: MCT_EINVAL for an index out of range, a
  * repeated node, a non-positive area (clockwise or degenerate), an edge
  * used by more than two triangles or twice in one direction, a node in no
@@ -229,7 +233,8 @@ int mct_set_time(mct_ctx *ctx, double dt, double cfl_fraction);
 int mct_finalize(mct_ctx *ctx);
 
 /* Enqueue n_steps time steps; asynchronous.  Each step splits at most one
- * element (the MCT pick) and the split acts from the next step on. */
+ * element with the global pick (several with the per-front pick); a split
+ * acts from the next step on. */
 int mct_step(mct_ctx *ctx, int64_t n_steps);
 
 /* Wait for the enqueued work; reports asynchronous device errors, and
