@@ -221,6 +221,22 @@ int mct_set_smoothing(mct_ctx *ctx, int mode);
  * (shortest edge) / c_d with c_d = sqrt(E / (rho (1 - nu^2))). */
 int mct_set_time(mct_ctx *ctx, double dt, double cfl_fraction);
 
+/* Caller-owned device arrays for the state of a plain binary64 Q4 context
+ * (e.g. the storage of torch tensors): u^k lives in ux[k & 1], uy[k & 1]
+ * (the step reads one pair and writes the other), v in vx, vy; each array
+ * holds n_nodes doubles in node-id order.  Call before mct_finalize, which
+ * zeroes them (on the context's stream: work of other streams on them must
+ * be complete) and uses them instead of allocating its own; the caller
+ * keeps them alive until mct_destroy (or a later finalize after unbinding)
+ * and does not write them while steps are enqueued.  views = NULL unbinds (the
+ * next finalize allocates again).  Errors: MCT_EINVAL for a NULL array;
+ * MCT_EUNSUPPORTED on a batch, a binary32 context or a triangle mesh. */
+typedef struct {
+    double *ux[2], *uy[2];
+    double *vx, *vy;
+} mct_device_views;
+int mct_bind_device_buffers(mct_ctx *ctx, const mct_device_views *views);
+
 /* Build the derived arrays (lumped mass, equivalent nodal forces, time
  * step), upload everything and zero the state (u = v = 0, step 0).  Then
  * estimate the stability limit of central differences, 2 / omega_max with

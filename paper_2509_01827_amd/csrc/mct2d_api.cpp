@@ -97,6 +97,10 @@ struct mct_ctx {
     float *fvx = nullptr, *fvy = nullptr, *fminv = nullptr, *fgc = nullptr, *farea = nullptr;
     float *ffext = nullptr, *fv0 = nullptr;
     uint8_t *dvmask = nullptr, *dsplit = nullptr;
+    // caller-owned state arrays (mct_bind_device_buffers): used instead of
+    // dux, duy, dvx, dvy and never freed by the library
+    bool bound = false;
+    mct_device_views views{};
     Control *dctl = nullptr;
     Slot *dslots = nullptr;
     LogRec *dlog = nullptr;
@@ -244,6 +248,9 @@ void release_device(mct_ctx *c) {
     drop_graphs(c);
     dfree(c->dX);
     dfree(c->dY);
+    if (c->bound) {  // the caller's arrays
+        c->dux[0] = c->dux[1] = c->duy[0] = c->duy[1] = c->dvx = c->dvy = nullptr;
+    }
     for (int i = 0; i < 2; ++i) {
         dfree(c->dux[i]);
         dfree(c->duy[i]);
@@ -1057,6 +1064,19 @@ int mct_set_order(mct_ctx *c, int order) {
     return set_launch_geometry(c);
 }
 
+int mct_bind_device_buffers(mct_ctx *c, const mct_device_views *v) {
+    if (!c) return MCT_EINVAL;
+    if (c->tri) return fail(c, MCT_EUNSUPPORTED, "device buffers bind the state of a Q4 grid");
+    if (c->batch) return fail(c, MCT_EUNSUPPORTED, "device buffers need a plain context");
+    if (c->precision != 64) return fail(c, MCT_EUNSUPPORTED, "device buffers hold binary64 state");
+    if (v && (!v->ux[0] || !v->ux[1] || !v->uy[0] || !v->uy[1] || !v->vx || !v->vy))
+        return fail(c, MCT_EINVAL, "null device array");
+    release_device(c);  // the state arrays change: finalize again
+    c->bound = v != nullptr;
+    c->views = v ? *v : mct_device_views{};
+    return MCT_OK;
+}
+
 int mct_finalize(mct_ctx *c) {
     if (!c) return MCT_EINVAL;
     TRI_FWD0(c, finalize);
@@ -1164,13 +1184,23 @@ int mct_finalize(mct_ctx *c) {
     }
     if (any_gc && (rc = upload(c, c->dgc, gc))) return rc;
     for (int i = 0; i < 2; ++i) {
-        HIP_TRY(c, hipMalloc((void **)&c->dux[i], sizeof(double) * nn));
-        HIP_TRY(c, hipMalloc((void **)&c->duy[i], sizeof(double) * nn));
+        if (c->bound) {
+            c->dux[i] = c->views.ux[i];
+            c->duy[i] = c->views.uy[i];
+        } else {
+            HIP_TRY(c, hipMalloc((void **)&c->dux[i], sizeof(double) * nn));
+            HIP_TRY(c, hipMalloc((void **)&c->duy[i], sizeof(double) * nn));
+        }
         HIP_TRY(c, hipMemsetAsync(c->dux[i], 0, sizeof(double) * nn, c->stream));
         HIP_TRY(c, hipMemsetAsync(c->duy[i], 0, sizeof(double) * nn, c->stream));
     }
-    HIP_TRY(c, hipMalloc((void **)&c->dvx, sizeof(double) * nn));
-    HIP_TRY(c, hipMalloc((void **)&c->dvy, sizeof(double) * nn));
+    if (c->bound) {
+        c->dvx = c->views.vx;
+        c->dvy = c->views.vy;
+    } else {
+        HIP_TRY(c, hipMalloc((void **)&c->dvx, sizeof(double) * nn));
+        HIP_TRY(c, hipMalloc((void **)&c->dvy, sizeof(double) * nn));
+    }
     HIP_TRY(c, hipMemsetAsync(c->dvx, 0, sizeof(double) * nn, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->dvy, 0, sizeof(double) * nn, c->stream));
     if (c->precision == 32) {

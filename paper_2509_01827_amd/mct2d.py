@@ -37,6 +37,10 @@ class Info(C.Structure):
                 ("dt_limit", C.c_double), ("tip", C.c_int64)]
 
 
+class DeviceViews(C.Structure):
+    _fields_ = [("ux", C.c_void_p * 2), ("uy", C.c_void_p * 2), ("vx", C.c_void_p), ("vy", C.c_void_p)]
+
+
 EXPORTS = [
     "mct_create", "mct_destroy", "mct_last_error", "mct_set_mesh_grid", "mct_set_material",
     "mct_set_traction", "mct_set_velocity_bc", "mct_set_notch", "mct_set_time", "mct_finalize",
@@ -47,7 +51,7 @@ EXPORTS = [
     "mct_mlp_create", "mct_mlp_destroy", "mct_mlp_last_error", "mct_mlp_set_params", "mct_mlp_get_params",
     "mct_mlp_forward", "mct_mlp_gradient", "mct_mlp_train_step", "mct_get_energies", "mct_set_tracking",
     "mct_set_load_curve", "mct_set_mesh_tri", "mct_set_front_pick",
-    "mct_set_smoothing",
+    "mct_set_smoothing", "mct_bind_device_buffers",
 ]
 N_FEATURES = 10
 N_PARAMS = 4929
@@ -95,6 +99,7 @@ def load() -> C.CDLL:
     L.mct_set_load_curve.argtypes = [P, C.c_int64, dp, dp]
     L.mct_set_front_pick.argtypes = [P, C.c_double]
     L.mct_set_smoothing.argtypes = [P, C.c_int]
+    L.mct_bind_device_buffers.argtypes = [P, C.POINTER(DeviceViews)]
     L.mct_finalize.argtypes = [P]
     L.mct_step.argtypes = [P, C.c_int64]
     L.mct_sync.argtypes = [P]
@@ -219,6 +224,21 @@ class Model:
     def set_load_curve(self, t, phi):
         t, phi = _f64(t), _f64(phi)
         self._check(self._L.mct_set_load_curve(self._h, len(t), t, phi), "set_load_curve")
+
+    def bind_device_buffers(self, ux0, ux1, uy0, uy1, vx, vy):
+        """Caller-owned state arrays (torch float64 tensors on the device,
+        n_nodes each, or raw device addresses): u^k lives in (ux0, uy0) for
+        even k and (ux1, uy1) for odd k.  Call before finalize; the tensors
+        are kept referenced by this model.  None for every argument unbinds."""
+        arrs = (ux0, ux1, uy0, uy1, vx, vy)
+        if all(a is None for a in arrs):
+            self._check(self._L.mct_bind_device_buffers(self._h, None), "bind_device_buffers")
+            return
+        ptr = [a if isinstance(a, int) else a.data_ptr() for a in arrs]
+        v = DeviceViews()
+        v.ux[0], v.ux[1], v.uy[0], v.uy[1], v.vx, v.vy = ptr
+        self._check(self._L.mct_bind_device_buffers(self._h, C.byref(v)), "bind_device_buffers")
+        self._keep.append(arrs)
 
     def set_smoothing(self, mode="point"):
         """Q4 edge smoothing: "point" (default) or "subcell"."""

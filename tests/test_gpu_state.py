@@ -146,3 +146,46 @@ def test_nonfinite_state_is_reported(gpu):
     m.step(3)
     with pytest.raises(gpu.MctError, match="non-finite"):
         m.sync()
+
+
+def test_bound_device_buffers(gpu):
+    """Caller-owned state arrays (torch tensors): finalize zeroes them, the
+    step runs on them (u^k in the pair of parity k), results equal an
+    unbound run bit for bit; unsupported contexts are refused."""
+    import torch
+    cfg = W.small_cases()["plate70x37_jitter"]
+    nn = (cfg["nx"] + 1) * (cfg["ny"] + 1)
+    t = [torch.full((nn,), 7.0, dtype=torch.float64, device="cuda") for _ in range(6)]
+    torch.cuda.synchronize()
+    m = gpu.Model()
+    gpu._setup(m, cfg)
+    with pytest.raises(gpu.MctError):
+        m.bind_device_buffers(0, 0, 0, 0, 0, 0)  # null device arrays
+    m.bind_device_buffers(*t)
+    m.finalize()
+    m.sync()
+    assert all(float(x.abs().max()) == 0.0 for x in t)
+    ref = gpu.from_config(cfg)
+    m.step(301)
+    ref.step(301)
+    m.sync()
+    (ux, uy), (vx, vy) = m.field(0), m.field(1)
+    (rx, ry), (rvx, rvy) = ref.field(0), ref.field(1)
+    assert np.array_equal(ux, rx) and np.array_equal(uy, ry)
+    assert np.array_equal(vx, rvx) and np.array_equal(vy, rvy)
+    lm, lr = m.crack_set(), ref.crack_set()
+    assert len(lr["elem"]) > 0
+    for k in ("step", "elem", "entry", "exit", "G"):
+        assert np.array_equal(lm[k], lr[k])
+    torch.cuda.synchronize()
+    assert np.array_equal(t[1].cpu().numpy(), ux) and np.array_equal(t[3].cpu().numpy(), uy)  # odd step
+    assert np.array_equal(t[4].cpu().numpy(), vx) and np.array_equal(t[5].cpu().numpy(), vy)
+    m.close()
+    assert np.array_equal(t[1].cpu().numpy(), ux)  # the caller's arrays outlive the model
+    f32 = gpu.Model(precision=32)
+    f32.set_mesh_grid(cfg["nx"], cfg["ny"], cfg["X"], cfg["Y"])
+    with pytest.raises(gpu.MctError):
+        f32.bind_device_buffers(*t)
+    b = gpu.Model(n_specimens=2)
+    with pytest.raises(gpu.MctError):
+        b.bind_device_buffers(*t)
