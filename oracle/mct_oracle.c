@@ -1090,6 +1090,30 @@ orc_model_t *orc_create_tri(int nn, const double *X, const double *Y, int ne, co
     return m;
 }
 
+/* Unstructured Q4 mesh: nn nodes, ne quadrilaterals with counter-clockwise
+ * node quadruples conn[4 e + 0..3] (local edge k joins local nodes k and
+ * k+1 mod 4, as on the structured grid).  Returns NULL for an index out of
+ * range, a repeated node in one element, or a mesh build_tables rejects.
+ * Positive areas are checked at finalize. */
+orc_model_t *orc_create_q4(int nn, const double *X, const double *Y, int ne, const int *conn) {
+    if (nn < 4 || ne < 1) return NULL;
+    for (int e = 0; e < ne; ++e) {
+        const int *c = &conn[4 * e];
+        for (int n = 0; n < 4; ++n) {
+            if (c[n] < 0 || c[n] >= nn) return NULL;
+            for (int q = 0; q < n; ++q)
+                if (c[q] == c[n]) return NULL;
+        }
+    }
+    orc_model_t *m = new_model(4, nn, ne, X, Y);
+    memcpy(m->conn, conn, sizeof(int) * 4 * (size_t)ne);
+    if (build_tables(m) != ORC_OK) {
+        orc_destroy(m);
+        return NULL;
+    }
+    return m;
+}
+
 int orc_set_material(orc_model_t *m, double E, double nu, double rho, const double *Gc,
                      double Gc_uniform, double gamma) {
     if (!(E > 0.0) || !(nu > -1.0 && nu < 0.5) || !(rho > 0.0) || !(gamma > 0.0)) return ORC_EINVAL;

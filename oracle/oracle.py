@@ -55,6 +55,8 @@ def lib(precision: int = 64):
         _lib.orc_create.argtypes = [C.c_int, C.c_int, dp, dp]
         _lib.orc_create_tri.restype = P
         _lib.orc_create_tri.argtypes = [C.c_int, dp, dp, C.c_int, ip]
+        _lib.orc_create_q4.restype = P
+        _lib.orc_create_q4.argtypes = [C.c_int, dp, dp, C.c_int, ip]
         _lib.orc_destroy.argtypes = [P]
         _lib.orc_set_material.argtypes = [P, C.c_double, C.c_double, C.c_double, C.c_void_p,
                                           C.c_double, C.c_double]
@@ -142,8 +144,8 @@ def mct_pick(G, elem, a, gamma, precision=64):
 
 class Oracle:
     """One model run by the plain CPU oracle: a structured Q4 grid (cfg keys
-    nx, ny) or an unstructured CST mesh (cfg key conn, [ne][3] CCW); cfg key
-    precision 32 runs the binary32 build."""
+    nx, ny) or an unstructured mesh (cfg key conn: [ne][3] CST or [ne][4]
+    Q4, counter-clockwise); cfg key precision 32 runs the binary32 build."""
 
     def __init__(self, cfg: dict, *, finalize: bool = True):
         self.precision = int(cfg.get("precision", 64))
@@ -151,9 +153,12 @@ class Oracle:
         self.cfg = cfg
         if cfg.get("conn") is not None:
             self.nx = self.ny = 0
-            conn = _i32(np.asarray(cfg["conn"]).reshape(-1))
+            cn = np.asarray(cfg["conn"])
+            nv = cn.shape[1]
+            conn = _i32(cn.reshape(-1))
             X = _f64(cfg["X"])
-            self.h = L.orc_create_tri(len(X), X, _f64(cfg["Y"]), len(conn) // 3, conn)
+            make = L.orc_create_tri if nv == 3 else L.orc_create_q4
+            self.h = make(len(X), X, _f64(cfg["Y"]), len(conn) // nv, conn)
         else:
             self.nx, self.ny = int(cfg["nx"]), int(cfg["ny"])
             self.h = L.orc_create(self.nx, self.ny, _f64(cfg["X"]), _f64(cfg["Y"]))

@@ -319,35 +319,39 @@ def _morton_sort(T, X, Y, h):
 
 
 def _edge_map(T):
-    """{(lo, hi): [(triangle, local edge), ...]} of a triangle list."""
+    """{(lo, hi): [(element, local edge), ...]} of a triangle or
+    quadrilateral list (local edge k joins local nodes k and k+1)."""
     m = {}
+    nv = T.shape[1]
     for t in range(len(T)):
-        for k in range(3):
-            a, b = int(T[t, k]), int(T[t, (k + 1) % 3])
+        for k in range(nv):
+            a, b = int(T[t, k]), int(T[t, (k + 1) % nv])
             m.setdefault((min(a, b), max(a, b)), []).append((t, k))
     return m
 
 
 def boundary_edges(T):
-    """Edges used by one triangle, as (a, b) in that triangle's CCW
+    """Edges used by one element, as (a, b) in that element's CCW
     direction (the domain lies to the left of a -> b)."""
     out = []
+    nv = T.shape[1]
     for (lo, hi), uses in _edge_map(T).items():
         if len(uses) == 1:
             t, k = uses[0]
-            out.append((int(T[t, k]), int(T[t, (k + 1) % 3])))
+            out.append((int(T[t, k]), int(T[t, (k + 1) % nv])))
     out.sort()
     return np.asarray(out, np.int64).reshape(-1, 2)
 
 
 def strip_notch(X, Y, T, y_c, x_end):
     """Pre-notch along the line y = y_c from the left boundary (x = 0) to
-    x_end: the strip of triangles the line crosses, walked from the boundary
-    edge through each triangle's other crossed edge while that crossing lies
-    at x <= x_end.  Node sides: above means Y > y_c.  Returns (elem, entry,
-    exit) with local edge indices."""
+    x_end: the strip of elements (triangles or convex quadrilaterals) the
+    line crosses, walked from the boundary edge through each element's other
+    crossed edge while that crossing lies at x <= x_end.  Node sides: above
+    means Y > y_c.  Returns (elem, entry, exit) with local edge indices."""
     above = Y > y_c
     em = _edge_map(T)
+    nv = T.shape[1]
 
     def crossing_x(a, b):
         return X[a] + (y_c - Y[a]) / (Y[b] - Y[a]) * (X[b] - X[a])
@@ -360,9 +364,9 @@ def strip_notch(X, Y, T, y_c, x_end):
     elems, ent, ext = [], [], []
     t, ke = start
     while True:
-        ks = [k for k in range(3) if k != ke and above[T[t, k]] != above[T[t, (k + 1) % 3]]]
+        ks = [k for k in range(nv) if k != ke and above[T[t, k]] != above[T[t, (k + 1) % nv]]]
         kx = ks[0]
-        a, b = int(T[t, kx]), int(T[t, (kx + 1) % 3])
+        a, b = int(T[t, kx]), int(T[t, (kx + 1) % nv])
         if crossing_x(a, b) > x_end:
             break
         elems.append(t); ent.append(ke); ext.append(kx)
@@ -494,3 +498,131 @@ def tri_fragment(nx, ny, h, *, v=5.0, seed=BASE_SEED + 90, steps=2000, name="tri
                 vbc=(np.asarray(nodes, np.int32), np.asarray(masks, np.uint8),
                      np.ascontiguousarray(np.asarray(vel, np.float64).reshape(-1, 2))),
                 t_ramp=0.0, notch=_empty_notch(), dt=0.0, cfl=0.5, steps=steps)
+
+
+# ---------------------------------------------------------------------------
+# Unstructured Q4 meshes (general connectivity, mct_set_mesh_q4)
+
+
+def quads_from_triangles(X, Y, T, h):
+    """All-quadrilateral mesh from a triangle mesh: every triangle (a, b, c)
+    splits into the three convex quadrilaterals (a, m_ab, g, m_ca),
+    (b, m_bc, g, m_ab), (c, m_ca, g, m_bc) through its edge midpoints m and
+    centroid g, counter-clockwise like the triangle.  Nodes and elements are
+    renumbered along a Morton curve (spacing h/2); each quadrilateral starts
+    at its smallest node id.  Returns (X, Y, Q)."""
+    X = np.asarray(X, np.float64)
+    Y = np.asarray(Y, np.float64)
+    T = np.asarray(T, np.int64)
+    nn0 = len(X)
+    mid = {}
+    xs, ys = list(X), list(Y)
+
+    def midpoint(a, b):
+        key = (min(a, b), max(a, b))
+        if key not in mid:
+            mid[key] = len(xs)
+            xs.append(0.5 * (X[a] + X[b]))
+            ys.append(0.5 * (Y[a] + Y[b]))
+        return mid[key]
+
+    quads = []
+    for t in range(len(T)):
+        a, b, c = (int(v) for v in T[t])
+        mab, mbc, mca = midpoint(a, b), midpoint(b, c), midpoint(c, a)
+        g = len(xs)
+        xs.append((X[a] + X[b] + X[c]) / 3.0)
+        ys.append((Y[a] + Y[b] + Y[c]) / 3.0)
+        quads += [(a, mab, g, mca), (b, mbc, g, mab), (c, mca, g, mbc)]
+    Xq, Yq = np.asarray(xs), np.asarray(ys)
+    Q = np.asarray(quads, np.int64)
+    assert len(Xq) == nn0 + len(mid) + len(T)
+    perm = morton_nodes(Xq, Yq, 0.5 * h)
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(len(perm))
+    Xq, Yq, Q = Xq[perm], Yq[perm], inv[Q]
+    r = np.argmin(Q, axis=1)
+    Q = np.stack([Q[np.arange(len(Q)), (r + q) % 4] for q in range(4)], axis=1)
+    cx, cy = Xq[Q].mean(axis=1), Yq[Q].mean(axis=1)
+    order = np.lexsort((Q[:, 3], Q[:, 2], Q[:, 1], Q[:, 0], _morton_key(cx, cy, 0.5 * h)))
+    return np.ascontiguousarray(Xq), np.ascontiguousarray(Yq), np.ascontiguousarray(Q[order].astype(np.int32))
+
+
+def quad_plate(nx, ny, lx, ly, *, traction=1.0e6, jitter=0.3, seed=BASE_SEED + 100, notch_len=None,
+               gc=GC_PLATE, gamma=1.0, steps=2000, cfl=0.5, name="quad_plate"):
+    """The Neumann branching plate on an unstructured all-quadrilateral mesh:
+    the CST plate's Delaunay triangles (points of an (nx+1) x (ny+1) grid
+    moved by +/-``jitter`` h) each split into three quadrilaterals; 1 MPa
+    normal traction on the upper and lower edges; pre-notch of length
+    ``notch_len`` (m) along a line just above mid-height from the left
+    edge."""
+    X, Y = grid_coords(nx, ny, lx, ly, jitter, seed)
+    h = min(lx / nx, ly / ny)
+    T = _triangulate(X, Y, h)[1]
+    X, Y, Q = quads_from_triangles(X, Y, T, h)
+    be = boundary_edges(Q)
+    top = (Y[be[:, 0]] == ly) & (Y[be[:, 1]] == ly)
+    bot = (Y[be[:, 0]] == 0.0) & (Y[be[:, 1]] == 0.0)
+    tn = np.concatenate([be[bot], be[top]]).astype(np.int32)
+    tt = np.zeros((len(tn), 2))
+    tt[:bot.sum(), 1] = -traction
+    tt[bot.sum():, 1] = traction
+    # the notch line avoids the nodes (grid rows, midpoints, centroids)
+    notch = strip_notch(X, Y, Q, 0.5 * ly + 0.137 * h, notch_len) if notch_len else _empty_notch()
+    return dict(name=name, conn=Q, X=X, Y=Y, E=E_PLATE, nu=NU_PLATE, rho=RHO_PLATE,
+                gc_uniform=gc, gc_field=None, gamma=gamma,
+                traction_nodes=np.ascontiguousarray(tn), traction=np.ascontiguousarray(tt),
+                vbc=_empty_bc(), t_ramp=0.0, notch=notch, dt=0.0, cfl=cfl, steps=steps)
+
+
+def as_unstructured_q4(cfg, seed=BASE_SEED + 110):
+    """A structured-grid workload written as an unstructured Q4 mesh: nodes
+    and elements in a seeded random order, each element's node list rotated
+    by a seeded offset (local edge k of the grid element becomes local edge
+    k - r).  Loads, prescribed velocities, Gc and the notch follow."""
+    nx, ny = cfg["nx"], cfg["ny"]
+    nn, ne = (nx + 1) * (ny + 1), nx * ny
+    u = uniform01(seed, nn + 2 * ne)
+    pn = np.argsort(u[:nn], kind="stable")          # new id -> old id
+    pe = np.argsort(u[nn:nn + ne], kind="stable")
+    rot = np.floor(4.0 * u[nn + ne:]).astype(np.int64) % 4  # per new element
+    inv_n = np.empty(nn, np.int64)
+    inv_n[pn] = np.arange(nn)
+    inv_e = np.empty(ne, np.int64)
+    inv_e[pe] = np.arange(ne)
+    Q = np.empty((ne, 4), np.int64)
+    for e_new in range(ne):
+        e = int(pe[e_new])
+        i, j = e % nx, e // nx
+        nd = [j * (nx + 1) + i, j * (nx + 1) + i + 1, (j + 1) * (nx + 1) + i + 1, (j + 1) * (nx + 1) + i]
+        r = int(rot[e_new])
+        Q[e_new] = [inv_n[nd[(q + r) % 4]] for q in range(4)]
+    c = dict(cfg)
+    c.pop("nx"); c.pop("ny")
+    c["name"] = cfg.get("name", "grid") + "_unstructured"
+    c["X"] = np.ascontiguousarray(cfg["X"][pn])
+    c["Y"] = np.ascontiguousarray(cfg["Y"][pn])
+    c["conn"] = np.ascontiguousarray(Q.astype(np.int32))
+    tn = np.asarray(cfg["traction_nodes"], np.int64)
+    c["traction_nodes"] = np.ascontiguousarray(inv_n[tn].astype(np.int32)) if len(tn) else tn.astype(np.int32)
+    vn, vm, vv = cfg["vbc"]
+    c["vbc"] = (np.ascontiguousarray(inv_n[np.asarray(vn, np.int64)].astype(np.int32)), vm, vv)
+    if cfg.get("gc_field") is not None:
+        c["gc_field"] = np.ascontiguousarray(np.asarray(cfg["gc_field"])[pe])
+    el, en, ex = cfg["notch"]
+    el = np.asarray(el, np.int64)
+    rr = rot[inv_e[el]] if len(el) else np.zeros(0, np.int64)
+    c["notch"] = (np.ascontiguousarray(inv_e[el].astype(np.int32)),
+                  np.ascontiguousarray(((np.asarray(en, np.int64) - rr) % 4).astype(np.uint8)),
+                  np.ascontiguousarray(((np.asarray(ex, np.int64) - rr) % 4).astype(np.uint8)))
+    c["perm"] = (pn, pe, rot)
+    return c
+
+
+def quad_small_cases():
+    """Unstructured Q4 parity cases: the jittered 70 x 37 plate renumbered,
+    and a plate of quadrilaterals split from triangles (irregular valences)."""
+    return {
+        "grid70x37_unstructured": as_unstructured_q4(small_cases()["plate70x37_jitter"]),
+        "quad_plate24x10": quad_plate(24, 10, 0.1, 0.04, notch_len=0.05, steps=1200),
+    }
