@@ -68,6 +68,7 @@ def bytes_per_step(cfgs, precision: int = 64) -> int:
 # of a 256 MiB device copy (FETCH_SIZE x 1.99979, WRITE_SIZE x 1.0).  A figure
 # holds for the kernel sources it was taken on (their hash) and the tile
 # shape; otherwise the traffic is reported as unknown.
+TRI_SOURCES = ("mct2d_tri.hip", "mct2d_tri.h", "mct2d_front.h", "mct2d_device.h", "mct2d_impl.h")
 MEASURED_TRAFFIC = {
     "plate400": {"sources": ("mct2d_step.hip", "mct2d_impl.h", "mct2d_device.h"),
                  "sha256": "a1bff16478392399f4310c25dd04486078e02be2e0f4ec6a09126a222be5fce0",
@@ -78,14 +79,12 @@ MEASURED_TRAFFIC = {
     "batch256": {"sources": ("mct2d_step.hip", "mct2d_impl.h", "mct2d_device.h"),
                  "sha256": "a1bff16478392399f4310c25dd04486078e02be2e0f4ec6a09126a222be5fce0",
                  "tile": 1, "fetch_kib": 424165.6375, "write_kib": 487135.1203125},
-    # two launches per step: k_force (15 001.02 / 14 990.25) + k_node (17 013.19 / 5 024.44)
-    "tri320k": {"sources": ("mct2d_tri.hip", "mct2d_tri.h"),
-                "sha256": "fca6fd65cfd16805d02797cfe8831d01951623b888afc4e440dad1941056a3ac",
-                "tile": 1, "fetch_kib": 32014.2128125, "write_kib": 20014.6875},
+    # two launches per step: k_force (15 006.20 / 14 990.25) + k_node (17 011.00 / 5 024.44)
+    "tri320k": {"sources": TRI_SOURCES, "sha256": "6b7235fdbe3f2b76d4adc9549deae7e98228ff110a5f0582efd67564561afb1d",
+                "tile": 1, "fetch_kib": 32017.2, "write_kib": 20014.6875},
     # one launch per step: k_fused on 64-node patches (the commit, once per 64 steps, is negligible)
-    "cylinder53k": {"sources": ("mct2d_tri.hip", "mct2d_tri.h"),
-                    "sha256": "fca6fd65cfd16805d02797cfe8831d01951623b888afc4e440dad1941056a3ac",
-                    "tile": 2, "fetch_kib": 5298.39875, "write_kib": 868.84375},
+    "cylinder53k": {"sources": TRI_SOURCES, "sha256": "6b7235fdbe3f2b76d4adc9549deae7e98228ff110a5f0582efd67564561afb1d",
+                    "tile": 2, "fetch_kib": 5302.844375, "write_kib": 868.84375},
 }
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131086.604, 262144.0 / 262144.0
 

@@ -46,7 +46,9 @@
  *     floating-point atomics).
  *   - Triangle meshes (mct_set_mesh_tri) run the same step with
  *     constant-strain triangles (Sec. 2.1, Eqs. CST_strain_discretization,
- *     CST_fint_discretization; the two-path rule after Fig. 2-2).
+ *     CST_fint_discretization; the two-path rule after Fig. 2-2), and
+ *     quadrilateral meshes of any connectivity (mct_set_mesh_q4) the Q4 step
+ *     of the structured grid.
  */
 #ifndef MCT2D_H
 #define MCT2D_H
@@ -141,6 +143,27 @@ int mct_set_mesh_grid(mct_ctx *ctx, int32_t nx, int32_t ny, const double *X, con
  * triangle; MCT_EUNSUPPORTED on a batch context. */
 int mct_set_mesh_tri(mct_ctx *ctx, int64_t n_nodes, const double *X, const double *Y, int64_t n_elems,
                      const int32_t *conn);
+
+/* Mesh of bilinear quadrilaterals with general connectivity (the Q4 element
+ * of Sec. 2.1, Eq. QUAD_strain_discretization; Sec. 2.2, the four-edge rule
+ * after Fig. 2-3): n_nodes reference coordinates X, Y and n_elems
+ * counter-clockwise node quadruples conn[4 e + 0..3] (plain binary64
+ * contexts only).  Local edge k joins local nodes k and (k+1) % 4, with the
+ * edge midpoints at natural coordinates (0,-1), (1,0), (0,1), (-1,0) as on
+ * the structured grid; the step is the grid's, with neighbours taken from
+ * the connectivity: B of each element at the midpoint of its own local edge,
+ * c_{e,k} = A_e / 4, w_j = A_j / (A_lo + A_hi), lumped mass rho A / 4, the
+ * Q4 piece forces of split elements, greedy colouring in element-id order.
+ * Split codes and crack records use these local edges (entry/exit in 0..3).
+ * Ids are the caller's (no renumbering).  After this call every set-up call,
+ * step and query below applies to this mesh as for mct_set_mesh_tri, with
+ * the same exceptions; the step always runs the element kernel plus the
+ * node kernel (mct_set_launch tile 2..4 falls back to them), and sub-cell
+ * smoothing is for structured grids only.  Errors: as mct_set_mesh_tri, and
+ * MCT_EINVAL for a quadrilateral that is not convex (every corner turning
+ * left). */
+int mct_set_mesh_q4(mct_ctx *ctx, int64_t n_nodes, const double *X, const double *Y, int64_t n_elems,
+                    const int32_t *conn);
 
 /* Linear elastic plane-stress material (Young's modulus E, Poisson ratio
  * nu, density rho) and critical energy release rate: Gc[e] per element

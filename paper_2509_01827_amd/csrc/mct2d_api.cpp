@@ -126,8 +126,9 @@ struct mct_ctx {
     double *dpow = nullptr;    // power iteration: y, u, z, scratch (2 nn_max each)
     int32_t *dflag = nullptr;  // non-finite watchdog
 
-    // CST path: set by mct_set_mesh_tri (plain contexts only); the ABI
-    // forwards every call of such a context to it
+    // unstructured-mesh path (triangles or quadrilaterals): set by
+    // mct_set_mesh_tri / mct_set_mesh_q4 (plain binary64 contexts only); the
+    // ABI forwards every call of such a context to it
     mct::tri::Model *tri = nullptr;
 
     // learned split-screen (plain contexts only)
@@ -169,7 +170,7 @@ int fail(mct_ctx *c, int code, const char *fmt, ...) {
             return fail((ctx), MCT_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));               \
     } while (0)
 
-// Forward a call of a CST context to the triangle path.
+// Forward a call of an unstructured-mesh context to its path.
 #define TRI_FWD(c, fn, ...)                                               \
     do {                                                                 \
         if ((c)->tri) return mct::tri::fn(*(c)->tri, mct::tri::Host{(c)->err, (c)->stream}, __VA_ARGS__); \
@@ -180,7 +181,7 @@ int fail(mct_ctx *c, int code, const char *fmt, ...) {
     } while (0)
 #define TRI_UNSUPPORTED(c, what)                                                     \
     do {                                                                             \
-        if ((c)->tri) return fail((c), MCT_EUNSUPPORTED, "%s: not for a triangle mesh", what); \
+        if ((c)->tri) return fail((c), MCT_EUNSUPPORTED, "%s: not for an unstructured mesh", what); \
     } while (0)
 
 template <typename T>
@@ -830,23 +831,36 @@ int mct_destroy(mct_ctx *c) {
 
 const char *mct_last_error(const mct_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
-int mct_set_mesh_tri(mct_ctx *c, int64_t n_nodes, const double *X, const double *Y, int64_t n_elems,
-                     const int32_t *conn) {
+// Both unstructured element kinds run on the unstructured-mesh path.
+static int set_mesh_unstructured(mct_ctx *c, int nv, int64_t n_nodes, const double *X, const double *Y,
+                                 int64_t n_elems, const int32_t *conn) {
     if (!c) return MCT_EINVAL;
-    if (c->batch) return fail(c, MCT_EUNSUPPORTED, "triangle meshes need a plain context");
-    if (c->precision == 32) return fail(c, MCT_EUNSUPPORTED, "triangle meshes need a binary64 context");
+    const char *what = nv == 4 ? "unstructured quadrilateral" : "triangle";
+    if (c->batch) return fail(c, MCT_EUNSUPPORTED, "%s meshes need a plain context", what);
+    if (c->precision == 32) return fail(c, MCT_EUNSUPPORTED, "%s meshes need a binary64 context", what);
     release_device(c);
     c->specs.assign(1, Spec{});
     c->finalized = false;
     if (!c->tri) c->tri = new (std::nothrow) mct::tri::Model;
     if (!c->tri) return MCT_ENOMEM;
-    const int rc = mct::tri::set_mesh(*c->tri, mct::tri::Host{c->err, c->stream}, n_nodes, X, Y, n_elems, conn);
+    const int rc =
+        mct::tri::set_mesh(*c->tri, mct::tri::Host{c->err, c->stream}, nv, n_nodes, X, Y, n_elems, conn);
     if (rc) {
         mct::tri::release(*c->tri);
         delete c->tri;
         c->tri = nullptr;
     }
     return rc;
+}
+
+int mct_set_mesh_tri(mct_ctx *c, int64_t n_nodes, const double *X, const double *Y, int64_t n_elems,
+                     const int32_t *conn) {
+    return set_mesh_unstructured(c, 3, n_nodes, X, Y, n_elems, conn);
+}
+
+int mct_set_mesh_q4(mct_ctx *c, int64_t n_nodes, const double *X, const double *Y, int64_t n_elems,
+                    const int32_t *conn) {
+    return set_mesh_unstructured(c, 4, n_nodes, X, Y, n_elems, conn);
 }
 
 int mct_set_mesh_grid(mct_ctx *c, int32_t nx, int32_t ny, const double *X, const double *Y) {
@@ -1017,7 +1031,7 @@ int mct_set_smoothing(mct_ctx *c, int mode) {
     if (mode != MCT_SMOOTH_POINT && mode != MCT_SMOOTH_SUBCELL) return fail(c, MCT_EINVAL, "unknown smoothing %d", mode);
     if (c->tri) {
         if (mode == MCT_SMOOTH_SUBCELL)
-            return fail(c, MCT_EUNSUPPORTED, "sub-cell smoothing is for Q4 grids (CST smoothing is exact)");
+            return fail(c, MCT_EUNSUPPORTED, "sub-cell smoothing is for structured Q4 grids");
         return MCT_OK;
     }
     if (c->batch && mode == MCT_SMOOTH_SUBCELL)

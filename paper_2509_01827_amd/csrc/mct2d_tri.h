@@ -34,18 +34,26 @@ constexpr int32_t kOwned = 1 << 30;    // patch element flag: evaluate its candi
 // Node flags (one byte per node).
 constexpr uint8_t kFixX = 1, kFixY = 2, kLoaded = 4;
 
-// The kernels' view of one CST mesh.  Nodal vectors are interleaved
-// (x, y) pairs so that one 16-byte load fetches both components.
+// The kernels' view of one unstructured mesh: constant-strain triangles
+// (nv = 3) or bilinear quadrilaterals (nv = 4).  Nodal vectors are
+// interleaved (x, y) pairs so that one 16-byte load fetches both components.
 struct Params {
     int32_t nn, ne;
     int32_t log_cap;
     int32_t sct;     // 1: single crack-tip tracking
     int32_t ncurve;  // traction load curve points (0: constant tractions)
-    int32_t pad;
-    const int4 *conn;    // per element: nodes n0 n1 n2 (CCW), .w unused
+    int32_t nv;      // nodes (and edges) per element: 3 or 4
+    const int4 *conn;    // per element: nodes n0 n1 n2 (n3) (CCW); .w unused for triangles
     const int4 *nbr;     // per element: neighbour across local edge k = 0, 1, 2 (-1: none);
                          // .w: local index of that edge in the neighbour, 2 bits per k
     const int4 *opp;     // per element: the neighbour's node off the shared edge k (-1: none)
+    // quadrilaterals: neighbour across local edge k = 0..3 (-1: none), the
+    // local index of that edge in the neighbour (2 bits per k), and the
+    // neighbour's two nodes off the shared edge (its local nodes loc + 2 and
+    // loc + 3; the shared edge runs backwards in the neighbour)
+    const int4 *q_nbr;
+    const uint8_t *q_loc;
+    const int4 *q_oa, *q_ob;
     const double2 *xy;   // reference coordinates
     double2 *u0, *u1;    // displacement u^k in buffer k & 1 (ping-pong: a step reads one, writes the other)
     double2 *v;          // velocity
@@ -95,8 +103,8 @@ struct Params {
 
 // Evaluation outputs of the query kernels (nullptr = skip).
 struct Eval {
-    double *sig_ek;     // 9 per element: stress at local edge k (NaN where no intact neighbour)
-    double *es_ek;      // 3 per element: 1/2 A_s sigma:eps of local edge k where this element
+    double *sig_ek;     // 3 nv per element: stress at local edge k (NaN where no intact neighbour)
+    double *es_ek;      // nv per element: 1/2 A_s sigma:eps of local edge k where this element
                         // owns the edge (lower-id intact neighbour), else 0
     double *pe;         // per element: strain energy of the split pieces
     double *principal;  // per element: largest principal stress of the mean edge stress (NaN split)

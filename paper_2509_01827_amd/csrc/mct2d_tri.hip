@@ -29,6 +29,7 @@
 // launch geometry.
 #include <cmath>
 
+#include "mct2d_device.h"
 #include "mct2d_front.h"
 #include "mct2d_tri.h"
 
@@ -255,6 +256,284 @@ __device__ __forceinline__ double2 piece_force_at(const Piece &a, const Piece &b
     return make_double2(0.0, 0.0);
 }
 
+// ---- bilinear quadrilaterals (nv = 4) -----------------------------------
+// The Q4 form of the step on an unstructured mesh (Sec. 2.1,
+// Eq. QUAD_strain_discretization, edge quadrature at the midpoints of the
+// element's own local edges; the four-edge rule after Fig. 2-3): the same
+// arithmetic as the structured grid's step, with the neighbours found
+// through tables instead of grid indices.
+
+template <typename T>
+__device__ __forceinline__ T sel4(int n, const T &a, const T &b, const T &c, const T &d) {
+    return n == 0 ? a : (n == 1 ? b : (n == 2 ? c : d));
+}
+
+// Area of a quadrilateral: half the cross product of its diagonals.
+__device__ __forceinline__ double quad_area(const double x[4], const double y[4]) {
+    return 0.5 * ((x[2] - x[0]) * (y[3] - y[1]) - (x[3] - x[1]) * (y[2] - y[0]));
+}
+
+// One piece of a split quadrilateral: the np = 1..3 local nodes after the
+// entry edge up to the exit edge, closed by the two crack midpoints (area
+// by a fan from the entry midpoint).  Three nodes: a constant-strain
+// triangle over them whose forces are scaled by the piece's area; two: a
+// bar along them with cross-section A_piece / L; one: nothing.  F[d] is the
+// force on local node (entry + 1 + d) mod 4.
+struct QPiece {
+    int l0, np;
+    double2 F[3];
+    double w;  // strain energy
+};
+
+__device__ __forceinline__ QPiece quad_piece(const Params &p, const double2 ue[4], const double x[4],
+                                             const double y[4], int entry, int exit) {
+    QPiece r;
+    r.l0 = (entry + 1) & 3;
+    r.np = (exit - entry) & 3;
+    r.w = 0.0;
+    r.F[0] = r.F[1] = r.F[2] = make_double2(0.0, 0.0);
+    if (r.np == 1) return r;
+    const int l1 = (entry + 2) & 3, l2 = (entry + 3) & 3, e1 = (entry + 1) & 3, x1 = (exit + 1) & 3;
+    const double px0 = 0.5 * (sel4(entry, x[0], x[1], x[2], x[3]) + sel4(e1, x[0], x[1], x[2], x[3]));
+    const double py0 = 0.5 * (sel4(entry, y[0], y[1], y[2], y[3]) + sel4(e1, y[0], y[1], y[2], y[3]));
+    const double pxm = 0.5 * (sel4(exit, x[0], x[1], x[2], x[3]) + sel4(x1, x[0], x[1], x[2], x[3]));
+    const double pym = 0.5 * (sel4(exit, y[0], y[1], y[2], y[3]) + sel4(x1, y[0], y[1], y[2], y[3]));
+    const double2 P0 = make_double2(sel4(r.l0, x[0], x[1], x[2], x[3]), sel4(r.l0, y[0], y[1], y[2], y[3]));
+    const double2 P1 = make_double2(sel4(l1, x[0], x[1], x[2], x[3]), sel4(l1, y[0], y[1], y[2], y[3]));
+    const double2 P2 = make_double2(sel4(l2, x[0], x[1], x[2], x[3]), sel4(l2, y[0], y[1], y[2], y[3]));
+    // fan terms over the polygon M_entry, P0, .., M_exit
+    double s = 0.0;
+    s += (P0.x - px0) * (P1.y - py0) - (P1.x - px0) * (P0.y - py0);
+    if (r.np == 3) {
+        s += (P1.x - px0) * (P2.y - py0) - (P2.x - px0) * (P1.y - py0);
+        s += (P2.x - px0) * (pym - py0) - (pxm - px0) * (P2.y - py0);
+    } else {
+        s += (P1.x - px0) * (pym - py0) - (pxm - px0) * (P1.y - py0);
+    }
+    const double Ap = 0.5 * s;
+    const double2 u0 = sel4(r.l0, ue[0], ue[1], ue[2], ue[3]), u1 = sel4(l1, ue[0], ue[1], ue[2], ue[3]);
+    if (r.np == 2) {
+        const double dx = P1.x - P0.x, dy = P1.y - P0.y;
+        const double L2 = dx * dx + dy * dy;
+        const double dux = u1.x - u0.x, duy = u1.y - u0.y;
+        const double str = (dx * dux + dy * duy) / L2;
+        const double stress = p.E * str;
+        const double coef = Ap * stress / L2;
+        r.F[1] = make_double2(coef * dx, coef * dy);
+        r.F[0] = make_double2(-(coef * dx), -(coef * dy));
+        r.w = 0.5 * Ap * stress * str;
+        return r;
+    }
+    const double2 u3[3] = {u0, u1, sel4(l2, ue[0], ue[1], ue[2], ue[3])};
+    const Geo g = make_geo(P0, P1, P2);
+    double q[3], sg[3];
+    strain(g, u3, q);
+    hooke(p, q, sg);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        r.F[i] = make_double2(Ap * fma(g.by[i], sg[2], g.bx[i] * sg[0]), Ap * fma(g.bx[i], sg[2], g.by[i] * sg[1]));
+    r.w = 0.5 * Ap * ((sg[0] * q[0] + sg[1] * q[1]) + sg[2] * q[2]);
+    return r;
+}
+
+// Force of a split quadrilateral's pieces on local node n (every node lies
+// in exactly one piece).
+__device__ __forceinline__ double2 qpiece_force_at(const QPiece &a, const QPiece &b, int n) {
+    const int da = (n - a.l0) & 3, db = (n - b.l0) & 3;
+    if (da < a.np) return sel3(da, a.F[0], a.F[1], a.F[2]);
+    return sel3(db, b.F[0], b.F[1], b.F[2]);
+}
+
+// Everything a quadrilateral element contributes to one pass: its four
+// nodal forces into the slot-major force array, with `cands` its crack-tip
+// candidates, with EVAL the query outputs.  An intact element computes the
+// strain of each local edge k at the edge's midpoint from its own nodes and,
+// if the neighbour across k is intact, that of the neighbour at the same
+// edge (recomputed in the neighbour's own node order: its local nodes loc,
+// loc+1 are our k+1, k and loc+2, loc+3 come from the tables), smooths them
+// with w = A_lo / (A_lo + A_hi), applies Hooke's law and adds
+// B_k^T sigma_k over k = 0..3, scaled by A/4 (Sec. 2.1, the c_{e,k} = A/4
+// reading).  A free-surface edge a (no intact neighbour) is a candidate: G
+// of the three paths k = a+1, a+2, a+3 with the stretch gate, then the
+// four-edge element rule (Sec. 2.2).
+template <bool EVAL>
+__device__ __forceinline__ void quad_element(const Params &p, const SplitView &sv, const double2 *u, int e,
+                                             bool cands, Cand *clist, int32_t *ccount, const Eval &ev) {
+    const int4 c = p.conn[e];
+    const uint8_t code = sv(e);
+    double2 *fe = p.fe + e;
+    const int64_t fs = p.ne;
+    double2 ue[4], xe[4];
+    ue[0] = u[c.x];
+    ue[1] = u[c.y];
+    ue[2] = u[c.z];
+    ue[3] = u[c.w];
+    xe[0] = p.xy[c.x];
+    xe[1] = p.xy[c.y];
+    xe[2] = p.xy[c.z];
+    xe[3] = p.xy[c.w];
+    double x[4], y[4];
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        x[n] = xe[n].x;
+        y[n] = xe[n].y;
+    }
+    if (code) {
+        const QPiece pa = quad_piece(p, ue, x, y, (code >> 2) & 3, code & 3);
+        const QPiece pb = quad_piece(p, ue, x, y, code & 3, (code >> 2) & 3);
+#pragma unroll
+        for (int n = 0; n < 4; ++n) fe[n * fs] = qpiece_force_at(pa, pb, n);
+        if constexpr (EVAL) {
+            double w = pa.w;
+            w += pb.w;
+            if (ev.pe) ev.pe[e] = w;
+            if (ev.es_ek)
+                for (int k = 0; k < 4; ++k) ev.es_ek[4 * (int64_t)e + k] = 0.0;
+            if (ev.principal) ev.principal[e] = NAN;
+            if (ev.sig_ek)
+                for (int k = 0; k < 12; ++k) ev.sig_ek[12 * (int64_t)e + k] = NAN;
+        }
+        return;
+    }
+    const double A = quad_area(x, y);
+    const int4 nb = p.q_nbr[e];
+    const uint32_t lc = p.q_loc[e];
+    const int4 oa = p.q_oa[e], ob = p.q_ob[e];
+    double ux[4], uy[4];
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        ux[n] = ue[n].x;
+        uy[n] = ue[n].y;
+    }
+    double sig[4][3], eps[4][3], An[4], sx[4], sy[4];
+    bool two[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double gx[4], gy[4], q[3];
+        dev::q4_grad(x, y, k, gx, gy);
+        dev::strain<4>(gx, gy, ux, uy, q);
+        const int n = sel4(k, nb.x, nb.y, nb.z, nb.w);
+        two[k] = n >= 0 && sv(n) == 0;
+        An[k] = 0.0;
+        if (!two[k]) {
+            eps[k][0] = q[0];
+            eps[k][1] = q[1];
+            eps[k][2] = q[2];
+        } else {
+            const int loc = (lc >> (2 * k)) & 3;
+            const int ia = sel4(k, oa.x, oa.y, oa.z, oa.w), ib = sel4(k, ob.x, ob.y, ob.z, ob.w);
+            const double2 XA = p.xy[ia], XB = p.xy[ib], UA = u[ia], UB = u[ib];
+            const int k1 = (k + 1) & 3;
+            double x2[4], y2[4], u2x[4], u2y[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int t = (m - loc) & 3;
+                x2[m] = sel4(t, x[k1], x[k], XA.x, XB.x);
+                y2[m] = sel4(t, y[k1], y[k], XA.y, XB.y);
+                u2x[m] = sel4(t, ux[k1], ux[k], UA.x, UB.x);
+                u2y[m] = sel4(t, uy[k1], uy[k], UA.y, UB.y);
+            }
+            const double A2 = quad_area(x2, y2);
+            double hx[4], hy[4], q2[3];
+            dev::q4_grad_rt(x2, y2, loc, hx, hy);
+            dev::strain<4>(hx, hy, u2x, u2y, q2);
+            An[k] = A2;
+            const bool self_lo = e < n;
+            const double Alo = self_lo ? A : A2, Ahi = self_lo ? A2 : A;
+            const double sum = Alo + Ahi;
+            const double w0 = Alo / sum, w1 = Ahi / sum;
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                const double lo = self_lo ? q[cc] : q2[cc], hi = self_lo ? q2[cc] : q[cc];
+                eps[k][cc] = fma(w1, hi, w0 * lo);
+            }
+        }
+        hooke(p, eps[k], sig[k]);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const double tx = fma(gy[m], sig[k][2], gx[m] * sig[k][0]);
+            const double ty = fma(gx[m], sig[k][2], gy[m] * sig[k][1]);
+            sx[m] = k == 0 ? tx : sx[m] + tx;
+            sy[m] = k == 0 ? ty : sy[m] + ty;
+        }
+    }
+    const double cA = 0.25 * A;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) fe[m * fs] = make_double2(cA * sx[m], cA * sy[m]);
+    if constexpr (EVAL) {
+        if (ev.pe) ev.pe[e] = 0.0;
+        if (ev.sig_ek)
+            for (int k = 0; k < 4; ++k)
+                for (int cc = 0; cc < 3; ++cc) ev.sig_ek[12 * (int64_t)e + 3 * k + cc] = sig[k][cc];
+        if (ev.es_ek) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int n = sel4(k, nb.x, nb.y, nb.z, nb.w);
+                double term = 0.0;
+                if (!two[k] || e < n) {
+                    // smoothing domain: a quarter of each intact neighbour,
+                    // lower element id first
+                    double As = 0.0;
+                    As += A / 4.0;
+                    if (two[k]) As += An[k] / 4.0;
+                    term = 0.5 * As * (sig[k][0] * eps[k][0] + sig[k][1] * eps[k][1] + sig[k][2] * eps[k][2]);
+                }
+                ev.es_ek[4 * (int64_t)e + k] = term;
+            }
+        }
+        if (ev.principal) {
+            double m[3];
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) m[cc] = (((sig[0][cc] + sig[1][cc]) + sig[2][cc]) + sig[3][cc]) / 4.0;
+            const double cc = 0.5 * (m[0] + m[1]), hd = 0.5 * (m[0] - m[1]);
+            ev.principal[e] = cc + sqrt(hd * hd + m[2] * m[2]);
+        }
+        return;
+    }
+    if (!cands || (two[0] && two[1] && two[2] && two[3])) return;
+    const int tip = p.sct ? p.ctl->tip : -1;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        if (two[a]) continue;
+        if (p.sct && tip != 4 * e + a) continue;
+        const int a1 = (a + 1) & 3;
+        const double dux = ux[a1] - ux[a], duy = uy[a1] - uy[a];
+        const double x1 = x[a] + ux[a], y1 = y[a] + uy[a];
+        const double x2 = x[a1] + ux[a1], y2 = y[a1] + uy[a1];
+        const double lx = x2 - x1, ly = y2 - y1;
+        const double Lx = x[a1] - x[a], Ly = y[a1] - y[a];
+        if (!((lx * lx + ly * ly) > (Lx * Lx + Ly * Ly))) continue;  // H = 0: every G is 0
+        double G[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int k = (a + 1 + j) & 3;
+            double nx, ny, len;
+            dev::path_geom(x, y, a, k, nx, ny, len);
+            const double spx = fma(sig[k][2], ny, sig[k][0] * nx);
+            const double spy = fma(sig[k][1], ny, sig[k][2] * nx);
+            G[j] = 0.5 * fma(duy, spy, dux * spx);
+        }
+        const double Gc = p.gc[e];
+        int best = -1;
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            if (G[j] > Gc && (best < 0 || G[j] > sel3(best, G[0], G[1], G[2]))) best = j;
+        if (best < 0) continue;
+        const double Gb = sel3(best, G[0], G[1], G[2]);
+        bool ok = true;
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            if (j != best && G[j] > Gc && !(Gb > p.gamma * (Gb - G[j]))) ok = false;
+        if (!ok) continue;
+        const int slot = atomicAdd(ccount, 1);
+        Cand cd;
+        cd.G = Gb;
+        cd.elem = e;
+        cd.ak = (a << 2) | ((a + 1 + best) & 3);
+        clist[slot] = cd;
+    }
+}
+
 // Forces of element e on its three local nodes from displacement u (the
 // step's element pass).  An intact element computes its own strain and that
 // of each intact neighbour (recomputed from u and the coordinates; the
@@ -435,6 +714,17 @@ __global__ __launch_bounds__(kB) void k_force(Params p, const double2 *u, Eval e
     }
 }
 
+// Element pass of a quadrilateral mesh (as k_force).
+template <bool EVAL>
+__global__ __launch_bounds__(kB) void k_qforce(Params p, const double2 *u, Eval ev, int j) {
+    const int e = blockIdx.x * kB + threadIdx.x;
+    if (e >= p.ne) return;
+    if constexpr (!EVAL) {
+        if (((p.ctl->base + j) & 1) != 0) u = p.u1;  // u^k
+    }
+    quad_element<EVAL>(p, SplitView{p.split, -1, 0}, u, e, !EVAL, p.cand, &p.ctl->nacc, ev);
+}
+
 __device__ __forceinline__ double load_factor(const Params &p, double t) {
     if (p.ncurve == 0) return 1.0;
     if (t <= p.curve_t[0]) return p.curve_phi[0];
@@ -517,12 +807,26 @@ __device__ void apply_pick(const Params &p, const Cand &b, int64_t k) {
     ctl->nsplit = ns + 1;
     const int4 c = p.conn[e];
     double nx, ny, len;
-    path_geom(p, c, a, kx, nx, ny, len);
+    if (p.nv == 4) {
+        const double2 P0 = p.xy[sel4(a, c.x, c.y, c.z, c.w)], P1 = p.xy[sel4((a + 1) & 3, c.x, c.y, c.z, c.w)];
+        const double2 Q0 = p.xy[sel4(kx, c.x, c.y, c.z, c.w)], Q1 = p.xy[sel4((kx + 1) & 3, c.x, c.y, c.z, c.w)];
+        dev::path_geom_pts(P0.x, P0.y, P1.x, P1.y, Q0.x, Q0.y, Q1.x, Q1.y, nx, ny, len);
+    } else {
+        path_geom(p, c, a, kx, nx, ny, len);
+    }
     ctl->Ud = ctl->Ud + p.gc[e] * len;
     if (p.sct) {
-        const int4 nb = p.nbr[e];
-        const int m = kx == 0 ? nb.x : (kx == 1 ? nb.y : nb.z);
-        ctl->tip = (m < 0 || p.split[m] != 0) ? -1 : 4 * m + ((nb.w >> (2 * kx)) & 3);
+        int m, loc;
+        if (p.nv == 4) {
+            const int4 nb = p.q_nbr[e];
+            m = sel4(kx, nb.x, nb.y, nb.z, nb.w);
+            loc = (p.q_loc[e] >> (2 * kx)) & 3;
+        } else {
+            const int4 nb = p.nbr[e];
+            m = kx == 0 ? nb.x : (kx == 1 ? nb.y : nb.z);
+            loc = (nb.w >> (2 * kx)) & 3;
+        }
+        ctl->tip = (m < 0 || p.split[m] != 0) ? -1 : 4 * m + loc;
     }
 }
 
@@ -808,15 +1112,17 @@ constexpr int kFrontThreads = 1024;
 struct TriGeom {
     const int4 *conn;
     const double2 *xy;
+    int nv;
+    __device__ int node(const int4 &c, int n) const { return sel4(n % nv, c.x, c.y, c.z, c.w); }
     __device__ double2 tip(int e, int a) const {
         const int4 c = conn[e];
-        const double2 P = xy[node_of(c, a)], Q = xy[node_of(c, (a + 1) % 3)];
+        const double2 P = xy[node(c, a)], Q = xy[node(c, a + 1)];
         return make_double2(0.5 * (P.x + Q.x), 0.5 * (P.y + Q.y));
     }
     __device__ double path_len(int e, int a, int k) const {
         const int4 c = conn[e];
-        const double2 P0 = xy[node_of(c, a)], P1 = xy[node_of(c, (a + 1) % 3)];
-        const double2 Q0 = xy[node_of(c, k)], Q1 = xy[node_of(c, (k + 1) % 3)];
+        const double2 P0 = xy[node(c, a)], P1 = xy[node(c, a + 1)];
+        const double2 Q0 = xy[node(c, k)], Q1 = xy[node(c, k + 1)];
         const double g0x = 0.5 * (P0.x + P1.x), g0y = 0.5 * (P0.y + P1.y);
         const double gkx = 0.5 * (Q0.x + Q1.x), gky = 0.5 * (Q0.y + Q1.y);
         const double dx = gkx - g0x, dy = gky - g0y;
@@ -849,6 +1155,7 @@ __global__ __launch_bounds__(kFrontThreads) void k_front(Params p, int j) {
     TriGeom g;
     g.conn = p.conn;
     g.xy = p.xy;
+    g.nv = p.nv;
     front_pick_block<kFrontThreads>(v, g, j);
 }
 
@@ -856,7 +1163,7 @@ __global__ __launch_bounds__(kFrontThreads) void k_front(Params p, int j) {
 
 hipError_t launch_step(const Params &p, int j, hipStream_t st) {
     if (p.patch_emax > 0) {
-        if (p.patch_nodes < 1 || p.patch_nodes > kB || p.patch_emax > 1024) return hipErrorInvalidValue;
+        if (p.nv != 3 || p.patch_nodes < 1 || p.patch_nodes > kB || p.patch_emax > 1024) return hipErrorInvalidValue;
         const int np = (p.nn + p.patch_nodes - 1) / p.patch_nodes;
         const int key = p.nlist_w * 4 + (p.patch_emax <= 256 ? 0 : p.patch_emax <= 512 ? 1 : 2);
         switch (key) {
@@ -876,7 +1183,10 @@ hipError_t launch_step(const Params &p, int j, hipStream_t st) {
             k_pick<<<1, kB, 0, st>>>(p, j);
         return hipGetLastError();
     }
-    k_force<false><<<nb_of(p.ne), kB, 0, st>>>(p, p.u0, Eval{}, j);
+    if (p.nv == 4)
+        k_qforce<false><<<nb_of(p.ne), kB, 0, st>>>(p, p.u0, Eval{}, j);
+    else
+        k_force<false><<<nb_of(p.ne), kB, 0, st>>>(p, p.u0, Eval{}, j);
     if (p.front_r2 > 0.0) k_front<<<1, kFrontThreads, 0, st>>>(p, j);
     const int nb = nb_of(p.nn);
     switch (p.nlist ? p.nlist_w : 0) {
@@ -900,7 +1210,10 @@ hipError_t launch_commit(const Params &p, int n, hipStream_t st) {
 hipError_t launch_eval(const Params &p, const double2 *u, const double2 *v, int64_t k, double phi,
                        const double *mass, const Eval &ev, hipStream_t st) {
     (void)hipGetLastError();
-    k_force<true><<<nb_of(p.ne), kB, 0, st>>>(p, u, ev, 0);
+    if (p.nv == 4)
+        k_qforce<true><<<nb_of(p.ne), kB, 0, st>>>(p, u, ev, 0);
+    else
+        k_force<true><<<nb_of(p.ne), kB, 0, st>>>(p, u, ev, 0);
     k_eval_nodes<<<nb_of(p.nn), kB, 0, st>>>(p, u, v, k, phi, mass, ev);
     return hipGetLastError();
 }

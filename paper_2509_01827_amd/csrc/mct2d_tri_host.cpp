@@ -1,4 +1,5 @@
-// Host side of the CST path (unstructured triangle meshes): mesh tables,
+// Host side of the unstructured-mesh path (constant-strain triangles or
+// bilinear quadrilaterals): mesh tables,
 // greedy colouring, lumped mass, equivalent nodal tractions, device memory,
 // the time-step loop (HIP graphs of step kernels) and the queries.
 //
@@ -81,8 +82,8 @@ int read_ctl(Model &m, Host h, Ctl *out) {
 int ensure_eval(Model &m, Host h) {
     if (m.ev.fint) return MCT_OK;
     const size_t nn = (size_t)m.nn, ne = (size_t)m.ne, ns = (size_t)m.ns;
-    TRY(h, hipMalloc((void **)&m.ev.sig_ek, sizeof(double) * 9 * ne));
-    TRY(h, hipMalloc((void **)&m.ev.es_ek, sizeof(double) * 3 * ne));
+    TRY(h, hipMalloc((void **)&m.ev.sig_ek, sizeof(double) * 3 * m.nv * ne));
+    TRY(h, hipMalloc((void **)&m.ev.es_ek, sizeof(double) * m.nv * ne));
     TRY(h, hipMalloc((void **)&m.ev.pe, sizeof(double) * ne));
     TRY(h, hipMalloc((void **)&m.ev.principal, sizeof(double) * ne));
     TRY(h, hipMalloc((void **)&m.ev.fint, sizeof(double) * 2 * nn));
@@ -232,6 +233,7 @@ int choose_kernels(Model &m, Host h) {
     p.patch_nodes = 0;
     p.fold = 0;
     int P = 0;
+    if (m.nv != 3) return MCT_OK;  // quadrilaterals: the split kernels
     if (m.kernels >= 2)
         P = 64 << (m.kernels - 2);
     else if (m.kernels == 0 && m.ne < kFusedMaxElems)
@@ -269,6 +271,10 @@ void release(Model &m) {
     dfree(m.dconn);
     dfree(m.dnbr);
     dfree(m.dopp);
+    dfree(m.dq_nbr);
+    dfree(m.dq_loc);
+    dfree(m.dq_oa);
+    dfree(m.dq_ob);
     dfree(m.dnlist);
     dfree(m.dminv);
     dfree(m.dgc);
@@ -315,60 +321,78 @@ void release(Model &m) {
     m.finalized = false;
 }
 
-int set_mesh(Model &m, Host h, int64_t nn, const double *X, const double *Y, int64_t ne, const int32_t *conn) {
-    if (nn < 3 || ne < 1 || !X || !Y || !conn) return fail(h, MCT_EINVAL, "mesh needs >= 3 nodes, >= 1 triangle");
+int set_mesh(Model &m, Host h, int nv, int64_t nn, const double *X, const double *Y, int64_t ne,
+             const int32_t *conn) {
+    const char *what = nv == 4 ? "quadrilateral" : "triangle";
+    if (nv != 3 && nv != 4) return fail(h, MCT_EINVAL, "elements have 3 or 4 nodes");
+    if (nn < nv || ne < 1 || !X || !Y || !conn)
+        return fail(h, MCT_EINVAL, "mesh needs >= %d nodes, >= 1 %s", nv, what);
     if (ne > ((int64_t)1 << 29) || nn > ((int64_t)1 << 30)) return fail(h, MCT_EINVAL, "mesh too large");
     release(m);
     Model fresh;
+    fresh.nv = nv;
     fresh.nn = nn;
     fresh.ne = ne;
     fresh.X.assign(X, X + nn);
     fresh.Y.assign(Y, Y + nn);
-    fresh.conn.assign(conn, conn + 3 * ne);
+    fresh.conn.assign(conn, conn + nv * ne);
     std::vector<uint8_t> used(nn, 0);
     fresh.area.resize(ne);
     for (int64_t e = 0; e < ne; ++e) {
-        const int32_t *c = &conn[3 * e];
-        for (int n = 0; n < 3; ++n) {
-            if (c[n] < 0 || c[n] >= nn) return fail(h, MCT_EINVAL, "triangle %lld: node out of range", (long long)e);
+        const int32_t *c = &conn[nv * e];
+        for (int n = 0; n < nv; ++n) {
+            if (c[n] < 0 || c[n] >= nn) return fail(h, MCT_EINVAL, "%s %lld: node out of range", what, (long long)e);
             used[c[n]] = 1;
+            for (int q = 0; q < n; ++q)
+                if (c[q] == c[n]) return fail(h, MCT_EINVAL, "%s %lld repeats a node", what, (long long)e);
         }
-        if (c[0] == c[1] || c[1] == c[2] || c[0] == c[2])
-            return fail(h, MCT_EINVAL, "triangle %lld repeats a node", (long long)e);
-        const double x0 = X[c[0]], x1 = X[c[1]], x2 = X[c[2]], y0 = Y[c[0]], y1 = Y[c[1]], y2 = Y[c[2]];
-        const double A = 0.5 * ((x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0));
+        double A;
+        if (nv == 3) {
+            const double x0 = X[c[0]], x1 = X[c[1]], x2 = X[c[2]], y0 = Y[c[0]], y1 = Y[c[1]], y2 = Y[c[2]];
+            A = 0.5 * ((x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0));
+        } else {
+            // half the cross product of the diagonals; every corner must turn
+            // left (convex, counter-clockwise), else the bilinear map folds
+            A = 0.5 * ((X[c[2]] - X[c[0]]) * (Y[c[3]] - Y[c[1]]) - (X[c[3]] - X[c[1]]) * (Y[c[2]] - Y[c[0]]));
+            for (int n = 0; n < 4; ++n) {
+                const int32_t a = c[(n + 3) & 3], b = c[n], d = c[(n + 1) & 3];
+                const double cr = (X[b] - X[a]) * (Y[d] - Y[b]) - (Y[b] - Y[a]) * (X[d] - X[b]);
+                if (!(cr > 0.0))
+                    return fail(h, MCT_EINVAL, "quadrilateral %lld is not convex and counter-clockwise", (long long)e);
+            }
+        }
         if (!(A > 0.0))
-            return fail(h, MCT_EINVAL, "triangle %lld has non-positive area (clockwise or degenerate)", (long long)e);
+            return fail(h, MCT_EINVAL, "%s %lld has non-positive area (clockwise or degenerate)", what, (long long)e);
         fresh.area[e] = A;
     }
     for (int64_t i = 0; i < nn; ++i)
-        if (!used[i]) return fail(h, MCT_EINVAL, "node %lld belongs to no triangle", (long long)i);
+        if (!used[i]) return fail(h, MCT_EINVAL, "node %lld belongs to no element", (long long)i);
     // edges: (lower node, higher node, element, local edge), sorted
     struct Rec {
         int32_t lo, hi, e, k;
     };
-    std::vector<Rec> r(3 * ne);
+    std::vector<Rec> r(nv * ne);
     for (int64_t e = 0; e < ne; ++e)
-        for (int k = 0; k < 3; ++k) {
-            const int32_t a = conn[3 * e + k], b = conn[3 * e + (k + 1) % 3];
-            r[3 * e + k] = {std::min(a, b), std::max(a, b), (int32_t)e, k};
+        for (int k = 0; k < nv; ++k) {
+            const int32_t a = conn[nv * e + k], b = conn[nv * e + (k + 1) % nv];
+            r[nv * e + k] = {std::min(a, b), std::max(a, b), (int32_t)e, k};
         }
     std::sort(r.begin(), r.end(), [](const Rec &p, const Rec &q) {
         if (p.lo != q.lo) return p.lo < q.lo;
         if (p.hi != q.hi) return p.hi < q.hi;
         return p.e < q.e;
     });
-    fresh.elem_edge.assign(3 * ne, -1);
+    fresh.elem_edge.assign(nv * ne, -1);
     std::vector<int32_t> edge_loc;
     int64_t ns = 0;
     for (size_t i = 0; i < r.size(); ++i) {
         if (i > 0 && r[i].lo == r[i - 1].lo && r[i].hi == r[i - 1].hi) {
             const int64_t s = ns - 1;
             if (fresh.edge_elem[2 * s + 1] >= 0)
-                return fail(h, MCT_EINVAL, "edge (%d, %d) belongs to more than two triangles", r[i].lo, r[i].hi);
+                return fail(h, MCT_EINVAL, "edge (%d, %d) belongs to more than two elements", r[i].lo, r[i].hi);
             const int32_t e0 = fresh.edge_elem[2 * s], k0 = edge_loc[2 * s];
-            if (conn[3 * e0 + k0] == conn[3 * r[i].e + r[i].k])
-                return fail(h, MCT_EINVAL, "triangles %d and %d run edge (%d, %d) in the same direction", e0,
+            if (conn[nv * e0 + k0] == conn[nv * r[i].e + r[i].k])
+                return fail(h, MCT_EINVAL, "elements %d and %d run edge (%d, %d) in the same direction", e0,
                             r[i].e, r[i].lo, r[i].hi);
             fresh.edge_elem[2 * s + 1] = r[i].e;
             edge_loc[2 * s + 1] = r[i].k;
@@ -381,20 +405,20 @@ int set_mesh(Model &m, Host h, int64_t nn, const double *X, const double *Y, int
             edge_loc.push_back(-1);
             ++ns;
         }
-        fresh.elem_edge[3 * (int64_t)r[i].e + r[i].k] = (int32_t)(ns - 1);
+        fresh.elem_edge[nv * (int64_t)r[i].e + r[i].k] = (int32_t)(ns - 1);
     }
     fresh.ns = ns;
-    fresh.nbr.assign(4 * ne, -1);
+    fresh.nbr.assign((nv + 1) * ne, -1);
     for (int64_t e = 0; e < ne; ++e) {
         int32_t packed = 0;
-        for (int k = 0; k < 3; ++k) {
-            const int64_t s = fresh.elem_edge[3 * e + k];
+        for (int k = 0; k < nv; ++k) {
+            const int64_t s = fresh.elem_edge[nv * e + k];
             const int side = fresh.edge_elem[2 * s] == e ? 1 : 0;
-            fresh.nbr[4 * e + k] = fresh.edge_elem[2 * s + side];
-            const int32_t loc = fresh.nbr[4 * e + k] >= 0 ? edge_loc[2 * s + side] : 0;
+            fresh.nbr[(nv + 1) * e + k] = fresh.edge_elem[2 * s + side];
+            const int32_t loc = fresh.nbr[(nv + 1) * e + k] >= 0 ? edge_loc[2 * s + side] : 0;
             packed |= loc << (2 * k);
         }
-        fresh.nbr[4 * e + 3] = packed;
+        fresh.nbr[(nv + 1) * e + nv] = packed;
     }
     m = std::move(fresh);
     return MCT_OK;
@@ -471,7 +495,7 @@ int set_notch(Model &m, Host h, int64_t n, const int32_t *elem, const uint8_t *e
     std::vector<int32_t> el;
     std::vector<uint8_t> code;
     for (int64_t i = 0; i < n; ++i) {
-        if (elem[i] < 0 || elem[i] >= m.ne || entry[i] > 2 || exit[i] > 2 || entry[i] == exit[i])
+        if (elem[i] < 0 || elem[i] >= m.ne || entry[i] >= m.nv || exit[i] >= m.nv || entry[i] == exit[i])
             return fail(h, MCT_EINVAL, "notch element %lld invalid", (long long)i);
         el.push_back(elem[i]);
         code.push_back((uint8_t)(kSplitFlag | (entry[i] << 2) | exit[i]));
@@ -497,7 +521,7 @@ int set_load_curve(Model &m, Host h, int64_t n, const double *t, const double *p
 int set_tracking(Model &m, Host h, int mode, int32_t elem, int edge) {
     if (need_mesh(m)) return fail(h, MCT_ESTATE, "set the mesh first");
     if (mode != MCT_TRACK_MCT && mode != MCT_TRACK_SCT) return fail(h, MCT_EINVAL, "unknown tracking mode %d", mode);
-    if (mode == MCT_TRACK_SCT && elem >= 0 && (elem >= m.ne || edge < 0 || edge > 2))
+    if (mode == MCT_TRACK_SCT && elem >= 0 && (elem >= m.ne || edge < 0 || edge >= m.nv))
         return fail(h, MCT_EINVAL, "start tip out of range");
     m.sct = mode == MCT_TRACK_SCT;
     m.sct_elem = elem;
@@ -525,12 +549,13 @@ int set_time(Model &m, Host h, double dt, double cfl) {
 int finalize(Model &m, Host h) {
     if (need_mesh(m) || !m.have_material) return fail(h, MCT_ESTATE, "mesh and material are required");
     const int64_t nn = m.nn, ne = m.ne, ns = m.ns;
+    const int nv = m.nv;
     release(m);  // device state only; the host tables stay
-    // lumped mass rho A / 3, element-id order per node
+    // lumped mass rho A / nv, element-id order per node
     m.mass.assign(nn, 0.0);
     for (int64_t e = 0; e < ne; ++e) {
-        const double me = m.rho * m.area[e] / 3.0;
-        for (int n = 0; n < 3; ++n) m.mass[m.conn[3 * e + n]] += me;
+        const double me = m.rho * m.area[e] / (double)nv;
+        for (int n = 0; n < nv; ++n) m.mass[m.conn[nv * e + n]] += me;
     }
     std::vector<double> minv(nn);
     for (int64_t i = 0; i < nn; ++i) minv[i] = 1.0 / m.mass[i];
@@ -571,25 +596,25 @@ int finalize(Model &m, Host h) {
         m.dt = m.cfl * hmin / cd;
     }
     // greedy colouring and the per-node gather lists in colour order
-    std::vector<int32_t> noff(nn + 1, 0), nel(3 * ne);
+    std::vector<int32_t> noff(nn + 1, 0), nel(nv * ne);
     for (int64_t e = 0; e < ne; ++e)
-        for (int n = 0; n < 3; ++n) noff[m.conn[3 * e + n] + 1]++;
+        for (int n = 0; n < nv; ++n) noff[m.conn[nv * e + n] + 1]++;
     for (int64_t i = 0; i < nn; ++i) noff[i + 1] += noff[i];
     {
         std::vector<int32_t> fill(nn, 0);
         for (int64_t e = 0; e < ne; ++e)
-            for (int n = 0; n < 3; ++n) {
-                const int32_t g = m.conn[3 * e + n];
-                nel[noff[g] + fill[g]++] = (int32_t)(3 * e + n);
+            for (int n = 0; n < nv; ++n) {
+                const int32_t g = m.conn[nv * e + n];
+                nel[noff[g] + fill[g]++] = (int32_t)(nv * e + n);
             }
     }
     std::vector<int32_t> color(ne, 0);
     for (int64_t e = 0; e < ne; ++e) {
         uint64_t used = 0;
-        for (int n = 0; n < 3; ++n) {
-            const int32_t g = m.conn[3 * e + n];
+        for (int n = 0; n < nv; ++n) {
+            const int32_t g = m.conn[nv * e + n];
             for (int32_t t = noff[g]; t < noff[g + 1]; ++t) {
-                const int32_t o = nel[t] / 3;
+                const int32_t o = nel[t] / nv;
                 if (o < e) used |= 1ull << color[o];
             }
         }
@@ -600,30 +625,40 @@ int finalize(Model &m, Host h) {
     }
     for (int64_t i = 0; i < nn; ++i)
         std::sort(nel.begin() + noff[i], nel.begin() + noff[i + 1],
-                  [&](int32_t p, int32_t q) { return color[p / 3] < color[q / 3]; });
+                  [&](int32_t p, int32_t q) { return color[p / nv] < color[q / nv]; });
     m.gnoff = noff;
     m.gnel = nel;
     // gather entries name force slots n * ne + e (slot-major element forces)
-    for (int32_t &v : nel) v = (v % 3) * (int32_t)ne + v / 3;
+    for (int32_t &v : nel) v = (v % nv) * (int32_t)ne + v / nv;
     // device arrays
     // per element: neighbours, and each neighbour's node off the shared edge
     // (the neighbour runs the edge backwards, so its local node loc + 2)
-    std::vector<int4> c4(ne), n4(ne), o4(ne);
+    std::vector<int4> c4(ne), n4(ne), o4(ne), qa(nv == 4 ? ne : 0), qb(nv == 4 ? ne : 0);
+    std::vector<uint8_t> ql(nv == 4 ? ne : 0);
+    const int st = nv + 1;
     for (int64_t e = 0; e < ne; ++e) {
-        c4[e] = make_int4(m.conn[3 * e], m.conn[3 * e + 1], m.conn[3 * e + 2], 0);
-        n4[e] = make_int4(m.nbr[4 * e], m.nbr[4 * e + 1], m.nbr[4 * e + 2], m.nbr[4 * e + 3]);
-        int32_t o[3];
-        for (int k = 0; k < 3; ++k) {
-            const int32_t nb = m.nbr[4 * e + k];
-            o[k] = -1;
+        const int32_t *ce = &m.conn[nv * e];
+        c4[e] = make_int4(ce[0], ce[1], ce[2], nv == 4 ? ce[3] : 0);
+        int32_t o[4] = {-1, -1, -1, -1}, o2[4] = {-1, -1, -1, -1};
+        for (int k = 0; k < nv; ++k) {
+            const int32_t nb = m.nbr[st * e + k];
             if (nb < 0) continue;
-            const int loc = (m.nbr[4 * e + 3] >> (2 * k)) & 3;
-            if (m.conn[3 * (int64_t)nb + loc] != m.conn[3 * e + (k + 1) % 3] ||
-                m.conn[3 * (int64_t)nb + (loc + 1) % 3] != m.conn[3 * e + k])
+            const int loc = (m.nbr[st * e + nv] >> (2 * k)) & 3;
+            const int32_t *cn = &m.conn[nv * (int64_t)nb];
+            if (cn[loc] != ce[(k + 1) % nv] || cn[(loc + 1) % nv] != ce[k])
                 return fail(h, MCT_EINVAL, "inconsistent neighbour table at element %lld", (long long)e);
-            o[k] = m.conn[3 * (int64_t)nb + (loc + 2) % 3];
+            o[k] = cn[(loc + 2) % nv];
+            if (nv == 4) o2[k] = cn[(loc + 3) % nv];
         }
-        o4[e] = make_int4(o[0], o[1], o[2], 0);
+        if (nv == 3) {
+            n4[e] = make_int4(m.nbr[st * e], m.nbr[st * e + 1], m.nbr[st * e + 2], m.nbr[st * e + 3]);
+            o4[e] = make_int4(o[0], o[1], o[2], 0);
+        } else {
+            n4[e] = make_int4(m.nbr[st * e], m.nbr[st * e + 1], m.nbr[st * e + 2], m.nbr[st * e + 3]);
+            ql[e] = (uint8_t)m.nbr[st * e + 4];
+            qa[e] = make_int4(o[0], o[1], o[2], o[3]);
+            qb[e] = make_int4(o2[0], o2[1], o2[2], o2[3]);
+        }
     }
     // padded gather lists (node-major, W slots) when every node touches <= 16 elements
     int32_t maxdeg = 0;
@@ -646,8 +681,15 @@ int finalize(Model &m, Host h) {
     for (size_t q = 0; q < m.notch_elem.size(); ++q) split[m.notch_elem[q]] = m.notch_code[q];
     int rc;
     if ((rc = upload<int4>(h, m.dconn, c4.data(), ne))) return rc;
-    if ((rc = upload<int4>(h, m.dnbr, n4.data(), ne))) return rc;
-    if ((rc = upload<int4>(h, m.dopp, o4.data(), ne))) return rc;
+    if (nv == 3) {
+        if ((rc = upload<int4>(h, m.dnbr, n4.data(), ne))) return rc;
+        if ((rc = upload<int4>(h, m.dopp, o4.data(), ne))) return rc;
+    } else {
+        if ((rc = upload<int4>(h, m.dq_nbr, n4.data(), ne))) return rc;
+        if ((rc = upload<uint8_t>(h, m.dq_loc, ql.data(), ne))) return rc;
+        if ((rc = upload<int4>(h, m.dq_oa, qa.data(), ne))) return rc;
+        if ((rc = upload<int4>(h, m.dq_ob, qb.data(), ne))) return rc;
+    }
     if (!nlist.empty() && (rc = upload<int32_t>(h, m.dnlist, nlist.data(), nlist.size()))) return rc;
     if ((rc = upload<double>(h, m.dminv, minv.data(), nn))) return rc;
     if ((rc = upload<double>(h, m.dmass, m.mass.data(), nn))) return rc;
@@ -658,7 +700,7 @@ int finalize(Model &m, Host h) {
     if ((rc = upload<uint8_t>(h, m.dflag, flag.data(), nn))) return rc;
     if ((rc = upload<uint8_t>(h, m.dsplit, split.data(), ne))) return rc;
     if ((rc = upload<int32_t>(h, m.dcsr_off, noff.data(), nn + 1))) return rc;
-    if ((rc = upload<int32_t>(h, m.dcsr_ent, nel.data(), 3 * ne))) return rc;
+    if ((rc = upload<int32_t>(h, m.dcsr_ent, nel.data(), nv * ne))) return rc;
     if ((rc = upload<int32_t>(h, m.dedge_elem, m.edge_elem.data(), 2 * ns))) return rc;
     const size_t ncv = m.curve_t.size();
     if (ncv) {
@@ -672,16 +714,16 @@ int finalize(Model &m, Host h) {
     TRY(h, hipMemsetAsync(m.du[0], 0, sizeof(double2) * nn, h.stream));
     TRY(h, hipMemsetAsync(m.du[1], 0, sizeof(double2) * nn, h.stream));
     TRY(h, hipMemsetAsync(m.dv, 0, sizeof(double2) * nn, h.stream));
-    TRY(h, hipMalloc((void **)&m.dfe, sizeof(double2) * 3 * ne));
-    TRY(h, hipMalloc((void **)&m.dcand, sizeof(Cand) * 3 * ne));
+    TRY(h, hipMalloc((void **)&m.dfe, sizeof(double2) * nv * ne));
+    TRY(h, hipMalloc((void **)&m.dcand, sizeof(Cand) * nv * ne));
     if (m.front_rho > 0) {
         if (m.sct) return fail(h, MCT_EINVAL, "per-front pick and single-tip tracking exclude each other");
-        TRY(h, hipMalloc((void **)&m.dfmid, sizeof(double2) * 3 * ne));
-        TRY(h, hipMalloc((void **)&m.dflen, sizeof(double) * 3 * ne));
-        TRY(h, hipMalloc((void **)&m.dforder, sizeof(int32_t) * 3 * ne));
-        TRY(h, hipMalloc((void **)&m.dfbucket, sizeof(int32_t) * 3 * ne));
-        TRY(h, hipMalloc((void **)&m.dfsorted, sizeof(int32_t) * 3 * ne));
-        TRY(h, hipMalloc((void **)&m.dfplist, sizeof(int32_t) * 3 * ne));
+        TRY(h, hipMalloc((void **)&m.dfmid, sizeof(double2) * nv * ne));
+        TRY(h, hipMalloc((void **)&m.dflen, sizeof(double) * nv * ne));
+        TRY(h, hipMalloc((void **)&m.dforder, sizeof(int32_t) * nv * ne));
+        TRY(h, hipMalloc((void **)&m.dfbucket, sizeof(int32_t) * nv * ne));
+        TRY(h, hipMalloc((void **)&m.dfsorted, sizeof(int32_t) * nv * ne));
+        TRY(h, hipMalloc((void **)&m.dfplist, sizeof(int32_t) * nv * ne));
     }
     TRY(h, hipMalloc((void **)&m.dlog, sizeof(LogRec) * ne));
     TRY(h, hipMalloc((void **)&m.dctl, sizeof(Ctl)));
@@ -698,9 +740,9 @@ int finalize(Model &m, Host h) {
                 if (!split[e]) continue;
                 const int ks[2] = {(split[e] >> 2) & 3, split[e] & 3};
                 for (int k : ks) {
-                    const int32_t nb = m.nbr[4 * e + k];
+                    const int32_t nb = m.nbr[st * e + k];
                     if (nb < 0 || split[nb]) continue;
-                    tip = nb * 4 + ((m.nbr[4 * e + 3] >> (2 * k)) & 3);
+                    tip = nb * 4 + ((m.nbr[st * e + nv] >> (2 * k)) & 3);
                     ++count;
                 }
             }
@@ -719,9 +761,14 @@ int finalize(Model &m, Host h) {
     p.log_cap = (int32_t)ne;
     p.sct = m.sct;
     p.ncurve = (int32_t)ncv;
+    p.nv = nv;
     p.conn = m.dconn;
     p.nbr = m.dnbr;
     p.opp = m.dopp;
+    p.q_nbr = m.dq_nbr;
+    p.q_loc = m.dq_loc;
+    p.q_oa = m.dq_oa;
+    p.q_ob = m.dq_ob;
     p.nlist = m.dnlist;
     p.nlist_w = m.dnlist ? W : 0;
     // the fused step's slot lists have the padded lists' width
@@ -759,13 +806,15 @@ int finalize(Model &m, Host h) {
     p.fsorted = m.dfsorted;
     p.fplist = m.dfplist;
     {
-        // hash cell: at least rho and the longest edge (the largest distance
-        // between two nodes of a triangle)
+        // hash cell: at least rho and the largest distance between two
+        // nodes of an element (two tip points of one element are closer)
         double dmax = 0.0;
-        for (int64_t s = 0; s < ns; ++s) {
-            const int32_t a = m.edge_node[2 * s], b = m.edge_node[2 * s + 1];
-            dmax = std::max(dmax, std::hypot(m.X[b] - m.X[a], m.Y[b] - m.Y[a]));
-        }
+        for (int64_t e = 0; e < ne; ++e)
+            for (int a = 0; a < nv; ++a)
+                for (int b = a + 1; b < nv; ++b) {
+                    const int32_t i = m.conn[nv * e + a], j = m.conn[nv * e + b];
+                    dmax = std::max(dmax, std::hypot(m.X[j] - m.X[i], m.Y[j] - m.Y[i]));
+                }
         p.fcell = std::max(m.front_rho, dmax) * (1.0 + 1e-9);
     }
     TRY(h, hipStreamSynchronize(h.stream));
@@ -950,8 +999,9 @@ int get_field(Model &m, Host h, int which, int64_t cap, double *out) {
     }
     // edge stresses from the element-edge table: the lower-id side if it is
     // intact, else the other side (NaN where neither is)
-    std::vector<double> sk(9 * ne);
-    TRY(h, hipMemcpyAsync(sk.data(), m.ev.sig_ek, sizeof(double) * 9 * ne, hipMemcpyDeviceToHost, h.stream));
+    const int nv = m.nv;
+    std::vector<double> sk(3 * nv * ne);
+    TRY(h, hipMemcpyAsync(sk.data(), m.ev.sig_ek, sizeof(double) * 3 * nv * ne, hipMemcpyDeviceToHost, h.stream));
     TRY(h, hipStreamSynchronize(h.stream));
     for (int64_t s = 0; s < ns; ++s) {
         double v[3] = {NAN, NAN, NAN};
@@ -959,8 +1009,8 @@ int get_field(Model &m, Host h, int which, int64_t cap, double *out) {
             const int32_t e = m.edge_elem[2 * s + side];
             if (e < 0) continue;
             int k = 0;
-            while (m.elem_edge[3 * (int64_t)e + k] != s) ++k;
-            const double *q = &sk[9 * (int64_t)e + 3 * k];
+            while (m.elem_edge[nv * (int64_t)e + k] != s) ++k;
+            const double *q = &sk[3 * nv * (int64_t)e + 3 * k];
             if (!std::isnan(q[0]) || !std::isnan(q[1]) || !std::isnan(q[2])) {
                 v[0] = q[0];
                 v[1] = q[1];
@@ -980,7 +1030,7 @@ int get_energies(Model &m, Host h, double out[4]) {
     if (rc) return rc;
     TRY(h, launch_sum(m.ev.node_e, m.nn, 2, 0, m.dpart, m.dsums, h.stream));
     TRY(h, launch_sum(m.ev.node_e, m.nn, 2, 1, m.dpart, m.dsums + 1, h.stream));
-    TRY(h, launch_sum(m.ev.es_ek, 3 * m.ne, 1, 0, m.dpart, m.dsums + 2, h.stream));
+    TRY(h, launch_sum(m.ev.es_ek, m.nv * m.ne, 1, 0, m.dpart, m.dsums + 2, h.stream));
     TRY(h, launch_sum(m.ev.pe, m.ne, 1, 0, m.dpart, m.dsums + 3, h.stream));
     double s[4];
     TRY(h, hipMemcpyAsync(s, m.dsums, sizeof s, hipMemcpyDeviceToHost, h.stream));
@@ -1000,9 +1050,12 @@ int get_split_codes(Model &m, Host h, int64_t cap, uint8_t *out) {
     return MCT_OK;
 }
 
-// Checkpoint layout: 8-byte magic, n_nodes, n_elems (int64), the control
-// block, u and v (interleaved pairs), split codes, then the logged splits.
-static const uint64_t kMagic = 0x3152544432544d43ull;  // "MCT2DTR1"
+// Checkpoint layout: 8-byte magic (one per element kind), n_nodes, n_elems
+// (int64), the control block, u and v (interleaved pairs), split codes,
+// then the logged splits.
+static const uint64_t kMagic = 0x3152544432544d43ull;    // "MCT2DTR1"
+static const uint64_t kMagicQ4 = 0x3152554432544d43ull;  // "MCT2DUR1"
+static uint64_t magic_of(const Model &m) { return m.nv == 4 ? kMagicQ4 : kMagic; }
 
 int checkpoint(Model &m, Host h, void *buf, int64_t cap, int64_t *bytes) {
     if (!m.finalized) return fail(h, MCT_ESTATE, "finalize first");
@@ -1015,7 +1068,7 @@ int checkpoint(Model &m, Host h, void *buf, int64_t cap, int64_t *bytes) {
     if (!buf) return MCT_OK;
     if (cap < need) return fail(h, MCT_ECAPACITY, "checkpoint needs %lld bytes", (long long)need);
     char *p = static_cast<char *>(buf);
-    const int64_t hdr[3] = {(int64_t)kMagic, m.nn, m.ne};
+    const int64_t hdr[3] = {(int64_t)magic_of(m), m.nn, m.ne};
     std::memcpy(p, hdr, 24);
     p += 24;
     std::memcpy(p, &c, sizeof c);
@@ -1037,7 +1090,7 @@ int restore(Model &m, Host h, const void *buf, int64_t bytes) {
     const char *p = static_cast<const char *>(buf);
     int64_t hdr[3];
     std::memcpy(hdr, p, 24);
-    if ((uint64_t)hdr[0] != kMagic || hdr[1] != m.nn || hdr[2] != m.ne)
+    if ((uint64_t)hdr[0] != magic_of(m) || hdr[1] != m.nn || hdr[2] != m.ne)
         return fail(h, MCT_EINVAL, "checkpoint does not match this mesh");
     Ctl c;
     std::memcpy(&c, p + 24, sizeof c);
@@ -1045,7 +1098,7 @@ int restore(Model &m, Host h, const void *buf, int64_t bytes) {
     if (c.nsplit < 0 || c.base < 0 || c.nacc != 0 ||
         bytes != 24 + (int64_t)sizeof(Ctl) + 32 * m.nn + m.ne + (int64_t)sizeof(LogRec) * nlog)
         return fail(h, MCT_EINVAL, "checkpoint size or control block invalid");
-    if (c.tip < -1 || c.tip >= 4 * m.ne || (c.tip >= 0 && (c.tip & 3) > 2))
+    if (c.tip < -1 || c.tip >= 4 * m.ne || (c.tip >= 0 && (c.tip & 3) >= m.nv))
         return fail(h, MCT_EINVAL, "checkpoint tip invalid");
     p += 24 + sizeof c;
     TRY(h, hipStreamSynchronize(h.stream));
@@ -1058,7 +1111,8 @@ int restore(Model &m, Host h, const void *buf, int64_t bytes) {
     std::vector<uint8_t> split(p, p + m.ne);
     for (int64_t e = 0; e < m.ne; ++e) {
         const uint8_t s = split[e];
-        if (s && (!(s & kSplitFlag) || ((s >> 2) & 3) > 2 || (s & 3) > 2 || ((s >> 2) & 3) == (s & 3) || (s & 0x70)))
+        if (s && (!(s & kSplitFlag) || ((s >> 2) & 3) >= m.nv || (s & 3) >= m.nv || ((s >> 2) & 3) == (s & 3) ||
+                  (s & 0x70)))
             return fail(h, MCT_EINVAL, "checkpoint split code of element %lld invalid", (long long)e);
     }
     TRY(h, hipMemcpy(m.dsplit, split.data(), m.ne, hipMemcpyHostToDevice));

@@ -1,6 +1,7 @@
-// Host side of the CST (unstructured triangle mesh) path: the model a
-// context holds after mct_set_mesh_tri, and the functions the C ABI
-// forwards to for such a context.  Not part of the ABI.
+// Host side of the unstructured-mesh path (constant-strain triangles or
+// bilinear quadrilaterals): the model a context holds after
+// mct_set_mesh_tri or mct_set_mesh_q4, and the functions the C ABI forwards
+// to for such a context.  Not part of the ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -18,12 +19,13 @@ namespace tri {
 struct Model {
     // mesh (as given) and its tables, built by set_mesh
     int64_t nn = 0, ne = 0, ns = 0;
+    int nv = 3;                      // nodes (and edges) per element: 3 or 4
     std::vector<double> X, Y;
-    std::vector<int32_t> conn;       // 3 per element
+    std::vector<int32_t> conn;       // nv per element
     std::vector<int32_t> edge_node;  // 2 per edge (lower node id first), edges sorted by node pair
     std::vector<int32_t> edge_elem;  // 2 per edge (lower element id first, -1 none)
-    std::vector<int32_t> elem_edge;  // 3 per element
-    std::vector<int32_t> nbr;        // 4 per element: neighbours across k = 0..2, packed local edges
+    std::vector<int32_t> elem_edge;  // nv per element
+    std::vector<int32_t> nbr;        // nv + 1 per element: neighbours across k = 0..nv-1, packed local edges
     std::vector<double> area;
     // material and loads
     bool have_material = false;
@@ -51,16 +53,19 @@ struct Model {
     Params prm{};
     // device memory
     int4 *dconn = nullptr, *dnbr = nullptr, *dopp = nullptr;
+    int4 *dq_nbr = nullptr, *dq_oa = nullptr, *dq_ob = nullptr;  // quadrilaterals
+    uint8_t *dq_loc = nullptr;
     double *dminv = nullptr, *dgc = nullptr, *dcurve = nullptr, *dmass = nullptr;
     double2 *dxy = nullptr, *du[2] = {nullptr, nullptr}, *dv = nullptr, *dfext = nullptr, *dv0 = nullptr,
             *dfe = nullptr;
     int32_t *dpatch_off = nullptr, *dpatch_elem = nullptr;
     int32_t *dfold_n = nullptr;     // folded pick: 3 candidate counters
-    Cand *dfold_cand = nullptr;     //   and 3 candidate sets of 3 ne
+    Cand *dfold_cand = nullptr;     //   and 3 candidate sets of 3 ne (triangles only)
     uint16_t *dpatch_slots = nullptr;
-    // step kernels: 0 automatic, 1 split, 2/3/4 fused on 64/128/256-node patches
+    // step kernels: 0 automatic, 1 split, 2/3/4 fused on 64/128/256-node
+    // patches (triangles; quadrilateral meshes run the split kernels)
     int kernels = 0;
-    // node -> incident (3 * element + local node) entries in colour order
+    // node -> incident (nv * element + local node) entries in colour order
     std::vector<int32_t> gnoff, gnel;
     uint8_t *dflag = nullptr, *dsplit = nullptr;
     int32_t *dcsr_off = nullptr, *dcsr_ent = nullptr, *dnlist = nullptr, *dedge_elem = nullptr, *dwatch = nullptr;
@@ -86,7 +91,9 @@ struct Host {
 };
 
 void release(Model &m);
-int set_mesh(Model &m, Host h, int64_t nn, const double *X, const double *Y, int64_t ne, const int32_t *conn);
+// nv = 3: triangles (3 nodes per element); nv = 4: convex quadrilaterals.
+int set_mesh(Model &m, Host h, int nv, int64_t nn, const double *X, const double *Y, int64_t ne,
+             const int32_t *conn);
 int set_material(Model &m, Host h, double E, double nu, double rho, const double *Gc, double Gc_uniform,
                  double gamma);
 int set_traction(Model &m, Host h, int64_t n, const int32_t *edge_nodes, const double *t);

@@ -50,7 +50,7 @@ EXPORTS = [
     "mct_screen_collect", "mct_screen_enable", "mct_screen_disable", "mct_screen_stats",
     "mct_mlp_create", "mct_mlp_destroy", "mct_mlp_last_error", "mct_mlp_set_params", "mct_mlp_get_params",
     "mct_mlp_forward", "mct_mlp_gradient", "mct_mlp_train_step", "mct_get_energies", "mct_set_tracking",
-    "mct_set_load_curve", "mct_set_mesh_tri", "mct_set_front_pick",
+    "mct_set_load_curve", "mct_set_mesh_tri", "mct_set_mesh_q4", "mct_set_front_pick",
     "mct_set_smoothing", "mct_bind_device_buffers",
 ]
 N_FEATURES = 10
@@ -90,6 +90,7 @@ def load() -> C.CDLL:
     L.mct_last_error.restype = C.c_char_p
     L.mct_set_mesh_grid.argtypes = [P, C.c_int32, C.c_int32, dp, dp]
     L.mct_set_mesh_tri.argtypes = [P, C.c_int64, dp, dp, C.c_int64, ip]
+    L.mct_set_mesh_q4.argtypes = [P, C.c_int64, dp, dp, C.c_int64, ip]
     L.mct_set_material.argtypes = [P, C.c_double, C.c_double, C.c_double, P, C.c_double, C.c_double]
     L.mct_set_traction.argtypes = [P, C.c_int64, ip, dp]
     L.mct_set_velocity_bc.argtypes = [P, C.c_int64, ip, bp, dp, C.c_double]
@@ -196,6 +197,13 @@ class Model:
         conn = _i32(np.asarray(conn).reshape(-1))
         X = _f64(X)
         self._check(self._L.mct_set_mesh_tri(self._h, len(X), X, _f64(Y), len(conn) // 3, conn), "set_mesh_tri")
+
+    def set_mesh_q4(self, X, Y, conn):
+        """Unstructured Q4 mesh: node coordinates and [ne][4] CCW convex
+        quadrilaterals."""
+        conn = _i32(np.asarray(conn).reshape(-1))
+        X = _f64(X)
+        self._check(self._L.mct_set_mesh_q4(self._h, len(X), X, _f64(Y), len(conn) // 4, conn), "set_mesh_q4")
 
     def set_material(self, E, nu, rho, gc=None, gc_uniform=0.0, gamma=1.0):
         self._gc = None if gc is None else _f64(gc)
@@ -451,7 +459,10 @@ class Mlp:
 
 def _setup(m: Model, cfg: dict):
     if cfg.get("conn") is not None:
-        m.set_mesh_tri(cfg["X"], cfg["Y"], cfg["conn"])
+        if np.asarray(cfg["conn"]).shape[1] == 4:
+            m.set_mesh_q4(cfg["X"], cfg["Y"], cfg["conn"])
+        else:
+            m.set_mesh_tri(cfg["X"], cfg["Y"], cfg["conn"])
     else:
         m.set_mesh_grid(cfg["nx"], cfg["ny"], cfg["X"], cfg["Y"])
     m.set_material(cfg["E"], cfg["nu"], cfg["rho"], cfg.get("gc_field"), cfg.get("gc_uniform", 0.0),

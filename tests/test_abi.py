@@ -15,7 +15,7 @@ HEADER = os.path.join(ROOT, "include", "mct2d.h")
 def _declared():
     txt = open(HEADER).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(mct_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(mct_[a-z0-9_]+)\s*\(", txt)))
 
 
 def test_header_declares_binding_names():

@@ -1,0 +1,213 @@
+"""Unstructured Q4 path (mct_set_mesh_q4) on the GPU against the CPU oracle.
+
+Bar (as for the triangle path): the split log, split codes, tips and the
+displacement / velocity fields bit-identical to the oracle's after every
+checked step count, with and without HIP graphs, in both tracking modes and
+with the per-front pick; queried forces, stresses and accelerations to
+1e-12 relative, energies (sums in another order) to 1e-12 relative.  A
+structured grid written as an unstructured mesh (renumbered, node lists
+rotated) runs the structured path's crack sequence."""
+import numpy as np
+import pytest
+
+from paper_2509_01827_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2509_01827_amd import mct2d
+    mct2d.load()
+    return mct2d
+
+
+def _same(m, o, label):
+    lg, ol = m.crack_set(), o.log()
+    for k in ("step", "elem", "entry", "exit"):
+        assert np.array_equal(lg[k].astype(np.int64), ol[k].astype(np.int64)), (label, k)
+    assert np.array_equal(lg["G"], ol["G"]), label
+    st = o.state()
+    assert np.array_equal(m.split_codes(), st["split"]), label
+    (ux, uy), (vx, vy) = m.field(0), m.field(1)
+    for a, b, name in ((ux, st["ux"], "ux"), (uy, st["uy"], "uy"), (vx, st["vx"], "vx"), (vy, st["vy"], "vy")):
+        assert np.array_equal(a, b), (label, name, np.abs(a - b).max())
+    inf = m.info()
+    assert inf["n_splits"] == len(ol["elem"])
+    assert inf["dissipated"] == o.info()["Ud"], label
+
+
+@pytest.mark.parametrize("name", sorted(W.quad_small_cases()))
+def test_q4u_matches_oracle(gpu, oracle_mod, name):
+    cfg = W.quad_small_cases()[name]
+    print("case", name, flush=True)
+    o = oracle_mod.Oracle(cfg)
+    # the element kernel plus the node kernel, whatever the launch choice
+    models = [gpu.from_config(cfg, tile=t, use_graph=g) for t, g in ((0, True), (1, False), (2, True))]
+    assert [m.launch()["tile"] for m in models] == [1, 1, 1]
+    inf = models[0].info()
+    assert (inf["n_nodes"], inf["n_elems"], inf["n_edges"]) == (o.info()["nn"], o.info()["ne"], o.info()["ns"])
+    assert inf["dt"] == o.info()["dt"]
+    done = 0
+    for chunk in (1, 63, 136, 400, 600):
+        o.step(chunk)
+        done += chunk
+        for m in models:
+            m.step(chunk)
+            m.sync()
+            _same(m, o, (name, done, m.launch()["tile"]))
+    e, xy = models[0].tips()
+    oe, oxy = o.tips()
+    assert np.array_equal(e, oe) and np.array_equal(xy, oxy)
+    assert len(o.log()["elem"]) > 5, "the case should crack within the checked steps"
+    print(name, "splits", len(o.log()["elem"]), flush=True)
+
+
+def test_q4u_sct_and_front_pick(gpu, oracle_mod):
+    base = W.quad_small_cases()["grid70x37_unstructured"]
+    for cfg, label in ((dict(base, tracking=("sct", -1, 0)), "sct"), (dict(base, front_radius=2.5e-3), "front")):
+        print("case", label, flush=True)
+        o = oracle_mod.Oracle(cfg)
+        m = gpu.from_config(cfg)
+        if label == "sct":
+            assert m.tip() == o.tip() and o.tip() is not None
+        for chunk in (100, 501, 599):
+            o.step(chunk)
+            m.step(chunk)
+            _same(m, o, (label, chunk))
+            if label == "sct":
+                assert m.tip() == o.tip()
+        assert len(o.log()["elem"]) > 3, label
+
+
+def test_q4u_is_the_structured_grid(gpu):
+    """The renumbered grid cracks like the structured grid: the same steps,
+    elements (through the permutation), local edges (through the rotation)
+    and G to 1e-9 (sums of another order)."""
+    base = W.small_cases()["plate70x37_jitter"]
+    u = W.as_unstructured_q4(base)
+    pn, pe, rot = u["perm"]
+    a = gpu.from_config(base)
+    b = gpu.from_config(u)
+    a.step(900)
+    b.step(900)
+    la, lb = a.crack_set(), b.crack_set()
+    n = 10
+    assert len(la["elem"]) > n
+    assert np.array_equal(lb["step"][:n], la["step"][:n])
+    assert np.array_equal(pe[lb["elem"][:n]], la["elem"][:n])
+    r = rot[lb["elem"][:n]]
+    assert np.array_equal((lb["entry"][:n].astype(np.int64) + r) % 4, la["entry"][:n])
+    assert np.array_equal((lb["exit"][:n].astype(np.int64) + r) % 4, la["exit"][:n])
+    np.testing.assert_allclose(lb["G"][:n], la["G"][:n], rtol=1e-9)
+
+
+def _edge_index(tabs, ne):
+    ee = np.full((ne, 4), -1, np.int64)
+    for s in range(len(tabs["edge_elem"])):
+        for side in range(2):
+            e = tabs["edge_elem"][s, side]
+            if e >= 0:
+                ee[e, tabs["edge_loc"][s, side]] = s
+    return ee
+
+
+@pytest.mark.parametrize("name", sorted(W.quad_small_cases()))
+def test_q4u_fields_and_energies(gpu, oracle_mod, name):
+    cfg = W.quad_small_cases()[name]
+    steps = 800
+    m = gpu.from_config(cfg)
+    o = oracle_mod.Oracle(cfg)
+    m.step(steps)
+    o.step(steps)
+    st = o.state()
+    assert (st["split"] != 0).sum() > len(cfg["notch"][0])  # a cracked state
+    fx, fy, sig, ok = o.internal_force(st["ux"], st["uy"], with_stress=True)
+    scale = max(np.abs(fx).max(), np.abs(fy).max())
+    gx, gy = m.field(gpu.FIELD_FINT)
+    assert np.abs(gx - fx).max() <= 1e-12 * scale and np.abs(gy - fy).max() <= 1e-12 * scale
+    gs = m.field(gpu.FIELD_SIGMA_EDGE)
+    okb = ok.astype(bool)
+    assert np.all(np.isnan(gs[~okb]))
+    smax = np.abs(sig[okb]).max()
+    assert np.abs(gs[okb] - sig[okb]).max() <= 1e-12 * smax
+    tabs = o.tables()
+    phi = o.load_factor(steps * o.info()["dt"])
+    fe = tabs["fext"]
+    ax = (phi * fe[:, 0] - fx) / tabs["mass"]
+    ay = (phi * fe[:, 1] - fy) / tabs["mass"]
+    nodes, masks, _ = cfg["vbc"]
+    for n, mk in zip(nodes, masks):
+        if mk & 1:
+            ax[n] = 0.0
+        if mk & 2:
+            ay[n] = 0.0
+    ga, gb = m.field(gpu.FIELD_A)
+    amax = max(np.abs(ax).max(), np.abs(ay).max())
+    assert np.abs(ga - ax).max() <= 1e-11 * amax and np.abs(gb - ay).max() <= 1e-11 * amax
+    ne = o.info()["ne"]
+    ee = _edge_index(tabs, ne)
+    split = st["split"]
+    gp = m.field(gpu.FIELD_PRINCIPAL)
+    assert np.all(np.isnan(gp[split != 0]))
+    intact = np.where(split == 0)[0]
+    mean = sig[ee[intact]].sum(axis=1) / 4.0
+    c = 0.5 * (mean[:, 0] + mean[:, 1])
+    r = np.sqrt((0.5 * (mean[:, 0] - mean[:, 1])) ** 2 + mean[:, 2] ** 2)
+    np.testing.assert_allclose(gp[intact], c + r, rtol=1e-12, atol=1e-12 * smax)
+    ge, oe = m.energies(), o.energies()
+    print(name, ge, oe, flush=True)
+    for k in ("kin", "strain", "wext"):
+        assert ge[k] == pytest.approx(oe[k], rel=1e-12, abs=1e-300), k
+    assert ge["Ud"] == pytest.approx(oe["Ud"], rel=1e-12)
+
+
+def test_q4u_checkpoint_restore(gpu):
+    cfg = W.quad_small_cases()["quad_plate24x10"]
+    a = gpu.from_config(cfg)
+    a.step(451)  # odd: the state sits in the second displacement buffer
+    ck = a.checkpoint()
+    a.step(400)
+    b = gpu.from_config(cfg, use_graph=False)
+    b.restore(ck)
+    b.step(400)
+    la, lb = a.crack_set(), b.crack_set()
+    for k in ("step", "elem", "entry", "exit", "G"):
+        assert np.array_equal(la[k], lb[k])
+    assert np.array_equal(a.field(0)[0], b.field(0)[0]) and np.array_equal(a.field(1)[1], b.field(1)[1])
+    assert a.info()["dissipated"] == b.info()["dissipated"]
+    # another mesh does not take it
+    with pytest.raises(gpu.MctError):
+        gpu.from_config(W.quad_small_cases()["grid70x37_unstructured"]).restore(ck)
+
+
+def test_q4u_invalid_meshes(gpu):
+    X = np.array([0.0, 1.0, 2.0, 0.0, 1.0, 2.0])
+    Y = np.array([0.0, 0.0, 0.0, 1.0, 1.0, 1.0])
+    good = np.array([[0, 1, 4, 3], [1, 2, 5, 4]], np.int32)
+    m = gpu.Model()
+    m.set_mesh_q4(X, Y, good)
+    # a dart: positive area, but it turns right at its third corner
+    dart = (np.array([0.0, 2.0, 0.5, 0.0]), np.array([0.0, 0.0, 0.5, 2.0]), np.array([[0, 1, 2, 3]], np.int32))
+    for xx, yy, conn in ((X, Y, good[:, [0, 3, 2, 1]]),  # clockwise
+                         (X, Y, np.array([[0, 1, 1, 3], [1, 2, 5, 4]], np.int32)),  # repeated node
+                         (X, Y, np.array([[0, 1, 4, 3], [1, 2, 5, 6]], np.int32)),  # out of range
+                         (X, Y, np.array([[0, 1, 4, 3], [0, 1, 4, 3]], np.int32)),  # edges reused one way
+                         dart):  # not convex
+        with pytest.raises(gpu.MctError):
+            m.set_mesh_q4(xx, yy, conn)
+    with pytest.raises(gpu.MctError):  # a node in no element
+        m.set_mesh_q4(np.append(X, 3.0), np.append(Y, 3.0), good)
+    m.set_mesh_q4(X, Y, good)
+    m.set_notch(np.array([0], np.int32), np.array([3], np.uint8), np.array([1], np.uint8))  # edges 0..3
+    with pytest.raises(gpu.MctError):
+        m.set_notch(np.array([0], np.int32), np.array([4], np.uint8), np.array([1], np.uint8))
+    with pytest.raises(gpu.MctError):  # sub-cell smoothing: structured grids only
+        m.set_smoothing("subcell")
+    with pytest.raises(gpu.MctError):  # plain binary64 contexts only
+        gpu.Model(precision=32).set_mesh_q4(X, Y, good)
+    with pytest.raises(gpu.MctError):
+        gpu.Model(n_specimens=2).set_mesh_q4(X, Y, good)
