@@ -327,7 +327,9 @@ int set_mesh(Model &m, Host h, int nv, int64_t nn, const double *X, const double
     if (nv != 3 && nv != 4) return fail(h, MCT_EINVAL, "elements have 3 or 4 nodes");
     if (nn < nv || ne < 1 || !X || !Y || !conn)
         return fail(h, MCT_EINVAL, "mesh needs >= %d nodes, >= 1 %s", nv, what);
-    if (ne > ((int64_t)1 << 29) || nn > ((int64_t)1 << 30)) return fail(h, MCT_EINVAL, "mesh too large");
+    // element * 4 + edge keys, force slots n * ne + e and list entries
+    // nv * e + n stay in int32
+    if (ne >= ((int64_t)1 << 29) || nn > ((int64_t)1 << 30)) return fail(h, MCT_EINVAL, "mesh too large");
     release(m);
     Model fresh;
     fresh.nv = nv;
