@@ -38,6 +38,8 @@ WORKLOADS = {
                "319792 triangles), notch 50 mm, 1 MPa",
     "cylinder53k": "pressured hollow cylinder r 50/100 mm on an unstructured CST mesh (h 1 mm, ~53000 triangles), "
                    "steel, 400 MPa pulse",
+    "quad160k": "branching plate 100x40 mm on an unstructured Q4 mesh (each Delaunay triangle of 259x104 "
+                "jittered points split into 3 quadrilaterals, ~160000 elements), notch 50 mm, 1 MPa",
 }
 
 
@@ -53,12 +55,17 @@ def bytes_per_step(cfgs, precision: int = 64) -> int:
     """Algorithmic HBM bytes of one step: per node read u, v, X, Y, 1/m and
     write u, v (11 values: 88 bytes in binary64, 44 in binary32); per Q4
     element its split code and its area (9 bytes, 5 in binary32; the
-    structured grid needs no connectivity); per CST element its split code
-    and its three node ids (13 bytes)."""
+    structured grid needs no connectivity); per element of an unstructured
+    mesh its split code and its node ids (13 bytes for a triangle, 17 for a
+    quadrilateral)."""
     w = 8 if precision == 64 else 4
     total = 0
     for c in cfgs:
-        total += 11 * w * n_nodes(c) + (13 if c.get("conn") is not None else 1 + w) * n_elems(c)
+        if c.get("conn") is not None:
+            per_elem = 1 + 4 * len(c["conn"][0])
+        else:
+            per_elem = 1 + w
+        total += 11 * w * n_nodes(c) + per_elem * n_elems(c)
     return total
 
 
@@ -79,12 +86,15 @@ MEASURED_TRAFFIC = {
     "batch256": {"sources": ("mct2d_step.hip", "mct2d_impl.h", "mct2d_device.h"),
                  "sha256": "a1bff16478392399f4310c25dd04486078e02be2e0f4ec6a09126a222be5fce0",
                  "tile": 1, "fetch_kib": 424165.6375, "write_kib": 487135.1203125},
-    # two launches per step: k_force (15 006.20 / 14 990.25) + k_node (17 011.00 / 5 024.44)
-    "tri320k": {"sources": TRI_SOURCES, "sha256": "6b7235fdbe3f2b76d4adc9549deae7e98228ff110a5f0582efd67564561afb1d",
-                "tile": 1, "fetch_kib": 32017.2, "write_kib": 20014.6875},
+    # two launches per step: k_force (15 010.69 / 14 990.25) + k_node (17 024.27 / 5 024.44)
+    "tri320k": {"sources": TRI_SOURCES, "sha256": "d16bede8607789a99646c87a563b8fe2c281e21a90c390afe2ace3d6c1bbe3cd",
+                "tile": 1, "fetch_kib": 32034.95655, "write_kib": 20014.6875},
     # one launch per step: k_fused on 64-node patches (the commit, once per 64 steps, is negligible)
-    "cylinder53k": {"sources": TRI_SOURCES, "sha256": "6b7235fdbe3f2b76d4adc9549deae7e98228ff110a5f0582efd67564561afb1d",
-                    "tile": 2, "fetch_kib": 5302.844375, "write_kib": 868.84375},
+    "cylinder53k": {"sources": TRI_SOURCES, "sha256": "d16bede8607789a99646c87a563b8fe2c281e21a90c390afe2ace3d6c1bbe3cd",
+                    "tile": 2, "fetch_kib": 5302.845, "write_kib": 868.84375},
+    # two launches per step: k_qforce (10 998.97 / 9 984.35) + k_node (12 405.03 / 5 005.25)
+    "quad160k": {"sources": TRI_SOURCES, "sha256": "d16bede8607789a99646c87a563b8fe2c281e21a90c390afe2ace3d6c1bbe3cd",
+                 "tile": 1, "fetch_kib": 23404.0003125, "write_kib": 14989.604375},
 }
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131086.604, 262144.0 / 262144.0
 
@@ -234,7 +244,8 @@ def main():
         m.screen_enable(mlp, screen["tau"], screen["period"])
     else:
         cfgs = [{"plate400": W.config2, "fragment2000": W.config3, "tri320k": W.tri_plate320k,
-                 "cylinder53k": lambda: W.tri_cylinder(steps=2000, name="cylinder53k")}[args.workload]()]
+                 "cylinder53k": lambda: W.tri_cylinder(steps=2000, name="cylinder53k"),
+                 "quad160k": W.quad_plate160k}[args.workload]()]
         if args.smoothing != "point":
             cfgs[0]["smoothing"] = args.smoothing
         if args.front_radius > 0:

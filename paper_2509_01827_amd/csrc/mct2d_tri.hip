@@ -274,74 +274,67 @@ __device__ __forceinline__ double quad_area(const double x[4], const double y[4]
 }
 
 // One piece of a split quadrilateral: the np = 1..3 local nodes after the
-// entry edge up to the exit edge, closed by the two crack midpoints (area
-// by a fan from the entry midpoint).  Three nodes: a constant-strain
+// entry edge EN up to the exit edge EX, closed by the two crack midpoints
+// (area by a fan from the entry midpoint).  Three nodes: a constant-strain
 // triangle over them whose forces are scaled by the piece's area; two: a
-// bar along them with cross-section A_piece / L; one: nothing.  F[d] is the
-// force on local node (entry + 1 + d) mod 4.
-struct QPiece {
-    int l0, np;
-    double2 F[3];
-    double w;  // strain energy
-};
-
-__device__ __forceinline__ QPiece quad_piece(const Params &p, const double2 ue[4], const double x[4],
-                                             const double y[4], int entry, int exit) {
-    QPiece r;
-    r.l0 = (entry + 1) & 3;
-    r.np = (exit - entry) & 3;
-    r.w = 0.0;
-    r.F[0] = r.F[1] = r.F[2] = make_double2(0.0, 0.0);
-    if (r.np == 1) return r;
-    const int l1 = (entry + 2) & 3, l2 = (entry + 3) & 3, e1 = (entry + 1) & 3, x1 = (exit + 1) & 3;
-    const double px0 = 0.5 * (sel4(entry, x[0], x[1], x[2], x[3]) + sel4(e1, x[0], x[1], x[2], x[3]));
-    const double py0 = 0.5 * (sel4(entry, y[0], y[1], y[2], y[3]) + sel4(e1, y[0], y[1], y[2], y[3]));
-    const double pxm = 0.5 * (sel4(exit, x[0], x[1], x[2], x[3]) + sel4(x1, x[0], x[1], x[2], x[3]));
-    const double pym = 0.5 * (sel4(exit, y[0], y[1], y[2], y[3]) + sel4(x1, y[0], y[1], y[2], y[3]));
-    const double2 P0 = make_double2(sel4(r.l0, x[0], x[1], x[2], x[3]), sel4(r.l0, y[0], y[1], y[2], y[3]));
-    const double2 P1 = make_double2(sel4(l1, x[0], x[1], x[2], x[3]), sel4(l1, y[0], y[1], y[2], y[3]));
-    const double2 P2 = make_double2(sel4(l2, x[0], x[1], x[2], x[3]), sel4(l2, y[0], y[1], y[2], y[3]));
-    // fan terms over the polygon M_entry, P0, .., M_exit
-    double s = 0.0;
-    s += (P0.x - px0) * (P1.y - py0) - (P1.x - px0) * (P0.y - py0);
-    if (r.np == 3) {
-        s += (P1.x - px0) * (P2.y - py0) - (P2.x - px0) * (P1.y - py0);
-        s += (P2.x - px0) * (pym - py0) - (pxm - px0) * (P2.y - py0);
+// bar along them with cross-section A_piece / L; one: nothing.  Adds the
+// forces of its nodes to f (each node lies in one piece) and returns the
+// strain energy.  The edges are template arguments, so every node value is
+// addressed statically.
+template <int EN, int EX>
+__device__ __forceinline__ double quad_piece(const Params &p, const double2 ue[4], const double x[4],
+                                             const double y[4], double2 f[4]) {
+    constexpr int np = (EX - EN) & 3;
+    constexpr int l0 = (EN + 1) & 3, l1 = (EN + 2) & 3, l2 = (EN + 3) & 3;
+    if constexpr (np == 1) {
+        f[l0] = make_double2(0.0, 0.0);
+        return 0.0;
     } else {
-        s += (P1.x - px0) * (pym - py0) - (pxm - px0) * (P1.y - py0);
+        const double px0 = 0.5 * (x[EN] + x[(EN + 1) & 3]), py0 = 0.5 * (y[EN] + y[(EN + 1) & 3]);
+        const double pxm = 0.5 * (x[EX] + x[(EX + 1) & 3]), pym = 0.5 * (y[EX] + y[(EX + 1) & 3]);
+        const double2 P0 = make_double2(x[l0], y[l0]), P1 = make_double2(x[l1], y[l1]);
+        // fan terms over the polygon M_entry, P0, .., M_exit
+        double s = 0.0;
+        s += (P0.x - px0) * (P1.y - py0) - (P1.x - px0) * (P0.y - py0);
+        if constexpr (np == 3) {
+            const double2 P2 = make_double2(x[l2], y[l2]);
+            s += (P1.x - px0) * (P2.y - py0) - (P2.x - px0) * (P1.y - py0);
+            s += (P2.x - px0) * (pym - py0) - (pxm - px0) * (P2.y - py0);
+            const double Ap = 0.5 * s;
+            const double2 u3[3] = {ue[l0], ue[l1], ue[l2]};
+            const Geo g = make_geo(P0, P1, P2);
+            double q[3], sg[3];
+            strain(g, u3, q);
+            hooke(p, q, sg);
+            f[l0] = make_double2(Ap * fma(g.by[0], sg[2], g.bx[0] * sg[0]), Ap * fma(g.bx[0], sg[2], g.by[0] * sg[1]));
+            f[l1] = make_double2(Ap * fma(g.by[1], sg[2], g.bx[1] * sg[0]), Ap * fma(g.bx[1], sg[2], g.by[1] * sg[1]));
+            f[l2] = make_double2(Ap * fma(g.by[2], sg[2], g.bx[2] * sg[0]), Ap * fma(g.bx[2], sg[2], g.by[2] * sg[1]));
+            return 0.5 * Ap * ((sg[0] * q[0] + sg[1] * q[1]) + sg[2] * q[2]);
+        } else {
+            s += (P1.x - px0) * (pym - py0) - (pxm - px0) * (P1.y - py0);
+            const double Ap = 0.5 * s;
+            const double dx = P1.x - P0.x, dy = P1.y - P0.y;
+            const double L2 = dx * dx + dy * dy;
+            const double dux = ue[l1].x - ue[l0].x, duy = ue[l1].y - ue[l0].y;
+            const double str = (dx * dux + dy * duy) / L2;
+            const double stress = p.E * str;
+            const double coef = Ap * stress / L2;
+            f[l1] = make_double2(coef * dx, coef * dy);
+            f[l0] = make_double2(-(coef * dx), -(coef * dy));
+            return 0.5 * Ap * stress * str;
+        }
     }
-    const double Ap = 0.5 * s;
-    const double2 u0 = sel4(r.l0, ue[0], ue[1], ue[2], ue[3]), u1 = sel4(l1, ue[0], ue[1], ue[2], ue[3]);
-    if (r.np == 2) {
-        const double dx = P1.x - P0.x, dy = P1.y - P0.y;
-        const double L2 = dx * dx + dy * dy;
-        const double dux = u1.x - u0.x, duy = u1.y - u0.y;
-        const double str = (dx * dux + dy * duy) / L2;
-        const double stress = p.E * str;
-        const double coef = Ap * stress / L2;
-        r.F[1] = make_double2(coef * dx, coef * dy);
-        r.F[0] = make_double2(-(coef * dx), -(coef * dy));
-        r.w = 0.5 * Ap * stress * str;
-        return r;
-    }
-    const double2 u3[3] = {u0, u1, sel4(l2, ue[0], ue[1], ue[2], ue[3])};
-    const Geo g = make_geo(P0, P1, P2);
-    double q[3], sg[3];
-    strain(g, u3, q);
-    hooke(p, q, sg);
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-        r.F[i] = make_double2(Ap * fma(g.by[i], sg[2], g.bx[i] * sg[0]), Ap * fma(g.bx[i], sg[2], g.by[i] * sg[1]));
-    r.w = 0.5 * Ap * ((sg[0] * q[0] + sg[1] * q[1]) + sg[2] * q[2]);
-    return r;
 }
 
-// Force of a split quadrilateral's pieces on local node n (every node lies
-// in exactly one piece).
-__device__ __forceinline__ double2 qpiece_force_at(const QPiece &a, const QPiece &b, int n) {
-    const int da = (n - a.l0) & 3, db = (n - b.l0) & 3;
-    if (da < a.np) return sel3(da, a.F[0], a.F[1], a.F[2]);
-    return sel3(db, b.F[0], b.F[1], b.F[2]);
+// Forces (into f) and strain energy (returned) of a quadrilateral split
+// along the path from local edge EN to local edge EX: the piece after the
+// entry edge, then the piece after the exit edge.
+template <int EN, int EX>
+__device__ __forceinline__ double quad_split(const Params &p, const double2 ue[4], const double x[4],
+                                             const double y[4], double2 f[4]) {
+    double w = quad_piece<EN, EX>(p, ue, x, y, f);
+    w += quad_piece<EX, EN>(p, ue, x, y, f);
+    return w;
 }
 
 // Everything a quadrilateral element contributes to one pass: its four
@@ -379,13 +372,22 @@ __device__ __forceinline__ void quad_element(const Params &p, const SplitView &s
         y[n] = xe[n].y;
     }
     if (code) {
-        const QPiece pa = quad_piece(p, ue, x, y, (code >> 2) & 3, code & 3);
-        const QPiece pb = quad_piece(p, ue, x, y, code & 3, (code >> 2) & 3);
+        double2 f[4];
+        double w = 0.0;
+        switch (code & 15) {
+#define QSPLIT(EN, EX) \
+    case (EN << 2) | EX: w = quad_split<EN, EX>(p, ue, x, y, f); break;
+            QSPLIT(0, 1) QSPLIT(0, 2) QSPLIT(0, 3) QSPLIT(1, 0) QSPLIT(1, 2) QSPLIT(1, 3)
+            QSPLIT(2, 0) QSPLIT(2, 1) QSPLIT(2, 3) QSPLIT(3, 0) QSPLIT(3, 1) QSPLIT(3, 2)
+#undef QSPLIT
+            default:  // entry = exit: rejected at set-up and never picked
 #pragma unroll
-        for (int n = 0; n < 4; ++n) fe[n * fs] = qpiece_force_at(pa, pb, n);
+                for (int n = 0; n < 4; ++n) f[n] = make_double2(0.0, 0.0);
+                break;
+        }
+#pragma unroll
+        for (int n = 0; n < 4; ++n) fe[n * fs] = f[n];
         if constexpr (EVAL) {
-            double w = pa.w;
-            w += pb.w;
             if (ev.pe) ev.pe[e] = w;
             if (ev.es_ek)
                 for (int k = 0; k < 4; ++k) ev.es_ek[4 * (int64_t)e + k] = 0.0;

@@ -619,6 +619,15 @@ def as_unstructured_q4(cfg, seed=BASE_SEED + 110):
     return c
 
 
+def quad_plate160k(steps=20000):
+    """The 100 x 40 mm Neumann branching plate on an unstructured
+    all-quadrilateral mesh: the Delaunay triangles of 259 x 104 jittered
+    points each split into three quadrilaterals (about 160 000 elements, the
+    400 x 400 Q4 plate's element count), half-length pre-notch."""
+    return quad_plate(258, 103, 0.1, 0.04, notch_len=0.05, steps=steps, seed=BASE_SEED + 120,
+                      name="quad_plate160k")
+
+
 def quad_small_cases():
     """Unstructured Q4 parity cases: the jittered 70 x 37 plate renumbered,
     and a plate of quadrilaterals split from triangles (irregular valences)."""

@@ -211,3 +211,15 @@ def test_q4u_invalid_meshes(gpu):
         gpu.Model(precision=32).set_mesh_q4(X, Y, good)
     with pytest.raises(gpu.MctError):
         gpu.Model(n_specimens=2).set_mesh_q4(X, Y, good)
+
+
+def test_q4u_fullsize_plate(gpu, oracle_mod):
+    """The unstructured Q4 benchmark mesh (about 160 000 quadrilaterals split
+    from Delaunay triangles) for 300 steps, as timed: bit-identical fields."""
+    cfg = W.quad_plate160k()
+    o = oracle_mod.Oracle(cfg)
+    m = gpu.from_config(cfg)
+    assert m.launch()["tile"] == 1
+    o.step(300)
+    m.step(300)
+    _same(m, o, "quad_plate160k")
