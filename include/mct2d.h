@@ -135,8 +135,8 @@ int mct_set_mesh_grid(mct_ctx *ctx, int32_t nx, int32_t ny, const double *X, con
  * space-filling curve) is the caller's choice and pays in cache reuse.
  * After this call the context runs the CST path: every set-up call, step
  * and query below applies to the triangle mesh, except the tile shapes
- * (mct_set_launch selects the step kernels instead), mct_autotune,
- * mct_get_path_geometry and the split-screen (MCT_EUNSUPPORTED).  Velocity conditions may be
+ * (mct_set_launch selects the step kernels instead), mct_autotune and the
+ * split-screen (MCT_EUNSUPPORTED).  Velocity conditions may be
  * prescribed at any node.  Errors: MCT_EINVAL for an index out of range, a
  * repeated node, a non-positive area (clockwise or degenerate), an edge
  * used by more than two triangles or twice in one direction, a node in no
@@ -323,7 +323,9 @@ int mct_get_energies(mct_ctx *ctx, double out[4]);
  * as the step evaluates it on the GPU: 36 doubles per element, for a = 0..3
  * and j = 0..2 (exit edge k = a+1+j mod 4) the unit normal (x, y) of the
  * segment G0-Gk oriented toward node n_{a+1}, and its length (reference
- * coordinates).  Elements out of range give MCT_EINVAL. */
+ * coordinates).  On a triangle mesh the paths are a = 0..2, j = 0..1 (exit
+ * edge a+1+j mod 3) and the other entries are NaN.  Elements out of range
+ * give MCT_EINVAL. */
 int mct_get_path_geometry(mct_ctx *ctx, int64_t n, const int32_t *elem, double *out);
 
 /* Split code of every element (n_elems bytes). */

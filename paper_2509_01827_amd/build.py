@@ -15,7 +15,8 @@ LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "libmct2d.so")
 SOURCES = [os.path.join(CSRC, "mct2d_api.cpp"), os.path.join(CSRC, "mct2d_step.hip"),
            os.path.join(CSRC, "mct2d_screen.hip"), os.path.join(CSRC, "mct2d_state.hip"),
-           os.path.join(CSRC, "mct2d_tri.hip"), os.path.join(CSRC, "mct2d_tri_host.cpp")]
+           os.path.join(CSRC, "mct2d_tri.hip"), os.path.join(CSRC, "mct2d_tri_host.cpp"),
+           os.path.join(CSRC, "mct2d_tri_geom.hip")]
 HEADERS = [os.path.join(CSRC, "mct2d_impl.h"), os.path.join(CSRC, "mct2d_device.h"),
            os.path.join(CSRC, "mct2d_tri.h"), os.path.join(CSRC, "mct2d_tri_host.h"),
            os.path.join(ROOT, "include", "mct2d.h")]

@@ -1573,7 +1573,7 @@ int mct_get_energies(mct_ctx *c, double out[4]) {
 
 int mct_get_path_geometry(mct_ctx *c, int64_t n, const int32_t *elem, double *out) {
     if (!c || n < 0 || (n && (!elem || !out))) return MCT_EINVAL;
-    TRI_UNSUPPORTED(c, "path geometry");
+    TRI_FWD(c, get_path_geometry, n, elem, out);
     if (!c->finalized) return fail(c, MCT_ESTATE, "finalize first");
     const Spec &s = cur(c);
     if (n > INT32_MAX / 36) return fail(c, MCT_EINVAL, "too many elements");

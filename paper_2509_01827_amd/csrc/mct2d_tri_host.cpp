@@ -9,6 +9,7 @@
 // order (smallest colour not used by an earlier element sharing a node), and
 // the nodal sums of element forces run in colour order.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -1049,6 +1050,30 @@ int get_split_codes(Model &m, Host h, int64_t cap, uint8_t *out) {
     if (cap < m.ne) return fail(h, MCT_ECAPACITY, "need %lld bytes", (long long)m.ne);
     TRY(h, hipMemcpyAsync(out, m.dsplit, m.ne, hipMemcpyDeviceToHost, h.stream));
     TRY(h, hipStreamSynchronize(h.stream));
+    return MCT_OK;
+}
+
+int get_path_geometry(Model &m, Host h, int64_t n, const int32_t *elem, double *out) {
+    if (!m.finalized) return fail(h, MCT_ESTATE, "finalize first");
+    if (n > INT32_MAX / 36) return fail(h, MCT_EINVAL, "too many elements");
+    for (int64_t i = 0; i < n; ++i)
+        if (elem[i] < 0 || elem[i] >= m.ne) return fail(h, MCT_EINVAL, "element %d out of range", elem[i]);
+    if (!n) return MCT_OK;
+    int32_t *de = nullptr;
+    double *dout = nullptr;
+    TRY(h, hipMalloc((void **)&de, sizeof(int32_t) * (size_t)n));
+    if (hipMalloc((void **)&dout, sizeof(double) * 36 * (size_t)n) != hipSuccess) {
+        (void)hipFree(de);
+        return fail(h, MCT_ENOMEM, "geometry buffer");
+    }
+    hipError_t e = hipMemcpyAsync(de, elem, sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, h.stream);
+    if (e == hipSuccess) e = launch_path_geometry(m.prm, (int)n, de, dout, h.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out, dout, sizeof(double) * 36 * (size_t)n, hipMemcpyDeviceToHost, h.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h.stream);
+    (void)hipFree(de);
+    (void)hipFree(dout);
+    if (e != hipSuccess) return fail(h, MCT_EDEVICE, "path geometry: %s", hipGetErrorString(e));
     return MCT_OK;
 }
 

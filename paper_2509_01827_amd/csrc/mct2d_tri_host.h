@@ -120,6 +120,11 @@ int get_field(Model &m, Host h, int which, int64_t cap, double *out);
 int get_energies(Model &m, Host h, double out[4]);
 int get_split_codes(Model &m, Host h, int64_t cap, uint8_t *out);
 int checkpoint(Model &m, Host h, void *buf, int64_t cap, int64_t *bytes);
+// Crack-path normals and lengths of n elements, 36 values each
+// (mct_get_path_geometry's layout; NaN where a triangle has no such path).
+int get_path_geometry(Model &m, Host h, int64_t n, const int32_t *elem, double *out);
+// Device side (mct2d_tri_geom.hip).
+hipError_t launch_path_geometry(const Params &p, int n, const int32_t *elem, double *out, hipStream_t st);
 int restore(Model &m, Host h, const void *buf, int64_t bytes);
 
 }  // namespace tri

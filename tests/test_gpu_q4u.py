@@ -223,3 +223,28 @@ def test_q4u_fullsize_plate(gpu, oracle_mod):
     o.step(300)
     m.step(300)
     _same(m, o, "quad_plate160k")
+
+
+@pytest.mark.parametrize("kind", ["q4u", "tri"])
+def test_unstructured_path_geometry_bitwise(gpu, oracle_mod, kind):
+    """mct_get_path_geometry on unstructured meshes: every path of sampled
+    elements equals the oracle's normal and length bit for bit; paths a
+    triangle does not have are NaN."""
+    cfg = (W.quad_small_cases()["quad_plate24x10"] if kind == "q4u"
+           else W.tri_small_cases()["tri_plate40x16"])
+    nv = np.asarray(cfg["conn"]).shape[1]
+    m = gpu.from_config(cfg)
+    o = oracle_mod.Oracle(cfg)
+    ne = len(cfg["conn"])
+    elems = np.unique(np.linspace(0, ne - 1, 97).astype(np.int32))
+    g = m.path_geometry(elems)
+    for i, e in enumerate(elems):
+        for a in range(4):
+            for j in range(3):
+                if a >= nv or j >= nv - 1:
+                    assert np.all(np.isnan(g[i, a, j])), (e, a, j)
+                    continue
+                k = (a + 1 + j) % nv
+                assert np.array_equal(g[i, a, j], o.path_normal(int(e), a, k)), (kind, e, a, k)
+    with pytest.raises(gpu.MctError):
+        m.path_geometry(np.array([ne], np.int32))
