@@ -135,8 +135,8 @@ int mct_set_mesh_grid(mct_ctx *ctx, int32_t nx, int32_t ny, const double *X, con
  * space-filling curve) is the caller's choice and pays in cache reuse.
  * After this call the context runs the CST path: every set-up call, step
  * and query below applies to the triangle mesh, except the tile shapes
- * (mct_set_launch selects the step kernels instead), mct_autotune and the
- * split-screen (MCT_EUNSUPPORTED).  Velocity conditions may be
+ * (mct_set_launch and mct_autotune select the step kernels instead) and
+ * the split-screen (MCT_EUNSUPPORTED).  Velocity conditions may be
  * prescribed at any node.  Errors: MCT_EINVAL for an index out of range, a
  * repeated node, a non-positive area (clockwise or degenerate), an edge
  * used by more than two triangles or twice in one direction, a node in no
@@ -370,8 +370,12 @@ int mct_set_order(mct_ctx *ctx, int order);
 
 /* Launch autotuner: times trial_steps steps for every tile shape (and, for
  * a batch, every unit order) from the current state, restores that state
- * and keeps the fastest choice.  Outputs (any may be NULL): the chosen tile,
- * order and its time per step in microseconds. */
+ * and keeps the fastest choice.  On an unstructured mesh the choices are
+ * the step kernels of mct_set_launch (triangles: 1 the element plus node
+ * kernels, 2/3/4 the fused kernel on 64/128/256-node patches;
+ * quadrilaterals: 1 only).  Outputs (any may be NULL): the chosen tile (as
+ * mct_get_launch reports it), order and its time per step in
+ * microseconds. */
 int mct_autotune(mct_ctx *ctx, int trial_steps, int *tile, int *order, double *us_per_step);
 
 /* Launch shape in use: tile index, unit order, workgroups per step (on a

@@ -1724,9 +1724,64 @@ int mct_restore(mct_ctx *c, const void *buf, int64_t bytes) {
     return MCT_OK;
 }
 
+// The autotuner of an unstructured mesh: every step-kernel choice (the
+// element plus node kernels; for triangles also the fused kernel on 64-,
+// 128- and 256-node patches) timed from the current state, which is then
+// restored; the fastest choice is kept.
+static int autotune_unstructured(mct_ctx *c, int trial_steps, int *tile_out, int *order_out,
+                                 double *us_per_step_out) {
+    mct::tri::Model &m = *c->tri;
+    const mct::tri::Host h{c->err, c->stream};
+    if (!m.finalized) return fail(c, MCT_ESTATE, "finalize first");
+    if (trial_steps < 1) return fail(c, MCT_EINVAL, "trial_steps must be positive");
+    int64_t bytes = 0;
+    int rc = mct::tri::checkpoint(m, h, nullptr, 0, &bytes);
+    if (rc) return rc;
+    std::vector<char> ck((size_t)bytes);
+    if ((rc = mct::tri::checkpoint(m, h, ck.data(), bytes, &bytes))) return rc;
+    const int saved_kind = m.kernels;
+    const bool saved_graph = m.use_graph;
+    m.use_graph = false;  // candidates are timed with direct launches
+    float best = INFINITY;
+    int best_kind = 1;
+    const int nkinds = m.nv == 3 ? 4 : 1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = MCT_EDEVICE;
+    for (int kind = 1; kind <= nkinds && rc == MCT_OK; ++kind) {
+        if ((rc = mct::tri::set_kernels(m, h, kind))) break;
+        if ((rc = mct::tri::restore(m, h, ck.data(), bytes))) break;
+        if ((rc = mct::tri::step(m, h, 2))) break;  // warm
+        if (hipEventRecord(e0, c->stream) != hipSuccess) rc = MCT_EDEVICE;
+        if (!rc) rc = mct::tri::step(m, h, trial_steps);
+        if (!rc && hipEventRecord(e1, c->stream) != hipSuccess) rc = MCT_EDEVICE;
+        if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = MCT_EDEVICE;
+        float ms = 0.f;
+        if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = MCT_EDEVICE;
+        if (!rc && ms < best) {
+            best = ms;
+            best_kind = kind;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    m.use_graph = saved_graph;
+    if (rc) {
+        (void)mct::tri::set_kernels(m, h, saved_kind);
+        (void)mct::tri::restore(m, h, ck.data(), bytes);
+        return rc == MCT_EDEVICE ? fail(c, rc, "autotune timing failed") : rc;
+    }
+    if ((rc = mct::tri::set_kernels(m, h, best_kind))) return rc;
+    if ((rc = mct::tri::restore(m, h, ck.data(), bytes))) return rc;
+    const int P = m.prm.patch_emax > 0 ? m.prm.patch_nodes : 0;
+    if (tile_out) *tile_out = P == 64 ? 2 : P == 128 ? 3 : P == 256 ? 4 : 1;
+    if (order_out) *order_out = 0;
+    if (us_per_step_out) *us_per_step_out = 1e3 * (double)best / trial_steps;
+    return MCT_OK;
+}
+
 int mct_autotune(mct_ctx *c, int trial_steps, int *tile_out, int *order_out, double *us_per_step_out) {
     if (!c) return MCT_EINVAL;
-    TRI_UNSUPPORTED(c, "autotune");
+    if (c->tri) return autotune_unstructured(c, trial_steps, tile_out, order_out, us_per_step_out);
     if (!c->finalized) return fail(c, MCT_ESTATE, "finalize first");
     if (trial_steps < 1) return fail(c, MCT_EINVAL, "trial_steps must be positive");
     int64_t bytes = 0;

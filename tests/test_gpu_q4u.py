@@ -248,3 +248,25 @@ def test_unstructured_path_geometry_bitwise(gpu, oracle_mod, kind):
                 assert np.array_equal(g[i, a, j], o.path_normal(int(e), a, k)), (kind, e, a, k)
     with pytest.raises(gpu.MctError):
         m.path_geometry(np.array([ne], np.int32))
+
+
+@pytest.mark.parametrize("kind", ["q4u", "tri"])
+def test_unstructured_autotune(gpu, oracle_mod, kind):
+    """The autotuner of an unstructured mesh times its step-kernel choices,
+    keeps the fastest and leaves the state as it was: the run continues
+    bit-identical to the oracle."""
+    cfg = (W.quad_small_cases()["quad_plate24x10"] if kind == "q4u"
+           else W.tri_small_cases()["tri_cylinder_coarse"])
+    m = gpu.from_config(cfg)
+    o = oracle_mod.Oracle(cfg)
+    m.step(400)
+    o.step(400)
+    r = m.autotune(trial_steps=30)
+    print(kind, r, flush=True)
+    assert r["tile"] in ((1,) if kind == "q4u" else (1, 2, 3, 4)) and r["us_per_step"] > 0
+    assert m.launch()["tile"] == r["tile"]
+    assert m.info()["step"] == 400
+    _same(m, o, (kind, "after autotune"))
+    m.step(300)
+    o.step(300)
+    _same(m, o, (kind, "continued"))
