@@ -75,26 +75,24 @@ def bytes_per_step(cfgs, precision: int = 64) -> int:
 # of a 256 MiB device copy (FETCH_SIZE x 1.99979, WRITE_SIZE x 1.0).  A figure
 # holds for the kernel sources it was taken on (their hash) and the tile
 # shape; otherwise the traffic is reported as unknown.
+Q4_SOURCES = ("mct2d_step.hip", "mct2d_impl.h", "mct2d_device.h")
 TRI_SOURCES = ("mct2d_tri.hip", "mct2d_tri.h", "mct2d_front.h", "mct2d_device.h", "mct2d_impl.h")
 MEASURED_TRAFFIC = {
-    "plate400": {"sources": ("mct2d_step.hip", "mct2d_impl.h", "mct2d_device.h"),
-                 "sha256": "a1bff16478392399f4310c25dd04486078e02be2e0f4ec6a09126a222be5fce0",
-                 "tile": 1, "fetch_kib": 5599.51375, "write_kib": 5044.40625},
-    "plate400_f32": {"sources": ("mct2d_step.hip", "mct2d_impl.h", "mct2d_device.h"),
-                     "sha256": "a1bff16478392399f4310c25dd04486078e02be2e0f4ec6a09126a222be5fce0",
-                     "tile": 1, "fetch_kib": 2971.135, "write_kib": 2534.78125},
-    "batch256": {"sources": ("mct2d_step.hip", "mct2d_impl.h", "mct2d_device.h"),
-                 "sha256": "a1bff16478392399f4310c25dd04486078e02be2e0f4ec6a09126a222be5fce0",
-                 "tile": 1, "fetch_kib": 424165.6375, "write_kib": 487135.1203125},
-    # two launches per step: k_force (15 010.69 / 14 990.25) + k_node (17 024.27 / 5 024.44)
-    "tri320k": {"sources": TRI_SOURCES, "sha256": "d16bede8607789a99646c87a563b8fe2c281e21a90c390afe2ace3d6c1bbe3cd",
-                "tile": 1, "fetch_kib": 32034.95655, "write_kib": 20014.6875},
+    "plate400": {"sources": Q4_SOURCES, "sha256": "e21cb10097444fa6533a4ce77a20f1c40cff18503738fada4504552f6d92e596",
+                 "tile": 1, "fetch_kib": 5604.514375, "write_kib": 5044.40625},
+    "plate400_f32": {"sources": Q4_SOURCES, "sha256": "e21cb10097444fa6533a4ce77a20f1c40cff18503738fada4504552f6d92e596",
+                     "tile": 1, "fetch_kib": 2967.829375, "write_kib": 2534.78125},
+    "batch256": {"sources": Q4_SOURCES, "sha256": "e21cb10097444fa6533a4ce77a20f1c40cff18503738fada4504552f6d92e596",
+                 "tile": 1, "fetch_kib": 423823.190625, "write_kib": 485850.68125},
+    # two launches per step: k_force (15 006.17 / 14 990.25) + k_node (17 014.01 / 5 024.44)
+    "tri320k": {"sources": TRI_SOURCES, "sha256": "9991853dfaedba4f0b5c1afc6731b7505f9e3ec19df83254745b697753d12dde",
+                "tile": 1, "fetch_kib": 32020.18375, "write_kib": 20014.6875},
     # one launch per step: k_fused on 64-node patches (the commit, once per 64 steps, is negligible)
-    "cylinder53k": {"sources": TRI_SOURCES, "sha256": "d16bede8607789a99646c87a563b8fe2c281e21a90c390afe2ace3d6c1bbe3cd",
-                    "tile": 2, "fetch_kib": 5302.845, "write_kib": 868.84375},
-    # two launches per step: k_qforce (10 998.97 / 9 984.35) + k_node (12 405.03 / 5 005.25)
-    "quad160k": {"sources": TRI_SOURCES, "sha256": "d16bede8607789a99646c87a563b8fe2c281e21a90c390afe2ace3d6c1bbe3cd",
-                 "tile": 1, "fetch_kib": 23404.0003125, "write_kib": 14989.604375},
+    "cylinder53k": {"sources": TRI_SOURCES, "sha256": "9991853dfaedba4f0b5c1afc6731b7505f9e3ec19df83254745b697753d12dde",
+                    "tile": 2, "fetch_kib": 5302.3446875, "write_kib": 868.84375},
+    # two launches per step: k_qforce (10 982.15 / 9 974.60) + k_node (12 405.03 / 5 005.25)
+    "quad160k": {"sources": TRI_SOURCES, "sha256": "9991853dfaedba4f0b5c1afc6731b7505f9e3ec19df83254745b697753d12dde",
+                 "tile": 1, "fetch_kib": 23387.1796875, "write_kib": 14979.84984375},
 }
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131086.604, 262144.0 / 262144.0
 

@@ -84,10 +84,13 @@ __device__ __forceinline__ void cand_wave_reduce(CandT<T> &c) {
     }
 }
 
-// Workgroup-wide reduction; the result is valid in thread 0.
+// Workgroup-wide reduction; the result is valid in thread 0.  A wave whose
+// lanes hold no candidate (G < 0 everywhere: the empty value, which merging
+// leaves unchanged) skips the shuffle tree; its lane 0 already holds the
+// wave's result.
 template <int NT, class T>
 __device__ __forceinline__ void cand_block_reduce(CandT<T> &c, CandT<T> *red) {
-    cand_wave_reduce(c);
+    if (__ballot(c.G >= T(0)) != 0ull) cand_wave_reduce(c);  // uniform over the wave
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) red[wave] = c;
     __syncthreads();

@@ -753,14 +753,15 @@ __device__ __forceinline__ bool better(const Cand &a, const Cand &b) {
     return (a.ak >> 2) < (b.ak >> 2);
 }
 
-// MCT pick of step k over the candidate list (whole workgroup), then the
-// split, its log record, U_d and the single tip.
 // Best of n accepted candidates (largest G, then lower element, then lower
 // tip edge) and the smallest G, by the whole workgroup; valid in thread 0.
-// n is uniform over the workgroup.
+// n is uniform over the workgroup.  Each thread scans its share of the
+// list, each wave holding an entry reduces by shuffles (the order is total,
+// so the result does not depend on the grouping), and thread 0 merges the
+// waves' results.
 __device__ __forceinline__ void best_of(const Cand *list, int n, Cand &best_out, double &gmin_out) {
-    __shared__ Cand s_best[kB];
-    __shared__ double s_min[kB];
+    __shared__ Cand s_best[kB / 64];
+    __shared__ double s_min[kB / 64];
     Cand best;
     best.G = -1.0;
     best.elem = 0x7fffffff;
@@ -771,18 +772,32 @@ __device__ __forceinline__ void best_of(const Cand *list, int n, Cand &best_out,
         if (better(cd, best)) best = cd;
         gmin = fmin(gmin, cd.G);
     }
-    s_best[threadIdx.x] = best;
-    s_min[threadIdx.x] = gmin;
-    __syncthreads();
-    for (int w = kB / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            if (better(s_best[threadIdx.x + w], s_best[threadIdx.x])) s_best[threadIdx.x] = s_best[threadIdx.x + w];
-            s_min[threadIdx.x] = fmin(s_min[threadIdx.x], s_min[threadIdx.x + w]);
+    if (__ballot(best.G >= 0.0) != 0ull) {  // uniform over the wave
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            Cand o;
+            o.G = __shfl_xor(best.G, off, 64);
+            o.elem = __shfl_xor(best.elem, off, 64);
+            o.ak = __shfl_xor(best.ak, off, 64);
+            const double gm = __shfl_xor(gmin, off, 64);
+            if (better(o, best)) best = o;
+            gmin = fmin(gmin, gm);
         }
-        __syncthreads();
     }
-    best_out = s_best[0];
-    gmin_out = s_min[0];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        s_best[wave] = best;
+        s_min[wave] = gmin;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kB / 64; ++w) {
+            if (better(s_best[w], best)) best = s_best[w];
+            gmin = fmin(gmin, s_min[w]);
+        }
+    }
+    best_out = best;
+    gmin_out = gmin;
 }
 
 // Record the split of step k picked from candidate b: its code, the log,
