@@ -270,3 +270,25 @@ def test_unstructured_autotune(gpu, oracle_mod, kind):
     m.step(300)
     o.step(300)
     _same(m, o, (kind, "continued"))
+
+
+@pytest.mark.parametrize("kind", ["fragment_ramp_weibull", "pulse_curve"])
+def test_q4u_loading_variants(gpu, oracle_mod, kind):
+    """Renumbered grids under the other loadings: outward edge velocities
+    with a ramp and a Weibull Gc field (fragmentation), and a traction
+    pulse given by a load curve; bit-identical to the oracle."""
+    if kind == "fragment_ramp_weibull":
+        base = dict(W.fragmentation(61, 33, 1e-3, seed=W.BASE_SEED + 17, steps=400), t_ramp=5e-6)
+    else:
+        base = W.pulse_plate(48, 32, 0.048, 0.032, peak=2e6, steps=900, t0=2e-5, tau=4e-5)
+    cfg = W.as_unstructured_q4(base)
+    o = oracle_mod.Oracle(cfg)
+    m = gpu.from_config(cfg)
+    done = 0
+    for chunk in (1, 99, 300, 500):
+        o.step(chunk)
+        m.step(chunk)
+        done += chunk
+        _same(m, o, (kind, done))
+    assert len(o.log()["elem"]) > 0, kind
+    print(kind, "splits", len(o.log()["elem"]), flush=True)
