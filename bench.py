@@ -78,12 +78,12 @@ def bytes_per_step(cfgs, precision: int = 64) -> int:
 Q4_SOURCES = ("mct2d_step.hip", "mct2d_impl.h", "mct2d_device.h")
 TRI_SOURCES = ("mct2d_tri.hip", "mct2d_tri.h", "mct2d_front.h", "mct2d_device.h", "mct2d_impl.h")
 MEASURED_TRAFFIC = {
-    "plate400": {"sources": Q4_SOURCES, "sha256": "e21cb10097444fa6533a4ce77a20f1c40cff18503738fada4504552f6d92e596",
-                 "tile": 1, "fetch_kib": 5604.514375, "write_kib": 5044.40625},
-    "plate400_f32": {"sources": Q4_SOURCES, "sha256": "e21cb10097444fa6533a4ce77a20f1c40cff18503738fada4504552f6d92e596",
-                     "tile": 1, "fetch_kib": 2967.829375, "write_kib": 2534.78125},
-    "batch256": {"sources": Q4_SOURCES, "sha256": "e21cb10097444fa6533a4ce77a20f1c40cff18503738fada4504552f6d92e596",
-                 "tile": 1, "fetch_kib": 423823.190625, "write_kib": 485850.68125},
+    "plate400": {"sources": Q4_SOURCES, "sha256": "a6140c37bbd33d5cff0a1091d3cdfe767eaf756c679d596bb8c541efb07f717e",
+                 "tile": 1, "fetch_kib": 5589.8934375, "write_kib": 5044.40625},
+    "plate400_f32": {"sources": Q4_SOURCES, "sha256": "a6140c37bbd33d5cff0a1091d3cdfe767eaf756c679d596bb8c541efb07f717e",
+                     "tile": 1, "fetch_kib": 2959.135, "write_kib": 2534.78125},
+    "batch256": {"sources": Q4_SOURCES, "sha256": "a6140c37bbd33d5cff0a1091d3cdfe767eaf756c679d596bb8c541efb07f717e",
+                 "tile": 1, "fetch_kib": 423857.846875, "write_kib": 486074.4453125},
     # two launches per step: k_force (15 006.17 / 14 990.25) + k_node (17 014.01 / 5 024.44)
     "tri320k": {"sources": TRI_SOURCES, "sha256": "9991853dfaedba4f0b5c1afc6731b7505f9e3ec19df83254745b697753d12dde",
                 "tile": 1, "fetch_kib": 32020.18375, "write_kib": 20014.6875},

@@ -104,9 +104,10 @@ typedef struct {
  * A binary32 context reports u, v, split codes, the crack set (G exact in
  * binary64) and tips as computed; the derived fields and energies are
  * evaluated in binary64 from its state; checkpoints hold that state and
- * restore only into a binary32 context.  Not for binary32: triangle meshes,
- * batches, the split-screen, sub-cell smoothing, the per-front pick
- * (MCT_EUNSUPPORTED from the call that asks for them).
+ * restore only into a binary32 context.  Not for binary32: unstructured
+ * meshes, batches, the split-screen, the per-front pick (MCT_EUNSUPPORTED
+ * from the call that asks for them).  Sub-cell smoothing runs in binary32
+ * like the point rule.
  * hip_stream: a hipStream_t to enqueue on, or NULL for a library stream.
  * Errors: MCT_EINVAL (out NULL), MCT_EUNSUPPORTED (precision), MCT_EDEVICE. */
 int mct_create(mct_ctx **out, int precision, void *hip_stream);

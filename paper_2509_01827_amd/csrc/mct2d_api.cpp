@@ -437,6 +437,7 @@ void refresh_f32(mct_ctx *c) {
     f.area = c->farea;
     f.screen = nullptr;
     f.sct = p.sct;
+    f.subcell = p.subcell;
     f.ncurve = p.ncurve;
     f.curve_t = p.curve_t;
     f.curve_phi = p.curve_phi;
@@ -1036,8 +1037,6 @@ int mct_set_smoothing(mct_ctx *c, int mode) {
     }
     if (c->batch && mode == MCT_SMOOTH_SUBCELL)
         return fail(c, MCT_EUNSUPPORTED, "sub-cell smoothing needs a plain context");
-    if (c->precision == 32 && mode == MCT_SMOOTH_SUBCELL)
-        return fail(c, MCT_EUNSUPPORTED, "sub-cell smoothing needs binary64");
     Spec &s = cur(c);
     if (!s.nx) return fail(c, MCT_ESTATE, "set the mesh first");
     s.subcell = mode == MCT_SMOOTH_SUBCELL;

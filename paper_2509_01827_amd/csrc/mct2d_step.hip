@@ -974,13 +974,28 @@ __global__ __launch_bounds__(kFrontThreads) void k_front(StepParams p, int k_rel
 hipError_t launch_step(int tile, const Launch &L, int k_rel, int par0, hipStream_t s) {
     (void)hipGetLastError();  // report only this launch's error below
     if (L.f32) {
-        // binary32 step: plain models with the point rule and the global or
-        // single-tip pick
+        // binary32 step: plain models with the point rule or sub-cell
+        // smoothing and the global or single-tip pick
         const StepParamsF &p = L.p0f;
         switch (tile) {
-            case 1: k_step<float, 16, 16, false><<<p.nwg, 256, 0, s>>>(p, nullptr, nullptr, k_rel, par0); break;
-            case 2: k_step<float, 32, 8, false><<<p.nwg, 256, 0, s>>>(p, nullptr, nullptr, k_rel, par0); break;
-            default: k_step<float, 32, 16, false><<<p.nwg, 512, 0, s>>>(p, nullptr, nullptr, k_rel, par0); break;
+            case 1:
+                if (p.subcell)
+                    k_step<float, 16, 16, false, true><<<p.nwg, 256, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
+                else
+                    k_step<float, 16, 16, false><<<p.nwg, 256, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
+                break;
+            case 2:
+                if (p.subcell)
+                    k_step<float, 32, 8, false, true><<<p.nwg, 256, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
+                else
+                    k_step<float, 32, 8, false><<<p.nwg, 256, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
+                break;
+            default:
+                if (p.subcell)
+                    k_step<float, 32, 16, false, true><<<p.nwg, 512, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
+                else
+                    k_step<float, 32, 16, false><<<p.nwg, 512, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
+                break;
         }
         return hipGetLastError();
     }

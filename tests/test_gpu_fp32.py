@@ -139,8 +139,6 @@ def test_fp32_checkpoint(gpu):
 def test_fp32_unsupported(gpu):
     cfg = _f32(W.small_cases()["plate40x40"])
     with pytest.raises(gpu.MctError):
-        gpu.from_config(dict(cfg, smoothing="subcell"))
-    with pytest.raises(gpu.MctError):
         gpu.from_config(dict(cfg, front_radius=1e-3))
     t = W.tri_small_cases()["tri_plate40x16"]
     m = gpu.Model(precision=32)
@@ -148,3 +146,20 @@ def test_fp32_unsupported(gpu):
         m.set_mesh_tri(t["X"], t["Y"], t["conn"])
     with pytest.raises(gpu.MctError):
         gpu.Model(precision=32, n_specimens=2)
+
+
+@pytest.mark.parametrize("name", ["plate70x37_jitter", "fragment97x45"])
+def test_fp32_subcell_matches_oracle(gpu, oracle_mod, name):
+    """Sub-cell smoothing in binary32: bit-identical to the oracle's binary32
+    build for every tile shape, with and without graphs."""
+    cfg = _f32(dict(W.small_cases()[name], smoothing="subcell"))
+    o = oracle_mod.Oracle(cfg)
+    models = [gpu.from_config(cfg, tile=t, use_graph=g) for t in (1, 2, 3) for g in (True, False)]
+    done = 0
+    for chunk in (1, 63, 136, 400):
+        o.step(chunk)
+        done += chunk
+        for m in models:
+            m.step(chunk)
+            _same(m, o, (name, "subcell", done, m.launch()["tile"]))
+    assert len(o.log()["elem"]) > 0

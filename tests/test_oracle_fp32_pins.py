@@ -170,3 +170,26 @@ def test_rule_and_pick_tables_binary32(oracle_mod):
     for G, el, a, gamma, exp in PICKS:
         assert oracle_mod.mct_pick(G, el, a, gamma, precision=32) == exp
         assert oracle_mod.mct_pick(G, el, a, gamma, precision=64) == exp
+
+
+def test_subcell_internal_force_within_binary32_error(oracle_mod):
+    """Sub-cell smoothing in the binary32 build: on the same binary32 inputs
+    its internal force is the binary64 build's within 5e-5 max|f| (the
+    derivation of the point-rule bound applies: short sums of products of
+    gradients, stresses and areas), and not equal to it."""
+    cfg = dict(W.small_cases()["plate70x37_jitter"], smoothing="subcell")
+    o32 = oracle_mod.Oracle(dict(cfg, precision=32))
+    o64 = oracle_mod.Oracle(dict(cfg, X=_f32(cfg["X"]), Y=_f32(cfg["Y"])))
+    crack = oracle_mod.run(cfg, 900).state()["split"]
+    assert (crack != 0).sum() > 40
+    o32.set_split_codes(crack)
+    o64.set_split_codes(crack)
+    rng = np.random.default_rng(4)
+    ux = _f32(rng.standard_normal(len(cfg["X"])) * 1e-6)
+    uy = _f32(rng.standard_normal(len(cfg["X"])) * 1e-6)
+    a = o32.internal_force(ux, uy)
+    b = o64.internal_force(ux, uy)
+    scale = max(np.abs(b[0]).max(), np.abs(b[1]).max())
+    err = max(np.abs(a[0] - b[0]).max(), np.abs(a[1] - b[1]).max()) / scale
+    assert 1e-9 < err < 5e-5
+    assert _is_f32(a[0]) and _is_f32(a[1])
