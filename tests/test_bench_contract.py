@@ -56,3 +56,21 @@ def test_bench_json_line():
     cb = d["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["cores"] >= 1 and cb["value"] > 0
     assert "workload" in d["config"]
+
+
+def test_algorithmic_bytes_per_mesh_kind():
+    """bytes_per_step: 88 B per node (u, v, X, Y, 1/m read; u, v written) plus
+    per element 9 B on the structured grid (split code, area), 13 B for a
+    triangle and 17 B for a quadrilateral of an unstructured mesh (split code,
+    node ids); binary32 halves the floating-point part."""
+    sys.path.insert(0, ROOT)
+    import bench
+    import numpy as np
+    grid = {"nx": 4, "ny": 3, "X": np.zeros(20)}
+    tri = {"conn": np.zeros((7, 3), np.int32), "X": np.zeros(9)}
+    quad = {"conn": np.zeros((5, 4), np.int32), "X": np.zeros(11)}
+    assert bench.bytes_per_step([grid]) == 88 * 20 + 9 * 12
+    assert bench.bytes_per_step([grid], precision=32) == 44 * 20 + 5 * 12
+    assert bench.bytes_per_step([tri]) == 88 * 9 + 13 * 7
+    assert bench.bytes_per_step([quad]) == 88 * 11 + 17 * 5
+    assert bench.bytes_per_step([grid, tri]) == 88 * 29 + 9 * 12 + 13 * 7
