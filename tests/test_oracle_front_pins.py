@@ -27,10 +27,13 @@ def _same_log(a, b):
     return all(np.array_equal(a[k], b[k]) for k in ("step", "elem", "entry", "exit", "G"))
 
 
-@pytest.mark.parametrize("kind", ["q4", "cst"])
+@pytest.mark.parametrize("kind", ["q4", "cst", "q4u"])
 def test_infinite_radius_is_the_global_pick(oracle_mod, kind):
     if kind == "q4":
         cfg = W.small_cases()["fragment97x45"]
+        steps = 300
+    elif kind == "q4u":  # the same grid as an unstructured Q4 mesh
+        cfg = W.as_unstructured_q4(W.small_cases()["fragment97x45"])
         steps = 300
     else:
         cfg = W.tri_small_cases()["tri_fragment"]
@@ -69,7 +72,8 @@ def _tip_points(cfg, cand):
     X, Y = cfg["X"], cfg["Y"]
     if cfg.get("conn") is not None:
         T = np.asarray(cfg["conn"])
-        nodes = [(T[e, a], T[e, (a + 1) % 3]) for e, a in zip(cand["elem"], cand["a"])]
+        nv = T.shape[1]
+        nodes = [(T[e, a], T[e, (a + 1) % nv]) for e, a in zip(cand["elem"], cand["a"])]
     else:
         nx = cfg["nx"]
         out = []
@@ -110,10 +114,12 @@ def test_picked_set_is_sound_and_complete(oracle_mod):
         assert wins == (c in picked), c
 
 
-@pytest.mark.parametrize("kind", ["q4", "cst"])
+@pytest.mark.parametrize("kind", ["q4", "cst", "q4u"])
 def test_front_run_invariants(oracle_mod, kind):
     if kind == "q4":
         cfg = dict(W.small_cases()["fragment97x45"], front_radius=3e-3)
+    elif kind == "q4u":
+        cfg = dict(W.as_unstructured_q4(W.small_cases()["fragment97x45"]), front_radius=3e-3)
     else:
         cfg = dict(W.tri_small_cases()["tri_fragment"], front_radius=3e-3)
     o = oracle_mod.run(cfg, 300)
