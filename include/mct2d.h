@@ -247,17 +247,21 @@ int mct_set_time(mct_ctx *ctx, double dt, double cfl_fraction);
 
 /* Caller-owned device arrays for the state of a plain binary64 Q4 context
  * (e.g. the storage of torch tensors): u^k lives in ux[k & 1], uy[k & 1]
- * (the step reads one pair and writes the other), v in vx, vy; each array
- * holds n_nodes doubles in node-id order.  Call before mct_finalize, which
- * zeroes them (on the context's stream: work of other streams on them must
- * be complete) and uses them instead of allocating its own; the caller
- * keeps them alive until mct_destroy (or a later finalize after unbinding)
- * and does not write them while steps are enqueued.  views = NULL unbinds (the
- * next finalize allocates again).  Errors: MCT_EINVAL for a NULL array;
- * MCT_EUNSUPPORTED on a batch, a binary32 context or a triangle mesh. */
+ * (the step reads one pair and writes the other), v in vx, vy; each of the
+ * six distinct arrays holds at least n doubles (node-id order; the first
+ * n_nodes are used).  Call before mct_finalize, which checks n >= n_nodes
+ * (MCT_EINVAL otherwise), zeroes them (on the context's stream: work of
+ * other streams on them must be complete) and uses them instead of
+ * allocating its own; the caller keeps them alive until mct_destroy (or a
+ * later finalize after unbinding) and does not write them while steps are
+ * enqueued.  views = NULL unbinds (the next finalize allocates again), and
+ * so does a new mesh (mct_set_mesh_grid).  Errors: MCT_EINVAL for a NULL
+ * array, two equal arrays or n < 1; MCT_EUNSUPPORTED on a batch, a binary32
+ * context or a triangle mesh. */
 typedef struct {
     double *ux[2], *uy[2];
     double *vx, *vy;
+    int64_t n;  /* doubles each array holds */
 } mct_device_views;
 int mct_bind_device_buffers(mct_ctx *ctx, const mct_device_views *views);
 
@@ -276,6 +280,15 @@ int mct_finalize(mct_ctx *ctx);
  * element with the global pick (several with the per-front pick); a split
  * acts from the next step on. */
 int mct_step(mct_ctx *ctx, int64_t n_steps);
+
+/* Step timing (a measurement call, like mct_autotune): enqueues n steps
+ * (1..4096) as direct launches with a HIP event pair on the context's stream
+ * around every step-kernel launch and every pick/commit launch, waits, and
+ * returns the mean duration per step of the step kernel (out_us[0]) and of
+ * the pick/commit launches (out_us[1]) in microseconds.  The steps count as
+ * ordinary steps (the same results as mct_step).  Structured grids without
+ * the split-screen; MCT_EUNSUPPORTED otherwise. */
+int mct_profile_step(mct_ctx *ctx, int64_t n, double out_us[2]);
 
 /* Wait for the enqueued work; reports asynchronous device errors, and
  * MCT_ENUMERIC if any displacement or velocity of the current step is not
@@ -368,6 +381,55 @@ int mct_batch_select(mct_ctx *ctx, int64_t s);
  * interleaved over XCDs, 2 largest specimens first, banded.  Results do not
  * depend on it. */
 int mct_set_order(mct_ctx *ctx, int order);
+
+/* Uniform lattices.  A structured grid whose elements all have, bit for
+ * bit, the same geometry -- Q4 gradients at the four edge midpoints (Eq.
+ * QUAD_strain_discretization), area, and the unit normals and lengths of the
+ * twelve crack paths of Sec. 2.2 (Fig. 2-3) -- and the zero pattern of a
+ * rectangle (axis-parallel element edges) is a uniform lattice: e.g. a grid
+ * of square elements whose node coordinates i h are exact binary fractions.
+ * With MCT_LATTICE_AUTO (default) mct_finalize checks this on the device for
+ * binary64 contexts with the point rule (every element's values as the step
+ * computes them, compared with element 0's), and when every specimen of the
+ * context is a lattice the step takes the shared values instead of
+ * recomputing them per element (and stages no coordinates): the same
+ * operations in the same order, so the results are identical.
+ * MCT_LATTICE_GENERAL always runs the general step.  mct_set_lattice acts at
+ * the next mct_finalize (a finalized context must be finalized again);
+ * mct_get_lattice reports 1 when the finalized context steps with the
+ * lattice kernel.  Structured grids only (MCT_EUNSUPPORTED for a triangle
+ * or unstructured quadrilateral mesh). */
+enum { MCT_LATTICE_AUTO = 0, MCT_LATTICE_GENERAL = 1 };
+int mct_set_lattice(mct_ctx *ctx, int mode);
+int mct_get_lattice(mct_ctx *ctx, int *uniform);
+
+/* Near-threshold decision log (the floating-point contract of the split
+ * decisions: record every decision whose margin is within a relative
+ * tolerance, so that a divergence between two runs can be traced).  With
+ * tol > 0 every step records, in binary64 or binary32 as the step computes:
+ *   kind 1: a path of an evaluated candidate with |G - Gc| <= tol Gc (the
+ *           element rule's threshold, Sec. 2.2);
+ *   kind 2: a candidate with two or more paths above Gc whose largest two
+ *           differ by <= tol times the largest (the rule's argmax);
+ *   kind 3: such a candidate's split-ratio margin
+ *           |G* - gamma (G* - G_j)| <= tol G* against path j;
+ *   kind 4: the step's two largest accepted candidates differ by
+ *           <= tol times the largest (the MCT pick of Sec. 3);
+ *   kind 5: the pick's split-ratio margin |G* - gamma (G* - G_min)| <=
+ *           tol G* against the smallest accepted G.
+ * Record fields: step index, element, tip edge a, kind, exit edge k of the
+ * path concerned (kinds 1, 3) or chosen (2, 4, 5), the value G and the
+ * value it was compared with (ref).  Kinds 4 and 5 come from the global
+ * pick only.  cap (>= 1) records are held on the device; mct_set_near_log
+ * acts at the next mct_finalize (tol = 0 turns the log off) and the log
+ * starts empty there; checkpoints do not hold it.  mct_get_near_log copies
+ * the records sorted by (step, kind, element, a, k); MCT_ECAPACITY when
+ * more records were made than the device capacity (count reports how many)
+ * or than cap.  Plain structured-grid contexts (MCT_EUNSUPPORTED for a
+ * batch or an unstructured mesh); outputs may be NULL. */
+int mct_set_near_log(mct_ctx *ctx, double tol, int64_t cap);
+int mct_get_near_log(mct_ctx *ctx, int64_t cap, int32_t *step, int32_t *elem, uint8_t *a, uint8_t *kind,
+                     uint8_t *k, double *G, double *ref, int64_t *count);
 
 /* Launch autotuner: times trial_steps steps for every tile shape (and, for
  * a batch, every unit order) from the current state, restores that state

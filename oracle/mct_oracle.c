@@ -92,6 +92,22 @@ typedef struct {
     double G;
 } orc_split_t;
 
+/* One near-threshold decision (the floating-point contract asks for every
+ * decision whose margin is within a relative tolerance to be recorded, so
+ * that a divergence between two runs can be traced to it).  kind: 1 a path
+ * G against Gc (element rule threshold, Sec. 2.2); 2 the gap between the two
+ * largest paths above Gc of one element (the rule's argmax); 3 the element
+ * rule's split-ratio margin against one other path above Gc; 4 the gap
+ * between the two largest accepted candidates of a step (the MCT pick's
+ * argmax, Sec. 3); 5 the pick's split-ratio margin (against the smallest
+ * accepted G).  k is the exit edge of the path concerned (kinds 1, 3: that
+ * path; 2, 4, 5: the chosen one); G the chosen (or the path's) value, ref
+ * the value it was compared with. */
+typedef struct {
+    int step, elem, a, kind, k;
+    double G, ref;
+} orc_near_t;
+
 typedef struct {
     /* mesh: nv = 4 (Q4, structured grid) or 3 (CST, unstructured) */
     int nv, nx, ny, nn, ne, ns;
@@ -140,6 +156,10 @@ typedef struct {
     /* Q4 edge smoothing: 0 = the point rule (B of element j at the midpoint
      * of the edge), 1 = sub-cells (the triangle edge + centroid of j) */
     int subcell;
+    /* near-threshold decision log: tolerance (0 = off) and records */
+    double near_tol;
+    orc_near_t *near;
+    int nnear, capnear;
     /* scratch */
     real *sig;              /* 3 per edge */
     real *eps;              /* 3 per edge: smoothed strain */
@@ -643,6 +663,59 @@ int orc_element_rule(const double G[3], double Gc, double gamma) {
     return orc_element_rule_n(3, G, Gc, gamma);
 }
 
+/* Near-threshold records (see orc_near_t).  A decision is near when its
+ * margin is within near_tol relative to the value that decides it:
+ * |G - Gc| <= tol Gc, G1 - G2 <= tol G1, |G1 - gamma (G1 - Gj)| <= tol G1,
+ * each evaluated in the step's precision. */
+static void near_push(orc_model_t *m, int elem, int a, int kind, int k, real G, real ref) {
+    if (m->nnear == m->capnear) {
+        m->capnear = m->capnear ? 2 * m->capnear : 256;
+        m->near = realloc(m->near, sizeof(orc_near_t) * (size_t)m->capnear);
+    }
+    orc_near_t r = {(int)m->step, elem, a, kind, k, (double)G, (double)ref};
+    m->near[m->nnear++] = r;
+}
+
+/* Records of one evaluated candidate (element f, tip edge a; its n path
+ * values G, gate open): every path near Gc; with two or more paths above Gc
+ * the gap between the largest two and every split-ratio margin of the
+ * element rule. */
+static void near_candidate(orc_model_t *m, int f, int a, int n, const real *G, real Gc) {
+    const real tol = (real)m->near_tol, gamma = (real)m->gamma;
+    for (int j = 0; j < n; ++j)
+        if (fabs(G[j] - Gc) <= tol * Gc) near_push(m, f, a, 1, (a + 1 + j) % m->nv, G[j], Gc);
+    int best = -1, nS = 0;
+    for (int j = 0; j < n; ++j)
+        if (G[j] > Gc) {
+            nS++;
+            if (best < 0 || G[j] > G[best]) best = j;
+        }
+    if (nS < 2) return;
+    real second = R(-1.0);
+    for (int j = 0; j < n; ++j)
+        if (j != best && G[j] > Gc && G[j] > second) second = G[j];
+    if (G[best] - second <= tol * G[best]) near_push(m, f, a, 2, (a + 1 + best) % m->nv, G[best], second);
+    for (int j = 0; j < n; ++j) {
+        if (j == best || !(G[j] > Gc)) continue;
+        if (fabs(G[best] - gamma * (G[best] - G[j])) <= tol * G[best])
+            near_push(m, f, a, 3, (a + 1 + j) % m->nv, G[best], G[j]);
+    }
+}
+
+/* Records of the global pick over n >= 1 accepted candidates with best c:
+ * the gap to the second largest G (n >= 2) and the split-ratio margin
+ * against the smallest accepted G. */
+static void near_pick(orc_model_t *m, int n, const real *G, const int *elem, const int *a, const int *k, int c) {
+    const real tol = (real)m->near_tol, gamma = (real)m->gamma;
+    real second = R(-1.0), gmin = G[c];
+    for (int i = 0; i < n; ++i) {
+        if (G[i] < gmin) gmin = G[i];
+        if (i != c && G[i] > second) second = G[i];
+    }
+    if (n >= 2 && G[c] - second <= tol * G[c]) near_push(m, elem[c], a[c], 4, k[c], G[c], second);
+    if (fabs(G[c] - gamma * (G[c] - gmin)) <= tol * G[c]) near_push(m, elem[c], a[c], 5, k[c], G[c], gmin);
+}
+
 /* MCT pick (Sec. 3): the candidate with the largest G (ties: lower element
  * id, then lower tip edge) provided it passes the split-ratio test against
  * every other candidate.  Returns its index or -1. */
@@ -780,7 +853,8 @@ static void sct_phase(orc_model_t *m) {
     int s = m->elem_edge[4 * f + a], ff, aa;
     if (!edge_candidate(m, s, &ff, &aa) || ff != f) return;
     real G[3];
-    candidate_G(m, f, a, G);
+    int H = candidate_G(m, f, a, G);
+    if (H && m->near_tol > 0.0) near_candidate(m, f, a, m->nv - 1, G, r_gc(m, f));
     int j = element_rule(m->nv - 1, G, r_gc(m, f), (real)m->gamma);
     if (j < 0) return;
     int k = (a + 1 + j) % m->nv;
@@ -800,17 +874,35 @@ static void fracture_phase(orc_model_t *m) {
     /* per edge: accepted path index or -1 (evaluated independently) */
     int *acc = malloc(sizeof(int) * (size_t)cap);
     real *accG = malloc(sizeof(real) * (size_t)cap);
+    /* near-threshold log: every candidate's gate and path values */
+    const int near = m->near_tol > 0.0;
+    real *allG = near ? malloc(sizeof(real) * 3 * (size_t)cap) : NULL;
+    unsigned char *gate = near ? calloc((size_t)cap, 1) : NULL;
 #pragma omp parallel for schedule(dynamic, 4096)
     for (int s = 0; s < m->ns; ++s) {
         int f, a;
         acc[s] = -1;
         if (!edge_candidate(m, s, &f, &a)) continue;
         real G[3];
-        candidate_G(m, f, a, G);
+        int H = candidate_G(m, f, a, G);
+        if (near) {
+            gate[s] = (unsigned char)H;
+            for (int j = 0; j < 3; ++j) allG[3 * s + j] = G[j];
+        }
         int j = element_rule(m->nv - 1, G, r_gc(m, f), (real)m->gamma);
         if (j < 0) continue;
         acc[s] = j;
         accG[s] = G[j];
+    }
+    /* near-threshold records of the candidates, in edge-id order */
+    if (near) {
+        for (int s = 0; s < m->ns; ++s) {
+            int f, a;
+            if (!gate[s] || !edge_candidate(m, s, &f, &a)) continue;
+            near_candidate(m, f, a, m->nv - 1, &allG[3 * s], r_gc(m, f));
+        }
+        free(allG);
+        free(gate);
     }
     /* accepted candidates in edge-id order */
     int nc = 0;
@@ -838,6 +930,13 @@ static void fracture_phase(orc_model_t *m) {
         free(pick);
     } else {
         int c = mct_pick(nc, cG, cE, cA, (real)m->gamma);
+        if (near && nc > 0) {
+            /* the best key, whether or not it passes the split-ratio test */
+            int b = 0;
+            for (int i = 1; i < nc; ++i)
+                if (better_key(cG[i], cE[i], cA[i], cG[b], cE[b], cA[b])) b = i;
+            near_pick(m, nc, cG, cE, cA, cK, b);
+        }
         if (c >= 0) record_split(m, cE[c], cA[c], cK[c], cG[c]);
     }
     free(cG);
@@ -923,7 +1022,7 @@ void orc_destroy(orc_model_t *m) {
                     m->color, m->area, m->Gc, m->edge_trac, m->edge_loaded, m->vmask, m->v0,
                     m->mass, m->minv, m->fext, m->split, m->ux, m->uy, m->vx, m->vy, m->log,
                     m->sig, m->eps, m->sig_ok, m->fe, m->fx, m->fy, m->ax, m->ay, m->curve_t,
-                    m->curve_phi};
+                    m->curve_phi, m->near};
     for (size_t i = 0; i < sizeof(ptrs) / sizeof(ptrs[0]); ++i) free(ptrs[i]);
     free(m);
 }
@@ -1272,6 +1371,52 @@ int orc_set_front_pick(orc_model_t *m, double rho) {
     if (!(rho >= 0.0)) return ORC_EINVAL;
     m->front_r2 = rho * rho;
     return ORC_OK;
+}
+
+/* Near-threshold decision log with relative tolerance tol (> 0; 0 = off);
+ * clears the records. */
+int orc_set_near_log(orc_model_t *m, double tol) {
+    if (!(tol >= 0.0)) return ORC_EINVAL;
+    m->near_tol = tol;
+    m->nnear = 0;
+    return ORC_OK;
+}
+
+int orc_near_count(const orc_model_t *m) { return m->nnear; }
+
+/* Test hooks: the records one candidate (n path values, gate open) or one
+ * pick over n accepted candidates (best c) adds at the model's current step
+ * (values rounded to real). */
+int orc_near_candidate(orc_model_t *m, int f, int a, int n, const double *G, double Gc) {
+    real g[3] = {0, 0, 0};
+    if (n < 1 || n > 3) return ORC_EINVAL;
+    for (int j = 0; j < n; ++j) g[j] = (real)G[j];
+    near_candidate(m, f, a, n, g, (real)Gc);
+    return ORC_OK;
+}
+
+int orc_near_pick(orc_model_t *m, int n, const double *G, const int *elem, const int *a, const int *k, int c) {
+    if (n < 1 || c < 0 || c >= n) return ORC_EINVAL;
+    real *g = malloc(sizeof(real) * (size_t)n);
+    for (int i = 0; i < n; ++i) g[i] = (real)G[i];
+    near_pick(m, n, g, elem, a, k, c);
+    free(g);
+    return ORC_OK;
+}
+
+/* The records in the order they were made (steps ascending; in a step the
+ * candidates' records in edge-id order, then the pick's). */
+void orc_get_near(const orc_model_t *m, int *step, int *elem, int *a, int *kind, int *k, double *G, double *ref) {
+    for (int i = 0; i < m->nnear; ++i) {
+        const orc_near_t *r = &m->near[i];
+        step[i] = r->step;
+        elem[i] = r->elem;
+        a[i] = r->a;
+        kind[i] = r->kind;
+        k[i] = r->k;
+        G[i] = r->G;
+        ref[i] = r->ref;
+    }
 }
 
 /* Traction load curve (n >= 2 points, t strictly increasing), n = 0 clears. */

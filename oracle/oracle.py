@@ -90,6 +90,12 @@ def lib(precision: int = 64):
         _lib.orc_set_load_curve.argtypes = [P, C.c_int, dp, dp]
         _lib.orc_load_factor.argtypes = [P, C.c_double]
         _lib.orc_load_factor.restype = C.c_double
+        _lib.orc_set_near_log.argtypes = [P, C.c_double]
+        _lib.orc_near_count.argtypes = [P]
+        _lib.orc_near_count.restype = C.c_int
+        _lib.orc_get_near.argtypes = [P, ip, ip, ip, ip, ip, dp, dp]
+        _lib.orc_near_candidate.argtypes = [P, C.c_int, C.c_int, C.c_int, dp, C.c_double]
+        _lib.orc_near_pick.argtypes = [P, C.c_int, dp, ip, ip, ip, C.c_int]
         _lib.orc_set_threads.argtypes = [C.c_int]
         _lib.orc_get_threads.restype = C.c_int
         _lib.orc_precision.restype = C.c_int
@@ -189,6 +195,8 @@ class Oracle:
             self._check(L.orc_set_front_pick(self.h, float(cfg["front_radius"])))
         if cfg.get("smoothing") == "subcell":  # Q4 edge smoothing over triangular sub-cells
             self._check(L.orc_set_smoothing(self.h, 1))
+        if cfg.get("near_tol"):  # near-threshold decision log
+            self._check(L.orc_set_near_log(self.h, float(cfg["near_tol"])))
         if finalize:
             self._check(L.orc_finalize(self.h))
 
@@ -234,6 +242,15 @@ class Oracle:
         G = np.zeros(n)
         self._L.orc_get_log(self.h, st, el, en, ex, G)
         return dict(step=st, elem=el, entry=en, exit=ex, G=G)
+
+    def near_log(self):
+        """Near-threshold decisions (arrays step, elem, a, kind, k, G, ref)
+        in the order they were made."""
+        n = self._L.orc_near_count(self.h)
+        st, el, a, kd, k = (np.zeros(n, np.int32) for _ in range(5))
+        G, ref = np.zeros(n), np.zeros(n)
+        self._L.orc_get_near(self.h, st, el, a, kd, k, G, ref)
+        return dict(step=st, elem=el, a=a, kind=kd, k=k, G=G, ref=ref)
 
     def tables(self):
         inf = self.info()

@@ -116,8 +116,25 @@ struct mct_ctx {
     int nunits = 0;
     int32_t *dtip_counts = nullptr, *dtip_total = nullptr;
 
+    // uniform lattices: mode (0 automatic, 1 general kernel always), the
+    // shared geometry per specimen, and whether the step runs the lattice
+    // kernel (every specimen a lattice)
+    int lattice_mode = 0;
+    mct::LatticeConst *dlat = nullptr;
+    uint32_t *dlat_flag = nullptr;
+    bool uni = false;
+    // near-threshold decision log (plain contexts): tolerance (0 = off),
+    // capacity and device records
+    double near_tol = 0.0;
+    int64_t near_cap = 0;
+    mct::NearRec *dnear = nullptr;
+    uint32_t *dnear_count = nullptr;
+
     hipGraphExec_t graph[2] = {nullptr, nullptr};  // by parity of the first step
     int graph_tile[2] = {0, 0};
+    // a shorter segment (fewer than kGraphSteps steps), by parity: its length
+    hipGraphExec_t tgraph[2] = {nullptr, nullptr};
+    int tgraph_tile[2] = {0, 0}, tgraph_n[2] = {0, 0};
     int64_t steps_enqueued = 0;  // host view of the step counter
 
     // state queries
@@ -194,6 +211,9 @@ void drop_graphs(mct_ctx *c) {
     for (int i = 0; i < 2; ++i) {
         if (c->graph[i]) (void)hipGraphExecDestroy(c->graph[i]);
         c->graph[i] = nullptr;
+        if (c->tgraph[i]) (void)hipGraphExecDestroy(c->tgraph[i]);
+        c->tgraph[i] = nullptr;
+        c->tgraph_n[i] = 0;
         if (c->sgraph[i]) (void)hipGraphExecDestroy(c->sgraph[i]);
         c->sgraph[i] = nullptr;
     }
@@ -292,6 +312,11 @@ void release_device(mct_ctx *c) {
     dfree(c->dunits);
     dfree(c->dtip_counts);
     dfree(c->dtip_total);
+    dfree(c->dlat);
+    dfree(c->dlat_flag);
+    dfree(c->dnear);
+    dfree(c->dnear_count);
+    c->uni = false;
     free_screen(c);
     free_eval(c);
     c->finalized = false;
@@ -457,6 +482,11 @@ void refresh_f32(mct_ctx *c) {
     f.ctl = p.ctl;
     f.slots = p.slots;
     f.log = p.log;
+    f.lat = nullptr;
+    f.near = p.near;
+    f.near_count = p.near_count;
+    f.near_cap = p.near_cap;
+    f.near_tol = (float)p.near_tol;
 }
 
 // Binary32 contexts: copy the state into its binary64 mirror (exact) before
@@ -482,6 +512,7 @@ int narrow_state(mct_ctx *c) {
 mct::Launch launch_of(const mct_ctx *c) {
     mct::Launch L;
     L.batched = c->batch;
+    L.uni = c->uni;
     L.p0 = c->specs[0].prm;
     L.f32 = c->precision == 32;
     L.p0f = c->specs[0].prmf;
@@ -492,25 +523,61 @@ mct::Launch launch_of(const mct_ctx *c) {
     return L;
 }
 
-// A segment of kGraphSteps steps followed by its commit, captured once per
-// parity of the segment's first step.
-int build_graph(mct_ctx *c, int par0) {
-    if (c->graph[par0]) (void)hipGraphExecDestroy(c->graph[par0]);
-    c->graph[par0] = nullptr;
+// Where the pick of a step is taken.  A launch of few workgroups folds it
+// into the next step: every workgroup reduces the published candidates
+// itself (no extra launch; such a launch is one latency-bound wave of
+// workgroups).  A batch, or a model of many workgroups (several rounds per
+// step), commits every step instead: one small launch (a workgroup per
+// specimen) reduces them, splits and logs, so the next step's workgroups
+// read the new split codes from memory and skip the reduction and its
+// memory round trip.
+constexpr int64_t kFoldMaxWorkgroups = 4096;
+bool commit_each_step(const mct_ctx *c) {
+    if (c->batch) return true;
+    const mct::StepParams &p = c->specs[0].prm;
+    return p.front == 0 && (int64_t)p.nwg > kFoldMaxWorkgroups;
+}
+
+// n steps of a segment starting at parity par0, closed by the commit.
+hipError_t enqueue_segment(const mct_ctx *c, const mct::Launch &L, int n, int par0, hipStream_t st) {
+    hipError_t e = hipSuccess;
+    if (commit_each_step(c)) {
+        for (int i = 0; e == hipSuccess && i < n; ++i) {
+            e = mct::launch_step(c->tile, L, 0, (par0 + i) & 1, st);
+            if (e == hipSuccess) e = mct::launch_commit(L, 1, st);
+        }
+        return e;
+    }
+    for (int i = 0; e == hipSuccess && i < n; ++i) e = mct::launch_step(c->tile, L, i, par0, st);
+    if (e == hipSuccess) e = mct::launch_commit(L, n, st);
+    return e;
+}
+
+// A segment of n steps followed by its commit, captured once per parity of
+// the segment's first step: n = kGraphSteps in graph[], shorter ones (the
+// tail of a request) in tgraph[].
+int build_graph(mct_ctx *c, int par0, int n = kGraphSteps) {
+    hipGraphExec_t &slot = n == kGraphSteps ? c->graph[par0] : c->tgraph[par0];
+    if (slot) (void)hipGraphExecDestroy(slot);
+    slot = nullptr;
     hipStream_t cap;
     HIP_TRY(c, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     hipGraph_t g = nullptr;
     const mct::Launch L = launch_of(c);
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
-    for (int i = 0; e == hipSuccess && i < kGraphSteps; ++i) e = mct::launch_step(c->tile, L, i, par0, cap);
-    if (e == hipSuccess) e = mct::launch_commit(L, kGraphSteps, cap);
+    if (e == hipSuccess) e = enqueue_segment(c, L, n, par0, cap);
     hipError_t e2 = hipStreamEndCapture(cap, &g);
     if (e == hipSuccess) e = e2;
-    if (e == hipSuccess) e = hipGraphInstantiate(&c->graph[par0], g, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphInstantiate(&slot, g, nullptr, nullptr, 0);
     if (g) (void)hipGraphDestroy(g);
     (void)hipStreamDestroy(cap);
     if (e != hipSuccess) return fail(c, MCT_EDEVICE, "graph capture: %s", hipGetErrorString(e));
-    c->graph_tile[par0] = c->tile;
+    if (n == kGraphSteps) {
+        c->graph_tile[par0] = c->tile;
+    } else {
+        c->tgraph_tile[par0] = c->tile;
+        c->tgraph_n[par0] = n;
+    }
     return MCT_OK;
 }
 
@@ -840,6 +907,8 @@ static int set_mesh_unstructured(mct_ctx *c, int nv, int64_t n_nodes, const doub
     if (c->batch) return fail(c, MCT_EUNSUPPORTED, "%s meshes need a plain context", what);
     if (c->precision == 32) return fail(c, MCT_EUNSUPPORTED, "%s meshes need a binary64 context", what);
     release_device(c);
+    c->bound = false;
+    c->views = mct_device_views{};
     c->specs.assign(1, Spec{});
     c->finalized = false;
     if (!c->tri) c->tri = new (std::nothrow) mct::tri::Model;
@@ -875,6 +944,9 @@ int mct_set_mesh_grid(mct_ctx *c, int32_t nx, int32_t ny, const double *X, const
     // element ids, and element * 4 + local edge keys, stay in int32
     if ((int64_t)nx * ny > (int64_t)1 << 29) return fail(c, MCT_EINVAL, "grid too large (more than 2^29 elements)");
     release_device(c);
+    // a new mesh unbinds caller-owned state arrays (they were sized for the old one)
+    c->bound = false;
+    c->views = mct_device_views{};
     Spec s;
     s.nx = nx;
     s.ny = ny;
@@ -1077,6 +1149,69 @@ int mct_set_order(mct_ctx *c, int order) {
     return set_launch_geometry(c);
 }
 
+int mct_set_lattice(mct_ctx *c, int mode) {
+    if (!c) return MCT_EINVAL;
+    if (mode != MCT_LATTICE_AUTO && mode != MCT_LATTICE_GENERAL) return fail(c, MCT_EINVAL, "lattice mode %d", mode);
+    if (c->tri) return fail(c, MCT_EUNSUPPORTED, "the lattice kernel is for structured grids");
+    c->lattice_mode = mode;
+    if (c->finalized) release_device(c);  // takes effect at the next finalize
+    return MCT_OK;
+}
+
+int mct_get_lattice(mct_ctx *c, int *uniform) {
+    if (!c || !uniform) return MCT_EINVAL;
+    *uniform = (!c->tri && c->finalized && c->uni) ? 1 : 0;
+    return MCT_OK;
+}
+
+int mct_set_near_log(mct_ctx *c, double tol, int64_t cap) {
+    if (!c) return MCT_EINVAL;
+    if (c->tri) return fail(c, MCT_EUNSUPPORTED, "the near-threshold log is for structured grids");
+    if (c->batch) return fail(c, MCT_EUNSUPPORTED, "the near-threshold log needs a plain context");
+    if (!(tol >= 0.0) || !(tol < 1.0)) return fail(c, MCT_EINVAL, "tolerance %g outside [0, 1)", tol);
+    if (tol > 0.0 && (cap < 1 || cap > (int64_t)1 << 30)) return fail(c, MCT_EINVAL, "capacity %lld", (long long)cap);
+    c->near_tol = tol;
+    c->near_cap = tol > 0.0 ? cap : 0;
+    if (c->finalized) release_device(c);  // takes effect at the next finalize
+    return MCT_OK;
+}
+
+int mct_get_near_log(mct_ctx *c, int64_t cap, int32_t *step, int32_t *elem, uint8_t *a, uint8_t *kind,
+                     uint8_t *k, double *G, double *ref, int64_t *count) {
+    if (!c || !count) return MCT_EINVAL;
+    *count = 0;
+    if (c->tri || c->batch) return fail(c, MCT_EUNSUPPORTED, "no near-threshold log on this context");
+    if (!c->finalized) return fail(c, MCT_ESTATE, "finalize first");
+    if (!c->dnear) return MCT_OK;
+    uint32_t n = 0;
+    HIP_TRY(c, hipMemcpyAsync(&n, c->dnear_count, sizeof n, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    *count = (int64_t)n;
+    if ((int64_t)n > c->near_cap) return fail(c, MCT_ECAPACITY, "near-threshold log overflow: %u records, capacity %lld",
+                                             n, (long long)c->near_cap);
+    if (cap < (int64_t)n) return fail(c, MCT_ECAPACITY, "capacity %lld < %u records", (long long)cap, n);
+    std::vector<mct::NearRec> r(n);
+    if (n) HIP_TRY(c, hipMemcpy(r.data(), c->dnear, sizeof(mct::NearRec) * n, hipMemcpyDeviceToHost));
+    // canonical order: the device appends in completion order
+    std::sort(r.begin(), r.end(), [](const mct::NearRec &x, const mct::NearRec &y) {
+        if (x.step != y.step) return x.step < y.step;
+        if (x.kind != y.kind) return x.kind < y.kind;
+        if (x.elem != y.elem) return x.elem < y.elem;
+        if (x.a != y.a) return x.a < y.a;
+        return x.k < y.k;
+    });
+    for (uint32_t i = 0; i < n; ++i) {
+        if (step) step[i] = r[i].step;
+        if (elem) elem[i] = r[i].elem;
+        if (a) a[i] = r[i].a;
+        if (kind) kind[i] = r[i].kind;
+        if (k) k[i] = r[i].k;
+        if (G) G[i] = r[i].G;
+        if (ref) ref[i] = r[i].ref;
+    }
+    return MCT_OK;
+}
+
 int mct_bind_device_buffers(mct_ctx *c, const mct_device_views *v) {
     if (!c) return MCT_EINVAL;
     if (c->tri) return fail(c, MCT_EUNSUPPORTED, "device buffers bind the state of a Q4 grid");
@@ -1084,6 +1219,13 @@ int mct_bind_device_buffers(mct_ctx *c, const mct_device_views *v) {
     if (c->precision != 64) return fail(c, MCT_EUNSUPPORTED, "device buffers hold binary64 state");
     if (v && (!v->ux[0] || !v->ux[1] || !v->uy[0] || !v->uy[1] || !v->vx || !v->vy))
         return fail(c, MCT_EINVAL, "null device array");
+    if (v) {
+        const double *a[6] = {v->ux[0], v->ux[1], v->uy[0], v->uy[1], v->vx, v->vy};
+        for (int i = 0; i < 6; ++i)
+            for (int j = i + 1; j < 6; ++j)
+                if (a[i] == a[j]) return fail(c, MCT_EINVAL, "device arrays %d and %d are the same", i, j);
+        if (v->n < 1) return fail(c, MCT_EINVAL, "device array length %lld", (long long)v->n);
+    }
     release_device(c);  // the state arrays change: finalize again
     c->bound = v != nullptr;
     c->views = v ? *v : mct_device_views{};
@@ -1196,6 +1338,9 @@ int mct_finalize(mct_ctx *c) {
         if ((rc = upload(c, c->dcurve, curves))) return rc;
     }
     if (any_gc && (rc = upload(c, c->dgc, gc))) return rc;
+    if (c->bound && c->views.n < nn)
+        return fail(c, MCT_EINVAL, "bound device arrays hold %lld values, the mesh has %lld nodes",
+                    (long long)c->views.n, (long long)nn);
     for (int i = 0; i < 2; ++i) {
         if (c->bound) {
             c->dux[i] = c->views.ux[i];
@@ -1330,6 +1475,48 @@ int mct_finalize(mct_ctx *c) {
         p.fsorted = c->dfsorted;
         p.fplist = c->dfplist;
         p.fcell = c->front_cell;
+        p.lat = nullptr;
+        p.near = nullptr;
+        p.near_count = nullptr;
+        p.near_cap = 0;
+        p.near_tol = 0.0;
+    }
+    // near-threshold decision log (plain contexts)
+    if (c->near_tol > 0.0 && !c->batch) {
+        HIP_TRY(c, hipMalloc((void **)&c->dnear, sizeof(mct::NearRec) * (size_t)c->near_cap));
+        HIP_TRY(c, hipMalloc((void **)&c->dnear_count, sizeof(uint32_t)));
+        HIP_TRY(c, hipMemsetAsync(c->dnear_count, 0, sizeof(uint32_t), c->stream));
+        StepParams &p = c->specs[0].prm;
+        p.near = c->dnear;
+        p.near_count = c->dnear_count;
+        p.near_cap = (int32_t)c->near_cap;
+        p.near_tol = c->near_tol;
+    }
+    // uniform lattices: binary64 point rule, every element's geometry equal
+    // bit for bit to element 0's (checked on the device with the step's own
+    // arithmetic); the step then takes the shared values
+    if (c->precision == 64 && c->lattice_mode == 0) {
+        const size_t nsp = c->specs.size();
+        HIP_TRY(c, hipMalloc((void **)&c->dlat, sizeof(mct::LatticeConst) * nsp));
+        HIP_TRY(c, hipMalloc((void **)&c->dlat_flag, sizeof(uint32_t) * nsp));
+        bool all = true;
+        for (size_t q = 0; q < nsp; ++q) {
+            const Spec &sq = c->specs[q];
+            if (sq.subcell) {
+                all = false;
+                continue;
+            }
+            HIP_TRY(c, mct::launch_lattice_check(sq.prm, c->dlat + q, c->dlat_flag + q, c->stream));
+        }
+        std::vector<uint32_t> flags(nsp, 1u);
+        HIP_TRY(c, hipMemcpyAsync(flags.data(), c->dlat_flag, sizeof(uint32_t) * nsp, hipMemcpyDeviceToHost,
+                                  c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        for (size_t q = 0; q < nsp && all; ++q) all = !c->specs[q].subcell && flags[q] == 0;
+        if (all) {
+            for (size_t q = 0; q < nsp; ++q) c->specs[q].prm.lat = c->dlat + q;
+            c->uni = true;
+        }
     }
     c->finalized = true;  // the launch geometry below needs the device arrays
     rc = set_launch_geometry(c);
@@ -1372,18 +1559,79 @@ int mct_step(mct_ctx *c, int64_t n) {
             left -= kGraphSteps;
             c->steps_enqueued += kGraphSteps;
         }
+        if (left > 0) {  // the tail, as a shorter captured segment
+            const int par0 = (int)(c->steps_enqueued & 1);
+            const int n_tail = (int)left;
+            if (!c->tgraph[par0] || c->tgraph_tile[par0] != c->tile || c->tgraph_n[par0] != n_tail) {
+                int rc = build_graph(c, par0, n_tail);
+                if (rc) return rc;
+            }
+            HIP_TRY(c, hipGraphLaunch(c->tgraph[par0], c->stream));
+            c->steps_enqueued += n_tail;
+            left = 0;
+        }
     }
     const mct::Launch L = launch_of(c);
     while (left > 0) {
         // direct segment, closed by its commit
         const int seg = (int)std::min<int64_t>(left, 1 << 20);
         const int par0 = (int)(c->steps_enqueued & 1);
-        for (int i = 0; i < seg; ++i) HIP_TRY(c, mct::launch_step(c->tile, L, i, par0, c->stream));
-        HIP_TRY(c, mct::launch_commit(L, seg, c->stream));
+        HIP_TRY(c, enqueue_segment(c, L, seg, par0, c->stream));
         left -= seg;
         c->steps_enqueued += seg;
     }
     return MCT_OK;
+}
+
+int mct_profile_step(mct_ctx *c, int64_t n, double out_us[2]) {
+    if (!c || !out_us) return MCT_EINVAL;
+    if (c->tri) return fail(c, MCT_EUNSUPPORTED, "step timing is for structured grids");
+    if (!c->finalized) return fail(c, MCT_ESTATE, "finalize first");
+    if (c->screen_on) return fail(c, MCT_EUNSUPPORTED, "step timing with the split-screen");
+    if (n < 1 || n > 4096) return fail(c, MCT_EINVAL, "step count %lld outside 1..4096", (long long)n);
+    const bool each = commit_each_step(c);
+    const int nc = each ? (int)n : 1;  // commits timed
+    std::vector<hipEvent_t> ev(2 * (size_t)n + 2 * (size_t)nc, nullptr);
+    int rc = MCT_OK;
+    for (hipEvent_t &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) rc = fail(c, MCT_EDEVICE, "event create");
+    const mct::Launch L = launch_of(c);
+    const int par0 = (int)(c->steps_enqueued & 1);
+    hipError_t e = hipSuccess;
+    for (int64_t i = 0; !rc && e == hipSuccess && i < n; ++i) {
+        e = hipEventRecord(ev[2 * i], c->stream);
+        if (e == hipSuccess)
+            e = each ? mct::launch_step(c->tile, L, 0, (int)((par0 + i) & 1), c->stream)
+                     : mct::launch_step(c->tile, L, (int)i, par0, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(ev[2 * i + 1], c->stream);
+        if (e == hipSuccess && (each || i == n - 1)) {
+            const size_t q = 2 * (size_t)n + 2 * (size_t)(each ? i : 0);
+            e = hipEventRecord(ev[q], c->stream);
+            if (e == hipSuccess) e = mct::launch_commit(L, each ? 1 : (int)n, c->stream);
+            if (e == hipSuccess) e = hipEventRecord(ev[q + 1], c->stream);
+        }
+    }
+    if (!rc && e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (!rc && e != hipSuccess) rc = fail(c, MCT_EDEVICE, "step timing: %s", hipGetErrorString(e));
+    if (!rc) {
+        c->steps_enqueued += n;
+        double ts = 0.0, tc = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]);
+            ts += ms;
+        }
+        for (int i = 0; i < nc; ++i) {
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, ev[2 * n + 2 * i], ev[2 * n + 2 * i + 1]);
+            tc += ms;
+        }
+        out_us[0] = 1e3 * ts / (double)n;
+        out_us[1] = 1e3 * tc / (double)n;
+    }
+    for (hipEvent_t &x : ev)
+        if (x) (void)hipEventDestroy(x);
+    return rc;
 }
 
 int mct_sync(mct_ctx *c) {

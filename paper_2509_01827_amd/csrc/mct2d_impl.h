@@ -35,7 +35,33 @@ static_assert(sizeof(AccCand) == 16, "AccCand layout");
 struct Slot {
     double G;     // largest accepted G of the workgroup
     double Gmin;  // smallest accepted G of the workgroup
+    double G2;    // second largest accepted G of the workgroup (-1: none)
     int32_t elem, a, k, pad;
+};
+
+// One near-threshold decision: a decision whose margin lies within the
+// relative tolerance near_tol (kind 1: a path G against Gc; 2: gap of the
+// two largest paths above Gc of an element; 3: the element rule's
+// split-ratio margin against one path; 4: gap of the two largest accepted
+// candidates of a step; 5: the pick's split-ratio margin against the
+// smallest accepted G).  k is the exit edge of the path concerned.
+struct NearRec {
+    int32_t step, elem;
+    uint8_t a, kind, k, pad0;
+    int32_t pad1;
+    double G, ref;
+};
+static_assert(sizeof(NearRec) == 32, "NearRec layout");
+
+// Geometry shared by every element of a uniform lattice (a structured grid
+// whose element gradients, areas and crack-path geometry set-up found
+// bitwise identical for all elements; binary64 point rule): the step takes
+// these instead of recomputing them per element.
+struct LatticeConst {
+    double B[4][8];       // at the midpoint of local edge k: dN_n/dx (n = 0..3), then dN_n/dy
+    double w;             // smoothing weight A / (A + A) of two intact neighbours
+    double c4;            // 0.25 A, the element force factor
+    double geo[4][3][3];  // tip edge a, path j: unit normal x, y and length
 };
 
 // Device-resident control block of one model.
@@ -54,7 +80,9 @@ static_assert(sizeof(Control) == 48, "Control layout");
 // offset to the specimen's part of the batch arrays.  T is the arithmetic
 // and storage type of the step (double, or float for the binary32 step,
 // whose set-up values are the binary64 ones rounded once); times, the load
-// curve, the log, U_d and the pick variant's buffers stay binary64.
+// curve, the log, U_d and the pick variant's buffers stay binary64.  (The
+// batched step copies a view field by field: load_view in mct2d_step.hip
+// lists every field.)
 template <class T>
 struct StepParamsT {
     int32_t nx, ny;     // elements per direction
@@ -98,6 +126,14 @@ struct StepParamsT {
     int32_t *forder;
     int32_t *fbucket, *fsorted, *fplist;
     double fcell;  // hash cell of the pick: >= rho and the largest element diameter
+    // uniform lattice (binary64 point rule): its shared geometry, or null
+    const LatticeConst *lat;
+    // near-threshold decision log (plain models): null when off
+    NearRec *near;
+    uint32_t *near_count;
+    int32_t near_cap;
+    int32_t pad_near;
+    T near_tol;
 };
 using StepParams = StepParamsT<double>;
 using StepParamsF = StepParamsT<float>;
@@ -114,6 +150,7 @@ TileShape tile_shape(int tile);  // tile in 1..kNumTiles
 // f32: a single binary32 specimen, p0f (p0 holds its binary64 mirror).
 struct Launch {
     bool batched;
+    bool uni;
     StepParams p0;
     const StepParams *views;
     const int2 *units;
@@ -123,9 +160,15 @@ struct Launch {
 };
 
 // One step of a segment (k_rel = index in the segment, par0 = parity of the
-// segment's first step), and the segment close after n steps.
+// segment's first step), and the segment close after n steps.  uni: every
+// specimen of the launch is a uniform lattice (its views carry lat).
 hipError_t launch_step(int tile, const Launch &L, int k_rel, int par0, hipStream_t s);
 hipError_t launch_commit(const Launch &L, int n, hipStream_t s);
+
+// Uniform-lattice check of one specimen: ref receives element 0's geometry
+// (LatticeConst), flag bit 0 = some element differs bitwise, bit 1 = the
+// gradients do not have the zero pattern of a rectangle.
+hipError_t launch_lattice_check(const StepParams &p, LatticeConst *ref, uint32_t *flag, hipStream_t s);
 
 // Crack-surface tips: compacted edge ids and reference midpoints.
 hipError_t launch_tips(int32_t nx, int32_t ny, const double *X, const double *Y,

@@ -44,9 +44,12 @@ __device__ __forceinline__ bool better(T g1, int e1, int a1, T g2, int e2, int a
     return g1 > g2 || (g1 == g2 && (e1 < e2 || (e1 == e2 && a1 < a2)));
 }
 
+// A reduction value: the best accepted candidate (G, e, a, k) of a set, the
+// second largest accepted G (G2, -1 when the set has one) and the smallest
+// accepted G.
 template <class T>
 struct CandT {
-    T G, Gmin;
+    T G, Gmin, G2;
     int e, a, k;
 };
 using Cand = CandT<double>;
@@ -55,13 +58,23 @@ template <class T>
 __device__ __forceinline__ void cand_none(CandT<T> &c) {
     c.G = T(-1);
     c.Gmin = T(__builtin_inff());
+    c.G2 = T(-1);
     c.e = INT_MAX;
     c.a = 4;
     c.k = 0;
 }
 
-template <class T>
-__device__ __forceinline__ void cand_merge(CandT<T> &c, T G, T Gmin, int e, int a, int k) {
+// Merge another set's value (a single candidate has G2 = -1): the second
+// largest of the union is the larger of the two second largest values and
+// the smaller of the two largest.  Kept only with the near-threshold log
+// (NEAR); otherwise G2 stays -1.
+template <bool NEAR, class T>
+__device__ __forceinline__ void cand_merge(CandT<T> &c, T G, T G2, T Gmin, int e, int a, int k) {
+    if constexpr (NEAR) {
+        const T lo = G < c.G ? G : c.G;
+        const T s2 = G2 > c.G2 ? G2 : c.G2;
+        c.G2 = lo > s2 ? lo : s2;
+    }
     if (better(G, e, a, c.G, c.e, c.a)) {
         c.G = G;
         c.e = e;
@@ -71,16 +84,18 @@ __device__ __forceinline__ void cand_merge(CandT<T> &c, T G, T Gmin, int e, int 
     if (Gmin < c.Gmin) c.Gmin = Gmin;
 }
 
-template <class T>
+template <bool NEAR, class T>
 __device__ __forceinline__ void cand_wave_reduce(CandT<T> &c) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
         T G = __shfl_xor(c.G, off, 64);
+        T G2 = T(-1);
+        if constexpr (NEAR) G2 = __shfl_xor(c.G2, off, 64);
         T Gm = __shfl_xor(c.Gmin, off, 64);
         int e = __shfl_xor(c.e, off, 64);
         int a = __shfl_xor(c.a, off, 64);
         int k = __shfl_xor(c.k, off, 64);
-        cand_merge(c, G, Gm, e, a, k);
+        cand_merge<NEAR>(c, G, G2, Gm, e, a, k);
     }
 }
 
@@ -88,14 +103,15 @@ __device__ __forceinline__ void cand_wave_reduce(CandT<T> &c) {
 // lanes hold no candidate (G < 0 everywhere: the empty value, which merging
 // leaves unchanged) skips the shuffle tree; its lane 0 already holds the
 // wave's result.
-template <int NT, class T>
+template <int NT, bool NEAR, class T>
 __device__ __forceinline__ void cand_block_reduce(CandT<T> &c, CandT<T> *red) {
-    if (__ballot(c.G >= T(0)) != 0ull) cand_wave_reduce(c);  // uniform over the wave
+    if (__ballot(c.G >= T(0)) != 0ull) cand_wave_reduce<NEAR>(c);  // uniform over the wave
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) red[wave] = c;
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int w = 1; w < NT / 64; ++w) cand_merge(c, red[w].G, red[w].Gmin, red[w].e, red[w].a, red[w].k);
+        for (int w = 1; w < NT / 64; ++w)
+            cand_merge<NEAR>(c, red[w].G, red[w].G2, red[w].Gmin, red[w].e, red[w].a, red[w].k);
     }
 }
 
@@ -124,21 +140,165 @@ __device__ __forceinline__ int xcd_tile(int b, int nwg) {
     return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + l;
 }
 
+// Read-only data the whole launch shares (a batch's unit table and views,
+// the lattice constants): read through the constant address space, so that
+// a workgroup-uniform address becomes a scalar load.
+template <class X>
+__device__ __forceinline__ const __attribute__((address_space(4))) X *kconst(const X *ptr) {
+    return (const __attribute__((address_space(4))) X *)ptr;
+}
+
+
+// A batch view, copied field by field with scalar loads from the constant
+// address space.  Pointers loaded from there are known to point to global
+// memory, so the step issues global (not flat) loads and stores through them:
+// flat accesses also count against the LDS wait counter, so each LDS wait
+// would wait for the memory loads in flight too.  (Every field of
+// StepParamsT is copied here.)
+template <class T>
+__device__ __forceinline__ void load_view(StepParamsT<T> &p, const StepParamsT<T> *v) {
+    const __attribute__((address_space(4))) StepParamsT<T> *s = kconst(v);
+    p.nx = s->nx; p.ny = s->ny; p.ntx = s->ntx; p.nty = s->nty;
+    p.nwg = s->nwg; p.log_cap = s->log_cap; p.X = s->X; p.Y = s->Y;
+    p.ux0 = s->ux0; p.uy0 = s->uy0; p.ux1 = s->ux1; p.uy1 = s->uy1;
+    p.vx = s->vx; p.vy = s->vy; p.minv = s->minv; p.split = s->split;
+    p.area = s->area; p.screen = s->screen; p.sct = s->sct; p.ncurve = s->ncurve;
+    p.curve_t = s->curve_t; p.curve_phi = s->curve_phi; p.gc = s->gc; p.gc_uniform = s->gc_uniform;
+    p.fext_p = s->fext_p; p.vmask_p = s->vmask_p; p.v0_p = s->v0_p; p.D11 = s->D11;
+    p.D12 = s->D12; p.D33 = s->D33; p.E = s->E; p.dt = s->dt;
+    p.t_ramp = s->t_ramp; p.dts = s->dts; p.gamma = s->gamma; p.ctl = s->ctl;
+    p.slots = s->slots; p.log = s->log; p.subcell = s->subcell; p.pad_sc = s->pad_sc;
+    p.front = s->front; p.fcap = s->fcap; p.front_r2 = s->front_r2; p.fcand = s->fcand;
+    p.fcount = s->fcount; p.fmid = s->fmid; p.flen = s->flen; p.forder = s->forder;
+    p.fbucket = s->fbucket; p.fsorted = s->fsorted; p.fplist = s->fplist; p.fcell = s->fcell;
+    p.lat = s->lat; p.near = s->near; p.near_count = s->near_count; p.near_cap = s->near_cap;
+    p.pad_near = s->pad_near; p.near_tol = s->near_tol;
+}
+
+// Non-zero pattern of the Q4 gradients at the midpoint of local edge k of a
+// rectangle (axis-parallel edges): dN_n/dx vanishes where dN_n/dxi does
+// (edges 0 and 2: the two nodes off the edge), dN_n/dy where dN_n/deta does
+// (edges 1 and 3).
+__host__ __device__ constexpr bool lat_nzx(int k, int n) {
+    return (k == 1 || k == 3) ? true : (k == 0 ? (n == 0 || n == 1) : (n == 2 || n == 3));
+}
+__host__ __device__ constexpr bool lat_nzy(int k, int n) {
+    return (k == 0 || k == 2) ? true : (k == 1 ? (n == 1 || n == 2) : (n == 0 || n == 3));
+}
+
+// Strain (B u) at the midpoint of local edge K of a lattice element with
+// the shared gradients B: the terms of strain<4> in the same order, the
+// vanishing products left out (adding a zero product changes at most the
+// sign of a zero).
+template <int K>
+__device__ __forceinline__ void strain_lat(const LatticeConst *L, const double ux[4], const double uy[4],
+                                           double q[3]) {
+    double exx = 0.0, eyy = 0.0, gxy = 0.0;
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        const double bx = kconst(L)->B[K][n], by = kconst(L)->B[K][4 + n];
+        if (lat_nzx(K, n)) exx = fma(bx, ux[n], exx);
+        if (lat_nzy(K, n)) eyy = fma(by, uy[n], eyy);
+        if (lat_nzy(K, n)) gxy = fma(by, ux[n], gxy);
+        if (lat_nzx(K, n)) gxy = fma(bx, uy[n], gxy);
+    }
+    q[0] = exx;
+    q[1] = eyy;
+    q[2] = gxy;
+}
+
+__device__ __forceinline__ void strain_lat_rt(const LatticeConst *L, int k, const double ux[4],
+                                              const double uy[4], double q[3]) {
+    switch (k) {
+        case 0: strain_lat<0>(L, ux, uy, q); break;
+        case 1: strain_lat<1>(L, ux, uy, q); break;
+        case 2: strain_lat<2>(L, ux, uy, q); break;
+        default: strain_lat<3>(L, ux, uy, q); break;
+    }
+}
+
+template <class T>
+__device__ __forceinline__ T absT(T x) {
+    return x < T(0) ? -x : x;
+}
+
+// Near-threshold records (plain models with the log on).
+template <class T>
+__device__ __forceinline__ void near_push(const StepParamsT<T> &p, int64_t step, int64_t e, int a, int kind, int k,
+                                          T G, T ref) {
+    const uint32_t i = atomicAdd(p.near_count, 1u);
+    if (i < (uint32_t)p.near_cap) {
+        NearRec r;
+        r.step = (int32_t)step;
+        r.elem = (int32_t)e;
+        r.a = (uint8_t)a;
+        r.kind = (uint8_t)kind;
+        r.k = (uint8_t)k;
+        r.pad0 = 0;
+        r.pad1 = 0;
+        r.G = (double)G;
+        r.ref = (double)ref;
+        p.near[i] = r;
+    }
+}
+
+// One evaluated candidate (gate open, path values G[0..2] of exit edges
+// a+1, a+2, a+3): paths near Gc; with two or more paths above Gc the gap of
+// the largest two and every split-ratio margin of the element rule.
+template <class T>
+__device__ __forceinline__ void near_candidate(const StepParamsT<T> &p, int64_t step, int64_t e, int a,
+                                               const T G[3], T gc) {
+    const T tol = p.near_tol, gamma = p.gamma;
+    int best = -1, nS = 0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        if (absT(G[j] - gc) <= tol * gc) near_push(p, step, e, a, 1, (a + 1 + j) & 3, G[j], gc);
+        if (G[j] > gc) {
+            nS++;
+            if (best < 0 || G[j] > G[best]) best = j;
+        }
+    }
+    if (nS < 2) return;
+    T gb = T(0), second = T(-1);
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+        if (j == best) gb = G[j];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+        if (j != best && G[j] > gc && G[j] > second) second = G[j];
+    if (gb - second <= tol * gb) near_push(p, step, e, a, 2, (a + 1 + best) & 3, gb, second);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        if (j == best || !(G[j] > gc)) continue;
+        if (absT(gb - gamma * (gb - G[j])) <= tol * gb) near_push(p, step, e, a, 3, (a + 1 + j) & 3, gb, G[j]);
+    }
+}
+
 }  // namespace
+
+// The pick's records: the gap of the two largest accepted G and the
+// split-ratio margin against the smallest (g holds the reduced set).
+template <class T>
+__device__ __forceinline__ void near_pick(const StepParamsT<T> &p, int64_t step, const CandT<T> &g) {
+    if (!p.near || p.sct || !(g.G >= T(0))) return;
+    const T tol = p.near_tol;
+    if (g.G2 >= T(0) && g.G - g.G2 <= tol * g.G) near_push(p, step, g.e, g.a, 4, g.k, g.G, g.G2);
+    if (absT(g.G - p.gamma * (g.G - g.Gmin)) <= tol * g.G) near_push(p, step, g.e, g.a, 5, g.k, g.G, g.Gmin);
+}
 
 // Reduce the candidates published in slot set `set` with the whole
 // workgroup; thread 0 receives the result.  Every thread must call it.
 // Slots hold binary64 values; a binary32 step's values are exact in them.
-template <int NT, class T>
+template <int NT, bool NEAR, class T>
 __device__ __forceinline__ CandT<T> reduce_slots(const StepParamsT<T> &p, int set, uint32_t n, CandT<T> *red) {
     const Slot *sl = p.slots + (size_t)set * p.nwg;
     CandT<T> g;
     cand_none(g);
     for (uint32_t s = threadIdx.x; s < n; s += NT) {
         const Slot x = sl[s];
-        cand_merge(g, T(x.G), T(x.Gmin), x.elem, x.a, x.k);
+        cand_merge<NEAR>(g, T(x.G), T(x.G2), T(x.Gmin), x.elem, x.a, x.k);
     }
-    cand_block_reduce<NT>(g, red);
+    cand_block_reduce<NT, NEAR>(g, red);
     return g;
 }
 
@@ -211,9 +371,23 @@ __device__ __forceinline__ int32_t tip_after(const StepParamsT<T> &p, const Cand
 // unit b = (specimen, tile) comes from `units` and the specimen's view (its
 // sizes, constants and pre-offset pointers) from `views`.  Otherwise the one
 // view `p0` is passed by value and workgroups map to tiles XCD-banded.
-template <class T, int TXE, int TYE, bool BATCHED, bool SC = false>
-__global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParamsT<T> p0, const StepParamsT<T> *views,
-                                                   const int2 *units, int k_rel, int par0) {
+//
+// UNI (binary64 point rule): every specimen of the launch is a uniform
+// lattice, whose element gradients, smoothing weight, force factor and
+// crack-path geometry are the shared values in p.lat (set-up verified them
+// bitwise equal to what each element would compute).  Only u and the split
+// codes are staged; coordinates are read from memory for candidates and
+// split elements alone.  Same operations in the same order, so the result
+// is the general kernel's bit for bit.
+//
+// NEAR (plain models, 16 x 16 tiles): the near-threshold decision log is on;
+// the reductions also carry the second largest accepted G.
+template <class T, int TXE, int TYE, bool BATCHED, bool SC = false, bool UNI = false, bool NEAR = false>
+__global__ __launch_bounds__(TXE *TYE, UNI ? 6 : 4) void k_step(StepParamsT<T> p0,
+                                                               const StepParamsT<T> *__restrict__ views,
+                                                               const int2 *__restrict__ units, int k_rel, int par0) {
+    static_assert(!UNI || (sizeof(T) == 8 && !SC), "the lattice kernel is binary64 with the point rule");
+    static_assert(!NEAR || !BATCHED, "the near-threshold log is for plain models");
     constexpr int NT = TXE * TYE;
     constexpr int TX = TXE - 1, TY = TYE - 1;  // owned nodes
     constexpr int HX = TXE + 3, HY = TYE + 3;  // staged nodes
@@ -227,12 +401,14 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParamsT<T> p0, const S
     // SC (sub-cell smoothing): a fourth component holds the lower-id side's
     // sub-cell area
     constexpr int NQ = ((SC ? 4 : 3) * NS > 8 * NT) ? (SC ? 4 : 3) * NS : 8 * NT;
-    __shared__ T s_ux[HX * HY], s_uy[HX * HY], s_X[HX * HY], s_Y[HX * HY];
+    constexpr int NXY = UNI ? 1 : HX * HY;
+    __shared__ T s_ux[HX * HY], s_uy[HX * HY], s_X[NXY], s_Y[NXY];
     // per edge and component (stride NS): first the strain part of the
     // lower-id element, then the smoothed stress; after the force phase the
     // same memory holds the element forces [8][NT]
     __shared__ T s_e[NQ];
-    __shared__ T s_area[EX * EY];
+    __shared__ T s_area[UNI ? 1 : EX * EY];
+    __shared__ T s_geo[UNI ? 36 : 1];  // lattice: crack-path geometry (a, j, {nx, ny, L})
     T *const s_fe = s_e;
     __shared__ uint8_t s_split[EX * EY];
     __shared__ uint16_t s_cand[4 * TX * TY];
@@ -247,8 +423,9 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParamsT<T> p0, const S
     int tile;
     StepParamsT<T> p;
     if constexpr (BATCHED) {
-        const int2 u = units[blockIdx.x];
-        p = views[u.x];
+        const __attribute__((address_space(4))) int *uu = kconst(reinterpret_cast<const int *>(units));
+        const int2 u = make_int2(uu[2 * blockIdx.x], uu[2 * blockIdx.x + 1]);
+        load_view(p, views + u.x);
         tile = u.y;
     } else {
         p = p0;
@@ -283,8 +460,10 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParamsT<T> p0, const S
             const int64_t n = (int64_t)gj * (nx + 1) + gi;
             ra[r] = ux_c[n];
             rb[r] = uy_c[n];
-            rc[r] = p.X[n];
-            rd[r] = p.Y[n];
+            if constexpr (!UNI) {
+                rc[r] = p.X[n];
+                rd[r] = p.Y[n];
+            }
         }
     }
     uint8_t rs[RE];
@@ -298,7 +477,7 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParamsT<T> p0, const S
         if (idx < NE2 && gi >= 0 && gi < nx && gj >= 0 && gj < ny) {
             const int64_t e = (int64_t)gj * nx + gi;
             rs[r] = p.split[e];
-            rarea[r] = p.area[e];
+            if constexpr (!UNI) rarea[r] = p.area[e];
         }
     }
     // screen state of this thread's ring element (owned elements only)
@@ -312,14 +491,37 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParamsT<T> p0, const S
     const int on_i = i0 + on_l, on_j = j0 + on_m;
     const bool on_valid = tid < TX * TY && on_i <= nx && on_j <= ny;
     const int64_t on_n = (int64_t)on_j * (nx + 1) + on_i;
+    // owned-node data for the update: the lattice kernel issues these loads
+    // with the staging loads (one memory round trip per workgroup); the
+    // general kernel, short of registers, once the candidates are done
+    T n_minv = T(0), n_vx = T(0), n_vy = T(0), n_fex = T(0), n_fey = T(0), n_v0x = T(0), n_v0y = T(0);
+    unsigned n_mask = 0;
+    auto load_node = [&]() {
+        if (on_valid) {
+            n_minv = p.minv[on_n];
+            n_vx = p.vx[on_n];
+            n_vy = p.vy[on_n];
+            const int pidx = perimeter_index(on_i, on_j, nx, ny);
+            if (pidx >= 0) {
+                n_fex = p.fext_p[2 * pidx];
+                n_fey = p.fext_p[2 * pidx + 1];
+                n_mask = p.vmask_p[pidx];
+                n_v0x = p.v0_p[2 * pidx];
+                n_v0y = p.v0_p[2 * pidx + 1];
+            }
+        }
+    };
+    if constexpr (UNI) load_node();
 #pragma unroll
     for (int r = 0; r < RH; ++r) {
         const int idx = tid + r * NT;
         if (idx < NHALO) {
             s_ux[idx] = ra[r];
             s_uy[idx] = rb[r];
-            s_X[idx] = rc[r];
-            s_Y[idx] = rd[r];
+            if constexpr (!UNI) {
+                s_X[idx] = rc[r];
+                s_Y[idx] = rd[r];
+            }
         }
     }
 #pragma unroll
@@ -327,8 +529,11 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParamsT<T> p0, const S
         const int idx = tid + r * NT;
         if (idx < NE2) {
             s_split[idx] = rs[r];
-            s_area[idx] = rarea[r];
+            if constexpr (!UNI) s_area[idx] = rarea[r];
         }
+    }
+    if constexpr (UNI) {
+        if (tid < 36) s_geo[tid] = (&kconst(p.lat)->geo[0][0][0])[tid];
     }
     if (tid == 0) {
         s_ncand = 0;
@@ -340,7 +545,7 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParamsT<T> p0, const S
 
     // ---- 2. the pick of the previous step -------------------------------
     if (nprev > 0) {  // uniform over the workgroup
-        const CandT<T> g = reduce_slots<NT>(p, set_r, nprev, s_red);  // contains a barrier
+        const CandT<T> g = reduce_slots<NT, NEAR>(p, set_r, nprev, s_red);  // contains a barrier
         if (tid == 0 && pick_accepted(p, g)) {
             const int fx = g.e % nx - (i0 - 2), fy = g.e / nx - (j0 - 2);
             if (fx >= 0 && fx < EX && fy >= 0 && fy < EY)
@@ -348,6 +553,8 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParamsT<T> p0, const S
             if (p.sct) s_tip = tip_after(p, g);
             if (leader) apply_split(p, g, base + k_rel - 1);
         }
+        if constexpr (NEAR)
+            if (tid == 0 && leader) near_pick(p, base + k_rel - 1, g);
     }
     if (tid == 0 && leader) {
         p.ctl->nslots[set_c] = 0;
@@ -360,6 +567,18 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParamsT<T> p0, const S
     }
     __syncthreads();
 
+    // reference coordinates of the staged node at offset o (lattice: read
+    // from memory, only for candidates and split elements)
+    auto node_xy = [&](int o, T &x, T &y) {
+        if constexpr (UNI) {
+            const int64_t n = (int64_t)(j0 - 2 + o / HX) * (nx + 1) + (i0 - 2 + o % HX);
+            x = p.X[n];
+            y = p.Y[n];
+        } else {
+            x = s_X[o];
+            y = s_Y[o];
+        }
+    };
     auto elem_xy = [&](int ex, int ey, T x[4], T y[4]) {
         const int b = ey * HX + ex;
         x[0] = s_X[b];
@@ -423,7 +642,11 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParamsT<T> p0, const S
             for (int c = 0; c < 3; ++c) s_e[c * NS + sid] = q[c];
             s_e[3 * NS + sid] = A;
         } else if (s_split[nb] == 0) {
-            const T w0 = A / (A + s_area[nb]);
+            T w0;
+            if constexpr (UNI)
+                w0 = kconst(p.lat)->w;
+            else
+                w0 = A / (A + s_area[nb]);
 #pragma unroll
             for (int c = 0; c < 3; ++c) s_e[c * NS + sid] = w0 * q[c];
         } else {
@@ -443,7 +666,11 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParamsT<T> p0, const S
 #pragma unroll
                 for (int c = 0; c < 3; ++c) eps[c] = fmat(w1, q[c], w0 * s_e[c * NS + sid]);
             } else {
-                const T w1 = A / (s_area[nb] + A);
+                T w1;
+                if constexpr (UNI)
+                    w1 = kconst(p.lat)->w;
+                else
+                    w1 = A / (s_area[nb] + A);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) eps[c] = fmat(w1, q[c], s_e[c * NS + sid]);
             }
@@ -470,8 +697,27 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParamsT<T> p0, const S
     // gradients (gx[k][0..2], gy[k][0..2]) and areas at[k]
     T gx[4][4], gy[4][4], at[4];
     T qh0[3], qh3[3];
-    const T my_area = s_area[e2];
-    if (code == 0) {
+    T my_area;
+    if constexpr (UNI)
+        my_area = T(0);  // unused: the lattice weights and force factor are shared
+    else
+        my_area = s_area[e2];
+    if (UNI && code == 0) {
+        T ux[4], uy[4];
+        elem_u(ex, ey, ux, uy);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            T q[3];
+            if constexpr (UNI) strain_lat_rt(p.lat, k, ux, uy, q);
+            if (k == 0) {
+                qh0[0] = q[0]; qh0[1] = q[1]; qh0[2] = q[2];
+            } else if (k == 3) {
+                qh3[0] = q[0]; qh3[1] = q[1]; qh3[2] = q[2];
+            } else {
+                lo_part(e2, my_area, k, sidx[k], q);
+            }
+        }
+    } else if (!UNI && code == 0) {
         T x[4], y[4];
         elem_xy(ex, ey, x, y);
         T ux[4], uy[4];
@@ -523,16 +769,22 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParamsT<T> p0, const S
         ore = rey * EX + rex;
         if (s_split[ore] == 0) {
             oin = true;
-            T x[4], y[4], ux[4], uy[4], dx[4], dy[4];
-            elem_xy(rex, rey, x, y);
+            T ux[4], uy[4];
             elem_u(rex, rey, ux, uy);
-            if constexpr (SC) {
-                oat = subcell_rt(x, y, ux, uy, ork, dx, dy, oq);
+            if constexpr (UNI) {
+                strain_lat_rt(p.lat, ork, ux, uy, oq);
+                if (og == 0 || og == 2) lo_part(ore, T(0), ork, osid, oq);
             } else {
-                q4_grad_rt(x, y, ork, dx, dy);
-                strain<4>(dx, dy, ux, uy, oq);
+                T x[4], y[4], dx[4], dy[4];
+                elem_xy(rex, rey, x, y);
+                if constexpr (SC) {
+                    oat = subcell_rt(x, y, ux, uy, ork, dx, dy, oq);
+                } else {
+                    q4_grad_rt(x, y, ork, dx, dy);
+                    strain<4>(dx, dy, ux, uy, oq);
+                }
+                if (og == 0 || og == 2) lo_part(ore, SC ? oat : s_area[ore], ork, osid, oq);
             }
-            if (og == 0 || og == 2) lo_part(ore, SC ? oat : s_area[ore], ork, osid, oq);
         }
     }
     __syncthreads();
@@ -542,26 +794,13 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParamsT<T> p0, const S
         lo_sigma(e2, 1, sidx[1]);
         lo_sigma(e2, 2, sidx[2]);
     }
-    if (oin && (og == 1 || og == 3)) hi_sigma(ore, SC ? oat : s_area[ore], ork, osid, oq);
-    __syncthreads();
-
-    // owned-node data for the update, loaded here so that the registers are
-    // free during the gradient phase and the latency hides behind the forces
-    T n_minv = T(0), n_vx = T(0), n_vy = T(0), n_fex = T(0), n_fey = T(0), n_v0x = T(0), n_v0y = T(0);
-    unsigned n_mask = 0;
-    if (on_valid) {
-        n_minv = p.minv[on_n];
-        n_vx = p.vx[on_n];
-        n_vy = p.vy[on_n];
-        const int pidx = perimeter_index(on_i, on_j, nx, ny);
-        if (pidx >= 0) {
-            n_fex = p.fext_p[2 * pidx];
-            n_fey = p.fext_p[2 * pidx + 1];
-            n_mask = p.vmask_p[pidx];
-            n_v0x = p.v0_p[2 * pidx];
-            n_v0y = p.v0_p[2 * pidx + 1];
-        }
+    if (oin && (og == 1 || og == 3)) {
+        if constexpr (UNI)
+            hi_sigma(ore, T(0), ork, osid, oq);
+        else
+            hi_sigma(ore, SC ? oat : s_area[ore], ork, osid, oq);
     }
+    __syncthreads();
 
     // smoothed stress at edge slot sid
     auto edge_sigma = [&](int sid, T sg[3]) {
@@ -570,7 +809,11 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParamsT<T> p0, const S
     };
 
     // ---- 4. element forces, one thread per element of the tile ring ----
+    // The general kernel computes them here, while the gradients are in
+    // registers; the lattice kernel after the candidates (its gradients are
+    // shared constants, so the forces need not stay live meanwhile).
     T fe[8];
+    auto element_forces = [&]() {
 #pragma unroll
     for (int c = 0; c < 8; ++c) fe[c] = T(0);
     if (SC && code == 0) {
@@ -585,6 +828,44 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParamsT<T> p0, const S
             }
         }
         subcell_force(bb, cb, at, sgk, fe);
+    } else if (UNI && code == 0) {
+        // the general loop below with the shared gradients; a vanishing
+        // gradient leaves one product of each pair
+        T sx[4], sy[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            T sg[3];
+            edge_sigma(sidx[k], sg);
+            const T s0 = sg[0], s1 = sg[1], s2 = sg[2];
+#pragma unroll
+            for (int n = 0; n < 4; ++n) {
+                const T bx = kconst(p.lat)->B[k][n], by = kconst(p.lat)->B[k][4 + n];
+                T tx, ty;
+                if (lat_nzx(k, n) && lat_nzy(k, n)) {
+                    tx = fmat(by, s2, bx * s0);
+                    ty = fmat(bx, s2, by * s1);
+                } else if (lat_nzx(k, n)) {
+                    tx = bx * s0;
+                    ty = bx * s2;
+                } else {
+                    tx = by * s2;
+                    ty = by * s1;
+                }
+                if (k == 0) {
+                    sx[n] = tx;
+                    sy[n] = ty;
+                } else {
+                    sx[n] = sx[n] + tx;
+                    sy[n] = sy[n] + ty;
+                }
+            }
+        }
+        const T c = kconst(p.lat)->c4;
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            fe[2 * n] = c * sx[n];
+            fe[2 * n + 1] = c * sy[n];
+        }
     } else if (code == 0) {
         T sx[4], sy[4];
 #pragma unroll
@@ -612,6 +893,8 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParamsT<T> p0, const S
             fe[2 * n + 1] = c * sy[n];
         }
     }
+    };
+    if constexpr (!UNI) element_forces();
 
     // free-surface candidates of the elements this tile owns (node n0 owned),
     // compacted with wavefront ballots into s_cand
@@ -685,7 +968,9 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParamsT<T> p0, const S
             gc = p.gc ? p.gc[ge] : p.gc_uniform;
             const int nb0 = (cje + 1) * HX + (cie + 1);
             const int o1 = nb0 + corner(a), o2 = nb0 + corner((a + 1) & 3);
-            const T X1 = s_X[o1], Y1 = s_Y[o1], X2 = s_X[o2], Y2 = s_Y[o2];
+            T X1, Y1, X2, Y2;
+            node_xy(o1, X1, Y1);
+            node_xy(o2, X2, Y2);
             const T ux1 = s_ux[o1], uy1 = s_uy[o1], ux2 = s_ux[o2], uy2 = s_uy[o2];
             const T dux = ux2 - ux1, duy = uy2 - uy1;
             const T x1 = X1 + ux1, y1 = Y1 + uy1;
@@ -697,8 +982,15 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParamsT<T> p0, const S
                 const int k = (a + 1 + j) & 3;
                 T sg[3], nxv, nyv, len;
                 edge_sigma(edge_slot(cie, cje, k), sg);
-                const int q0 = nb0 + corner(k), q1 = nb0 + corner((k + 1) & 3);
-                path_geom_pts(X1, Y1, X2, Y2, s_X[q0], s_Y[q0], s_X[q1], s_Y[q1], nxv, nyv, len);
+                if constexpr (UNI) {
+                    const int gq = (a * 3 + j) * 3;
+                    nxv = s_geo[gq];
+                    nyv = s_geo[gq + 1];
+                    len = s_geo[gq + 2];
+                } else {
+                    const int q0 = nb0 + corner(k), q1 = nb0 + corner((k + 1) & 3);
+                    path_geom_pts(X1, Y1, X2, Y2, s_X[q0], s_Y[q0], s_X[q1], s_Y[q1], nxv, nyv, len);
+                }
                 const T spx = fmat(sg[2], nyv, sg[0] * nxv);
                 const T spy = fmat(sg[1], nyv, sg[2] * nxv);
                 Gj = T(0.5) * fmat(duy, spy, dux * spx);
@@ -709,6 +1001,7 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParamsT<T> p0, const S
         const T G2 = __shfl(Gj, qb + 2, 64);
         if (live && H && j == 0) {
             const T Gv[3] = {Gj, G1, G2};
+            if constexpr (NEAR) near_candidate(p, base + k_rel, ge, a, Gv, gc);
             int jb = -1;
             T gb = T(0);
 #pragma unroll
@@ -722,7 +1015,7 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParamsT<T> p0, const S
 #pragma unroll
                 for (int q = 0; q < 3; ++q)
                     if (q != jb && Gv[q] > gc && !(gb > p.gamma * (gb - Gv[q]))) ok = false;
-                if (ok) cand_merge(best, gb, gb, (int)ge, a, (a + 1 + jb) & 3);
+                if (ok) cand_merge<NEAR>(best, gb, T(-1), gb, (int)ge, a, (a + 1 + jb) & 3);
                 if (ok && p.front) {  // per-front pick: every accepted candidate
                     const uint32_t slot = atomicAdd(p.fcount, 1u);
                     AccCand ac;
@@ -734,7 +1027,25 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParamsT<T> p0, const S
             }
         }
     }
-    if (ncand > 0) cand_block_reduce<NT>(best, s_red);  // uniform branch
+    if (ncand > 0) cand_block_reduce<NT, NEAR>(best, s_red);  // uniform branch
+    if constexpr (!UNI) {
+        // the general kernel's owned-node loads (inline: a lambda call here
+        // costs it registers); the latency hides behind the split pieces
+        if (on_valid) {
+            n_minv = p.minv[on_n];
+            n_vx = p.vx[on_n];
+            n_vy = p.vy[on_n];
+            const int pidx = perimeter_index(on_i, on_j, nx, ny);
+            if (pidx >= 0) {
+                n_fex = p.fext_p[2 * pidx];
+                n_fey = p.fext_p[2 * pidx + 1];
+                n_mask = p.vmask_p[pidx];
+                n_v0x = p.v0_p[2 * pidx];
+                n_v0y = p.v0_p[2 * pidx + 1];
+            }
+        }
+    }
+    if constexpr (UNI) element_forces();
     __syncthreads();  // strain slots are no longer read: reuse them for forces
 
     // ---- 6. colour-ordered gather to the owned nodes --------------------
@@ -762,8 +1073,11 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParamsT<T> p0, const S
         const int F = cst ? ((((eb - ea) & 3) == 3) ? ea : eb) : (((it - ncorner) & 1) ? eb : ea);
         const int n0 = F, n1 = (F + 1) & 3, n2 = (F + 2) & 3, n3 = (F + 3) & 3;
         const int o0 = nb0 + corner(n0), o1 = nb0 + corner(n1), o2 = nb0 + corner(n2), o3 = nb0 + corner(n3);
-        const T x0 = s_X[o0], x1 = s_X[o1], x2 = s_X[o2], x3 = s_X[o3];
-        const T y0 = s_Y[o0], y1 = s_Y[o1], y2 = s_Y[o2], y3 = s_Y[o3];
+        T x0, x1, x2, x3, y0, y1, y2, y3;
+        node_xy(o0, x0, y0);
+        node_xy(o1, x1, y1);
+        node_xy(o2, x2, y2);
+        node_xy(o3, x3, y3);
         const T gx = T(0.5) * (x0 + x1), gy = T(0.5) * (y0 + y1);  // midpoint of edge F
         if (cst) {
             // polygon: mid(F), n1, n2, n3, mid(F+3); shoelace fanned from mid(F)
@@ -855,6 +1169,7 @@ __global__ __launch_bounds__(TXE *TYE, 4) void k_step(StepParamsT<T> p0, const S
         Slot sl;
         sl.G = (double)best.G;
         sl.Gmin = (double)best.Gmin;
+        sl.G2 = (double)best.G2;
         sl.elem = best.e;
         sl.a = best.a;
         sl.k = best.k;
@@ -872,15 +1187,17 @@ template <class T, bool BATCHED>
 __global__ __launch_bounds__(kCommitThreads) void k_commit(StepParamsT<T> p0, const StepParamsT<T> *views, int n) {
     __shared__ CandT<T> s_red[kCommitThreads / 64];
     StepParamsT<T> p;
-    if constexpr (BATCHED)
-        p = views[blockIdx.x];
+    if constexpr (BATCHED) {
+        load_view(p, views + blockIdx.x);
+    }
     else
         p = p0;
     const int set = (n + 2) % 3;
-    const CandT<T> g = reduce_slots<kCommitThreads>(p, set, p.ctl->nslots[set], s_red);
+    const CandT<T> g = reduce_slots<kCommitThreads, true>(p, set, p.ctl->nslots[set], s_red);
     if (threadIdx.x != 0) return;
     const int64_t base = p.ctl->base;
     const bool acc = n > 0 && pick_accepted(p, g);
+    if (n > 0 && p.near) near_pick(p, base + n - 1, g);
     if (p.sct && n > 0) {
         // the tip at the start of step base + n goes where that step reads the
         // previous step's tip
@@ -971,8 +1288,94 @@ __global__ __launch_bounds__(kFrontThreads) void k_front(StepParams p, int k_rel
     front_pick_block<kFrontThreads>(v, g, k_rel);
 }
 
+// ------------------------------------------------------------------------
+// Uniform-lattice check: every element's gradients at its four edge
+// midpoints, its area and its twelve crack-path normals and lengths, as the
+// general step computes them, compared bit for bit with element 0's.
+// ------------------------------------------------------------------------
+namespace {
+
+__device__ void lattice_of(const StepParams &p, int64_t e, LatticeConst &L) {
+    const int64_t i = e % p.nx, j = e / p.nx;
+    const int64_t n0 = j * (p.nx + 1) + i;
+    const int64_t nd[4] = {n0, n0 + 1, n0 + p.nx + 2, n0 + p.nx + 1};
+    double x[4], y[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        x[q] = p.X[nd[q]];
+        y[q] = p.Y[nd[q]];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) q4_grad(x, y, k, &L.B[k][0], &L.B[k][4]);
+    const double A = p.area[e];
+    L.w = A / (A + A);
+    L.c4 = 0.25 * A;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj)
+            path_geom(x, y, a, (a + 1 + jj) & 3, L.geo[a][jj][0], L.geo[a][jj][1], L.geo[a][jj][2]);
+}
+
+__global__ void k_lattice_ref(StepParams p, LatticeConst *ref, uint32_t *flag) {
+    LatticeConst L;
+    lattice_of(p, 0, L);
+    *ref = L;
+    uint32_t f = 0;
+    for (int k = 0; k < 4; ++k)
+        for (int n = 0; n < 4; ++n) {
+            if (!lat_nzx(k, n) && L.B[k][n] != 0.0) f |= 2u;
+            if (!lat_nzy(k, n) && L.B[k][4 + n] != 0.0) f |= 2u;
+        }
+    *flag = f;
+}
+
+__global__ __launch_bounds__(256) void k_lattice_check(StepParams p, const LatticeConst *ref, uint32_t *flag) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ne = (int64_t)p.nx * p.ny;
+    bool diff = false;
+    if (e < ne) {
+        LatticeConst L;
+        lattice_of(p, e, L);
+        const unsigned long long *a = reinterpret_cast<const unsigned long long *>(&L);
+        const unsigned long long *b = reinterpret_cast<const unsigned long long *>(ref);
+        for (size_t q = 0; q < sizeof(LatticeConst) / 8; ++q) diff = diff || a[q] != b[q];
+        diff = diff || __double_as_longlong(p.area[e]) != __double_as_longlong(p.area[0]);
+    }
+    if (__ballot(diff) != 0ull && (threadIdx.x & 63) == 0) atomicOr(flag, 1u);
+}
+
+}  // namespace
+
+hipError_t launch_lattice_check(const StepParams &p, LatticeConst *ref, uint32_t *flag, hipStream_t s) {
+    (void)hipGetLastError();
+    const int64_t ne = (int64_t)p.nx * p.ny;
+    k_lattice_ref<<<1, 1, 0, s>>>(p, ref, flag);
+    k_lattice_check<<<(unsigned)((ne + 255) / 256), 256, 0, s>>>(p, ref, flag);
+    return hipGetLastError();
+}
+
 hipError_t launch_step(int tile, const Launch &L, int k_rel, int par0, hipStream_t s) {
     (void)hipGetLastError();  // report only this launch's error below
+    if (L.f32 && L.p0f.near) {
+        const StepParamsF &p = L.p0f;
+        if (p.subcell)
+            k_step<float, 16, 16, false, true, false, true><<<p.nwg, 256, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
+        else
+            k_step<float, 16, 16, false, false, false, true><<<p.nwg, 256, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
+        return hipGetLastError();
+    }
+    if (!L.f32 && !L.batched && L.p0.near) {
+        const StepParams &p = L.p0;
+        if (L.uni)
+            k_step<double, 16, 16, false, false, true, true><<<p.nwg, 256, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
+        else if (p.subcell)
+            k_step<double, 16, 16, false, true, false, true><<<p.nwg, 256, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
+        else
+            k_step<double, 16, 16, false, false, false, true><<<p.nwg, 256, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
+        if (p.front) k_front<<<1, kFrontThreads, 0, s>>>(p, k_rel);
+        return hipGetLastError();
+    }
     if (L.f32) {
         // binary32 step: plain models with the point rule or sub-cell
         // smoothing and the global or single-tip pick
@@ -1000,6 +1403,37 @@ hipError_t launch_step(int tile, const Launch &L, int k_rel, int par0, hipStream
         return hipGetLastError();
     }
     const StepParams &p = L.p0;
+    if (L.uni) {
+        // uniform lattices: binary64 point rule (batched, or plain without the
+        // per-front pick's extra launch below)
+        if (L.batched) {
+            switch (tile) {
+                case 1:
+                    k_step<double, 16, 16, true, false, true><<<L.nunits, 256, 0, s>>>(p, L.views, L.units, k_rel, par0);
+                    break;
+                case 2:
+                    k_step<double, 32, 8, true, false, true><<<L.nunits, 256, 0, s>>>(p, L.views, L.units, k_rel, par0);
+                    break;
+                default:
+                    k_step<double, 32, 16, true, false, true><<<L.nunits, 512, 0, s>>>(p, L.views, L.units, k_rel, par0);
+                    break;
+            }
+        } else {
+            switch (tile) {
+                case 1:
+                    k_step<double, 16, 16, false, false, true><<<p.nwg, 256, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
+                    break;
+                case 2:
+                    k_step<double, 32, 8, false, false, true><<<p.nwg, 256, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
+                    break;
+                default:
+                    k_step<double, 32, 16, false, false, true><<<p.nwg, 512, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
+                    break;
+            }
+            if (p.front) k_front<<<1, kFrontThreads, 0, s>>>(p, k_rel);
+        }
+        return hipGetLastError();
+    }
     if (L.batched) {
         switch (tile) {
             case 1: k_step<double, 16, 16, true><<<L.nunits, 256, 0, s>>>(p, L.views, L.units, k_rel, par0); break;

@@ -38,7 +38,8 @@ class Info(C.Structure):
 
 
 class DeviceViews(C.Structure):
-    _fields_ = [("ux", C.c_void_p * 2), ("uy", C.c_void_p * 2), ("vx", C.c_void_p), ("vy", C.c_void_p)]
+    _fields_ = [("ux", C.c_void_p * 2), ("uy", C.c_void_p * 2), ("vx", C.c_void_p), ("vy", C.c_void_p),
+                ("n", C.c_int64)]
 
 
 EXPORTS = [
@@ -51,8 +52,11 @@ EXPORTS = [
     "mct_mlp_create", "mct_mlp_destroy", "mct_mlp_last_error", "mct_mlp_set_params", "mct_mlp_get_params",
     "mct_mlp_forward", "mct_mlp_gradient", "mct_mlp_train_step", "mct_get_energies", "mct_set_tracking",
     "mct_set_load_curve", "mct_set_mesh_tri", "mct_set_mesh_q4", "mct_set_front_pick",
-    "mct_set_smoothing", "mct_bind_device_buffers",
+    "mct_set_smoothing", "mct_bind_device_buffers", "mct_set_lattice", "mct_get_lattice",
+    "mct_set_near_log", "mct_get_near_log", "mct_profile_step",
 ]
+LATTICE_AUTO = 0
+LATTICE_GENERAL = 1
 N_FEATURES = 10
 N_PARAMS = 4929
 
@@ -101,6 +105,11 @@ def load() -> C.CDLL:
     L.mct_set_front_pick.argtypes = [P, C.c_double]
     L.mct_set_smoothing.argtypes = [P, C.c_int]
     L.mct_bind_device_buffers.argtypes = [P, C.POINTER(DeviceViews)]
+    L.mct_set_lattice.argtypes = [P, C.c_int]
+    L.mct_get_lattice.argtypes = [P, C.POINTER(C.c_int)]
+    L.mct_set_near_log.argtypes = [P, C.c_double, C.c_int64]
+    L.mct_profile_step.argtypes = [P, C.c_int64, dp]
+    L.mct_get_near_log.argtypes = [P, C.c_int64, P, P, P, P, P, P, P, C.POINTER(C.c_int64)]
     L.mct_finalize.argtypes = [P]
     L.mct_step.argtypes = [P, C.c_int64]
     L.mct_sync.argtypes = [P]
@@ -138,6 +147,36 @@ def load() -> C.CDLL:
 
 def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def device_views(arrs, n, n_nodes):
+    """Checked (addresses, length) of six caller-owned state arrays: distinct
+    contiguous float64 torch tensors on one GPU device, or raw device
+    addresses with an explicit length n; the length must cover n_nodes."""
+    if len(arrs) != 6 or any(a is None for a in arrs):
+        raise MctError("bind_device_buffers: all six arrays or none")
+    if all(isinstance(a, int) for a in arrs):
+        if n is None:
+            raise MctError("bind_device_buffers: raw addresses need the length n")
+        ptr, length = list(arrs), int(n)
+    else:
+        import torch
+        for a in arrs:
+            if not isinstance(a, torch.Tensor):
+                raise MctError("bind_device_buffers: torch tensors or raw addresses, not mixed")
+            if a.dtype != torch.float64 or not a.is_cuda or not a.is_contiguous():
+                raise MctError("bind_device_buffers: contiguous float64 device tensors are required")
+            if a.device != arrs[0].device:
+                raise MctError("bind_device_buffers: all tensors on one device")
+        ptr = [a.data_ptr() for a in arrs]
+        length = min(a.numel() for a in arrs)
+        if n is not None:
+            length = min(length, int(n))
+    if len(set(ptr)) != 6 or 0 in ptr:
+        raise MctError("bind_device_buffers: six distinct non-null arrays are required")
+    if length < max(int(n_nodes), 1):
+        raise MctError("bind_device_buffers: %d values per array, the mesh has %d nodes" % (length, n_nodes))
+    return ptr, length
 
 
 def _i32(a):
@@ -233,18 +272,22 @@ class Model:
         t, phi = _f64(t), _f64(phi)
         self._check(self._L.mct_set_load_curve(self._h, len(t), t, phi), "set_load_curve")
 
-    def bind_device_buffers(self, ux0, ux1, uy0, uy1, vx, vy):
-        """Caller-owned state arrays (torch float64 tensors on the device,
-        n_nodes each, or raw device addresses): u^k lives in (ux0, uy0) for
-        even k and (ux1, uy1) for odd k.  Call before finalize; the tensors
-        are kept referenced by this model.  None for every argument unbinds."""
+    def bind_device_buffers(self, ux0, ux1, uy0, uy1, vx, vy, n=None):
+        """Caller-owned state arrays: six distinct contiguous torch float64
+        tensors on this context's device (cuda:0 unless the caller's stream
+        says otherwise) with at least n_nodes elements each; u^k lives in
+        (ux0, uy0) for even k and (ux1, uy1) for odd k.  Call after the mesh
+        and before finalize (finalize checks the length against the mesh);
+        the tensors are kept referenced by this model.  None for every
+        argument unbinds.  Raw device addresses (ints) need the length n."""
         arrs = (ux0, ux1, uy0, uy1, vx, vy)
         if all(a is None for a in arrs):
             self._check(self._L.mct_bind_device_buffers(self._h, None), "bind_device_buffers")
             return
-        ptr = [a if isinstance(a, int) else a.data_ptr() for a in arrs]
+        ptr, length = device_views(arrs, n, self.info()["n_nodes"])
         v = DeviceViews()
         v.ux[0], v.ux[1], v.uy[0], v.uy[1], v.vx, v.vy = ptr
+        v.n = length
         self._check(self._L.mct_bind_device_buffers(self._h, C.byref(v)), "bind_device_buffers")
         self._keep.append(arrs)
 
@@ -252,6 +295,37 @@ class Model:
         """Q4 edge smoothing: "point" (default) or "subcell"."""
         m = {"point": 0, "subcell": 1}[mode]
         self._check(self._L.mct_set_smoothing(self._h, m), "set_smoothing")
+
+    def set_lattice(self, mode=LATTICE_AUTO):
+        """Uniform-lattice kernel: LATTICE_AUTO (when set-up finds one) or
+        LATTICE_GENERAL (never); acts at the next finalize."""
+        self._check(self._L.mct_set_lattice(self._h, int(mode)), "set_lattice")
+
+    def lattice(self) -> bool:
+        """True when the finalized context steps with the uniform-lattice kernel."""
+        u = C.c_int(0)
+        self._check(self._L.mct_get_lattice(self._h, C.byref(u)), "get_lattice")
+        return bool(u.value)
+
+    def set_near_log(self, tol, cap=1 << 20):
+        """Near-threshold decision log with relative tolerance tol (0: off),
+        up to cap records on the device; acts at the next finalize."""
+        self._check(self._L.mct_set_near_log(self._h, float(tol), int(cap)), "set_near_log")
+
+    def near_log(self) -> dict:
+        """Near-threshold decisions sorted by (step, kind, elem, a, k)."""
+        cnt = C.c_int64(0)
+        rc = self._L.mct_get_near_log(self._h, 0, None, None, None, None, None, None, None, C.byref(cnt))
+        if rc not in (MCT_OK, MCT_ECAPACITY):
+            self._check(rc, "get_near_log")
+        n = cnt.value
+        st, el = np.zeros(n, np.int32), np.zeros(n, np.int32)
+        a, kd, k = (np.zeros(n, np.uint8) for _ in range(3))
+        G, ref = np.zeros(n), np.zeros(n)
+        self._check(self._L.mct_get_near_log(self._h, n, st.ctypes.data, el.ctypes.data, a.ctypes.data,
+                                             kd.ctypes.data, k.ctypes.data, G.ctypes.data, ref.ctypes.data,
+                                             C.byref(cnt)), "get_near_log")
+        return dict(step=st, elem=el, a=a, kind=kd, k=k, G=G, ref=ref)
 
     def set_front_pick(self, rho):
         """Per-front pick with competition radius rho (m); 0 = the global pick."""
@@ -295,6 +369,14 @@ class Model:
 
     def sync(self):
         self._check(self._L.mct_sync(self._h), "sync")
+
+    def profile_step(self, n):
+        """Run n steps as direct launches with HIP events around every
+        launch; returns the mean duration per step (microseconds) of the
+        step kernel and of the pick/commit launches."""
+        out = np.zeros(2)
+        self._check(self._L.mct_profile_step(self._h, int(n), out), "profile_step")
+        return dict(step_us=float(out[0]), commit_us=float(out[1]))
 
     # -- queries --------------------------------------------------------
     def info(self) -> dict:
@@ -483,6 +565,8 @@ def _setup(m: Model, cfg: dict):
         m.set_front_pick(cfg["front_radius"])
     if cfg.get("smoothing"):
         m.set_smoothing(cfg["smoothing"])
+    if cfg.get("near_tol"):
+        m.set_near_log(cfg["near_tol"], cfg.get("near_cap", 1 << 20))
 
 
 def from_config(cfg: dict, stream: int | None = None, tile: int = 0, use_graph: bool = True) -> Model:
@@ -491,6 +575,8 @@ def from_config(cfg: dict, stream: int | None = None, tile: int = 0, use_graph: 
     binary32 step."""
     m = Model(int(cfg.get("precision", 64)), stream)
     _setup(m, cfg)
+    if cfg.get("lattice") == "general" and cfg.get("conn") is None:
+        m.set_lattice(LATTICE_GENERAL)
     m.set_launch(tile, use_graph)
     m.finalize()
     return m
@@ -505,6 +591,8 @@ def batch_from_configs(cfgs, stream: int | None = None, tile: int = 0, order: in
         m.select(s)
         _setup(m, cfg)
     m.select(0)
+    if any(c.get("lattice") == "general" for c in cfgs):
+        m.set_lattice(LATTICE_GENERAL)
     m.set_launch(tile, use_graph)
     m.set_order(order)
     m.finalize()

@@ -213,10 +213,18 @@ def fragmentation(nx, ny, h, *, v=5.0, seed=BASE_SEED + 3, steps=10000,
                 dt=0.0, cfl=0.5, steps=steps)
 
 
+# Element side of the workloads whose size the set-up leaves open: binary
+# fractions of a metre close to 0.1 mm and 1 mm, so that every node
+# coordinate i h is exact and every element of the lattice has bitwise the
+# same geometry.
+H_FRAGMENT = 2.0 ** -13   # 0.1220703125 mm
+H_BATCH = 2.0 ** -10      # 0.9765625 mm
+
+
 def config3(steps=10000):
-    """2000x1000 Q4 mesh (h = 0.1 mm), 5 m/s outward on all edges,
-    Weibull(6, 3 N/m) Gc, no notch."""
-    return fragmentation(2000, 1000, 1.0e-4, steps=steps, name="fragment2000x1000")
+    """2000x1000 Q4 mesh (h = 2^-13 m, 0.122 mm: a 244 x 122 mm plate), 5 m/s
+    outward on all edges, Weibull(6, 3 N/m) Gc, no notch."""
+    return fragmentation(2000, 1000, H_FRAGMENT, steps=steps, name="fragment2000x1000")
 
 
 # Small cases that the oracle finishes in seconds; they span several GPU
@@ -235,15 +243,15 @@ def small_cases():
 
 
 def batch_specimens(n=256, *, seed=BASE_SEED + 4, steps=5000, nx_range=(64, 512),
-                    ny_range=(64, 256), h=1.0e-3):
+                    ny_range=(64, 256), h=H_BATCH):
     """Independent notched specimens of uneven size (the batched workload).
 
     Specimen s takes five uniforms u0..u4 from one SplitMix64 stream (seed,
     specimen order): nx = U{nx_range}, ny = U{ny_range}, notch length
     round(U(0.2, 0.6) nx) in row ny // 2, Weibull scale lambda = U(2, 4) N/m,
     traction U(0.5, 1.5) MPa; its Gc field uses the stream seed + 1000 (s+1)
-    (Weibull shape 6).  Square elements of side h, so all share one time
-    step."""
+    (Weibull shape 6).  Square elements of side h (2^-10 m by default), so
+    all share one time step."""
     u = uniform01(seed, 5 * n).reshape(n, 5)
     out = []
     for s in range(n):

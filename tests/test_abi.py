@@ -62,3 +62,30 @@ def test_workload_generators_are_seeded_and_shaped():
     assert g.mean() == pytest.approx(3.0 * 0.9277193336, rel=5e-3)
     # SplitMix64 reference value (seed 0, first output)
     assert int(W.splitmix64(0, 1)[0]) == 0xE220A8397B1DCDAF
+
+
+def test_device_views_refuse_bad_arrays():
+    """Caller-owned state arrays are checked before the library sees them:
+    CPU, wrong-dtype, strided, short or aliased tensors, mixed kinds and raw
+    addresses without a length are refused."""
+    import torch
+    nn = 50
+    ok = [torch.zeros(nn, dtype=torch.float64) for _ in range(6)]
+    with pytest.raises(mct2d.MctError, match="device tensors"):
+        mct2d.device_views(ok, None, nn)  # host tensors
+    with pytest.raises(mct2d.MctError, match="six arrays"):
+        mct2d.device_views(ok[:5] + [None], None, nn)
+    with pytest.raises(mct2d.MctError, match="length n"):
+        mct2d.device_views([1, 2, 3, 4, 5, 6], None, nn)
+    with pytest.raises(mct2d.MctError, match="distinct"):
+        mct2d.device_views([8, 8, 16, 24, 32, 40], nn, nn)
+    with pytest.raises(mct2d.MctError, match="non-null"):
+        mct2d.device_views([0, 8, 16, 24, 32, 40], nn, nn)
+    with pytest.raises(mct2d.MctError, match="nodes"):
+        mct2d.device_views([8, 16, 24, 32, 40, 48], nn - 1, nn)
+    with pytest.raises(mct2d.MctError, match="not mixed"):
+        mct2d.device_views([8, 16, 24, 32, 40, ok[0]], nn, nn)
+    ptr, length = mct2d.device_views([8, 16, 24, 32, 40, 48], nn + 3, nn)
+    assert ptr == [8, 16, 24, 32, 40, 48] and length == nn + 3
+    # the C side checks the same at finalize against the mesh (GPU tests)
+    assert "int64_t n;" in open(HEADER).read()

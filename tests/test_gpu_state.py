@@ -182,6 +182,31 @@ def test_bound_device_buffers(gpu):
     assert np.array_equal(t[4].cpu().numpy(), vx) and np.array_equal(t[5].cpu().numpy(), vy)
     m.close()
     assert np.array_equal(t[1].cpu().numpy(), ux)  # the caller's arrays outlive the model
+    # the library checks the arrays' length against the mesh at finalize, and
+    # a new mesh unbinds them
+    import ctypes
+    v = gpu.DeviceViews()
+    v.ux[0], v.ux[1], v.uy[0], v.uy[1], v.vx, v.vy = [x.data_ptr() for x in t]
+    v.n = nn - 1
+    m2 = gpu.Model()
+    gpu._setup(m2, cfg)
+    assert m2._L.mct_bind_device_buffers(m2._h, ctypes.byref(v)) == 0
+    assert m2._L.mct_finalize(m2._h) == -1
+    assert b"nodes" in m2._L.mct_last_error(m2._h)
+    v.n = nn
+    v.vy = v.vx
+    assert m2._L.mct_bind_device_buffers(m2._h, ctypes.byref(v)) == -1  # aliased arrays
+    m3 = gpu.Model()
+    gpu._setup(m3, cfg)
+    m3.bind_device_buffers(*t)
+    t[0].fill_(5.0)
+    torch.cuda.synchronize()
+    m3.set_mesh_grid(cfg["nx"], cfg["ny"], cfg["X"], cfg["Y"])
+    gpu._setup(m3, cfg)
+    m3.finalize()
+    m3.step(3)
+    m3.sync()
+    assert float(t[0].min()) == 5.0  # unbound by the new mesh: the library's own arrays ran
     f32 = gpu.Model(precision=32)
     f32.set_mesh_grid(cfg["nx"], cfg["ny"], cfg["X"], cfg["Y"])
     with pytest.raises(gpu.MctError):
