@@ -452,8 +452,20 @@ int mct_get_launch(mct_ctx *ctx, int *tile, int *order, int64_t *workgroups);
  * candidates of Sec. 2.2 evaluated) and then a small MLP scores every
  * candidate (f, a); until the next such step, G is evaluated only for the
  * candidates scored above tau and for candidates that appeared since.  The
- * MCT pick (Sec. 3) stays the same over the evaluated set, so a screened run
- * equals the plain run as long as no skipped candidate would have won.
+ * MCT pick (Sec. 3) stays the same over the evaluated set.
+ *
+ * The exact G is the judge: each window of screened steps (a period, or
+ * its part up to the next exact step) starts from a snapshot of the state,
+ * and every skipped candidate is bounded at every screened step, by
+ * |delta| max_k |sigma_k|_F / 2 >= |G_k| (Frobenius norm of the three path
+ * edges' stresses; open stretch gate only).  When a bound reaches Gc the
+ * skipped candidate might have been accepted, so the window is restored and
+ * replayed with the plain step.  Otherwise no skipped candidate can pass the
+ * element rule, the accepted sets and picks are the plain step's, and the
+ * window equals the plain run.  So a screened run equals the plain run bit
+ * for bit whatever the screen flags; a poor screen costs replays.  Each
+ * window ends with a synchronisation of the context's stream (the replay
+ * decision is taken on the host).
  *
  * Features of a candidate, in order (h = sqrt(A_f), sigma_ref =
  * sqrt(E Gc_f / h), sigma = mean of the four smoothed edge stresses of f):
@@ -498,8 +510,9 @@ int mct_screen_disable(mct_ctx *ctx);
 /* Counters since the screen buffers were created: [0] exact steps followed
  * by a screen evaluation, [1] candidates at those steps, [2] candidates
  * flagged, [3] misses: candidates skipped by the previous screen whose
- * max G / Gc exceeds 1 at an exact step. */
-int mct_screen_stats(mct_ctx *ctx, int64_t out[4]);
+ * max G / Gc exceeds 1 at an exact step, [4] windows judged, [5] windows
+ * replayed with the plain step (a skipped candidate's bound reached Gc). */
+int mct_screen_stats(mct_ctx *ctx, int64_t out[6]);
 
 /* MLP handle with its own HIP stream (NULL = library-created).  Parameters
  * start at zero.  set_params copies 4 929 host floats and resets the Adam

@@ -156,6 +156,7 @@ struct mct_ctx {
     mct::MlpDev smlp{};                             // weights in use (no Adam state)
     hipGraphExec_t sgraph[2] = {nullptr, nullptr};  // one screened period, by parity
     int sgraph_tile[2] = {0, 0};
+    int64_t screen_windows = 0, screen_replays = 0;  // judged windows, replayed ones
 };
 
 struct mct_mlp {
@@ -259,6 +260,10 @@ void free_screen(mct_ctx *c) {
     dfree(s.nfront);
     dfree(s.front_xy);
     dfree(s.stats);
+    dfree(s.trip);
+    dfree(s.snap_u);
+    dfree(s.snap_split);
+    dfree(s.snap_ctl);
     free_mlp(c->smlp);
     c->screen_alloc = false;
     c->screen_on = false;
@@ -616,7 +621,11 @@ int ensure_screen(mct_ctx *c) {
     HIP_TRY(c, hipMalloc((void **)&s.screen, sizeof(uint32_t) * ne));
     HIP_TRY(c, hipMalloc((void **)&s.nfront, sizeof(int32_t)));
     HIP_TRY(c, hipMalloc((void **)&s.front_xy, sizeof(double) * 4 * ne));
-    HIP_TRY(c, hipMalloc((void **)&s.stats, sizeof(unsigned long long) * 4));
+    HIP_TRY(c, hipMalloc((void **)&s.stats, sizeof(unsigned long long) * mct::kNumScreenStats));
+    HIP_TRY(c, hipMalloc((void **)&s.trip, sizeof(uint32_t)));
+    HIP_TRY(c, hipMalloc((void **)&s.snap_u, sizeof(double) * 4 * (size_t)sp.nn));
+    HIP_TRY(c, hipMalloc((void **)&s.snap_split, (size_t)std::max<int64_t>(ne, 1)));
+    HIP_TRY(c, hipMalloc((void **)&s.snap_ctl, sizeof(Control)));
     // no evaluation yet: history stamps never match, every candidate unseen
     HIP_TRY(c, mct::launch_fill_u32(reinterpret_cast<uint32_t *>(s.hist_t), nc, 0xFFFFFFFEu, c->stream));
     HIP_TRY(c, hipMemsetAsync(s.sweep, 0, sizeof(int32_t), c->stream));
@@ -624,7 +633,9 @@ int ensure_screen(mct_ctx *c) {
     HIP_TRY(c, hipMemsetAsync(s.nrows_last, 0, sizeof(int32_t), c->stream));
     HIP_TRY(c, hipMemsetAsync(s.nfront, 0, sizeof(int32_t), c->stream));
     HIP_TRY(c, hipMemsetAsync(s.screen, 0, sizeof(uint32_t) * ne, c->stream));
-    HIP_TRY(c, hipMemsetAsync(s.stats, 0, sizeof(unsigned long long) * 4, c->stream));
+    HIP_TRY(c, hipMemsetAsync(s.stats, 0, sizeof(unsigned long long) * mct::kNumScreenStats, c->stream));
+    HIP_TRY(c, hipMemsetAsync(s.trip, 0, sizeof(uint32_t), c->stream));
+    c->screen_windows = c->screen_replays = 0;
     int rc = alloc_mlp(c, c->smlp, false);
     if (rc) return rc;
     c->screen_alloc = true;
@@ -651,6 +662,7 @@ hipError_t screen_pipeline(mct_ctx *c, int par, hipStream_t st) {
 hipError_t screened_steps(mct_ctx *c, int64_t k0, int first, int count, int par0, hipStream_t st) {
     mct::Launch Lp = launch_of(c), Ls = launch_of(c);
     Ls.p0.screen = c->sd.screen;
+    Ls.p0.strip = c->sd.trip;
     hipError_t e = hipSuccess;
     for (int i = first; e == hipSuccess && i < first + count; ++i) {
         if ((k0 + i) % c->screen_period == 0) {
@@ -682,26 +694,45 @@ int build_screen_graph(mct_ctx *c, int par0) {
     return MCT_OK;
 }
 
+// Screened stepping, one window at a time (a period from its exact step,
+// or the part of one up to the next exact step).  Each window starts from a
+// snapshot of the state; its screened steps bound every candidate the screen
+// skips, and when a bound reaches Gc (the skipped candidate might have been
+// accepted: the window might differ from the plain step) the window is
+// restored and replayed with the plain step.  Otherwise no skipped candidate
+// could pass the element rule, so the accepted sets, the picks and the whole
+// window equal the plain step's.  Either way the run equals the plain run.
+// (The screen evaluation after a window's exact step is kept on a replay: it
+// ran on the state after that step, which the replay reproduces.)
 int step_screened(mct_ctx *c, int64_t n) {
     const int P = c->screen_period;
+    const mct::StepParams &p = c->specs[0].prm;
     int64_t left = n;
     while (left > 0) {
         const int64_t k0 = c->steps_enqueued;
         const int par0 = (int)(k0 & 1);
         const int q = (int)(k0 % P);
-        if (q == 0 && left >= P && c->use_graph) {
+        const int seg = (q == 0 && left >= P) ? P : (int)std::min<int64_t>(left, P - q);
+        HIP_TRY(c, mct::launch_snapshot(p, c->sd, par0, true, c->stream));
+        if (q == 0 && seg == P && c->use_graph) {
             if (!c->sgraph[par0] || c->sgraph_tile[par0] != c->tile) {
                 int rc = build_screen_graph(c, par0);
                 if (rc) return rc;
             }
             HIP_TRY(c, hipGraphLaunch(c->sgraph[par0], c->stream));
-            left -= P;
-            c->steps_enqueued += P;
-            continue;
+        } else {
+            HIP_TRY(c, screened_steps(c, k0, 0, seg, par0, c->stream));
+            HIP_TRY(c, mct::launch_commit(launch_of(c), seg, c->stream));
         }
-        const int seg = (int)std::min<int64_t>(left, P - q);  // up to the next sweep
-        HIP_TRY(c, screened_steps(c, k0, 0, seg, par0, c->stream));
-        HIP_TRY(c, mct::launch_commit(launch_of(c), seg, c->stream));
+        uint32_t trip = 0;
+        HIP_TRY(c, hipMemcpyAsync(&trip, c->sd.trip, sizeof trip, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        c->screen_windows++;
+        if (trip) {
+            HIP_TRY(c, mct::launch_snapshot(p, c->sd, par0, false, c->stream));
+            HIP_TRY(c, enqueue_segment(c, launch_of(c), seg, par0, c->stream));
+            c->screen_replays++;
+        }
         left -= seg;
         c->steps_enqueued += seg;
     }
@@ -1170,6 +1201,8 @@ int mct_set_near_log(mct_ctx *c, double tol, int64_t cap) {
     if (c->batch) return fail(c, MCT_EUNSUPPORTED, "the near-threshold log needs a plain context");
     if (!(tol >= 0.0) || !(tol < 1.0)) return fail(c, MCT_EINVAL, "tolerance %g outside [0, 1)", tol);
     if (tol > 0.0 && (cap < 1 || cap > (int64_t)1 << 30)) return fail(c, MCT_EINVAL, "capacity %lld", (long long)cap);
+    if (tol > 0.0 && c->screen_on)
+        return fail(c, MCT_EUNSUPPORTED, "the near-threshold log with the split-screen");
     c->near_tol = tol;
     c->near_cap = tol > 0.0 ? cap : 0;
     if (c->finalized) release_device(c);  // takes effect at the next finalize
@@ -2151,6 +2184,7 @@ int mct_screen_enable(mct_ctx *c, const mct_mlp *mlp, float tau, int period) {
     if (!c->batch && cur(c).front_rho > 0) return fail(c, MCT_EUNSUPPORTED, "the split-screen with the per-front pick");
     if (!c->batch && cur(c).subcell) return fail(c, MCT_EUNSUPPORTED, "the split-screen with sub-cell smoothing");
     if (period < 2) return fail(c, MCT_EINVAL, "period must be at least 2");
+    if (c->near_tol > 0.0) return fail(c, MCT_EUNSUPPORTED, "the split-screen with the near-threshold log");
     int rc = ensure_screen(c);
     if (rc) return rc;
     HIP_TRY(c, hipStreamSynchronize(mlp->stream));
@@ -2172,14 +2206,16 @@ int mct_screen_disable(mct_ctx *c) {
     return MCT_OK;
 }
 
-int mct_screen_stats(mct_ctx *c, int64_t out[4]) {
+int mct_screen_stats(mct_ctx *c, int64_t out[6]) {
     if (!c || !out) return MCT_EINVAL;
-    for (int i = 0; i < 4; ++i) out[i] = 0;
+    for (int i = 0; i < mct::kNumScreenStats; ++i) out[i] = 0;
     if (!c->screen_alloc) return MCT_OK;
     unsigned long long h[4];
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     HIP_TRY(c, hipMemcpy(h, c->sd.stats, sizeof h, hipMemcpyDeviceToHost));
     for (int i = 0; i < 4; ++i) out[i] = (int64_t)h[i];
+    out[mct::kStatWindows] = c->screen_windows;
+    out[mct::kStatReplays] = c->screen_replays;
     return MCT_OK;
 }
 

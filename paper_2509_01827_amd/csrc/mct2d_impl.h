@@ -96,6 +96,7 @@ struct StepParamsT {
     uint8_t *split;
     const T *area;  // per element (reference configuration)
     const uint32_t *screen;  // per element, byte a = screen state of candidate (e, a); null = no screen
+    uint32_t *strip;         // screened steps: set to 1 when a skipped candidate might pass Gc
     int32_t sct;             // 1: single crack-tip tracking (only the tip is a candidate)
     int32_t ncurve;          // traction load curve points (0: constant tractions)
     const double *curve_t, *curve_phi;
@@ -221,7 +222,9 @@ static_assert(kOffB3 + 1 == kParams, "parameter layout");
 // screen state byte of a candidate: not seen at the last evaluation
 // (evaluated), flagged (evaluated), or screened out (skipped)
 constexpr uint8_t kScreenUnseen = 0, kScreenFlagged = 1, kScreenSkip = 2;
-enum ScreenStat { kStatSweeps = 0, kStatCands = 1, kStatFlagged = 2, kStatMisses = 3 };
+enum ScreenStat { kStatSweeps = 0, kStatCands = 1, kStatFlagged = 2, kStatMisses = 3, kStatWindows = 4,
+                  kStatReplays = 5 };
+constexpr int kNumScreenStats = 6;
 
 // Device MLP: FP32 master parameters, Adam moments, bfloat16 weight copies
 // (W1 padded to 32 input rows with zeros).
@@ -247,7 +250,18 @@ struct ScreenDev {
     int32_t *nfront;        // crack-path ends of the running evaluation
     double *front_xy;       // their midpoints (capacity 2 ne)
     unsigned long long *stats;  // ScreenStat counters
+    // the judge of a screened window: its trip flag, and the snapshot of the
+    // state at the window's start (u^k, v, split codes, control block)
+    uint32_t *trip;
+    double *snap_u;      // 4 nn: ux, uy of u^k, then vx, vy
+    uint8_t *snap_split; // ne
+    Control *snap_ctl;
 };
+
+// Copy the state of a model (u^k from buffer par, v, split codes, control
+// block) into the screen's snapshot (save) or back (restore), and clear the
+// trip flag (save).
+hipError_t launch_snapshot(const StepParams &p, const ScreenDev &s, int par, bool save, hipStream_t st);
 
 hipError_t launch_screen_evaluate(const StepParams &p, const ScreenDev &s, int par, hipStream_t st);
 hipError_t launch_sweep_advance(const ScreenDev &s, hipStream_t st);

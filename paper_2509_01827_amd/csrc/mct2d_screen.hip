@@ -658,6 +658,47 @@ hipError_t launch_sweep_advance(const ScreenDev &s, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Snapshot of a screened window's starting state: u^k (buffer par), v, the
+// split codes and the control block, saved to or restored from the screen's
+// buffers by one grid-stride copy; saving also clears the trip flag.
+__global__ __launch_bounds__(kBlk) void k_snapshot(StepParams p, ScreenDev s, int par, int save) {
+    const int64_t nn = (int64_t)(p.nx + 1) * (p.ny + 1), ne = (int64_t)p.nx * p.ny;
+    double *ux = par ? p.ux1 : p.ux0, *uy = par ? p.uy1 : p.uy0;
+    double *live[4] = {ux, uy, p.vx, p.vy};
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 4 * nn + ne + 1; i += stride) {
+        if (i < 4 * nn) {
+            const int q = (int)(i / nn);
+            const int64_t n = i - q * nn;
+            if (save)
+                s.snap_u[i] = live[q][n];
+            else
+                live[q][n] = s.snap_u[i];
+        } else if (i < 4 * nn + ne) {
+            const int64_t e = i - 4 * nn;
+            if (save)
+                s.snap_split[e] = p.split[e];
+            else
+                p.split[e] = s.snap_split[e];
+        } else {
+            if (save) {
+                *s.snap_ctl = *p.ctl;
+                *s.trip = 0u;
+            } else {
+                *p.ctl = *s.snap_ctl;
+            }
+        }
+    }
+}
+
+hipError_t launch_snapshot(const StepParams &p, const ScreenDev &s, int par, bool save, hipStream_t st) {
+    (void)hipGetLastError();
+    const int64_t n = 4 * (int64_t)(p.nx + 1) * (p.ny + 1) + (int64_t)p.nx * p.ny + 1;
+    const int64_t nb = std::min<int64_t>((n + kBlk - 1) / kBlk, 8192);
+    k_snapshot<<<(int)nb, kBlk, 0, st>>>(p, s, par, save ? 1 : 0);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_u32(uint32_t *a, int64_t n, uint32_t v, hipStream_t st) {
     (void)hipGetLastError();
     const int64_t nb = std::min<int64_t>((n + kBlk - 1) / kBlk, 4096);

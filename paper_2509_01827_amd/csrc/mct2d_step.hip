@@ -162,7 +162,7 @@ __device__ __forceinline__ void load_view(StepParamsT<T> &p, const StepParamsT<T
     p.nwg = s->nwg; p.log_cap = s->log_cap; p.X = s->X; p.Y = s->Y;
     p.ux0 = s->ux0; p.uy0 = s->uy0; p.ux1 = s->ux1; p.uy1 = s->uy1;
     p.vx = s->vx; p.vy = s->vy; p.minv = s->minv; p.split = s->split;
-    p.area = s->area; p.screen = s->screen; p.sct = s->sct; p.ncurve = s->ncurve;
+    p.area = s->area; p.screen = s->screen; p.strip = s->strip; p.sct = s->sct; p.ncurve = s->ncurve;
     p.curve_t = s->curve_t; p.curve_phi = s->curve_phi; p.gc = s->gc; p.gc_uniform = s->gc_uniform;
     p.fext_p = s->fext_p; p.vmask_p = s->vmask_p; p.v0_p = s->v0_p; p.D11 = s->D11;
     p.D12 = s->D12; p.D33 = s->D33; p.E = s->E; p.dt = s->dt;
@@ -898,18 +898,28 @@ __global__ __launch_bounds__(TXE *TYE, UNI ? 6 : 4) void k_step(StepParamsT<T> p
 
     // free-surface candidates of the elements this tile owns (node n0 owned),
     // compacted with wavefront ballots into s_cand
+    // A screened step lists the candidates the screen skips too (smask):
+    // they are not evaluated, only bounded (the judge below).
     const bool owned = ie >= 1 && je >= 1 && code == 0;
-    unsigned fmask = 0;
+    unsigned fmask = 0, smask = 0;
     if (owned) {
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            if (s_split[nbr(e2, k)] != 0 && ((scr >> (8 * k)) & 0xFFu) != kScreenSkip) fmask |= 1u << k;
+            if (s_split[nbr(e2, k)] != 0) {
+                if (((scr >> (8 * k)) & 0xFFu) != kScreenSkip)
+                    fmask |= 1u << k;
+                else
+                    smask |= 1u << k;
+            }
         if (p.sct) {  // single-tip mode: the tip is the only candidate
             const int32_t tip = s_tip;
             const int64_t ge = (int64_t)(j0 - 1 + je) * nx + (i0 - 1 + ie);
             fmask = (tip >= 0 && (tip >> 2) == ge) ? (fmask & (1u << (tip & 3))) : 0u;
+            smask = 0;
         }
+        if (!p.strip) smask = 0;
     }
+    const unsigned cmask = fmask | smask;
     // split elements of the ring, listed by kind: a path between adjacent
     // edges leaves a 3-node piece (constant-strain triangle) and a 1-node
     // piece; a path between opposite edges leaves two 2-node pieces (bars).
@@ -924,7 +934,7 @@ __global__ __launch_bounds__(TXE *TYE, UNI ? 6 : 4) void k_step(StepParamsT<T> p
         int wtotal = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            bal[k] = __ballot((fmask >> k) & 1u);
+            bal[k] = __ballot((cmask >> k) & 1u);
             wtotal += __popcll(bal[k]);
         }
         const uint64_t bco = __ballot(is_corner), bth = __ballot(is_thru);
@@ -934,11 +944,12 @@ __global__ __launch_bounds__(TXE *TYE, UNI ? 6 : 4) void k_step(StepParamsT<T> p
         __syncthreads();
         if (is_corner) s_splitl[s_wbase2[wave] + __popcll(bco & lt)] = (uint16_t)tid;
         if (is_thru) s_splitl[NT - 1 - (s_wbase3[wave] + __popcll(bth & lt))] = (uint16_t)tid;
-        if (fmask) {
+        if (cmask) {
             int off = s_wbase[wave];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                if ((fmask >> k) & 1u) s_cand[off + __popcll(bal[k] & lt)] = (uint16_t)((tid << 2) | k);
+                if ((cmask >> k) & 1u)
+                    s_cand[off + __popcll(bal[k] & lt)] = (uint16_t)((tid << 2) | k | (((smask >> k) & 1u) << 15));
                 off += __popcll(bal[k]);
             }
         }
@@ -956,13 +967,15 @@ __global__ __launch_bounds__(TXE *TYE, UNI ? 6 : 4) void k_step(StepParamsT<T> p
     for (int c0 = 0; c0 < ncand; c0 += NT / 4) {  // same trip count in every lane
         const int c = c0 + (tid >> 2), j = tid & 3;
         const bool live = c < ncand;
-        T Gj = T(0), gc = T(0);
-        bool H = false;
+        T Gj = T(0), gc = T(0), d2 = T(0);
+        bool H = false, skipped = false;
         int a = 0;
         int64_t ge = 0;
         if (live) {
-            const int t = s_cand[c] >> 2;
-            a = s_cand[c] & 3;
+            const unsigned ent = s_cand[c];
+            skipped = (ent >> 15) != 0u;
+            const int t = (int)(ent & 0x7FFFu) >> 2;
+            a = (int)(ent & 3u);
             const int cie = t % TXE, cje = t / TXE;
             ge = (int64_t)(j0 - 1 + cje) * nx + (i0 - 1 + cie);
             gc = p.gc ? p.gc[ge] : p.gc_uniform;
@@ -978,7 +991,14 @@ __global__ __launch_bounds__(TXE *TYE, UNI ? 6 : 4) void k_step(StepParamsT<T> p
             const T lx = x2 - x1, ly = y2 - y1;
             const T Lx = X2 - X1, Ly = Y2 - Y1;
             H = (lx * lx + ly * ly) > (Lx * Lx + Ly * Ly);  // else G = 0 on all three paths
-            if (H && j < 3) {
+            if (skipped && H && j < 3) {
+                // |G_k| = |delta . sigma_k n_k| / 2 <= |delta| |sigma_k|_F / 2: lane j
+                // holds |sigma_k|_F^2 of its path's edge stress
+                T sg[3];
+                edge_sigma(edge_slot(cie, cje, (a + 1 + j) & 3), sg);
+                Gj = fmat(T(2) * sg[2], sg[2], fmat(sg[1], sg[1], sg[0] * sg[0]));
+                d2 = fmat(duy, duy, dux * dux);
+            } else if (H && j < 3) {
                 const int k = (a + 1 + j) & 3;
                 T sg[3], nxv, nyv, len;
                 edge_sigma(edge_slot(cie, cje, k), sg);
@@ -999,7 +1019,15 @@ __global__ __launch_bounds__(TXE *TYE, UNI ? 6 : 4) void k_step(StepParamsT<T> p
         const int qb = tid & 60;  // lane of j = 0 in this quad
         const T G1 = __shfl(Gj, qb + 1, 64);
         const T G2 = __shfl(Gj, qb + 2, 64);
-        if (live && H && j == 0) {
+        if (live && H && j == 0 && skipped) {
+            // the judge of a screened window: a skipped candidate whose bound
+            // (|delta| max_k |sigma_k|_F / 2, compared squared, with a margin
+            // of 1e-9 for rounding) reaches Gc might have been accepted, so the
+            // window is replayed with the plain step
+            const T f2 = G1 > G2 ? (G1 > Gj ? G1 : Gj) : (G2 > Gj ? G2 : Gj);
+            if (T(0.25) * d2 * f2 > gc * gc * T(1.0 - 1e-9)) atomicOr(p.strip, 1u);
+        }
+        if (live && H && j == 0 && !skipped) {
             const T Gv[3] = {Gj, G1, G2};
             if constexpr (NEAR) near_candidate(p, base + k_rel, ge, a, Gv, gc);
             int jb = -1;

@@ -473,9 +473,10 @@ class Model:
         self._check(self._L.mct_screen_disable(self._h), "screen_disable")
 
     def screen_stats(self) -> dict:
-        out = np.zeros(4, np.int64)
+        out = np.zeros(6, np.int64)
         self._check(self._L.mct_screen_stats(self._h, out.ctypes.data), "screen_stats")
-        return dict(sweeps=int(out[0]), candidates=int(out[1]), flagged=int(out[2]), misses=int(out[3]))
+        return dict(sweeps=int(out[0]), candidates=int(out[1]), flagged=int(out[2]), misses=int(out[3]),
+                    windows=int(out[4]), replays=int(out[5]))
 
 
 class Mlp:

@@ -176,22 +176,88 @@ def test_screen_flag_all_equals_plain(env):
             assert st["misses"] == 0
 
 
-def test_screen_flag_none_skips_and_counts(env):
+def test_screen_flag_none_equals_plain_through_replays(env):
+    """A screen that flags nothing skips every old candidate: the judge must
+    catch every window where a skipped candidate might have split and replay
+    it with the plain step, so the run still equals the plain run bit for
+    bit (graph and direct launches), with replays counted."""
     torch, mct2d, S = env
     cfg = W.small_cases()["plate70x37_jitter"]
     steps = 700
+    plain = _run(mct2d, cfg, steps)
     p = np.zeros(S.N_PARAMS, np.float32)
     p[-1] = -50.0
     mlp = mct2d.Mlp()
     mlp.set_params(p)
     a = _run(mct2d, cfg, steps, mlp, tau=0.0, period=50, use_graph=True)
     b = _run(mct2d, cfg, steps, mlp, tau=0.0, period=50, use_graph=False)
-    assert _same_run(a, b)  # screened runs are deterministic across launch modes
     st = a.screen_stats()
     print(st, flush=True)
     assert st["flagged"] == 0 and st["candidates"] > 0 and st["sweeps"] == 14
-    # splits still happen at the exact steps (and from newly created candidates)
-    assert len(a.crack_set()["elem"]) > 0
+    assert st["windows"] == 14 and 0 < st["replays"] <= st["windows"]
+    assert len(plain.crack_set()["elem"]) > 0
+    assert _same_run(plain, a) and _same_run(plain, b)
+    assert b.screen_stats()["replays"] == st["replays"]
+
+
+def test_screen_partial_windows_equal_plain(env):
+    """Step counts that cut periods (partial windows, direct launches) with a
+    screen flagging nothing: still the plain run."""
+    torch, mct2d, S = env
+    cfg = W.small_cases()["fragment97x45"]
+    plain = _run(mct2d, cfg, 330)
+    p = np.zeros(S.N_PARAMS, np.float32)
+    p[-1] = -50.0
+    mlp = mct2d.Mlp()
+    mlp.set_params(p)
+    m = mct2d.from_config(cfg)
+    m.screen_enable(mlp, 0.0, 40)
+    for n in (17, 1, 100, 52, 160):
+        m.step(n)
+    m.sync()
+    st = m.screen_stats()
+    print(st, flush=True)
+    assert st["replays"] > 0
+    assert _same_run(plain, m)
+
+
+def test_trained_screen_on_the_benchmark_plate():
+    """The shipped screen parameters on the 400 x 400 plate (a seed in no
+    training run), the full 20 000 steps: identical to the oracle's stored
+    run (tests/golden/plate400.json) bit for bit, through its replays."""
+    import hashlib
+    import json
+    import os
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2509_01827_amd import mct2d
+    here = os.path.dirname(os.path.abspath(__file__))
+    ref = json.load(open(os.path.join(here, "golden", "plate400.json")))
+    with open(os.path.join(os.path.dirname(here), "paper_2509_01827_amd", "screen_weights.json")) as f:
+        sw = json.load(f)
+    mlp = mct2d.Mlp()
+    mlp.set_params(np.asarray(sw["params"], np.float32))
+    cfg = W.config2()
+    m = mct2d.from_config(cfg)
+    m.screen_enable(mlp, sw["tau"], sw["period"])
+    m.step(cfg["steps"])
+    m.sync()
+    st = m.screen_stats()
+    print("trained screen", st, flush=True)
+    lg = m.crack_set()
+    assert len(lg["elem"]) == ref["n_splits"]
+    h = hashlib.sha256()
+    for k in ("step", "elem", "entry", "exit"):
+        h.update(np.ascontiguousarray(lg[k].astype("<i8")).tobytes())
+    h.update(np.ascontiguousarray(lg["G"].astype("<f8")).tobytes())
+    assert h.hexdigest() == ref["log_digest"]
+    assert hashlib.sha256(m.split_codes().tobytes()).hexdigest() == ref["codes_digest"]
+    nodes = np.asarray(ref["nodes"])
+    ux, uy = m.field(0)
+    assert np.array_equal(ux[nodes], [float.fromhex(x) for x in ref["ux"]])
+    assert st["windows"] == cfg["steps"] // sw["period"]
+    assert st["flagged"] < st["candidates"]  # the screen skips candidates
 
 
 def test_screen_invalid_uses(env):
