@@ -308,6 +308,23 @@ int mct_get_crack_set(mct_ctx *ctx, int64_t cap, int32_t *step, int32_t *elem, u
  * id; xy = reference midpoint (2 per tip).  Computed on the GPU. */
 int mct_get_tips(mct_ctx *ctx, int64_t cap, int32_t *edge, double *xy, int64_t *count);
 
+/* The tip query for callers that cannot allocate device memory -- code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc -- with device outputs: the same crack-surface tips as
+ * mct_get_tips (ascending edge id; reference midpoints), written to the
+ * caller's device arrays edge_dev (cap int32) and xy_dev (2 cap doubles),
+ * and their number to the device int32 *count_dev (when it exceeds cap only
+ * the first cap are written).  Asynchronous on the context's stream: no
+ * host synchronisation, no hipMalloc/hipFree.  Its block counts live in a
+ * static device array of 2^16 int32 per GPU (256 KiB: meshes of up to
+ * 2^24 edges; larger ones give MCT_EINVAL), held until the process ends and
+ * shared by every call on that GPU: calls that overlap on one GPU (several
+ * streams or threads) race.  The context's device must be current
+ * (MCT_EDEVICE otherwise).  Structured grids (MCT_EUNSUPPORTED otherwise);
+ * MCT_ESTATE before mct_finalize; MCT_EINVAL for a null count, a negative
+ * cap, or null arrays with cap > 0. */
+int mct_get_tips_noalloc(mct_ctx *ctx, int64_t cap, int32_t *edge_dev, double *xy_dev, int32_t *count_dev);
+
 /* Field of the current step k (evaluated on the GPU from u^k):
  *   MCT_FIELD_U          u^k, [x of all nodes, y of all nodes] (2 n_nodes);
  *   MCT_FIELD_V          v^{k-1/2} (v^0 at k = 0), same layout;

@@ -1748,7 +1748,7 @@ int mct_get_tips(mct_ctx *c, int64_t cap, int32_t *edge, double *xy, int64_t *co
     const Spec &s = cur(c);
     int32_t nb = 0, total = 0;
     HIP_TRY(c, mct::launch_tips(s.nx, s.ny, s.prm.X, s.prm.Y, s.prm.split, c->dtip_counts, &nb, nullptr, nullptr,
-                                c->dtip_total, c->stream));
+                                c->dtip_total, 0, c->stream));
     HIP_TRY(c, hipMemcpyAsync(&total, c->dtip_total, sizeof total, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     *count = total;
@@ -1762,7 +1762,7 @@ int mct_get_tips(mct_ctx *c, int64_t cap, int32_t *edge, double *xy, int64_t *co
         return fail(c, MCT_ENOMEM, "tip buffers");
     }
     hipError_t e = mct::launch_tips(s.nx, s.ny, s.prm.X, s.prm.Y, s.prm.split, c->dtip_counts, &nb, de, dxy,
-                                    c->dtip_total, c->stream);
+                                    c->dtip_total, total, c->stream);
     if (e == hipSuccess && edge)
         e = hipMemcpyAsync(edge, de, sizeof(int32_t) * (size_t)total, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess && xy)
@@ -1771,6 +1771,30 @@ int mct_get_tips(mct_ctx *c, int64_t cap, int32_t *edge, double *xy, int64_t *co
     (void)hipFree(de);
     (void)hipFree(dxy);
     if (e != hipSuccess) return fail(c, MCT_EDEVICE, "tips: %s", hipGetErrorString(e));
+    return MCT_OK;
+}
+
+int mct_get_tips_noalloc(mct_ctx *c, int64_t cap, int32_t *edge_dev, double *xy_dev, int32_t *count_dev) {
+    if (!c) return MCT_EINVAL;
+    if (c->tri) return fail(c, MCT_EUNSUPPORTED, "the no-allocation tip query is for structured grids");
+    if (!c->finalized) return fail(c, MCT_ESTATE, "finalize first");
+    if (!count_dev || cap < 0 || (cap > 0 && (!edge_dev || !xy_dev)))
+        return fail(c, MCT_EINVAL, "null device output or negative capacity");
+    const Spec &s = cur(c);
+    if (mct::tips_nblocks(s.ns) > mct::kTipScratchBlocks)
+        return fail(c, MCT_EINVAL, "%lld edges: the no-allocation tip query handles at most %lld",
+                    (long long)s.ns, (long long)mct::kTipScratchBlocks * 256);
+    int dev = -1;
+    HIP_TRY(c, hipGetDevice(&dev));
+    if (dev != c->device) return fail(c, MCT_EDEVICE, "device %d is current, the context is on device %d", dev, c->device);
+    int32_t *scr = nullptr;
+    HIP_TRY(c, mct::tips_scratch(&scr));
+    int32_t nb = 0;
+    // asynchronous on the context's stream: count (block counts in the
+    // scratch array, every entry written), scan (the total into *count_dev),
+    // write (at most cap tips)
+    HIP_TRY(c, mct::launch_tips(s.nx, s.ny, s.prm.X, s.prm.Y, s.prm.split, scr, &nb, cap > 0 ? edge_dev : nullptr,
+                                xy_dev, count_dev, cap, c->stream));
     return MCT_OK;
 }
 

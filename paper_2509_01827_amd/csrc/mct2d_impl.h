@@ -171,11 +171,17 @@ hipError_t launch_commit(const Launch &L, int n, hipStream_t s);
 // gradients do not have the zero pattern of a rectangle.
 hipError_t launch_lattice_check(const StepParams &p, LatticeConst *ref, uint32_t *flag, hipStream_t s);
 
-// Crack-surface tips: compacted edge ids and reference midpoints.
+// Crack-surface tips: compacted edge ids and reference midpoints (at most
+// cap written; count_out receives the total).
 hipError_t launch_tips(int32_t nx, int32_t ny, const double *X, const double *Y,
                        const uint8_t *split, int32_t *block_counts, int32_t *nblocks_out,
-                       int32_t *edge_out, double *xy_out, int32_t *count_out, hipStream_t s);
+                       int32_t *edge_out, double *xy_out, int32_t *count_out, int64_t cap, hipStream_t s);
 int tips_nblocks(int64_t n_edges);
+// The no-allocation tip query's block counts: a static device array, its
+// address on the current device (resolved once per device).
+constexpr int kTipScratchBlocks = 1 << 16;
+constexpr int kMaxDevices = 64;
+hipError_t tips_scratch(int32_t **out);
 
 // Crack-path normals and lengths of n elements (36 doubles each).
 hipError_t launch_path_geometry(const StepParams &p, int n, const int32_t *elem, double *out, hipStream_t s);

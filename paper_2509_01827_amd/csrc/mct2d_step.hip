@@ -32,6 +32,7 @@
 #include "mct2d_front.h"
 
 #include <climits>
+#include <mutex>
 
 namespace mct {
 
@@ -1565,7 +1566,7 @@ __global__ __launch_bounds__(1024) void k_tips_scan(int32_t *counts, int nblocks
 __global__ __launch_bounds__(kTipBlock) void k_tips_write(int nx, int ny, int64_t ns, const double *X,
                                                           const double *Y, const uint8_t *split,
                                                           const int32_t *offsets, int32_t *edge_out,
-                                                          double *xy_out) {
+                                                          double *xy_out, int64_t cap) {
     __shared__ int s_w[kTipBlock / 64];
     const int64_t s = (int64_t)blockIdx.x * kTipBlock + threadIdx.x;
     EdgeInfo ei{0, 0, -1, -1};
@@ -1583,9 +1584,11 @@ __global__ __launch_bounds__(kTipBlock) void k_tips_write(int nx, int ny, int64_
         for (int w = 0; w < wave; ++w) off += s_w[w];
         const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
         off += __popcll(b & lt);
-        edge_out[off] = (int32_t)s;
-        xy_out[2 * off] = 0.5 * (X[ei.lo] + X[ei.hi]);
-        xy_out[2 * off + 1] = 0.5 * (Y[ei.lo] + Y[ei.hi]);
+        if (off < cap) {  // the caller's capacity: the count reports the rest
+            edge_out[off] = (int32_t)s;
+            xy_out[2 * off] = 0.5 * (X[ei.lo] + X[ei.hi]);
+            xy_out[2 * off + 1] = 0.5 * (Y[ei.lo] + Y[ei.hi]);
+        }
     }
 }
 }  // namespace
@@ -1624,16 +1627,44 @@ hipError_t launch_path_geometry(const StepParams &p, int n, const int32_t *elem,
 
 int tips_nblocks(int64_t n_edges) { return (int)((n_edges + kTipBlock - 1) / kTipBlock); }
 
+// Scratch of the tip query that allocates nothing (mct_get_tips_noalloc):
+// the per-block counts of the compaction, for up to kTipScratchBlocks
+// blocks of kTipBlock edges.  Each GPU holds its own copy for the life of
+// the process; calls on one GPU share it (and race if they overlap).
+__device__ __align__(256) int32_t scratch[kTipScratchBlocks];
+
+hipError_t tips_scratch(int32_t **out) {
+    static std::mutex mu;
+    static int32_t *ptr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        // the array's address on the current device (the host-side name is
+        // not a device address)
+        e = hipGetSymbolAddress((void **)&ptr[dev], HIP_SYMBOL(scratch));
+        if (e != hipSuccess) {
+            ptr[dev] = nullptr;
+            return e;
+        }
+    }
+    *out = ptr[dev];
+    return hipSuccess;
+}
+
 hipError_t launch_tips(int32_t nx, int32_t ny, const double *X, const double *Y, const uint8_t *split,
                        int32_t *block_counts, int32_t *nblocks_out, int32_t *edge_out, double *xy_out,
-                       int32_t *count_out, hipStream_t s) {
+                       int32_t *count_out, int64_t cap, hipStream_t s) {
     const int64_t ns = 2 * (int64_t)nx * ny + nx + ny;
     const int nb = tips_nblocks(ns);
     *nblocks_out = nb;
     (void)hipGetLastError();
     k_tips_count<<<nb, kTipBlock, 0, s>>>(nx, ny, ns, split, block_counts);
     k_tips_scan<<<1, 1024, 0, s>>>(block_counts, nb, count_out);
-    if (edge_out) k_tips_write<<<nb, kTipBlock, 0, s>>>(nx, ny, ns, X, Y, split, block_counts, edge_out, xy_out);
+    if (edge_out)
+        k_tips_write<<<nb, kTipBlock, 0, s>>>(nx, ny, ns, X, Y, split, block_counts, edge_out, xy_out, cap);
     return hipGetLastError();
 }
 

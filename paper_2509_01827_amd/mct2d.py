@@ -53,7 +53,7 @@ EXPORTS = [
     "mct_mlp_forward", "mct_mlp_gradient", "mct_mlp_train_step", "mct_get_energies", "mct_set_tracking",
     "mct_set_load_curve", "mct_set_mesh_tri", "mct_set_mesh_q4", "mct_set_front_pick",
     "mct_set_smoothing", "mct_bind_device_buffers", "mct_set_lattice", "mct_get_lattice",
-    "mct_set_near_log", "mct_get_near_log", "mct_profile_step",
+    "mct_set_near_log", "mct_get_near_log", "mct_profile_step", "mct_get_tips_noalloc",
 ]
 LATTICE_AUTO = 0
 LATTICE_GENERAL = 1
@@ -109,6 +109,7 @@ def load() -> C.CDLL:
     L.mct_get_lattice.argtypes = [P, C.POINTER(C.c_int)]
     L.mct_set_near_log.argtypes = [P, C.c_double, C.c_int64]
     L.mct_profile_step.argtypes = [P, C.c_int64, dp]
+    L.mct_get_tips_noalloc.argtypes = [P, C.c_int64, P, P, P]
     L.mct_get_near_log.argtypes = [P, C.c_int64, P, P, P, P, P, P, P, C.POINTER(C.c_int64)]
     L.mct_finalize.argtypes = [P]
     L.mct_step.argtypes = [P, C.c_int64]
