@@ -474,8 +474,8 @@ int mct_get_launch(mct_ctx *ctx, int *tile, int *order, int64_t *workgroups);
  * The exact G is the judge: each window of screened steps (a period, or
  * its part up to the next exact step) starts from a snapshot of the state,
  * and every skipped candidate is bounded at every screened step, by
- * |delta| max_k |sigma_k|_F / 2 >= |G_k| (Frobenius norm of the three path
- * edges' stresses; open stretch gate only).  When a bound reaches Gc the
+ * max_k |sigma_k delta| / 2 >= |G_k| (sigma_k the smoothed stress of path k's
+ * exit edge, symmetric, and n_k a unit vector; open stretch gate only).  When a bound reaches Gc the
  * skipped candidate might have been accepted, so the window is restored and
  * replayed with the plain step.  Otherwise no skipped candidate can pass the
  * element rule, the accepted sets and picks are the plain step's, and the

@@ -968,7 +968,7 @@ __global__ __launch_bounds__(TXE *TYE, UNI ? 6 : 4) void k_step(StepParamsT<T> p
     for (int c0 = 0; c0 < ncand; c0 += NT / 4) {  // same trip count in every lane
         const int c = c0 + (tid >> 2), j = tid & 3;
         const bool live = c < ncand;
-        T Gj = T(0), gc = T(0), d2 = T(0);
+        T Gj = T(0), gc = T(0);
         bool H = false, skipped = false;
         int a = 0;
         int64_t ge = 0;
@@ -993,12 +993,13 @@ __global__ __launch_bounds__(TXE *TYE, UNI ? 6 : 4) void k_step(StepParamsT<T> p
             const T Lx = X2 - X1, Ly = Y2 - Y1;
             H = (lx * lx + ly * ly) > (Lx * Lx + Ly * Ly);  // else G = 0 on all three paths
             if (skipped && H && j < 3) {
-                // |G_k| = |delta . sigma_k n_k| / 2 <= |delta| |sigma_k|_F / 2: lane j
-                // holds |sigma_k|_F^2 of its path's edge stress
+                // |G_k| = |delta . sigma_k n_k| / 2 = |(sigma_k delta) . n_k| / 2
+                // <= |sigma_k delta| / 2 (sigma_k symmetric, n_k a unit vector):
+                // lane j holds |sigma_k delta|^2 of its path's edge stress
                 T sg[3];
                 edge_sigma(edge_slot(cie, cje, (a + 1 + j) & 3), sg);
-                Gj = fmat(T(2) * sg[2], sg[2], fmat(sg[1], sg[1], sg[0] * sg[0]));
-                d2 = fmat(duy, duy, dux * dux);
+                const T tx = fmat(sg[2], duy, sg[0] * dux), ty = fmat(sg[1], duy, sg[2] * dux);
+                Gj = fmat(ty, ty, tx * tx);
             } else if (H && j < 3) {
                 const int k = (a + 1 + j) & 3;
                 T sg[3], nxv, nyv, len;
@@ -1022,11 +1023,11 @@ __global__ __launch_bounds__(TXE *TYE, UNI ? 6 : 4) void k_step(StepParamsT<T> p
         const T G2 = __shfl(Gj, qb + 2, 64);
         if (live && H && j == 0 && skipped) {
             // the judge of a screened window: a skipped candidate whose bound
-            // (|delta| max_k |sigma_k|_F / 2, compared squared, with a margin
-            // of 1e-9 for rounding) reaches Gc might have been accepted, so the
+            // (max_k |sigma_k delta| / 2, compared squared, with a margin of
+            // 1e-9 for rounding) reaches Gc might have been accepted, so the
             // window is replayed with the plain step
             const T f2 = G1 > G2 ? (G1 > Gj ? G1 : Gj) : (G2 > Gj ? G2 : Gj);
-            if (T(0.25) * d2 * f2 > gc * gc * T(1.0 - 1e-9)) atomicOr(p.strip, 1u);
+            if (T(0.25) * f2 > gc * gc * T(1.0 - 1e-9)) atomicOr(p.strip, 1u);
         }
         if (live && H && j == 0 && !skipped) {
             const T Gv[3] = {Gj, G1, G2};

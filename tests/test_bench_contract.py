@@ -45,10 +45,12 @@ def _check_line(d, steps, workload):
     rf = d["roofline"]
     assert rf["bound"] == "hbm" and rf["peak"] == 8000.0 and rf["unit"] == "GB/s"
     assert rf["frac"] == pytest.approx(rf["achieved"] / rf["peak"])
-    # the step kernel's own duration, timed live, is within the step's
+    # achieved bandwidth from the timed window's time per step; the step
+    # kernel alone, timed per launch after the window, is of the same order
     kt = d["kernel_timing"]
-    assert 0 < kt["step_kernel_us"] and rf["kernel_us"] == kt["step_kernel_us"]
-    assert rf["achieved"] == pytest.approx(rf["bytes_per_launch"] / (kt["step_kernel_us"] * 1e-6) / 1e9)
+    assert rf["kernel_us"] == pytest.approx(d["ms_per_step"] * 1e3)
+    assert rf["achieved"] == pytest.approx(rf["bytes_per_launch"] / (d["ms_per_step"] * 1e-3) / 1e9)
+    assert 0.3 * rf["kernel_us"] < kt["step_kernel_us"] < 3.0 * rf["kernel_us"]
     cb = d["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["cores"] >= 1 and cb["value"] > 0
 
