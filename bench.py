@@ -43,6 +43,8 @@ WORKLOADS = {
     "plate400": "branching plate 400x400 Q4, 100x40 mm, jitter 1%, notch 50 mm, 1 MPa",
     "fragment2000": "fragmentation plate 2000x1000 Q4, h 2^-13 m, 5 m/s outward, Weibull(6,3) Gc",
     "screen400": "branching plate 400x400 Q4 (as plate400) with the learned split-screen, exact step every 50",
+    "screen2000": "fragmentation plate 2000x1000 Q4 (as fragment2000) with the learned split-screen, exact step "
+                  "every 50",
     "tri320k": "branching plate 100x40 mm on an unstructured CST mesh (Delaunay of 633x254 jittered points, "
                "319792 triangles), notch 50 mm, 1 MPa",
     "cylinder53k": "pressured hollow cylinder r 50/100 mm on an unstructured CST mesh (h 1 mm, ~53000 triangles), "
@@ -51,7 +53,8 @@ WORKLOADS = {
                 "jittered points split into 3 quadrilaterals, ~160000 elements), notch 50 mm, 1 MPa",
 }
 # untimed steps from t = 0 before the window (mid-run); 0 for the others
-DEFAULT_START = {"batch256": 2500, "plate400": 10000, "fragment2000": 5000, "screen400": 10000}
+DEFAULT_START = {"batch256": 2500, "plate400": 10000, "fragment2000": 5000, "screen400": 10000,
+                 "screen2000": 5000}
 
 
 def n_elems(c) -> int:
@@ -297,8 +300,8 @@ def main():
     screen = None
     if args.workload == "batch256":
         cfgs = W.batch_specimens()
-    elif args.workload == "screen400":
-        cfgs = [W.config2()]
+    elif args.workload in ("screen400", "screen2000"):
+        cfgs = [W.config2() if args.workload == "screen400" else W.config3()]
         with open(os.path.join(ROOT, "paper_2509_01827_amd", "screen_weights.json")) as f:
             screen = json.load(f)
     else:

@@ -364,8 +364,16 @@ int mct_get_split_codes(mct_ctx *ctx, int64_t cap, uint8_t *out);
 
 /* Copy the full dynamic state (u, v, split codes, step, U_d, log) into a
  * caller buffer; *bytes receives the size (call with host_buf NULL to query).
- * mct_restore loads a buffer produced by mct_checkpoint of a context with
- * the same mesh. */
+ * A plain context whose split-screen buffers exist (mct_screen_enable or
+ * mct_screen_collect was called) adds the screen's state: per-element
+ * screen states of the current window, the history behind feature 4 with
+ * its evaluation stamps, the evaluation count and the counters of
+ * mct_screen_stats.  mct_restore loads a buffer produced by mct_checkpoint
+ * of a context with the same mesh; with a screen section it restores the
+ * screen's state too (the window position follows from the step), so a
+ * screened run restored and continued with the same screen (mct_screen_enable
+ * with the same parameters, tau and period) is the uninterrupted run; without
+ * one the screen starts afresh. */
 int mct_checkpoint(mct_ctx *ctx, void *host_buf, int64_t cap, int64_t *bytes);
 int mct_restore(mct_ctx *ctx, const void *host_buf, int64_t bytes);
 
@@ -519,8 +527,8 @@ int mct_screen_collect(mct_ctx *ctx, int64_t cap, float *features, int32_t *elem
 /* Screened stepping with the parameters of `mlp` (copied; mlp may be
  * destroyed afterwards), threshold tau on the logit and the exact-step
  * period (>= 2; steps k with k % period == 0 are exact).  mct_screen_disable
- * returns to plain stepping.  Checkpoints do not hold the screen state:
- * mct_restore starts the screen afresh (history, states and counters). */
+ * returns to plain stepping.  Checkpoints hold the screen's state (see
+ * mct_checkpoint).  Not with the near-threshold log (MCT_EUNSUPPORTED). */
 int mct_screen_enable(mct_ctx *ctx, const mct_mlp *mlp, float tau, int period);
 int mct_screen_disable(mct_ctx *ctx);
 

@@ -1919,6 +1919,17 @@ int mct_get_split_codes(mct_ctx *c, int64_t cap, uint8_t *out) {
 // precision, so a state moves only between contexts of one precision.
 static const uint64_t kMagic = 0x4d43543244434b32ull;    // "MCT2DCK2"
 static const uint64_t kMagic32 = 0x4d43543246434b32ull;  // "MCT2FCK2"
+static const uint64_t kScreenTag = 0x314e524353544d43ull;  // "MCTSCRN1"
+
+// Optional last section of a plain context's checkpoint: the learned
+// split-screen's state (per-element screen states, the per-candidate history
+// behind feature 4 and its stamps, the evaluation count, the counters), so
+// that a restored screened run continues exactly where it was.
+static int64_t screen_section_bytes(const mct_ctx *c) {
+    if (c->batch || !c->screen_alloc) return 0;
+    const int64_t ne = c->specs[0].ne;
+    return 16 + 4 * ne + 8 * 4 * ne + 4 * 4 * ne + 8 + 8 * mct::kNumScreenStats;
+}
 
 int mct_checkpoint(mct_ctx *c, void *buf, int64_t cap, int64_t *bytes) {
     if (!c || !bytes) return MCT_EINVAL;
@@ -1936,6 +1947,7 @@ int mct_checkpoint(mct_ctx *c, void *buf, int64_t cap, int64_t *bytes) {
         const int64_t nlog = std::min<int64_t>(h[q].nsplit, s.prm.log_cap);
         need += 16 + (int64_t)sizeof(Control) + 32 * s.nn + s.ne + nlog * (int64_t)sizeof(LogRec);
     }
+    need += screen_section_bytes(c);
     *bytes = need;
     if (!buf) return MCT_OK;
     if (cap < need) return fail(c, MCT_ECAPACITY, "checkpoint needs %lld bytes", (long long)need);
@@ -1961,6 +1973,29 @@ int mct_checkpoint(mct_ctx *c, void *buf, int64_t cap, int64_t *bytes) {
         const int64_t nlog = std::min<int64_t>(h[q].nsplit, s.prm.log_cap);
         if (nlog) HIP_TRY(c, hipMemcpyAsync(p, s.prm.log, sizeof(LogRec) * nlog, hipMemcpyDeviceToHost, c->stream));
         p += sizeof(LogRec) * nlog;
+    }
+    if (screen_section_bytes(c)) {
+        const mct::ScreenDev &sd = c->sd;
+        const int64_t ne = c->specs[0].ne;
+        const uint64_t sh[2] = {kScreenTag, (uint64_t)ne};
+        std::memcpy(p, sh, sizeof sh);
+        p += sizeof sh;
+        HIP_TRY(c, hipMemcpyAsync(p, sd.screen, 4 * ne, hipMemcpyDeviceToHost, c->stream));
+        p += 4 * ne;
+        HIP_TRY(c, hipMemcpyAsync(p, sd.hist_g, 8 * 4 * ne, hipMemcpyDeviceToHost, c->stream));
+        p += 8 * 4 * ne;
+        HIP_TRY(c, hipMemcpyAsync(p, sd.hist_t, 4 * 4 * ne, hipMemcpyDeviceToHost, c->stream));
+        p += 4 * 4 * ne;
+        HIP_TRY(c, hipMemcpyAsync(p, sd.sweep, 4, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(p + 4, sd.nrows_last, 4, hipMemcpyDeviceToHost, c->stream));
+        p += 8;
+        unsigned long long st[4];
+        HIP_TRY(c, hipMemcpyAsync(st, sd.stats, sizeof st, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        const int64_t all[mct::kNumScreenStats] = {(int64_t)st[0], (int64_t)st[1], (int64_t)st[2], (int64_t)st[3],
+                                                  c->screen_windows, c->screen_replays};
+        std::memcpy(p, all, sizeof all);
+        p += sizeof all;
     }
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return MCT_OK;
@@ -1995,6 +2030,22 @@ int mct_restore(mct_ctx *c, const void *buf, int64_t bytes) {
         if (end - q < len) return fail(c, MCT_EINVAL, "checkpoint truncated");
         q += len;
     }
+    // the optional screen section (plain contexts)
+    const char *scr = nullptr;
+    if (end - q >= 16) {
+        uint64_t sh[2];
+        std::memcpy(sh, q, sizeof sh);
+        const int64_t ne = c->specs[0].ne;
+        if (sh[0] != kScreenTag || c->batch || (int64_t)sh[1] != ne)
+            return fail(c, MCT_EINVAL, "checkpoint has an unknown trailing section");
+        const int64_t len = 16 + 4 * ne + 8 * 4 * ne + 4 * 4 * ne + 8 + 8 * mct::kNumScreenStats;
+        if (end - q < len) return fail(c, MCT_EINVAL, "checkpoint truncated (screen state)");
+        scr = q + 16;
+    }
+    if (scr) {
+        int rc = ensure_screen(c);
+        if (rc) return rc;
+    }
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     for (int s = 0; s < S; ++s) {
         const Spec &sp = c->specs[s];
@@ -2015,13 +2066,35 @@ int mct_restore(mct_ctx *c, const void *buf, int64_t bytes) {
         p += sizeof(LogRec) * nlog;
     }
     if (int rc = narrow_state(c)) return rc;
-    if (c->screen_alloc) {  // the screen starts afresh from a restored state
+    if (scr) {  // the screen continues where the checkpoint was taken
+        const mct::ScreenDev &sd = c->sd;
+        const int64_t ne = c->specs[0].ne;
+        const char *r = scr;
+        HIP_TRY(c, hipMemcpyAsync(sd.screen, r, 4 * ne, hipMemcpyHostToDevice, c->stream));
+        r += 4 * ne;
+        HIP_TRY(c, hipMemcpyAsync(sd.hist_g, r, 8 * 4 * ne, hipMemcpyHostToDevice, c->stream));
+        r += 8 * 4 * ne;
+        HIP_TRY(c, hipMemcpyAsync(sd.hist_t, r, 4 * 4 * ne, hipMemcpyHostToDevice, c->stream));
+        r += 4 * 4 * ne;
+        HIP_TRY(c, hipMemcpyAsync(sd.sweep, r, 4, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(sd.nrows_last, r + 4, 4, hipMemcpyHostToDevice, c->stream));
+        r += 8;
+        int64_t all[mct::kNumScreenStats];
+        std::memcpy(all, r, sizeof all);
+        unsigned long long st[4] = {(unsigned long long)all[0], (unsigned long long)all[1],
+                                    (unsigned long long)all[2], (unsigned long long)all[3]};
+        HIP_TRY(c, hipMemcpyAsync(sd.stats, st, sizeof st, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        c->screen_windows = all[mct::kStatWindows];
+        c->screen_replays = all[mct::kStatReplays];
+    } else if (c->screen_alloc) {  // no screen state saved: the screen starts afresh
         const mct::ScreenDev &sd = c->sd;
         const int64_t ne = c->specs[0].ne;
         HIP_TRY(c, mct::launch_fill_u32(reinterpret_cast<uint32_t *>(sd.hist_t), 4 * ne, 0xFFFFFFFEu, c->stream));
         HIP_TRY(c, hipMemsetAsync(sd.screen, 0, sizeof(uint32_t) * ne, c->stream));
         HIP_TRY(c, hipMemsetAsync(sd.sweep, 0, sizeof(int32_t), c->stream));
         HIP_TRY(c, hipMemsetAsync(sd.stats, 0, sizeof(unsigned long long) * 4, c->stream));
+        c->screen_windows = c->screen_replays = 0;
     }
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->steps_enqueued = hs[0].base;
