@@ -110,6 +110,7 @@ struct mct_ctx {
     double2 *dfmid = nullptr;
     double *dflen = nullptr;
     int32_t *dforder = nullptr, *dfbucket = nullptr, *dfsorted = nullptr, *dfplist = nullptr;
+    int32_t *dfgrid = nullptr;  // bucket table of the pick over the whole GPU (large models)
     double front_cell = 0.0;
     StepParams *dviews = nullptr;
     int2 *dunits = nullptr;
@@ -313,6 +314,7 @@ void release_device(mct_ctx *c) {
     dfree(c->dfbucket);
     dfree(c->dfsorted);
     dfree(c->dfplist);
+    dfree(c->dfgrid);
     dfree(c->dviews);
     dfree(c->dunits);
     dfree(c->dtip_counts);
@@ -1440,6 +1442,11 @@ int mct_finalize(mct_ctx *c) {
         HIP_TRY(c, hipMalloc((void **)&c->dfbucket, sizeof(int32_t) * cap));
         HIP_TRY(c, hipMalloc((void **)&c->dfsorted, sizeof(int32_t) * cap));
         HIP_TRY(c, hipMalloc((void **)&c->dfplist, sizeof(int32_t) * cap));
+        if (ne >= mct::kFrontGridMinElements && std::isfinite(c->specs[0].front_rho)) {
+            // the pick over the whole GPU: its two bucket tables
+            HIP_TRY(c, hipMalloc((void **)&c->dfgrid, sizeof(int32_t) * 2 * mct::kFrontGridTable));
+            HIP_TRY(c, mct::front_grid_reset(c->dfgrid, c->stream));
+        }
         // hash cell: at least rho and the largest distance between two nodes
         // of an element (so same-element candidates are neighbours too)
         const Spec &s0 = c->specs[0];
@@ -1508,6 +1515,7 @@ int mct_finalize(mct_ctx *c) {
         p.fsorted = c->dfsorted;
         p.fplist = c->dfplist;
         p.fcell = c->front_cell;
+        p.fgrid = c->dfgrid;
         p.lat = nullptr;
         p.near = nullptr;
         p.near_count = nullptr;
@@ -2066,6 +2074,7 @@ int mct_restore(mct_ctx *c, const void *buf, int64_t bytes) {
         p += sizeof(LogRec) * nlog;
     }
     if (int rc = narrow_state(c)) return rc;
+    if (c->dfgrid) HIP_TRY(c, mct::front_grid_reset(c->dfgrid, c->stream));
     if (scr) {  // the screen continues where the checkpoint was taken
         const mct::ScreenDev &sd = c->sd;
         const int64_t ne = c->specs[0].ne;

@@ -48,10 +48,10 @@ __device__ __forceinline__ bool acc_better(const AccCand &x, const AccCand &y) {
 
 constexpr int kFrontBuckets = 4096;
 
-__device__ __forceinline__ int front_bucket(long long cx, long long cy) {
+__device__ __forceinline__ int front_bucket(long long cx, long long cy, int nbuckets = kFrontBuckets) {
     const unsigned long long h = (unsigned long long)cx * 0x9E3779B97F4A7C15ull ^
                                  (unsigned long long)cy * 0xC2B2AE3D27D4EB4Full;
-    return (int)((h >> 40) & (kFrontBuckets - 1));
+    return (int)((h >> 40) & (unsigned long long)(nbuckets - 1));
 }
 
 // The pick of step base + k_rel with one workgroup of NT threads.  Geom
@@ -223,6 +223,264 @@ __device__ void front_pick_block(const FrontView &v, const Geom &geo, int k_rel)
         *v.nsplit = ns0 + np;
         *v.count = 0;
     }
+}
+
+// ------------------------------------------------------------------------
+// The same pick spread over the whole GPU, for models with many candidates
+// per step; the tables are described with kFrontGridBuckets.
+//   k_fg_prep   (a thread per candidate) tip point and bucket; the
+//               candidate's index goes into the bucket's row of
+//               kFrontGridCap slots, or onto its overflow list when full
+//               (front_grid_insert).  The grid also clears the other table
+//               for the next step (front_grid_clear).  A step kernel that
+//               does both itself as it lists the candidates skips it.
+//   k_fg_decide (a wavefront per candidate) the own cell's row first, then
+//               the other eight cells' rows, one slot per lane, and any
+//               overflow list (lane q walks cell q's); the candidate is
+//               picked when no lane finds a competitor it fails against.
+//   k_fg_close  (one workgroup) ranks the picked ones by key (the keys
+//               staged in LDS), writes split codes and log records at
+//               their ranks and adds U_d in log order (the products G_c *
+//               path length formed in parallel, summed by one thread).
+// A candidate's decision depends only on the set of candidates, so the
+// picks, the log and U_d are those of front_pick_block, bit for bit.
+// ------------------------------------------------------------------------
+constexpr int kFrontGridBlocks = 1024;
+constexpr int kFrontGridThreads = 256;
+constexpr int kFrontCloseThreads = 1024;
+constexpr int kFrontRankChunk = 1024;
+constexpr int kFrontTermChunk = 1024;
+static_assert(kFrontGridCap == 64, "one row slot per lane of a wavefront");
+
+static_assert(kFrontGridHead == kFrontGridCnt + kFrontGridBuckets, "heads follow the counts");
+
+// Candidate c with tip point m into the table tb of its step; next holds
+// the overflow lists.
+__device__ __forceinline__ void front_grid_insert(int32_t *tb, double cell, int32_t *next, int32_t c, double2 m) {
+    const int b = front_bucket((long long)floor(m.x / cell), (long long)floor(m.y / cell), kFrontGridBuckets);
+    const int slot = atomicAdd(&tb[kFrontGridCnt + b], 1);
+    if (slot < kFrontGridCap)
+        tb[kFrontGridTab + (int64_t)b * kFrontGridCap + slot] = c;
+    else
+        next[c] = atomicExch(&tb[kFrontGridHead + b], c);
+}
+
+// Entries t = t0, t0 + stride, ... of the counts and heads of the table
+// the next step uses (tables: both; par: this step's parity).
+__device__ __forceinline__ void front_grid_clear(int32_t *tables, int par, int64_t t0, int64_t stride) {
+    int32_t *nx = tables + (par ^ 1) * kFrontGridTable;
+    for (int64_t t = t0; t < 2 * (int64_t)kFrontGridBuckets; t += stride)
+        nx[kFrontGridCnt + t] = t < kFrontGridBuckets ? 0 : -1;  // counts, then heads
+}
+
+namespace {  // kernels local to each translation unit that includes this header
+
+// acc_better(y, x) without branches, as 0 or 1
+__device__ __forceinline__ int acc_better_i(const AccCand &y, const AccCand &x) {
+    const bool gt = y.G > x.G, eq = y.G == x.G;
+    const bool tie = y.elem < x.elem || (y.elem == x.elem && (y.ak >> 2) < (x.ak >> 2));
+    return (int)(gt || (eq && tie));
+}
+
+// Ud + t[0] + t[1] + ... + t[m-1], added in this order (t in LDS); the
+// loads go out sixteen at a time ahead of the dependent additions.
+__device__ __forceinline__ double add_in_order(double Ud, const double *t, int m) {
+    int r = 0;
+    for (; r + 16 <= m; r += 16) {
+        double a[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) a[q] = t[r + q];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) Ud = Ud + a[q];
+    }
+    for (; r < m; ++r) Ud = Ud + t[r];
+    return Ud;
+}
+
+// the table of step base + k_rel
+__device__ __forceinline__ int32_t *front_table(const FrontView &v, int32_t *tables, int k_rel) {
+    return tables + ((*v.base + k_rel) & 1) * kFrontGridTable;
+}
+
+template <class Geom>
+__global__ __launch_bounds__(kFrontGridThreads) void k_fg_prep(FrontView v, Geom geo, int32_t *tables, int k_rel) {
+    const int par = (int)((*v.base + k_rel) & 1);
+    int32_t *tb = tables + par * kFrontGridTable;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    front_grid_clear(tables, par, blockIdx.x * blockDim.x + threadIdx.x, stride);
+    const uint32_t n = *v.count;
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) {
+        const AccCand x = v.cand[c];
+        const double2 m = geo.tip(x.elem, x.ak >> 2);
+        v.mid[c] = m;
+        front_grid_insert(tb, v.cell, v.sorted, (int32_t)c, m);
+    }
+}
+
+// Does candidate x (index c, tip point pc) fail against candidate d?
+__device__ __forceinline__ bool front_fails(const FrontView &v, const AccCand &x, double2 pc, int c, int d) {
+    if (d == c) return false;
+    const AccCand y = v.cand[d];
+    const double2 pd = v.mid[d];
+    const double ddx = pc.x - pd.x, ddy = pc.y - pd.y;
+    const bool compete = x.elem == y.elem || ddx * ddx + ddy * ddy < v.rho2;
+    return compete && (!acc_better(x, y) || !(x.G > v.gamma * (x.G - y.G)));
+}
+
+// The end of the pick (one workgroup of NT threads, tb the step's table).
+template <int NT, class Geom>
+__device__ void front_grid_close(const FrontView &v, const Geom &geo, int32_t *tb, int k_rel) {
+    __shared__ __align__(16) AccCand s_key[kFrontRankChunk];
+    __shared__ double s_term[kFrontTermChunk];
+    const int tid = threadIdx.x;
+    int32_t *np_ = tb + kFrontGridNp;
+    const int np = *np_;
+    const int64_t k = *v.base + k_rel;
+    const int64_t ns0 = *v.nsplit;
+    double Ud = *v.Ud;
+    __syncthreads();  // every wave has read the counts before thread 0 resets them
+    // rank of picked candidate i among the picked (key order); with at most
+    // kFrontTermChunk picked, each one's U_d term goes to LDS at its rank
+    for (int i0 = 0; i0 < np; i0 += NT) {
+        const int i = i0 + tid;
+        int c = -1;
+        AccCand x;
+        double term = 0.0;
+        if (i < np) {
+            c = v.plist[i];
+            x = v.cand[c];
+            const double gc = v.gc ? v.gc[x.elem] : v.gc_uniform;
+            term = gc * geo.path_len(x.elem, x.ak >> 2, x.ak & 3);
+        }
+        int rank = 0;
+        for (int j0 = 0; j0 < np; j0 += kFrontRankChunk) {
+            // the chunk's keys, padded to a multiple of 8 with keys that
+            // beat nothing (G = -1; accepted candidates have G > 0)
+            const int m = min(kFrontRankChunk, np - j0);
+            const int m8 = (m + 7) & ~7;
+            __syncthreads();
+            for (int j = tid; j < m8; j += NT) {
+                AccCand y;
+                if (j < m) {
+                    y = v.cand[v.plist[j0 + j]];
+                } else {
+                    y.G = -1.0;
+                    y.elem = 0x7fffffff;
+                    y.ak = 0;
+                }
+                s_key[j] = y;
+            }
+            __syncthreads();
+            if (i < np)
+                for (int j = 0; j < m8; j += 8) {
+                    AccCand y[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) y[q] = s_key[j + q];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) rank += acc_better_i(y[q], x);
+                }
+        }
+        if (i < np) {
+            v.order[rank] = (int32_t)c;
+            if (np <= kFrontTermChunk) s_term[rank] = term;
+            v.split[x.elem] = (uint8_t)(kSplitFlag | x.ak);
+            if (ns0 + rank < v.log_cap) {
+                LogRec r;
+                r.step = (int32_t)k;
+                r.elem = x.elem;
+                r.entry = (uint8_t)(x.ak >> 2);
+                r.exit = (uint8_t)(x.ak & 3);
+                r.pad0 = r.pad1 = 0;
+                r.pad2 = 0;
+                r.G = x.G;
+                v.log[ns0 + rank] = r;
+            }
+        }
+    }
+    __syncthreads();
+    // U_d in log order
+    if (np <= kFrontTermChunk) {
+        if (tid == 0) Ud = add_in_order(Ud, s_term, np);
+    } else {
+        for (int r0 = 0; r0 < np; r0 += NT) {
+            if (r0 + tid < np) {
+                const int c = v.order[r0 + tid];
+                const int e = v.cand[c].elem;
+                const double gc = v.gc ? v.gc[e] : v.gc_uniform;
+                s_term[tid] = gc * v.len[c];
+            }
+            __syncthreads();
+            if (tid == 0) Ud = add_in_order(Ud, s_term, min(NT, np - r0));
+            __syncthreads();
+        }
+    }
+    if (tid == 0) {
+        *v.Ud = Ud;
+        if (ns0 + np > v.log_cap) *v.overflow = 1;
+        *v.nsplit = ns0 + np;
+        *v.count = 0;
+        *np_ = 0;
+    }
+}
+
+__global__ __launch_bounds__(kFrontGridThreads) void k_fg_decide(FrontView v, int32_t *tables, int k_rel) {
+    int32_t *tb = front_table(v, tables, k_rel);
+    const uint32_t n = *v.count;
+    const int lane = threadIdx.x & 63;
+    const uint32_t nwave = gridDim.x * (blockDim.x >> 6);
+    for (uint32_t c = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < n; c += nwave) {
+        const AccCand x = v.cand[c];
+        const double2 pc = v.mid[c];
+        const long long cx = (long long)floor(pc.x / v.cell), cy = (long long)floor(pc.y / v.cell);
+        // cell q = 0..8 ((dx, dy) = (q % 3 - 1, q / 3 - 1)); q = 4 is the own cell
+        int cnt[9];
+        int bq[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            bq[q] = front_bucket(cx + q % 3 - 1, cy + q / 3 - 1, kFrontGridBuckets);
+            cnt[q] = tb[kFrontGridCnt + bq[q]];
+        }
+        bool fail = lane < cnt[4] && front_fails(v, x, pc, (int)c,
+                                                  tb[kFrontGridTab + (int64_t)bq[4] * kFrontGridCap + lane]);
+        if (__ballot(fail) == 0ull) {
+            int d[9];
+#pragma unroll
+            for (int q = 0; q < 9; ++q)
+                d[q] = (q != 4 && lane < cnt[q]) ? tb[kFrontGridTab + (int64_t)bq[q] * kFrontGridCap + lane] : -1;
+#pragma unroll
+            for (int q = 0; q < 9; ++q)
+                if (d[q] >= 0 && front_fails(v, x, pc, (int)c, d[q])) fail = true;
+            // overflow lists: lane q walks the list of cell q
+            int walk = -1;
+#pragma unroll
+            for (int q = 0; q < 9; ++q)
+                if (lane == q && cnt[q] > kFrontGridCap) walk = tb[kFrontGridHead + bq[q]];
+            for (; walk >= 0 && !fail; walk = v.sorted[walk])
+                if (front_fails(v, x, pc, (int)c, walk)) fail = true;
+        }
+        if (__ballot(fail) == 0ull && lane == 0) v.plist[atomicAdd(&tb[kFrontGridNp], 1)] = (int32_t)c;
+    }
+}
+
+template <class Geom>
+__global__ __launch_bounds__(kFrontCloseThreads) void k_fg_close(FrontView v, Geom geo, int32_t *tables, int k_rel) {
+    if (*v.count == 0) return;  // uniform; the count is reset by thread 0 after a barrier
+    front_grid_close<kFrontCloseThreads>(v, geo, front_table(v, tables, k_rel), k_rel);
+}
+
+}  // namespace
+
+// The launches of the pick of step base + k_rel over the two tables
+// (2 kFrontGridTable entries, as front_grid_reset leaves them: each pick
+// keeps them so for the next step); prepped: the step kernel has filled
+// the table, tip points and cleared the other table itself.
+template <class Geom>
+hipError_t launch_front_grid(const FrontView &v, const Geom &g, int32_t *tables, int k_rel, bool prepped,
+                             hipStream_t st) {
+    if (!prepped) k_fg_prep<Geom><<<kFrontGridBlocks, kFrontGridThreads, 0, st>>>(v, g, tables, k_rel);
+    k_fg_decide<<<kFrontGridBlocks, kFrontGridThreads, 0, st>>>(v, tables, k_rel);
+    k_fg_close<Geom><<<1, kFrontCloseThreads, 0, st>>>(v, g, tables, k_rel);
+    return hipGetLastError();
 }
 
 }  // namespace mct

@@ -30,6 +30,25 @@ struct AccCand {
 };
 static_assert(sizeof(AccCand) == 16, "AccCand layout");
 
+// Per-front pick over the whole GPU, used by models from
+// kFrontGridMinElements elements on (with a finite radius; smaller models
+// and rho = infinity take one workgroup).  Two int32 tables, one per step
+// parity, each: per bucket the number of candidates and the head of its
+// overflow list, the picked count, then kFrontGridCap candidate indices per
+// bucket.  Step k uses table k & 1 and clears the other one (counts 0,
+// heads -1) for step k + 1; the picked count returns to 0 at the end of
+// each pick.
+constexpr int kFrontGridBuckets = 1 << 16;
+constexpr int kFrontGridCap = 64;
+constexpr int64_t kFrontGridCnt = 0;
+constexpr int64_t kFrontGridHead = kFrontGridBuckets;
+constexpr int64_t kFrontGridNp = 2 * (int64_t)kFrontGridBuckets;
+constexpr int64_t kFrontGridTab = 2 * (int64_t)kFrontGridBuckets + 64;
+constexpr int64_t kFrontGridTable = kFrontGridTab + (int64_t)kFrontGridBuckets * kFrontGridCap;
+constexpr int64_t kFrontGridMinElements = 1 << 14;
+// both tables as the first pick expects them (after allocation, restore)
+hipError_t front_grid_reset(int32_t *tables, hipStream_t s);
+
 // Per-workgroup best candidate of one step (only workgroups with an
 // accepted candidate write one).
 struct Slot {
@@ -127,6 +146,7 @@ struct StepParamsT {
     int32_t *forder;
     int32_t *fbucket, *fsorted, *fplist;
     double fcell;  // hash cell of the pick: >= rho and the largest element diameter
+    int32_t *fgrid;  // the pick's bucket table over the whole GPU, or null for one workgroup
     // uniform lattice (binary64 point rule): its shared geometry, or null
     const LatticeConst *lat;
     // near-threshold decision log (plain models): null when off

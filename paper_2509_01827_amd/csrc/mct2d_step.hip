@@ -172,7 +172,7 @@ __device__ __forceinline__ void load_view(StepParamsT<T> &p, const StepParamsT<T
     p.front = s->front; p.fcap = s->fcap; p.front_r2 = s->front_r2; p.fcand = s->fcand;
     p.fcount = s->fcount; p.fmid = s->fmid; p.flen = s->flen; p.forder = s->forder;
     p.fbucket = s->fbucket; p.fsorted = s->fsorted; p.fplist = s->fplist; p.fcell = s->fcell;
-    p.lat = s->lat; p.near = s->near; p.near_count = s->near_count; p.near_cap = s->near_cap;
+    p.fgrid = s->fgrid; p.lat = s->lat; p.near = s->near; p.near_count = s->near_count; p.near_cap = s->near_cap;
     p.pad_near = s->pad_near; p.near_tol = s->near_tol;
 }
 
@@ -383,7 +383,8 @@ __device__ __forceinline__ int32_t tip_after(const StepParamsT<T> &p, const Cand
 //
 // NEAR (plain models, 16 x 16 tiles): the near-threshold decision log is on;
 // the reductions also carry the second largest accepted G.
-template <class T, int TXE, int TYE, bool BATCHED, bool SC = false, bool UNI = false, bool NEAR = false>
+template <class T, int TXE, int TYE, bool BATCHED, bool SC = false, bool UNI = false, bool NEAR = false,
+          bool FRONT = false>
 __global__ __launch_bounds__(TXE *TYE, UNI ? 6 : 4) void k_step(StepParamsT<T> p0,
                                                                const StepParamsT<T> *__restrict__ views,
                                                                const int2 *__restrict__ units, int k_rel, int par0) {
@@ -963,6 +964,8 @@ __global__ __launch_bounds__(TXE *TYE, UNI ? 6 : 4) void k_step(StepParamsT<T> p
     // edge a+1+j, lane 0 of the quad applies the element rule to the three
     // values.  Node data are read from LDS at computed offsets, so no array
     // is indexed by a run-time value.
+    if ((FRONT || NEAR) && p.fgrid)  // per-front pick over the whole GPU: the next step's table
+        front_grid_clear(p.fgrid, (int)((base + k_rel) & 1), (int64_t)blockIdx.x * NT + tid, (int64_t)gridDim.x * NT);
     CandT<T> best;
     cand_none(best);
     for (int c0 = 0; c0 < ncand; c0 += NT / 4) {  // same trip count in every lane
@@ -1053,6 +1056,19 @@ __global__ __launch_bounds__(TXE *TYE, UNI ? 6 : 4) void k_step(StepParamsT<T> p
                     ac.elem = (int32_t)ge;
                     ac.ak = (a << 2) | ((a + 1 + jb) & 3);
                     p.fcand[slot] = ac;
+                    if ((FRONT || NEAR) && p.fgrid) {
+                        // the pick over the whole GPU: tip point (midpoint of
+                        // the tip edge) into the step's bucket table
+                        const int t = (int)(s_cand[c] & 0x7FFFu) >> 2;
+                        const int nb0 = (t / TXE + 1) * HX + (t % TXE + 1);
+                        T X1, Y1, X2, Y2;
+                        node_xy(nb0 + corner(a), X1, Y1);
+                        node_xy(nb0 + corner((a + 1) & 3), X2, Y2);
+                        const double2 m = make_double2(0.5 * ((double)X1 + (double)X2), 0.5 * ((double)Y1 + (double)Y2));
+                        p.fmid[slot] = m;
+                        front_grid_insert(p.fgrid + ((base + k_rel) & 1) * kFrontGridTable, p.fcell, p.fsorted,
+                                          (int32_t)slot, m);
+                    }
                 }
             }
         }
@@ -1289,7 +1305,7 @@ struct Q4Geom {
     }
 };
 
-__global__ __launch_bounds__(kFrontThreads) void k_front(StepParams p, int k_rel) {
+__host__ __device__ inline FrontView q4_front_view(const StepParams &p) {
     FrontView v;
     v.cand = p.fcand;
     v.count = p.fcount;
@@ -1311,11 +1327,37 @@ __global__ __launch_bounds__(kFrontThreads) void k_front(StepParams p, int k_rel
     v.gc_uniform = p.gc_uniform;
     v.gamma = p.gamma;
     v.rho2 = p.front_r2;
+    return v;
+}
+
+__host__ __device__ inline Q4Geom q4_geom(const StepParams &p) {
     Q4Geom g;
     g.nx = p.nx;
     g.X = p.X;
     g.Y = p.Y;
-    front_pick_block<kFrontThreads>(v, g, k_rel);
+    return g;
+}
+
+__global__ __launch_bounds__(kFrontThreads) void k_front(StepParams p, int k_rel) {
+    front_pick_block<kFrontThreads>(q4_front_view(p), q4_geom(p), k_rel);
+}
+
+hipError_t front_grid_reset(int32_t *tables, hipStream_t s) {
+    for (int t = 0; t < 2; ++t) {
+        int32_t *tb = tables + t * kFrontGridTable;
+        hipError_t e = hipMemsetAsync(tb, 0, sizeof(int32_t) * kFrontGridTable, s);
+        if (e == hipSuccess) e = hipMemsetAsync(tb + kFrontGridHead, 0xff, sizeof(int32_t) * kFrontGridBuckets, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// The per-front pick after the step kernel: over the whole GPU when the
+// model has its bucket table, else one workgroup.
+static hipError_t launch_front(const StepParams &p, int k_rel, hipStream_t s) {
+    if (p.fgrid) return launch_front_grid(q4_front_view(p), q4_geom(p), p.fgrid, k_rel, true, s);
+    k_front<<<1, kFrontThreads, 0, s>>>(p, k_rel);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------
@@ -1403,8 +1445,34 @@ hipError_t launch_step(int tile, const Launch &L, int k_rel, int par0, hipStream
             k_step<double, 16, 16, false, true, false, true><<<p.nwg, 256, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
         else
             k_step<double, 16, 16, false, false, false, true><<<p.nwg, 256, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
-        if (p.front) k_front<<<1, kFrontThreads, 0, s>>>(p, k_rel);
+        if (p.front) return launch_front(p, k_rel, s);
         return hipGetLastError();
+    }
+    if (!L.f32 && !L.batched && L.p0.fgrid) {
+        // per-front pick over the whole GPU: the step kernels also fill the
+        // pick's bucket table
+        const StepParams &p = L.p0;
+#define KSTEP_FRONT(TX_, TY_, NT_, SC_, UNI_) \
+    k_step<double, TX_, TY_, false, SC_, UNI_, false, true><<<p.nwg, NT_, 0, s>>>(p, nullptr, nullptr, k_rel, par0)
+        switch (tile) {
+            case 1:
+                if (L.uni) KSTEP_FRONT(16, 16, 256, false, true);
+                else if (p.subcell) KSTEP_FRONT(16, 16, 256, true, false);
+                else KSTEP_FRONT(16, 16, 256, false, false);
+                break;
+            case 2:
+                if (L.uni) KSTEP_FRONT(32, 8, 256, false, true);
+                else if (p.subcell) KSTEP_FRONT(32, 8, 256, true, false);
+                else KSTEP_FRONT(32, 8, 256, false, false);
+                break;
+            default:
+                if (L.uni) KSTEP_FRONT(32, 16, 512, false, true);
+                else if (p.subcell) KSTEP_FRONT(32, 16, 512, true, false);
+                else KSTEP_FRONT(32, 16, 512, false, false);
+                break;
+        }
+#undef KSTEP_FRONT
+        return launch_front(p, k_rel, s);
     }
     if (L.f32) {
         // binary32 step: plain models with the point rule or sub-cell
@@ -1460,7 +1528,7 @@ hipError_t launch_step(int tile, const Launch &L, int k_rel, int par0, hipStream
                     k_step<double, 32, 16, false, false, true><<<p.nwg, 512, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
                     break;
             }
-            if (p.front) k_front<<<1, kFrontThreads, 0, s>>>(p, k_rel);
+            if (p.front) return launch_front(p, k_rel, s);
         }
         return hipGetLastError();
     }
@@ -1493,7 +1561,7 @@ hipError_t launch_step(int tile, const Launch &L, int k_rel, int par0, hipStream
                     k_step<double, 32, 16, false><<<p.nwg, 512, 0, s>>>(p, nullptr, nullptr, k_rel, par0);
                 break;
         }
-        if (p.front) k_front<<<1, kFrontThreads, 0, s>>>(p, k_rel);
+        if (p.front) return launch_front(p, k_rel, s);
     }
     return hipGetLastError();
 }

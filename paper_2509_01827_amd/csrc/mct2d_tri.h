@@ -99,6 +99,7 @@ struct Params {
     int32_t *forder;
     int32_t *fbucket, *fsorted, *fplist;
     double fcell;  // hash cell of the pick: >= rho and the largest element diameter
+    int32_t *fgrid;  // the pick's bucket table over the whole GPU, or null for one workgroup
 };
 
 // Evaluation outputs of the query kernels (nullptr = skip).

@@ -1147,7 +1147,7 @@ struct TriGeom {
     }
 };
 
-__global__ __launch_bounds__(kFrontThreads) void k_front(Params p, int j) {
+__host__ __device__ inline FrontView tri_front_view(const Params &p) {
     FrontView v;
     v.cand = p.cand;
     v.count = reinterpret_cast<uint32_t *>(&p.ctl->nacc);
@@ -1169,11 +1169,27 @@ __global__ __launch_bounds__(kFrontThreads) void k_front(Params p, int j) {
     v.gc_uniform = 0.0;
     v.gamma = p.gamma;
     v.rho2 = p.front_r2;
+    return v;
+}
+
+__host__ __device__ inline TriGeom tri_geom(const Params &p) {
     TriGeom g;
     g.conn = p.conn;
     g.xy = p.xy;
     g.nv = p.nv;
-    front_pick_block<kFrontThreads>(v, g, j);
+    return g;
+}
+
+__global__ __launch_bounds__(kFrontThreads) void k_front(Params p, int j) {
+    front_pick_block<kFrontThreads>(tri_front_view(p), tri_geom(p), j);
+}
+
+// The per-front pick: over the whole GPU when the mesh has its bucket
+// table, else one workgroup.
+hipError_t launch_front(const Params &p, int j, hipStream_t st) {
+    if (p.fgrid) return launch_front_grid(tri_front_view(p), tri_geom(p), p.fgrid, j, false, st);
+    k_front<<<1, kFrontThreads, 0, st>>>(p, j);
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -1194,17 +1210,18 @@ hipError_t launch_step(const Params &p, int j, hipStream_t st) {
             default: return hipErrorInvalidValue;
         }
         if (p.fold) return hipGetLastError();  // the next step (or the commit) picks
-        if (p.front_r2 > 0.0)
-            k_front<<<1, kFrontThreads, 0, st>>>(p, j);
-        else
-            k_pick<<<1, kB, 0, st>>>(p, j);
+        if (p.front_r2 > 0.0) return launch_front(p, j, st);
+        k_pick<<<1, kB, 0, st>>>(p, j);
         return hipGetLastError();
     }
     if (p.nv == 4)
         k_qforce<false><<<nb_of(p.ne), kB, 0, st>>>(p, p.u0, Eval{}, j);
     else
         k_force<false><<<nb_of(p.ne), kB, 0, st>>>(p, p.u0, Eval{}, j);
-    if (p.front_r2 > 0.0) k_front<<<1, kFrontThreads, 0, st>>>(p, j);
+    if (p.front_r2 > 0.0) {
+        const hipError_t e = launch_front(p, j, st);
+        if (e != hipSuccess) return e;
+    }
     const int nb = nb_of(p.nn);
     switch (p.nlist ? p.nlist_w : 0) {
         case 4: k_node<4><<<nb, kB, 0, st>>>(p, j); break;

@@ -306,6 +306,7 @@ void release(Model &m) {
     dfree(m.dfbucket);
     dfree(m.dfsorted);
     dfree(m.dfplist);
+    dfree(m.dfgrid);
     dfree(m.dlog);
     dfree(m.dctl);
     dfree(m.ev.sig_ek);
@@ -727,6 +728,11 @@ int finalize(Model &m, Host h) {
         TRY(h, hipMalloc((void **)&m.dfbucket, sizeof(int32_t) * nv * ne));
         TRY(h, hipMalloc((void **)&m.dfsorted, sizeof(int32_t) * nv * ne));
         TRY(h, hipMalloc((void **)&m.dfplist, sizeof(int32_t) * nv * ne));
+        if (ne >= mct::kFrontGridMinElements && std::isfinite(m.front_rho)) {
+            // the pick over the whole GPU: its two bucket tables
+            TRY(h, hipMalloc((void **)&m.dfgrid, sizeof(int32_t) * 2 * mct::kFrontGridTable));
+            TRY(h, mct::front_grid_reset(m.dfgrid, h.stream));
+        }
     }
     TRY(h, hipMalloc((void **)&m.dlog, sizeof(LogRec) * ne));
     TRY(h, hipMalloc((void **)&m.dctl, sizeof(Ctl)));
@@ -808,6 +814,7 @@ int finalize(Model &m, Host h) {
     p.fbucket = m.dfbucket;
     p.fsorted = m.dfsorted;
     p.fplist = m.dfplist;
+    p.fgrid = m.dfgrid;
     {
         // hash cell: at least rho and the largest distance between two
         // nodes of an element (two tip points of one element are closer)
@@ -1131,6 +1138,10 @@ int restore(Model &m, Host h, const void *buf, int64_t bytes) {
     TRY(h, hipStreamSynchronize(h.stream));
     TRY(h, hipMemcpy(m.dctl, &c, sizeof c, hipMemcpyHostToDevice));
     if (m.dfold_n) TRY(h, hipMemset(m.dfold_n, 0, 3 * sizeof(int32_t)));
+    if (m.dfgrid) {
+        TRY(h, front_grid_reset(m.dfgrid, h.stream));
+        TRY(h, hipStreamSynchronize(h.stream));
+    }
     TRY(h, hipMemcpy(m.du[c.base & 1], p, 16 * m.nn, hipMemcpyHostToDevice));
     p += 16 * m.nn;
     TRY(h, hipMemcpy(m.dv, p, 16 * m.nn, hipMemcpyHostToDevice));

@@ -73,6 +73,7 @@ struct Model {
     double2 *dfmid = nullptr;
     double *dflen = nullptr;
     int32_t *dforder = nullptr, *dfbucket = nullptr, *dfsorted = nullptr, *dfplist = nullptr;
+    int32_t *dfgrid = nullptr;  // bucket table of the pick over the whole GPU (large meshes)
     LogRec *dlog = nullptr;
     Ctl *dctl = nullptr;
     // query buffers (allocated on first use)

@@ -1,5 +1,7 @@
-"""Per-front pick on the GPU against the CPU oracle (Q4 grid and CST mesh):
-split logs, codes and fields bit-identical, with graph and direct launches;
+"""Per-front pick on the GPU against the CPU oracle (Q4 grid and CST mesh,
+the one-workgroup pick of small models and the pick over the whole GPU of
+models from 16 384 elements on): split logs, codes and fields
+bit-identical, with graph and direct launches;
 rho = infinity equals the global pick; errors for the combinations the
 variant excludes."""
 import math
@@ -48,6 +50,12 @@ CASES = {
     "q4_double_notch": (lambda: dict(_double_notch(), front_radius=8e-3), (64, 300, 336)),
     "cst_fragment": (lambda: dict(W.tri_small_cases()["tri_fragment"], front_radius=3e-3), (1, 99, 200)),
     "cst_cylinder": (lambda: dict(W.tri_small_cases()["tri_cylinder_coarse"], front_radius=2e-2), (64, 136, 200)),
+    # from 16 384 elements on the pick runs over the whole GPU (bucket lists
+    # in a global table, one thread per candidate): up to 145 splits per step
+    "q4_fragment_grid": (lambda: dict(W.fragmentation(200, 100, 1.0e-3, seed=W.BASE_SEED + 13, steps=300,
+                                                      name="fragment200x100"), front_radius=3e-3), (1, 99, 200)),
+    "cst_fragment_grid": (lambda: dict(W.tri_fragment(96, 90, 1.0e-3, steps=300, name="tri_fragment96x90"),
+                                       front_radius=3e-3), (1, 99, 200)),
 }
 
 
@@ -85,19 +93,29 @@ def test_infinite_radius_is_the_global_pick(gpu, oracle_mod, kind):
     assert np.array_equal(g.field(0)[0], f.field(0)[0])
 
 
-def test_front_pick_checkpoint(gpu):
-    cfg = dict(W.small_cases()["fragment97x45"], front_radius=3e-3)
+@pytest.mark.parametrize("name", ["q4_fragment", "q4_fragment_grid", "cst_fragment_grid"])
+def test_front_pick_checkpoint(gpu, name):
+    """Restored into a fresh model and into the same one (an odd number of
+    steps after the checkpoint, so that the grid pick's table of the next
+    step is the one the last step left in use)."""
+    cfg = CASES[name][0]()
     a = gpu.from_config(cfg)
     a.step(100)
     ck = a.checkpoint()
-    a.step(150)
+    a.step(151)
+    la = a.crack_set()
+    fa = a.field(0)[1]
+    assert len(la["elem"]) > 0
     b = gpu.from_config(cfg)
     b.restore(ck)
-    b.step(150)
-    la, lb = a.crack_set(), b.crack_set()
-    for k in ("step", "elem", "entry", "exit", "G"):
-        assert np.array_equal(la[k], lb[k])
-    assert np.array_equal(a.field(0)[1], b.field(0)[1])
+    b.step(151)
+    a.restore(ck)
+    a.step(151)
+    for m in (a, b):
+        lm = m.crack_set()
+        for k in ("step", "elem", "entry", "exit", "G"):
+            assert np.array_equal(la[k], lm[k]), k
+        assert np.array_equal(fa, m.field(0)[1])
 
 
 def test_front_pick_errors(gpu):
