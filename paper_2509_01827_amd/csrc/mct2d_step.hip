@@ -410,15 +410,19 @@ __global__ __launch_bounds__(TXE *TYE, UNI ? 6 : 4) void k_step(StepParamsT<T> p
     // same memory holds the element forces [8][NT]
     __shared__ T s_e[NQ];
     __shared__ T s_area[UNI ? 1 : EX * EY];
-    __shared__ T s_geo[UNI ? 36 : 1];  // lattice: crack-path geometry (a, j, {nx, ny, L})
     T *const s_fe = s_e;
     __shared__ uint8_t s_split[EX * EY];
-    __shared__ uint16_t s_cand[4 * TX * TY];
+    // candidate list; the lattice kernel keeps it in the part of s_e that
+    // the edge stresses leave free (it is dead before the forces are stored)
+    __shared__ uint16_t s_cand_own[UNI ? 1 : 4 * TX * TY];
+    static_assert(!UNI || 4 * TX * TY * sizeof(uint16_t) <= (NQ - 3 * NS) * sizeof(T), "s_cand in the tail of s_e");
+    uint16_t *const s_cand = UNI ? reinterpret_cast<uint16_t *>(s_e + 3 * NS) : s_cand_own;
     __shared__ uint16_t s_splitl[NT];
     __shared__ int s_ncand, s_ncorner, s_nthru;
     __shared__ int32_t s_tip;
     __shared__ T s_phi;
     __shared__ int s_wbase[NT / 64], s_wbase2[NT / 64], s_wbase3[NT / 64];
+    __shared__ int s_free[NT / 64];  // per wavefront: a staged element is split or outside the grid
     __shared__ CandT<T> s_red[NT / 64];
 
     const int tid = threadIdx.x;
@@ -526,16 +530,19 @@ __global__ __launch_bounds__(TXE *TYE, UNI ? 6 : 4) void k_step(StepParamsT<T> p
             }
         }
     }
+    bool free_el = false;
 #pragma unroll
     for (int r = 0; r < RE; ++r) {
         const int idx = tid + r * NT;
         if (idx < NE2) {
             s_split[idx] = rs[r];
             if constexpr (!UNI) s_area[idx] = rarea[r];
+            free_el = free_el || rs[r] != 0;
         }
     }
-    if constexpr (UNI) {
-        if (tid < 36) s_geo[tid] = (&kconst(p.lat)->geo[0][0][0])[tid];
+    {
+        const uint64_t b = __ballot(free_el);
+        if ((tid & 63) == 0) s_free[tid >> 6] = b != 0ull;
     }
     if (tid == 0) {
         s_ncand = 0;
@@ -550,8 +557,10 @@ __global__ __launch_bounds__(TXE *TYE, UNI ? 6 : 4) void k_step(StepParamsT<T> p
         const CandT<T> g = reduce_slots<NT, NEAR>(p, set_r, nprev, s_red);  // contains a barrier
         if (tid == 0 && pick_accepted(p, g)) {
             const int fx = g.e % nx - (i0 - 2), fy = g.e / nx - (j0 - 2);
-            if (fx >= 0 && fx < EX && fy >= 0 && fy < EY)
+            if (fx >= 0 && fx < EX && fy >= 0 && fy < EY) {
                 s_split[fy * EX + fx] = (uint8_t)(kSplitFlag | (g.a << 2) | g.k);
+                s_free[0] = 1;
+            }
             if (p.sct) s_tip = tip_after(p, g);
             if (leader) apply_split(p, g, base + k_rel - 1);
         }
@@ -568,6 +577,11 @@ __global__ __launch_bounds__(TXE *TYE, UNI ? 6 : 4) void k_step(StepParamsT<T> p
         }
     }
     __syncthreads();
+    // a tile without split or absent elements has no free-surface
+    // candidates and no split pieces: it skips their listing
+    bool tile_free = false;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) tile_free = tile_free || s_free[w] != 0;
 
     // reference coordinates of the staged node at offset o (lattice: read
     // from memory, only for candidates and split elements)
@@ -904,7 +918,7 @@ __global__ __launch_bounds__(TXE *TYE, UNI ? 6 : 4) void k_step(StepParamsT<T> p
     // they are not evaluated, only bounded (the judge below).
     const bool owned = ie >= 1 && je >= 1 && code == 0;
     unsigned fmask = 0, smask = 0;
-    if (owned) {
+    if (owned && tile_free) {
 #pragma unroll
         for (int k = 0; k < 4; ++k)
             if (s_split[nbr(e2, k)] != 0) {
@@ -929,7 +943,7 @@ __global__ __launch_bounds__(TXE *TYE, UNI ? 6 : 4) void k_step(StepParamsT<T> p
     const bool is_split = (code & kSplitFlag) != 0;
     const bool is_thru = is_split && ((((code & 3) - ((code >> 2) & 3)) & 3) == 2);
     const bool is_corner = is_split && !is_thru;
-    {
+    if (tile_free) {  // uniform over the workgroup
         const int lane = tid & 63, wave = tid >> 6;
         const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
         uint64_t bal[4];
@@ -1009,9 +1023,10 @@ __global__ __launch_bounds__(TXE *TYE, UNI ? 6 : 4) void k_step(StepParamsT<T> p
                 edge_sigma(edge_slot(cie, cje, k), sg);
                 if constexpr (UNI) {
                     const int gq = (a * 3 + j) * 3;
-                    nxv = s_geo[gq];
-                    nyv = s_geo[gq + 1];
-                    len = s_geo[gq + 2];
+                    const T *geo = &p.lat->geo[0][0][0];  // crack-path geometry (a, j, {nx, ny, L})
+                    nxv = geo[gq];
+                    nyv = geo[gq + 1];
+                    len = geo[gq + 2];
                 } else {
                     const int q0 = nb0 + corner(k), q1 = nb0 + corner((k + 1) & 3);
                     path_geom_pts(X1, Y1, X2, Y2, s_X[q0], s_Y[q0], s_X[q1], s_Y[q1], nxv, nyv, len);
