@@ -94,8 +94,8 @@ Q4_SOURCES = ("mct2d_step.hip", "mct2d_impl.h", "mct2d_device.h")
 TRI_SOURCES = ("mct2d_tri.hip", "mct2d_tri.h", "mct2d_front.h", "mct2d_device.h", "mct2d_impl.h")
 MEASURED_TRAFFIC = {
     # the batched lattice step kernel over the timed window (profiles/k_step_batch256_hbm_traffic.md)
-    "batch256": {"sources": Q4_SOURCES, "sha256": "c503c9474c8c19c3e21baaaca5f7b2626a5b14727f196715ff595d6653ad154f",
-                 "tile": 1, "fetch_kib": 286597.0478515625, "write_kib": 405515.7919921875},
+    "batch256": {"sources": Q4_SOURCES, "sha256": "81097b174d681abf1ac2df8c83730cb430cb69bda52276f636c9153eabbbb3b6",
+                 "tile": 1, "fetch_kib": 286612.064453125, "write_kib": 407355.82421875},
 }
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131086.604, 262144.0 / 262144.0
 
