@@ -238,9 +238,9 @@ __device__ void front_pick_block(const FrontView &v, const Geom &geo, int k_rel)
 //               the other eight cells' rows, one slot per lane, and any
 //               overflow list (lane q walks cell q's); the candidate is
 //               picked when no lane finds a competitor it fails against.
-//   k_fg_close  (one workgroup) ranks the picked ones by key (the keys
-//               staged in LDS), writes split codes and log records at
-//               their ranks and adds U_d in log order (the products G_c *
+//   k_fg_close  (one workgroup) puts the picked ones in key order (a
+//               bitonic sort in LDS), writes split codes and log records in
+//               that order and adds U_d in log order (the products G_c *
 //               path length formed in parallel, summed by one thread).
 // A candidate's decision depends only on the set of candidates, so the
 // picks, the log and U_d are those of front_pick_block, bit for bit.
@@ -248,8 +248,7 @@ __device__ void front_pick_block(const FrontView &v, const Geom &geo, int k_rel)
 constexpr int kFrontGridBlocks = 1024;
 constexpr int kFrontGridThreads = 256;
 constexpr int kFrontCloseThreads = 1024;
-constexpr int kFrontRankChunk = 1024;
-constexpr int kFrontTermChunk = 1024;
+constexpr int kFrontSortMax = 2048;
 static_assert(kFrontGridCap == 64, "one row slot per lane of a wavefront");
 
 static_assert(kFrontGridHead == kFrontGridCnt + kFrontGridBuckets, "heads follow the counts");
@@ -327,93 +326,105 @@ __device__ __forceinline__ bool front_fails(const FrontView &v, const AccCand &x
     return compete && (!acc_better(x, y) || !(x.G > v.gamma * (x.G - y.G)));
 }
 
-// The end of the pick (one workgroup of NT threads, tb the step's table).
+// Split code and log record of the picked candidate x at log position pos.
+__device__ __forceinline__ void front_record(const FrontView &v, const AccCand &x, int64_t k, int64_t pos) {
+    v.split[x.elem] = (uint8_t)(kSplitFlag | x.ak);
+    if (pos < v.log_cap) {
+        LogRec r;
+        r.step = (int32_t)k;
+        r.elem = x.elem;
+        r.entry = (uint8_t)(x.ak >> 2);
+        r.exit = (uint8_t)(x.ak & 3);
+        r.pad0 = r.pad1 = 0;
+        r.pad2 = 0;
+        r.G = x.G;
+        v.log[pos] = r;
+    }
+}
+
+// Puts the np picked candidates in key order, best first (a bitonic sort
+// over N = a power of two >= np entries, padded with keys that beat nothing:
+// G = -1, while accepted candidates have G > 0), writes their split codes
+// and log records in that order and adds their U_d terms to Ud in that
+// order.  key and cix (N entries each) are LDS or global memory; one
+// workgroup of NT threads; s_term holds kFrontSortMax doubles of LDS.
+template <int NT, class Geom>
+__device__ __forceinline__ void front_sort_close(const FrontView &v, const Geom &geo, AccCand *key, int32_t *cix,
+                                                 double *s_term, int np, int N, int64_t k, int64_t ns0,
+                                                 double &Ud) {
+    const int tid = threadIdx.x;
+    for (int j = tid; j < N; j += NT) {
+        AccCand y;
+        int32_t c = -1;
+        if (j < np) {
+            c = v.plist[j];
+            y = v.cand[c];
+        } else {
+            y.G = -1.0;
+            y.elem = 0x7fffffff;
+            y.ak = 0;
+        }
+        key[j] = y;
+        cix[j] = c;
+    }
+    __syncthreads();
+    for (int kk = 2; kk <= N; kk <<= 1)
+        for (int h = kk >> 1; h > 0; h >>= 1) {
+            for (int i = tid; i < N; i += NT) {
+                const int l = i ^ h;
+                if (l > i) {
+                    const AccCand a = key[i], b = key[l];
+                    // blocks with (i & kk) == 0 run best first
+                    if (((i & kk) == 0) ? acc_better(b, a) : acc_better(a, b)) {
+                        key[i] = b;
+                        key[l] = a;
+                        const int32_t t = cix[i];
+                        cix[i] = cix[l];
+                        cix[l] = t;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    // the picked candidates are distinct elements, so their keys are
+    // distinct and the order is the key order
+    for (int r0 = 0; r0 < np; r0 += kFrontSortMax) {
+        const int m = min(kFrontSortMax, np - r0);
+        for (int r = tid; r < m; r += NT) {
+            const AccCand x = key[r0 + r];
+            const double gc = v.gc ? v.gc[x.elem] : v.gc_uniform;
+            s_term[r] = gc * geo.path_len(x.elem, x.ak >> 2, x.ak & 3);
+            front_record(v, x, k, ns0 + r0 + r);
+        }
+        __syncthreads();
+        if (tid == 0) Ud = add_in_order(Ud, s_term, m);  // U_d in log order
+        __syncthreads();
+    }
+}
+
+// The end of the pick (one workgroup of NT threads, tb the step's table):
+// the sort runs in LDS when it fits there (and within the table's limit),
+// else in the tip-point and order scratch arrays, which the decision no
+// longer reads (N < 2 np <= 2 ne entries, within their capacity).
 template <int NT, class Geom>
 __device__ void front_grid_close(const FrontView &v, const Geom &geo, int32_t *tb, int k_rel) {
-    __shared__ __align__(16) AccCand s_key[kFrontRankChunk];
-    __shared__ double s_term[kFrontTermChunk];
+    __shared__ __align__(16) AccCand s_key[kFrontSortMax];
+    __shared__ int32_t s_cix[kFrontSortMax];
+    __shared__ double s_term[kFrontSortMax];
     const int tid = threadIdx.x;
     int32_t *np_ = tb + kFrontGridNp;
     const int np = *np_;
+    const int lds_max = tb[kFrontGridSortMax];
     const int64_t k = *v.base + k_rel;
     const int64_t ns0 = *v.nsplit;
     double Ud = *v.Ud;
     __syncthreads();  // every wave has read the counts before thread 0 resets them
-    // rank of picked candidate i among the picked (key order); with at most
-    // kFrontTermChunk picked, each one's U_d term goes to LDS at its rank
-    for (int i0 = 0; i0 < np; i0 += NT) {
-        const int i = i0 + tid;
-        int c = -1;
-        AccCand x;
-        double term = 0.0;
-        if (i < np) {
-            c = v.plist[i];
-            x = v.cand[c];
-            const double gc = v.gc ? v.gc[x.elem] : v.gc_uniform;
-            term = gc * geo.path_len(x.elem, x.ak >> 2, x.ak & 3);
-        }
-        int rank = 0;
-        for (int j0 = 0; j0 < np; j0 += kFrontRankChunk) {
-            // the chunk's keys, padded to a multiple of 8 with keys that
-            // beat nothing (G = -1; accepted candidates have G > 0)
-            const int m = min(kFrontRankChunk, np - j0);
-            const int m8 = (m + 7) & ~7;
-            __syncthreads();
-            for (int j = tid; j < m8; j += NT) {
-                AccCand y;
-                if (j < m) {
-                    y = v.cand[v.plist[j0 + j]];
-                } else {
-                    y.G = -1.0;
-                    y.elem = 0x7fffffff;
-                    y.ak = 0;
-                }
-                s_key[j] = y;
-            }
-            __syncthreads();
-            if (i < np)
-                for (int j = 0; j < m8; j += 8) {
-                    AccCand y[8];
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) y[q] = s_key[j + q];
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) rank += acc_better_i(y[q], x);
-                }
-        }
-        if (i < np) {
-            v.order[rank] = (int32_t)c;
-            if (np <= kFrontTermChunk) s_term[rank] = term;
-            v.split[x.elem] = (uint8_t)(kSplitFlag | x.ak);
-            if (ns0 + rank < v.log_cap) {
-                LogRec r;
-                r.step = (int32_t)k;
-                r.elem = x.elem;
-                r.entry = (uint8_t)(x.ak >> 2);
-                r.exit = (uint8_t)(x.ak & 3);
-                r.pad0 = r.pad1 = 0;
-                r.pad2 = 0;
-                r.G = x.G;
-                v.log[ns0 + rank] = r;
-            }
-        }
-    }
-    __syncthreads();
-    // U_d in log order
-    if (np <= kFrontTermChunk) {
-        if (tid == 0) Ud = add_in_order(Ud, s_term, np);
-    } else {
-        for (int r0 = 0; r0 < np; r0 += NT) {
-            if (r0 + tid < np) {
-                const int c = v.order[r0 + tid];
-                const int e = v.cand[c].elem;
-                const double gc = v.gc ? v.gc[e] : v.gc_uniform;
-                s_term[tid] = gc * v.len[c];
-            }
-            __syncthreads();
-            if (tid == 0) Ud = add_in_order(Ud, s_term, min(NT, np - r0));
-            __syncthreads();
-        }
-    }
+    int N = 2;
+    while (N < np) N <<= 1;
+    if (N <= lds_max && N <= kFrontSortMax)
+        front_sort_close<NT>(v, geo, s_key, s_cix, s_term, np, N, k, ns0, Ud);
+    else
+        front_sort_close<NT>(v, geo, reinterpret_cast<AccCand *>(v.mid), v.order, s_term, np, N, k, ns0, Ud);
     if (tid == 0) {
         *v.Ud = Ud;
         if (ns0 + np > v.log_cap) *v.overflow = 1;

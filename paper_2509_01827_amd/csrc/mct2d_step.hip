@@ -31,7 +31,9 @@
 #include "mct2d_impl.h"
 #include "mct2d_front.h"
 
+#include <algorithm>
 #include <climits>
+#include <cstdlib>
 #include <mutex>
 
 namespace mct {
@@ -383,6 +385,12 @@ __device__ __forceinline__ int32_t tip_after(const StepParamsT<T> &p, const Cand
 //
 // NEAR (plain models, 16 x 16 tiles): the near-threshold decision log is on;
 // the reductions also carry the second largest accepted G.
+//
+// FRONT (plain binary64 models): the per-front pick is on; every accepted
+// candidate is listed (one atomic per wavefront), and with the bucket table
+// of the pick over the whole GPU its tip point goes into the table.  The
+// NEAR instances carry the same code (the near log and the per-front pick
+// may be on together).
 template <class T, int TXE, int TYE, bool BATCHED, bool SC = false, bool UNI = false, bool NEAR = false,
           bool FRONT = false>
 __global__ __launch_bounds__(TXE *TYE, UNI ? 6 : 4) void k_step(StepParamsT<T> p0,
@@ -1047,6 +1055,9 @@ __global__ __launch_bounds__(TXE *TYE, UNI ? 6 : 4) void k_step(StepParamsT<T> p
             const T f2 = G1 > G2 ? (G1 > Gj ? G1 : Gj) : (G2 > Gj ? G2 : Gj);
             if (T(0.25) * f2 > gc * gc * T(1.0 - 1e-9)) atomicOr(p.strip, 1u);
         }
+        bool fr_app = false;  // per-front pick: an accepted candidate to append
+        double fr_G = 0.0;
+        int32_t fr_ak = 0;
         if (live && H && j == 0 && !skipped) {
             const T Gv[3] = {Gj, G1, G2};
             if constexpr (NEAR) near_candidate(p, base + k_rel, ge, a, Gv, gc);
@@ -1064,12 +1075,26 @@ __global__ __launch_bounds__(TXE *TYE, UNI ? 6 : 4) void k_step(StepParamsT<T> p
                 for (int q = 0; q < 3; ++q)
                     if (q != jb && Gv[q] > gc && !(gb > p.gamma * (gb - Gv[q]))) ok = false;
                 if (ok) cand_merge<NEAR>(best, gb, T(-1), gb, (int)ge, a, (a + 1 + jb) & 3);
-                if (ok && p.front) {  // per-front pick: every accepted candidate
-                    const uint32_t slot = atomicAdd(p.fcount, 1u);
+                if ((FRONT || NEAR) && ok && p.front) {
+                    fr_app = true;
+                    fr_G = (double)gb;
+                    fr_ak = (a << 2) | ((a + 1 + jb) & 3);
+                }
+            }
+        }
+        if ((FRONT || NEAR) && p.front) {  // uniform: the wave's accepted candidates, one atomic per wave
+            const uint64_t fm = __ballot(fr_app);
+            if (fm != 0ull) {
+                const int lane = tid & 63, first = __ffsll((unsigned long long)fm) - 1;
+                int slot0 = 0;
+                if (lane == first) slot0 = (int)atomicAdd(p.fcount, (uint32_t)__popcll(fm));
+                slot0 = __shfl(slot0, first, 64);
+                if (fr_app) {
+                    const uint32_t slot = (uint32_t)slot0 + (uint32_t)__popcll(fm & ((1ull << lane) - 1ull));
                     AccCand ac;
-                    ac.G = (double)gb;
+                    ac.G = fr_G;
                     ac.elem = (int32_t)ge;
-                    ac.ak = (a << 2) | ((a + 1 + jb) & 3);
+                    ac.ak = fr_ak;
                     p.fcand[slot] = ac;
                     if ((FRONT || NEAR) && p.fgrid) {
                         // the pick over the whole GPU: tip point (midpoint of
@@ -1357,14 +1382,22 @@ __global__ __launch_bounds__(kFrontThreads) void k_front(StepParams p, int k_rel
     front_pick_block<kFrontThreads>(q4_front_view(p), q4_geom(p), k_rel);
 }
 
-hipError_t front_grid_reset(int32_t *tables, hipStream_t s) {
+hipError_t front_grid_reset(int32_t *tables, int32_t sort_max, hipStream_t s) {
     for (int t = 0; t < 2; ++t) {
         int32_t *tb = tables + t * kFrontGridTable;
         hipError_t e = hipMemsetAsync(tb, 0, sizeof(int32_t) * kFrontGridTable, s);
         if (e == hipSuccess) e = hipMemsetAsync(tb + kFrontGridHead, 0xff, sizeof(int32_t) * kFrontGridBuckets, s);
+        if (e == hipSuccess) e = hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(tb + kFrontGridSortMax), sort_max, 1, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+int32_t front_sort_lds_max() {
+    const char *e = std::getenv("MCT_FRONT_SORT_LDS_MAX");
+    if (!e || !*e) return kFrontSortMax;
+    const long v = std::strtol(e, nullptr, 10);
+    return (int32_t)std::min<long>(std::max<long>(v, 2), kFrontSortMax);
 }
 
 // The per-front pick after the step kernel: over the whole GPU when the
@@ -1463,9 +1496,9 @@ hipError_t launch_step(int tile, const Launch &L, int k_rel, int par0, hipStream
         if (p.front) return launch_front(p, k_rel, s);
         return hipGetLastError();
     }
-    if (!L.f32 && !L.batched && L.p0.fgrid) {
-        // per-front pick over the whole GPU: the step kernels also fill the
-        // pick's bucket table
+    if (!L.f32 && !L.batched && L.p0.front) {
+        // per-front pick: the step kernels list every accepted candidate (and
+        // fill the bucket table of the pick over the whole GPU)
         const StepParams &p = L.p0;
 #define KSTEP_FRONT(TX_, TY_, NT_, SC_, UNI_) \
     k_step<double, TX_, TY_, false, SC_, UNI_, false, true><<<p.nwg, NT_, 0, s>>>(p, nullptr, nullptr, k_rel, par0)

@@ -79,6 +79,25 @@ def test_front_pick_matches_oracle(gpu, oracle_mod, name):
     print(name, "splits", len(lg["elem"]), "steps with splits", len(np.unique(lg["step"])), flush=True)
 
 
+@pytest.mark.parametrize("name", ["q4_fragment_grid", "cst_fragment_grid"])
+def test_front_pick_scratch_sort(gpu, oracle_mod, monkeypatch, name):
+    """The pick's closing sort in the scratch arrays (global memory) instead
+    of LDS, as for steps with more picked candidates than LDS holds: forced
+    from 16 picked candidates on by the testing knob MCT_FRONT_SORT_LDS_MAX,
+    read when the model is finalised."""
+    monkeypatch.setenv("MCT_FRONT_SORT_LDS_MAX", "16")
+    make, chunks = CASES[name]
+    cfg = make()
+    o = oracle_mod.Oracle(cfg)
+    m = gpu.from_config(cfg)
+    for ch in chunks:
+        o.step(ch)
+        m.step(ch)
+        m.sync()
+        _same(m, o, (name, "scratch sort"))
+    assert np.bincount(o.log()["step"]).max() > 16
+
+
 @pytest.mark.parametrize("kind", ["q4", "cst"])
 def test_infinite_radius_is_the_global_pick(gpu, oracle_mod, kind):
     cfg = W.small_cases()["fragment97x45"] if kind == "q4" else W.tri_small_cases()["tri_fragment"]
