@@ -223,7 +223,12 @@ int mct_set_tracking(mct_ctx *ctx, int mode, int32_t tip_elem, int tip_edge);
  * order.  rho = +infinity gives the global pick exactly; rho = 0 (default)
  * selects the global pick.  Plain contexts (Q4 grid or CST mesh);
  * MCT_EUNSUPPORTED on a batch or with the split-screen, MCT_EINVAL at
- * finalize together with single-tip tracking. */
+ * finalize together with single-tip tracking.  Models from 16 384 elements
+ * on (finite rho) pick over the whole GPU with two bucket tables of 16.5
+ * MiB each, allocated at finalize; the environment variable
+ * MCT_FRONT_SORT_LDS_MAX (2..2048, read at finalize and restore; a testing
+ * knob) lowers how many picked candidates of a step are sorted in LDS
+ * before the sort moves to device scratch arrays (same results). */
 int mct_set_front_pick(mct_ctx *ctx, double rho);
 
 /* Edge smoothing of Q4 elements.  MCT_SMOOTH_POINT (default): B of a
