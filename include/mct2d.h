@@ -225,10 +225,11 @@ int mct_set_tracking(mct_ctx *ctx, int mode, int32_t tip_elem, int tip_edge);
  * MCT_EUNSUPPORTED on a batch or with the split-screen, MCT_EINVAL at
  * finalize together with single-tip tracking.  Models from 16 384 elements
  * on (finite rho) pick over the whole GPU with two bucket tables of 16.5
- * MiB each, allocated at finalize; the environment variable
- * MCT_FRONT_SORT_LDS_MAX (2..2048, read at finalize and restore; a testing
- * knob) lowers how many picked candidates of a step are sorted in LDS
- * before the sort moves to device scratch arrays (same results). */
+ * MiB each, allocated at finalize.  Testing knobs (environment, read at
+ * finalize and restore; same results): MCT_FRONT_RANK_MAX (0..256) lowers
+ * up to how many picked candidates of a step are ranked by counting, and
+ * MCT_FRONT_SORT_LDS_MAX (2..2048) how many the sort holds in LDS before it
+ * moves to device scratch arrays. */
 int mct_set_front_pick(mct_ctx *ctx, double rho);
 
 /* Edge smoothing of Q4 elements.  MCT_SMOOTH_POINT (default): B of a

@@ -1445,7 +1445,7 @@ int mct_finalize(mct_ctx *c) {
         if (ne >= mct::kFrontGridMinElements && std::isfinite(c->specs[0].front_rho)) {
             // the pick over the whole GPU: its two bucket tables
             HIP_TRY(c, hipMalloc((void **)&c->dfgrid, sizeof(int32_t) * 2 * mct::kFrontGridTable));
-            HIP_TRY(c, mct::front_grid_reset(c->dfgrid, mct::front_sort_lds_max(), c->stream));
+            HIP_TRY(c, mct::front_grid_reset(c->dfgrid, c->stream));
         }
         // hash cell: at least rho and the largest distance between two nodes
         // of an element (so same-element candidates are neighbours too)
@@ -2074,7 +2074,7 @@ int mct_restore(mct_ctx *c, const void *buf, int64_t bytes) {
         p += sizeof(LogRec) * nlog;
     }
     if (int rc = narrow_state(c)) return rc;
-    if (c->dfgrid) HIP_TRY(c, mct::front_grid_reset(c->dfgrid, mct::front_sort_lds_max(), c->stream));
+    if (c->dfgrid) HIP_TRY(c, mct::front_grid_reset(c->dfgrid, c->stream));
     if (scr) {  // the screen continues where the checkpoint was taken
         const mct::ScreenDev &sd = c->sd;
         const int64_t ne = c->specs[0].ne;

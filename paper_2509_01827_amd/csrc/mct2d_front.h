@@ -238,10 +238,11 @@ __device__ void front_pick_block(const FrontView &v, const Geom &geo, int k_rel)
 //               the other eight cells' rows, one slot per lane, and any
 //               overflow list (lane q walks cell q's); the candidate is
 //               picked when no lane finds a competitor it fails against.
-//   k_fg_close  (one workgroup) puts the picked ones in key order (a
-//               bitonic sort in LDS), writes split codes and log records in
-//               that order and adds U_d in log order (the products G_c *
-//               path length formed in parallel, summed by one thread).
+//   k_fg_close  (one workgroup) puts the picked ones in key order (each
+//               ranked by counting the better keys in LDS, or for many a
+//               bitonic sort), writes split codes and log records in that
+//               order and adds U_d in log order (the products G_c * path
+//               length formed in parallel, summed by one thread).
 // A candidate's decision depends only on the set of candidates, so the
 // picks, the log and U_d are those of front_pick_block, bit for bit.
 // ------------------------------------------------------------------------
@@ -249,6 +250,7 @@ constexpr int kFrontGridBlocks = 1024;
 constexpr int kFrontGridThreads = 256;
 constexpr int kFrontCloseThreads = 1024;
 constexpr int kFrontSortMax = 2048;
+constexpr int kFrontCountMax = 256;
 static_assert(kFrontGridCap == 64, "one row slot per lane of a wavefront");
 
 static_assert(kFrontGridHead == kFrontGridCnt + kFrontGridBuckets, "heads follow the counts");
@@ -346,19 +348,22 @@ __device__ __forceinline__ void front_record(const FrontView &v, const AccCand &
 // over N = a power of two >= np entries, padded with keys that beat nothing:
 // G = -1, while accepted candidates have G > 0), writes their split codes
 // and log records in that order and adds their U_d terms to Ud in that
-// order.  key and cix (N entries each) are LDS or global memory; one
-// workgroup of NT threads; s_term holds kFrontSortMax doubles of LDS.
+// order.  key, cix and term (N entries each) are LDS or global memory; the
+// terms (G_c x path length) are formed before the sort and move with their
+// keys.  One workgroup of NT threads.
 template <int NT, class Geom>
 __device__ __forceinline__ void front_sort_close(const FrontView &v, const Geom &geo, AccCand *key, int32_t *cix,
-                                                 double *s_term, int np, int N, int64_t k, int64_t ns0,
-                                                 double &Ud) {
+                                                 double *term, int np, int N, int64_t k, int64_t ns0, double &Ud) {
     const int tid = threadIdx.x;
     for (int j = tid; j < N; j += NT) {
         AccCand y;
         int32_t c = -1;
+        double t = 0.0;
         if (j < np) {
             c = v.plist[j];
             y = v.cand[c];
+            const double gc = v.gc ? v.gc[y.elem] : v.gc_uniform;
+            t = gc * geo.path_len(y.elem, y.ak >> 2, y.ak & 3);
         } else {
             y.G = -1.0;
             y.elem = 0x7fffffff;
@@ -366,6 +371,7 @@ __device__ __forceinline__ void front_sort_close(const FrontView &v, const Geom 
         }
         key[j] = y;
         cix[j] = c;
+        term[j] = t;
     }
     __syncthreads();
     for (int kk = 2; kk <= N; kk <<= 1)
@@ -378,9 +384,12 @@ __device__ __forceinline__ void front_sort_close(const FrontView &v, const Geom 
                     if (((i & kk) == 0) ? acc_better(b, a) : acc_better(a, b)) {
                         key[i] = b;
                         key[l] = a;
-                        const int32_t t = cix[i];
+                        const int32_t c = cix[i];
                         cix[i] = cix[l];
-                        cix[l] = t;
+                        cix[l] = c;
+                        const double t = term[i];
+                        term[i] = term[l];
+                        term[l] = t;
                     }
                 }
             }
@@ -388,26 +397,20 @@ __device__ __forceinline__ void front_sort_close(const FrontView &v, const Geom 
         }
     // the picked candidates are distinct elements, so their keys are
     // distinct and the order is the key order
-    for (int r0 = 0; r0 < np; r0 += kFrontSortMax) {
-        const int m = min(kFrontSortMax, np - r0);
-        for (int r = tid; r < m; r += NT) {
-            const AccCand x = key[r0 + r];
-            const double gc = v.gc ? v.gc[x.elem] : v.gc_uniform;
-            s_term[r] = gc * geo.path_len(x.elem, x.ak >> 2, x.ak & 3);
-            front_record(v, x, k, ns0 + r0 + r);
-        }
-        __syncthreads();
-        if (tid == 0) Ud = add_in_order(Ud, s_term, m);  // U_d in log order
-        __syncthreads();
-    }
+    for (int r = tid; r < np; r += NT) front_record(v, key[r], k, ns0 + r);
+    if (tid == 0) Ud = add_in_order(Ud, term, np);  // U_d in log order
 }
 
-// The end of the pick (one workgroup of NT threads, tb the step's table):
-// the sort runs in LDS when it fits there (and within the table's limit),
-// else in the tip-point and order scratch arrays, which the decision no
-// longer reads (N < 2 np <= 2 ne entries, within their capacity).
+// The end of the pick (one workgroup of NT threads, tb the step's table).
+// Up to kFrontCountMax picked candidates (and the table's counting limit):
+// each thread ranks its own by counting the better keys (staged in LDS).
+// More: a sort, in LDS when it fits there (and within the table's sort
+// limit), else in the tip-point, order and path-length scratch arrays,
+// which the decision no longer reads (N < 2 np <= 2 ne entries, within
+// their capacity).
 template <int NT, class Geom>
 __device__ void front_grid_close(const FrontView &v, const Geom &geo, int32_t *tb, int k_rel) {
+    static_assert(kFrontCountMax <= NT && kFrontCountMax <= kFrontSortMax, "one picked candidate per thread");
     __shared__ __align__(16) AccCand s_key[kFrontSortMax];
     __shared__ int32_t s_cix[kFrontSortMax];
     __shared__ double s_term[kFrontSortMax];
@@ -415,16 +418,48 @@ __device__ void front_grid_close(const FrontView &v, const Geom &geo, int32_t *t
     int32_t *np_ = tb + kFrontGridNp;
     const int np = *np_;
     const int lds_max = tb[kFrontGridSortMax];
+    const int rank_max = tb[kFrontGridRankMax];
     const int64_t k = *v.base + k_rel;
     const int64_t ns0 = *v.nsplit;
     double Ud = *v.Ud;
     __syncthreads();  // every wave has read the counts before thread 0 resets them
     int N = 2;
     while (N < np) N <<= 1;
-    if (N <= lds_max && N <= kFrontSortMax)
+    if (np <= rank_max && np <= kFrontCountMax) {
+        // keys padded to a multiple of 8 as in the sort
+        const int np8 = (np + 7) & ~7;
+        AccCand x;
+        double t = 0.0;
+        if (tid < np) {
+            x = v.cand[v.plist[tid]];
+            const double gc = v.gc ? v.gc[x.elem] : v.gc_uniform;
+            t = gc * geo.path_len(x.elem, x.ak >> 2, x.ak & 3);
+        } else {
+            x.G = -1.0;
+            x.elem = 0x7fffffff;
+            x.ak = 0;
+        }
+        if (tid < np8) s_key[tid] = x;
+        __syncthreads();
+        if (tid < np) {
+            int rank = 0;
+            for (int j = 0; j < np8; j += 8) {
+                AccCand y[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) y[q] = s_key[j + q];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) rank += acc_better_i(y[q], x);
+            }
+            s_term[rank] = t;
+            front_record(v, x, k, ns0 + rank);
+        }
+        __syncthreads();
+        if (tid == 0) Ud = add_in_order(Ud, s_term, np);  // U_d in log order
+    } else if (N <= lds_max && N <= kFrontSortMax) {
         front_sort_close<NT>(v, geo, s_key, s_cix, s_term, np, N, k, ns0, Ud);
-    else
-        front_sort_close<NT>(v, geo, reinterpret_cast<AccCand *>(v.mid), v.order, s_term, np, N, k, ns0, Ud);
+    } else {
+        front_sort_close<NT>(v, geo, reinterpret_cast<AccCand *>(v.mid), v.order, v.len, np, N, k, ns0, Ud);
+    }
     if (tid == 0) {
         *v.Ud = Ud;
         if (ns0 + np > v.log_cap) *v.overflow = 1;

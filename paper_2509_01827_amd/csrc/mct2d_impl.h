@@ -34,8 +34,8 @@ static_assert(sizeof(AccCand) == 16, "AccCand layout");
 // kFrontGridMinElements elements on (with a finite radius; smaller models
 // and rho = infinity take one workgroup).  Two int32 tables, one per step
 // parity, each: per bucket the number of candidates and the head of its
-// overflow list, the picked count, the close's LDS sort limit, then
-// kFrontGridCap candidate indices per bucket.  Step k uses table k & 1 and clears the other one (counts 0,
+// overflow list, the picked count, the close's LDS sort and counting-rank
+// limits, then kFrontGridCap candidate indices per bucket.  Step k uses table k & 1 and clears the other one (counts 0,
 // heads -1) for step k + 1; the picked count returns to 0 at the end of
 // each pick.
 constexpr int kFrontGridBuckets = 1 << 16;
@@ -44,16 +44,19 @@ constexpr int64_t kFrontGridCnt = 0;
 constexpr int64_t kFrontGridHead = kFrontGridBuckets;
 constexpr int64_t kFrontGridNp = 2 * (int64_t)kFrontGridBuckets;
 constexpr int64_t kFrontGridSortMax = kFrontGridNp + 1;  // LDS entries the close may sort in
+constexpr int64_t kFrontGridRankMax = kFrontGridNp + 2;  // picked counts the close ranks by counting
 constexpr int64_t kFrontGridTab = 2 * (int64_t)kFrontGridBuckets + 64;
 constexpr int64_t kFrontGridTable = kFrontGridTab + (int64_t)kFrontGridBuckets * kFrontGridCap;
 constexpr int64_t kFrontGridMinElements = 1 << 14;
-// both tables as the first pick expects them (after allocation, restore);
-// sort_max: the close's LDS sort limit (entries, at most kFrontSortMax in
-// mct2d_front.h; smaller limits send more picks through the scratch arrays)
-hipError_t front_grid_reset(int32_t *tables, int32_t sort_max, hipStream_t s);
-// the sort limit: MCT_FRONT_SORT_LDS_MAX from the environment (a testing
-// knob, 2..2048), else 2048
-int32_t front_sort_lds_max();
+// both tables as the first pick expects them (after allocation, restore),
+// with the close's limits from front_close_limits
+hipError_t front_grid_reset(int32_t *tables, hipStream_t s);
+// The close's limits (testing knobs from the environment, read here):
+// MCT_FRONT_SORT_LDS_MAX (2..2048, default 2048), how many entries its sort
+// may hold in LDS before it moves to the scratch arrays, and
+// MCT_FRONT_RANK_MAX (0..256, default 256), up to how many picked
+// candidates it ranks by counting instead of sorting.
+void front_close_limits(int32_t *sort_lds_max, int32_t *rank_max);
 
 // Per-workgroup best candidate of one step (only workgroups with an
 // accepted candidate write one).

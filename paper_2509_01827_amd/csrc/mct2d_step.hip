@@ -1382,22 +1382,29 @@ __global__ __launch_bounds__(kFrontThreads) void k_front(StepParams p, int k_rel
     front_pick_block<kFrontThreads>(q4_front_view(p), q4_geom(p), k_rel);
 }
 
-hipError_t front_grid_reset(int32_t *tables, int32_t sort_max, hipStream_t s) {
+static int32_t env_limit(const char *name, long lo, long hi, long dflt) {
+    const char *e = std::getenv(name);
+    if (!e || !*e) return (int32_t)dflt;
+    return (int32_t)std::min<long>(std::max<long>(std::strtol(e, nullptr, 10), lo), hi);
+}
+
+void front_close_limits(int32_t *sort_lds_max, int32_t *rank_max) {
+    *sort_lds_max = env_limit("MCT_FRONT_SORT_LDS_MAX", 2, kFrontSortMax, kFrontSortMax);
+    *rank_max = env_limit("MCT_FRONT_RANK_MAX", 0, kFrontCountMax, kFrontCountMax);
+}
+
+hipError_t front_grid_reset(int32_t *tables, hipStream_t s) {
+    int32_t sort_max, rank_max;
+    front_close_limits(&sort_max, &rank_max);
     for (int t = 0; t < 2; ++t) {
         int32_t *tb = tables + t * kFrontGridTable;
         hipError_t e = hipMemsetAsync(tb, 0, sizeof(int32_t) * kFrontGridTable, s);
         if (e == hipSuccess) e = hipMemsetAsync(tb + kFrontGridHead, 0xff, sizeof(int32_t) * kFrontGridBuckets, s);
         if (e == hipSuccess) e = hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(tb + kFrontGridSortMax), sort_max, 1, s);
+        if (e == hipSuccess) e = hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(tb + kFrontGridRankMax), rank_max, 1, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
-}
-
-int32_t front_sort_lds_max() {
-    const char *e = std::getenv("MCT_FRONT_SORT_LDS_MAX");
-    if (!e || !*e) return kFrontSortMax;
-    const long v = std::strtol(e, nullptr, 10);
-    return (int32_t)std::min<long>(std::max<long>(v, 2), kFrontSortMax);
 }
 
 // The per-front pick after the step kernel: over the whole GPU when the

@@ -731,7 +731,7 @@ int finalize(Model &m, Host h) {
         if (ne >= mct::kFrontGridMinElements && std::isfinite(m.front_rho)) {
             // the pick over the whole GPU: its two bucket tables
             TRY(h, hipMalloc((void **)&m.dfgrid, sizeof(int32_t) * 2 * mct::kFrontGridTable));
-            TRY(h, mct::front_grid_reset(m.dfgrid, mct::front_sort_lds_max(), h.stream));
+            TRY(h, mct::front_grid_reset(m.dfgrid, h.stream));
         }
     }
     TRY(h, hipMalloc((void **)&m.dlog, sizeof(LogRec) * ne));
@@ -1139,7 +1139,7 @@ int restore(Model &m, Host h, const void *buf, int64_t bytes) {
     TRY(h, hipMemcpy(m.dctl, &c, sizeof c, hipMemcpyHostToDevice));
     if (m.dfold_n) TRY(h, hipMemset(m.dfold_n, 0, 3 * sizeof(int32_t)));
     if (m.dfgrid) {
-        TRY(h, front_grid_reset(m.dfgrid, front_sort_lds_max(), h.stream));
+        TRY(h, front_grid_reset(m.dfgrid, h.stream));
         TRY(h, hipStreamSynchronize(h.stream));
     }
     TRY(h, hipMemcpy(m.du[c.base & 1], p, 16 * m.nn, hipMemcpyHostToDevice));

@@ -80,12 +80,17 @@ def test_front_pick_matches_oracle(gpu, oracle_mod, name):
 
 
 @pytest.mark.parametrize("name", ["q4_fragment_grid", "cst_fragment_grid"])
-def test_front_pick_scratch_sort(gpu, oracle_mod, monkeypatch, name):
-    """The pick's closing sort in the scratch arrays (global memory) instead
-    of LDS, as for steps with more picked candidates than LDS holds: forced
-    from 16 picked candidates on by the testing knob MCT_FRONT_SORT_LDS_MAX,
-    read when the model is finalised."""
-    monkeypatch.setenv("MCT_FRONT_SORT_LDS_MAX", "16")
+@pytest.mark.parametrize("limits", [("0", "2048"), ("4", "16")], ids=["lds_sort", "all_paths"])
+def test_front_pick_close_paths(gpu, oracle_mod, monkeypatch, name, limits):
+    """The pick's close takes three paths by the number of picked candidates
+    of a step: ranking by counting (up to 256), a sort in LDS, a sort in the
+    scratch arrays (global memory).  The testing knobs MCT_FRONT_RANK_MAX and
+    MCT_FRONT_SORT_LDS_MAX, read when the model is finalised, lower the
+    limits so that small steps take the other paths: every step sorts in
+    LDS, or steps with up to 4 picks count, up to 16 sort in LDS and more
+    sort in global memory."""
+    monkeypatch.setenv("MCT_FRONT_RANK_MAX", limits[0])
+    monkeypatch.setenv("MCT_FRONT_SORT_LDS_MAX", limits[1])
     make, chunks = CASES[name]
     cfg = make()
     o = oracle_mod.Oracle(cfg)
@@ -94,8 +99,9 @@ def test_front_pick_scratch_sort(gpu, oracle_mod, monkeypatch, name):
         o.step(ch)
         m.step(ch)
         m.sync()
-        _same(m, o, (name, "scratch sort"))
-    assert np.bincount(o.log()["step"]).max() > 16
+        _same(m, o, (name, limits))
+    per_step = np.bincount(o.log()["step"])
+    assert per_step.max() > 16 and np.any((per_step > 4) & (per_step <= 16))
 
 
 @pytest.mark.parametrize("kind", ["q4", "cst"])
