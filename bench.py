@@ -94,7 +94,7 @@ Q4_SOURCES = ("mct2d_step.hip", "mct2d_impl.h", "mct2d_device.h")
 TRI_SOURCES = ("mct2d_tri.hip", "mct2d_tri.h", "mct2d_front.h", "mct2d_device.h", "mct2d_impl.h")
 MEASURED_TRAFFIC = {
     # the batched lattice step kernel over the timed window (profiles/k_step_batch256_hbm_traffic.md)
-    "batch256": {"sources": Q4_SOURCES, "sha256": "af3200e203192cfa15657b62439e60c1ef2596c3444d7a5b87b834a3ca910804",
+    "batch256": {"sources": Q4_SOURCES, "sha256": "108c332c567ebe9f1623b934559234294a2c7c704a500b8c585e7aa72bc3364c",
                  "tile": 1, "fetch_kib": 286606.654296875, "write_kib": 407108.041015625},
 }
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131086.604, 262144.0 / 262144.0
