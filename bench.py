@@ -280,7 +280,7 @@ def main():
         print(json.dumps({"q4": kernel_sha256(Q4_SOURCES), "tri": kernel_sha256(TRI_SOURCES)}))
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d refused)" % args.gpus,
+        print("bench.py measures one GPU: the library has no multi-GPU path (--gpus %d refused)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
     if args.copy_probe:

@@ -31,7 +31,7 @@
  *     its element splits the tip moves to the exit edge.
  *   - Explicit formulation: Sec. 2 opening sentence.
  *
- * Readings where the paper is silent (each is listed in the design doc):
+ * Readings where the paper is silent (the same readings as the library's):
  *   - B of element j at edge g_s is the isoparametric Q4 gradient evaluated
  *     at the midpoint of that edge in j's natural coordinates (reference
  *     configuration, small strain).
