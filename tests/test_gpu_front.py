@@ -56,6 +56,12 @@ CASES = {
                                                       name="fragment200x100"), front_radius=3e-3), (1, 99, 200)),
     "cst_fragment_grid": (lambda: dict(W.tri_fragment(96, 90, 1.0e-3, steps=300, name="tri_fragment96x90"),
                                        front_radius=3e-3), (1, 99, 200)),
+    # a radius of a quarter of the plate: a few cells hold thousands of
+    # accepted candidates, so the 64-slot bucket rows overflow into lists
+    "q4_fragment_grid_wide": (lambda: dict(W.fragmentation(200, 100, 1.0e-3, seed=W.BASE_SEED + 13, steps=300,
+                                                           name="fragment200x100"), front_radius=5e-2), (1, 99, 200)),
+    "cst_fragment_grid_wide": (lambda: dict(W.tri_fragment(96, 90, 1.0e-3, steps=300, name="tri_fragment96x90"),
+                                            front_radius=5e-2), (1, 99, 200)),
 }
 
 
