@@ -237,12 +237,13 @@ __device__ void front_pick_block(const FrontView &v, const Geom &geo, int k_rel)
 //   k_fg_decide (a wavefront per candidate) the own cell's row first, then
 //               the other eight cells' rows, one slot per lane, and any
 //               overflow list (lane q walks cell q's); the candidate is
-//               picked when no lane finds a competitor it fails against.
+//               picked when no lane finds a competitor it fails against,
+//               and listed with its U_d term (G_c * path length) beside it.
 //   k_fg_close  (one workgroup) puts the picked ones in key order (each
 //               ranked by counting the better keys in LDS, or for many a
 //               bitonic sort), writes split codes and log records in that
-//               order and adds U_d in log order (the products G_c * path
-//               length formed in parallel, summed by one thread).
+//               order and adds U_d in log order (the decision's products
+//               G_c * path length, summed by one thread).
 // A candidate's decision depends only on the set of candidates, so the
 // picks, the log and U_d are those of front_pick_block, bit for bit.
 // ------------------------------------------------------------------------
@@ -349,8 +350,8 @@ __device__ __forceinline__ void front_record(const FrontView &v, const AccCand &
 // G = -1, while accepted candidates have G > 0), writes their split codes
 // and log records in that order and adds their U_d terms to Ud in that
 // order.  key, cix and term (N entries each) are LDS or global memory; the
-// terms (G_c x path length) are formed before the sort and move with their
-// keys.  One workgroup of NT threads.
+// terms (G_c x path length, stored by the decision beside each picked
+// candidate) move with their keys.  One workgroup of NT threads.
 template <int NT, class Geom>
 __device__ __forceinline__ void front_sort_close(const FrontView &v, const Geom &geo, AccCand *key, int32_t *cix,
                                                  double *term, int np, int N, int64_t k, int64_t ns0, double &Ud) {
@@ -362,8 +363,7 @@ __device__ __forceinline__ void front_sort_close(const FrontView &v, const Geom 
         if (j < np) {
             c = v.plist[j];
             y = v.cand[c];
-            const double gc = v.gc ? v.gc[y.elem] : v.gc_uniform;
-            t = gc * geo.path_len(y.elem, y.ak >> 2, y.ak & 3);
+            t = v.len[j];  // the decision's U_d term of picked candidate j
         } else {
             y.G = -1.0;
             y.elem = 0x7fffffff;
@@ -432,8 +432,7 @@ __device__ void front_grid_close(const FrontView &v, const Geom &geo, int32_t *t
         double t = 0.0;
         if (tid < np) {
             x = v.cand[v.plist[tid]];
-            const double gc = v.gc ? v.gc[x.elem] : v.gc_uniform;
-            t = gc * geo.path_len(x.elem, x.ak >> 2, x.ak & 3);
+            t = v.len[tid];
         } else {
             x.G = -1.0;
             x.elem = 0x7fffffff;
@@ -469,7 +468,8 @@ __device__ void front_grid_close(const FrontView &v, const Geom &geo, int32_t *t
     }
 }
 
-__global__ __launch_bounds__(kFrontGridThreads) void k_fg_decide(FrontView v, int32_t *tables, int k_rel) {
+template <class Geom>
+__global__ __launch_bounds__(kFrontGridThreads) void k_fg_decide(FrontView v, Geom geo, int32_t *tables, int k_rel) {
     int32_t *tb = front_table(v, tables, k_rel);
     const uint32_t n = *v.count;
     const int lane = threadIdx.x & 63;
@@ -504,7 +504,13 @@ __global__ __launch_bounds__(kFrontGridThreads) void k_fg_decide(FrontView v, in
             for (; walk >= 0 && !fail; walk = v.sorted[walk])
                 if (front_fails(v, x, pc, (int)c, walk)) fail = true;
         }
-        if (__ballot(fail) == 0ull && lane == 0) v.plist[atomicAdd(&tb[kFrontGridNp], 1)] = (int32_t)c;
+        if (__ballot(fail) == 0ull && lane == 0) {
+            // picked: listed, with its U_d term G_c x path length beside it
+            const int i = atomicAdd(&tb[kFrontGridNp], 1);
+            v.plist[i] = (int32_t)c;
+            const double gc = v.gc ? v.gc[x.elem] : v.gc_uniform;
+            v.len[i] = gc * geo.path_len(x.elem, x.ak >> 2, x.ak & 3);
+        }
     }
 }
 
@@ -524,7 +530,7 @@ template <class Geom>
 hipError_t launch_front_grid(const FrontView &v, const Geom &g, int32_t *tables, int k_rel, bool prepped,
                              hipStream_t st) {
     if (!prepped) k_fg_prep<Geom><<<kFrontGridBlocks, kFrontGridThreads, 0, st>>>(v, g, tables, k_rel);
-    k_fg_decide<<<kFrontGridBlocks, kFrontGridThreads, 0, st>>>(v, tables, k_rel);
+    k_fg_decide<Geom><<<kFrontGridBlocks, kFrontGridThreads, 0, st>>>(v, g, tables, k_rel);
     k_fg_close<Geom><<<1, kFrontCloseThreads, 0, st>>>(v, g, tables, k_rel);
     return hipGetLastError();
 }
