@@ -352,9 +352,9 @@ __device__ __forceinline__ void front_record(const FrontView &v, const AccCand &
 // order.  key, cix and term (N entries each) are LDS or global memory; the
 // terms (G_c x path length, stored by the decision beside each picked
 // candidate) move with their keys.  One workgroup of NT threads.
-template <int NT, class Geom>
-__device__ __forceinline__ void front_sort_close(const FrontView &v, const Geom &geo, AccCand *key, int32_t *cix,
-                                                 double *term, int np, int N, int64_t k, int64_t ns0, double &Ud) {
+template <int NT>
+__device__ __forceinline__ void front_sort_close(const FrontView &v, AccCand *key, int32_t *cix, double *term, int np,
+                                                 int N, int64_t k, int64_t ns0, double &Ud) {
     const int tid = threadIdx.x;
     for (int j = tid; j < N; j += NT) {
         AccCand y;
@@ -408,8 +408,8 @@ __device__ __forceinline__ void front_sort_close(const FrontView &v, const Geom 
 // limit), else in the tip-point, order and path-length scratch arrays,
 // which the decision no longer reads (N < 2 np <= 2 ne entries, within
 // their capacity).
-template <int NT, class Geom>
-__device__ void front_grid_close(const FrontView &v, const Geom &geo, int32_t *tb, int k_rel) {
+template <int NT>
+__device__ void front_grid_close(const FrontView &v, int32_t *tb, int k_rel) {
     static_assert(kFrontCountMax <= NT && kFrontCountMax <= kFrontSortMax, "one picked candidate per thread");
     __shared__ __align__(16) AccCand s_key[kFrontSortMax];
     __shared__ int32_t s_cix[kFrontSortMax];
@@ -455,9 +455,9 @@ __device__ void front_grid_close(const FrontView &v, const Geom &geo, int32_t *t
         __syncthreads();
         if (tid == 0) Ud = add_in_order(Ud, s_term, np);  // U_d in log order
     } else if (N <= lds_max && N <= kFrontSortMax) {
-        front_sort_close<NT>(v, geo, s_key, s_cix, s_term, np, N, k, ns0, Ud);
+        front_sort_close<NT>(v, s_key, s_cix, s_term, np, N, k, ns0, Ud);
     } else {
-        front_sort_close<NT>(v, geo, reinterpret_cast<AccCand *>(v.mid), v.order, v.len, np, N, k, ns0, Ud);
+        front_sort_close<NT>(v, reinterpret_cast<AccCand *>(v.mid), v.order, v.len, np, N, k, ns0, Ud);
     }
     if (tid == 0) {
         *v.Ud = Ud;
@@ -514,10 +514,9 @@ __global__ __launch_bounds__(kFrontGridThreads) void k_fg_decide(FrontView v, Ge
     }
 }
 
-template <class Geom>
-__global__ __launch_bounds__(kFrontCloseThreads) void k_fg_close(FrontView v, Geom geo, int32_t *tables, int k_rel) {
+__global__ __launch_bounds__(kFrontCloseThreads) void k_fg_close(FrontView v, int32_t *tables, int k_rel) {
     if (*v.count == 0) return;  // uniform; the count is reset by thread 0 after a barrier
-    front_grid_close<kFrontCloseThreads>(v, geo, front_table(v, tables, k_rel), k_rel);
+    front_grid_close<kFrontCloseThreads>(v, front_table(v, tables, k_rel), k_rel);
 }
 
 }  // namespace
@@ -531,7 +530,7 @@ hipError_t launch_front_grid(const FrontView &v, const Geom &g, int32_t *tables,
                              hipStream_t st) {
     if (!prepped) k_fg_prep<Geom><<<kFrontGridBlocks, kFrontGridThreads, 0, st>>>(v, g, tables, k_rel);
     k_fg_decide<Geom><<<kFrontGridBlocks, kFrontGridThreads, 0, st>>>(v, g, tables, k_rel);
-    k_fg_close<Geom><<<1, kFrontCloseThreads, 0, st>>>(v, g, tables, k_rel);
+    k_fg_close<<<1, kFrontCloseThreads, 0, st>>>(v, tables, k_rel);
     return hipGetLastError();
 }
 
