@@ -420,26 +420,39 @@ __global__ __launch_bounds__(TXE *TYE, UNI ? 6 : 4) void k_step(StepParamsT<T> p
     __shared__ T s_area[UNI ? 1 : EX * EY];
     T *const s_fe = s_e;
     __shared__ uint8_t s_split[EX * EY];
-    // candidate list; the lattice kernel keeps it in the part of s_e that
-    // the edge stresses leave free (it is dead before the forces are stored)
-    __shared__ uint16_t s_cand_own[UNI ? 1 : 4 * TX * TY];
-    static_assert(!UNI || 4 * TX * TY * sizeof(uint16_t) <= (NQ - 3 * NS) * sizeof(T), "s_cand in the tail of s_e");
-    uint16_t *const s_cand = UNI ? reinterpret_cast<uint16_t *>(s_e + 3 * NS) : s_cand_own;
+    __shared__ uint16_t s_cand_own[UNI ? 1 : 4 * TX * TY];  // candidate list
     __shared__ uint16_t s_splitl[NT];
     __shared__ int s_ncand, s_ncorner, s_nthru;
     __shared__ int32_t s_tip;
     __shared__ T s_phi;
-    __shared__ int s_wbase[NT / 64], s_wbase2[NT / 64], s_wbase3[NT / 64];
-    __shared__ int s_free[NT / 64];  // per wavefront: a staged element is split or outside the grid
-    __shared__ CandT<T> s_red[NT / 64];
+    // per wavefront: list offsets of the compaction, and whether a staged
+    // element is split or outside the grid; the reduction of candidates
+    __shared__ int s_wb_own[UNI ? 1 : 4 * (NT / 64)];
+    __shared__ CandT<T> s_red_own[UNI ? 1 : NT / 64];
+    // The lattice kernel keeps the list and these small arrays in the part
+    // of s_e that the edge stresses leave free (none of them is live when
+    // the forces are stored there).
+    constexpr int kTailCand = 4 * TX * TY * (int)sizeof(uint16_t);
+    constexpr int kTailRed = (kTailCand + 15) & ~15;
+    constexpr int kTailWb = kTailRed + (NT / 64) * (int)sizeof(CandT<T>);
+    constexpr int kTailEnd = kTailWb + 4 * (NT / 64) * (int)sizeof(int);
+    static_assert(!UNI || kTailEnd <= (NQ - 3 * NS) * (int)sizeof(T), "small arrays in the tail of s_e");
+    char *const s_tail = reinterpret_cast<char *>(s_e + 3 * NS);
+    uint16_t *const s_cand = UNI ? reinterpret_cast<uint16_t *>(s_tail) : s_cand_own;
+    CandT<T> *const s_red = UNI ? reinterpret_cast<CandT<T> *>(s_tail + kTailRed) : s_red_own;
+    int *const s_wbase = UNI ? reinterpret_cast<int *>(s_tail + kTailWb) : s_wb_own;
+    int *const s_wbase2 = s_wbase + NT / 64, *const s_wbase3 = s_wbase + 2 * (NT / 64);
+    int *const s_free = s_wbase + 3 * (NT / 64);
 
     const int tid = threadIdx.x;
     int tile;
     StepParamsT<T> p;
+    const StepParamsT<T> *vsrc = nullptr;  // batch: the specimen's view
     if constexpr (BATCHED) {
         const __attribute__((address_space(4))) int *uu = kconst(reinterpret_cast<const int *>(units));
         const int2 u = make_int2(uu[2 * blockIdx.x], uu[2 * blockIdx.x + 1]);
-        load_view(p, views + u.x);
+        vsrc = views + u.x;
+        load_view(p, vsrc);
         tile = u.y;
     } else {
         p = p0;
@@ -1228,6 +1241,18 @@ __global__ __launch_bounds__(TXE *TYE, UNI ? 6 : 4) void k_step(StepParamsT<T> p
         }
 
         // ---- 7. central-difference update of the owned node --------------
+        if constexpr (BATCHED) {
+            // the output pointers read from the view again (as for the
+            // publication below)
+            const StepParamsT<T> *v2 = vsrc;
+            int par2 = par0 + k_rel;
+            asm volatile("" : "+s"(v2), "+s"(par2));
+            const __attribute__((address_space(4))) StepParamsT<T> *w = kconst(v2);
+            p.vx = w->vx;
+            p.vy = w->vy;
+            ux_n = (par2 & 1) ? w->ux0 : w->ux1;
+            uy_n = (par2 & 1) ? w->uy0 : w->uy1;
+        }
         const int64_t kabs = base + k_rel;
         const int hidx = (on_m + 2) * HX + (on_l + 2);
         const T phi = s_phi;
@@ -1251,6 +1276,18 @@ __global__ __launch_bounds__(TXE *TYE, UNI ? 6 : 4) void k_step(StepParamsT<T> p
     // Read by the next step after the kernel boundary; no fence here (a
     // device-scope release would write back the whole L2 of the XCD).
     if (tid == 0 && best.G >= T(0) && !p.front) {
+        if constexpr (BATCHED) {
+            // a batch reads these from the view again (the pointer made
+            // opaque, so that the loads are not merged with the ones at the
+            // start): scalar registers are short, and held across the step
+            // these would be spilled
+            const StepParamsT<T> *v2 = vsrc;
+            asm volatile("" : "+s"(v2));
+            const __attribute__((address_space(4))) StepParamsT<T> *w = kconst(v2);
+            p.ctl = w->ctl;
+            p.slots = w->slots;
+            p.nwg = w->nwg;
+        }
         const uint32_t slot = atomicAdd(&p.ctl->nslots[set_w], 1u);
         Slot sl;
         sl.G = (double)best.G;
