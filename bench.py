@@ -94,7 +94,7 @@ Q4_SOURCES = ("mct2d_step.hip", "mct2d_impl.h", "mct2d_device.h")
 TRI_SOURCES = ("mct2d_tri.hip", "mct2d_tri.h", "mct2d_front.h", "mct2d_device.h", "mct2d_impl.h")
 MEASURED_TRAFFIC = {
     # the batched lattice step kernel over the timed window (profiles/k_step_batch256_hbm_traffic.md)
-    "batch256": {"sources": Q4_SOURCES, "sha256": "0d10731be65d1ab94ac8cc224ca04d07069937dfb3099cb0c69c0ec302639c97",
+    "batch256": {"sources": Q4_SOURCES, "sha256": "0be1dd5dbc91c01e5a3c4180b502f3022bb21a0a5fecd3af32a219a3f8110831",
                  "tile": 1, "fetch_kib": 286603.1083984375, "write_kib": 407268.94677734375},
 }
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131086.604, 262144.0 / 262144.0

@@ -390,10 +390,13 @@ int mct_restore(mct_ctx *ctx, const void *host_buf, int64_t bytes);
  * node kernel; 2, 3, 4 = one fused kernel over patches of 64, 128, 256
  * consecutive nodes (element forces summed in LDS; used when its tables fit:
  * at most 16 elements at a node and 1024 in a patch, else the split
- * kernels); 0 = automatic (fused on 64-node patches below 2^18 triangles,
- * split above).  Results do not depend on any of these choices
- * (fixed summation orders).  Errors: MCT_EINVAL for a tile index out of
- * range. */
+ * kernels); 5 = the fused kernel on the largest patches (64 to 256 nodes)
+ * that hold at most 256 elements each; 0 = automatic (5).  The environment
+ * variable MCT_PATCH_NODES, read when the choice is made, sets the patch
+ * size of choice 5 instead (1..256 nodes; a testing and tuning knob).
+ * Results do not depend on any of these choices (fixed summation orders).
+ * Errors: MCT_EINVAL for a tile index out of range (0..5 on a triangle
+ * mesh). */
 int mct_set_launch(mct_ctx *ctx, int tile, int use_graph);
 
 /* Batch of independent specimens (same step, one launch per time step over
@@ -466,14 +469,16 @@ int mct_get_near_log(mct_ctx *ctx, int64_t cap, int32_t *step, int32_t *elem, ui
  * a batch, every unit order) from the current state, restores that state
  * and keeps the fastest choice.  On an unstructured mesh the choices are
  * the step kernels of mct_set_launch (triangles: 1 the element plus node
- * kernels, 2/3/4 the fused kernel on 64/128/256-node patches;
+ * kernels, 2/3/4 the fused kernel on 64/128/256-node patches, 5 on patches
+ * of the size it finds;
  * quadrilaterals: 1 only).  Outputs (any may be NULL): the chosen tile (as
  * mct_get_launch reports it), order and its time per step in
  * microseconds. */
 int mct_autotune(mct_ctx *ctx, int trial_steps, int *tile, int *order, double *us_per_step);
 
 /* Launch shape in use: tile index, unit order, workgroups per step (on a
- * triangle mesh: the step kernels in use, 1 split or 2..4 fused, never 0;
+ * triangle mesh: the step kernels in use, 1 split, 2..4 fused on 64..256-node
+ * patches or 5 fused on patches of another size, never 0;
  * the workgroups of the fused kernel or of the element kernel). */
 int mct_get_launch(mct_ctx *ctx, int *tile, int *order, int64_t *workgroups);
 

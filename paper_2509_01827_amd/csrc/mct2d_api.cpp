@@ -1163,8 +1163,9 @@ int mct_set_time(mct_ctx *c, double dt, double cfl_fraction) {
 int mct_set_launch(mct_ctx *c, int tile, int use_graph) {
     if (!c) return MCT_EINVAL;
     if (c->tri) {
-        // tile = step kernels: 0 automatic, 1 split, 2..4 fused on 64..256-node patches
-        if (tile < 0 || tile > 4) return fail(c, MCT_EINVAL, "a triangle mesh takes tile 0..4 (step kernels)");
+        // tile = step kernels: 0 automatic, 1 split, 2..4 fused on 64..256-node
+        // patches, 5 fused on patches of the size it finds
+        if (tile < 0 || tile > 5) return fail(c, MCT_EINVAL, "a triangle mesh takes tile 0..5 (step kernels)");
         c->tri->use_graph = use_graph != 0;
         return mct::tri::set_kernels(*c->tri, mct::tri::Host{c->err, c->stream}, tile);
     }
@@ -2110,10 +2111,19 @@ int mct_restore(mct_ctx *c, const void *buf, int64_t bytes) {
     return MCT_OK;
 }
 
+// The step kernels in use on an unstructured mesh as a launch index: 1 split
+// (workgroups of the element kernel), 2/3/4 fused on 64/128/256-node
+// patches, 5 fused on patches of another size;
+// workgroups of the fused kernel = patches.
+static int tri_launch_index(const mct::tri::Model &m) {
+    const int P = m.prm.patch_emax > 0 ? m.prm.patch_nodes : 0;
+    return P == 0 ? 1 : P == 64 ? 2 : P == 128 ? 3 : P == 256 ? 4 : 5;
+}
+
 // The autotuner of an unstructured mesh: every step-kernel choice (the
 // element plus node kernels; for triangles also the fused kernel on 64-,
-// 128- and 256-node patches) timed from the current state, which is then
-// restored; the fastest choice is kept.
+// 128- and 256-node patches and on patches of the size it finds) timed from
+// the current state, which is then restored; the fastest choice is kept.
 static int autotune_unstructured(mct_ctx *c, int trial_steps, int *tile_out, int *order_out,
                                  double *us_per_step_out) {
     mct::tri::Model &m = *c->tri;
@@ -2130,7 +2140,7 @@ static int autotune_unstructured(mct_ctx *c, int trial_steps, int *tile_out, int
     m.use_graph = false;  // candidates are timed with direct launches
     float best = INFINITY;
     int best_kind = 1;
-    const int nkinds = m.nv == 3 ? 4 : 1;
+    const int nkinds = m.nv == 3 ? 5 : 1;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = MCT_EDEVICE;
     for (int kind = 1; kind <= nkinds && rc == MCT_OK; ++kind) {
@@ -2158,8 +2168,7 @@ static int autotune_unstructured(mct_ctx *c, int trial_steps, int *tile_out, int
     }
     if ((rc = mct::tri::set_kernels(m, h, best_kind))) return rc;
     if ((rc = mct::tri::restore(m, h, ck.data(), bytes))) return rc;
-    const int P = m.prm.patch_emax > 0 ? m.prm.patch_nodes : 0;
-    if (tile_out) *tile_out = P == 64 ? 2 : P == 128 ? 3 : P == 256 ? 4 : 1;
+    if (tile_out) *tile_out = tri_launch_index(m);
     if (order_out) *order_out = 0;
     if (us_per_step_out) *us_per_step_out = 1e3 * (double)best / trial_steps;
     return MCT_OK;
@@ -2225,10 +2234,8 @@ int mct_autotune(mct_ctx *c, int trial_steps, int *tile_out, int *order_out, dou
 int mct_get_launch(mct_ctx *c, int *tile, int *order, int64_t *workgroups) {
     if (!c) return MCT_EINVAL;
     if (c->tri) {
-        // the kernels in use: 1 split (workgroups of the element kernel),
-        // 2/3/4 fused on 64/128/256-node patches (workgroups = patches)
         const int P = c->tri->prm.patch_emax > 0 ? c->tri->prm.patch_nodes : 0;
-        if (tile) *tile = P == 64 ? 2 : P == 128 ? 3 : P == 256 ? 4 : 1;
+        if (tile) *tile = tri_launch_index(*c->tri);
         if (order) *order = 0;
         if (workgroups) *workgroups = P ? (c->tri->nn + P - 1) / P : (c->tri->ne + 255) / 256;
         return MCT_OK;

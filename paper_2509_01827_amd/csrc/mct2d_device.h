@@ -14,6 +14,16 @@ __device__ __forceinline__ double eta_n(int n) { return (n >= 2) ? 1.0 : -1.0; }
 __device__ __forceinline__ double xi_m(int k) { return k == 1 ? 1.0 : (k == 3 ? -1.0 : 0.0); }
 __device__ __forceinline__ double eta_m(int k) { return k == 0 ? -1.0 : (k == 2 ? 1.0 : 0.0); }
 
+// Map workgroups onto work blocks (tiles, runs of elements or nodes) so that
+// consecutive workgroups of one XCD (the hardware deals workgroup ids
+// round-robin over the 8 XCDs) own a contiguous band of blocks and share the
+// lines at the band's inner borders in their L2.  A bijection of [0, nwg).
+__device__ __forceinline__ int xcd_tile(int b, int nwg) {
+    const int q = nwg / 8, r = nwg % 8;
+    const int x = b % 8, l = b / 8;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + l;
+}
+
 // Pointer parameters that may receive nullptr take their type from another
 // argument.
 template <class T>

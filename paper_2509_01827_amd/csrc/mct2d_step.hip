@@ -134,15 +134,6 @@ __device__ __forceinline__ int perimeter_index(int i, int j, int nx, int ny) {
     return -1;
 }
 
-// Map workgroups onto tiles so that consecutive workgroups of one XCD (the
-// hardware deals workgroup ids round-robin over the 8 XCDs) own a
-// contiguous band of tiles and share halo lines in their L2.
-__device__ __forceinline__ int xcd_tile(int b, int nwg) {
-    const int q = nwg / 8, r = nwg % 8;
-    const int x = b % 8, l = b / 8;
-    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + l;
-}
-
 // Read-only data the whole launch shares (a batch's unit table and views,
 // the lattice constants): read through the constant address space, so that
 // a workgroup-uniform address becomes a scalar load.

@@ -28,7 +28,7 @@ struct Ctl {
 };
 static_assert(sizeof(Ctl) == 40, "Ctl layout");
 
-constexpr int64_t kFusedMaxElems = 1 << 18;  // automatic choice: fused step below this size
+constexpr int kPatchMaxNodes = 256;  // fused step: one node per thread of its workgroup
 constexpr int32_t kOwned = 1 << 30;    // patch element flag: evaluate its candidates here
 
 // Node flags (one byte per node).
@@ -73,7 +73,7 @@ struct Params {
     // their candidates) and per owned node its force slots in the patch's LDS
     // (3 slot + local node, 0xffff = none), node-major, nlist_w per node
     int32_t patch_emax;      // largest patch element count (0: fused step off)
-    int32_t patch_nodes;     // 64, 128 or 256
+    int32_t patch_nodes;     // 64, 128, 256 or the found size (at most kPatchMaxNodes)
     const int32_t *patch_off;
     const int32_t *patch_elem;
     const uint16_t *patch_slots;

@@ -38,6 +38,7 @@ namespace tri {
 namespace {
 
 constexpr int kB = 256;
+static_assert(kPatchMaxNodes <= kB, "a fused patch has one node per thread");
 
 int nb_of(int64_t n) { return (int)((n + kB - 1) / kB > 0 ? (n + kB - 1) / kB : 1); }
 
@@ -614,7 +615,7 @@ __device__ __forceinline__ void element_force(const Params &p, const SplitView &
 // Element pass.  eval: query mode (u given, outputs in ev, no candidates).
 template <bool EVAL>
 __global__ __launch_bounds__(kB) void k_force(Params p, const double2 *u, Eval ev, int j) {
-    const int e = blockIdx.x * kB + threadIdx.x;
+    const int e = dev::xcd_tile(blockIdx.x, gridDim.x) * kB + threadIdx.x;
     if (e >= p.ne) return;
     if constexpr (!EVAL) {
         if (((p.ctl->base + j) & 1) != 0) u = p.u1;  // u^k
@@ -719,7 +720,7 @@ __global__ __launch_bounds__(kB) void k_force(Params p, const double2 *u, Eval e
 // Element pass of a quadrilateral mesh (as k_force).
 template <bool EVAL>
 __global__ __launch_bounds__(kB) void k_qforce(Params p, const double2 *u, Eval ev, int j) {
-    const int e = blockIdx.x * kB + threadIdx.x;
+    const int e = dev::xcd_tile(blockIdx.x, gridDim.x) * kB + threadIdx.x;
     if (e >= p.ne) return;
     if constexpr (!EVAL) {
         if (((p.ctl->base + j) & 1) != 0) u = p.u1;  // u^k
@@ -906,7 +907,7 @@ __global__ __launch_bounds__(kB) void k_node(Params p, int j) {
     if (blockIdx.x == 0) pick(p, k);
     if (threadIdx.x == 0) s_phi = load_factor(p, (double)k * p.dt);
     __syncthreads();
-    const int i = blockIdx.x * kB + threadIdx.x;
+    const int i = dev::xcd_tile(blockIdx.x, gridDim.x) * kB + threadIdx.x;
     if (i >= p.nn) return;
     const double2 f = gather<W>(p, i);
     const uint8_t fl = p.nflag[i];
@@ -947,7 +948,7 @@ __global__ __launch_bounds__(kB) void k_fused(Params p, int j) {
     const int64_t k = p.ctl->base + j;
     const bool odd = (k & 1) != 0;
     const double2 *u = odd ? p.u1 : p.u0;
-    const int b = blockIdx.x, tid = threadIdx.x;
+    const int b = dev::xcd_tile(blockIdx.x, gridDim.x), tid = threadIdx.x;
     Cand *clist = p.cand;
     int32_t *ccount = &p.ctl->nacc;
     if (p.fold) {
@@ -1196,7 +1197,7 @@ hipError_t launch_front(const Params &p, int j, hipStream_t st) {
 
 hipError_t launch_step(const Params &p, int j, hipStream_t st) {
     if (p.patch_emax > 0) {
-        if (p.nv != 3 || p.patch_nodes < 1 || p.patch_nodes > kB || p.patch_emax > 1024) return hipErrorInvalidValue;
+        if (p.nv != 3 || p.patch_nodes < 1 || p.patch_nodes > kPatchMaxNodes || p.patch_emax > 1024) return hipErrorInvalidValue;
         const int np = (p.nn + p.patch_nodes - 1) / p.patch_nodes;
         const int key = p.nlist_w * 4 + (p.patch_emax <= 256 ? 0 : p.patch_emax <= 512 ? 1 : 2);
         switch (key) {

@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 
@@ -221,13 +222,38 @@ int build_patches(Model &m, Host h, int P, int32_t *emax_out) {
     return MCT_OK;
 }
 
+// Patch size of the fused step: the largest patch (64 to kPatchMaxNodes
+// nodes) whose patches all hold at most 256 elements.  Such patches keep the
+// LDS, and with it the occupancy, of the smallest kernel instance and
+// compute their elements in one pass of the workgroup; among them the
+// largest leave the fewest border elements computed twice and the fewest
+// partly idle wavefronts.  Found from 128 nodes down, each try scaled by
+// 256 over the element count of the fullest patch; the environment variable
+// MCT_PATCH_NODES sets the size instead (a testing and tuning knob).  Leaves
+// the tables of the chosen size built; emax 0 when they do not fit.
+int sized_patches(Model &m, Host h, int *P_out, int32_t *emax) {
+    int64_t P = 128;
+    if (const char *e = std::getenv("MCT_PATCH_NODES"); e && *e) {
+        P = std::min<int64_t>(std::max<long>(std::strtol(e, nullptr, 10), 1), kPatchMaxNodes);
+        *P_out = (int)P;
+        return build_patches(m, h, (int)P, emax);
+    }
+    for (;;) {
+        int rc = build_patches(m, h, (int)P, emax);
+        if (rc) return rc;
+        if (*emax <= 256 || P == 64) {  // fits (or, emax 0, the tables never do)
+            *P_out = (int)P;
+            return MCT_OK;
+        }
+        P = std::max<int64_t>(64, std::min<int64_t>(P - 1, P * 256 / *emax));
+    }
+}
+
 // Step kernels from the requested choice: 1 split kernels; 2, 3, 4 the fused
-// kernel on patches of 64, 128, 256 nodes; 0 automatic: fused on 64-node
-// patches below kFusedMaxElems elements (the launch it saves is a large part
-// of a short step), split above (the element kernel keeps more waves in
-// flight than the patches, and the redundant border elements cost more than
-// the force hand-off).  A fused choice whose tables do not fit runs the split
-// kernels.
+// kernel on patches of 64, 128, 256 nodes; 5 and 0 (automatic) the fused
+// kernel on patches of the size sized_patches finds.  A fused choice
+// whose tables do not fit runs the split kernels.  Quadrilaterals take the
+// split kernels.
 int choose_kernels(Model &m, Host h) {
     Params &p = m.prm;
     p.patch_emax = 0;
@@ -235,13 +261,13 @@ int choose_kernels(Model &m, Host h) {
     p.fold = 0;
     int P = 0;
     if (m.nv != 3) return MCT_OK;  // quadrilaterals: the split kernels
-    if (m.kernels >= 2)
+    if (m.kernels >= 2 && m.kernels <= 4)
         P = 64 << (m.kernels - 2);
-    else if (m.kernels == 0 && m.ne < kFusedMaxElems)
-        P = 64;
+    else if (m.kernels == 0 || m.kernels == 5)
+        P = -1;
     if (P == 0 || !m.dnlist) return MCT_OK;
     int32_t emax = 0;
-    int rc = build_patches(m, h, P, &emax);
+    int rc = P > 0 ? build_patches(m, h, P, &emax) : sized_patches(m, h, &P, &emax);
     if (rc) return rc;
     if (emax == 0) return MCT_OK;
     p.patch_emax = emax;
@@ -872,7 +898,7 @@ int step(Model &m, Host h, int64_t n) {
 }
 
 int set_kernels(Model &m, Host h, int kind) {
-    if (kind < 0 || kind > 4) return fail(h, MCT_EINVAL, "step kernel choice %d out of range (0..4)", kind);
+    if (kind < 0 || kind > 5) return fail(h, MCT_EINVAL, "step kernel choice %d out of range (0..5)", kind);
     m.kernels = kind;
     if (!m.finalized) return MCT_OK;
     if (m.graph) {

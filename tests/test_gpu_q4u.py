@@ -263,7 +263,7 @@ def test_unstructured_autotune(gpu, oracle_mod, kind):
     o.step(400)
     r = m.autotune(trial_steps=30)
     print(kind, r, flush=True)
-    assert r["tile"] in ((1,) if kind == "q4u" else (1, 2, 3, 4)) and r["us_per_step"] > 0
+    assert r["tile"] in ((1,) if kind == "q4u" else (1, 2, 3, 4, 5)) and r["us_per_step"] > 0
     assert m.launch()["tile"] == r["tile"]
     assert m.info()["step"] == 400
     _same(m, o, (kind, "after autotune"))

@@ -41,12 +41,25 @@ def _same(m, o, label):
 
 
 @pytest.mark.parametrize("name", sorted(W.tri_small_cases()))
-def test_tri_matches_oracle(gpu, oracle_mod, name):
+def test_tri_matches_oracle(gpu, oracle_mod, name, monkeypatch):
     cfg = W.tri_small_cases()[name]
     o = oracle_mod.Oracle(cfg)
     # split step kernels (1), fused on 64-, 128-, 256-node patches (2, 3, 4)
     models = [gpu.from_config(cfg, tile=t, use_graph=g) for t in (1, 2, 3, 4) for g in (True, False)]
     assert [m.launch()["tile"] for m in models] == [1, 1, 2, 2, 3, 3, 4, 4]
+    # fused on 77-node patches (not a multiple of the wavefront, the last one
+    # ragged), and on patches of the size the library finds
+    nn = models[0].info()["n_nodes"]
+    monkeypatch.setenv("MCT_PATCH_NODES", "77")
+    sized = [gpu.from_config(cfg, tile=5, use_graph=g) for g in (True, False)]
+    monkeypatch.delenv("MCT_PATCH_NODES")
+    for m in sized:
+        lau = m.launch()
+        assert lau["tile"] == 5 and lau["workgroups"] == -(-nn // 77), lau
+    auto = gpu.from_config(cfg)
+    assert auto.launch()["tile"] in (2, 3, 5), auto.launch()
+    print(name, "automatic patches", auto.launch(), flush=True)
+    models += sized + [auto]
     inf = models[0].info()
     assert (inf["n_nodes"], inf["n_elems"], inf["n_edges"]) == (o.info()["nn"], o.info()["ne"], o.info()["ns"])
     assert inf["dt"] == o.info()["dt"]
@@ -214,7 +227,7 @@ def test_tri_invalid_meshes(gpu):
     with pytest.raises(gpu.MctError):  # a node in no triangle
         m.set_mesh_tri(np.append(X, 2.0), np.append(Y, 2.0), good)
     m.set_mesh_tri(X, Y, good)
-    for bad in (-1, 5):  # step kernel choices are 0..4
+    for bad in (-1, 6):  # step kernel choices are 0..5
         with pytest.raises(gpu.MctError):
             m.set_launch(bad, True)
     with pytest.raises(gpu.MctError):  # notch local edges are 0..2
@@ -230,11 +243,15 @@ def test_tri_fullsize_plate_sampled(gpu, oracle_mod):
     cfg = W.tri_plate320k()
     o = oracle_mod.Oracle(cfg)
     m = gpu.from_config(cfg)
-    assert m.launch()["tile"] == 1  # the automatic choice at this size (split kernels), as timed
-    f = gpu.from_config(cfg, tile=2)  # and the fused kernel on 64-node patches
-    assert f.launch()["tile"] == 2
+    # the automatic choice (the fused kernel on its largest patches of at most
+    # 256 elements), as timed
+    assert m.launch()["tile"] == 5, m.launch()
+    s = gpu.from_config(cfg, tile=1)  # the split kernels
+    f = gpu.from_config(cfg, tile=2)  # the fused kernel on 64-node patches
+    assert s.launch()["tile"] == 1 and f.launch()["tile"] == 2
     o.step(300)
-    m.step(300)
-    f.step(300)
-    _same(m, o, "tri_plate320k")
+    for x in (m, s, f):
+        x.step(300)
+    _same(m, o, "tri_plate320k sized patches")
+    _same(s, o, "tri_plate320k split")
     _same(f, o, "tri_plate320k fused")
