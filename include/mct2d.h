@@ -158,9 +158,9 @@ int mct_set_mesh_tri(mct_ctx *ctx, int64_t n_nodes, const double *X, const doubl
  * Split codes and crack records use these local edges (entry/exit in 0..3).
  * Ids are the caller's (no renumbering).  After this call every set-up call,
  * step and query below applies to this mesh as for mct_set_mesh_tri, with
- * the same exceptions; the step always runs the element kernel plus the
- * node kernel (mct_set_launch tile 2..4 falls back to them), and sub-cell
- * smoothing is for structured grids only.  Errors: as mct_set_mesh_tri, and
+ * the same exceptions (the step kernels are chosen as on a triangle mesh,
+ * by mct_set_launch), and sub-cell smoothing is for structured grids
+ * only.  Errors: as mct_set_mesh_tri, and
  * MCT_EINVAL for a quadrilateral that is not convex (every corner turning
  * left). */
 int mct_set_mesh_q4(mct_ctx *ctx, int64_t n_nodes, const double *X, const double *Y, int64_t n_elems,
@@ -385,18 +385,19 @@ int mct_restore(mct_ctx *ctx, const void *host_buf, int64_t bytes);
 
 /* Launch tuning: tile shape index (0 = automatic, which is 16x16; 1 = 16x16, 2 = 32x8,
  * 3 = 32x16 elements per workgroup) and whether mct_step replays captured
- * HIP graphs (1, default) or launches kernel by kernel (0).  On a triangle
- * mesh the tile index selects the step kernels: 1 = an element kernel and a
- * node kernel; 2, 3, 4 = one fused kernel over patches of 64, 128, 256
+ * HIP graphs (1, default) or launches kernel by kernel (0).  On an
+ * unstructured mesh (triangles or quadrilaterals) the tile index selects the
+ * step kernels: 1 = an element kernel and a node kernel; 2, 3, 4 = one fused kernel over patches of 64, 128, 256
  * consecutive nodes (element forces summed in LDS; used when its tables fit:
  * at most 16 elements at a node and 1024 in a patch, else the split
  * kernels); 5 = the fused kernel on the largest patches (64 to 256 nodes)
- * that hold at most 256 elements each; 0 = automatic (5).  The environment
+ * that hold at most 256 elements each; 0 = automatic (5 on triangles, 1 on
+ * quadrilaterals).  The environment
  * variable MCT_PATCH_NODES, read when the choice is made, sets the patch
  * size of choice 5 instead (1..256 nodes; a testing and tuning knob).
  * Results do not depend on any of these choices (fixed summation orders).
- * Errors: MCT_EINVAL for a tile index out of range (0..5 on a triangle
- * mesh). */
+ * Errors: MCT_EINVAL for a tile index out of range (0..5 on an
+ * unstructured mesh). */
 int mct_set_launch(mct_ctx *ctx, int tile, int use_graph);
 
 /* Batch of independent specimens (same step, one launch per time step over
@@ -468,17 +469,16 @@ int mct_get_near_log(mct_ctx *ctx, int64_t cap, int32_t *step, int32_t *elem, ui
 /* Launch autotuner: times trial_steps steps for every tile shape (and, for
  * a batch, every unit order) from the current state, restores that state
  * and keeps the fastest choice.  On an unstructured mesh the choices are
- * the step kernels of mct_set_launch (triangles: 1 the element plus node
- * kernels, 2/3/4 the fused kernel on 64/128/256-node patches, 5 on patches
- * of the size it finds;
- * quadrilaterals: 1 only).  Outputs (any may be NULL): the chosen tile (as
+ * the step kernels of mct_set_launch (1 the element plus node kernels,
+ * 2/3/4 the fused kernel on 64/128/256-node patches, 5 on patches of the
+ * size it finds).  Outputs (any may be NULL): the chosen tile (as
  * mct_get_launch reports it), order and its time per step in
  * microseconds. */
 int mct_autotune(mct_ctx *ctx, int trial_steps, int *tile, int *order, double *us_per_step);
 
 /* Launch shape in use: tile index, unit order, workgroups per step (on a
- * triangle mesh: the step kernels in use, 1 split, 2..4 fused on 64..256-node
- * patches or 5 fused on patches of another size, never 0;
+ * unstructured mesh: the step kernels in use, 1 split, 2..4 fused on
+ * 64..256-node patches or 5 fused on patches of another size, never 0;
  * the workgroups of the fused kernel or of the element kernel). */
 int mct_get_launch(mct_ctx *ctx, int *tile, int *order, int64_t *workgroups);
 

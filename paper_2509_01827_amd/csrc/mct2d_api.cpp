@@ -1165,7 +1165,7 @@ int mct_set_launch(mct_ctx *c, int tile, int use_graph) {
     if (c->tri) {
         // tile = step kernels: 0 automatic, 1 split, 2..4 fused on 64..256-node
         // patches, 5 fused on patches of the size it finds
-        if (tile < 0 || tile > 5) return fail(c, MCT_EINVAL, "a triangle mesh takes tile 0..5 (step kernels)");
+        if (tile < 0 || tile > 5) return fail(c, MCT_EINVAL, "an unstructured mesh takes tile 0..5 (step kernels)");
         c->tri->use_graph = use_graph != 0;
         return mct::tri::set_kernels(*c->tri, mct::tri::Host{c->err, c->stream}, tile);
     }
@@ -2121,8 +2121,8 @@ static int tri_launch_index(const mct::tri::Model &m) {
 }
 
 // The autotuner of an unstructured mesh: every step-kernel choice (the
-// element plus node kernels; for triangles also the fused kernel on 64-,
-// 128- and 256-node patches and on patches of the size it finds) timed from
+// element plus node kernels, the fused kernel on 64-, 128- and 256-node
+// patches and on patches of the size it finds) timed from
 // the current state, which is then restored; the fastest choice is kept.
 static int autotune_unstructured(mct_ctx *c, int trial_steps, int *tile_out, int *order_out,
                                  double *us_per_step_out) {
@@ -2140,7 +2140,7 @@ static int autotune_unstructured(mct_ctx *c, int trial_steps, int *tile_out, int
     m.use_graph = false;  // candidates are timed with direct launches
     float best = INFINITY;
     int best_kind = 1;
-    const int nkinds = m.nv == 3 ? 5 : 1;
+    const int nkinds = 5;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = MCT_EDEVICE;
     for (int kind = 1; kind <= nkinds && rc == MCT_OK; ++kind) {

@@ -339,7 +339,7 @@ __device__ __forceinline__ double quad_split(const Params &p, const double2 ue[4
 }
 
 // Everything a quadrilateral element contributes to one pass: its four
-// nodal forces into the slot-major force array, with `cands` its crack-tip
+// nodal forces (force of local node n at fe[n fs]), with `cands` its crack-tip
 // candidates, with EVAL the query outputs.  An intact element computes the
 // strain of each local edge k at the edge's midpoint from its own nodes and,
 // if the neighbour across k is intact, that of the neighbour at the same
@@ -352,11 +352,10 @@ __device__ __forceinline__ double quad_split(const Params &p, const double2 ue[4
 // four-edge element rule (Sec. 2.2).
 template <bool EVAL>
 __device__ __forceinline__ void quad_element(const Params &p, const SplitView &sv, const double2 *u, int e,
-                                             bool cands, Cand *clist, int32_t *ccount, const Eval &ev) {
+                                             bool cands, Cand *clist, int32_t *ccount, const Eval &ev,
+                                             double2 *fe, int64_t fs) {
     const int4 c = p.conn[e];
     const uint8_t code = sv(e);
-    double2 *fe = p.fe + e;
-    const int64_t fs = p.ne;
     double2 ue[4], xe[4];
     ue[0] = u[c.x];
     ue[1] = u[c.y];
@@ -725,7 +724,8 @@ __global__ __launch_bounds__(kB) void k_qforce(Params p, const double2 *u, Eval 
     if constexpr (!EVAL) {
         if (((p.ctl->base + j) & 1) != 0) u = p.u1;  // u^k
     }
-    quad_element<EVAL>(p, SplitView{p.split, -1, 0}, u, e, !EVAL, p.cand, &p.ctl->nacc, ev);
+    // slot-major element forces: node slot n of element e at fe[n ne + e]
+    quad_element<EVAL>(p, SplitView{p.split, -1, 0}, u, e, !EVAL, p.cand, &p.ctl->nacc, ev, p.fe + e, p.ne);
 }
 
 __device__ __forceinline__ double load_factor(const Params &p, double t) {
@@ -933,15 +933,16 @@ __global__ __launch_bounds__(kB) void k_node(Params p, int j) {
     (odd ? p.u0 : p.u1)[i] = make_double2(u.x + p.dt * vx, u.y + p.dt * vy);
 }
 
-// Fused step of one patch of patch_nodes consecutive nodes: the forces of every
+// Fused step of one patch of patch_nodes consecutive nodes (NV nodes per
+// element: 3 triangles, 4 quadrilaterals): the forces of every
 // element touching the patch (elements on patch borders are computed by
 // each patch they touch; only the owning patch evaluates their candidates)
 // go to LDS, then every owned node sums its slots in colour order and is
 // updated.  u^k is read from buffer k & 1 and u^{k+1} written to the other,
 // so neighbouring workgroups never see a half-updated displacement.
-template <int W, int EMAX>
+template <int NV, int W, int EMAX>
 __global__ __launch_bounds__(kB) void k_fused(Params p, int j) {
-    __shared__ double2 s_f[3 * EMAX];
+    __shared__ double2 s_f[NV * EMAX];
     __shared__ double s_phi;
     __shared__ int s_pe;
     __shared__ uint8_t s_pcode;
@@ -961,7 +962,7 @@ __global__ __launch_bounds__(kB) void k_fused(Params p, int j) {
         if (n > 0) {
             Cand bst;
             double gmin;
-            best_of(p.fold_cand + (int64_t)prev * 3 * p.ne, n, bst, gmin);
+            best_of(p.fold_cand + (int64_t)prev * NV * p.ne, n, bst, gmin);
             if (tid == 0 && bst.G > p.gamma * (bst.G - gmin)) {
                 s_pe = bst.elem;
                 s_pcode = (uint8_t)(kSplitFlag | bst.ak);
@@ -971,19 +972,23 @@ __global__ __launch_bounds__(kB) void k_fused(Params p, int j) {
         // set (j + 1) mod 3 was last read by step j - 1: clear it for step j + 1
         if (b == 0 && tid == 0) p.fold_n[(j + 1) % 3] = 0;
         __syncthreads();
-        clist = p.fold_cand + (int64_t)(j % 3) * 3 * p.ne;
+        clist = p.fold_cand + (int64_t)(j % 3) * NV * p.ne;
         ccount = p.fold_n + j % 3;
     }
     const SplitView sv{p.split, p.fold ? s_pe : -1, p.fold ? s_pcode : (uint8_t)0};
     const int s0 = p.patch_off[b], s1 = p.patch_off[b + 1];
     for (int s = s0 + tid; s < s1; s += kB) {
         const int32_t rec = p.patch_elem[s];
-        double2 f[3];
-        element_force(p, sv, u, rec & (kOwned - 1), (rec & kOwned) != 0, clist, ccount, f);
-        const int l = 3 * (s - s0);
-        s_f[l] = f[0];
-        s_f[l + 1] = f[1];
-        s_f[l + 2] = f[2];
+        const int l = NV * (s - s0);
+        if constexpr (NV == 3) {
+            double2 f[3];
+            element_force(p, sv, u, rec & (kOwned - 1), (rec & kOwned) != 0, clist, ccount, f);
+            s_f[l] = f[0];
+            s_f[l + 1] = f[1];
+            s_f[l + 2] = f[2];
+        } else {
+            quad_element<false>(p, sv, u, rec & (kOwned - 1), (rec & kOwned) != 0, clist, ccount, Eval{}, s_f + l, 1);
+        }
     }
     if (tid == 0) s_phi = load_factor(p, (double)k * p.dt);
     __syncthreads();
@@ -1035,7 +1040,7 @@ __global__ __launch_bounds__(kB) void k_commit_fold(Params p, int n) {
     const int64_t base = p.ctl->base;
     if (n > 0) {
         const int set = (n + 2) % 3;
-        pick_from(p, p.fold_cand + (int64_t)set * 3 * p.ne, p.fold_n + set, base + n - 1);
+        pick_from(p, p.fold_cand + (int64_t)set * p.nv * p.ne, p.fold_n + set, base + n - 1);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1197,16 +1202,18 @@ hipError_t launch_front(const Params &p, int j, hipStream_t st) {
 
 hipError_t launch_step(const Params &p, int j, hipStream_t st) {
     if (p.patch_emax > 0) {
-        if (p.nv != 3 || p.patch_nodes < 1 || p.patch_nodes > kPatchMaxNodes || p.patch_emax > 1024) return hipErrorInvalidValue;
+        if ((p.nv != 3 && p.nv != 4) || p.patch_nodes < 1 || p.patch_nodes > kPatchMaxNodes ||
+            p.patch_emax > 1024)
+            return hipErrorInvalidValue;
         const int np = (p.nn + p.patch_nodes - 1) / p.patch_nodes;
-        const int key = p.nlist_w * 4 + (p.patch_emax <= 256 ? 0 : p.patch_emax <= 512 ? 1 : 2);
+        const int key = (p.nv * 32 + p.nlist_w) * 4 + (p.patch_emax <= 256 ? 0 : p.patch_emax <= 512 ? 1 : 2);
         switch (key) {
-#define FUSED(Wv, E, kk) \
-    case Wv * 4 + kk: k_fused<Wv, E><<<np, kB, 0, st>>>(p, j); break;
-            FUSED(4, 256, 0) FUSED(4, 512, 1) FUSED(4, 1024, 2)
-            FUSED(8, 256, 0) FUSED(8, 512, 1) FUSED(8, 1024, 2)
-            FUSED(12, 256, 0) FUSED(12, 512, 1) FUSED(12, 1024, 2)
-            FUSED(16, 256, 0) FUSED(16, 512, 1) FUSED(16, 1024, 2)
+#define FUSED(NVv, Wv, E, kk) \
+    case (NVv * 32 + Wv) * 4 + kk: k_fused<NVv, Wv, E><<<np, kB, 0, st>>>(p, j); break;
+#define FUSED_W(NVv, Wv) FUSED(NVv, Wv, 256, 0) FUSED(NVv, Wv, 512, 1) FUSED(NVv, Wv, 1024, 2)
+            FUSED_W(3, 4) FUSED_W(3, 8) FUSED_W(3, 12) FUSED_W(3, 16)
+            FUSED_W(4, 4) FUSED_W(4, 8) FUSED_W(4, 12) FUSED_W(4, 16)
+#undef FUSED_W
 #undef FUSED
             default: return hipErrorInvalidValue;
         }

@@ -166,7 +166,8 @@ int eval_state(Model &m, Host h, Ctl *ctl, bool with_energy) {
     return MCT_OK;
 }
 
-// Fused-step tables for patches of P consecutive nodes (one workgroup each):
+// Fused-step tables for patches of P consecutive nodes (one workgroup each;
+// triangles or quadrilaterals, nv nodes per element):
 // the patch's elements (every element touching an owned node, ascending id,
 // flagged kOwned in the patch of its smallest node, which alone evaluates its
 // candidates) and, per owned node, the LDS slots of its element forces in
@@ -176,6 +177,7 @@ int eval_state(Model &m, Host h, Ctl *ctl, bool with_energy) {
 int build_patches(Model &m, Host h, int P, int32_t *emax_out) {
     *emax_out = 0;
     const int64_t nn = m.nn, ne = m.ne;
+    const int nv = m.nv;
     const std::vector<int32_t> &noff = m.gnoff, &nel = m.gnel;
     int32_t maxdeg = 0;
     for (int64_t i = 0; i < nn; ++i) maxdeg = std::max(maxdeg, noff[i + 1] - noff[i]);
@@ -190,7 +192,7 @@ int build_patches(Model &m, Host h, int P, int32_t *emax_out) {
         els.clear();
         for (int64_t i = n0; i < n1; ++i)
             for (int32_t t = noff[i]; t < noff[i + 1]; ++t) {
-                const int32_t e = nel[t] / 3;
+                const int32_t e = nel[t] / nv;
                 if (stamp[e] != (int32_t)b) {
                     stamp[e] = (int32_t)b;
                     els.push_back(e);
@@ -202,13 +204,13 @@ int build_patches(Model &m, Host h, int P, int32_t *emax_out) {
         for (size_t q = 0; q < els.size(); ++q) {
             const int32_t e = els[q];
             slot_of[e] = (int32_t)q;
-            const int32_t mn = std::min(m.conn[3 * e], std::min(m.conn[3 * e + 1], m.conn[3 * e + 2]));
+            const int32_t mn = *std::min_element(m.conn.begin() + (int64_t)nv * e, m.conn.begin() + (int64_t)nv * (e + 1));
             pelem.push_back(e | (mn / P == b ? kOwned : 0));
         }
         poff.push_back((int32_t)pelem.size());
         for (int64_t i = n0; i < n1; ++i)
             for (int32_t t = noff[i]; t < noff[i + 1]; ++t)
-                pslots[(size_t)i * W + (t - noff[i])] = (uint16_t)(3 * slot_of[nel[t] / 3] + nel[t] % 3);
+                pslots[(size_t)i * W + (t - noff[i])] = (uint16_t)(nv * slot_of[nel[t] / nv] + nel[t] % nv);
     }
     dfree(m.dpatch_off);
     dfree(m.dpatch_elem);
@@ -227,12 +229,12 @@ int build_patches(Model &m, Host h, int P, int32_t *emax_out) {
 // LDS, and with it the occupancy, of the smallest kernel instance and
 // compute their elements in one pass of the workgroup; among them the
 // largest leave the fewest border elements computed twice and the fewest
-// partly idle wavefronts.  Found from 128 nodes down, each try scaled by
+// partly idle wavefronts.  Found from kPatchMaxNodes down, each try scaled by
 // 256 over the element count of the fullest patch; the environment variable
 // MCT_PATCH_NODES sets the size instead (a testing and tuning knob).  Leaves
 // the tables of the chosen size built; emax 0 when they do not fit.
 int sized_patches(Model &m, Host h, int *P_out, int32_t *emax) {
-    int64_t P = 128;
+    int64_t P = kPatchMaxNodes;
     if (const char *e = std::getenv("MCT_PATCH_NODES"); e && *e) {
         P = std::min<int64_t>(std::max<long>(std::strtol(e, nullptr, 10), 1), kPatchMaxNodes);
         *P_out = (int)P;
@@ -251,19 +253,20 @@ int sized_patches(Model &m, Host h, int *P_out, int32_t *emax) {
 
 // Step kernels from the requested choice: 1 split kernels; 2, 3, 4 the fused
 // kernel on patches of 64, 128, 256 nodes; 5 and 0 (automatic) the fused
-// kernel on patches of the size sized_patches finds.  A fused choice
-// whose tables do not fit runs the split kernels.  Quadrilaterals take the
-// split kernels.
+// kernel on patches of the size sized_patches finds; 0 (automatic) is 5 on
+// triangles and 1 on quadrilaterals (whose element needs about 175 vector
+// registers: two waves per SIMD, too few to hide a patch's chain of
+// dependent loads; the split kernels are faster there).  A fused choice
+// whose tables do not fit runs the split kernels.
 int choose_kernels(Model &m, Host h) {
     Params &p = m.prm;
     p.patch_emax = 0;
     p.patch_nodes = 0;
     p.fold = 0;
     int P = 0;
-    if (m.nv != 3) return MCT_OK;  // quadrilaterals: the split kernels
     if (m.kernels >= 2 && m.kernels <= 4)
         P = 64 << (m.kernels - 2);
-    else if (m.kernels == 0 || m.kernels == 5)
+    else if (m.kernels == 5 || (m.kernels == 0 && m.nv == 3))
         P = -1;
     if (P == 0 || !m.dnlist) return MCT_OK;
     int32_t emax = 0;
@@ -280,7 +283,8 @@ int choose_kernels(Model &m, Host h) {
         if (!m.dfold_n) {
             TRY(h, hipMalloc((void **)&m.dfold_n, 3 * sizeof(int32_t)));
             TRY(h, hipMemsetAsync(m.dfold_n, 0, 3 * sizeof(int32_t), h.stream));
-            TRY(h, hipMalloc((void **)&m.dfold_cand, sizeof(Cand) * 9 * (size_t)std::max<int64_t>(m.ne, 1)));
+            // three sets of at most one candidate per element edge
+            TRY(h, hipMalloc((void **)&m.dfold_cand, sizeof(Cand) * 3 * m.nv * (size_t)std::max<int64_t>(m.ne, 1)));
             TRY(h, hipStreamSynchronize(h.stream));
         }
         p.fold = 1;

@@ -41,13 +41,26 @@ def _same(m, o, label):
 
 
 @pytest.mark.parametrize("name", sorted(W.quad_small_cases()))
-def test_q4u_matches_oracle(gpu, oracle_mod, name):
+def test_q4u_matches_oracle(gpu, oracle_mod, name, monkeypatch):
     cfg = W.quad_small_cases()[name]
     print("case", name, flush=True)
     o = oracle_mod.Oracle(cfg)
-    # the element kernel plus the node kernel, whatever the launch choice
-    models = [gpu.from_config(cfg, tile=t, use_graph=g) for t, g in ((0, True), (1, False), (2, True))]
-    assert [m.launch()["tile"] for m in models] == [1, 1, 1]
+    # the element kernel plus the node kernel (1), the fused kernel on 64-,
+    # 128-, 256-node patches (2, 3, 4), on 77-node patches (not a multiple of
+    # the wavefront, the last one ragged) and on patches of the size the
+    # library finds
+    models = [gpu.from_config(cfg, tile=t, use_graph=g) for t, g in ((1, False), (2, True), (3, False), (4, True))]
+    assert [m.launch()["tile"] for m in models] == [1, 2, 3, 4]
+    nn = models[0].info()["n_nodes"]
+    monkeypatch.setenv("MCT_PATCH_NODES", "77")
+    sized = gpu.from_config(cfg, tile=5, use_graph=True)
+    monkeypatch.delenv("MCT_PATCH_NODES")
+    assert sized.launch()["tile"] == 5 and sized.launch()["workgroups"] == -(-nn // 77), sized.launch()
+    auto = gpu.from_config(cfg, tile=5, use_graph=False)
+    assert auto.launch()["tile"] in (2, 3, 4, 5), auto.launch()
+    print(name, "automatic patches", auto.launch(), flush=True)
+    models += [sized, auto]
+    assert gpu.from_config(cfg).launch()["tile"] == 1  # the automatic choice: split kernels
     inf = models[0].info()
     assert (inf["n_nodes"], inf["n_elems"], inf["n_edges"]) == (o.info()["nn"], o.info()["ne"], o.info()["ns"])
     assert inf["dt"] == o.info()["dt"]
@@ -219,10 +232,14 @@ def test_q4u_fullsize_plate(gpu, oracle_mod):
     cfg = W.quad_plate160k()
     o = oracle_mod.Oracle(cfg)
     m = gpu.from_config(cfg)
-    assert m.launch()["tile"] == 1
+    assert m.launch()["tile"] == 1, m.launch()  # the automatic choice (split kernels), as timed
+    f = gpu.from_config(cfg, tile=5)  # the fused kernel on patches it sizes
+    assert f.launch()["tile"] in (4, 5), f.launch()
     o.step(300)
     m.step(300)
-    _same(m, o, "quad_plate160k")
+    f.step(300)
+    _same(m, o, "quad_plate160k split")
+    _same(f, o, "quad_plate160k fused")
 
 
 @pytest.mark.parametrize("kind", ["q4u", "tri"])
@@ -263,7 +280,7 @@ def test_unstructured_autotune(gpu, oracle_mod, kind):
     o.step(400)
     r = m.autotune(trial_steps=30)
     print(kind, r, flush=True)
-    assert r["tile"] in ((1,) if kind == "q4u" else (1, 2, 3, 4, 5)) and r["us_per_step"] > 0
+    assert r["tile"] in (1, 2, 3, 4, 5) and r["us_per_step"] > 0
     assert m.launch()["tile"] == r["tile"]
     assert m.info()["step"] == 400
     _same(m, o, (kind, "after autotune"))
