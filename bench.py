@@ -54,7 +54,7 @@ WORKLOADS = {
 }
 # untimed steps from t = 0 before the window (mid-run); 0 for the others
 DEFAULT_START = {"batch256": 2500, "plate400": 10000, "fragment2000": 5000, "screen400": 10000,
-                 "screen2000": 5000}
+                 "screen2000": 5000, "tri320k": 10000, "quad160k": 10000}
 
 
 def n_elems(c) -> int:
