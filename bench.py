@@ -98,10 +98,10 @@ MEASURED_TRAFFIC = {
                  "tile": 1, "fetch_kib": 286603.1083984375, "write_kib": 407268.94677734375},
     # the fused triangle step on its automatic patches (profiles/k_fused_tri320k_hbm_traffic.md)
     "tri320k": {"sources": TRI_SOURCES, "sha256": "05418286f5084cd1360c30145edcc96fe12503b68b6182f787d902a72e113623",
-                "tile": 5, "fetch_kib": 15753.344063, "write_kib": 5024.472187},
+                "tile": 5, "fetch_kib": 15771.187935, "write_kib": 5024.496771},
     # the quadrilateral element and node kernels (profiles/k_qforce_quad160k_kernel_trace.md)
     "quad160k": {"sources": TRI_SOURCES, "sha256": "05418286f5084cd1360c30145edcc96fe12503b68b6182f787d902a72e113623",
-                 "tile": 1, "fetch_kib": 19176.382812, "write_kib": 14972.847969},
+                 "tile": 1, "fetch_kib": 19185.771746, "write_kib": 14974.014660},
 }
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131086.604, 262144.0 / 262144.0
 
