@@ -43,10 +43,11 @@ struct Params {
     int32_t sct;     // 1: single crack-tip tracking
     int32_t ncurve;  // traction load curve points (0: constant tractions)
     int32_t nv;      // nodes (and edges) per element: 3 or 4
-    const int4 *conn;    // per element: nodes n0 n1 n2 (n3) (CCW); .w unused for triangles
+    const int4 *conn;    // per element: nodes n0 n1 n2 (n3) (CCW); triangles: .w = the
+                         // neighbour's node off the shared edge 0 (-1: none)
     const int4 *nbr;     // per element: neighbour across local edge k = 0, 1, 2 (-1: none);
                          // .w: local index of that edge in the neighbour, 2 bits per k
-    const int4 *opp;     // per element: the neighbour's node off the shared edge k (-1: none)
+    const int2 *opp;     // per triangle: the neighbours' nodes off the shared edges 1, 2 (-1: none)
     // quadrilaterals: neighbour across local edge k = 0..3 (-1: none), the
     // local index of that edge in the neighbour (2 bits per k), and the
     // neighbour's two nodes off the shared edge (its local nodes loc + 2 and

@@ -559,17 +559,17 @@ __device__ __forceinline__ void element_force(const Params &p, const SplitView &
         return;
     }
     const int4 nb = p.nbr[e];
-    const int4 op = p.opp[e];
+    const int2 op = p.opp[e];  // the far nodes of edges 1, 2 (that of edge 0 is c.w)
     double2 ue[3], uo[3], xe[3], xo[3];
     load_u(u, c, ue);
     load_u(p.xy, c, xe);
     const double2 z2 = make_double2(0.0, 0.0);
-    uo[0] = op.x >= 0 ? u[op.x] : z2;
-    uo[1] = op.y >= 0 ? u[op.y] : z2;
-    uo[2] = op.z >= 0 ? u[op.z] : z2;
-    xo[0] = op.x >= 0 ? p.xy[op.x] : z2;
-    xo[1] = op.y >= 0 ? p.xy[op.y] : z2;
-    xo[2] = op.z >= 0 ? p.xy[op.z] : z2;
+    uo[0] = c.w >= 0 ? u[c.w] : z2;
+    uo[1] = op.x >= 0 ? u[op.x] : z2;
+    uo[2] = op.y >= 0 ? u[op.y] : z2;
+    xo[0] = c.w >= 0 ? p.xy[c.w] : z2;
+    xo[1] = op.x >= 0 ? p.xy[op.x] : z2;
+    xo[2] = op.y >= 0 ? p.xy[op.y] : z2;
     const Geo g = make_geo(xe[0], xe[1], xe[2]);
     double q[3];
     strain(g, ue, q);
@@ -651,17 +651,17 @@ __global__ __launch_bounds__(kB) void k_force(Params p, const double2 *u, Eval e
         return;
     }
     const int4 nb = p.nbr[e];
-    const int4 op = p.opp[e];
+    const int2 op = p.opp[e];  // the far nodes of edges 1, 2 (that of edge 0 is c.w)
     double2 ue[3], uo[3], xe[3], xo[3];
     load_u(u, c, ue);
     load_u(p.xy, c, xe);
     const double2 z2 = make_double2(0.0, 0.0);
-    uo[0] = op.x >= 0 ? u[op.x] : z2;
-    uo[1] = op.y >= 0 ? u[op.y] : z2;
-    uo[2] = op.z >= 0 ? u[op.z] : z2;
-    xo[0] = op.x >= 0 ? p.xy[op.x] : z2;
-    xo[1] = op.y >= 0 ? p.xy[op.y] : z2;
-    xo[2] = op.z >= 0 ? p.xy[op.z] : z2;
+    uo[0] = c.w >= 0 ? u[c.w] : z2;
+    uo[1] = op.x >= 0 ? u[op.x] : z2;
+    uo[2] = op.y >= 0 ? u[op.y] : z2;
+    xo[0] = c.w >= 0 ? p.xy[c.w] : z2;
+    xo[1] = op.x >= 0 ? p.xy[op.x] : z2;
+    xo[2] = op.y >= 0 ? p.xy[op.y] : z2;
     const Geo g = make_geo(xe[0], xe[1], xe[2]);
     double q[3];
     strain(g, ue, q);

@@ -666,8 +666,11 @@ int finalize(Model &m, Host h) {
     for (int32_t &v : nel) v = (v % nv) * (int32_t)ne + v / nv;
     // device arrays
     // per element: neighbours, and each neighbour's node off the shared edge
-    // (the neighbour runs the edge backwards, so its local node loc + 2)
-    std::vector<int4> c4(ne), n4(ne), o4(ne), qa(nv == 4 ? ne : 0), qb(nv == 4 ? ne : 0);
+    // (the neighbour runs the edge backwards, so its local node loc + 2); a
+    // triangle keeps the one off edge 0 in its node record's free fourth
+    // slot (40 B of element records per triangle instead of 48)
+    std::vector<int4> c4(ne), n4(ne), qa(nv == 4 ? ne : 0), qb(nv == 4 ? ne : 0);
+    std::vector<int2> o2v(nv == 3 ? ne : 0);
     std::vector<uint8_t> ql(nv == 4 ? ne : 0);
     const int st = nv + 1;
     for (int64_t e = 0; e < ne; ++e) {
@@ -686,7 +689,8 @@ int finalize(Model &m, Host h) {
         }
         if (nv == 3) {
             n4[e] = make_int4(m.nbr[st * e], m.nbr[st * e + 1], m.nbr[st * e + 2], m.nbr[st * e + 3]);
-            o4[e] = make_int4(o[0], o[1], o[2], 0);
+            c4[e].w = o[0];
+            o2v[e] = make_int2(o[1], o[2]);
         } else {
             n4[e] = make_int4(m.nbr[st * e], m.nbr[st * e + 1], m.nbr[st * e + 2], m.nbr[st * e + 3]);
             ql[e] = (uint8_t)m.nbr[st * e + 4];
@@ -717,7 +721,7 @@ int finalize(Model &m, Host h) {
     if ((rc = upload<int4>(h, m.dconn, c4.data(), ne))) return rc;
     if (nv == 3) {
         if ((rc = upload<int4>(h, m.dnbr, n4.data(), ne))) return rc;
-        if ((rc = upload<int4>(h, m.dopp, o4.data(), ne))) return rc;
+        if ((rc = upload<int2>(h, m.dopp, o2v.data(), ne))) return rc;
     } else {
         if ((rc = upload<int4>(h, m.dq_nbr, n4.data(), ne))) return rc;
         if ((rc = upload<uint8_t>(h, m.dq_loc, ql.data(), ne))) return rc;

@@ -52,7 +52,8 @@ struct Model {
     std::vector<double> mass;
     Params prm{};
     // device memory
-    int4 *dconn = nullptr, *dnbr = nullptr, *dopp = nullptr;
+    int4 *dconn = nullptr, *dnbr = nullptr;
+    int2 *dopp = nullptr;
     int4 *dq_nbr = nullptr, *dq_oa = nullptr, *dq_ob = nullptr;  // quadrilaterals
     uint8_t *dq_loc = nullptr;
     double *dminv = nullptr, *dgc = nullptr, *dcurve = nullptr, *dmass = nullptr;
