@@ -84,15 +84,19 @@ def test_q4u_sct_and_front_pick(gpu, oracle_mod):
     for cfg, label in ((dict(base, tracking=("sct", -1, 0)), "sct"), (dict(base, front_radius=2.5e-3), "front")):
         print("case", label, flush=True)
         o = oracle_mod.Oracle(cfg)
-        m = gpu.from_config(cfg)
+        # the element plus node kernels, and the fused kernel (whose step is
+        # then followed by the pick's own launch)
+        models = [gpu.from_config(cfg, tile=t) for t in (1, 5)]
+        assert [m.launch()["tile"] for m in models][0] == 1 and models[1].launch()["tile"] != 1
         if label == "sct":
-            assert m.tip() == o.tip() and o.tip() is not None
+            assert all(m.tip() == o.tip() for m in models) and o.tip() is not None
         for chunk in (100, 501, 599):
             o.step(chunk)
-            m.step(chunk)
-            _same(m, o, (label, chunk))
-            if label == "sct":
-                assert m.tip() == o.tip()
+            for m in models:
+                m.step(chunk)
+                _same(m, o, (label, chunk, m.launch()["tile"]))
+                if label == "sct":
+                    assert m.tip() == o.tip()
         assert len(o.log()["elem"]) > 3, label
 
 
@@ -192,6 +196,22 @@ def test_q4u_checkpoint_restore(gpu):
         assert np.array_equal(la[k], lb[k])
     assert np.array_equal(a.field(0)[0], b.field(0)[0]) and np.array_equal(a.field(1)[1], b.field(1)[1])
     assert a.info()["dissipated"] == b.info()["dissipated"]
+    # the fused kernel takes the same checkpoint and continues alike, and its
+    # own checkpoint restores into the split kernels
+    f = gpu.from_config(cfg, tile=5)
+    f.restore(ck)
+    f.step(200)
+    ckf = f.checkpoint()
+    f.step(200)
+    g = gpu.from_config(cfg, tile=1)
+    g.restore(ckf)
+    g.step(200)
+    for m in (f, g):
+        lm = m.crack_set()
+        for k in ("step", "elem", "entry", "exit", "G"):
+            assert np.array_equal(la[k], lm[k]), (m.launch(), k)
+        assert np.array_equal(a.field(0)[0], m.field(0)[0]) and np.array_equal(a.field(1)[1], m.field(1)[1])
+        assert a.info()["dissipated"] == m.info()["dissipated"]
     # another mesh does not take it
     with pytest.raises(gpu.MctError):
         gpu.from_config(W.quad_small_cases()["grid70x37_unstructured"]).restore(ck)
