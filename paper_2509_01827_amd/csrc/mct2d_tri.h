@@ -29,6 +29,7 @@ struct Ctl {
 static_assert(sizeof(Ctl) == 40, "Ctl layout");
 
 constexpr int kPatchMaxNodes = 256;  // fused step: one node per thread of its workgroup
+constexpr uint32_t kNoSlot = 1023;       // patch neighbour slot: none
 constexpr int32_t kOwned = 1 << 30;    // patch element flag: evaluate its candidates here
 
 // Node flags (one byte per node).
@@ -78,6 +79,15 @@ struct Params {
     const int32_t *patch_off;
     const int32_t *patch_elem;
     const uint16_t *patch_slots;
+    // triangles: the ring of each patch (elements outside it next to one of
+    // its elements; ids ascending, entries patch_ring_off[b] ..) and per
+    // patch element its neighbours' strain slots in the patch's LDS (the
+    // patch's elements first, then its ring): .x = slot of the neighbour
+    // across local edge k in bits 10k .. 10k + 9 (kNoSlot: none), .y bit k set
+    // when the element's id is below that neighbour's
+    const int32_t *patch_ring_off;
+    const int32_t *patch_ring;
+    const uint2 *patch_nbr;
     Cand *cand;          // 3 ne
     // fused step with the global pick folded in (multi-tip tracking): the
     // accepted candidates of segment step j go to set j mod 3 of fold_cand

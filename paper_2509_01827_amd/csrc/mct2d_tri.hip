@@ -611,6 +611,72 @@ __device__ __forceinline__ void element_force(const Params &p, const SplitView &
     }
 }
 
+// element_force of an intact triangle whose neighbours' strains and areas
+// sit in LDS (s_q[c][slot], s_A[slot]; area 0: a split or absent element),
+// slots and lower-id flags in nbs (the fused step's patch tables).  The
+// element's own geometry g, strain q and values ue come from the caller.
+// Arithmetic as edge_strain's: a neighbour's strain there is recomputed in
+// the neighbour's own node order, so it equals the one the neighbour
+// computed for itself, which is what the LDS holds.
+__device__ __forceinline__ void element_force_shared(const Params &p, int e, const int4 &c, const double2 ue[3],
+                                                     const Geo &g, const double q[3], uint2 nbs,
+                                                     const double (*s_q)[2 * kB], const double *s_A, bool cands,
+                                                     Cand *clist, int32_t *ccount, double2 f[3]) {
+    double sig[3][3];
+    bool two[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const uint32_t sl = (nbs.x >> (10 * k)) & kNoSlot;
+        const double A2 = sl != kNoSlot ? s_A[sl] : 0.0;
+        two[k] = A2 != 0.0;
+        double eps[3];
+        if (!two[k]) {
+            eps[0] = q[0];
+            eps[1] = q[1];
+            eps[2] = q[2];
+        } else {
+            const double q2[3] = {s_q[0][sl], s_q[1][sl], s_q[2][sl]};
+            const bool self_lo = ((nbs.y >> k) & 1u) != 0;
+            const double Alo = self_lo ? g.A : A2, Ahi = self_lo ? A2 : g.A;
+            const double sum = Alo + Ahi;
+            const double w0 = Alo / sum, w1 = Ahi / sum;
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                const double lo = self_lo ? q[cc] : q2[cc], hi = self_lo ? q2[cc] : q[cc];
+                eps[cc] = fma(w1, hi, w0 * lo);
+            }
+        }
+        hooke(p, eps, sig[k]);
+    }
+    double S[3];
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) S[cc] = (sig[0][cc] + sig[1][cc]) + sig[2][cc];
+    const double coef = g.A / 3.0;
+#pragma unroll
+    for (int n = 0; n < 3; ++n)
+        f[n] = make_double2(coef * fma(g.by[n], S[2], g.bx[n] * S[0]), coef * fma(g.bx[n], S[2], g.by[n] * S[1]));
+    if (!cands || (two[0] && two[1] && two[2])) return;
+    const int tip = p.sct ? p.ctl->tip : -1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (two[a]) continue;
+        if (p.sct && tip != 4 * e + a) continue;
+        double G;
+        const Sig s0 = {{sig[0][0], sig[0][1], sig[0][2]}}, s1 = {{sig[1][0], sig[1][1], sig[1][2]}},
+                  s2 = {{sig[2][0], sig[2][1], sig[2][2]}};
+        const int j = candidate(p, e, c, sel3(a, ue[0], ue[1], ue[2]), sel3((a + 1) % 3, ue[0], ue[1], ue[2]), s0,
+                                s1, s2, a, G);
+        if (j < 0) continue;
+        const int k = (a + 1 + j) % 3;
+        const int slot = atomicAdd(ccount, 1);
+        Cand cd;
+        cd.G = G;
+        cd.elem = e;
+        cd.ak = (a << 2) | k;
+        clist[slot] = cd;
+    }
+}
+
 // Element pass.  eval: query mode (u given, outputs in ev, no candidates).
 template <bool EVAL>
 __global__ __launch_bounds__(kB) void k_force(Params p, const double2 *u, Eval ev, int j) {
@@ -942,7 +1008,13 @@ __global__ __launch_bounds__(kB) void k_node(Params p, int j) {
 // so neighbouring workgroups never see a half-updated displacement.
 template <int NV, int W, int EMAX>
 __global__ __launch_bounds__(kB) void k_fused(Params p, int j) {
+    // triangles in patches of at most 256 elements and 256 ring elements
+    // share their strains through LDS (one element and one ring element per
+    // thread); the other forms recompute each neighbour's strain
+    constexpr bool SHARED = NV == 3 && EMAX == kB;
     __shared__ double2 s_f[NV * EMAX];
+    __shared__ double s_q[SHARED ? 3 : 1][SHARED ? 2 * kB : 1];
+    __shared__ double s_A[SHARED ? 2 * kB : 1];
     __shared__ double s_phi;
     __shared__ int s_pe;
     __shared__ uint8_t s_pcode;
@@ -977,6 +1049,75 @@ __global__ __launch_bounds__(kB) void k_fused(Params p, int j) {
     }
     const SplitView sv{p.split, p.fold ? s_pe : -1, p.fold ? s_pcode : (uint8_t)0};
     const int s0 = p.patch_off[b], s1 = p.patch_off[b + 1];
+    if constexpr (SHARED) {
+        // own strain and area of the patch element and ring element of this
+        // thread into the LDS slots tid and (s1 - s0) + tid
+        const int s = s0 + tid;
+        const bool mine = s < s1;
+        int e = 0;
+        bool owned = false;
+        int4 c = make_int4(0, 0, 0, 0);
+        uint8_t code = 0;
+        double2 ue[3];
+        Geo g;
+        double q[3];
+        if (mine) {
+            const int32_t rec = p.patch_elem[s];
+            e = rec & (kOwned - 1);
+            owned = (rec & kOwned) != 0;
+            c = p.conn[e];
+            code = sv(e);
+            if (code == 0) {
+                double2 xe[3];
+                load_u(u, c, ue);
+                load_u(p.xy, c, xe);
+                g = make_geo(xe[0], xe[1], xe[2]);
+                strain(g, ue, q);
+                s_q[0][tid] = q[0];
+                s_q[1][tid] = q[1];
+                s_q[2][tid] = q[2];
+                s_A[tid] = g.A;
+            } else {
+                s_A[tid] = 0.0;
+            }
+        }
+        const int r0 = p.patch_ring_off[b], r = r0 + tid;
+        if (r < p.patch_ring_off[b + 1]) {
+            const int er = p.patch_ring[r];
+            const int l = s1 - s0 + tid;
+            if (sv(er) == 0) {
+                const int4 cr = p.conn[er];
+                double2 ur[3], xr[3];
+                load_u(u, cr, ur);
+                load_u(p.xy, cr, xr);
+                const Geo gr = make_geo(xr[0], xr[1], xr[2]);
+                double qr[3];
+                strain(gr, ur, qr);
+                s_q[0][l] = qr[0];
+                s_q[1][l] = qr[1];
+                s_q[2][l] = qr[2];
+                s_A[l] = gr.A;
+            } else {
+                s_A[l] = 0.0;
+            }
+        }
+        __syncthreads();
+        if (mine) {
+            double2 f[3];
+            if (code) {
+                const Piece pa = piece(p, u, c, (code >> 2) & 3, code & 3);
+                const Piece pb = piece(p, u, c, code & 3, (code >> 2) & 3);
+                f[0] = piece_force_at(pa, pb, 0);
+                f[1] = piece_force_at(pa, pb, 1);
+                f[2] = piece_force_at(pa, pb, 2);
+            } else {
+                element_force_shared(p, e, c, ue, g, q, p.patch_nbr[s], s_q, s_A, owned, clist, ccount, f);
+            }
+            s_f[3 * tid] = f[0];
+            s_f[3 * tid + 1] = f[1];
+            s_f[3 * tid + 2] = f[2];
+        }
+    } else {
     for (int s = s0 + tid; s < s1; s += kB) {
         const int32_t rec = p.patch_elem[s];
         const int l = NV * (s - s0);
@@ -989,6 +1130,7 @@ __global__ __launch_bounds__(kB) void k_fused(Params p, int j) {
         } else {
             quad_element<false>(p, sv, u, rec & (kOwned - 1), (rec & kOwned) != 0, clist, ccount, Eval{}, s_f + l, 1);
         }
+    }
     }
     if (tid == 0) s_phi = load_factor(p, (double)k * p.dt);
     __syncthreads();

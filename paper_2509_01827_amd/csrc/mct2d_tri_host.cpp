@@ -167,13 +167,16 @@ int eval_state(Model &m, Host h, Ctl *ctl, bool with_energy) {
 }
 
 // Fused-step tables for patches of P consecutive nodes (one workgroup each;
-// triangles or quadrilaterals, nv nodes per element):
-// the patch's elements (every element touching an owned node, ascending id,
-// flagged kOwned in the patch of its smallest node, which alone evaluates its
-// candidates) and, per owned node, the LDS slots of its element forces in
-// colour order, padded to the gather lists' width.  Returns the largest
-// element count of a patch, 0 if the tables do not fit the kernel (more than
-// 16 elements at a node or 1024 in a patch).
+// triangles or quadrilaterals, nv nodes per element): the patch's elements
+// (every element touching an owned node, ascending id, flagged kOwned in the
+// patch of its smallest node, which alone evaluates its candidates) and, per
+// owned node, the LDS slots of its element forces in colour order, padded to
+// the gather lists' width.  Triangles also get each patch's ring (the
+// neighbours of its elements outside it, ascending) and per patch element
+// its neighbours' strain slots (patch elements first, then the ring) with
+// the lower-id flags.  Returns the largest element count of a patch (for
+// triangles the larger of it and the ring's), 0 if the tables do not fit
+// the kernel (more than 16 elements at a node or 1024 in a patch).
 int build_patches(Model &m, Host h, int P, int32_t *emax_out) {
     *emax_out = 0;
     const int64_t nn = m.nn, ne = m.ne;
@@ -184,7 +187,9 @@ int build_patches(Model &m, Host h, int P, int32_t *emax_out) {
     const int32_t W = (maxdeg + 3) / 4 * 4;
     if (W > 16) return MCT_OK;
     const int64_t npatch = (nn + P - 1) / P;
-    std::vector<int32_t> poff{0}, pelem, slot_of(ne, -1), stamp(ne, -1), els;
+    const int st = nv + 1;  // neighbour table stride
+    std::vector<int32_t> poff{0}, pelem, slot_of(ne, -1), stamp(ne, -1), els, roff{0}, pring, ring;
+    std::vector<uint2> pnbr;
     std::vector<uint16_t> pslots((size_t)npatch * P * W, 0xffff);
     int32_t emax = 0;
     for (int64_t b = 0; b < npatch; ++b) {
@@ -211,14 +216,52 @@ int build_patches(Model &m, Host h, int P, int32_t *emax_out) {
         for (int64_t i = n0; i < n1; ++i)
             for (int32_t t = noff[i]; t < noff[i + 1]; ++t)
                 pslots[(size_t)i * W + (t - noff[i])] = (uint16_t)(nv * slot_of[nel[t] / nv] + nel[t] % nv);
+        if (nv != 3) continue;
+        // the ring: neighbours outside the patch (stamp marks the patch's own
+        // elements with b; the ring's with -2 - b)
+        ring.clear();
+        for (const int32_t e : els)
+            for (int k = 0; k < 3; ++k) {
+                const int32_t nb = m.nbr[st * (int64_t)e + k];
+                if (nb >= 0 && stamp[nb] != (int32_t)b && stamp[nb] != -2 - (int32_t)b) {
+                    stamp[nb] = -2 - (int32_t)b;
+                    ring.push_back(nb);
+                }
+            }
+        std::sort(ring.begin(), ring.end());
+        emax = std::max<int32_t>(emax, (int32_t)ring.size());
+        for (size_t q = 0; q < ring.size(); ++q) {
+            slot_of[ring[q]] = (int32_t)(els.size() + q);
+            pring.push_back(ring[q]);
+        }
+        roff.push_back((int32_t)pring.size());
+        const bool fits = els.size() + ring.size() < kNoSlot;
+        for (const int32_t e : els) {
+            uint2 r = make_uint2(0, 0);
+            for (int k = 0; k < 3; ++k) {
+                const int32_t nb = m.nbr[st * (int64_t)e + k];
+                const uint32_t sl = (nb >= 0 && fits) ? (uint32_t)slot_of[nb] : kNoSlot;
+                r.x |= sl << (10 * k);
+                if (nb >= 0 && e < nb) r.y |= 1u << k;
+            }
+            pnbr.push_back(r);
+        }
     }
     dfree(m.dpatch_off);
     dfree(m.dpatch_elem);
     dfree(m.dpatch_slots);
+    dfree(m.dpatch_ring_off);
+    dfree(m.dpatch_ring);
+    dfree(m.dpatch_nbr);
     int rc;
     if ((rc = upload<int32_t>(h, m.dpatch_off, poff.data(), poff.size()))) return rc;
     if ((rc = upload<int32_t>(h, m.dpatch_elem, pelem.data(), pelem.size()))) return rc;
     if ((rc = upload<uint16_t>(h, m.dpatch_slots, pslots.data(), pslots.size()))) return rc;
+    if (nv == 3) {
+        if ((rc = upload<int32_t>(h, m.dpatch_ring_off, roff.data(), roff.size()))) return rc;
+        if (!pring.empty() && (rc = upload<int32_t>(h, m.dpatch_ring, pring.data(), pring.size()))) return rc;
+        if ((rc = upload<uint2>(h, m.dpatch_nbr, pnbr.data(), pnbr.size()))) return rc;
+    }
     TRY(h, hipStreamSynchronize(h.stream));
     *emax_out = emax;
     return MCT_OK;
@@ -278,6 +321,9 @@ int choose_kernels(Model &m, Host h) {
     p.patch_off = m.dpatch_off;
     p.patch_elem = m.dpatch_elem;
     p.patch_slots = m.dpatch_slots;
+    p.patch_ring_off = m.dpatch_ring_off;
+    p.patch_ring = m.dpatch_ring;
+    p.patch_nbr = m.dpatch_nbr;
     // the global multi-tip pick folds into the next fused step
     if (!m.sct && !(m.front_rho > 0)) {
         if (!m.dfold_n) {
@@ -317,6 +363,9 @@ void release(Model &m) {
     dfree(m.dpatch_off);
     dfree(m.dpatch_elem);
     dfree(m.dpatch_slots);
+    dfree(m.dpatch_ring_off);
+    dfree(m.dpatch_ring);
+    dfree(m.dpatch_nbr);
     dfree(m.dfold_n);
     dfree(m.dfold_cand);
     dfree(m.dv);

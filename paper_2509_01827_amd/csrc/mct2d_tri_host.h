@@ -59,12 +59,13 @@ struct Model {
     double *dminv = nullptr, *dgc = nullptr, *dcurve = nullptr, *dmass = nullptr;
     double2 *dxy = nullptr, *du[2] = {nullptr, nullptr}, *dv = nullptr, *dfext = nullptr, *dv0 = nullptr,
             *dfe = nullptr;
-    int32_t *dpatch_off = nullptr, *dpatch_elem = nullptr;
+    int32_t *dpatch_off = nullptr, *dpatch_elem = nullptr, *dpatch_ring_off = nullptr, *dpatch_ring = nullptr;
+    uint2 *dpatch_nbr = nullptr;
     int32_t *dfold_n = nullptr;     // folded pick: 3 candidate counters
     Cand *dfold_cand = nullptr;     //   and 3 candidate sets of 3 ne (triangles only)
     uint16_t *dpatch_slots = nullptr;
     // step kernels: 0 automatic, 1 split, 2/3/4 fused on 64/128/256-node
-    // patches (triangles; quadrilateral meshes run the split kernels)
+    // patches, 5 fused on patches of the size sized_patches finds
     int kernels = 0;
     // node -> incident (nv * element + local node) entries in colour order
     std::vector<int32_t> gnoff, gnel;
