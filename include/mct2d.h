@@ -391,8 +391,8 @@ int mct_restore(mct_ctx *ctx, const void *host_buf, int64_t bytes);
  * consecutive nodes (element forces summed in LDS; used when its tables fit:
  * at most 16 elements at a node and 1024 in a patch, else the split
  * kernels); 5 = the fused kernel on the largest patches (64 to 256 nodes)
- * that hold at most 256 elements each; 0 = automatic (5 on triangles, 1 on
- * quadrilaterals).  The environment
+ * that hold at most 256 elements each (shrunk to even out the compute
+ * units' shares); 0 = automatic (5).  The environment
  * variable MCT_PATCH_NODES, read when the choice is made, sets the patch
  * size of choice 5 instead (1..256 nodes; a testing and tuning knob).
  * Results do not depend on any of these choices (fixed summation orders).

@@ -79,12 +79,14 @@ struct Params {
     const int32_t *patch_off;
     const int32_t *patch_elem;
     const uint16_t *patch_slots;
-    // triangles: the ring of each patch (elements outside it next to one of
-    // its elements; ids ascending, entries patch_ring_off[b] ..) and per
-    // patch element its neighbours' strain slots in the patch's LDS (the
-    // patch's elements first, then its ring): .x = slot of the neighbour
-    // across local edge k in bits 10k .. 10k + 9 (kNoSlot: none), .y bit k set
-    // when the element's id is below that neighbour's
+    // the ring of each patch (elements outside it next to one of its
+    // elements; ids ascending, entries patch_ring_off[b] ..) and per patch
+    // element its neighbours' strain slots in the patch's LDS (the patch's
+    // elements first, then its ring): .x = slot of the neighbour across
+    // local edge k = 0..2 in bits 10k .. 10k + 9, .y bits 0..9 that across
+    // edge 3 (kNoSlot: none); .y bit 10 + k set when the element's id is
+    // below that neighbour's, .y bits 16 + 2k, 17 + 2k the shared edge's
+    // local index in the neighbour
     const int32_t *patch_ring_off;
     const int32_t *patch_ring;
     const uint2 *patch_nbr;

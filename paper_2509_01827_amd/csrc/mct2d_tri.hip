@@ -338,6 +338,60 @@ __device__ __forceinline__ double quad_split(const Params &p, const double2 ue[4
     return w;
 }
 
+// Crack-tip candidates of an intact quadrilateral with free-surface edges
+// (two[a] false): for each such edge a (single-tip tracking: the tip edge
+// only) with the stretch gate open, G of the three paths k = a+1, a+2, a+3
+// from the smoothed edge stresses (sig(k, s) gives edge k's), then the
+// four-edge element rule (Sec. 2.2); an accepted candidate is appended to
+// clist.
+template <class SigFn>
+__device__ __forceinline__ void quad_candidates(const Params &p, int e, const double x[4], const double y[4],
+                                                const double ux[4], const double uy[4], SigFn &&sig,
+                                                const bool two[4], Cand *clist, int32_t *ccount) {
+    const int tip = p.sct ? p.ctl->tip : -1;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        if (two[a]) continue;
+        if (p.sct && tip != 4 * e + a) continue;
+        const int a1 = (a + 1) & 3;
+        const double dux = ux[a1] - ux[a], duy = uy[a1] - uy[a];
+        const double x1 = x[a] + ux[a], y1 = y[a] + uy[a];
+        const double x2 = x[a1] + ux[a1], y2 = y[a1] + uy[a1];
+        const double lx = x2 - x1, ly = y2 - y1;
+        const double Lx = x[a1] - x[a], Ly = y[a1] - y[a];
+        if (!((lx * lx + ly * ly) > (Lx * Lx + Ly * Ly))) continue;  // H = 0: every G is 0
+        double G[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int k = (a + 1 + j) & 3;
+            double nx, ny, len, sg[3];
+            dev::path_geom(x, y, a, k, nx, ny, len);
+            sig(k, sg);
+            const double spx = fma(sg[2], ny, sg[0] * nx);
+            const double spy = fma(sg[1], ny, sg[2] * nx);
+            G[j] = 0.5 * fma(duy, spy, dux * spx);
+        }
+        const double Gc = p.gc[e];
+        int best = -1;
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            if (G[j] > Gc && (best < 0 || G[j] > sel3(best, G[0], G[1], G[2]))) best = j;
+        if (best < 0) continue;
+        const double Gb = sel3(best, G[0], G[1], G[2]);
+        bool ok = true;
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            if (j != best && G[j] > Gc && !(Gb > p.gamma * (Gb - G[j]))) ok = false;
+        if (!ok) continue;
+        const int slot = atomicAdd(ccount, 1);
+        Cand cd;
+        cd.G = Gb;
+        cd.elem = e;
+        cd.ak = (a << 2) | ((a + 1 + best) & 3);
+        clist[slot] = cd;
+    }
+}
+
 // Everything a quadrilateral element contributes to one pass: its four
 // nodal forces (force of local node n at fe[n fs]), with `cands` its crack-tip
 // candidates, with EVAL the query outputs.  An intact element computes the
@@ -493,47 +547,14 @@ __device__ __forceinline__ void quad_element(const Params &p, const SplitView &s
         return;
     }
     if (!cands || (two[0] && two[1] && two[2] && two[3])) return;
-    const int tip = p.sct ? p.ctl->tip : -1;
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        if (two[a]) continue;
-        if (p.sct && tip != 4 * e + a) continue;
-        const int a1 = (a + 1) & 3;
-        const double dux = ux[a1] - ux[a], duy = uy[a1] - uy[a];
-        const double x1 = x[a] + ux[a], y1 = y[a] + uy[a];
-        const double x2 = x[a1] + ux[a1], y2 = y[a1] + uy[a1];
-        const double lx = x2 - x1, ly = y2 - y1;
-        const double Lx = x[a1] - x[a], Ly = y[a1] - y[a];
-        if (!((lx * lx + ly * ly) > (Lx * Lx + Ly * Ly))) continue;  // H = 0: every G is 0
-        double G[3];
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const int k = (a + 1 + j) & 3;
-            double nx, ny, len;
-            dev::path_geom(x, y, a, k, nx, ny, len);
-            const double spx = fma(sig[k][2], ny, sig[k][0] * nx);
-            const double spy = fma(sig[k][1], ny, sig[k][2] * nx);
-            G[j] = 0.5 * fma(duy, spy, dux * spx);
-        }
-        const double Gc = p.gc[e];
-        int best = -1;
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-            if (G[j] > Gc && (best < 0 || G[j] > sel3(best, G[0], G[1], G[2]))) best = j;
-        if (best < 0) continue;
-        const double Gb = sel3(best, G[0], G[1], G[2]);
-        bool ok = true;
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-            if (j != best && G[j] > Gc && !(Gb > p.gamma * (Gb - G[j]))) ok = false;
-        if (!ok) continue;
-        const int slot = atomicAdd(ccount, 1);
-        Cand cd;
-        cd.G = Gb;
-        cd.elem = e;
-        cd.ak = (a << 2) | ((a + 1 + best) & 3);
-        clist[slot] = cd;
-    }
+    quad_candidates(
+        p, e, x, y, ux, uy,
+        [&](int k, double sg[3]) {
+            sg[0] = sig[k][0];
+            sg[1] = sig[k][1];
+            sg[2] = sig[k][2];
+        },
+        two, clist, ccount);
 }
 
 // Forces of element e on its three local nodes from displacement u (the
@@ -636,7 +657,7 @@ __device__ __forceinline__ void element_force_shared(const Params &p, int e, con
             eps[2] = q[2];
         } else {
             const double q2[3] = {s_q[0][sl], s_q[1][sl], s_q[2][sl]};
-            const bool self_lo = ((nbs.y >> k) & 1u) != 0;
+            const bool self_lo = ((nbs.y >> (10 + k)) & 1u) != 0;
             const double Alo = self_lo ? g.A : A2, Ahi = self_lo ? A2 : g.A;
             const double sum = Alo + Ahi;
             const double w0 = Alo / sum, w1 = Ahi / sum;
@@ -999,6 +1020,72 @@ __global__ __launch_bounds__(kB) void k_node(Params p, int j) {
     (odd ? p.u0 : p.u1)[i] = make_double2(u.x + p.dt * vx, u.y + p.dt * vy);
 }
 
+// LDS slots of the quadrilateral fused step: 256 patch elements and 128 ring
+// elements, each with its four edge-midpoint strains and its area.
+constexpr int kQuadSlots = kB + kB / 2;
+
+// Coordinates and displacements of the four nodes of quadrilateral e.
+__device__ __forceinline__ void quad_nodes(const Params &p, const double2 *u, int e, double x[4], double y[4],
+                                           double ux[4], double uy[4]) {
+    const int4 c = p.conn[e];
+    const double2 u0 = u[c.x], u1 = u[c.y], u2 = u[c.z], u3 = u[c.w];
+    const double2 x0 = p.xy[c.x], x1 = p.xy[c.y], x2 = p.xy[c.z], x3 = p.xy[c.w];
+    x[0] = x0.x, x[1] = x1.x, x[2] = x2.x, x[3] = x3.x;
+    y[0] = x0.y, y[1] = x1.y, y[2] = x2.y, y[3] = x3.y;
+    ux[0] = u0.x, ux[1] = u1.x, ux[2] = u2.x, ux[3] = u3.x;
+    uy[0] = u0.y, uy[1] = u1.y, uy[2] = u2.y, uy[3] = u3.y;
+}
+
+// An intact quadrilateral's strains at its four edge midpoints (row 3k + c
+// of s_qd) and its area (row 12) into LDS slot l.
+__device__ __forceinline__ void quad_store_strains(const double x[4], const double y[4], const double ux[4],
+                                                   const double uy[4], double *s_qd, int l) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double gx[4], gy[4], q[3];
+        dev::q4_grad(x, y, k, gx, gy);
+        dev::strain<4>(gx, gy, ux, uy, q);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) s_qd[(3 * k + c) * kQuadSlots + l] = q[c];
+    }
+    s_qd[12 * kQuadSlots + l] = quad_area(x, y);
+}
+
+// Smoothed stress of local edge k of an intact quadrilateral (area A, nodes
+// x, y, ux, uy) whose neighbours' edge strains sit in LDS, and its gradients
+// at that edge's midpoint.  Arithmetic as quad_element's: the neighbour's
+// strain there, recomputed in the neighbour's own node order, equals the one
+// the neighbour stored for itself.
+__device__ __forceinline__ void quad_edge_sigma_shared(const Params &p, int k, const double x[4], const double y[4],
+                                                       const double ux[4], const double uy[4], double A,
+                                                       uint2 nbs, const double *s_qd, double gx[4], double gy[4],
+                                                       double sg[3], bool &two) {
+    double q[3], eps[3];
+    dev::q4_grad(x, y, k, gx, gy);
+    dev::strain<4>(gx, gy, ux, uy, q);
+    const uint32_t sl = k < 3 ? (nbs.x >> (10 * k)) & kNoSlot : nbs.y & kNoSlot;
+    const double A2 = sl != kNoSlot ? s_qd[12 * kQuadSlots + sl] : 0.0;
+    two = A2 != 0.0;
+    if (!two) {
+        eps[0] = q[0];
+        eps[1] = q[1];
+        eps[2] = q[2];
+    } else {
+        const int loc = (nbs.y >> (16 + 2 * k)) & 3;
+        const bool self_lo = ((nbs.y >> (10 + k)) & 1u) != 0;
+        const double Alo = self_lo ? A : A2, Ahi = self_lo ? A2 : A;
+        const double sum = Alo + Ahi;
+        const double w0 = Alo / sum, w1 = Ahi / sum;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double q2 = s_qd[(3 * loc + c) * kQuadSlots + sl];
+            const double lo = self_lo ? q[c] : q2, hi = self_lo ? q2 : q[c];
+            eps[c] = fma(w1, hi, w0 * lo);
+        }
+    }
+    hooke(p, eps, sg);
+}
+
 // Fused step of one patch of patch_nodes consecutive nodes (NV nodes per
 // element: 3 triangles, 4 quadrilaterals): the forces of every
 // element touching the patch (elements on patch borders are computed by
@@ -1012,9 +1099,14 @@ __global__ __launch_bounds__(kB) void k_fused(Params p, int j) {
     // share their strains through LDS (one element and one ring element per
     // thread); the other forms recompute each neighbour's strain
     constexpr bool SHARED = NV == 3 && EMAX == kB;
-    __shared__ double2 s_f[NV * EMAX];
+    // quadrilaterals likewise with 128 ring elements; their forces reuse the
+    // strains' LDS once every element has read its neighbours' strains
+    constexpr bool SHARED4 = NV == 4 && EMAX == kB;
+    __shared__ double2 s_fa[SHARED4 ? 1 : NV * EMAX];
     __shared__ double s_q[SHARED ? 3 : 1][SHARED ? 2 * kB : 1];
     __shared__ double s_A[SHARED ? 2 * kB : 1];
+    __shared__ __align__(16) double s_qd[SHARED4 ? 13 * kQuadSlots : 1];
+    double2 *const s_f = SHARED4 ? reinterpret_cast<double2 *>(s_qd) : s_fa;
     __shared__ double s_phi;
     __shared__ int s_pe;
     __shared__ uint8_t s_pcode;
@@ -1116,6 +1208,102 @@ __global__ __launch_bounds__(kB) void k_fused(Params p, int j) {
             s_f[3 * tid] = f[0];
             s_f[3 * tid + 1] = f[1];
             s_f[3 * tid + 2] = f[2];
+        }
+    } else if constexpr (SHARED4) {
+        const int s = s0 + tid;
+        const bool mine = s < s1;
+        int e = 0;
+        bool owned = false;
+        uint8_t code = 0;
+        double x[4], y[4], ux[4], uy[4];
+        if (mine) {
+            const int32_t rec = p.patch_elem[s];
+            e = rec & (kOwned - 1);
+            owned = (rec & kOwned) != 0;
+            code = sv(e);
+            quad_nodes(p, u, e, x, y, ux, uy);
+            if (code == 0)
+                quad_store_strains(x, y, ux, uy, s_qd, tid);
+            else
+                s_qd[12 * kQuadSlots + tid] = 0.0;
+        }
+        const int r = p.patch_ring_off[b] + tid;
+        if (r < p.patch_ring_off[b + 1]) {
+            const int er = p.patch_ring[r];
+            const int l = s1 - s0 + tid;
+            if (sv(er) == 0) {
+                double xr[4], yr[4], uxr[4], uyr[4];
+                quad_nodes(p, u, er, xr, yr, uxr, uyr);
+                quad_store_strains(xr, yr, uxr, uyr, s_qd, l);
+            } else {
+                s_qd[12 * kQuadSlots + l] = 0.0;
+            }
+        }
+        __syncthreads();
+        double2 f[4];
+        if (mine) {
+            if (code) {
+                const double2 ue[4] = {make_double2(ux[0], uy[0]), make_double2(ux[1], uy[1]),
+                                       make_double2(ux[2], uy[2]), make_double2(ux[3], uy[3])};
+                switch (code & 15) {
+#define QSPLIT(EN, EX) \
+    case (EN << 2) | EX: (void)quad_split<EN, EX>(p, ue, x, y, f); break;
+                    QSPLIT(0, 1) QSPLIT(0, 2) QSPLIT(0, 3) QSPLIT(1, 0) QSPLIT(1, 2) QSPLIT(1, 3)
+                    QSPLIT(2, 0) QSPLIT(2, 1) QSPLIT(2, 3) QSPLIT(3, 0) QSPLIT(3, 1) QSPLIT(3, 2)
+#undef QSPLIT
+                    default:
+#pragma unroll
+                        for (int n = 0; n < 4; ++n) f[n] = make_double2(0.0, 0.0);
+                        break;
+                }
+            } else {
+                const uint2 nbs = p.patch_nbr[s];
+                const double A = s_qd[12 * kQuadSlots + tid];
+                bool two[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const uint32_t sl = k < 3 ? (nbs.x >> (10 * k)) & kNoSlot : nbs.y & kNoSlot;
+                    two[k] = sl != kNoSlot && s_qd[12 * kQuadSlots + sl] != 0.0;
+                }
+                if (owned && !(two[0] && two[1] && two[2] && two[3])) {
+                    // a free-surface element: the edge stresses its candidates
+                    // need, each computed where it is used
+                    quad_candidates(
+                        p, e, x, y, ux, uy,
+                        [&](int k, double sg[3]) {
+                            // an opaque copy of the area keeps the compiler from
+                            // merging these calls into four stresses held at once
+                            double Ak = A;
+                            asm volatile("" : "+v"(Ak));
+                            double gx[4], gy[4];
+                            bool t;
+                            quad_edge_sigma_shared(p, k, x, y, ux, uy, Ak, nbs, s_qd, gx, gy, sg, t);
+                        },
+                        two, clist, ccount);
+                }
+                double sx[4], sy[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    double gx[4], gy[4], sg[3];
+                    bool t;
+                    quad_edge_sigma_shared(p, k, x, y, ux, uy, A, nbs, s_qd, gx, gy, sg, t);
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        const double tx = fma(gy[m], sg[2], gx[m] * sg[0]);
+                        const double ty = fma(gx[m], sg[2], gy[m] * sg[1]);
+                        sx[m] = k == 0 ? tx : sx[m] + tx;
+                        sy[m] = k == 0 ? ty : sy[m] + ty;
+                    }
+                }
+                const double cA = 0.25 * A;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) f[m] = make_double2(cA * sx[m], cA * sy[m]);
+            }
+        }
+        __syncthreads();  // every strain read: the forces take the LDS over
+        if (mine) {
+#pragma unroll
+            for (int n = 0; n < 4; ++n) s_f[4 * tid + n] = f[n];
         }
     } else {
     for (int s = s0 + tid; s < s1; s += kB) {

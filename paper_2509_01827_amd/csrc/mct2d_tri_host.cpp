@@ -171,13 +171,14 @@ int eval_state(Model &m, Host h, Ctl *ctl, bool with_energy) {
 // (every element touching an owned node, ascending id, flagged kOwned in the
 // patch of its smallest node, which alone evaluates its candidates) and, per
 // owned node, the LDS slots of its element forces in colour order, padded to
-// the gather lists' width.  Triangles also get each patch's ring (the
-// neighbours of its elements outside it, ascending) and per patch element
-// its neighbours' strain slots (patch elements first, then the ring) with
-// the lower-id flags.  Returns the largest element count of a patch (for
-// triangles the larger of it and the ring's), 0 if the tables do not fit
-// the kernel (more than 16 elements at a node or 1024 in a patch).
-int build_patches(Model &m, Host h, int P, int32_t *emax_out) {
+// the gather lists' width; each patch's ring (the neighbours of its
+// elements outside it, ascending) and per patch element its neighbours'
+// strain slots (patch elements first, then the ring), lower-id flags and
+// the shared edges' local indices in the neighbours.  Returns the largest
+// element count of a patch (257 when it is at most 256 but a ring exceeds
+// what the 256-slot kernel holds), 0 if the tables do not fit the kernel
+// (more than 16 elements at a node or 1024 in a patch).
+int build_patches(Model &m, Host h, int P, int32_t *emax_out, int32_t *rmax_out = nullptr) {
     *emax_out = 0;
     const int64_t nn = m.nn, ne = m.ne;
     const int nv = m.nv;
@@ -191,7 +192,7 @@ int build_patches(Model &m, Host h, int P, int32_t *emax_out) {
     std::vector<int32_t> poff{0}, pelem, slot_of(ne, -1), stamp(ne, -1), els, roff{0}, pring, ring;
     std::vector<uint2> pnbr;
     std::vector<uint16_t> pslots((size_t)npatch * P * W, 0xffff);
-    int32_t emax = 0;
+    int32_t emax = 0, rmax = 0;
     for (int64_t b = 0; b < npatch; ++b) {
         const int64_t n0 = b * P, n1 = std::min<int64_t>(nn, n0 + P);
         els.clear();
@@ -216,12 +217,11 @@ int build_patches(Model &m, Host h, int P, int32_t *emax_out) {
         for (int64_t i = n0; i < n1; ++i)
             for (int32_t t = noff[i]; t < noff[i + 1]; ++t)
                 pslots[(size_t)i * W + (t - noff[i])] = (uint16_t)(nv * slot_of[nel[t] / nv] + nel[t] % nv);
-        if (nv != 3) continue;
         // the ring: neighbours outside the patch (stamp marks the patch's own
         // elements with b; the ring's with -2 - b)
         ring.clear();
         for (const int32_t e : els)
-            for (int k = 0; k < 3; ++k) {
+            for (int k = 0; k < nv; ++k) {
                 const int32_t nb = m.nbr[st * (int64_t)e + k];
                 if (nb >= 0 && stamp[nb] != (int32_t)b && stamp[nb] != -2 - (int32_t)b) {
                     stamp[nb] = -2 - (int32_t)b;
@@ -229,7 +229,7 @@ int build_patches(Model &m, Host h, int P, int32_t *emax_out) {
                 }
             }
         std::sort(ring.begin(), ring.end());
-        emax = std::max<int32_t>(emax, (int32_t)ring.size());
+        rmax = std::max<int32_t>(rmax, (int32_t)ring.size());
         for (size_t q = 0; q < ring.size(); ++q) {
             slot_of[ring[q]] = (int32_t)(els.size() + q);
             pring.push_back(ring[q]);
@@ -238,12 +238,18 @@ int build_patches(Model &m, Host h, int P, int32_t *emax_out) {
         const bool fits = els.size() + ring.size() < kNoSlot;
         for (const int32_t e : els) {
             uint2 r = make_uint2(0, 0);
-            for (int k = 0; k < 3; ++k) {
+            const uint32_t locs = (uint32_t)m.nbr[st * (int64_t)e + nv];
+            for (int k = 0; k < nv; ++k) {
                 const int32_t nb = m.nbr[st * (int64_t)e + k];
                 const uint32_t sl = (nb >= 0 && fits) ? (uint32_t)slot_of[nb] : kNoSlot;
-                r.x |= sl << (10 * k);
-                if (nb >= 0 && e < nb) r.y |= 1u << k;
+                if (k < 3)
+                    r.x |= sl << (10 * k);
+                else
+                    r.y |= sl;
+                if (nb >= 0 && e < nb) r.y |= 1u << (10 + k);
+                r.y |= ((locs >> (2 * k)) & 3u) << (16 + 2 * k);
             }
+            if (nv == 3) r.y |= kNoSlot;
             pnbr.push_back(r);
         }
     }
@@ -257,23 +263,30 @@ int build_patches(Model &m, Host h, int P, int32_t *emax_out) {
     if ((rc = upload<int32_t>(h, m.dpatch_off, poff.data(), poff.size()))) return rc;
     if ((rc = upload<int32_t>(h, m.dpatch_elem, pelem.data(), pelem.size()))) return rc;
     if ((rc = upload<uint16_t>(h, m.dpatch_slots, pslots.data(), pslots.size()))) return rc;
-    if (nv == 3) {
-        if ((rc = upload<int32_t>(h, m.dpatch_ring_off, roff.data(), roff.size()))) return rc;
-        if (!pring.empty() && (rc = upload<int32_t>(h, m.dpatch_ring, pring.data(), pring.size()))) return rc;
-        if ((rc = upload<uint2>(h, m.dpatch_nbr, pnbr.data(), pnbr.size()))) return rc;
-    }
+    if ((rc = upload<int32_t>(h, m.dpatch_ring_off, roff.data(), roff.size()))) return rc;
+    if (!pring.empty() && (rc = upload<int32_t>(h, m.dpatch_ring, pring.data(), pring.size()))) return rc;
+    if ((rc = upload<uint2>(h, m.dpatch_nbr, pnbr.data(), pnbr.size()))) return rc;
     TRY(h, hipStreamSynchronize(h.stream));
+    // the 256-slot kernel shares strains through LDS and holds 256 ring
+    // triangles or 128 ring quadrilaterals (four edge strains each); with a
+    // larger ring the patches take the 512-slot kernel, which recomputes
+    // the neighbours' strains and reads no ring
+    if (emax <= 256 && rmax > (nv == 3 ? 256 : 128)) emax = 257;
     *emax_out = emax;
+    if (rmax_out) *rmax_out = rmax;
     return MCT_OK;
 }
 
 // Patch size of the fused step: the largest patch (64 to kPatchMaxNodes
-// nodes) whose patches all hold at most 256 elements.  Such patches keep the
-// LDS, and with it the occupancy, of the smallest kernel instance and
-// compute their elements in one pass of the workgroup; among them the
+// nodes) whose patches all hold at most 256 elements and whose rings fit
+// the 256-slot kernel (build_patches).  Such patches take that kernel, which
+// shares strains through LDS at the smallest LDS and register footprint,
+// and compute their elements in one pass of the workgroup; among them the
 // largest leave the fewest border elements computed twice and the fewest
 // partly idle wavefronts.  Found from kPatchMaxNodes down, each try scaled by
-// 256 over the element count of the fullest patch; the environment variable
+// 256 over the element count of the fullest patch (or the ring limit over
+// the largest ring), then shrunk to even out the compute units' shares
+// (below); the environment variable
 // MCT_PATCH_NODES sets the size instead (a testing and tuning knob).  Leaves
 // the tables of the chosen size built; emax 0 when they do not fit.
 int sized_patches(Model &m, Host h, int *P_out, int32_t *emax) {
@@ -283,24 +296,43 @@ int sized_patches(Model &m, Host h, int *P_out, int32_t *emax) {
         *P_out = (int)P;
         return build_patches(m, h, (int)P, emax);
     }
+    const int32_t rcap = m.nv == 3 ? 256 : 128;  // ring elements the 256-slot kernel holds
     for (;;) {
-        int rc = build_patches(m, h, (int)P, emax);
+        int32_t rmax = 0;
+        int rc = build_patches(m, h, (int)P, emax, &rmax);
         if (rc) return rc;
-        if (*emax <= 256 || P == 64) {  // fits (or, emax 0, the tables never do)
-            *P_out = (int)P;
-            return MCT_OK;
-        }
-        P = std::max<int64_t>(64, std::min<int64_t>(P - 1, P * 256 / *emax));
+        if (*emax <= 256 || P == 64) break;  // fits (or, emax 0, the tables never do)
+        const int64_t Pn = (*emax == 257 && rmax > rcap) ? P * rcap / rmax : P * 256 / *emax;
+        P = std::max<int64_t>(64, std::min<int64_t>(P - 1, Pn));
     }
+    // Then as many patches as fill the next whole number of patches per
+    // compute unit: the step lasts as long as the busiest unit's patches, so
+    // smaller patches that even the units out cost nothing extra.
+    int dev = 0, ncu = 0;
+    if (*emax > 0 && *emax <= 256 && hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0) {
+        const int64_t nn = m.nn, per_cu = ((nn + P - 1) / P + ncu - 1) / ncu;
+        const int64_t Pe = std::max<int64_t>(64, (nn + per_cu * ncu - 1) / (per_cu * ncu));
+        if (Pe < P) {
+            int32_t e2 = 0;
+            int rc = build_patches(m, h, (int)Pe, &e2);
+            if (rc) return rc;
+            if (e2 > 0 && e2 <= 256) {
+                *emax = e2;
+                P = Pe;
+            } else if ((rc = build_patches(m, h, (int)P, emax))) {  // keep the larger size
+                return rc;
+            }
+        }
+    }
+    *P_out = (int)P;
+    return MCT_OK;
 }
 
 // Step kernels from the requested choice: 1 split kernels; 2, 3, 4 the fused
 // kernel on patches of 64, 128, 256 nodes; 5 and 0 (automatic) the fused
-// kernel on patches of the size sized_patches finds; 0 (automatic) is 5 on
-// triangles and 1 on quadrilaterals (whose element needs about 175 vector
-// registers: two waves per SIMD, too few to hide a patch's chain of
-// dependent loads; the split kernels are faster there).  A fused choice
-// whose tables do not fit runs the split kernels.
+// kernel on patches of the size sized_patches finds, and 0 (automatic) the
+// same.  A fused choice whose tables do not fit runs the split kernels.
 int choose_kernels(Model &m, Host h) {
     Params &p = m.prm;
     p.patch_emax = 0;
@@ -309,7 +341,7 @@ int choose_kernels(Model &m, Host h) {
     int P = 0;
     if (m.kernels >= 2 && m.kernels <= 4)
         P = 64 << (m.kernels - 2);
-    else if (m.kernels == 5 || (m.kernels == 0 && m.nv == 3))
+    else if (m.kernels == 0 || m.kernels == 5)
         P = -1;
     if (P == 0 || !m.dnlist) return MCT_OK;
     int32_t emax = 0;

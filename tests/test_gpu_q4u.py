@@ -60,7 +60,7 @@ def test_q4u_matches_oracle(gpu, oracle_mod, name, monkeypatch):
     assert auto.launch()["tile"] in (2, 3, 4, 5), auto.launch()
     print(name, "automatic patches", auto.launch(), flush=True)
     models += [sized, auto]
-    assert gpu.from_config(cfg).launch()["tile"] == 1  # the automatic choice: split kernels
+    assert gpu.from_config(cfg).launch() == auto.launch()  # the automatic choice
     inf = models[0].info()
     assert (inf["n_nodes"], inf["n_elems"], inf["n_edges"]) == (o.info()["nn"], o.info()["ne"], o.info()["ns"])
     assert inf["dt"] == o.info()["dt"]
@@ -252,14 +252,17 @@ def test_q4u_fullsize_plate(gpu, oracle_mod):
     cfg = W.quad_plate160k()
     o = oracle_mod.Oracle(cfg)
     m = gpu.from_config(cfg)
-    assert m.launch()["tile"] == 1, m.launch()  # the automatic choice (split kernels), as timed
-    f = gpu.from_config(cfg, tile=5)  # the fused kernel on patches it sizes
-    assert f.launch()["tile"] in (4, 5), f.launch()
+    # the automatic choice (the fused kernel on patches it sizes), as timed
+    assert m.launch()["tile"] == 5, m.launch()
+    s = gpu.from_config(cfg, tile=1)  # the element kernel plus the node kernel
+    f = gpu.from_config(cfg, tile=4)  # the fused kernel that re-derives neighbour strains
+    assert s.launch()["tile"] == 1 and f.launch()["tile"] == 4
     o.step(300)
-    m.step(300)
-    f.step(300)
-    _same(m, o, "quad_plate160k split")
-    _same(f, o, "quad_plate160k fused")
+    for x in (m, s, f):
+        x.step(300)
+    _same(m, o, "quad_plate160k fused, shared strains")
+    _same(s, o, "quad_plate160k split")
+    _same(f, o, "quad_plate160k fused, 256-node patches")
 
 
 @pytest.mark.parametrize("kind", ["q4u", "tri"])
