@@ -30,6 +30,7 @@ static_assert(sizeof(Ctl) == 40, "Ctl layout");
 
 constexpr int kPatchMaxNodes = 256;  // fused step: one node per thread of its workgroup
 constexpr uint32_t kNoSlot = 1023;       // patch neighbour slot: none
+constexpr int kPatchLocalNodes = 384;    // triangles: nodes of a patch staged in LDS
 constexpr int32_t kOwned = 1 << 30;    // patch element flag: evaluate its candidates here
 
 // Node flags (one byte per node).
@@ -90,6 +91,14 @@ struct Params {
     const int32_t *patch_ring_off;
     const int32_t *patch_ring;
     const uint2 *patch_nbr;
+    // triangles: each patch's nodes in LDS (its own nodes b P .. in order,
+    // then its halo: the other nodes of its and its ring's triangles,
+    // ascending, entries patch_halo_off[b] ..) and every patch and ring
+    // triangle's nodes as indices into that list (.x = n0 | n1 << 16, .y = n2)
+    const int32_t *patch_halo_off;
+    const int32_t *patch_halo;
+    const uint2 *patch_lconn;
+    const uint2 *patch_ring_lconn;
     Cand *cand;          // 3 ne
     // fused step with the global pick folded in (multi-tip tracking): the
     // accepted candidates of segment step j go to set j mod 3 of fold_cand

@@ -635,11 +635,12 @@ __device__ __forceinline__ void element_force(const Params &p, const SplitView &
 // element_force of an intact triangle whose neighbours' strains and areas
 // sit in LDS (s_q[c][slot], s_A[slot]; area 0: a split or absent element),
 // slots and lower-id flags in nbs (the fused step's patch tables).  The
-// element's own geometry g, strain q and values ue come from the caller.
+// element's own geometry g, strain q and values ue come from the caller;
+// its node record is read only for candidates.
 // Arithmetic as edge_strain's: a neighbour's strain there is recomputed in
 // the neighbour's own node order, so it equals the one the neighbour
 // computed for itself, which is what the LDS holds.
-__device__ __forceinline__ void element_force_shared(const Params &p, int e, const int4 &c, const double2 ue[3],
+__device__ __forceinline__ void element_force_shared(const Params &p, int e, const double2 ue[3],
                                                      const Geo &g, const double q[3], uint2 nbs,
                                                      const double (*s_q)[2 * kB], const double *s_A, bool cands,
                                                      Cand *clist, int32_t *ccount, double2 f[3]) {
@@ -677,6 +678,7 @@ __device__ __forceinline__ void element_force_shared(const Params &p, int e, con
     for (int n = 0; n < 3; ++n)
         f[n] = make_double2(coef * fma(g.by[n], S[2], g.bx[n] * S[0]), coef * fma(g.bx[n], S[2], g.by[n] * S[1]));
     if (!cands || (two[0] && two[1] && two[2])) return;
+    const int4 c = p.conn[e];  // a free-surface element: its nodes, for the path geometry
     const int tip = p.sct ? p.ctl->tip : -1;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -1107,6 +1109,7 @@ __global__ __launch_bounds__(kB) void k_fused(Params p, int j) {
     __shared__ double s_A[SHARED ? 2 * kB : 1];
     __shared__ __align__(16) double s_qd[SHARED4 ? 13 * kQuadSlots : 1];
     double2 *const s_f = SHARED4 ? reinterpret_cast<double2 *>(s_qd) : s_fa;
+    static_assert(!SHARED || NV * EMAX >= 2 * kPatchLocalNodes, "the staged nodes fit the forces' LDS");
     __shared__ double s_phi;
     __shared__ int s_pe;
     __shared__ uint8_t s_pcode;
@@ -1142,27 +1145,49 @@ __global__ __launch_bounds__(kB) void k_fused(Params p, int j) {
     const SplitView sv{p.split, p.fold ? s_pe : -1, p.fold ? s_pcode : (uint8_t)0};
     const int s0 = p.patch_off[b], s1 = p.patch_off[b + 1];
     if constexpr (SHARED) {
-        // own strain and area of the patch element and ring element of this
-        // thread into the LDS slots tid and (s1 - s0) + tid
+        // the patch's node values into LDS (its own nodes, contiguous, then
+        // its halo), in the space the forces take over later; then the own
+        // strain and area of this thread's patch element and ring element
+        // from there into the LDS slots tid and (s1 - s0) + tid
+        double2 *const s_nu = s_f, *const s_nx = s_f + kPatchLocalNodes;
+        const int nown = min(p.patch_nodes, p.nn - b * p.patch_nodes);
+        const int h0 = p.patch_halo_off[b], nloc = nown + p.patch_halo_off[b + 1] - h0;
+        for (int l = tid; l < nloc; l += kB) {
+            const int g = l < nown ? b * p.patch_nodes + l : p.patch_halo[h0 + l - nown];
+            s_nu[l] = u[g];
+            s_nx[l] = p.xy[g];
+        }
         const int s = s0 + tid;
         const bool mine = s < s1;
         int e = 0;
         bool owned = false;
-        int4 c = make_int4(0, 0, 0, 0);
         uint8_t code = 0;
-        double2 ue[3];
-        Geo g;
-        double q[3];
+        uint2 lc = make_uint2(0, 0);
         if (mine) {
             const int32_t rec = p.patch_elem[s];
             e = rec & (kOwned - 1);
             owned = (rec & kOwned) != 0;
-            c = p.conn[e];
             code = sv(e);
+            lc = p.patch_lconn[s];
+        }
+        const int r = p.patch_ring_off[b] + tid;
+        const bool ringel = r < p.patch_ring_off[b + 1];
+        uint8_t rcode = 1;
+        uint2 rlc = make_uint2(0, 0);
+        if (ringel) {
+            rcode = sv(p.patch_ring[r]);
+            rlc = p.patch_ring_lconn[r];
+        }
+        __syncthreads();
+        double2 ue[3];
+        Geo g;
+        double q[3];
+        if (mine) {
             if (code == 0) {
                 double2 xe[3];
-                load_u(u, c, ue);
-                load_u(p.xy, c, xe);
+                const int l0 = lc.x & 0xffff, l1 = lc.x >> 16, l2 = lc.y;
+                ue[0] = s_nu[l0], ue[1] = s_nu[l1], ue[2] = s_nu[l2];
+                xe[0] = s_nx[l0], xe[1] = s_nx[l1], xe[2] = s_nx[l2];
                 g = make_geo(xe[0], xe[1], xe[2]);
                 strain(g, ue, q);
                 s_q[0][tid] = q[0];
@@ -1173,16 +1198,12 @@ __global__ __launch_bounds__(kB) void k_fused(Params p, int j) {
                 s_A[tid] = 0.0;
             }
         }
-        const int r0 = p.patch_ring_off[b], r = r0 + tid;
-        if (r < p.patch_ring_off[b + 1]) {
-            const int er = p.patch_ring[r];
+        if (ringel) {
             const int l = s1 - s0 + tid;
-            if (sv(er) == 0) {
-                const int4 cr = p.conn[er];
-                double2 ur[3], xr[3];
-                load_u(u, cr, ur);
-                load_u(p.xy, cr, xr);
-                const Geo gr = make_geo(xr[0], xr[1], xr[2]);
+            if (rcode == 0) {
+                const int l0 = rlc.x & 0xffff, l1 = rlc.x >> 16, l2 = rlc.y;
+                const double2 ur[3] = {s_nu[l0], s_nu[l1], s_nu[l2]};
+                const Geo gr = make_geo(s_nx[l0], s_nx[l1], s_nx[l2]);
                 double qr[3];
                 strain(gr, ur, qr);
                 s_q[0][l] = qr[0];
@@ -1193,17 +1214,18 @@ __global__ __launch_bounds__(kB) void k_fused(Params p, int j) {
                 s_A[l] = 0.0;
             }
         }
-        __syncthreads();
+        __syncthreads();  // every strain stored, every node value read: the forces take the node space over
         if (mine) {
             double2 f[3];
             if (code) {
+                const int4 c = p.conn[e];
                 const Piece pa = piece(p, u, c, (code >> 2) & 3, code & 3);
                 const Piece pb = piece(p, u, c, code & 3, (code >> 2) & 3);
                 f[0] = piece_force_at(pa, pb, 0);
                 f[1] = piece_force_at(pa, pb, 1);
                 f[2] = piece_force_at(pa, pb, 2);
             } else {
-                element_force_shared(p, e, c, ue, g, q, p.patch_nbr[s], s_q, s_A, owned, clist, ccount, f);
+                element_force_shared(p, e, ue, g, q, p.patch_nbr[s], s_q, s_A, owned, clist, ccount, f);
             }
             s_f[3 * tid] = f[0];
             s_f[3 * tid + 1] = f[1];

@@ -190,9 +190,10 @@ int build_patches(Model &m, Host h, int P, int32_t *emax_out, int32_t *rmax_out 
     const int64_t npatch = (nn + P - 1) / P;
     const int st = nv + 1;  // neighbour table stride
     std::vector<int32_t> poff{0}, pelem, slot_of(ne, -1), stamp(ne, -1), els, roff{0}, pring, ring;
-    std::vector<uint2> pnbr;
+    std::vector<uint2> pnbr, plconn, prlconn;
+    std::vector<int32_t> hoff{0}, phalo, halo, nstamp(nv == 3 ? nn : 0, -1), nloc(nv == 3 ? nn : 0, 0);
     std::vector<uint16_t> pslots((size_t)npatch * P * W, 0xffff);
-    int32_t emax = 0, rmax = 0;
+    int32_t emax = 0, rmax = 0, lmax = 0;
     for (int64_t b = 0; b < npatch; ++b) {
         const int64_t n0 = b * P, n1 = std::min<int64_t>(nn, n0 + P);
         els.clear();
@@ -252,6 +253,37 @@ int build_patches(Model &m, Host h, int P, int32_t *emax_out, int32_t *rmax_out 
             if (nv == 3) r.y |= kNoSlot;
             pnbr.push_back(r);
         }
+        if (nv != 3) continue;
+        // the patch's nodes: its own (local b P ..), then the halo
+        halo.clear();
+        for (int64_t i = n0; i < n1; ++i) {
+            nstamp[i] = (int32_t)b;
+            nloc[i] = (int32_t)(i - n0);
+        }
+        auto take = [&](int32_t e) {
+            for (int n = 0; n < 3; ++n) {
+                const int32_t g = m.conn[3 * (int64_t)e + n];
+                if (nstamp[g] != (int32_t)b) {
+                    nstamp[g] = (int32_t)b;
+                    halo.push_back(g);
+                }
+            }
+        };
+        for (const int32_t e : els) take(e);
+        for (const int32_t e : ring) take(e);
+        std::sort(halo.begin(), halo.end());
+        for (size_t q = 0; q < halo.size(); ++q) {
+            nloc[halo[q]] = (int32_t)(n1 - n0 + q);
+            phalo.push_back(halo[q]);
+        }
+        hoff.push_back((int32_t)phalo.size());
+        lmax = std::max<int32_t>(lmax, (int32_t)(n1 - n0 + halo.size()));
+        auto lconn = [&](int32_t e) {
+            const int32_t *c = &m.conn[3 * (int64_t)e];
+            return make_uint2((uint32_t)nloc[c[0]] | ((uint32_t)nloc[c[1]] << 16), (uint32_t)nloc[c[2]]);
+        };
+        for (const int32_t e : els) plconn.push_back(lconn(e));
+        for (const int32_t e : ring) prlconn.push_back(lconn(e));
     }
     dfree(m.dpatch_off);
     dfree(m.dpatch_elem);
@@ -266,12 +298,23 @@ int build_patches(Model &m, Host h, int P, int32_t *emax_out, int32_t *rmax_out 
     if ((rc = upload<int32_t>(h, m.dpatch_ring_off, roff.data(), roff.size()))) return rc;
     if (!pring.empty() && (rc = upload<int32_t>(h, m.dpatch_ring, pring.data(), pring.size()))) return rc;
     if ((rc = upload<uint2>(h, m.dpatch_nbr, pnbr.data(), pnbr.size()))) return rc;
+    dfree(m.dpatch_halo_off);
+    dfree(m.dpatch_halo);
+    dfree(m.dpatch_lconn);
+    dfree(m.dpatch_ring_lconn);
+    if (nv == 3) {
+        if ((rc = upload<int32_t>(h, m.dpatch_halo_off, hoff.data(), hoff.size()))) return rc;
+        if (!phalo.empty() && (rc = upload<int32_t>(h, m.dpatch_halo, phalo.data(), phalo.size()))) return rc;
+        if ((rc = upload<uint2>(h, m.dpatch_lconn, plconn.data(), plconn.size()))) return rc;
+        if (!prlconn.empty() && (rc = upload<uint2>(h, m.dpatch_ring_lconn, prlconn.data(), prlconn.size())))
+            return rc;
+    }
     TRY(h, hipStreamSynchronize(h.stream));
     // the 256-slot kernel shares strains through LDS and holds 256 ring
     // triangles or 128 ring quadrilaterals (four edge strains each); with a
     // larger ring the patches take the 512-slot kernel, which recomputes
     // the neighbours' strains and reads no ring
-    if (emax <= 256 && rmax > (nv == 3 ? 256 : 128)) emax = 257;
+    if (emax <= 256 && (rmax > (nv == 3 ? 256 : 128) || lmax > kPatchLocalNodes)) emax = 257;
     *emax_out = emax;
     if (rmax_out) *rmax_out = rmax;
     return MCT_OK;
@@ -356,6 +399,10 @@ int choose_kernels(Model &m, Host h) {
     p.patch_ring_off = m.dpatch_ring_off;
     p.patch_ring = m.dpatch_ring;
     p.patch_nbr = m.dpatch_nbr;
+    p.patch_halo_off = m.dpatch_halo_off;
+    p.patch_halo = m.dpatch_halo;
+    p.patch_lconn = m.dpatch_lconn;
+    p.patch_ring_lconn = m.dpatch_ring_lconn;
     // the global multi-tip pick folds into the next fused step
     if (!m.sct && !(m.front_rho > 0)) {
         if (!m.dfold_n) {
@@ -398,6 +445,10 @@ void release(Model &m) {
     dfree(m.dpatch_ring_off);
     dfree(m.dpatch_ring);
     dfree(m.dpatch_nbr);
+    dfree(m.dpatch_halo_off);
+    dfree(m.dpatch_halo);
+    dfree(m.dpatch_lconn);
+    dfree(m.dpatch_ring_lconn);
     dfree(m.dfold_n);
     dfree(m.dfold_cand);
     dfree(m.dv);

@@ -60,7 +60,8 @@ struct Model {
     double2 *dxy = nullptr, *du[2] = {nullptr, nullptr}, *dv = nullptr, *dfext = nullptr, *dv0 = nullptr,
             *dfe = nullptr;
     int32_t *dpatch_off = nullptr, *dpatch_elem = nullptr, *dpatch_ring_off = nullptr, *dpatch_ring = nullptr;
-    uint2 *dpatch_nbr = nullptr;
+    uint2 *dpatch_nbr = nullptr, *dpatch_lconn = nullptr, *dpatch_ring_lconn = nullptr;
+    int32_t *dpatch_halo_off = nullptr, *dpatch_halo = nullptr;
     int32_t *dfold_n = nullptr;     // folded pick: 3 candidate counters
     Cand *dfold_cand = nullptr;     //   and 3 candidate sets of 3 ne (triangles only)
     uint16_t *dpatch_slots = nullptr;
