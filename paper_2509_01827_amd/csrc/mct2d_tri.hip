@@ -1100,16 +1100,16 @@ __global__ __launch_bounds__(kB) void k_fused(Params p, int j) {
     // triangles in patches of at most 256 elements and 256 ring elements
     // share their strains through LDS (one element and one ring element per
     // thread); the other forms recompute each neighbour's strain
-    constexpr bool SHARED = NV == 3 && EMAX == kB;
+    constexpr bool SHARED3 = NV == 3 && EMAX == kB;
     // quadrilaterals likewise with 128 ring elements; their forces reuse the
     // strains' LDS once every element has read its neighbours' strains
     constexpr bool SHARED4 = NV == 4 && EMAX == kB;
     __shared__ double2 s_fa[SHARED4 ? 1 : NV * EMAX];
-    __shared__ double s_q[SHARED ? 3 : 1][SHARED ? 2 * kB : 1];
-    __shared__ double s_A[SHARED ? 2 * kB : 1];
+    __shared__ double s_q[SHARED3 ? 3 : 1][SHARED3 ? 2 * kB : 1];
+    __shared__ double s_A[SHARED3 ? 2 * kB : 1];
     __shared__ __align__(16) double s_qd[SHARED4 ? 13 * kQuadSlots : 1];
     double2 *const s_f = SHARED4 ? reinterpret_cast<double2 *>(s_qd) : s_fa;
-    static_assert(!SHARED || NV * EMAX >= 2 * kPatchLocalNodes, "the staged nodes fit the forces' LDS");
+    static_assert(!SHARED3 || NV * EMAX >= 2 * kPatchLocalNodes, "the staged nodes fit the forces' LDS");
     __shared__ double s_phi;
     __shared__ int s_pe;
     __shared__ uint8_t s_pcode;
@@ -1144,7 +1144,7 @@ __global__ __launch_bounds__(kB) void k_fused(Params p, int j) {
     }
     const SplitView sv{p.split, p.fold ? s_pe : -1, p.fold ? s_pcode : (uint8_t)0};
     const int s0 = p.patch_off[b], s1 = p.patch_off[b + 1];
-    if constexpr (SHARED) {
+    if constexpr (SHARED3) {
         // the patch's node values into LDS (its own nodes, contiguous, then
         // its halo), in the space the forces take over later; then the own
         // strain and area of this thread's patch element and ring element
@@ -1214,7 +1214,7 @@ __global__ __launch_bounds__(kB) void k_fused(Params p, int j) {
                 s_A[l] = 0.0;
             }
         }
-        __syncthreads();  // every strain stored, every node value read: the forces take the node space over
+        __syncthreads();  // strains stored, node values read: the forces take the node space over
         if (mine) {
             double2 f[3];
             if (code) {
@@ -1328,19 +1328,21 @@ __global__ __launch_bounds__(kB) void k_fused(Params p, int j) {
             for (int n = 0; n < 4; ++n) s_f[4 * tid + n] = f[n];
         }
     } else {
-    for (int s = s0 + tid; s < s1; s += kB) {
-        const int32_t rec = p.patch_elem[s];
-        const int l = NV * (s - s0);
-        if constexpr (NV == 3) {
-            double2 f[3];
-            element_force(p, sv, u, rec & (kOwned - 1), (rec & kOwned) != 0, clist, ccount, f);
-            s_f[l] = f[0];
-            s_f[l + 1] = f[1];
-            s_f[l + 2] = f[2];
-        } else {
-            quad_element<false>(p, sv, u, rec & (kOwned - 1), (rec & kOwned) != 0, clist, ccount, Eval{}, s_f + l, 1);
+        // the other forms: each element re-derives its neighbours' strains
+        for (int s = s0 + tid; s < s1; s += kB) {
+            const int32_t rec = p.patch_elem[s];
+            const int l = NV * (s - s0);
+            if constexpr (NV == 3) {
+                double2 f[3];
+                element_force(p, sv, u, rec & (kOwned - 1), (rec & kOwned) != 0, clist, ccount, f);
+                s_f[l] = f[0];
+                s_f[l + 1] = f[1];
+                s_f[l + 2] = f[2];
+            } else {
+                quad_element<false>(p, sv, u, rec & (kOwned - 1), (rec & kOwned) != 0, clist, ccount, Eval{},
+                                    s_f + l, 1);
+            }
         }
-    }
     }
     if (tid == 0) s_phi = load_factor(p, (double)k * p.dt);
     __syncthreads();
