@@ -78,6 +78,42 @@ def test_tri_matches_oracle(gpu, oracle_mod, name, monkeypatch):
     print(name, "splits", len(o.log()["elem"]), flush=True)
 
 
+def _shuffled_nodes(cfg, seed):
+    """The same mesh with its node ids in a seeded random order (element ids
+    and each triangle's node order kept)."""
+    nn = len(cfg["X"])
+    pn = np.argsort(W.uniform01(seed, nn), kind="stable")  # new id -> old id
+    inv = np.empty(nn, np.int64)
+    inv[pn] = np.arange(nn)
+    vn, vm, vv = cfg["vbc"]
+    return dict(cfg, name=cfg["name"] + "_shuffled", X=np.ascontiguousarray(cfg["X"][pn]),
+                Y=np.ascontiguousarray(cfg["Y"][pn]),
+                conn=np.ascontiguousarray(inv[np.asarray(cfg["conn"], np.int64)].astype(np.int32)),
+                traction_nodes=np.ascontiguousarray(inv[np.asarray(cfg["traction_nodes"], np.int64)].astype(np.int32)),
+                vbc=(np.ascontiguousarray(inv[np.asarray(vn, np.int64)].astype(np.int32)), vm, vv))
+
+
+def test_tri_shuffled_nodes(gpu, oracle_mod, monkeypatch):
+    """Node ids without locality: the fused kernel's patches of consecutive
+    nodes scatter, their rings and staged node lists overflow what the
+    shared-strain kernel holds, and every launch choice falls back (to the
+    kernel that re-derives neighbour strains, or to the split kernels) with
+    results still equal to the oracle's on the same mesh."""
+    cfg = _shuffled_nodes(W.tri_small_cases()["tri_plate40x16"], W.BASE_SEED + 120)
+    o = oracle_mod.Oracle(cfg)
+    models = [gpu.from_config(cfg, tile=t) for t in (0, 1, 2)]
+    monkeypatch.setenv("MCT_PATCH_NODES", "16")  # small patches: 512-slot kernel or the shared one
+    models.append(gpu.from_config(cfg, tile=5))
+    monkeypatch.delenv("MCT_PATCH_NODES")
+    print("launches", [m.launch() for m in models], flush=True)
+    for chunk in (1, 299, 700):
+        o.step(chunk)
+        for m in models:
+            m.step(chunk)
+            _same(m, o, ("shuffled", chunk, m.launch()))
+    assert len(o.log()["elem"]) > 3
+
+
 def test_tri_sct_matches_oracle(gpu, oracle_mod):
     cfg = dict(W.tri_small_cases()["tri_plate40x16"], tracking=("sct", -1, 0))
     o = oracle_mod.Oracle(cfg)
