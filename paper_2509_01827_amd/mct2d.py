@@ -342,6 +342,11 @@ class Model:
         return None if t < 0 else (t >> 2, t & 3)
 
     def set_launch(self, tile=0, use_graph=True):
+        """Tile shape (grids: 0 automatic, 1 16x16, 2 32x8, 3 32x16) or, on
+        an unstructured mesh, the step kernels (0 automatic, 1 element plus
+        node kernels, 2/3/4 the fused kernel on 64/128/256-node patches, 5
+        on patches of the size the library finds); whether steps replay
+        captured HIP graphs.  Takes effect at once on a finalized model."""
         self._check(self._L.mct_set_launch(self._h, int(tile), int(bool(use_graph))), "set_launch")
 
     def select(self, s):
@@ -357,6 +362,8 @@ class Model:
         return dict(tile=t.value, order=o.value, us_per_step=us.value)
 
     def launch(self):
+        """The launch shape in use: tile (the step kernels on an unstructured
+        mesh, never 0), unit order and workgroups per step."""
         t, o, w = C.c_int(0), C.c_int(0), C.c_int64(0)
         self._check(self._L.mct_get_launch(self._h, C.byref(t), C.byref(o), C.byref(w)), "get_launch")
         return dict(tile=t.value, order=o.value, workgroups=w.value)
