@@ -332,3 +332,23 @@ def test_q4u_loading_variants(gpu, oracle_mod, kind):
         _same(m, o, (kind, done))
     assert len(o.log()["elem"]) > 0, kind
     print(kind, "splits", len(o.log()["elem"]), flush=True)
+
+
+@pytest.mark.parametrize("nodes", [1, 3, 256])
+def test_fused_patch_extremes(gpu, oracle_mod, monkeypatch, nodes):
+    """Patch sizes at the ends of the fused kernel's range (one node per
+    patch; a few; 256, whose patches take the 512- or 1024-slot kernel), on
+    a small triangle and a small quadrilateral case: bit-identical to the
+    oracle."""
+    for cfg in (W.tri_small_cases()["tri_plate40x16"], W.quad_small_cases()["quad_plate24x10"]):
+        o = oracle_mod.Oracle(cfg)
+        monkeypatch.setenv("MCT_PATCH_NODES", str(nodes))
+        m = gpu.from_config(cfg, tile=5)
+        monkeypatch.delenv("MCT_PATCH_NODES")
+        nn = m.info()["n_nodes"]
+        lau = m.launch()
+        assert lau["workgroups"] == -(-nn // nodes), (cfg["name"], lau)
+        for chunk in (1, 150, 450):
+            o.step(chunk)
+            m.step(chunk)
+            _same(m, o, (cfg["name"], nodes, chunk))
