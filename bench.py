@@ -97,11 +97,11 @@ MEASURED_TRAFFIC = {
     "batch256": {"sources": Q4_SOURCES, "sha256": "0be1dd5dbc91c01e5a3c4180b502f3022bb21a0a5fecd3af32a219a3f8110831",
                  "tile": 1, "fetch_kib": 286603.1083984375, "write_kib": 407268.94677734375},
     # the fused triangle step on its automatic patches (profiles/k_fused_tri320k_hbm_traffic.md)
-    "tri320k": {"sources": TRI_SOURCES, "sha256": "0a00ab3998906162ae8f1936f740ae84b91d50c2675c605a498ef1b30daec2c5",
-                "tile": 5, "fetch_kib": 12141.251998, "write_kib": 5024.631608},
+    "tri320k": {"sources": TRI_SOURCES, "sha256": "806d14d94b3934373738da96454bcb13719769a770e41e96dd202916c26c103e",
+                "tile": 5, "fetch_kib": 12160.925545, "write_kib": 5024.832886},
     # the fused quadrilateral step on its automatic patches (profiles/k_fused_quad160k_kernel_trace.md)
-    "quad160k": {"sources": TRI_SOURCES, "sha256": "0a00ab3998906162ae8f1936f740ae84b91d50c2675c605a498ef1b30daec2c5",
-                 "tile": 5, "fetch_kib": 9233.879816, "write_kib": 5005.355169},
+    "quad160k": {"sources": TRI_SOURCES, "sha256": "806d14d94b3934373738da96454bcb13719769a770e41e96dd202916c26c103e",
+                 "tile": 5, "fetch_kib": 9238.957200, "write_kib": 5005.347145},
 }
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131086.604, 262144.0 / 262144.0
 

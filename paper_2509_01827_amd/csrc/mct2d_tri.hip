@@ -1096,7 +1096,8 @@ __device__ __forceinline__ void quad_edge_sigma_shared(const Params &p, int k, c
 // updated.  u^k is read from buffer k & 1 and u^{k+1} written to the other,
 // so neighbouring workgroups never see a half-updated displacement.
 template <int NV, int W, int EMAX>
-__global__ __launch_bounds__(kB) void k_fused(Params p, int j) {
+__global__ __launch_bounds__(kB) __attribute__((amdgpu_waves_per_eu(NV == 3 && EMAX == kB ? 5 : 1)))
+void k_fused(Params p, int j) {
     // triangles in patches of at most 256 elements and 256 ring elements
     // share their strains through LDS (one element and one ring element per
     // thread); the other forms recompute each neighbour's strain
@@ -1119,6 +1120,41 @@ __global__ __launch_bounds__(kB) void k_fused(Params p, int j) {
     const int b = dev::xcd_tile(blockIdx.x, gridDim.x), tid = threadIdx.x;
     Cand *clist = p.cand;
     int32_t *ccount = &p.ctl->nacc;
+    const int s0 = p.patch_off[b], s1 = p.patch_off[b + 1];
+    // shared-strain triangles: this thread's staged nodes (slots tid and
+    // tid + kB of the patch's node list) and its element records, loaded
+    // here, before the folded pick, which they do not depend on
+    static_assert(kPatchLocalNodes <= 2 * kB, "at most two staged nodes per thread");
+    double2 st_u0, st_x0, st_u1, st_x1;
+    bool st0 = false, st1 = false;
+    int32_t rec = 0, er = -1;
+    uint2 lc = make_uint2(0, 0), rlc = make_uint2(0, 0);
+    if constexpr (SHARED3) {
+        const int nown = min(p.patch_nodes, p.nn - b * p.patch_nodes);
+        const int h0 = p.patch_halo_off[b], nloc = nown + p.patch_halo_off[b + 1] - h0;
+        const int la = tid, lb = tid + kB;
+        st0 = la < nloc;
+        st1 = lb < nloc;
+        if (st0) {
+            const int g = la < nown ? b * p.patch_nodes + la : p.patch_halo[h0 + la - nown];
+            st_u0 = u[g];
+            st_x0 = p.xy[g];
+        }
+        if (st1) {
+            const int g = lb < nown ? b * p.patch_nodes + lb : p.patch_halo[h0 + lb - nown];
+            st_u1 = u[g];
+            st_x1 = p.xy[g];
+        }
+        if (s0 + tid < s1) {
+            rec = p.patch_elem[s0 + tid];
+            lc = p.patch_lconn[s0 + tid];
+        }
+        const int r = p.patch_ring_off[b] + tid;
+        if (r < p.patch_ring_off[b + 1]) {
+            er = p.patch_ring[r];
+            rlc = p.patch_ring_lconn[r];
+        }
+    }
     if (p.fold) {
         // the pick of the segment's previous step, from its candidates (set
         // (j - 1) mod 3), taken alike by every workgroup; workgroup 0 records
@@ -1143,41 +1179,21 @@ __global__ __launch_bounds__(kB) void k_fused(Params p, int j) {
         ccount = p.fold_n + j % 3;
     }
     const SplitView sv{p.split, p.fold ? s_pe : -1, p.fold ? s_pcode : (uint8_t)0};
-    const int s0 = p.patch_off[b], s1 = p.patch_off[b + 1];
     if constexpr (SHARED3) {
         // the patch's node values into LDS (its own nodes, contiguous, then
         // its halo), in the space the forces take over later; then the own
         // strain and area of this thread's patch element and ring element
         // from there into the LDS slots tid and (s1 - s0) + tid
         double2 *const s_nu = s_f, *const s_nx = s_f + kPatchLocalNodes;
-        const int nown = min(p.patch_nodes, p.nn - b * p.patch_nodes);
-        const int h0 = p.patch_halo_off[b], nloc = nown + p.patch_halo_off[b + 1] - h0;
-        for (int l = tid; l < nloc; l += kB) {
-            const int g = l < nown ? b * p.patch_nodes + l : p.patch_halo[h0 + l - nown];
-            s_nu[l] = u[g];
-            s_nx[l] = p.xy[g];
-        }
+        if (st0) s_nu[tid] = st_u0, s_nx[tid] = st_x0;
+        if (st1) s_nu[tid + kB] = st_u1, s_nx[tid + kB] = st_x1;
         const int s = s0 + tid;
         const bool mine = s < s1;
-        int e = 0;
-        bool owned = false;
-        uint8_t code = 0;
-        uint2 lc = make_uint2(0, 0);
-        if (mine) {
-            const int32_t rec = p.patch_elem[s];
-            e = rec & (kOwned - 1);
-            owned = (rec & kOwned) != 0;
-            code = sv(e);
-            lc = p.patch_lconn[s];
-        }
-        const int r = p.patch_ring_off[b] + tid;
-        const bool ringel = r < p.patch_ring_off[b + 1];
-        uint8_t rcode = 1;
-        uint2 rlc = make_uint2(0, 0);
-        if (ringel) {
-            rcode = sv(p.patch_ring[r]);
-            rlc = p.patch_ring_lconn[r];
-        }
+        const int e = rec & (kOwned - 1);
+        const bool owned = (rec & kOwned) != 0;
+        const uint8_t code = mine ? sv(e) : 0;
+        const bool ringel = er >= 0;
+        const uint8_t rcode = ringel ? sv(er) : 1;
         __syncthreads();
         double2 ue[3];
         Geo g;
